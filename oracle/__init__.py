@@ -1,0 +1,2 @@
+"""FP64 CPU oracle for SL1M (test infrastructure only; see sl1m_oracle)."""
+from .sl1m_oracle import *  # noqa: F401,F403
