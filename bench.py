@@ -1,0 +1,214 @@
+"""Benchmark of the SL1M hot path on one MI355X.
+
+Workload: config 2 of the measurement plan -- a 256x256 wide-field delta grid
+over l, m in +-0.3 (65,536 pixels) against 97,536 visibilities of a
+128-antenna array (12 snapshots over 6 h, 150 MHz), FP32 operator with FP64
+phase.  A step is one FISTA iteration: forward operator, residual, adjoint,
+threshold and momentum update, i.e. 2 x 65,536 x 97,536 pixel-visibility
+evaluations.  The timed region is exactly `--steps` iterations of one L1 solve
+(100 by default, the workload's solve length) with L fixed beforehand.
+
+Prints one JSON line with the throughput, the dominant kernel's roofline
+fraction (kernel durations from HIP events recorded by the library around
+each launch on the launch stream) and the FP64 CPU oracle's rate on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector peak (published)
+FLOP_PER_EVAL_DELTA = 14            # phase 3 FMA, reduction 2, sin+cos 2, accumulate 2 FMA
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sl1m_kernels.hip", "sl1m_internal.h"):
+        with open(os.path.join(ROOT, "paper_1310_2078_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = d.get(kernel)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, threads: int):
+    """The FP64 oracle, untuned, on a bounded sample of the workload: the
+    forward for the first 512*threads visibilities (all pixels) and the adjoint
+    for the first 2048*threads pixels against the first quarter of the
+    visibilities."""
+    import oracle as O
+    p = O.Problem.from_workload(wl, threads=threads)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(wl.n_pix)
+    nf = min(wl.n_vis, 512 * threads)
+    t0 = time.perf_counter()
+    O.forward_rows(p, x, np.arange(nf))
+    tf = time.perf_counter() - t0
+    nvq = wl.n_vis // 4
+    pq = O.Problem(l=wl.l, m=wl.m, u=wl.u[:nvq], v=wl.v[:nvq], w=wl.w[:nvq], threads=threads)
+    na = min(wl.n_pix, 2048 * threads)
+    r = rng.standard_normal(nvq) + 1j * rng.standard_normal(nvq)
+    t0 = time.perf_counter()
+    O.adjoint_cols(pq, r, np.arange(na))
+    ta = time.perf_counter() - t0
+    evals = nf * wl.n_pix + na * nvq
+    return {
+        "value": evals / (tf + ta),
+        "unit": "evals/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"forward rows 0..{nf - 1} x {wl.n_pix} pixels + adjoint pixels 0..{na - 1} "
+                  f"x {nvq} visibilities ({evals:.3e} evals, {tf + ta:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-ops", type=int, default=0,
+                    help="after the timed region, run this many extra forward+adjoint pairs "
+                         "(for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU pixel sharding is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1310_2078_amd import sl1m
+    from paper_1310_2078_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    wl = W.config2()
+    n_pix, n_vis = wl.n_pix, wl.n_vis
+    print(f"[bench] config2 n_pix={n_pix} n_vis={n_vis} steps={args.steps} warmup={args.warmup}",
+          file=sys.stderr, flush=True)
+    plan = sl1m.Plan.from_workload(wl, device=dev)
+    noise = torch.as_tensor(wl.noise, dtype=torch.complex64, device=dev)
+    V = plan.forward(wl.x_true) + noise            # synthetic data, not timed
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rq = plan.estimate_L(wl.power_iters, seed=0)
+    torch.cuda.synchronize()
+    t_power = time.perf_counter() - t0
+    L = 1.01 * rq
+
+    if args.warmup > 0:
+        plan.solve(V, wl.lam, args.warmup, L=L)
+    torch.cuda.synchronize()
+    plan.timing_begin(max(16, 2 * args.steps + 8))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    img, info = plan.solve(V, wl.lam, args.steps, L=L)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = plan.timing_end()
+    elapsed = t1 - t0
+    evals = 2.0 * n_pix * n_vis * args.steps
+    print(f"[bench] solve {args.steps} it in {elapsed:.4f} s; timing {tim}; info {info}",
+          file=sys.stderr, flush=True)
+
+    for _ in range(args.profile_ops):
+        plan.adjoint(plan.forward(img))
+    torch.cuda.synchronize()
+
+    fwd_n, fwd_ms = tim["forward"]
+    adj_n, adj_ms = tim["adjoint"]
+    fis_n, fis_ms = tim["fista"]
+    fwd_avg = fwd_ms / max(fwd_n, 1)
+    adj_avg = adj_ms / max(adj_n, 1)
+    if adj_avg >= fwd_avg:
+        dom, dom_ms, dom_name = "adjoint", adj_avg, "k_adj_delta<float,4>"
+    else:
+        dom, dom_ms, dom_name = "forward", fwd_avg, "k_fwd_delta<float,4>"
+    flops = FLOP_PER_EVAL_DELTA * n_pix * n_vis
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    out = {
+        "metric": "pixel x visibility evals/s (forward + adjoint), FISTA iteration on config 2",
+        "value": evals / elapsed,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 phase)",
+        "data": "synthetic",
+        "config": {
+            "workload": "config2: 256x256 wide-field delta pixels over +-0.3, 97,536 visibilities "
+                        "(128 antennas, 12 snapshots, 150 MHz), FISTA lambda=3*sigma*sqrt(N_v)",
+            "n_pix": n_pix,
+            "n_vis": n_vis,
+            "evals_per_step": 2 * n_pix * n_vis,
+        },
+        "l1_solve_time_s": elapsed,
+        "solve": {
+            "iterations": args.steps,
+            "time_s": elapsed,
+            "power_iteration_s": t_power,
+            "power_iterations": wl.power_iters,
+            "L": L,
+            "F": info["F"],
+            "nnz": info["nnz"],
+        },
+        "kernels": {
+            "forward_avg_ms": fwd_avg,
+            "adjoint_avg_ms": adj_avg,
+            "fista_update_avg_ms": fis_ms / max(fis_n, 1),
+            "forward_evals_per_s": n_pix * n_vis / (fwd_avg * 1e-3),
+            "adjoint_evals_per_s": n_pix * n_vis / (adj_avg * 1e-3),
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom_name,
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": load_traffic(dom_name),
+            "flop_per_eval": FLOP_PER_EVAL_DELTA,
+            "evals_per_launch": n_pix * n_vis,
+        },
+    }
+    if not args.no_cpu_baseline:
+        try:
+            threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        except AttributeError:
+            threads = 1
+        out["cpu_baseline"] = cpu_baseline(wl, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

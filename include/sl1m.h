@@ -1,0 +1,205 @@
+/*
+ * sl1m.h -- C ABI of the SL1M hot path on MI355X (gfx950).
+ *
+ * SL1M deconvolves interferometer data by minimising
+ *     F(I) = 1/2 |V - M I|^2 + lambda * sum_j I_j   over I >= 0
+ * (Hardy 2013, eq. (cme) together with the iteration of Section
+ * "Implementation of SL1M"), where M maps pixel fluxes to ungridded
+ * visibilities and every entry of M is recomputed from its closed form each
+ * time it is used (Section "On-the-fly computation versus in-memory
+ * computation"); no matrix is ever stored.
+ *
+ * Notation: j = pixel, k = visibility.  Phases are in turns.
+ *
+ * Conventions for every call below
+ *  - Array arguments are DEVICE pointers owned by the caller unless the
+ *    comment says "host".  The library never frees them.
+ *  - The library allocates no device memory: a plan's workspace is sized by
+ *    sl1m_plan_workspace_bytes() and provided by the caller; it must stay
+ *    alive and untouched until sl1m_plan_destroy().
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*; NULL means the default stream) unless the comment says they
+ *    synchronise.
+ *  - Every call returns sl1m_status (0 = OK, negative = error).  Arguments
+ *    are validated on the host before any launch; on error nothing is
+ *    launched and sl1m_last_error() returns a thread-local message.
+ *  - No C++ exception crosses this interface.
+ *  - Calls that share a plan must not run concurrently (the plan's workspace
+ *    holds per-call scratch such as split-K partial sums).
+ *  - Real/complex element types follow the plan's precision: float32 and
+ *    complex64 (interleaved re, im) for SL1M_PREC_FP32, float64 and
+ *    complex128 for SL1M_PREC_FP64.
+ */
+#ifndef SL1M_H_
+#define SL1M_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SL1M_OK = 0,
+  SL1M_EINVAL = -1,     /* bad argument (null pointer, size, enum value)          */
+  SL1M_EDOMAIN = -2,    /* a pixel with l^2 + m^2 >= 1, sigma < 0, non-finite input */
+  SL1M_ENOMEM = -3,     /* workspace too small                                    */
+  SL1M_EHIP = -4,       /* a HIP runtime call failed                              */
+  SL1M_EDIVERGED = -5,  /* solver produced a non-finite objective (L too small)   */
+  SL1M_ECANCELLED = -6  /* reserved for the serving layer                         */
+} sl1m_status;
+
+/* Pixel basis functions (Section "Defining the direct solution"). */
+typedef enum {
+  SL1M_PIX_DELTA = 0,          /* eq. (deltam): Dirac delta pixels                    */
+  SL1M_PIX_GAUSS_PARAXIAL = 1, /* eq. (samlm4): Gaussian pixel, paraxial w phase      */
+  SL1M_PIX_GAUSS_WIDE = 2      /* eq. (samlm5): Gaussian pixel, centre w phase kept   */
+} sl1m_pixel_kind;
+
+typedef enum {
+  SL1M_PREC_FP64 = 0, /* everything in float64                                   */
+  SL1M_PREC_FP32 = 1  /* float64 phase with exact reduction to [-1/2, 1/2] turn;
+                         sincos, gains and accumulation in float32                */
+} sl1m_precision;
+
+/*
+ * One deconvolution problem.  All arrays are device pointers.
+ *  l, m      [n_pix] float64  direction cosines of the pixel centres; the
+ *                             paper allows arbitrary (off-grid) positions
+ *                             (Section "Delta function pixels"); l^2+m^2 < 1.
+ *  sigma     [n_pix] float64  Gaussian scale of eq. (gaus),
+ *                             f = exp(-pi r^2 / sigma^2) / sigma^2; NULL = all 0.
+ *  kind      [n_pix] uint8    sl1m_pixel_kind; NULL = DELTA where sigma == 0,
+ *                             GAUSS_WIDE elsewhere.
+ *  u, v, w   [n_vis] float64  baseline coordinates in wavelengths.
+ *  ant_p, ant_q [n_vis] int32 antennas of each visibility; NULL = unit gains.
+ *  ant_gain  [2*n_ant] float64 complex gain constant c_a (re, im) per antenna;
+ *                             NULL = 1.
+ *  ant_fwhm  [n_ant] float64  power-beam full width at half maximum F_a
+ *                             (radians of l, m) per antenna; NULL = flat beam.
+ *    The direction-dependent gain of eq. (samdelta) is taken as
+ *    A_jk = E_p(l_j,m_j) conj(E_q(l_j,m_j)), E_a = c_a exp(-2 ln2 r^2 / F_a^2),
+ *    evaluated at the pixel centre for Gaussian pixels (as eq. (samlm3)
+ *    assumes).
+ *  precision sl1m_precision.
+ */
+typedef struct {
+  int64_t n_pix;
+  const double* l;
+  const double* m;
+  const double* sigma;
+  const uint8_t* kind;
+  int64_t n_vis;
+  const double* u;
+  const double* v;
+  const double* w;
+  const int32_t* ant_p;
+  const int32_t* ant_q;
+  int32_t n_ant;
+  const double* ant_gain;
+  const double* ant_fwhm;
+  int32_t precision;
+  int32_t reserved;
+} sl1m_problem;
+
+typedef struct sl1m_plan sl1m_plan;
+
+/* Bytes of device workspace that sl1m_plan_create() needs for `problem`.
+ * Reads sigma, kind, ant_p, ant_q and ant_fwhm with blocking device-to-host
+ * copies when they are given (the grouping of pixels and the gain mode set the
+ * layout); the other arrays are not read.  At most 16 distinct (kind, sigma)
+ * Gaussian groups per problem; more gives SL1M_EINVAL. */
+sl1m_status sl1m_plan_workspace_bytes(const sl1m_problem* problem, size_t* bytes);
+
+/* Build a plan: derives per-pixel quantities (n, n - 1, 1/n, the wide-field
+ * remainder n - 1 + r^2/2, beam factors) and per-visibility gains into the
+ * workspace, groups pixels by (kind, sigma) and checks the domain.  The
+ * problem's device arrays are read during this call only.  Synchronises
+ * `stream` once.  On success *out owns host memory released by
+ * sl1m_plan_destroy(). */
+sl1m_status sl1m_plan_create(const sl1m_problem* problem, void* workspace, size_t workspace_bytes,
+                             void* stream, sl1m_plan** out);
+
+sl1m_status sl1m_plan_destroy(sl1m_plan* plan);
+
+/* Forward operator, eq. (sme): vis[k] = sum_j M_kj x[j] with M from eq. (deltam),
+ * (samlm4) or (samlm5) per pixel.  x: real [n_pix]; vis: complex [n_vis].
+ * x may be any sign. */
+sl1m_status sl1m_forward(sl1m_plan* plan, const void* x, void* vis, void* stream);
+
+/* Adjoint (back-projection of the gradient step, Section "Implementation of
+ * SL1M"): g[j] = Re sum_k conj(M_kj) r[k].  r: complex [n_vis]; g: real [n_pix]. */
+sl1m_status sl1m_adjoint(sl1m_plan* plan, const void* r, void* g, void* stream);
+
+/* Largest eigenvalue of Re(M^H M) (the step-size constant L of the FISTA
+ * iteration; the paper leaves the method open) by `iters` steps of power
+ * iteration.  Start vector: x0 (device, real [n_pix]) if not NULL, else
+ * U[0,1) values from the SplitMix64 generator (Steele, Lea & Flood 2014) at
+ * counter j+1 from state `seed` for pixel j.  *rayleigh_out (host) receives
+ * the last Rayleigh quotient <x, A x> with |x| = 1.  Synchronises. */
+sl1m_status sl1m_estimate_L(sl1m_plan* plan, int32_t iters, uint64_t seed, const void* x0,
+                            double* rayleigh_out, void* stream);
+
+typedef struct {
+  double lambda;        /* regularisation weight of eq. (cme)                        */
+  double eps;           /* stop when |F_k - F_prev| <= eps F_prev between two checks;
+                           0 disables (the paper stops on a small relative change)   */
+  int32_t max_iter;     /* iteration cap                                             */
+  int32_t check_every;  /* iterations between objective checks when eps > 0 (>= 1)   */
+  double L;             /* step constant; <= 0 runs sl1m_estimate_L first            */
+  double L_safety;      /* factor applied to an estimated L (e.g. 1.01); <= 0 -> 1.01 */
+  int32_t power_iters;  /* power-iteration steps when L <= 0 (e.g. 30)               */
+  int32_t reserved;
+  uint64_t seed;        /* SplitMix64 state for the power-iteration start            */
+} sl1m_solve_params;
+
+typedef struct {
+  int32_t iters;        /* iterations run                                            */
+  int32_t converged;    /* 1 if stopped by eps                                       */
+  double L;             /* step constant used                                        */
+  double F;             /* objective at the returned image                           */
+  double l2_term;       /* 1/2 |V - M I|^2                                           */
+  double l1_term;       /* sum_j I_j                                                 */
+  int64_t nnz;          /* non-zero pixels                                           */
+  int32_t status;       /* sl1m_status of the solve                                  */
+  int32_t reserved;
+} sl1m_solve_info;
+
+/* FISTA with the positive threshold of eq. (threshp):
+ *   y_1 = I_0 = 0, t_1 = 1;
+ *   I_k = T^{lambda/L}(y_k - Re M^H (M y_k - V) / L);
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2;
+ *   y_{k+1} = I_k + ((t_k - 1)/t_{k+1}) (I_k - I_{k-1}).
+ * vis: complex [n_vis] data V; img_out: real [n_pix] final I; info: host.
+ * Synchronises at the end (and at each objective check when eps > 0).
+ * Returns SL1M_EDIVERGED if the final objective is not finite. */
+sl1m_status sl1m_solve(sl1m_plan* plan, const void* vis, const sl1m_solve_params* params,
+                       void* img_out, sl1m_solve_info* info, void* stream);
+
+/* Kernel timing (tracing).  Between sl1m_timing_begin() and sl1m_timing_end()
+ * the plan records a pair of HIP events around every launch of its operator
+ * kernels on the launch stream (at most max_launches launches per kind; later
+ * launches are not timed).  sl1m_timing_end() synchronises on the recorded
+ * events and reports, per kind, the number of timed launches and the sum of
+ * their durations in milliseconds.  Kinds: 0 = forward operator kernels,
+ * 1 = adjoint operator kernels, 2 = FISTA vector update. */
+typedef struct {
+  int64_t launches[4];
+  double total_ms[4];
+} sl1m_timing;
+
+sl1m_status sl1m_timing_begin(sl1m_plan* plan, int32_t max_launches);
+sl1m_status sl1m_timing_end(sl1m_plan* plan, sl1m_timing* out /* host */);
+
+/* Message of the last error on this thread ("" if none). */
+const char* sl1m_last_error(void);
+
+/* Library version string. */
+const char* sl1m_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SL1M_H_ */

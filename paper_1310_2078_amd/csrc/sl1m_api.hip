@@ -1,0 +1,643 @@
+// C ABI of the SL1M library: plans, operator calls, power iteration, FISTA.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sl1m_internal.h"
+
+namespace sl1m {
+
+namespace {
+thread_local std::string g_last_error;
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Everything about a problem that the host needs before any device buffer
+// exists: the grouping of pixels into (kind, sigma) segments, the permutation
+// into that order, gain flags and the tiling of both operators.
+struct Analysis {
+  int64_t n_pix = 0, n_vis = 0;
+  int precision = SL1M_PREC_FP32;
+  size_t rb = 4;
+  std::vector<int32_t> perm;  // empty = identity
+  std::vector<Segment> segs;
+  std::vector<double> layer_sigma;
+  bool has_gain = false, beam_pair = false;
+  double beam_coef = 0.0;     // separable beam: scale *= 2^(beam_coef r^2)
+  int fwd_vpl = 4, adj_ppl = 4;
+  std::vector<Chunk> fd, fg, pd, pg;
+  int64_t kchunk = 0;
+  int n_achunks = 0;
+};
+
+sl1m_status d2h(void* dst, const void* src, size_t bytes, const char* what) {
+  if (bytes == 0) return SL1M_OK;
+  hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_error(e, what);
+  return SL1M_OK;
+}
+
+size_t pixrec_bytes(size_t rb) { return rb == 8 ? sizeof(PixRec<double>) : sizeof(PixRec<float>); }
+size_t visrecD_bytes(size_t rb) {
+  return rb == 8 ? sizeof(VisRecD<double>) : sizeof(VisRecD<float>);
+}
+size_t visrecG_bytes(size_t rb) {
+  return rb == 8 ? sizeof(VisRecG<double>) : sizeof(VisRecG<float>);
+}
+
+sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
+  if (!pr) return set_error(SL1M_EINVAL, "problem is NULL");
+  if (pr->n_pix < 0 || pr->n_vis < 0) return set_error(SL1M_EINVAL, "negative size");
+  if (pr->n_pix > INT32_MAX || pr->n_vis > INT32_MAX)
+    return set_error(SL1M_EINVAL, "n_pix and n_vis must be below 2^31");
+  if (pr->precision != SL1M_PREC_FP32 && pr->precision != SL1M_PREC_FP64)
+    return set_error(SL1M_EINVAL, "unknown precision");
+  if (pr->n_pix > 0 && (!pr->l || !pr->m)) return set_error(SL1M_EINVAL, "l or m is NULL");
+  if (pr->n_vis > 0 && (!pr->u || !pr->v || !pr->w))
+    return set_error(SL1M_EINVAL, "u, v or w is NULL");
+  a.n_pix = pr->n_pix;
+  a.n_vis = pr->n_vis;
+  a.precision = pr->precision;
+  a.rb = pr->precision == SL1M_PREC_FP64 ? 8 : 4;
+  const int64_t np = pr->n_pix;
+
+  // ---- pixel kinds and scales -> segments
+  std::vector<uint8_t> kind;
+  std::vector<double> sigma;
+  if (np > 0 && (pr->sigma || pr->kind)) {
+    if (pr->sigma) {
+      sigma.resize(np);
+      sl1m_status s = d2h(sigma.data(), pr->sigma, np * sizeof(double), "read sigma");
+      if (s) return s;
+    }
+    if (pr->kind) {
+      kind.resize(np);
+      sl1m_status s = d2h(kind.data(), pr->kind, np, "read kind");
+      if (s) return s;
+    }
+  }
+  a.segs.clear();
+  a.layer_sigma.clear();
+  if (kind.empty() && sigma.empty()) {
+    a.segs.push_back(Segment{0, np, SL1M_PIX_DELTA, 0.0, -1});
+  } else {
+    // key: (kind, sigma) for Gaussian pixels; all delta pixels share one group
+    std::map<std::pair<int, double>, std::vector<int32_t>> groups;
+    std::vector<int32_t> deltas;
+    for (int64_t j = 0; j < np; ++j) {
+      const double s = sigma.empty() ? 0.0 : sigma[j];
+      int k;
+      if (!kind.empty()) {
+        k = kind[j];
+        if (k > SL1M_PIX_GAUSS_WIDE) return set_error(SL1M_EINVAL, "pixel kind out of range");
+      } else {
+        k = s > 0.0 ? SL1M_PIX_GAUSS_WIDE : SL1M_PIX_DELTA;
+      }
+      if (!(s >= 0.0) || !std::isfinite(s))
+        return set_error(SL1M_EDOMAIN, "sigma must be finite and >= 0");
+      if (k == SL1M_PIX_DELTA)
+        deltas.push_back(static_cast<int32_t>(j));
+      else
+        groups[{k, s}].push_back(static_cast<int32_t>(j));
+    }
+    if (static_cast<int>(groups.size()) > kMaxLayers)
+      return set_error(SL1M_EINVAL, "more than 16 distinct (kind, sigma) Gaussian pixel groups");
+    a.perm.reserve(np);
+    a.perm.insert(a.perm.end(), deltas.begin(), deltas.end());
+    a.segs.push_back(Segment{0, static_cast<int64_t>(deltas.size()), SL1M_PIX_DELTA, 0.0, -1});
+    int layer = 0;
+    for (auto& g : groups) {
+      Segment s{static_cast<int64_t>(a.perm.size()), static_cast<int64_t>(g.second.size()),
+                g.first.first, g.first.second, layer++};
+      a.perm.insert(a.perm.end(), g.second.begin(), g.second.end());
+      a.segs.push_back(s);
+      a.layer_sigma.push_back(g.first.second);
+    }
+    bool identity = true;
+    for (int64_t j = 0; j < np && identity; ++j) identity = a.perm[j] == j;
+    if (identity) a.perm.clear();
+  }
+
+  // ---- gains
+  a.has_gain = pr->ant_p != nullptr && pr->n_vis > 0;
+  a.beam_pair = false;
+  a.beam_coef = 0.0;
+  if (a.has_gain) {
+    if (!pr->ant_q) return set_error(SL1M_EINVAL, "ant_p given without ant_q");
+    if (pr->n_ant <= 0) return set_error(SL1M_EINVAL, "n_ant must be > 0 with antenna indices");
+    std::vector<int32_t> ap(pr->n_vis), aq(pr->n_vis);
+    sl1m_status s = d2h(ap.data(), pr->ant_p, pr->n_vis * 4, "read ant_p");
+    if (s) return s;
+    s = d2h(aq.data(), pr->ant_q, pr->n_vis * 4, "read ant_q");
+    if (s) return s;
+    for (int64_t k = 0; k < pr->n_vis; ++k)
+      if (ap[k] < 0 || ap[k] >= pr->n_ant || aq[k] < 0 || aq[k] >= pr->n_ant)
+        return set_error(SL1M_EINVAL, "antenna index out of range");
+    if (pr->ant_fwhm) {
+      std::vector<double> F(pr->n_ant);
+      s = d2h(F.data(), pr->ant_fwhm, pr->n_ant * sizeof(double), "read ant_fwhm");
+      if (s) return s;
+      bool equal = true;
+      for (double f : F) {
+        if (!(f > 0.0) || !std::isfinite(f))
+          return set_error(SL1M_EDOMAIN, "ant_fwhm must be finite and > 0");
+        equal = equal && f == F[0];
+      }
+      if (equal)
+        a.beam_coef = -4.0 / (F[0] * F[0]);  // E_p conj(E_q) beam = 2^(-4 r^2 / F^2)
+      else
+        a.beam_pair = true;
+    }
+  }
+
+  // ---- tiling
+  const int64_t nv = pr->n_vis;
+  a.fwd_vpl = nv >= 64LL * kBlock * 4 ? 4 : (nv >= 32LL * kBlock * 2 ? 2 : 1);
+  if (a.beam_pair) a.fwd_vpl = 4;
+  const int64_t vtiles = (nv + kBlock * a.fwd_vpl - 1) / (kBlock * a.fwd_vpl);
+  int64_t target_chunks = vtiles > 0 ? (4096 + vtiles - 1) / vtiles : 1;
+  target_chunks = std::max<int64_t>(1, std::min<int64_t>(64, target_chunks));
+  const int64_t cp = std::max<int64_t>(64, (np + target_chunks - 1) / std::max<int64_t>(1, target_chunks));
+  a.fd.clear();
+  a.fg.clear();
+  for (size_t si = 0; si < a.segs.size(); ++si) {
+    const Segment& s = a.segs[si];
+    for (int64_t j = s.start; j < s.start + s.count; j += cp) {
+      Chunk c{j, std::min(j + cp, s.start + s.count), s.sigma, static_cast<int32_t>(si), s.layer};
+      (s.kind == SL1M_PIX_DELTA ? a.fd : a.fg).push_back(c);
+    }
+  }
+  if (nv == 0) {
+    a.fd.clear();
+    a.fg.clear();
+  }
+  a.adj_ppl = np >= 64LL * kBlock * 4 ? 4 : (np >= 32LL * kBlock * 2 ? 2 : 1);
+  if (a.beam_pair) a.adj_ppl = 4;
+  const int64_t tp = static_cast<int64_t>(kBlock) * a.adj_ppl;
+  a.pd.clear();
+  a.pg.clear();
+  for (size_t si = 0; si < a.segs.size(); ++si) {
+    const Segment& s = a.segs[si];
+    for (int64_t j = s.start; j < s.start + s.count; j += tp) {
+      Chunk c{j, std::min(j + tp, s.start + s.count), s.sigma, static_cast<int32_t>(si), s.layer};
+      (s.kind == SL1M_PIX_DELTA ? a.pd : a.pg).push_back(c);
+    }
+  }
+  const int64_t ptiles = static_cast<int64_t>(a.pd.size() + a.pg.size());
+  if (nv > 0 && ptiles > 0) {
+    int64_t want = std::max<int64_t>(1, std::min<int64_t>(64, (4096 + ptiles - 1) / ptiles));
+    a.kchunk = std::max<int64_t>(64, (nv + want - 1) / want);
+    a.n_achunks = static_cast<int>((nv + a.kchunk - 1) / a.kchunk);
+  } else {
+    a.kchunk = 0;
+    a.n_achunks = 0;
+  }
+  return SL1M_OK;
+}
+
+struct Layout {
+  size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
+      layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, total;
+};
+
+Layout layout(const Analysis& a) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t np = static_cast<size_t>(a.n_pix), nv = static_cast<size_t>(a.n_vis), rb = a.rb;
+  const size_t nl = a.layer_sigma.size();
+  const size_t nfc = a.fd.size() + a.fg.size();
+  const size_t npt = a.pd.size() + a.pg.size();
+  L.perm = take(4 * np);
+  L.pixrec = take(pixrec_bytes(rb) * np);
+  L.pl = take(8 * np);
+  L.pm = take(8 * np);
+  L.pc3 = take(8 * np);
+  L.pc4 = take(8 * np);
+  L.pscale = take(rb * np);
+  L.pr2 = take(rb * np);
+  L.vu = take(8 * nv);
+  L.vv = take(8 * nv);
+  L.vw = take(8 * nv);
+  L.vgain = take(a.has_gain ? 2 * rb * nv : 0);
+  L.vbeta = take(a.beam_pair ? rb * nv : 0);
+  L.visrecD = take(visrecD_bytes(rb) * nv);
+  L.visrecG = take(visrecG_bytes(rb) * nl * nv);
+  L.layerDs = take(2 * rb * nl * nv);
+  L.chunks = take(sizeof(Chunk) * (nfc + npt));
+  L.fpart = take(2 * rb * nfc * nv);
+  L.apart = take(rb * static_cast<size_t>(a.n_achunks) * np);
+  L.xperm = take(rb * np);
+  L.img = take(rb * np);
+  L.res = take(2 * rb * nv);
+  L.red = take(8 * 3 * kRedBlocks + 8 * kMaxLayers);
+  L.red_out = take(8 * 8);
+  L.flag = take(sizeof(int));
+  L.total = off;
+  return L;
+}
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+#define SL1M_HIP(call, what)                           \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_error(e_, what);  \
+  } while (0)
+
+sl1m_status check_plan(sl1m_plan* p) {
+  if (!p) return set_error(SL1M_EINVAL, "plan is NULL");
+  return SL1M_OK;
+}
+
+sl1m_status read_red(sl1m_plan* p, double* host, int n, hipStream_t st) {
+  SL1M_HIP(hipMemcpyAsync(host, p->red_out, sizeof(double) * n, hipMemcpyDeviceToHost, st),
+           "read reduction");
+  SL1M_HIP(hipStreamSynchronize(st), "synchronise");
+  return SL1M_OK;
+}
+
+// V_hat = M x for x already in permuted order in p->xperm (or `xp`); result
+// combined into `out` (caller order) minus `data` if given.
+sl1m_status apply_forward(sl1m_plan* p, const void* xp, const void* data, void* out, bool recs,
+                          hipStream_t st) {
+  SL1M_HIP(timed(p, 0, st, [&] { return launch_forward(p, xp, st); }), "forward kernel");
+  SL1M_HIP(launch_forward_reduce(p, data, out, recs, st), "forward reduce");
+  return SL1M_OK;
+}
+
+sl1m_status power_iteration(sl1m_plan* p, int32_t iters, uint64_t seed, const void* x0,
+                            double* rq_out, hipStream_t st) {
+  if (x0)
+    SL1M_HIP(launch_gather(p, x0, p->xperm, st), "gather start vector");
+  else
+    SL1M_HIP(launch_splitmix_start(p, seed, p->xperm, st), "start vector");
+  double h[3];
+  SL1M_HIP(launch_dot_norm(p, p->xperm, p->xperm, st), "norm");
+  sl1m_status s = read_red(p, h, 2, st);
+  if (s) return s;
+  if (!(h[1] > 0.0)) return set_error(SL1M_EINVAL, "power iteration start vector is zero");
+  SL1M_HIP(launch_scale(p, p->xperm, p->n_pix, 1.0 / std::sqrt(h[1]), st), "normalise");
+  double rq = 0.0;
+  for (int32_t it = 0; it < iters; ++it) {
+    s = apply_forward(p, p->xperm, nullptr, p->res, true, st);
+    if (s) return s;
+    SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, st); }), "adjoint kernel");
+    SL1M_HIP(launch_adjoint_reduce(p, p->img, false, st), "adjoint reduce");
+    SL1M_HIP(launch_dot_norm(p, p->xperm, p->img, st), "rayleigh");
+    s = read_red(p, h, 2, st);
+    if (s) return s;
+    rq = h[0];
+    if (!(h[1] > 0.0)) break;
+    SL1M_HIP(launch_copy_real(p, p->img, p->xperm, p->n_pix, st), "copy");
+    SL1M_HIP(launch_scale(p, p->xperm, p->n_pix, 1.0 / std::sqrt(h[1]), st), "normalise");
+  }
+  *rq_out = rq;
+  return SL1M_OK;
+}
+
+}  // namespace
+
+sl1m_status set_error(sl1m_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+sl1m_status hip_error(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return SL1M_EHIP;
+}
+
+}  // namespace sl1m
+
+using namespace sl1m;
+
+extern "C" {
+
+const char* sl1m_last_error(void) { return g_last_error.c_str(); }
+
+const char* sl1m_version(void) { return "sl1m-mi355x 0.1 (gfx950)"; }
+
+sl1m_status sl1m_plan_workspace_bytes(const sl1m_problem* problem, size_t* bytes) {
+  try {
+    if (!bytes) return set_error(SL1M_EINVAL, "bytes is NULL");
+    Analysis a;
+    sl1m_status s = analyze(problem, a);
+    if (s) return s;
+    *bytes = layout(a).total;
+    return SL1M_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(SL1M_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
+}
+
+sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t workspace_bytes,
+                             void* stream, sl1m_plan** out) {
+  try {
+    if (!out) return set_error(SL1M_EINVAL, "out is NULL");
+    *out = nullptr;
+    Analysis a;
+    sl1m_status s = analyze(pr, a);
+    if (s) return s;
+    const Layout L = layout(a);
+    if (!workspace) return set_error(SL1M_EINVAL, "workspace is NULL");
+    if (workspace_bytes < L.total)
+      return set_error(SL1M_ENOMEM, "workspace smaller than sl1m_plan_workspace_bytes()");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return set_error(SL1M_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = S(stream);
+    int device = 0;
+    SL1M_HIP(hipGetDevice(&device), "get device");
+    sl1m_plan* p = new sl1m_plan();
+    p->device = device;
+    p->n_pix = a.n_pix;
+    p->n_vis = a.n_vis;
+    p->precision = a.precision;
+    p->real_bytes = a.rb;
+    p->has_gain = a.has_gain;
+    p->beam_pair = a.beam_pair;
+    p->segs = a.segs;
+    p->layer_sigma = a.layer_sigma;
+    p->n_layers = static_cast<int>(a.layer_sigma.size());
+    p->fwd_vpl = a.fwd_vpl;
+    p->adj_ppl = a.adj_ppl;
+    p->fchunks_delta = a.fd;
+    p->fchunks_gauss = a.fg;
+    p->n_fchunks = static_cast<int>(a.fd.size() + a.fg.size());
+    p->ptiles_delta = a.pd;
+    p->ptiles_gauss = a.pg;
+    p->adj_kchunk = a.kchunk;
+    p->n_achunks = a.n_achunks;
+    for (const Segment& sg : a.segs) {
+      if (sg.count == 0) continue;
+      (sg.kind == SL1M_PIX_DELTA ? p->any_delta : p->any_gauss) = true;
+    }
+    char* w = static_cast<char*>(workspace);
+    p->ws = w;
+    p->ws_bytes = workspace_bytes;
+    p->perm = reinterpret_cast<int32_t*>(w + L.perm);
+    p->pixrec = w + L.pixrec;
+    p->pl = reinterpret_cast<double*>(w + L.pl);
+    p->pm = reinterpret_cast<double*>(w + L.pm);
+    p->pc3 = reinterpret_cast<double*>(w + L.pc3);
+    p->pc4 = reinterpret_cast<double*>(w + L.pc4);
+    p->pscale = w + L.pscale;
+    p->pr2 = w + L.pr2;
+    p->vu = reinterpret_cast<double*>(w + L.vu);
+    p->vv = reinterpret_cast<double*>(w + L.vv);
+    p->vw = reinterpret_cast<double*>(w + L.vw);
+    p->vgain = a.has_gain ? w + L.vgain : nullptr;
+    p->vbeta = a.beam_pair ? w + L.vbeta : nullptr;
+    p->visrecD = w + L.visrecD;
+    p->visrecG = p->n_layers ? w + L.visrecG : nullptr;
+    p->layerDs = p->n_layers ? w + L.layerDs : nullptr;
+    p->d_fchunks = reinterpret_cast<Chunk*>(w + L.chunks);
+    p->d_ptiles = p->d_fchunks + p->n_fchunks;
+    p->fpart = w + L.fpart;
+    p->apart = w + L.apart;
+    p->xperm = w + L.xperm;
+    p->img = w + L.img;
+    p->res = w + L.res;
+    p->red = reinterpret_cast<double*>(w + L.red);
+    p->red_out = reinterpret_cast<double*>(w + L.red_out);
+    p->flag = reinterpret_cast<int*>(w + L.flag);
+
+    auto fail = [&](sl1m_status st_) {
+      delete p;
+      return st_;
+    };
+    // permutation, chunk tables, layer sigmas (host -> device)
+    std::vector<int32_t> perm = a.perm;
+    if (perm.empty()) {
+      perm.resize(a.n_pix);
+      for (int64_t j = 0; j < a.n_pix; ++j) perm[j] = static_cast<int32_t>(j);
+    }
+    std::vector<Chunk> chunks;
+    chunks.insert(chunks.end(), a.fd.begin(), a.fd.end());
+    chunks.insert(chunks.end(), a.fg.begin(), a.fg.end());
+    chunks.insert(chunks.end(), a.pd.begin(), a.pd.end());
+    chunks.insert(chunks.end(), a.pg.begin(), a.pg.end());
+    hipError_t e = hipSuccess;
+    if (!perm.empty())
+      e = hipMemcpyAsync(p->perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !chunks.empty())
+      e = hipMemcpyAsync(p->d_fchunks, chunks.data(), chunks.size() * sizeof(Chunk),
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && p->n_layers)
+      e = hipMemcpyAsync(p->red, a.layer_sigma.data(), p->n_layers * sizeof(double),
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_fill(p->flag, 1, sizeof(int), st);
+    if (e == hipSuccess)
+      e = launch_domain_check(p, pr->l, pr->m, pr->sigma, pr->u, pr->v, pr->w, st);
+    if (e == hipSuccess) e = launch_prep_pixels(p, pr->l, pr->m, nullptr, a.beam_coef, st);
+    if (e == hipSuccess)
+      e = launch_prep_vis(p, pr->u, pr->v, pr->w, pr->ant_p, pr->ant_q, pr->ant_gain,
+                          a.beam_pair ? pr->ant_fwhm : nullptr, pr->n_ant, st);
+    if (e == hipSuccess)
+      e = launch_fill(p->apart, static_cast<size_t>(p->n_achunks) * p->n_pix, a.rb, st);
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, p->flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(hip_error(e, "plan preparation"));
+    if (bad) {
+      set_error(SL1M_EDOMAIN,
+                std::to_string(bad) +
+                    " input(s) outside the domain (need l^2+m^2 < 1, finite sigma >= 0, finite u,v,w)");
+      return fail(SL1M_EDOMAIN);
+    }
+    *out = p;
+    return SL1M_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(SL1M_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
+}
+
+static void timing_release(sl1m_plan* p) {
+  for (auto& v : p->tev) {
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    v.clear();
+  }
+  for (int& c : p->tcount) c = 0;
+  p->timing = false;
+  p->timing_cap = 0;
+}
+
+sl1m_status sl1m_plan_destroy(sl1m_plan* plan) {
+  if (plan) timing_release(plan);
+  delete plan;
+  return SL1M_OK;
+}
+
+sl1m_status sl1m_timing_begin(sl1m_plan* p, int32_t max_launches) {
+  try {
+    if (sl1m_status s = check_plan(p)) return s;
+    if (max_launches < 1 || max_launches > (1 << 20))
+      return set_error(SL1M_EINVAL, "max_launches must be in [1, 2^20]");
+    timing_release(p);
+    for (auto& v : p->tev) {
+      v.resize(2 * static_cast<size_t>(max_launches));
+      for (hipEvent_t& e : v) SL1M_HIP(hipEventCreate(&e), "create timing event");
+    }
+    p->timing_cap = max_launches;
+    p->timing = true;
+    return SL1M_OK;
+  } catch (...) {
+    return set_error(SL1M_ENOMEM, "host allocation failed");
+  }
+}
+
+sl1m_status sl1m_timing_end(sl1m_plan* p, sl1m_timing* out) {
+  if (sl1m_status s = check_plan(p)) return s;
+  if (!out) return set_error(SL1M_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (!p->timing) return set_error(SL1M_EINVAL, "timing was not started");
+  for (int kind = 0; kind < 3; ++kind) {
+    double total = 0.0;
+    for (int i = 0; i < p->tcount[kind]; ++i) {
+      hipEvent_t a = p->tev[kind][2 * i], b = p->tev[kind][2 * i + 1];
+      SL1M_HIP(hipEventSynchronize(b), "timing sync");
+      float ms = 0.f;
+      SL1M_HIP(hipEventElapsedTime(&ms, a, b), "timing elapsed");
+      total += ms;
+    }
+    out->launches[kind] = p->tcount[kind];
+    out->total_ms[kind] = total;
+  }
+  timing_release(p);
+  return SL1M_OK;
+}
+
+sl1m_status sl1m_forward(sl1m_plan* p, const void* x, void* vis, void* stream) {
+  try {
+    if (sl1m_status s = check_plan(p)) return s;
+    if ((p->n_pix > 0 && !x) || (p->n_vis > 0 && !vis))
+      return set_error(SL1M_EINVAL, "x or vis is NULL");
+    hipStream_t st = S(stream);
+    SL1M_HIP(launch_gather(p, x, p->xperm, st), "gather");
+    return apply_forward(p, p->xperm, nullptr, vis, false, st);
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
+}
+
+sl1m_status sl1m_adjoint(sl1m_plan* p, const void* r, void* g, void* stream) {
+  try {
+    if (sl1m_status s = check_plan(p)) return s;
+    if ((p->n_vis > 0 && !r) || (p->n_pix > 0 && !g))
+      return set_error(SL1M_EINVAL, "r or g is NULL");
+    hipStream_t st = S(stream);
+    SL1M_HIP(launch_adjoint_prep(p, r, st), "adjoint prep");
+    SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, st); }), "adjoint kernel");
+    SL1M_HIP(launch_adjoint_reduce(p, g, true, st), "adjoint reduce");
+    return SL1M_OK;
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
+}
+
+sl1m_status sl1m_estimate_L(sl1m_plan* p, int32_t iters, uint64_t seed, const void* x0,
+                            double* rayleigh_out, void* stream) {
+  try {
+    if (sl1m_status s = check_plan(p)) return s;
+    if (!rayleigh_out) return set_error(SL1M_EINVAL, "rayleigh_out is NULL");
+    if (iters < 1) return set_error(SL1M_EINVAL, "iters must be >= 1");
+    if (p->n_pix == 0) return set_error(SL1M_EINVAL, "no pixels");
+    return power_iteration(p, iters, seed, x0, rayleigh_out, S(stream));
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
+}
+
+sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* prm,
+                       void* img_out, sl1m_solve_info* info, void* stream) {
+  try {
+    if (sl1m_status s = check_plan(p)) return s;
+    if (!prm || !info) return set_error(SL1M_EINVAL, "params or info is NULL");
+    if ((p->n_vis > 0 && !vis) || (p->n_pix > 0 && !img_out))
+      return set_error(SL1M_EINVAL, "vis or img_out is NULL");
+    if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda))
+      return set_error(SL1M_EINVAL, "lambda must be finite and >= 0");
+    if (prm->max_iter < 0) return set_error(SL1M_EINVAL, "max_iter must be >= 0");
+    if (!(prm->eps >= 0.0)) return set_error(SL1M_EINVAL, "eps must be >= 0");
+    if (prm->eps > 0.0 && prm->check_every < 1)
+      return set_error(SL1M_EINVAL, "check_every must be >= 1 when eps > 0");
+    std::memset(info, 0, sizeof(*info));
+    hipStream_t st = S(stream);
+    double L = prm->L;
+    if (!(L > 0.0)) {
+      const int32_t pit = prm->power_iters > 0 ? prm->power_iters : 30;
+      double rq = 0.0;
+      sl1m_status s = power_iteration(p, pit, prm->seed, nullptr, &rq, st);
+      if (s) return s;
+      const double safety = prm->L_safety > 0.0 ? prm->L_safety : 1.01;
+      L = safety * rq;
+      if (!(L > 0.0)) return set_error(SL1M_EINVAL, "estimated L is not positive (M = 0?)");
+    }
+    info->L = L;
+    const double inv_L = 1.0 / L, thr = prm->lambda / L;
+    SL1M_HIP(launch_fill(p->xperm, p->n_pix, p->real_bytes, st), "zero y");
+    SL1M_HIP(launch_fill(p->img, p->n_pix, p->real_bytes, st), "zero I");
+    double t = 1.0, F_prev = -1.0;
+    double h[3];
+    int32_t k = 0;
+    for (k = 1; k <= prm->max_iter; ++k) {
+      const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+      const double beta = (t - 1.0) / tn;
+      sl1m_status s = apply_forward(p, p->xperm, vis, p->res, true, st);
+      if (s) return s;
+      SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, st); }), "adjoint kernel");
+      SL1M_HIP(timed(p, 2, st, [&] { return launch_fista_update(p, inv_L, thr, beta, st); }),
+               "fista update");
+      t = tn;
+      if (prm->eps > 0.0 && k % prm->check_every == 0) {
+        s = apply_forward(p, p->img, vis, p->res, false, st);
+        if (s) return s;
+        SL1M_HIP(launch_objective_terms(p, p->res, p->img, st), "objective");
+        s = read_red(p, h, 3, st);
+        if (s) return s;
+        const double F = h[0] + prm->lambda * h[1];
+        if (!std::isfinite(F)) break;
+        if (F_prev >= 0.0 && std::fabs(F - F_prev) <= prm->eps * F_prev) {
+          info->converged = 1;
+          break;
+        }
+        F_prev = F;
+      }
+    }
+    info->iters = std::min(k, prm->max_iter);
+    sl1m_status s = apply_forward(p, p->img, vis, p->res, false, st);
+    if (s) return s;
+    SL1M_HIP(launch_objective_terms(p, p->res, p->img, st), "objective");
+    SL1M_HIP(launch_unpermute(p, p->img, img_out, st), "unpermute image");
+    s = read_red(p, h, 3, st);
+    if (s) return s;
+    info->l2_term = h[0];
+    info->l1_term = h[1];
+    info->nnz = static_cast<int64_t>(h[2]);
+    info->F = h[0] + prm->lambda * h[1];
+    if (!std::isfinite(info->F)) {
+      info->status = SL1M_EDIVERGED;
+      return set_error(SL1M_EDIVERGED, "objective is not finite (is L too small?)");
+    }
+    info->status = SL1M_OK;
+    return SL1M_OK;
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
+}
+
+}  // extern "C"

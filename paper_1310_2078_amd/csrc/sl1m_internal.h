@@ -1,0 +1,179 @@
+// Internal declarations of the SL1M HIP library (gfx950).
+//
+// Data layout in HBM (all inside the caller's workspace):
+//   pixels are regrouped into segments of equal (kind, sigma) and stored in
+//   that permuted order twice: as 48/64-byte records read through the scalar
+//   unit by the forward kernels (one record per loop step, uniform across the
+//   wavefront) and as structure-of-arrays read per lane by the adjoint kernels.
+//   Visibilities keep the caller's order; their static per-visibility data and
+//   the per-call residual travel in 32..88-byte records that the adjoint
+//   kernels read through the scalar unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sl1m.h"
+
+namespace sl1m {
+
+constexpr int kBlock = 256;           // threads per block (4 wavefronts)
+constexpr int kMaxLayers = 16;        // distinct (kind, sigma) groups per plan
+constexpr double kMagic = 805306368.0;  // 1.5 * 2^29: ulp 2^-23 turn; low 23 bits = fraction
+
+// Pixel record for the forward kernels (read via scalar loads).
+//   delta:    c3 = n - 1 (stable form), c4 unused
+//   gaussian: c3 = l^2 + m^2,            c4 = n - 1 + r^2/2 (0 for paraxial)
+// scale = (1/n) * per-pixel beam (separable gains) ; r2r = l^2+m^2 in R.
+template <typename R>
+struct PixRec {
+  double l, m, c3, c4;
+  R lr, mr, scale, r2r;
+};
+
+// Per-visibility record for delta adjoint kernels.
+template <typename R>
+struct VisRecD {
+  double u, v, w;
+  R rre, rim;
+};
+
+// Per-(layer, visibility) record for Gaussian adjoint kernels.  The phase is
+// psi = A l + B m + C r^2 + NW kappa + E0 (turns, E0 carries kMagic in FP32
+// mode); the taper is exp(c1 * ((u - w l)^2 + (v - w m)^2)).
+template <typename R>
+struct VisRecG {
+  double A, B, C, NW, E0;
+  R ur, vr, wr, c1;
+  R rre, rim;
+};
+
+struct Segment {
+  int64_t start, count;  // in permuted pixel order
+  int kind;              // sl1m_pixel_kind
+  double sigma;
+  int layer;             // index among Gaussian layers, -1 for delta
+};
+
+struct Chunk {           // a contiguous pixel range inside one segment
+  int64_t j0, j1;
+  double sigma;          // Gaussian scale of the segment (0 for delta)
+  int32_t seg, layer;
+};
+
+}  // namespace sl1m
+
+struct sl1m_plan {
+  int device = 0;
+  int64_t n_pix = 0, n_vis = 0;
+  int precision = SL1M_PREC_FP32;
+  size_t real_bytes = 4;      // 4 or 8
+  bool has_gain = false;      // per-visibility complex gain constants present
+  bool beam_pair = false;     // per-pair (non-separable) beam factors
+  bool any_gauss = false, any_delta = false;
+  int n_layers = 0;           // Gaussian layers
+  std::vector<sl1m::Segment> segs;
+  std::vector<double> layer_sigma;
+
+  // forward tiling: lanes own visibilities
+  int fwd_vpl = 4;            // visibilities per lane
+  int64_t fwd_vtiles = 0;
+  std::vector<sl1m::Chunk> fchunks_delta, fchunks_gauss;
+  int n_fchunks = 0;
+  // adjoint tiling: lanes own pixels
+  int adj_ppl = 4;            // pixels per lane
+  std::vector<sl1m::Chunk> ptiles_delta, ptiles_gauss;
+  int64_t adj_kchunk = 0;     // visibilities per chunk
+  int n_achunks = 0;
+
+  // device buffers (carved from the workspace)
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t* perm = nullptr;          // permuted index -> caller index
+  void* pixrec = nullptr;           // PixRec<R>[n_pix]
+  double *pl = nullptr, *pm = nullptr, *pc3 = nullptr, *pc4 = nullptr;  // SoA
+  void* pscale = nullptr;           // R[n_pix]
+  void* pr2 = nullptr;              // R[n_pix]
+  double *vu = nullptr, *vv = nullptr, *vw = nullptr;  // visibility coordinates
+  void* vgain = nullptr;            // R[2*n_vis] complex gain G_k (or null)
+  void* vbeta = nullptr;            // R[n_vis] pair beam exponent (or null)
+  void* visrecD = nullptr;          // VisRecD<R>[n_vis]
+  void* visrecG = nullptr;          // VisRecG<R>[n_layers*n_vis]
+  void* layerDs = nullptr;          // R[2*n_layers*n_vis]: D and s
+  sl1m::Chunk* d_fchunks = nullptr; // device copies of the chunk tables
+  sl1m::Chunk* d_ptiles = nullptr;
+  void* fpart = nullptr;            // R2[n_fchunks][n_vis]
+  void* apart = nullptr;            // R[n_achunks][n_pix]
+  void* xperm = nullptr;            // R[n_pix] permuted input / iterate y
+  void* img = nullptr;              // R[n_pix] iterate I
+  void* res = nullptr;              // R[2*n_vis] residual
+  double* red = nullptr;            // reduction scratch [kRedSlots]
+  double* red_out = nullptr;        // [8] final reduction results
+  int* flag = nullptr;              // domain-check counter
+
+  // kernel timing (sl1m_timing_begin/end)
+  bool timing = false;
+  int timing_cap = 0;
+  std::vector<hipEvent_t> tev[4];   // pairs (start, stop) per kind
+  int tcount[4] = {0, 0, 0, 0};
+};
+
+namespace sl1m {
+
+constexpr int kRedBlocks = 256;
+
+// Records a timing event pair around `launch` when timing is enabled.
+template <typename F>
+hipError_t timed(sl1m_plan* p, int kind, hipStream_t st, F&& launch) {
+  const bool on = p->timing && p->tcount[kind] < p->timing_cap;
+  if (on) {
+    hipError_t e = hipEventRecord(p->tev[kind][2 * p->tcount[kind]], st);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch();
+  if (on && e == hipSuccess) {
+    e = hipEventRecord(p->tev[kind][2 * p->tcount[kind] + 1], st);
+    ++p->tcount[kind];
+  }
+  return e;
+}
+
+// status helpers (sl1m_api.hip)
+sl1m_status set_error(sl1m_status s, const std::string& msg);
+sl1m_status hip_error(hipError_t e, const char* what);
+
+// kernels and launchers (sl1m_kernels.hip)
+hipError_t launch_prep_pixels(sl1m_plan* p, const double* l, const double* m,
+                              const double* ant_fwhm_dev_unused, double beam_coef,
+                              hipStream_t st);
+hipError_t launch_prep_vis(sl1m_plan* p, const double* u, const double* v, const double* w,
+                           const int32_t* ap, const int32_t* aq, const double* gain,
+                           const double* fwhm, int32_t n_ant, hipStream_t st);
+hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, hipStream_t st);
+hipError_t launch_forward(sl1m_plan* p, const void* xp, hipStream_t st);
+hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool adj_records,
+                                 hipStream_t st);
+hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, hipStream_t st);
+hipError_t launch_adjoint(sl1m_plan* p, hipStream_t st);
+hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g_out, bool unpermute, hipStream_t st);
+hipError_t launch_fista_update(sl1m_plan* p, double inv_L, double thr, double beta,
+                               hipStream_t st);
+hipError_t launch_fill(void* dst, size_t n_elems, size_t elem_bytes, hipStream_t st);
+hipError_t launch_splitmix_start(sl1m_plan* p, uint64_t seed, void* dst, hipStream_t st);
+hipError_t launch_scale(sl1m_plan* p, void* x, int64_t n, double a, hipStream_t st);
+hipError_t launch_unpermute(sl1m_plan* p, const void* src, void* dst, hipStream_t st);
+hipError_t launch_copy_real(sl1m_plan* p, const void* src, void* dst, int64_t n, hipStream_t st);
+// Fixed-order FP64 reductions; results land in p->red_out.
+//   dot_norm: red_out[0] = <a, b>, red_out[1] = <b, b>            (real [n_pix])
+//   objective: red_out[0] = 1/2 |res|^2, red_out[1] = sum I, red_out[2] = nnz
+hipError_t launch_dot_norm(sl1m_plan* p, const void* a, const void* b, hipStream_t st);
+hipError_t launch_objective_terms(sl1m_plan* p, const void* res, const void* img,
+                                  hipStream_t st);
+hipError_t launch_domain_check(sl1m_plan* p, const double* l, const double* m,
+                               const double* sigma, const double* u, const double* v,
+                               const double* w, hipStream_t st);
+
+}  // namespace sl1m

@@ -1,0 +1,999 @@
+// HIP kernels of the SL1M hot path for gfx950 (MI355X).
+//
+// Operator kernels evaluate every entry of M from its closed form when it is
+// used (Hardy 2013, Section "On-the-fly computation versus in-memory
+// computation"); nothing of M is stored.
+//
+//  * forward  V_k = sum_j M_kj x_j : a lane owns visibilities (VPL per lane,
+//    in registers, FP64 coordinates); the pixel records stream through the
+//    scalar unit, one uniform record per loop step, so every lane of a
+//    wavefront reads the same pixel without LDS traffic.
+//  * adjoint  g_j = Re sum_k conj(M_kj) r_k : a lane owns pixels (PPL per lane);
+//    visibility records (coordinates + residual) stream through the scalar unit.
+//  * Split-K: each block sums one chunk of the streamed index into its own row
+//    of a partial buffer; a reduce kernel adds the rows in a fixed order, so
+//    results are bitwise reproducible run to run.
+//
+// Phase arithmetic (FP32 precision mode): theta = u l + v m + w (n - 1) is
+// formed by three FP64 FMAs starting from kMagic = 1.5*2^29.  Every
+// intermediate then carries a unit in the last place of exactly 2^-23 turn, so
+// the low 23 bits of the result's mantissa are the fractional phase; OR-ing
+// them into the mantissa of 1.0f gives 1 + frac(theta) in [1, 2) at no extra
+// arithmetic, which v_sin_f32 / v_cos_f32 (arguments in turns) take directly.
+// The reduction is exact up to three roundings of at most 2^-24 turn each.
+//
+// FP64 precision mode: the same kernels with FP64 amplitudes and accumulators,
+// the phase reduced as theta - rint(theta) and sincospi/exp in FP64.
+#include <type_traits>
+
+#include "sl1m_internal.h"
+
+namespace sl1m {
+
+namespace {
+
+template <typename R>
+struct Cplx;
+template <>
+struct Cplx<float> {
+  using T = float2;
+};
+template <>
+struct Cplx<double> {
+  using T = double2;
+};
+template <typename R>
+using C2 = typename Cplx<R>::T;
+
+constexpr int kSeg = 64;  // inner FP32 accumulation length (two-level sums)
+
+template <typename R>
+__device__ __forceinline__ constexpr double phase_origin() {
+  return std::is_same<R, float>::value ? kMagic : 0.0;
+}
+
+// (cos 2 pi theta, sin 2 pi theta) from t = phase_origin + theta.
+__device__ __forceinline__ void phasor(double t, float& c, float& s) {
+  const uint32_t lo = static_cast<uint32_t>(__double2loint(t));
+  const float f = __uint_as_float((lo & 0x007FFFFFu) | 0x3F800000u);  // 1 + frac(theta)
+  s = __builtin_amdgcn_sinf(f);
+  c = __builtin_amdgcn_cosf(f);
+}
+__device__ __forceinline__ void phasor(double t, double& c, double& s) {
+  const double r = t - rint(t);
+  sincospi(2.0 * r, &s, &c);
+}
+
+// 2^x
+__device__ __forceinline__ float pow2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double pow2(double x) { return exp2(x); }
+
+// Natural exponent scale used with pow2 for the Gaussian taper.
+template <typename R>
+__device__ __forceinline__ constexpr double taper_scale() {
+  return 1.4426950408889634;  // log2(e): exp(x) = 2^(x log2 e)
+}
+
+// ---------------------------------------------------------------------------
+// forward kernels
+// ---------------------------------------------------------------------------
+
+template <typename R, int VPL, bool BEAM>
+__global__ __launch_bounds__(kBlock) void k_fwd_delta(
+    const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, const double* __restrict__ vu,
+    const double* __restrict__ vv, const double* __restrict__ vw, const R* __restrict__ vbeta,
+    const Chunk* __restrict__ chunks, int64_t n_vis, C2<R>* __restrict__ part, int row0) {
+  const Chunk ch = chunks[blockIdx.y];
+  const int64_t kbase = static_cast<int64_t>(blockIdx.x) * (kBlock * VPL) + threadIdx.x;
+  double u[VPL], v[VPL], w[VPL];
+  R beta[VPL], ore[VPL], oim[VPL];
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    const bool ok = k < n_vis;
+    u[i] = ok ? vu[k] : 0.0;
+    v[i] = ok ? vv[k] : 0.0;
+    w[i] = ok ? vw[k] : 0.0;
+    beta[i] = (BEAM && ok) ? vbeta[k] : R(0);
+    ore[i] = R(0);
+    oim[i] = R(0);
+  }
+  const double origin = phase_origin<R>();
+  const int jb = static_cast<int>(ch.j0), je = static_cast<int>(ch.j1);
+  for (int j0 = jb; j0 < je; j0 += kSeg) {
+    const int j1 = j0 + kSeg < je ? j0 + kSeg : je;
+    R re[VPL], im[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) re[i] = im[i] = R(0);
+    for (int j = j0; j < j1; ++j) {
+      const double pl = pix[j].l, pm = pix[j].m, pn = pix[j].c3;
+      const R a = pix[j].scale * xp[j];
+      const R r2 = BEAM ? pix[j].r2r : R(0);
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) {
+        const double t = fma(w[i], pn, fma(v[i], pm, fma(u[i], pl, origin)));
+        R c, s;
+        phasor(t, c, s);
+        const R ai = BEAM ? a * pow2(beta[i] * r2) : a;
+        re[i] = fma(ai, c, re[i]);
+        im[i] = fma(-ai, s, im[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      ore[i] += re[i];
+      oim[i] += im[i];
+    }
+  }
+  C2<R>* out = part + static_cast<int64_t>(row0 + blockIdx.y) * n_vis;
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    if (k < n_vis) {
+      C2<R> o;
+      o.x = ore[i];
+      o.y = oim[i];
+      out[k] = o;
+    }
+  }
+}
+
+// Gaussian pixels, eq. (samlm4)/(samlm5) in completed-square form:
+//   M = g (1/n) D (1 + i s) exp(-pi sigma^2 D |(u,v) - w (l,m)|^2)
+//       exp(2 pi i [D(-(u l + v m) + (w/2)(r^2 - sigma^4 rho^2)) - w kappa])
+// with s = w sigma^2, D = 1/(1+s^2), kappa = n - 1 + r^2/2 (0 for paraxial).
+// The factor D(1 + i s) is constant per (visibility, segment) and applied once
+// to the segment's sum.
+template <typename R, int VPL, bool BEAM>
+__global__ __launch_bounds__(kBlock) void k_fwd_gauss(
+    const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, const double* __restrict__ vu,
+    const double* __restrict__ vv, const double* __restrict__ vw, const R* __restrict__ vbeta,
+    const Chunk* __restrict__ chunks, int64_t n_vis, C2<R>* __restrict__ part, int row0) {
+  const Chunk ch = chunks[blockIdx.y];
+  const int64_t kbase = static_cast<int64_t>(blockIdx.x) * (kBlock * VPL) + threadIdx.x;
+  const double sig2 = ch.sigma * ch.sigma;
+  double A[VPL], B[VPL], C[VPL], NW[VPL], E0[VPL];
+  R ur[VPL], vr[VPL], wr[VPL], c1[VPL], Dd[VPL], Ds[VPL], beta[VPL], ore[VPL], oim[VPL];
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    const bool ok = k < n_vis;
+    const double u = ok ? vu[k] : 0.0, v = ok ? vv[k] : 0.0, w = ok ? vw[k] : 0.0;
+    const double s = w * sig2;
+    const double D = 1.0 / (1.0 + s * s);
+    A[i] = -D * u;
+    B[i] = -D * v;
+    C[i] = 0.5 * D * w;
+    NW[i] = -w;
+    E0[i] = phase_origin<R>() - 0.5 * D * w * sig2 * sig2 * (u * u + v * v);
+    ur[i] = static_cast<R>(u);
+    vr[i] = static_cast<R>(v);
+    wr[i] = static_cast<R>(w);
+    c1[i] = static_cast<R>(-M_PI * sig2 * D * taper_scale<R>());
+    Dd[i] = static_cast<R>(D);
+    Ds[i] = static_cast<R>(D * s);
+    beta[i] = (BEAM && ok) ? vbeta[k] : R(0);
+    ore[i] = R(0);
+    oim[i] = R(0);
+  }
+  const int jb = static_cast<int>(ch.j0), je = static_cast<int>(ch.j1);
+  for (int j0 = jb; j0 < je; j0 += kSeg) {
+    const int j1 = j0 + kSeg < je ? j0 + kSeg : je;
+    R re[VPL], im[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) re[i] = im[i] = R(0);
+    for (int j = j0; j < j1; ++j) {
+      const double pl = pix[j].l, pm = pix[j].m, pr2 = pix[j].c3, pk = pix[j].c4;
+      const R lr = pix[j].lr, mr = pix[j].mr;
+      const R a = pix[j].scale * xp[j];
+      const R r2 = BEAM ? pix[j].r2r : R(0);
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) {
+        const double t = fma(A[i], pl, fma(B[i], pm, fma(C[i], pr2, fma(NW[i], pk, E0[i]))));
+        R c, s;
+        phasor(t, c, s);
+        const R du = fma(-wr[i], lr, ur[i]);
+        const R dv = fma(-wr[i], mr, vr[i]);
+        const R q = fma(du, du, dv * dv);
+        R amp = a * pow2(c1[i] * q);
+        if (BEAM) amp *= pow2(beta[i] * r2);
+        re[i] = fma(amp, c, re[i]);
+        im[i] = fma(amp, s, im[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      ore[i] += re[i];
+      oim[i] += im[i];
+    }
+  }
+  C2<R>* out = part + static_cast<int64_t>(row0 + blockIdx.y) * n_vis;
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    if (k < n_vis) {
+      C2<R> o;
+      o.x = Dd[i] * ore[i] - Ds[i] * oim[i];
+      o.y = Ds[i] * ore[i] + Dd[i] * oim[i];
+      out[k] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint kernels
+// ---------------------------------------------------------------------------
+
+template <typename R, int PPL, bool BEAM>
+__global__ __launch_bounds__(kBlock) void k_adj_delta(
+    const VisRecD<R>* __restrict__ vrec, const R* __restrict__ vbeta, const double* __restrict__ pl,
+    const double* __restrict__ pm, const double* __restrict__ pc3, const R* __restrict__ pr2,
+    const Chunk* __restrict__ tiles, int64_t kchunk, int64_t n_vis, int64_t n_pix,
+    R* __restrict__ part) {
+  const Chunk tl = tiles[blockIdx.x];
+  const int k0 = static_cast<int>(blockIdx.y * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  double l[PPL], m[PPL], c3[PPL];
+  R r2[PPL], og[PPL];
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int64_t j = tl.j0 + threadIdx.x + static_cast<int64_t>(i) * kBlock;
+    const bool ok = j < tl.j1;
+    l[i] = ok ? pl[j] : 0.0;
+    m[i] = ok ? pm[j] : 0.0;
+    c3[i] = ok ? pc3[j] : 0.0;
+    r2[i] = (BEAM && ok) ? pr2[j] : R(0);
+    og[i] = R(0);
+  }
+  const double origin = phase_origin<R>();
+  for (int kk = k0; kk < k1; kk += kSeg) {
+    const int ke = kk + kSeg < k1 ? kk + kSeg : k1;
+    R g[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) g[i] = R(0);
+    for (int k = kk; k < ke; ++k) {
+      const double u = vrec[k].u, v = vrec[k].v, w = vrec[k].w;
+      const R rre = vrec[k].rre, rim = vrec[k].rim;
+      const R bt = BEAM ? vbeta[k] : R(0);
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) {
+        const double t = fma(c3[i], w, fma(m[i], v, fma(l[i], u, origin)));
+        R c, s;
+        phasor(t, c, s);
+        if (BEAM) {
+          const R val = fma(c, rre, -s * rim);
+          g[i] = fma(pow2(bt * r2[i]), val, g[i]);
+        } else {
+          g[i] = fma(c, rre, g[i]);
+          g[i] = fma(-s, rim, g[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) og[i] += g[i];
+  }
+  R* out = part + static_cast<int64_t>(blockIdx.y) * n_pix;
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int64_t j = tl.j0 + threadIdx.x + static_cast<int64_t>(i) * kBlock;
+    if (j < tl.j1) out[j] = og[i];
+  }
+}
+
+template <typename R, int PPL, bool BEAM>
+__global__ __launch_bounds__(kBlock) void k_adj_gauss(
+    const VisRecG<R>* __restrict__ vrec, const R* __restrict__ vbeta, const double* __restrict__ pl,
+    const double* __restrict__ pm, const double* __restrict__ pc3, const double* __restrict__ pc4,
+    const R* __restrict__ pr2, const Chunk* __restrict__ tiles, int64_t kchunk, int64_t n_vis,
+    int64_t n_pix, R* __restrict__ part) {
+  const Chunk tl = tiles[blockIdx.x];
+  const VisRecG<R>* rec = vrec + static_cast<int64_t>(tl.layer) * n_vis;
+  const int k0 = static_cast<int>(blockIdx.y * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  double l[PPL], m[PPL], c3[PPL], c4[PPL];
+  R lr[PPL], mr[PPL], r2[PPL], og[PPL];
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int64_t j = tl.j0 + threadIdx.x + static_cast<int64_t>(i) * kBlock;
+    const bool ok = j < tl.j1;
+    l[i] = ok ? pl[j] : 0.0;
+    m[i] = ok ? pm[j] : 0.0;
+    c3[i] = ok ? pc3[j] : 0.0;
+    c4[i] = ok ? pc4[j] : 0.0;
+    lr[i] = static_cast<R>(l[i]);
+    mr[i] = static_cast<R>(m[i]);
+    r2[i] = (BEAM && ok) ? pr2[j] : R(0);
+    og[i] = R(0);
+  }
+  for (int kk = k0; kk < k1; kk += kSeg) {
+    const int ke = kk + kSeg < k1 ? kk + kSeg : k1;
+    R g[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) g[i] = R(0);
+    for (int k = kk; k < ke; ++k) {
+      const double A = rec[k].A, B = rec[k].B, C = rec[k].C, NW = rec[k].NW, E0 = rec[k].E0;
+      const R ur = rec[k].ur, vr = rec[k].vr, wr = rec[k].wr, c1 = rec[k].c1;
+      const R rre = rec[k].rre, rim = rec[k].rim;
+      const R bt = BEAM ? vbeta[k] : R(0);
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) {
+        const double t = fma(A, l[i], fma(B, m[i], fma(C, c3[i], fma(NW, c4[i], E0))));
+        R c, s;
+        phasor(t, c, s);
+        const R du = fma(-wr, lr[i], ur);
+        const R dv = fma(-wr, mr[i], vr);
+        const R q = fma(du, du, dv * dv);
+        R e = pow2(c1 * q);
+        if (BEAM) e *= pow2(bt * r2[i]);
+        // Re[(c - i s)(rre + i rim)] = c rre + s rim
+        const R val = fma(c, rre, s * rim);
+        g[i] = fma(e, val, g[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) og[i] += g[i];
+  }
+  R* out = part + static_cast<int64_t>(blockIdx.y) * n_pix;
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int64_t j = tl.j0 + threadIdx.x + static_cast<int64_t>(i) * kBlock;
+    if (j < tl.j1) out[j] = og[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions of split-K partials, residual, adjoint records, FISTA update
+// ---------------------------------------------------------------------------
+
+// vis[k] = G_k * sum_c part[c][k]  (minus data[k] if data != null).  When
+// `recs` is set, also writes the adjoint records' residual:
+//   delta:  conj(G_k) vis[k];   Gaussian layer L: D(1 - i s) conj(G_k) vis[k].
+template <typename R>
+__global__ void k_fwd_reduce(const C2<R>* __restrict__ part, int n_rows, int64_t n_vis,
+                             const R* __restrict__ gain, const C2<R>* __restrict__ data,
+                             C2<R>* __restrict__ out, VisRecD<R>* __restrict__ recD,
+                             VisRecG<R>* __restrict__ recG, const R* __restrict__ layerDs,
+                             int n_layers) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n_vis) return;
+  R re = R(0), im = R(0);
+  for (int c = 0; c < n_rows; ++c) {
+    const C2<R> q = part[static_cast<int64_t>(c) * n_vis + k];
+    re += q.x;
+    im += q.y;
+  }
+  R gr = R(1), gi = R(0);
+  if (gain) {
+    gr = gain[2 * k];
+    gi = gain[2 * k + 1];
+    const R tr = gr * re - gi * im;
+    im = gr * im + gi * re;
+    re = tr;
+  }
+  if (data) {
+    re -= data[k].x;
+    im -= data[k].y;
+  }
+  if (out) {
+    C2<R> o;
+    o.x = re;
+    o.y = im;
+    out[k] = o;
+  }
+  // conj(G) * residual
+  const R cr = gr * re + gi * im;
+  const R ci = gr * im - gi * re;
+  if (recD) {
+    recD[k].rre = cr;
+    recD[k].rim = ci;
+  }
+  for (int L = 0; L < n_layers; ++L) {
+    const R D = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2];
+    const R s = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2 + 1];
+    // D (1 - i s) (cr + i ci)
+    recG[static_cast<int64_t>(L) * n_vis + k].rre = D * (cr + s * ci);
+    recG[static_cast<int64_t>(L) * n_vis + k].rim = D * (ci - s * cr);
+  }
+}
+
+// g = scale_j * sum_c part[c][j], written to out[perm[j]] (unpermute) or out[j].
+template <typename R>
+__global__ void k_adj_reduce(const R* __restrict__ part, int n_rows, int64_t n_pix,
+                             const R* __restrict__ scale, const int32_t* __restrict__ perm,
+                             R* __restrict__ out) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n_pix) return;
+  R g = R(0);
+  for (int c = 0; c < n_rows; ++c) g += part[static_cast<int64_t>(c) * n_pix + j];
+  g *= scale[j];
+  out[perm ? perm[j] : j] = g;
+}
+
+// One FISTA step on permuted vectors (Section "Implementation of SL1M"):
+//   z = y - g / L;  I_k = T^{lambda/L}(z)  (eq. threshp);  y <- I_k + beta (I_k - I_{k-1})
+// with g = scale_j * sum_c part[c][j] and beta = (t_k - 1) / t_{k+1}.
+template <typename R>
+__global__ void k_fista(const R* __restrict__ part, int n_rows, int64_t n_pix,
+                        const R* __restrict__ scale, R* __restrict__ y, R* __restrict__ img,
+                        R inv_L, R thr, R beta) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n_pix) return;
+  R g = R(0);
+  for (int c = 0; c < n_rows; ++c) g += part[static_cast<int64_t>(c) * n_pix + j];
+  g *= scale[j];
+  const R z = y[j] - g * inv_L;
+  const R in = z > thr ? z - thr : R(0);
+  const R io = img[j];
+  y[j] = in + beta * (in - io);
+  img[j] = in;
+}
+
+// ---------------------------------------------------------------------------
+// plan preparation
+// ---------------------------------------------------------------------------
+
+// Per-pixel quantities for one segment (permuted positions [j0, j0+count)).
+//   r^2 = l^2 + m^2, n = sqrt(1 - r^2), n - 1 = -r^2 / (1 + n),
+//   kappa = n - 1 + r^2/2 = -r^4 / (2 (1 + n)^2), scale = (1/n) * 2^(bc r^2)
+template <typename R>
+__global__ void k_prep_pixels(const int32_t* __restrict__ perm, const double* __restrict__ l,
+                              const double* __restrict__ m, int64_t j0, int64_t count, int kind,
+                              double beam_coef, PixRec<R>* __restrict__ rec,
+                              double* __restrict__ pl, double* __restrict__ pm,
+                              double* __restrict__ pc3, double* __restrict__ pc4,
+                              R* __restrict__ pscale, R* __restrict__ pr2) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int64_t j = j0 + t;
+  const int32_t o = perm[j];
+  const double L = l[o], Mm = m[o];
+  const double r2 = L * L + Mm * Mm;
+  const double n = sqrt(1.0 - r2);
+  const double nu = -r2 / (1.0 + n);
+  const double kappa = -(r2 * r2) / (2.0 * (1.0 + n) * (1.0 + n));
+  const double scale = (1.0 / n) * exp2(beam_coef * r2);
+  double c3, c4;
+  if (kind == SL1M_PIX_DELTA) {
+    c3 = nu;
+    c4 = 0.0;
+  } else {
+    c3 = r2;
+    c4 = kind == SL1M_PIX_GAUSS_WIDE ? kappa : 0.0;
+  }
+  PixRec<R> q;
+  q.l = L;
+  q.m = Mm;
+  q.c3 = c3;
+  q.c4 = c4;
+  q.lr = static_cast<R>(L);
+  q.mr = static_cast<R>(Mm);
+  q.scale = static_cast<R>(scale);
+  q.r2r = static_cast<R>(r2);
+  rec[j] = q;
+  pl[j] = L;
+  pm[j] = Mm;
+  pc3[j] = c3;
+  pc4[j] = c4;
+  pscale[j] = static_cast<R>(scale);
+  pr2[j] = static_cast<R>(r2);
+}
+
+// Per-visibility data: coordinates, gains G_k = c_p conj(c_q), pair-beam
+// exponent beta_k = -2 (1/F_p^2 + 1/F_q^2) (so that E_p conj(E_q) carries
+// 2^(beta_k r^2)), static parts of the adjoint records, and per Gaussian layer
+// the constants of the completed-square form.
+template <typename R>
+__global__ void k_prep_vis(const double* __restrict__ u, const double* __restrict__ v,
+                           const double* __restrict__ w, const int32_t* __restrict__ ap,
+                           const int32_t* __restrict__ aq, const double* __restrict__ gain,
+                           const double* __restrict__ fwhm, int64_t n_vis, double* __restrict__ vu,
+                           double* __restrict__ vv, double* __restrict__ vw, R* __restrict__ vgain,
+                           R* __restrict__ vbeta, VisRecD<R>* __restrict__ recD,
+                           VisRecG<R>* __restrict__ recG, R* __restrict__ layerDs,
+                           const double* __restrict__ layer_sigma, int n_layers) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n_vis) return;
+  const double U = u[k], V = v[k], W = w[k];
+  vu[k] = U;
+  vv[k] = V;
+  vw[k] = W;
+  if (vgain) {
+    const int p = ap[k], q = aq[k];
+    double pr = 1.0, pi = 0.0, qr = 1.0, qi = 0.0;
+    if (gain) {
+      pr = gain[2 * p];
+      pi = gain[2 * p + 1];
+      qr = gain[2 * q];
+      qi = gain[2 * q + 1];
+    }
+    // c_p conj(c_q)
+    vgain[2 * k] = static_cast<R>(pr * qr + pi * qi);
+    vgain[2 * k + 1] = static_cast<R>(pi * qr - pr * qi);
+  }
+  if (vbeta) {
+    const double Fp = fwhm[ap[k]], Fq = fwhm[aq[k]];
+    vbeta[k] = static_cast<R>(-2.0 * (1.0 / (Fp * Fp) + 1.0 / (Fq * Fq)));
+  }
+  if (recD) {
+    recD[k].u = U;
+    recD[k].v = V;
+    recD[k].w = W;
+    recD[k].rre = R(0);
+    recD[k].rim = R(0);
+  }
+  for (int L = 0; L < n_layers; ++L) {
+    const double sig2 = layer_sigma[L] * layer_sigma[L];
+    const double s = W * sig2;
+    const double D = 1.0 / (1.0 + s * s);
+    VisRecG<R> g;
+    g.A = -D * U;
+    g.B = -D * V;
+    g.C = 0.5 * D * W;
+    g.NW = -W;
+    g.E0 = phase_origin<R>() - 0.5 * D * W * sig2 * sig2 * (U * U + V * V);
+    g.ur = static_cast<R>(U);
+    g.vr = static_cast<R>(V);
+    g.wr = static_cast<R>(W);
+    g.c1 = static_cast<R>(-M_PI * sig2 * D * taper_scale<R>());
+    g.rre = R(0);
+    g.rim = R(0);
+    recG[static_cast<int64_t>(L) * n_vis + k] = g;
+    layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2] = static_cast<R>(D);
+    layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2 + 1] = static_cast<R>(s);
+  }
+}
+
+// Adjoint records' residual from a caller vector r (complex, caller order).
+template <typename R>
+__global__ void k_adj_prep(const C2<R>* __restrict__ r, int64_t n_vis, const R* __restrict__ gain,
+                           VisRecD<R>* __restrict__ recD, VisRecG<R>* __restrict__ recG,
+                           const R* __restrict__ layerDs, int n_layers) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n_vis) return;
+  R re = r[k].x, im = r[k].y;
+  if (gain) {
+    const R gr = gain[2 * k], gi = gain[2 * k + 1];
+    const R tr = gr * re + gi * im;
+    im = gr * im - gi * re;
+    re = tr;
+  }
+  if (recD) {
+    recD[k].rre = re;
+    recD[k].rim = im;
+  }
+  for (int L = 0; L < n_layers; ++L) {
+    const R D = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2];
+    const R s = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2 + 1];
+    recG[static_cast<int64_t>(L) * n_vis + k].rre = D * (re + s * im);
+    recG[static_cast<int64_t>(L) * n_vis + k].rim = D * (im - s * re);
+  }
+}
+
+template <typename R>
+__global__ void k_gather(const R* __restrict__ x, const int32_t* __restrict__ perm, int64_t n,
+                         R* __restrict__ xp) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n) xp[j] = x[perm[j]];
+}
+
+template <typename R>
+__global__ void k_unpermute(const R* __restrict__ src, const int32_t* __restrict__ perm, int64_t n,
+                            R* __restrict__ dst) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n) dst[perm[j]] = src[j];
+}
+
+template <typename R>
+__global__ void k_copy(const R* __restrict__ src, int64_t n, R* __restrict__ dst) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n) dst[j] = src[j];
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ dst, int64_t n) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n) dst[j] = 0u;
+}
+
+template <typename R>
+__global__ void k_scale(R* __restrict__ x, int64_t n, R a) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n) x[j] *= a;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) in counter form: the value for caller
+// pixel o is mix(seed + (o + 1) * gamma); uniform = (z >> 11) * 2^-53.
+template <typename R>
+__global__ void k_splitmix(const int32_t* __restrict__ perm, int64_t n, uint64_t seed,
+                           R* __restrict__ x) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint64_t o = static_cast<uint64_t>(perm[j]);
+  uint64_t z = seed + (o + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  x[j] = static_cast<R>(static_cast<double>(z >> 11) * 0x1.0p-53);
+}
+
+// Fixed-order two-stage FP64 reductions.  Stage 1: block b reduces the
+// contiguous range [b*per, (b+1)*per) with a tree in shared memory; stage 2:
+// one block sums the kRedBlocks partials in order.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_red_dot(const R* __restrict__ a, const R* __restrict__ b,
+                                                    int64_t n, double* __restrict__ red) {
+  __shared__ double sh[kBlock];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  double ab = 0.0, bb = 0.0;
+  for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
+    const double bv = b[j];
+    ab += static_cast<double>(a[j]) * bv;
+    bb += bv * bv;
+  }
+  ab = block_sum(ab, sh);
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    red[2 * blockIdx.x] = ab;
+    red[2 * blockIdx.x + 1] = bb;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_red_obj(const R* __restrict__ res, int64_t n_vis,
+                                                    const R* __restrict__ img, int64_t n_pix,
+                                                    double* __restrict__ red) {
+  __shared__ double sh[kBlock];
+  double rr = 0.0, s = 0.0, nz = 0.0;
+  {
+    const int64_t per = (n_vis + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = static_cast<int64_t>(blockIdx.x) * per;
+    const int64_t hi = lo + per < n_vis ? lo + per : n_vis;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+      const double a = res[2 * k], b = res[2 * k + 1];
+      rr += a * a + b * b;
+    }
+  }
+  {
+    const int64_t per = (n_pix + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = static_cast<int64_t>(blockIdx.x) * per;
+    const int64_t hi = lo + per < n_pix ? lo + per : n_pix;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
+      const double v = img[j];
+      s += v;
+      nz += v != 0.0 ? 1.0 : 0.0;
+    }
+  }
+  rr = block_sum(rr, sh);
+  s = block_sum(s, sh);
+  nz = block_sum(nz, sh);
+  if (threadIdx.x == 0) {
+    red[3 * blockIdx.x] = rr;
+    red[3 * blockIdx.x + 1] = s;
+    red[3 * blockIdx.x + 2] = nz;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_red_final(const double* __restrict__ red, int n_blocks,
+                                                      int width, double* __restrict__ out,
+                                                      double first_scale) {
+  __shared__ double sh[kBlock];
+  for (int c = 0; c < width; ++c) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) v += red[width * b + c];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) out[c] = c == 0 ? v * first_scale : v;
+  }
+}
+
+__global__ void k_domain(const double* __restrict__ l, const double* __restrict__ m,
+                         const double* __restrict__ sigma, int64_t n_pix,
+                         const double* __restrict__ u, const double* __restrict__ v,
+                         const double* __restrict__ w, int64_t n_vis, int* __restrict__ flag) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  int bad = 0;
+  if (t < n_pix) {
+    const double L = l[t], Mm = m[t];
+    const double r2 = L * L + Mm * Mm;
+    if (!(r2 < 1.0)) bad = 1;  // also catches NaN
+    if (sigma) {
+      const double s = sigma[t];
+      if (!(s >= 0.0) || !isfinite(s)) bad = 1;
+    }
+  }
+  if (t < n_vis) {
+    if (!isfinite(u[t]) || !isfinite(v[t]) || !isfinite(w[t])) bad = 1;
+  }
+  if (bad) atomicAdd(flag, 1);
+}
+
+inline unsigned grid1(int64_t n, int b = kBlock) { return static_cast<unsigned>((n + b - 1) / b); }
+
+template <typename R, int VPL, bool BEAM>
+hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st) {
+  const int64_t vt = (p->n_vis + kBlock * VPL - 1) / (kBlock * VPL);
+  C2<R>* part = static_cast<C2<R>*>(p->fpart);
+  const int nd = static_cast<int>(p->fchunks_delta.size());
+  const int ng = static_cast<int>(p->fchunks_gauss.size());
+  if (nd > 0) {
+    hipLaunchKernelGGL((k_fwd_delta<R, VPL, BEAM>), dim3(static_cast<unsigned>(vt), nd), dim3(kBlock),
+                       0, st, static_cast<const PixRec<R>*>(p->pixrec), static_cast<const R*>(xp),
+                       p->vu, p->vv, p->vw, static_cast<const R*>(p->vbeta), p->d_fchunks,
+                       p->n_vis, part, 0);
+  }
+  if (ng > 0) {
+    hipLaunchKernelGGL((k_fwd_gauss<R, VPL, BEAM>), dim3(static_cast<unsigned>(vt), ng), dim3(kBlock),
+                       0, st, static_cast<const PixRec<R>*>(p->pixrec), static_cast<const R*>(xp),
+                       p->vu, p->vv, p->vw, static_cast<const R*>(p->vbeta), p->d_fchunks + nd,
+                       p->n_vis, part, nd);
+  }
+  return hipGetLastError();
+}
+
+template <typename R, int PPL, bool BEAM>
+hipError_t adj_launch_t(sl1m_plan* p, hipStream_t st) {
+  R* part = static_cast<R*>(p->apart);
+  const int nd = static_cast<int>(p->ptiles_delta.size());
+  const int ng = static_cast<int>(p->ptiles_gauss.size());
+  if (nd > 0) {
+    hipLaunchKernelGGL((k_adj_delta<R, PPL, BEAM>), dim3(nd, p->n_achunks), dim3(kBlock), 0, st,
+                       static_cast<const VisRecD<R>*>(p->visrecD), static_cast<const R*>(p->vbeta),
+                       p->pl, p->pm, p->pc3, static_cast<const R*>(p->pr2), p->d_ptiles,
+                       p->adj_kchunk, p->n_vis, p->n_pix, part);
+  }
+  if (ng > 0) {
+    hipLaunchKernelGGL((k_adj_gauss<R, PPL, BEAM>), dim3(ng, p->n_achunks), dim3(kBlock), 0, st,
+                       static_cast<const VisRecG<R>*>(p->visrecG), static_cast<const R*>(p->vbeta),
+                       p->pl, p->pm, p->pc3, p->pc4, static_cast<const R*>(p->pr2),
+                       p->d_ptiles + nd, p->adj_kchunk, p->n_vis, p->n_pix, part);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define SL1M_DISPATCH_R(p, FN, ...) \
+  ((p)->precision == SL1M_PREC_FP64 ? FN<double>(__VA_ARGS__) : FN<float>(__VA_ARGS__))
+
+template <typename R>
+static hipError_t prep_pixels_t(sl1m_plan* p, const double* l, const double* m, double bc,
+                                hipStream_t st) {
+  for (const Segment& s : p->segs) {
+    if (s.count == 0) continue;
+    hipLaunchKernelGGL((k_prep_pixels<R>), dim3(grid1(s.count)), dim3(kBlock), 0, st, p->perm, l,
+                       m, s.start, s.count, s.kind, bc, static_cast<PixRec<R>*>(p->pixrec), p->pl,
+                       p->pm, p->pc3, p->pc4, static_cast<R*>(p->pscale), static_cast<R*>(p->pr2));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_pixels(sl1m_plan* p, const double* l, const double* m, const double*,
+                              double beam_coef, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, prep_pixels_t, p, l, m, beam_coef, st);
+}
+
+template <typename R>
+static hipError_t prep_vis_t(sl1m_plan* p, const double* u, const double* v, const double* w,
+                             const int32_t* ap, const int32_t* aq, const double* gain,
+                             const double* fwhm, const double* d_layer_sigma, hipStream_t st) {
+  if (p->n_vis == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_prep_vis<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st, u, v, w, ap, aq,
+                     gain, fwhm, p->n_vis, p->vu, p->vv, p->vw, static_cast<R*>(p->vgain),
+                     static_cast<R*>(p->vbeta), static_cast<VisRecD<R>*>(p->visrecD),
+                     static_cast<VisRecG<R>*>(p->visrecG), static_cast<R*>(p->layerDs),
+                     d_layer_sigma, p->n_layers);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_vis(sl1m_plan* p, const double* u, const double* v, const double* w,
+                           const int32_t* ap, const int32_t* aq, const double* gain,
+                           const double* fwhm, int32_t, hipStream_t st) {
+  // layer sigmas travel in the reduction scratch (plan creation only)
+  return SL1M_DISPATCH_R(p, prep_vis_t, p, u, v, w, ap, aq, gain, fwhm, p->red, st);
+}
+
+template <typename R>
+static hipError_t gather_t(sl1m_plan* p, const void* x, void* xp, hipStream_t st) {
+  if (p->n_pix == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+                     static_cast<const R*>(x), p->perm, p->n_pix, static_cast<R*>(xp));
+  return hipGetLastError();
+}
+hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, gather_t, p, x, xp, st);
+}
+
+template <typename R>
+static hipError_t forward_t(sl1m_plan* p, const void* xp, hipStream_t st) {
+  if (p->n_vis == 0 || p->n_fchunks == 0) return hipSuccess;
+  if (p->beam_pair) return fwd_launch_t<R, 4, true>(p, xp, st);
+  switch (p->fwd_vpl) {
+    case 1:
+      return fwd_launch_t<R, 1, false>(p, xp, st);
+    case 2:
+      return fwd_launch_t<R, 2, false>(p, xp, st);
+    default:
+      return fwd_launch_t<R, 4, false>(p, xp, st);
+  }
+}
+hipError_t launch_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, forward_t, p, xp, st);
+}
+
+template <typename R>
+static hipError_t fwd_reduce_t(sl1m_plan* p, const void* data, void* out, bool recs,
+                               hipStream_t st) {
+  if (p->n_vis == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_fwd_reduce<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
+                     static_cast<const C2<R>*>(p->fpart), p->n_fchunks, p->n_vis,
+                     static_cast<const R*>(p->vgain), static_cast<const C2<R>*>(data),
+                     static_cast<C2<R>*>(out),
+                     recs ? static_cast<VisRecD<R>*>(p->visrecD) : nullptr,
+                     recs ? static_cast<VisRecG<R>*>(p->visrecG) : nullptr,
+                     static_cast<const R*>(p->layerDs), recs ? p->n_layers : 0);
+  return hipGetLastError();
+}
+hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool recs,
+                                 hipStream_t st) {
+  return SL1M_DISPATCH_R(p, fwd_reduce_t, p, data, out, recs, st);
+}
+
+template <typename R>
+static hipError_t adj_prep_t(sl1m_plan* p, const void* r, hipStream_t st) {
+  if (p->n_vis == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_adj_prep<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
+                     static_cast<const C2<R>*>(r), p->n_vis, static_cast<const R*>(p->vgain),
+                     static_cast<VisRecD<R>*>(p->visrecD), static_cast<VisRecG<R>*>(p->visrecG),
+                     static_cast<const R*>(p->layerDs), p->n_layers);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, adj_prep_t, p, r, st);
+}
+
+template <typename R>
+static hipError_t adjoint_t(sl1m_plan* p, hipStream_t st) {
+  if (p->n_pix == 0 || p->n_achunks == 0) return hipSuccess;
+  if (p->beam_pair) return adj_launch_t<R, 4, true>(p, st);
+  switch (p->adj_ppl) {
+    case 1:
+      return adj_launch_t<R, 1, false>(p, st);
+    case 2:
+      return adj_launch_t<R, 2, false>(p, st);
+    default:
+      return adj_launch_t<R, 4, false>(p, st);
+  }
+}
+hipError_t launch_adjoint(sl1m_plan* p, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, adjoint_t, p, st);
+}
+
+template <typename R>
+static hipError_t adj_reduce_t(sl1m_plan* p, void* g, bool unpermute, hipStream_t st) {
+  if (p->n_pix == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_adj_reduce<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+                     static_cast<const R*>(p->apart), p->n_achunks, p->n_pix,
+                     static_cast<const R*>(p->pscale), unpermute ? p->perm : nullptr,
+                     static_cast<R*>(g));
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g, bool unpermute, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, adj_reduce_t, p, g, unpermute, st);
+}
+
+template <typename R>
+static hipError_t fista_t(sl1m_plan* p, double inv_L, double thr, double beta, hipStream_t st) {
+  if (p->n_pix == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_fista<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+                     static_cast<const R*>(p->apart), p->n_achunks, p->n_pix,
+                     static_cast<const R*>(p->pscale), static_cast<R*>(p->xperm),
+                     static_cast<R*>(p->img), static_cast<R>(inv_L), static_cast<R>(thr),
+                     static_cast<R>(beta));
+  return hipGetLastError();
+}
+hipError_t launch_fista_update(sl1m_plan* p, double inv_L, double thr, double beta,
+                               hipStream_t st) {
+  return SL1M_DISPATCH_R(p, fista_t, p, inv_L, thr, beta, st);
+}
+
+hipError_t launch_fill(void* dst, size_t n_elems, size_t elem_bytes, hipStream_t st) {
+  const int64_t words = static_cast<int64_t>((n_elems * elem_bytes + 3) / 4);
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid1(words)), dim3(kBlock), 0, st,
+                     static_cast<uint32_t*>(dst), words);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t splitmix_t(sl1m_plan* p, uint64_t seed, void* dst, hipStream_t st) {
+  if (p->n_pix == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_splitmix<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st, p->perm,
+                     p->n_pix, seed, static_cast<R*>(dst));
+  return hipGetLastError();
+}
+hipError_t launch_splitmix_start(sl1m_plan* p, uint64_t seed, void* dst, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, splitmix_t, p, seed, dst, st);
+}
+
+template <typename R>
+static hipError_t scale_t(sl1m_plan*, void* x, int64_t n, double a, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_scale<R>), dim3(grid1(n)), dim3(kBlock), 0, st, static_cast<R*>(x), n,
+                     static_cast<R>(a));
+  return hipGetLastError();
+}
+hipError_t launch_scale(sl1m_plan* p, void* x, int64_t n, double a, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, scale_t, p, x, n, a, st);
+}
+
+template <typename R>
+static hipError_t unpermute_t(sl1m_plan* p, const void* src, void* dst, hipStream_t st) {
+  if (p->n_pix == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_unpermute<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+                     static_cast<const R*>(src), p->perm, p->n_pix, static_cast<R*>(dst));
+  return hipGetLastError();
+}
+hipError_t launch_unpermute(sl1m_plan* p, const void* src, void* dst, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, unpermute_t, p, src, dst, st);
+}
+
+template <typename R>
+static hipError_t copy_t(sl1m_plan*, const void* src, void* dst, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_copy<R>), dim3(grid1(n)), dim3(kBlock), 0, st, static_cast<const R*>(src),
+                     n, static_cast<R*>(dst));
+  return hipGetLastError();
+}
+hipError_t launch_copy_real(sl1m_plan* p, const void* src, void* dst, int64_t n, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, copy_t, p, src, dst, n, st);
+}
+
+template <typename R>
+static hipError_t dot_t(sl1m_plan* p, const void* a, const void* b, hipStream_t st) {
+  hipLaunchKernelGGL((k_red_dot<R>), dim3(kRedBlocks), dim3(kBlock), 0, st,
+                     static_cast<const R*>(a), static_cast<const R*>(b), p->n_pix, p->red);
+  hipLaunchKernelGGL(k_red_final, dim3(1), dim3(kBlock), 0, st, p->red, kRedBlocks, 2, p->red_out,
+                     1.0);
+  return hipGetLastError();
+}
+hipError_t launch_dot_norm(sl1m_plan* p, const void* a, const void* b, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, dot_t, p, a, b, st);
+}
+
+template <typename R>
+static hipError_t obj_t(sl1m_plan* p, const void* res, const void* img, hipStream_t st) {
+  hipLaunchKernelGGL((k_red_obj<R>), dim3(kRedBlocks), dim3(kBlock), 0, st,
+                     static_cast<const R*>(res), p->n_vis, static_cast<const R*>(img), p->n_pix,
+                     p->red);
+  hipLaunchKernelGGL(k_red_final, dim3(1), dim3(kBlock), 0, st, p->red, kRedBlocks, 3, p->red_out,
+                     0.5);
+  return hipGetLastError();
+}
+hipError_t launch_objective_terms(sl1m_plan* p, const void* res, const void* img,
+                                  hipStream_t st) {
+  return SL1M_DISPATCH_R(p, obj_t, p, res, img, st);
+}
+
+hipError_t launch_domain_check(sl1m_plan* p, const double* l, const double* m,
+                               const double* sigma, const double* u, const double* v,
+                               const double* w, hipStream_t st) {
+  const int64_t n = p->n_pix > p->n_vis ? p->n_pix : p->n_vis;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_domain, dim3(grid1(n)), dim3(kBlock), 0, st, l, m, sigma, p->n_pix, u, v,
+                     w, p->n_vis, p->flag);
+  return hipGetLastError();
+}
+
+}  // namespace sl1m

@@ -1,0 +1,261 @@
+"""Python binding of libsl1m.so (the C ABI declared in include/sl1m.h).
+
+Argument marshalling only: every step of the operator and the solver runs in
+the library's HIP kernels.  PyTorch provides device memory and streams.  If
+the library has not been built the binding raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsl1m.so")
+
+OK, EINVAL, EDOMAIN, ENOMEM, EHIP, EDIVERGED, ECANCELLED = 0, -1, -2, -3, -4, -5, -6
+PIX_DELTA, PIX_GAUSS_PARAXIAL, PIX_GAUSS_WIDE = 0, 1, 2
+PREC_FP64, PREC_FP32 = 0, 1
+
+_lib = None
+
+
+class SL1MError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"sl1m status {status}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("n_pix", ctypes.c_int64),
+        ("l", ctypes.c_void_p),
+        ("m", ctypes.c_void_p),
+        ("sigma", ctypes.c_void_p),
+        ("kind", ctypes.c_void_p),
+        ("n_vis", ctypes.c_int64),
+        ("u", ctypes.c_void_p),
+        ("v", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+        ("ant_p", ctypes.c_void_p),
+        ("ant_q", ctypes.c_void_p),
+        ("n_ant", ctypes.c_int32),
+        ("ant_gain", ctypes.c_void_p),
+        ("ant_fwhm", ctypes.c_void_p),
+        ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [
+        ("lam", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("L", ctypes.c_double),
+        ("L_safety", ctypes.c_double),
+        ("power_iters", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("L", ctypes.c_double),
+        ("F", ctypes.c_double),
+        ("l2_term", ctypes.c_double),
+        ("l1_term", ctypes.c_double),
+        ("nnz", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsl1m.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_uint64, ctypes.c_double)
+        L.sl1m_plan_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]
+        L.sl1m_plan_create.argtypes = [ctypes.POINTER(Problem), vp, ctypes.c_size_t, vp,
+                                       ctypes.POINTER(vp)]
+        L.sl1m_plan_destroy.argtypes = [vp]
+        L.sl1m_forward.argtypes = [vp, vp, vp, vp]
+        L.sl1m_adjoint.argtypes = [vp, vp, vp, vp]
+        L.sl1m_estimate_L.argtypes = [vp, i32, u64, vp, ctypes.POINTER(dbl), vp]
+        L.sl1m_solve.argtypes = [vp, vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(SolveInfo), vp]
+        L.sl1m_timing_begin.argtypes = [vp, i32]
+        L.sl1m_timing_end.argtypes = [vp, ctypes.POINTER(Timing)]
+        L.sl1m_last_error.restype = ctypes.c_char_p
+        L.sl1m_version.restype = ctypes.c_char_p
+        for name in ("sl1m_plan_workspace_bytes", "sl1m_plan_create", "sl1m_plan_destroy",
+                     "sl1m_forward", "sl1m_adjoint", "sl1m_estimate_L", "sl1m_solve",
+                     "sl1m_timing_begin", "sl1m_timing_end"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise SL1MError(status, lib().sl1m_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(a, dtype, device):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+class Plan:
+    """A planned SL1M operator on one GPU.
+
+    Inputs are NumPy arrays or torch tensors; they are copied to the device
+    and kept alive with the plan.  ``precision`` is "fp32" (FP64 phase,
+    FP32 sincos/accumulation) or "fp64".
+    """
+
+    def __init__(self, l, m, u, v, w, sigma=None, kind=None, ant_p=None, ant_q=None,
+                 ant_gain=None, ant_fwhm=None, precision: str = "fp32", device="cuda",
+                 stream=None):
+        self.device = torch.device(device)
+        self.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
+        self.rdtype = torch.float32 if self.precision == PREC_FP32 else torch.float64
+        self.cdtype = torch.complex64 if self.precision == PREC_FP32 else torch.complex128
+        d = self.device
+        self._keep = dict(
+            l=_dev(l, torch.float64, d), m=_dev(m, torch.float64, d),
+            u=_dev(u, torch.float64, d), v=_dev(v, torch.float64, d), w=_dev(w, torch.float64, d),
+            sigma=_dev(sigma, torch.float64, d), kind=_dev(kind, torch.uint8, d),
+            ant_p=_dev(ant_p, torch.int32, d), ant_q=_dev(ant_q, torch.int32, d),
+            ant_fwhm=_dev(ant_fwhm, torch.float64, d))
+        if ant_gain is not None:
+            g = np.asarray(ant_gain.cpu() if isinstance(ant_gain, torch.Tensor) else ant_gain,
+                           np.complex128)
+            self._keep["ant_gain"] = torch.as_tensor(np.stack([g.real, g.imag], 1).ravel(),
+                                                     dtype=torch.float64, device=d)
+            n_ant = g.shape[0]
+        else:
+            self._keep["ant_gain"] = None
+            n_ant = 0
+        if ant_p is not None and n_ant == 0:
+            n_ant = int(max(int(np.max(np.asarray(ant_p))), int(np.max(np.asarray(ant_q))))) + 1
+        if ant_fwhm is not None:
+            n_ant = max(n_ant, int(np.asarray(ant_fwhm).shape[0]))
+        k = self._keep
+        self.n_pix = int(k["l"].shape[0])
+        self.n_vis = int(k["u"].shape[0])
+        self._prob = Problem(
+            n_pix=self.n_pix, l=_ptr(k["l"]), m=_ptr(k["m"]), sigma=_ptr(k["sigma"]),
+            kind=_ptr(k["kind"]), n_vis=self.n_vis, u=_ptr(k["u"]), v=_ptr(k["v"]),
+            w=_ptr(k["w"]), ant_p=_ptr(k["ant_p"]), ant_q=_ptr(k["ant_q"]), n_ant=n_ant,
+            ant_gain=_ptr(k["ant_gain"]), ant_fwhm=_ptr(k["ant_fwhm"]),
+            precision=self.precision, reserved=0)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().sl1m_plan_workspace_bytes(ctypes.byref(self._prob), ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=d)
+        h = ctypes.c_void_p()
+        _check(lib().sl1m_plan_create(ctypes.byref(self._prob), _ptr(self._ws),
+                                      ctypes.c_size_t(self._ws.numel()), _stream(stream),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, wl, precision="fp32", device="cuda", with_kinds=True):
+        kw = {}
+        if with_kinds and (np.any(wl.kind != 0) or np.any(wl.sigma != 0)):
+            kw = dict(sigma=wl.sigma, kind=wl.kind)
+        return cls(wl.l, wl.m, wl.u, wl.v, wl.w, ant_p=wl.ant_p, ant_q=wl.ant_q,
+                   ant_gain=wl.ant_gain, ant_fwhm=wl.ant_fwhm, precision=precision,
+                   device=device, **kw)
+
+    # -- operator -----------------------------------------------------------
+    def forward(self, x, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        x = _dev(x, self.rdtype, self.device)
+        if out is None:
+            out = torch.empty(self.n_vis, dtype=self.cdtype, device=self.device)
+        _check(lib().sl1m_forward(self._h, _ptr(x), _ptr(out), _stream(stream)))
+        return out
+
+    def adjoint(self, r, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        r = _dev(r, self.cdtype, self.device)
+        if out is None:
+            out = torch.empty(self.n_pix, dtype=self.rdtype, device=self.device)
+        _check(lib().sl1m_adjoint(self._h, _ptr(r), _ptr(out), _stream(stream)))
+        return out
+
+    def estimate_L(self, iters: int = 30, seed: int = 0, x0=None, stream=None) -> float:
+        rq = ctypes.c_double(0.0)
+        x0t = _dev(x0, self.rdtype, self.device)
+        _check(lib().sl1m_estimate_L(self._h, int(iters), ctypes.c_uint64(seed), _ptr(x0t),
+                                     ctypes.byref(rq), _stream(stream)))
+        return float(rq.value)
+
+    def solve(self, vis, lam: float, max_iter: int, L: float = 0.0, eps: float = 0.0,
+              check_every: int = 1, power_iters: int = 30, seed: int = 0,
+              L_safety: float = 1.01, out: Optional[torch.Tensor] = None, stream=None):
+        vis = _dev(vis, self.cdtype, self.device)
+        if out is None:
+            out = torch.empty(self.n_pix, dtype=self.rdtype, device=self.device)
+        prm = SolveParams(lam=float(lam), eps=float(eps), max_iter=int(max_iter),
+                          check_every=int(check_every), L=float(L), L_safety=float(L_safety),
+                          power_iters=int(power_iters), reserved=0, seed=ctypes.c_uint64(seed))
+        info = SolveInfo()
+        _check(lib().sl1m_solve(self._h, _ptr(vis), ctypes.byref(prm), _ptr(out),
+                                ctypes.byref(info), _stream(stream)))
+        return out, info.as_dict()
+
+    def timing_begin(self, max_launches: int = 4096):
+        _check(lib().sl1m_timing_begin(self._h, int(max_launches)))
+
+    def timing_end(self):
+        """Returns {kind: (launches, total_ms)} for forward, adjoint, fista."""
+        t = Timing()
+        _check(lib().sl1m_timing_end(self._h, ctypes.byref(t)))
+        names = ("forward", "adjoint", "fista")
+        return {n: (int(t.launches[i]), float(t.total_ms[i])) for i, n in enumerate(names)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sl1m_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def version() -> str:
+    return lib().sl1m_version().decode()

@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every symbol that include/sl1m.h
+declares; host-only argument checks behave as documented.  No GPU calls."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1310_2078_amd import sl1m
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "sl1m.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sl1m_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(sl1m.LIB_PATH):
+        pytest.fail("libsl1m.so is not built: run __graft_entry__.build()")
+    return sl1m.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared_functions()
+    assert {"sl1m_forward", "sl1m_adjoint", "sl1m_solve", "sl1m_plan_create"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/sl1m.h but not exported"
+
+
+def test_library_reports_version(L):
+    assert "gfx950" in sl1m.version()
+
+
+def test_host_argument_checks(L):
+    nbytes = ctypes.c_size_t(0)
+    assert L.sl1m_plan_workspace_bytes(None, ctypes.byref(nbytes)) == sl1m.EINVAL
+    pr = sl1m.Problem(n_pix=-1, n_vis=10, precision=sl1m.PREC_FP32)
+    assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    assert b"negative" in L.sl1m_last_error()
+    pr = sl1m.Problem(n_pix=10, n_vis=10, precision=7)
+    assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    pr = sl1m.Problem(n_pix=10, n_vis=10, precision=sl1m.PREC_FP32)   # NULL l, m
+    assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    assert L.sl1m_forward(None, None, None, None) == sl1m.EINVAL
+    assert L.sl1m_solve(None, None, None, None, None, None) == sl1m.EINVAL
+
+
+def test_workspace_size_grows_with_problem(L):
+    """Workspace sizing is host arithmetic on the sizes (delta pixels, no
+    kinds or antenna arrays, so no device access)."""
+    fake = ctypes.c_void_p(0x1000)
+
+    def size(n_pix, n_vis, prec=sl1m.PREC_FP32):
+        pr = sl1m.Problem(n_pix=n_pix, l=fake, m=fake, n_vis=n_vis, u=fake, v=fake, w=fake,
+                          precision=prec)
+        b = ctypes.c_size_t(0)
+        assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(b)) == 0
+        return b.value
+
+    a = size(1024, 2000)
+    b = size(65536, 97536)
+    assert 0 < a < b
+    assert size(1024, 2000, sl1m.PREC_FP64) > a
+    assert size(0, 0) > 0          # empty problems are legal
+    assert b < 2 ** 30             # config-2 workspace stays far below HBM

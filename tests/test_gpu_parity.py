@@ -1,0 +1,265 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+FP32 mode: norm-relative error <= 1e-5 for both operators; image error of
+the FISTA solve <= 1e-4 of the peak.  FP64 mode: <= 1e-11.  Every case
+prints its name first so a failing GPU step can be identified from the log.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1310_2078_amd import sl1m
+from paper_1310_2078_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-11}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _rand(seed, n_pix, n_vis):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n_pix)
+    r = rng.standard_normal(n_vis) + 1j * rng.standard_normal(n_vis)
+    return x, r
+
+
+def _check_ops(wl, prec, tag, x=None, r=None):
+    say(f"[case] {tag} prec={prec} n_pix={wl.n_pix} n_vis={wl.n_vis}")
+    plan = sl1m.Plan.from_workload(wl, precision=prec)
+    p = O.Problem.from_workload(wl)
+    xs, rs = _rand(99, wl.n_pix, wl.n_vis)
+    x = xs if x is None else x
+    r = rs if r is None else r
+    Vg = plan.forward(x).cpu().numpy()
+    Vo = O.forward(p, x)
+    gg = plan.adjoint(r).cpu().numpy()
+    go = O.adjoint(p, r)
+    ef, ea = rel(Vg, Vo), rel(gg, go)
+    say(f"    forward rel err {ef:.3e}  adjoint rel err {ea:.3e}")
+    assert ef <= TOL[prec] and ea <= TOL[prec]
+    return plan
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_config1_operators(prec):
+    _check_ops(W.config1(), prec, "config1")
+
+
+@pytest.mark.parametrize("kind,sigma,gains,distinct", [
+    (W.PIX_DELTA, 0.0, False, False),
+    (W.PIX_GAUSS_PARAXIAL, 3e-3, False, False),
+    (W.PIX_GAUSS_WIDE, 3e-3, False, False),
+    (W.PIX_DELTA, 0.0, True, False),
+    (W.PIX_GAUSS_WIDE, 2e-3, True, False),
+    (W.PIX_DELTA, 0.0, True, True),
+    (W.PIX_GAUSS_WIDE, 2e-3, True, True),
+])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_irregular_ragged_operators(kind, sigma, gains, distinct, prec):
+    """Off-grid pixels over +-0.2, sizes that span several tiles and end in a
+    ragged tail, every pixel kind, separable and per-pair gains."""
+    wl = W.small_random(5, 2537, 3001, kind=kind, sigma=sigma, with_gains=gains,
+                        distinct_fwhm=distinct, uv_radius=1200.0, w_sigma=300.0)
+    _check_ops(wl, prec, f"irregular kind={kind} sigma={sigma} gains={gains} distinct={distinct}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_mixed_kinds_and_layers(prec):
+    """Delta, paraxial and wide-field pixels with several sigmas in one plan,
+    interleaved in the caller's order (exercises grouping and permutation)."""
+    rng = np.random.default_rng(8)
+    wl = W.small_random(6, 3000, 1500, half_extent=0.3, with_gains=True)
+    kinds = rng.integers(0, 3, wl.n_pix).astype(np.uint8)
+    sig = rng.choice([1.5e-3, 3e-3, 6e-3], wl.n_pix)
+    sig[kinds == 0] = 0.0
+    wl.kind, wl.sigma = kinds, sig
+    _check_ops(wl, prec, "mixed kinds/layers")
+
+
+def test_config2_full_size_sampled():
+    """Config 2 at full size in the benchmark's launch configuration: sampled
+    visibilities (every 97th) and pixels (every 61st) against the oracle, and
+    the adjoint identity on the full GPU vectors."""
+    wl = W.config2()
+    say(f"[case] config2 full n_pix={wl.n_pix} n_vis={wl.n_vis}")
+    plan = sl1m.Plan.from_workload(wl)
+    p = O.Problem.from_workload(wl)
+    x, r = _rand(7, wl.n_pix, wl.n_vis)
+    Vg = plan.forward(x).cpu().numpy()
+    gg = plan.adjoint(r).cpu().numpy()
+    ks = np.arange(0, wl.n_vis, 97)
+    js = np.arange(0, wl.n_pix, 61)
+    ef = rel(Vg[ks], O.forward_rows(p, x, ks))
+    ea = rel(gg[js], O.adjoint_cols(p, r, js))
+    lhs = np.vdot(Vg.astype(np.complex128), r).real
+    rhs = float(np.dot(x, gg.astype(np.float64)))
+    ident = abs(lhs - rhs) / (np.linalg.norm(Vg) * np.linalg.norm(r))
+    say(f"    sampled forward {ef:.3e} adjoint {ea:.3e} identity {ident:.3e}")
+    assert ef <= 1e-5 and ea <= 1e-5 and ident <= 1e-5
+
+
+def test_config2_long_baseline_precision_stress():
+    """Radius-3 km array (phases ~1e4 rad): the FP64 phase with exact
+    reduction keeps the FP32 operator within tolerance."""
+    wl = W.config2(diameter_m=6000.0)
+    sub = np.arange(0, wl.n_vis, 8)
+    pix = np.arange(0, wl.n_pix, 16)
+    wl2 = W.Workload("stress", wl.l[pix], wl.m[pix], wl.sigma[pix], wl.kind[pix],
+                     wl.u[sub], wl.v[sub], wl.w[sub])
+    assert np.max(np.abs(wl2.u)) > 2500
+    _check_ops(wl2, "fp32", "config2 6km stress")
+
+
+def test_empty_inputs():
+    say("[case] empty inputs")
+    wl = W.small_random(1, 10, 20)
+    e1 = W.Workload("np0", wl.l[:0], wl.m[:0], wl.sigma[:0], wl.kind[:0], wl.u, wl.v, wl.w)
+    plan = sl1m.Plan.from_workload(e1)
+    V = plan.forward(np.zeros(0)).cpu().numpy()
+    assert V.shape == (20,) and np.all(V == 0)
+    e2 = W.Workload("nv0", wl.l, wl.m, wl.sigma, wl.kind, wl.u[:0], wl.v[:0], wl.w[:0])
+    plan = sl1m.Plan.from_workload(e2)
+    g = plan.adjoint(np.zeros(0, complex)).cpu().numpy()
+    assert g.shape == (10,) and np.all(g == 0)
+    V = plan.forward(np.ones(10)).cpu().numpy()
+    assert V.shape == (0,)
+
+
+def test_single_pixel_single_visibility():
+    say("[case] 1x1")
+    p = sl1m.Plan([0.6], [0.0], [5 / 12], [0.0], [0.0], precision="fp64")
+    V = p.forward(np.ones(1)).cpu().numpy()
+    np.testing.assert_allclose(V, [-1.25j], atol=1e-14)
+
+
+def test_unit_delta_at_phase_centre():
+    say("[case] unit delta at phase centre")
+    wl = W.config1()
+    plan = sl1m.Plan.from_workload(wl)
+    x = np.zeros(wl.n_pix)
+    x[16 + 32 * 16] = 1.0
+    V = plan.forward(x).cpu().numpy()
+    assert np.max(np.abs(V - 1.0)) < 2e-6
+
+
+def test_determinism_and_permutation_invariance():
+    say("[case] determinism / permutation")
+    wl = W.small_random(4, 4000, 5000, half_extent=0.3)
+    x, r = _rand(3, wl.n_pix, wl.n_vis)
+    plan = sl1m.Plan.from_workload(wl)
+    a = plan.forward(x).cpu().numpy()
+    b = plan.forward(x).cpu().numpy()
+    assert np.array_equal(a, b)
+    ga = plan.adjoint(r).cpu().numpy()
+    gb = plan.adjoint(r).cpu().numpy()
+    assert np.array_equal(ga, gb)
+    perm = np.random.default_rng(0).permutation(wl.n_pix)
+    plan2 = sl1m.Plan(wl.l[perm], wl.m[perm], wl.u, wl.v, wl.w)
+    c = plan2.forward(x[perm]).cpu().numpy()
+    assert rel(c, a) < 2e-6
+    gc = plan2.adjoint(r).cpu().numpy()
+    assert rel(gc, ga[perm]) < 1e-12
+
+
+def test_domain_and_argument_errors():
+    say("[case] errors")
+    with pytest.raises(sl1m.SL1MError) as e:
+        sl1m.Plan([0.8, 0.7], [0.7, 0.0], [1.0], [1.0], [1.0])
+    assert e.value.status == sl1m.EDOMAIN
+    with pytest.raises(sl1m.SL1MError) as e:
+        sl1m.Plan([0.1], [0.0], [1.0], [1.0], [float("nan")])
+    assert e.value.status == sl1m.EDOMAIN
+    with pytest.raises(sl1m.SL1MError) as e:
+        sl1m.Plan([0.1], [0.0], [1.0, 2.0], [1.0, 2.0], [1.0, 2.0], ant_p=[0, 5], ant_q=[1, 1],
+                  ant_gain=np.ones(2, complex))
+    assert e.value.status == sl1m.EINVAL
+    with pytest.raises(sl1m.SL1MError) as e:
+        sl1m.Plan([0.1], [0.0], [1.0], [1.0], [1.0], sigma=[-1.0])
+    assert e.value.status == sl1m.EDOMAIN
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_estimate_L_matches_oracle(prec):
+    say(f"[case] estimate_L {prec}")
+    wl = W.config1()
+    plan = sl1m.Plan.from_workload(wl, precision=prec)
+    op = O.Operator(O.Problem.from_workload(wl))
+    _, rq_o = O.power_iteration(op, 30, seed=0)
+    rq_g = plan.estimate_L(30, seed=0)
+    say(f"    oracle {rq_o:.10g} gpu {rq_g:.10g}")
+    assert abs(rq_g - rq_o) <= (1e-5 if prec == "fp32" else 1e-11) * rq_o
+
+
+def _config1_data():
+    wl = W.config1()
+    op = O.Operator(O.Problem.from_workload(wl))
+    V = op.forward(wl.x_true) + wl.noise
+    L, _ = O.power_iteration(op, 30, seed=0)
+    return wl, op, V, L
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_config1_solve_matches_oracle(prec):
+    """Config 1: 100 FISTA iterations with the same L; image error relative to
+    the peak, plus the reported objective terms."""
+    say(f"[case] config1 solve {prec}")
+    wl, op, V, L = _config1_data()
+    ref = O.fista(op, V, L, wl.lam, wl.n_iter)
+    plan = sl1m.Plan.from_workload(wl, precision=prec)
+    img, info = plan.solve(V, wl.lam, wl.n_iter, L=L)
+    img = img.cpu().numpy()
+    err = np.max(np.abs(img - ref.image)) / np.max(ref.image)
+    say(f"    image err/peak {err:.3e}  F gpu {info['F']:.8g} oracle {ref.F:.8g}  nnz {info['nnz']} {ref.nnz}")
+    assert err <= (1e-4 if prec == "fp32" else 1e-10)
+    assert info["iters"] == wl.n_iter and info["status"] == 0
+    assert abs(info["F"] - ref.F) <= (1e-4 if prec == "fp32" else 1e-10) * ref.F
+    assert abs(info["l1_term"] - ref.l1_term) <= 1e-4 * ref.l1_term
+
+
+def test_solve_with_estimated_L_and_termination():
+    say("[case] solve eps / estimated L")
+    wl, op, V, L = _config1_data()
+    plan = sl1m.Plan.from_workload(wl)
+    img, info = plan.solve(V, wl.lam, 100, L=0.0, power_iters=30, seed=0)
+    assert abs(info["L"] - L) <= 1e-5 * L
+    _, loose = plan.solve(V, wl.lam, 2000, L=L, eps=1e-3, check_every=5)
+    _, tight = plan.solve(V, wl.lam, 2000, L=L, eps=1e-7, check_every=5)
+    say(f"    loose {loose['iters']} tight {tight['iters']}")
+    assert loose["converged"] == 1 and loose["iters"] <= tight["iters"]
+
+
+def test_solve_diverges_with_tiny_L():
+    """A step constant far below lambda_max makes the iteration blow up: the
+    solve reports SL1M_EDIVERGED (condition forced from the host)."""
+    say("[case] divergence")
+    wl, op, V, L = _config1_data()
+    plan = sl1m.Plan.from_workload(wl)
+    with pytest.raises(sl1m.SL1MError) as e:
+        plan.solve(V, wl.lam, 80, L=0.01 * L)
+    assert e.value.status == sl1m.EDIVERGED
+
+
+def test_kernel_timing_counts_launches():
+    say("[case] timing")
+    wl, op, V, L = _config1_data()
+    plan = sl1m.Plan.from_workload(wl)
+    plan.timing_begin(64)
+    plan.solve(V, wl.lam, 5, L=L)
+    t = plan.timing_end()
+    assert t["forward"][0] == 6 and t["adjoint"][0] == 5 and t["fista"][0] == 5
+    assert t["forward"][1] > 0
