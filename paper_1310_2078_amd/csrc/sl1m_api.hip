@@ -591,6 +591,7 @@ sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* p
     const double inv_L = 1.0 / L, thr = prm->lambda / L;
     SL1M_HIP(launch_fill(p->xperm, p->n_pix, p->real_bytes, st), "zero y");
     SL1M_HIP(launch_fill(p->img, p->n_pix, p->real_bytes, st), "zero I");
+    SL1M_HIP(launch_fill(p->flag, 1, sizeof(int), st), "zero divergence flag");
     double t = 1.0, F_prev = -1.0;
     double h[3];
     int32_t k = 0;
@@ -623,15 +624,19 @@ sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* p
     if (s) return s;
     SL1M_HIP(launch_objective_terms(p, p->res, p->img, st), "objective");
     SL1M_HIP(launch_unpermute(p, p->img, img_out, st), "unpermute image");
+    int nonfinite = 0;
+    SL1M_HIP(hipMemcpyAsync(&nonfinite, p->flag, sizeof(int), hipMemcpyDeviceToHost, st),
+             "read divergence flag");
     s = read_red(p, h, 3, st);
     if (s) return s;
     info->l2_term = h[0];
     info->l1_term = h[1];
     info->nnz = static_cast<int64_t>(h[2]);
     info->F = h[0] + prm->lambda * h[1];
-    if (!std::isfinite(info->F)) {
+    if (!std::isfinite(info->F) || nonfinite) {
       info->status = SL1M_EDIVERGED;
-      return set_error(SL1M_EDIVERGED, "objective is not finite (is L too small?)");
+      return set_error(SL1M_EDIVERGED,
+                       "the iteration produced non-finite values (is L too small?)");
     }
     info->status = SL1M_OK;
     return SL1M_OK;

@@ -412,16 +412,19 @@ __global__ void k_adj_reduce(const R* __restrict__ part, int n_rows, int64_t n_p
 // One FISTA step on permuted vectors (Section "Implementation of SL1M"):
 //   z = y - g / L;  I_k = T^{lambda/L}(z)  (eq. threshp);  y <- I_k + beta (I_k - I_{k-1})
 // with g = scale_j * sum_c part[c][j] and beta = (t_k - 1) / t_{k+1}.
+// A non-finite z (overflow of a diverging iteration) would be mapped to 0 by
+// the threshold; it is recorded in *flag instead so the solve can report it.
 template <typename R>
 __global__ void k_fista(const R* __restrict__ part, int n_rows, int64_t n_pix,
                         const R* __restrict__ scale, R* __restrict__ y, R* __restrict__ img,
-                        R inv_L, R thr, R beta) {
+                        R inv_L, R thr, R beta, int* __restrict__ flag) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n_pix) return;
   R g = R(0);
   for (int c = 0; c < n_rows; ++c) g += part[static_cast<int64_t>(c) * n_pix + j];
   g *= scale[j];
   const R z = y[j] - g * inv_L;
+  if (!isfinite(z)) atomicOr(flag, 1);
   const R in = z > thr ? z - thr : R(0);
   const R io = img[j];
   y[j] = in + beta * (in - io);
@@ -900,7 +903,7 @@ static hipError_t fista_t(sl1m_plan* p, double inv_L, double thr, double beta, h
                      static_cast<const R*>(p->apart), p->n_achunks, p->n_pix,
                      static_cast<const R*>(p->pscale), static_cast<R*>(p->xperm),
                      static_cast<R*>(p->img), static_cast<R>(inv_L), static_cast<R>(thr),
-                     static_cast<R>(beta));
+                     static_cast<R>(beta), p->flag);
   return hipGetLastError();
 }
 hipError_t launch_fista_update(sl1m_plan* p, double inv_L, double thr, double beta,
