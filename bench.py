@@ -86,12 +86,85 @@ def cpu_baseline(wl, threads: int):
     }
 
 
+def _time_ops(plan, fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def extras(plan2, wl2, dev):
+    """Secondary workloads, reported beside the headline line (not in `value`)."""
+    import torch
+    from paper_1310_2078_amd import sl1m
+    from paper_1310_2078_amd import workloads as W
+    ex = {}
+    # multi-RHS: 4 right-hand sides (Stokes I, Q, U, V) at config 2's shape
+    rng = np.random.default_rng(5)
+    X = torch.as_tensor(rng.standard_normal((4, wl2.n_pix)), dtype=torch.float32, device=dev)
+    pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=4)
+    Vm = pm.forward_multi(X)
+    tf = _time_ops(pm, lambda: pm.forward_multi(X, out=Vm), 3)
+    G = torch.empty((4, wl2.n_pix), dtype=torch.float32, device=dev)
+    ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), 3)
+    ev = wl2.n_pix * wl2.n_vis
+    ex["config2_shape_multi_rhs4"] = {
+        "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+        "phasor_evals_per_s": 2 * ev / (tf + ta),
+        "rhs_products_per_s": 8 * ev / (tf + ta)}
+    del pm, Vm, G, X
+    # config 4: multiscale Gaussian pixels with direction-dependent gains
+    wl4 = W.config4()
+    t0 = time.perf_counter()
+    p4 = sl1m.Plan.from_workload(wl4, device=dev)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    x4 = torch.as_tensor(rng.standard_normal(wl4.n_pix), dtype=torch.float32, device=dev)
+    V4 = p4.forward(x4)
+    g4 = torch.empty(wl4.n_pix, dtype=torch.float32, device=dev)
+    p4.timing_begin(16)
+    tf = _time_ops(p4, lambda: p4.forward(x4, out=V4), 2)
+    ta = _time_ops(p4, lambda: p4.adjoint(V4, out=g4), 2)
+    t4 = p4.timing_end()
+    n_delta = 1024 * 1024
+    n_gauss = wl4.n_pix - n_delta
+    flops = (14 * n_delta + 26 * n_gauss) * wl4.n_vis
+    ex["config4"] = {
+        "n_pix": wl4.n_pix, "n_vis": wl4.n_vis, "plan_s": t_plan,
+        "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+        "forward_kernel_ms": t4["forward"][1] / max(t4["forward"][0], 1),
+        "adjoint_kernel_ms": t4["adjoint"][1] / max(t4["adjoint"][0], 1),
+        "evals_per_s": 2 * wl4.n_pix * wl4.n_vis / (tf + ta),
+        "fista_iteration_s_est": tf + ta,
+        "algorithmic_tflops": 2 * flops / (tf + ta) / 1e12}
+    del p4, x4, V4, g4
+    # config 1: plain SL1M in FP64 (100 iterations + 30 power steps)
+    wl1 = W.config1()
+    p1 = sl1m.Plan.from_workload(wl1, device=dev, precision="fp64")
+    V1 = p1.forward(wl1.x_true) + torch.as_tensor(wl1.noise, device=dev)
+    p1.solve(V1, wl1.lam, 5, L=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = p1.solve(V1, wl1.lam, wl1.n_iter, L=0.0, power_iters=wl1.power_iters)
+    torch.cuda.synchronize()
+    ex["config1_fp64_solve"] = {"time_s": time.perf_counter() - t0, "iterations": wl1.n_iter,
+                                "power_iterations": wl1.power_iters, "F": info["F"],
+                                "nnz": info["nnz"]}
+    return ex
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary workloads (config 4, multi-RHS, FP64 config 1)")
     ap.add_argument("--profile-ops", type=int, default=0,
                     help="after the timed region, run this many extra forward+adjoint pairs "
                          "(for profiler runs)")
@@ -201,6 +274,8 @@ def main():
             "evals_per_launch": n_pix * n_vis,
         },
     }
+    if not args.no_extras:
+        out["extras"] = extras(plan, wl, dev)
     if not args.no_cpu_baseline:
         try:
             threads = max(1, min(16, len(os.sched_getaffinity(0))))

@@ -83,6 +83,8 @@ typedef enum {
  *    evaluated at the pixel centre for Gaussian pixels (as eq. (samlm3)
  *    assumes).
  *  precision sl1m_precision.
+ *  max_rhs   largest n_rhs that sl1m_forward_multi/sl1m_adjoint_multi will be
+ *            called with (sizes the workspace); 0 means 1.
  */
 typedef struct {
   int64_t n_pix;
@@ -100,7 +102,7 @@ typedef struct {
   const double* ant_gain;
   const double* ant_fwhm;
   int32_t precision;
-  int32_t reserved;
+  int32_t max_rhs;      /* right-hand sides per operator call: 0 or 1, 2, 4, 8 */
 } sl1m_problem;
 
 typedef struct sl1m_plan sl1m_plan;
@@ -131,6 +133,22 @@ sl1m_status sl1m_forward(sl1m_plan* plan, const void* x, void* vis, void* stream
 /* Adjoint (back-projection of the gradient step, Section "Implementation of
  * SL1M"): g[j] = Re sum_k conj(M_kj) r[k].  r: complex [n_vis]; g: real [n_pix]. */
 sl1m_status sl1m_adjoint(sl1m_plan* plan, const void* r, void* g, void* stream);
+
+/* Several real right-hand sides through the same operator in one pass: the
+ * paper treats each polarisation independently through the same M (Section
+ * "Defining the direct solution"), so Stokes I, Q, U, V share every phasor.
+ *   forward: vis[r][k] = sum_j M_kj x[r][j],  x: real [n_rhs][n_pix],
+ *            vis: complex [n_rhs][n_vis];
+ *   adjoint: g[r][j] = Re sum_k conj(M_kj) rr[r][k],  rr: complex [n_rhs][n_vis],
+ *            g: real [n_rhs][n_pix].
+ * n_rhs is 1, 2, 4 or 8 and at most the plan's max_rhs (else SL1M_EINVAL).
+ * Every pixel kind and gain mode is supported; accumulation is FP32 (FP64 in
+ * SL1M_PREC_FP64 plans), each right-hand side summed in the same order as a
+ * single-right-hand-side call. */
+sl1m_status sl1m_forward_multi(sl1m_plan* plan, int32_t n_rhs, const void* x, void* vis,
+                               void* stream);
+sl1m_status sl1m_adjoint_multi(sl1m_plan* plan, int32_t n_rhs, const void* rr, void* g,
+                               void* stream);
 
 /* Largest eigenvalue of Re(M^H M) (the step-size constant L of the FISTA
  * iteration; the paper leaves the method open) by `iters` steps of power

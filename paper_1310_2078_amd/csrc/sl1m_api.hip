@@ -24,6 +24,7 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 struct Analysis {
   int64_t n_pix = 0, n_vis = 0;
   int precision = SL1M_PREC_FP32;
+  int max_rhs = 1;
   size_t rb = 4;
   std::vector<int32_t> perm;  // empty = identity
   std::vector<Segment> segs;
@@ -61,8 +62,12 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   if (pr->n_pix > 0 && (!pr->l || !pr->m)) return set_error(SL1M_EINVAL, "l or m is NULL");
   if (pr->n_vis > 0 && (!pr->u || !pr->v || !pr->w))
     return set_error(SL1M_EINVAL, "u, v or w is NULL");
+  if (pr->max_rhs != 0 && pr->max_rhs != 1 && pr->max_rhs != 2 && pr->max_rhs != 4 &&
+      pr->max_rhs != 8)
+    return set_error(SL1M_EINVAL, "max_rhs must be 0, 1, 2, 4 or 8");
   a.n_pix = pr->n_pix;
   a.n_vis = pr->n_vis;
+  a.max_rhs = pr->max_rhs > 0 ? pr->max_rhs : 1;
   a.precision = pr->precision;
   a.rb = pr->precision == SL1M_PREC_FP64 ? 8 : 4;
   const int64_t np = pr->n_pix;
@@ -203,7 +208,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
-      layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, total;
+      rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -215,6 +220,7 @@ Layout layout(const Analysis& a) {
     return o;
   };
   const size_t np = static_cast<size_t>(a.n_pix), nv = static_cast<size_t>(a.n_vis), rb = a.rb;
+  const size_t nr = static_cast<size_t>(a.max_rhs);
   const size_t nl = a.layer_sigma.size();
   const size_t nfc = a.fd.size() + a.fg.size();
   const size_t npt = a.pd.size() + a.pg.size();
@@ -233,11 +239,12 @@ Layout layout(const Analysis& a) {
   L.vbeta = take(a.beam_pair ? rb * nv : 0);
   L.visrecD = take(visrecD_bytes(rb) * nv);
   L.visrecG = take(visrecG_bytes(rb) * nl * nv);
+  L.rres = take(2 * rb * (1 + nl) * nv * nr);
   L.layerDs = take(2 * rb * nl * nv);
   L.chunks = take(sizeof(Chunk) * (nfc + npt));
-  L.fpart = take(2 * rb * nfc * nv);
-  L.apart = take(rb * static_cast<size_t>(a.n_achunks) * np);
-  L.xperm = take(rb * np);
+  L.fpart = take(2 * rb * nfc * nv * nr);
+  L.apart = take(rb * static_cast<size_t>(a.n_achunks) * np * nr);
+  L.xperm = take(rb * np * nr);
   L.img = take(rb * np);
   L.res = take(2 * rb * nv);
   L.red = take(8 * 3 * kRedBlocks + 8 * kMaxLayers);
@@ -270,16 +277,16 @@ sl1m_status read_red(sl1m_plan* p, double* host, int n, hipStream_t st) {
 // V_hat = M x for x already in permuted order in p->xperm (or `xp`); result
 // combined into `out` (caller order) minus `data` if given.
 sl1m_status apply_forward(sl1m_plan* p, const void* xp, const void* data, void* out, bool recs,
-                          hipStream_t st) {
-  SL1M_HIP(timed(p, 0, st, [&] { return launch_forward(p, xp, st); }), "forward kernel");
-  SL1M_HIP(launch_forward_reduce(p, data, out, recs, st), "forward reduce");
+                          hipStream_t st, int nr = 1) {
+  SL1M_HIP(timed(p, 0, st, [&] { return launch_forward(p, xp, nr, st); }), "forward kernel");
+  SL1M_HIP(launch_forward_reduce(p, data, out, recs, nr, st), "forward reduce");
   return SL1M_OK;
 }
 
 sl1m_status power_iteration(sl1m_plan* p, int32_t iters, uint64_t seed, const void* x0,
                             double* rq_out, hipStream_t st) {
   if (x0)
-    SL1M_HIP(launch_gather(p, x0, p->xperm, st), "gather start vector");
+    SL1M_HIP(launch_gather(p, x0, p->xperm, 1, st), "gather start vector");
   else
     SL1M_HIP(launch_splitmix_start(p, seed, p->xperm, st), "start vector");
   double h[3];
@@ -292,8 +299,8 @@ sl1m_status power_iteration(sl1m_plan* p, int32_t iters, uint64_t seed, const vo
   for (int32_t it = 0; it < iters; ++it) {
     s = apply_forward(p, p->xperm, nullptr, p->res, true, st);
     if (s) return s;
-    SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, st); }), "adjoint kernel");
-    SL1M_HIP(launch_adjoint_reduce(p, p->img, false, st), "adjoint reduce");
+    SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
+    SL1M_HIP(launch_adjoint_reduce(p, p->img, false, 1, st), "adjoint reduce");
     SL1M_HIP(launch_dot_norm(p, p->xperm, p->img, st), "rayleigh");
     s = read_red(p, h, 2, st);
     if (s) return s;
@@ -365,6 +372,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->n_pix = a.n_pix;
     p->n_vis = a.n_vis;
     p->precision = a.precision;
+    p->max_rhs = a.max_rhs;
     p->real_bytes = a.rb;
     p->has_gain = a.has_gain;
     p->beam_pair = a.beam_pair;
@@ -402,6 +410,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->vbeta = a.beam_pair ? w + L.vbeta : nullptr;
     p->visrecD = w + L.visrecD;
     p->visrecG = p->n_layers ? w + L.visrecG : nullptr;
+    p->rres = w + L.rres;
     p->layerDs = p->n_layers ? w + L.layerDs : nullptr;
     p->d_fchunks = reinterpret_cast<Chunk*>(w + L.chunks);
     p->d_ptiles = p->d_fchunks + p->n_fchunks;
@@ -446,7 +455,8 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       e = launch_prep_vis(p, pr->u, pr->v, pr->w, pr->ant_p, pr->ant_q, pr->ant_gain,
                           a.beam_pair ? pr->ant_fwhm : nullptr, pr->n_ant, st);
     if (e == hipSuccess)
-      e = launch_fill(p->apart, static_cast<size_t>(p->n_achunks) * p->n_pix, a.rb, st);
+      e = launch_fill(p->apart, static_cast<size_t>(p->n_achunks) * p->n_pix * p->max_rhs, a.rb,
+                      st);
     int bad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&bad, p->flag, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -521,32 +531,57 @@ sl1m_status sl1m_timing_end(sl1m_plan* p, sl1m_timing* out) {
   return SL1M_OK;
 }
 
-sl1m_status sl1m_forward(sl1m_plan* p, const void* x, void* vis, void* stream) {
+static sl1m_status forward_impl(sl1m_plan* p, int32_t nr, const void* x, void* vis,
+                                void* stream) {
   try {
     if (sl1m_status s = check_plan(p)) return s;
+    if (nr != 1 && nr != 2 && nr != 4 && nr != 8)
+      return set_error(SL1M_EINVAL, "n_rhs must be 1, 2, 4 or 8");
+    if (nr > p->max_rhs) return set_error(SL1M_EINVAL, "n_rhs exceeds the plan's max_rhs");
     if ((p->n_pix > 0 && !x) || (p->n_vis > 0 && !vis))
       return set_error(SL1M_EINVAL, "x or vis is NULL");
     hipStream_t st = S(stream);
-    SL1M_HIP(launch_gather(p, x, p->xperm, st), "gather");
-    return apply_forward(p, p->xperm, nullptr, vis, false, st);
+    SL1M_HIP(launch_gather(p, x, p->xperm, nr, st), "gather");
+    return apply_forward(p, p->xperm, nullptr, vis, false, st, nr);
   } catch (...) {
     return set_error(SL1M_EINVAL, "unexpected host error");
   }
 }
 
-sl1m_status sl1m_adjoint(sl1m_plan* p, const void* r, void* g, void* stream) {
+static sl1m_status adjoint_impl(sl1m_plan* p, int32_t nr, const void* r, void* g, void* stream) {
   try {
     if (sl1m_status s = check_plan(p)) return s;
+    if (nr != 1 && nr != 2 && nr != 4 && nr != 8)
+      return set_error(SL1M_EINVAL, "n_rhs must be 1, 2, 4 or 8");
+    if (nr > p->max_rhs) return set_error(SL1M_EINVAL, "n_rhs exceeds the plan's max_rhs");
     if ((p->n_vis > 0 && !r) || (p->n_pix > 0 && !g))
       return set_error(SL1M_EINVAL, "r or g is NULL");
     hipStream_t st = S(stream);
-    SL1M_HIP(launch_adjoint_prep(p, r, st), "adjoint prep");
-    SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, st); }), "adjoint kernel");
-    SL1M_HIP(launch_adjoint_reduce(p, g, true, st), "adjoint reduce");
+    SL1M_HIP(launch_adjoint_prep(p, r, nr, st), "adjoint prep");
+    SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, nr, st); }), "adjoint kernel");
+    SL1M_HIP(launch_adjoint_reduce(p, g, true, nr, st), "adjoint reduce");
     return SL1M_OK;
   } catch (...) {
     return set_error(SL1M_EINVAL, "unexpected host error");
   }
+}
+
+sl1m_status sl1m_forward(sl1m_plan* p, const void* x, void* vis, void* stream) {
+  return forward_impl(p, 1, x, vis, stream);
+}
+
+sl1m_status sl1m_adjoint(sl1m_plan* p, const void* r, void* g, void* stream) {
+  return adjoint_impl(p, 1, r, g, stream);
+}
+
+sl1m_status sl1m_forward_multi(sl1m_plan* p, int32_t n_rhs, const void* x, void* vis,
+                               void* stream) {
+  return forward_impl(p, n_rhs, x, vis, stream);
+}
+
+sl1m_status sl1m_adjoint_multi(sl1m_plan* p, int32_t n_rhs, const void* r, void* g,
+                               void* stream) {
+  return adjoint_impl(p, n_rhs, r, g, stream);
 }
 
 sl1m_status sl1m_estimate_L(sl1m_plan* p, int32_t iters, uint64_t seed, const void* x0,
@@ -600,7 +635,7 @@ sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* p
       const double beta = (t - 1.0) / tn;
       sl1m_status s = apply_forward(p, p->xperm, vis, p->res, true, st);
       if (s) return s;
-      SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, st); }), "adjoint kernel");
+      SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
       SL1M_HIP(timed(p, 2, st, [&] { return launch_fista_update(p, inv_L, thr, beta, st); }),
                "fista update");
       t = tn;

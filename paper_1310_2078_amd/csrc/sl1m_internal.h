@@ -34,11 +34,11 @@ struct PixRec {
   R lr, mr, scale, r2r;
 };
 
-// Per-visibility record for delta adjoint kernels.
+// Per-visibility coordinates for delta adjoint kernels (read via scalar
+// loads); the per-call residual lives in a separate array.
 template <typename R>
 struct VisRecD {
-  double u, v, w;
-  R rre, rim;
+  double u, v, w, pad;
 };
 
 // Per-(layer, visibility) record for Gaussian adjoint kernels.  The phase is
@@ -48,7 +48,6 @@ template <typename R>
 struct VisRecG {
   double A, B, C, NW, E0;
   R ur, vr, wr, c1;
-  R rre, rim;
 };
 
 struct Segment {
@@ -70,6 +69,7 @@ struct sl1m_plan {
   int device = 0;
   int64_t n_pix = 0, n_vis = 0;
   int precision = SL1M_PREC_FP32;
+  int max_rhs = 1;            // right-hand sides the workspace is sized for
   size_t real_bytes = 4;      // 4 or 8
   bool has_gain = false;      // per-visibility complex gain constants present
   bool beam_pair = false;     // per-pair (non-separable) beam factors
@@ -102,6 +102,7 @@ struct sl1m_plan {
   void* vbeta = nullptr;            // R[n_vis] pair beam exponent (or null)
   void* visrecD = nullptr;          // VisRecD<R>[n_vis]
   void* visrecG = nullptr;          // VisRecG<R>[n_layers*n_vis]
+  void* rres = nullptr;             // C2<R>[(1+n_layers)][n_vis][max_rhs] adjoint residuals
   void* layerDs = nullptr;          // R[2*n_layers*n_vis]: D and s
   sl1m::Chunk* d_fchunks = nullptr; // device copies of the chunk tables
   sl1m::Chunk* d_ptiles = nullptr;
@@ -152,13 +153,15 @@ hipError_t launch_prep_pixels(sl1m_plan* p, const double* l, const double* m,
 hipError_t launch_prep_vis(sl1m_plan* p, const double* u, const double* v, const double* w,
                            const int32_t* ap, const int32_t* aq, const double* gain,
                            const double* fwhm, int32_t n_ant, hipStream_t st);
-hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, hipStream_t st);
-hipError_t launch_forward(sl1m_plan* p, const void* xp, hipStream_t st);
+// nr = number of right-hand sides (1, 2, 4 or 8); vectors are [nr][n].
+hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, int nr, hipStream_t st);
+hipError_t launch_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st);
 hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool adj_records,
+                                 int nr, hipStream_t st);
+hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t st);
+hipError_t launch_adjoint(sl1m_plan* p, int nr, hipStream_t st);
+hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g_out, bool unpermute, int nr,
                                  hipStream_t st);
-hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, hipStream_t st);
-hipError_t launch_adjoint(sl1m_plan* p, hipStream_t st);
-hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g_out, bool unpermute, hipStream_t st);
 hipError_t launch_fista_update(sl1m_plan* p, double inv_L, double thr, double beta,
                                hipStream_t st);
 hipError_t launch_fill(void* dst, size_t n_elems, size_t elem_bytes, hipStream_t st);

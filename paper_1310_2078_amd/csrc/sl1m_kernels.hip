@@ -77,16 +77,20 @@ __device__ __forceinline__ constexpr double taper_scale() {
 // ---------------------------------------------------------------------------
 // forward kernels
 // ---------------------------------------------------------------------------
+//
+// NR right-hand sides share every phasor: x is [NR][n_pix] (permuted order),
+// partial rows are [NR][n_rows][n_vis].
 
-template <typename R, int VPL, bool BEAM>
+template <typename R, int VPL, bool BEAM, int NR>
 __global__ __launch_bounds__(kBlock) void k_fwd_delta(
-    const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, const double* __restrict__ vu,
-    const double* __restrict__ vv, const double* __restrict__ vw, const R* __restrict__ vbeta,
-    const Chunk* __restrict__ chunks, int64_t n_vis, C2<R>* __restrict__ part, int row0) {
+    const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, int64_t n_pix,
+    const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ vw,
+    const R* __restrict__ vbeta, const Chunk* __restrict__ chunks, int64_t n_vis,
+    C2<R>* __restrict__ part, int row0, int n_rows) {
   const Chunk ch = chunks[blockIdx.y];
   const int64_t kbase = static_cast<int64_t>(blockIdx.x) * (kBlock * VPL) + threadIdx.x;
   double u[VPL], v[VPL], w[VPL];
-  R beta[VPL], ore[VPL], oim[VPL];
+  R beta[VPL], ore[NR][VPL], oim[NR][VPL];
 #pragma unroll
   for (int i = 0; i < VPL; ++i) {
     const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
@@ -95,45 +99,58 @@ __global__ __launch_bounds__(kBlock) void k_fwd_delta(
     v[i] = ok ? vv[k] : 0.0;
     w[i] = ok ? vw[k] : 0.0;
     beta[i] = (BEAM && ok) ? vbeta[k] : R(0);
-    ore[i] = R(0);
-    oim[i] = R(0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) ore[r][i] = oim[r][i] = R(0);
   }
   const double origin = phase_origin<R>();
   const int jb = static_cast<int>(ch.j0), je = static_cast<int>(ch.j1);
   for (int j0 = jb; j0 < je; j0 += kSeg) {
     const int j1 = j0 + kSeg < je ? j0 + kSeg : je;
-    R re[VPL], im[VPL];
+    R re[NR][VPL], im[NR][VPL];
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) re[i] = im[i] = R(0);
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) re[r][i] = im[r][i] = R(0);
     for (int j = j0; j < j1; ++j) {
       const double pl = pix[j].l, pm = pix[j].m, pn = pix[j].c3;
-      const R a = pix[j].scale * xp[j];
+      R a[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) a[r] = pix[j].scale * xp[r * n_pix + j];
       const R r2 = BEAM ? pix[j].r2r : R(0);
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
         const double t = fma(w[i], pn, fma(v[i], pm, fma(u[i], pl, origin)));
         R c, s;
         phasor(t, c, s);
-        const R ai = BEAM ? a * pow2(beta[i] * r2) : a;
-        re[i] = fma(ai, c, re[i]);
-        im[i] = fma(-ai, s, im[i]);
+        const R b = BEAM ? pow2(beta[i] * r2) : R(1);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const R ai = BEAM ? a[r] * b : a[r];
+          re[r][i] = fma(ai, c, re[r][i]);
+          im[r][i] = fma(-ai, s, im[r][i]);
+        }
       }
     }
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-      ore[i] += re[i];
-      oim[i] += im[i];
-    }
-  }
-  C2<R>* out = part + static_cast<int64_t>(row0 + blockIdx.y) * n_vis;
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-  for (int i = 0; i < VPL; ++i) {
-    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
-    if (k < n_vis) {
-      C2<R> o;
-      o.x = ore[i];
-      o.y = oim[i];
-      out[k] = o;
+      for (int i = 0; i < VPL; ++i) {
+        ore[r][i] += re[r][i];
+        oim[r][i] += im[r][i];
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    C2<R>* out = part + static_cast<int64_t>(r * n_rows + row0 + blockIdx.y) * n_vis;
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+      if (k < n_vis) {
+        C2<R> o;
+        o.x = ore[r][i];
+        o.y = oim[r][i];
+        out[k] = o;
+      }
     }
   }
 }
@@ -144,16 +161,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd_delta(
 // with s = w sigma^2, D = 1/(1+s^2), kappa = n - 1 + r^2/2 (0 for paraxial).
 // The factor D(1 + i s) is constant per (visibility, segment) and applied once
 // to the segment's sum.
-template <typename R, int VPL, bool BEAM>
+template <typename R, int VPL, bool BEAM, int NR>
 __global__ __launch_bounds__(kBlock) void k_fwd_gauss(
-    const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, const double* __restrict__ vu,
-    const double* __restrict__ vv, const double* __restrict__ vw, const R* __restrict__ vbeta,
-    const Chunk* __restrict__ chunks, int64_t n_vis, C2<R>* __restrict__ part, int row0) {
+    const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, int64_t n_pix,
+    const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ vw,
+    const R* __restrict__ vbeta, const Chunk* __restrict__ chunks, int64_t n_vis,
+    C2<R>* __restrict__ part, int row0, int n_rows) {
   const Chunk ch = chunks[blockIdx.y];
   const int64_t kbase = static_cast<int64_t>(blockIdx.x) * (kBlock * VPL) + threadIdx.x;
   const double sig2 = ch.sigma * ch.sigma;
   double A[VPL], B[VPL], C[VPL], NW[VPL], E0[VPL];
-  R ur[VPL], vr[VPL], wr[VPL], c1[VPL], Dd[VPL], Ds[VPL], beta[VPL], ore[VPL], oim[VPL];
+  R ur[VPL], vr[VPL], wr[VPL], c1[VPL], Dd[VPL], Ds[VPL], beta[VPL];
+  R ore[NR][VPL], oim[NR][VPL];
 #pragma unroll
   for (int i = 0; i < VPL; ++i) {
     const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
@@ -173,19 +192,23 @@ __global__ __launch_bounds__(kBlock) void k_fwd_gauss(
     Dd[i] = static_cast<R>(D);
     Ds[i] = static_cast<R>(D * s);
     beta[i] = (BEAM && ok) ? vbeta[k] : R(0);
-    ore[i] = R(0);
-    oim[i] = R(0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) ore[r][i] = oim[r][i] = R(0);
   }
   const int jb = static_cast<int>(ch.j0), je = static_cast<int>(ch.j1);
   for (int j0 = jb; j0 < je; j0 += kSeg) {
     const int j1 = j0 + kSeg < je ? j0 + kSeg : je;
-    R re[VPL], im[VPL];
+    R re[NR][VPL], im[NR][VPL];
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) re[i] = im[i] = R(0);
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) re[r][i] = im[r][i] = R(0);
     for (int j = j0; j < j1; ++j) {
       const double pl = pix[j].l, pm = pix[j].m, pr2 = pix[j].c3, pk = pix[j].c4;
       const R lr = pix[j].lr, mr = pix[j].mr;
-      const R a = pix[j].scale * xp[j];
+      R a[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) a[r] = pix[j].scale * xp[r * n_pix + j];
       const R r2 = BEAM ? pix[j].r2r : R(0);
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
@@ -195,27 +218,36 @@ __global__ __launch_bounds__(kBlock) void k_fwd_gauss(
         const R du = fma(-wr[i], lr, ur[i]);
         const R dv = fma(-wr[i], mr, vr[i]);
         const R q = fma(du, du, dv * dv);
-        R amp = a * pow2(c1[i] * q);
-        if (BEAM) amp *= pow2(beta[i] * r2);
-        re[i] = fma(amp, c, re[i]);
-        im[i] = fma(amp, s, im[i]);
+        R e = pow2(c1[i] * q);
+        if (BEAM) e *= pow2(beta[i] * r2);
+        const R ec = e * c, es = e * s;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          re[r][i] = fma(a[r], ec, re[r][i]);
+          im[r][i] = fma(a[r], es, im[r][i]);
+        }
       }
     }
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-      ore[i] += re[i];
-      oim[i] += im[i];
-    }
-  }
-  C2<R>* out = part + static_cast<int64_t>(row0 + blockIdx.y) * n_vis;
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-  for (int i = 0; i < VPL; ++i) {
-    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
-    if (k < n_vis) {
-      C2<R> o;
-      o.x = Dd[i] * ore[i] - Ds[i] * oim[i];
-      o.y = Ds[i] * ore[i] + Dd[i] * oim[i];
-      out[k] = o;
+      for (int i = 0; i < VPL; ++i) {
+        ore[r][i] += re[r][i];
+        oim[r][i] += im[r][i];
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    C2<R>* out = part + static_cast<int64_t>(r * n_rows + row0 + blockIdx.y) * n_vis;
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+      if (k < n_vis) {
+        C2<R> o;
+        o.x = Dd[i] * ore[r][i] - Ds[i] * oim[r][i];
+        o.y = Ds[i] * ore[r][i] + Dd[i] * oim[r][i];
+        out[k] = o;
+      }
     }
   }
 }
@@ -223,37 +255,52 @@ __global__ __launch_bounds__(kBlock) void k_fwd_gauss(
 // ---------------------------------------------------------------------------
 // adjoint kernels
 // ---------------------------------------------------------------------------
+//
+// A plan's pixel tiles hold kBlock * adj_ppl pixels; a kernel with PPL pixels
+// per lane covers a tile with `sub` = adj_ppl / PPL consecutive blocks.
+// Residual records: rres[(layer_slot * n_vis + k) * NR + r] (slot 0 = delta,
+// slot 1 + L = Gaussian layer L).  Partial rows are [NR][gridDim.y][n_pix].
 
-template <typename R, int PPL, bool BEAM>
+template <typename R, int PPL, bool BEAM, int NR>
 __global__ __launch_bounds__(kBlock) void k_adj_delta(
-    const VisRecD<R>* __restrict__ vrec, const R* __restrict__ vbeta, const double* __restrict__ pl,
-    const double* __restrict__ pm, const double* __restrict__ pc3, const R* __restrict__ pr2,
-    const Chunk* __restrict__ tiles, int64_t kchunk, int64_t n_vis, int64_t n_pix,
-    R* __restrict__ part) {
-  const Chunk tl = tiles[blockIdx.x];
+    const VisRecD<R>* __restrict__ vrec, const C2<R>* __restrict__ rres,
+    const R* __restrict__ vbeta, const double* __restrict__ pl, const double* __restrict__ pm,
+    const double* __restrict__ pc3, const R* __restrict__ pr2, const Chunk* __restrict__ tiles,
+    int sub, int64_t kchunk, int64_t n_vis, int64_t n_pix, R* __restrict__ part) {
+  const Chunk tl = tiles[blockIdx.x / sub];
+  const int64_t jbase = tl.j0 + static_cast<int64_t>(blockIdx.x % sub) * (kBlock * PPL) + threadIdx.x;
   const int k0 = static_cast<int>(blockIdx.y * kchunk);
   const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
   double l[PPL], m[PPL], c3[PPL];
-  R r2[PPL], og[PPL];
+  R r2[PPL], og[NR][PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) {
-    const int64_t j = tl.j0 + threadIdx.x + static_cast<int64_t>(i) * kBlock;
+    const int64_t j = jbase + static_cast<int64_t>(i) * kBlock;
     const bool ok = j < tl.j1;
     l[i] = ok ? pl[j] : 0.0;
     m[i] = ok ? pm[j] : 0.0;
     c3[i] = ok ? pc3[j] : 0.0;
     r2[i] = (BEAM && ok) ? pr2[j] : R(0);
-    og[i] = R(0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) og[r][i] = R(0);
   }
   const double origin = phase_origin<R>();
   for (int kk = k0; kk < k1; kk += kSeg) {
     const int ke = kk + kSeg < k1 ? kk + kSeg : k1;
-    R g[PPL];
+    R g[NR][PPL];
 #pragma unroll
-    for (int i = 0; i < PPL; ++i) g[i] = R(0);
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) g[r][i] = R(0);
     for (int k = kk; k < ke; ++k) {
       const double u = vrec[k].u, v = vrec[k].v, w = vrec[k].w;
-      const R rre = vrec[k].rre, rim = vrec[k].rim;
+      R rre[NR], rim[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const C2<R> q = rres[static_cast<int64_t>(k) * NR + r];
+        rre[r] = q.x;
+        rim[r] = q.y;
+      }
       const R bt = BEAM ? vbeta[k] : R(0);
 #pragma unroll
       for (int i = 0; i < PPL; ++i) {
@@ -261,40 +308,52 @@ __global__ __launch_bounds__(kBlock) void k_adj_delta(
         R c, s;
         phasor(t, c, s);
         if (BEAM) {
-          const R val = fma(c, rre, -s * rim);
-          g[i] = fma(pow2(bt * r2[i]), val, g[i]);
-        } else {
-          g[i] = fma(c, rre, g[i]);
-          g[i] = fma(-s, rim, g[i]);
+          const R b = pow2(bt * r2[i]);
+          c *= b;
+          s *= b;
+        }
+        // Re[(c + i s)(rre + i rim)] = c rre - s rim
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          g[r][i] = fma(c, rre[r], g[r][i]);
+          g[r][i] = fma(-s, rim[r], g[r][i]);
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < PPL; ++i) og[i] += g[i];
-  }
-  R* out = part + static_cast<int64_t>(blockIdx.y) * n_pix;
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-  for (int i = 0; i < PPL; ++i) {
-    const int64_t j = tl.j0 + threadIdx.x + static_cast<int64_t>(i) * kBlock;
-    if (j < tl.j1) out[j] = og[i];
+      for (int i = 0; i < PPL; ++i) og[r][i] += g[r][i];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    R* out = part + static_cast<int64_t>(r * gridDim.y + blockIdx.y) * n_pix;
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      const int64_t j = jbase + static_cast<int64_t>(i) * kBlock;
+      if (j < tl.j1) out[j] = og[r][i];
+    }
   }
 }
 
-template <typename R, int PPL, bool BEAM>
+template <typename R, int PPL, bool BEAM, int NR>
 __global__ __launch_bounds__(kBlock) void k_adj_gauss(
-    const VisRecG<R>* __restrict__ vrec, const R* __restrict__ vbeta, const double* __restrict__ pl,
-    const double* __restrict__ pm, const double* __restrict__ pc3, const double* __restrict__ pc4,
-    const R* __restrict__ pr2, const Chunk* __restrict__ tiles, int64_t kchunk, int64_t n_vis,
-    int64_t n_pix, R* __restrict__ part) {
-  const Chunk tl = tiles[blockIdx.x];
+    const VisRecG<R>* __restrict__ vrec, const C2<R>* __restrict__ rres,
+    const R* __restrict__ vbeta, const double* __restrict__ pl, const double* __restrict__ pm,
+    const double* __restrict__ pc3, const double* __restrict__ pc4, const R* __restrict__ pr2,
+    const Chunk* __restrict__ tiles, int sub, int64_t kchunk, int64_t n_vis, int64_t n_pix,
+    R* __restrict__ part) {
+  const Chunk tl = tiles[blockIdx.x / sub];
+  const int64_t jbase = tl.j0 + static_cast<int64_t>(blockIdx.x % sub) * (kBlock * PPL) + threadIdx.x;
   const VisRecG<R>* rec = vrec + static_cast<int64_t>(tl.layer) * n_vis;
+  const C2<R>* res = rres + static_cast<int64_t>(1 + tl.layer) * n_vis * NR;
   const int k0 = static_cast<int>(blockIdx.y * kchunk);
   const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
   double l[PPL], m[PPL], c3[PPL], c4[PPL];
-  R lr[PPL], mr[PPL], r2[PPL], og[PPL];
+  R lr[PPL], mr[PPL], r2[PPL], og[NR][PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) {
-    const int64_t j = tl.j0 + threadIdx.x + static_cast<int64_t>(i) * kBlock;
+    const int64_t j = jbase + static_cast<int64_t>(i) * kBlock;
     const bool ok = j < tl.j1;
     l[i] = ok ? pl[j] : 0.0;
     m[i] = ok ? pm[j] : 0.0;
@@ -303,17 +362,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_gauss(
     lr[i] = static_cast<R>(l[i]);
     mr[i] = static_cast<R>(m[i]);
     r2[i] = (BEAM && ok) ? pr2[j] : R(0);
-    og[i] = R(0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) og[r][i] = R(0);
   }
   for (int kk = k0; kk < k1; kk += kSeg) {
     const int ke = kk + kSeg < k1 ? kk + kSeg : k1;
-    R g[PPL];
+    R g[NR][PPL];
 #pragma unroll
-    for (int i = 0; i < PPL; ++i) g[i] = R(0);
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) g[r][i] = R(0);
     for (int k = kk; k < ke; ++k) {
       const double A = rec[k].A, B = rec[k].B, C = rec[k].C, NW = rec[k].NW, E0 = rec[k].E0;
       const R ur = rec[k].ur, vr = rec[k].vr, wr = rec[k].wr, c1 = rec[k].c1;
-      const R rre = rec[k].rre, rim = rec[k].rim;
+      R rre[NR], rim[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const C2<R> q = res[static_cast<int64_t>(k) * NR + r];
+        rre[r] = q.x;
+        rim[r] = q.y;
+      }
       const R bt = BEAM ? vbeta[k] : R(0);
 #pragma unroll
       for (int i = 0; i < PPL; ++i) {
@@ -325,19 +393,28 @@ __global__ __launch_bounds__(kBlock) void k_adj_gauss(
         const R q = fma(du, du, dv * dv);
         R e = pow2(c1 * q);
         if (BEAM) e *= pow2(bt * r2[i]);
+        const R ec = e * c, es = e * s;
         // Re[(c - i s)(rre + i rim)] = c rre + s rim
-        const R val = fma(c, rre, s * rim);
-        g[i] = fma(e, val, g[i]);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          g[r][i] = fma(ec, rre[r], g[r][i]);
+          g[r][i] = fma(es, rim[r], g[r][i]);
+        }
       }
     }
 #pragma unroll
-    for (int i = 0; i < PPL; ++i) og[i] += g[i];
-  }
-  R* out = part + static_cast<int64_t>(blockIdx.y) * n_pix;
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-  for (int i = 0; i < PPL; ++i) {
-    const int64_t j = tl.j0 + threadIdx.x + static_cast<int64_t>(i) * kBlock;
-    if (j < tl.j1) out[j] = og[i];
+      for (int i = 0; i < PPL; ++i) og[r][i] += g[r][i];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    R* out = part + static_cast<int64_t>(r * gridDim.y + blockIdx.y) * n_pix;
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      const int64_t j = jbase + static_cast<int64_t>(i) * kBlock;
+      if (j < tl.j1) out[j] = og[r][i];
+    }
   }
 }
 
@@ -345,68 +422,78 @@ __global__ __launch_bounds__(kBlock) void k_adj_gauss(
 // reductions of split-K partials, residual, adjoint records, FISTA update
 // ---------------------------------------------------------------------------
 
-// vis[k] = G_k * sum_c part[c][k]  (minus data[k] if data != null).  When
-// `recs` is set, also writes the adjoint records' residual:
-//   delta:  conj(G_k) vis[k];   Gaussian layer L: D(1 - i s) conj(G_k) vis[k].
+// Writes the adjoint residual records of visibility k for right-hand side r
+// from the complex value (re, im) already including the gain G_k:
+//   slot 0 (delta):          conj(G_k) v
+//   slot 1 + L (Gaussian L): D (1 - i s) conj(G_k) v
 template <typename R>
-__global__ void k_fwd_reduce(const C2<R>* __restrict__ part, int n_rows, int64_t n_vis,
-                             const R* __restrict__ gain, const C2<R>* __restrict__ data,
-                             C2<R>* __restrict__ out, VisRecD<R>* __restrict__ recD,
-                             VisRecG<R>* __restrict__ recG, const R* __restrict__ layerDs,
-                             int n_layers) {
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= n_vis) return;
-  R re = R(0), im = R(0);
-  for (int c = 0; c < n_rows; ++c) {
-    const C2<R> q = part[static_cast<int64_t>(c) * n_vis + k];
-    re += q.x;
-    im += q.y;
-  }
-  R gr = R(1), gi = R(0);
-  if (gain) {
-    gr = gain[2 * k];
-    gi = gain[2 * k + 1];
-    const R tr = gr * re - gi * im;
-    im = gr * im + gi * re;
-    re = tr;
-  }
-  if (data) {
-    re -= data[k].x;
-    im -= data[k].y;
-  }
-  if (out) {
-    C2<R> o;
-    o.x = re;
-    o.y = im;
-    out[k] = o;
-  }
-  // conj(G) * residual
+__device__ __forceinline__ void write_res(C2<R>* __restrict__ rres, const R* __restrict__ layerDs,
+                                          int n_layers, int64_t n_vis, int nr, int64_t k, int r,
+                                          R gr, R gi, R re, R im) {
   const R cr = gr * re + gi * im;
   const R ci = gr * im - gi * re;
-  if (recD) {
-    recD[k].rre = cr;
-    recD[k].rim = ci;
-  }
+  C2<R> o;
+  o.x = cr;
+  o.y = ci;
+  rres[k * nr + r] = o;
   for (int L = 0; L < n_layers; ++L) {
     const R D = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2];
     const R s = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2 + 1];
-    // D (1 - i s) (cr + i ci)
-    recG[static_cast<int64_t>(L) * n_vis + k].rre = D * (cr + s * ci);
-    recG[static_cast<int64_t>(L) * n_vis + k].rim = D * (ci - s * cr);
+    o.x = D * (cr + s * ci);
+    o.y = D * (ci - s * cr);
+    rres[(static_cast<int64_t>(1 + L) * n_vis + k) * nr + r] = o;
   }
 }
 
-// g = scale_j * sum_c part[c][j], written to out[perm[j]] (unpermute) or out[j].
+// vis[r][k] = G_k * sum_c part[r][c][k]  (minus data[r][k] if data != null);
+// writes the adjoint residual records when `rres` is set.
 template <typename R>
-__global__ void k_adj_reduce(const R* __restrict__ part, int n_rows, int64_t n_pix,
+__global__ void k_fwd_reduce(const C2<R>* __restrict__ part, int n_rows, int64_t n_vis, int nr,
+                             const R* __restrict__ gain, const C2<R>* __restrict__ data,
+                             C2<R>* __restrict__ out, C2<R>* __restrict__ rres,
+                             const R* __restrict__ layerDs, int n_layers) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n_vis) return;
+  const R gr = gain ? gain[2 * k] : R(1), gi = gain ? gain[2 * k + 1] : R(0);
+  for (int r = 0; r < nr; ++r) {
+    R re = R(0), im = R(0);
+    for (int c = 0; c < n_rows; ++c) {
+      const C2<R> q = part[static_cast<int64_t>(r * n_rows + c) * n_vis + k];
+      re += q.x;
+      im += q.y;
+    }
+    if (gain) {
+      const R tr = gr * re - gi * im;
+      im = gr * im + gi * re;
+      re = tr;
+    }
+    if (data) {
+      re -= data[r * n_vis + k].x;
+      im -= data[r * n_vis + k].y;
+    }
+    if (out) {
+      C2<R> o;
+      o.x = re;
+      o.y = im;
+      out[r * n_vis + k] = o;
+    }
+    if (rres) write_res<R>(rres, layerDs, n_layers, n_vis, nr, k, r, gr, gi, re, im);
+  }
+}
+
+// g[r][perm[j]] (or g[r][j]) = scale_j * sum_c part[r][c][j].
+template <typename R>
+__global__ void k_adj_reduce(const R* __restrict__ part, int n_rows, int64_t n_pix, int nr,
                              const R* __restrict__ scale, const int32_t* __restrict__ perm,
                              R* __restrict__ out) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n_pix) return;
-  R g = R(0);
-  for (int c = 0; c < n_rows; ++c) g += part[static_cast<int64_t>(c) * n_pix + j];
-  g *= scale[j];
-  out[perm ? perm[j] : j] = g;
+  const int64_t dst = perm ? perm[j] : j;
+  for (int r = 0; r < nr; ++r) {
+    R g = R(0);
+    for (int c = 0; c < n_rows; ++c) g += part[static_cast<int64_t>(r * n_rows + c) * n_pix + j];
+    out[r * n_pix + dst] = g * scale[j];
+  }
 }
 
 // One FISTA step on permuted vectors (Section "Implementation of SL1M"):
@@ -521,8 +608,7 @@ __global__ void k_prep_vis(const double* __restrict__ u, const double* __restric
     recD[k].u = U;
     recD[k].v = V;
     recD[k].w = W;
-    recD[k].rre = R(0);
-    recD[k].rim = R(0);
+    recD[k].pad = 0.0;
   }
   for (int L = 0; L < n_layers; ++L) {
     const double sig2 = layer_sigma[L] * layer_sigma[L];
@@ -538,45 +624,33 @@ __global__ void k_prep_vis(const double* __restrict__ u, const double* __restric
     g.vr = static_cast<R>(V);
     g.wr = static_cast<R>(W);
     g.c1 = static_cast<R>(-M_PI * sig2 * D * taper_scale<R>());
-    g.rre = R(0);
-    g.rim = R(0);
     recG[static_cast<int64_t>(L) * n_vis + k] = g;
     layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2] = static_cast<R>(D);
     layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2 + 1] = static_cast<R>(s);
   }
 }
 
-// Adjoint records' residual from a caller vector r (complex, caller order).
+// Adjoint residual records from caller vectors r[nr][n_vis] (complex).
 template <typename R>
-__global__ void k_adj_prep(const C2<R>* __restrict__ r, int64_t n_vis, const R* __restrict__ gain,
-                           VisRecD<R>* __restrict__ recD, VisRecG<R>* __restrict__ recG,
+__global__ void k_adj_prep(const C2<R>* __restrict__ r, int64_t n_vis, int nr,
+                           const R* __restrict__ gain, C2<R>* __restrict__ rres,
                            const R* __restrict__ layerDs, int n_layers) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n_vis) return;
-  R re = r[k].x, im = r[k].y;
-  if (gain) {
-    const R gr = gain[2 * k], gi = gain[2 * k + 1];
-    const R tr = gr * re + gi * im;
-    im = gr * im - gi * re;
-    re = tr;
-  }
-  if (recD) {
-    recD[k].rre = re;
-    recD[k].rim = im;
-  }
-  for (int L = 0; L < n_layers; ++L) {
-    const R D = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2];
-    const R s = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2 + 1];
-    recG[static_cast<int64_t>(L) * n_vis + k].rre = D * (re + s * im);
-    recG[static_cast<int64_t>(L) * n_vis + k].rim = D * (im - s * re);
+  const R gr = gain ? gain[2 * k] : R(1), gi = gain ? gain[2 * k + 1] : R(0);
+  for (int q = 0; q < nr; ++q) {
+    const C2<R> v = r[q * n_vis + k];
+    write_res<R>(rres, layerDs, n_layers, n_vis, nr, k, q, gr, gi, v.x, v.y);
   }
 }
 
 template <typename R>
 __global__ void k_gather(const R* __restrict__ x, const int32_t* __restrict__ perm, int64_t n,
-                         R* __restrict__ xp) {
+                         int nr, R* __restrict__ xp) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j < n) xp[j] = x[perm[j]];
+  if (j >= n) return;
+  const int64_t o = perm[j];
+  for (int r = 0; r < nr; ++r) xp[r * n + j] = x[r * n + o];
 }
 
 template <typename R>
@@ -724,43 +798,49 @@ __global__ void k_domain(const double* __restrict__ l, const double* __restrict_
 
 inline unsigned grid1(int64_t n, int b = kBlock) { return static_cast<unsigned>((n + b - 1) / b); }
 
-template <typename R, int VPL, bool BEAM>
+template <typename R, int VPL, bool BEAM, int NR>
 hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st) {
   const int64_t vt = (p->n_vis + kBlock * VPL - 1) / (kBlock * VPL);
   C2<R>* part = static_cast<C2<R>*>(p->fpart);
   const int nd = static_cast<int>(p->fchunks_delta.size());
   const int ng = static_cast<int>(p->fchunks_gauss.size());
+  const int rows = p->n_fchunks;
   if (nd > 0) {
-    hipLaunchKernelGGL((k_fwd_delta<R, VPL, BEAM>), dim3(static_cast<unsigned>(vt), nd), dim3(kBlock),
-                       0, st, static_cast<const PixRec<R>*>(p->pixrec), static_cast<const R*>(xp),
-                       p->vu, p->vv, p->vw, static_cast<const R*>(p->vbeta), p->d_fchunks,
-                       p->n_vis, part, 0);
+    hipLaunchKernelGGL((k_fwd_delta<R, VPL, BEAM, NR>), dim3(static_cast<unsigned>(vt), nd),
+                       dim3(kBlock), 0, st, static_cast<const PixRec<R>*>(p->pixrec),
+                       static_cast<const R*>(xp), p->n_pix, p->vu, p->vv, p->vw,
+                       static_cast<const R*>(p->vbeta), p->d_fchunks, p->n_vis, part, 0, rows);
   }
   if (ng > 0) {
-    hipLaunchKernelGGL((k_fwd_gauss<R, VPL, BEAM>), dim3(static_cast<unsigned>(vt), ng), dim3(kBlock),
-                       0, st, static_cast<const PixRec<R>*>(p->pixrec), static_cast<const R*>(xp),
-                       p->vu, p->vv, p->vw, static_cast<const R*>(p->vbeta), p->d_fchunks + nd,
-                       p->n_vis, part, nd);
+    hipLaunchKernelGGL((k_fwd_gauss<R, VPL, BEAM, NR>), dim3(static_cast<unsigned>(vt), ng),
+                       dim3(kBlock), 0, st, static_cast<const PixRec<R>*>(p->pixrec),
+                       static_cast<const R*>(xp), p->n_pix, p->vu, p->vv, p->vw,
+                       static_cast<const R*>(p->vbeta), p->d_fchunks + nd, p->n_vis, part, nd,
+                       rows);
   }
   return hipGetLastError();
 }
 
-template <typename R, int PPL, bool BEAM>
+template <typename R, int PPL, bool BEAM, int NR>
 hipError_t adj_launch_t(sl1m_plan* p, hipStream_t st) {
   R* part = static_cast<R*>(p->apart);
   const int nd = static_cast<int>(p->ptiles_delta.size());
   const int ng = static_cast<int>(p->ptiles_gauss.size());
+  const int sub = p->adj_ppl / PPL;  // blocks per plan tile
+  const C2<R>* rres = static_cast<const C2<R>*>(p->rres);
   if (nd > 0) {
-    hipLaunchKernelGGL((k_adj_delta<R, PPL, BEAM>), dim3(nd, p->n_achunks), dim3(kBlock), 0, st,
-                       static_cast<const VisRecD<R>*>(p->visrecD), static_cast<const R*>(p->vbeta),
-                       p->pl, p->pm, p->pc3, static_cast<const R*>(p->pr2), p->d_ptiles,
-                       p->adj_kchunk, p->n_vis, p->n_pix, part);
+    hipLaunchKernelGGL((k_adj_delta<R, PPL, BEAM, NR>), dim3(nd * sub, p->n_achunks), dim3(kBlock),
+                       0, st, static_cast<const VisRecD<R>*>(p->visrecD), rres,
+                       static_cast<const R*>(p->vbeta), p->pl, p->pm, p->pc3,
+                       static_cast<const R*>(p->pr2), p->d_ptiles, sub, p->adj_kchunk, p->n_vis,
+                       p->n_pix, part);
   }
   if (ng > 0) {
-    hipLaunchKernelGGL((k_adj_gauss<R, PPL, BEAM>), dim3(ng, p->n_achunks), dim3(kBlock), 0, st,
-                       static_cast<const VisRecG<R>*>(p->visrecG), static_cast<const R*>(p->vbeta),
-                       p->pl, p->pm, p->pc3, p->pc4, static_cast<const R*>(p->pr2),
-                       p->d_ptiles + nd, p->adj_kchunk, p->n_vis, p->n_pix, part);
+    hipLaunchKernelGGL((k_adj_gauss<R, PPL, BEAM, NR>), dim3(ng * sub, p->n_achunks), dim3(kBlock),
+                       0, st, static_cast<const VisRecG<R>*>(p->visrecG), rres,
+                       static_cast<const R*>(p->vbeta), p->pl, p->pm, p->pc3, p->pc4,
+                       static_cast<const R*>(p->pr2), p->d_ptiles + nd, sub, p->adj_kchunk,
+                       p->n_vis, p->n_pix, part);
   }
   return hipGetLastError();
 }
@@ -808,92 +888,106 @@ hipError_t launch_prep_vis(sl1m_plan* p, const double* u, const double* v, const
 }
 
 template <typename R>
-static hipError_t gather_t(sl1m_plan* p, const void* x, void* xp, hipStream_t st) {
+static hipError_t gather_t(sl1m_plan* p, const void* x, void* xp, int nr, hipStream_t st) {
   if (p->n_pix == 0) return hipSuccess;
   hipLaunchKernelGGL((k_gather<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
-                     static_cast<const R*>(x), p->perm, p->n_pix, static_cast<R*>(xp));
+                     static_cast<const R*>(x), p->perm, p->n_pix, nr, static_cast<R*>(xp));
   return hipGetLastError();
 }
-hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, hipStream_t st) {
-  return SL1M_DISPATCH_R(p, gather_t, p, x, xp, st);
+hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, int nr, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, gather_t, p, x, xp, nr, st);
 }
 
 template <typename R>
-static hipError_t forward_t(sl1m_plan* p, const void* xp, hipStream_t st) {
+static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
   if (p->n_vis == 0 || p->n_fchunks == 0) return hipSuccess;
-  if (p->beam_pair) return fwd_launch_t<R, 4, true>(p, xp, st);
-  switch (p->fwd_vpl) {
+  const bool bm = p->beam_pair;
+  switch (nr) {
     case 1:
-      return fwd_launch_t<R, 1, false>(p, xp, st);
+      if (bm) return fwd_launch_t<R, 4, true, 1>(p, xp, st);
+      if (p->fwd_vpl == 1) return fwd_launch_t<R, 1, false, 1>(p, xp, st);
+      if (p->fwd_vpl == 2) return fwd_launch_t<R, 2, false, 1>(p, xp, st);
+      return fwd_launch_t<R, 4, false, 1>(p, xp, st);
     case 2:
-      return fwd_launch_t<R, 2, false>(p, xp, st);
+      return bm ? fwd_launch_t<R, 2, true, 2>(p, xp, st) : fwd_launch_t<R, 2, false, 2>(p, xp, st);
+    case 4:
+      return bm ? fwd_launch_t<R, 1, true, 4>(p, xp, st) : fwd_launch_t<R, 1, false, 4>(p, xp, st);
+    case 8:
+      return bm ? fwd_launch_t<R, 1, true, 8>(p, xp, st) : fwd_launch_t<R, 1, false, 8>(p, xp, st);
     default:
-      return fwd_launch_t<R, 4, false>(p, xp, st);
+      return hipErrorInvalidValue;
   }
 }
-hipError_t launch_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
-  return SL1M_DISPATCH_R(p, forward_t, p, xp, st);
+hipError_t launch_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, forward_t, p, xp, nr, st);
 }
 
 template <typename R>
-static hipError_t fwd_reduce_t(sl1m_plan* p, const void* data, void* out, bool recs,
+static hipError_t fwd_reduce_t(sl1m_plan* p, const void* data, void* out, bool recs, int nr,
                                hipStream_t st) {
   if (p->n_vis == 0) return hipSuccess;
   hipLaunchKernelGGL((k_fwd_reduce<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
-                     static_cast<const C2<R>*>(p->fpart), p->n_fchunks, p->n_vis,
+                     static_cast<const C2<R>*>(p->fpart), p->n_fchunks, p->n_vis, nr,
                      static_cast<const R*>(p->vgain), static_cast<const C2<R>*>(data),
-                     static_cast<C2<R>*>(out),
-                     recs ? static_cast<VisRecD<R>*>(p->visrecD) : nullptr,
-                     recs ? static_cast<VisRecG<R>*>(p->visrecG) : nullptr,
-                     static_cast<const R*>(p->layerDs), recs ? p->n_layers : 0);
-  return hipGetLastError();
-}
-hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool recs,
-                                 hipStream_t st) {
-  return SL1M_DISPATCH_R(p, fwd_reduce_t, p, data, out, recs, st);
-}
-
-template <typename R>
-static hipError_t adj_prep_t(sl1m_plan* p, const void* r, hipStream_t st) {
-  if (p->n_vis == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_adj_prep<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
-                     static_cast<const C2<R>*>(r), p->n_vis, static_cast<const R*>(p->vgain),
-                     static_cast<VisRecD<R>*>(p->visrecD), static_cast<VisRecG<R>*>(p->visrecG),
+                     static_cast<C2<R>*>(out), recs ? static_cast<C2<R>*>(p->rres) : nullptr,
                      static_cast<const R*>(p->layerDs), p->n_layers);
   return hipGetLastError();
 }
-hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, hipStream_t st) {
-  return SL1M_DISPATCH_R(p, adj_prep_t, p, r, st);
+hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool recs, int nr,
+                                 hipStream_t st) {
+  return SL1M_DISPATCH_R(p, fwd_reduce_t, p, data, out, recs, nr, st);
 }
 
 template <typename R>
-static hipError_t adjoint_t(sl1m_plan* p, hipStream_t st) {
+static hipError_t adj_prep_t(sl1m_plan* p, const void* r, int nr, hipStream_t st) {
+  if (p->n_vis == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_adj_prep<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
+                     static_cast<const C2<R>*>(r), p->n_vis, nr, static_cast<const R*>(p->vgain),
+                     static_cast<C2<R>*>(p->rres), static_cast<const R*>(p->layerDs),
+                     p->n_layers);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, adj_prep_t, p, r, nr, st);
+}
+
+template <typename R>
+static hipError_t adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
   if (p->n_pix == 0 || p->n_achunks == 0) return hipSuccess;
-  if (p->beam_pair) return adj_launch_t<R, 4, true>(p, st);
-  switch (p->adj_ppl) {
+  const bool bm = p->beam_pair;
+  switch (nr) {
     case 1:
-      return adj_launch_t<R, 1, false>(p, st);
+      if (bm) return adj_launch_t<R, 4, true, 1>(p, st);
+      if (p->adj_ppl == 1) return adj_launch_t<R, 1, false, 1>(p, st);
+      if (p->adj_ppl == 2) return adj_launch_t<R, 2, false, 1>(p, st);
+      return adj_launch_t<R, 4, false, 1>(p, st);
     case 2:
-      return adj_launch_t<R, 2, false>(p, st);
+      if (p->adj_ppl == 1)
+        return bm ? adj_launch_t<R, 1, true, 2>(p, st) : adj_launch_t<R, 1, false, 2>(p, st);
+      return bm ? adj_launch_t<R, 2, true, 2>(p, st) : adj_launch_t<R, 2, false, 2>(p, st);
+    case 4:
+      return bm ? adj_launch_t<R, 1, true, 4>(p, st) : adj_launch_t<R, 1, false, 4>(p, st);
+    case 8:
+      return bm ? adj_launch_t<R, 1, true, 8>(p, st) : adj_launch_t<R, 1, false, 8>(p, st);
     default:
-      return adj_launch_t<R, 4, false>(p, st);
+      return hipErrorInvalidValue;
   }
 }
-hipError_t launch_adjoint(sl1m_plan* p, hipStream_t st) {
-  return SL1M_DISPATCH_R(p, adjoint_t, p, st);
+hipError_t launch_adjoint(sl1m_plan* p, int nr, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, adjoint_t, p, nr, st);
 }
 
 template <typename R>
-static hipError_t adj_reduce_t(sl1m_plan* p, void* g, bool unpermute, hipStream_t st) {
+static hipError_t adj_reduce_t(sl1m_plan* p, void* g, bool unpermute, int nr, hipStream_t st) {
   if (p->n_pix == 0) return hipSuccess;
   hipLaunchKernelGGL((k_adj_reduce<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
-                     static_cast<const R*>(p->apart), p->n_achunks, p->n_pix,
+                     static_cast<const R*>(p->apart), p->n_achunks, p->n_pix, nr,
                      static_cast<const R*>(p->pscale), unpermute ? p->perm : nullptr,
                      static_cast<R*>(g));
   return hipGetLastError();
 }
-hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g, bool unpermute, hipStream_t st) {
-  return SL1M_DISPATCH_R(p, adj_reduce_t, p, g, unpermute, st);
+hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g, bool unpermute, int nr, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, adj_reduce_t, p, g, unpermute, nr, st);
 }
 
 template <typename R>

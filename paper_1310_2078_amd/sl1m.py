@@ -46,7 +46,7 @@ class Problem(ctypes.Structure):
         ("ant_gain", ctypes.c_void_p),
         ("ant_fwhm", ctypes.c_void_p),
         ("precision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("max_rhs", ctypes.c_int32),
     ]
 
 
@@ -100,6 +100,8 @@ def lib() -> ctypes.CDLL:
         L.sl1m_plan_destroy.argtypes = [vp]
         L.sl1m_forward.argtypes = [vp, vp, vp, vp]
         L.sl1m_adjoint.argtypes = [vp, vp, vp, vp]
+        L.sl1m_forward_multi.argtypes = [vp, i32, vp, vp, vp]
+        L.sl1m_adjoint_multi.argtypes = [vp, i32, vp, vp, vp]
         L.sl1m_estimate_L.argtypes = [vp, i32, u64, vp, ctypes.POINTER(dbl), vp]
         L.sl1m_solve.argtypes = [vp, vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(SolveInfo), vp]
         L.sl1m_timing_begin.argtypes = [vp, i32]
@@ -107,7 +109,8 @@ def lib() -> ctypes.CDLL:
         L.sl1m_last_error.restype = ctypes.c_char_p
         L.sl1m_version.restype = ctypes.c_char_p
         for name in ("sl1m_plan_workspace_bytes", "sl1m_plan_create", "sl1m_plan_destroy",
-                     "sl1m_forward", "sl1m_adjoint", "sl1m_estimate_L", "sl1m_solve",
+                     "sl1m_forward", "sl1m_adjoint", "sl1m_forward_multi",
+                     "sl1m_adjoint_multi", "sl1m_estimate_L", "sl1m_solve",
                      "sl1m_timing_begin", "sl1m_timing_end"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -146,7 +149,7 @@ class Plan:
 
     def __init__(self, l, m, u, v, w, sigma=None, kind=None, ant_p=None, ant_q=None,
                  ant_gain=None, ant_fwhm=None, precision: str = "fp32", device="cuda",
-                 stream=None):
+                 stream=None, max_rhs: int = 1):
         self.device = torch.device(device)
         self.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
         self.rdtype = torch.float32 if self.precision == PREC_FP32 else torch.float64
@@ -179,7 +182,8 @@ class Plan:
             kind=_ptr(k["kind"]), n_vis=self.n_vis, u=_ptr(k["u"]), v=_ptr(k["v"]),
             w=_ptr(k["w"]), ant_p=_ptr(k["ant_p"]), ant_q=_ptr(k["ant_q"]), n_ant=n_ant,
             ant_gain=_ptr(k["ant_gain"]), ant_fwhm=_ptr(k["ant_fwhm"]),
-            precision=self.precision, reserved=0)
+            precision=self.precision, max_rhs=int(max_rhs))
+        self.max_rhs = int(max_rhs)
         nbytes = ctypes.c_size_t(0)
         _check(lib().sl1m_plan_workspace_bytes(ctypes.byref(self._prob), ctypes.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
@@ -191,13 +195,13 @@ class Plan:
         self._h = h
 
     @classmethod
-    def from_workload(cls, wl, precision="fp32", device="cuda", with_kinds=True):
+    def from_workload(cls, wl, precision="fp32", device="cuda", with_kinds=True, max_rhs=1):
         kw = {}
         if with_kinds and (np.any(wl.kind != 0) or np.any(wl.sigma != 0)):
             kw = dict(sigma=wl.sigma, kind=wl.kind)
         return cls(wl.l, wl.m, wl.u, wl.v, wl.w, ant_p=wl.ant_p, ant_q=wl.ant_q,
                    ant_gain=wl.ant_gain, ant_fwhm=wl.ant_fwhm, precision=precision,
-                   device=device, **kw)
+                   device=device, max_rhs=max_rhs, **kw)
 
     # -- operator -----------------------------------------------------------
     def forward(self, x, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -212,6 +216,24 @@ class Plan:
         if out is None:
             out = torch.empty(self.n_pix, dtype=self.rdtype, device=self.device)
         _check(lib().sl1m_adjoint(self._h, _ptr(r), _ptr(out), _stream(stream)))
+        return out
+
+    def forward_multi(self, x, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """x: real [R][n_pix] -> complex [R][n_vis]."""
+        x = _dev(x, self.rdtype, self.device)
+        R = int(x.shape[0])
+        if out is None:
+            out = torch.empty((R, self.n_vis), dtype=self.cdtype, device=self.device)
+        _check(lib().sl1m_forward_multi(self._h, R, _ptr(x), _ptr(out), _stream(stream)))
+        return out
+
+    def adjoint_multi(self, r, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """r: complex [R][n_vis] -> real [R][n_pix]."""
+        r = _dev(r, self.cdtype, self.device)
+        R = int(r.shape[0])
+        if out is None:
+            out = torch.empty((R, self.n_pix), dtype=self.rdtype, device=self.device)
+        _check(lib().sl1m_adjoint_multi(self._h, R, _ptr(r), _ptr(out), _stream(stream)))
         return out
 
     def estimate_L(self, iters: int = 30, seed: int = 0, x0=None, stream=None) -> float:

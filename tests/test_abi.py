@@ -43,6 +43,11 @@ def test_host_argument_checks(L):
     assert b"negative" in L.sl1m_last_error()
     pr = sl1m.Problem(n_pix=10, n_vis=10, precision=7)
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    pr = sl1m.Problem(n_pix=10, l=fake, m=fake, n_vis=10, u=fake, v=fake, w=fake,
+                      precision=sl1m.PREC_FP32, max_rhs=3)
+    assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    assert b"max_rhs" in L.sl1m_last_error()
     pr = sl1m.Problem(n_pix=10, n_vis=10, precision=sl1m.PREC_FP32)   # NULL l, m
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
     assert L.sl1m_forward(None, None, None, None) == sl1m.EINVAL
@@ -67,3 +72,9 @@ def test_workspace_size_grows_with_problem(L):
     assert size(1024, 2000, sl1m.PREC_FP64) > a
     assert size(0, 0) > 0          # empty problems are legal
     assert b < 2 ** 30             # config-2 workspace stays far below HBM
+    fake = ctypes.c_void_p(0x1000)
+    pr4 = sl1m.Problem(n_pix=65536, l=fake, m=fake, n_vis=97536, u=fake, v=fake, w=fake,
+                       precision=sl1m.PREC_FP32, max_rhs=4)
+    b4 = ctypes.c_size_t(0)
+    assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr4), ctypes.byref(b4)) == 0
+    assert b4.value > b
