@@ -85,6 +85,9 @@ typedef enum {
  *  precision sl1m_precision.
  *  max_rhs   largest n_rhs that sl1m_forward_multi/sl1m_adjoint_multi will be
  *            called with (sizes the workspace); 0 means 1.
+ *  tile_blocks  number of thread blocks the split of one operator application
+ *            aims at (more blocks: more parallelism, larger partial-sum
+ *            buffers); 0 means 4096, enough to fill the 256 compute units.
  */
 typedef struct {
   int64_t n_pix;
@@ -103,6 +106,8 @@ typedef struct {
   const double* ant_fwhm;
   int32_t precision;
   int32_t max_rhs;      /* right-hand sides per operator call: 0 or 1, 2, 4, 8 */
+  int32_t tile_blocks;  /* blocks one operator launch aims at; 0 = 4096       */
+  int32_t reserved;
 } sl1m_problem;
 
 typedef struct sl1m_plan sl1m_plan;
@@ -209,6 +214,77 @@ typedef struct {
 
 sl1m_status sl1m_timing_begin(sl1m_plan* plan, int32_t max_launches);
 sl1m_status sl1m_timing_end(sl1m_plan* plan, sl1m_timing* out /* host */);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of many solves on one GPU.
+ *
+ * The paper solves every channel as an independent deconvolution (Sections
+ * "NGC5921" and "NGC2403": 63 and 61 per-channel solves).  A server runs many
+ * such solves of different sizes together.  It sub-allocates each admitted
+ * request's plan and FISTA state from one caller-provided device arena
+ * (admission by footprint; a request waits while its footprint does not fit
+ * or no slot is free).  Work advances in rounds: one launch of each batched
+ * kernel covers the work items of every active request.  A round holds about
+ * `round_budget_evals` pixel-visibility evaluations: each of the n active
+ * requests advances by at most max(budget / n, budget / 32) evaluations (at
+ * least one work item, never past the end of its current phase), so small
+ * requests finish a whole FISTA iteration per round while large ones advance
+ * part of one.  A request's arithmetic and
+ * summation order depend only on its own problem: its image is bitwise the
+ * same alone and in any mix.  FP32 plans, one right-hand side; the solve runs
+ * the power iteration when params->L <= 0, then params->max_iter FISTA
+ * iterations (params->eps is not used), then the objective terms.
+ * --------------------------------------------------------------------------- */
+typedef struct sl1m_server sl1m_server;
+
+typedef struct {
+  int64_t rounds;            /* rounds launched                              */
+  int64_t completed_rounds;  /* rounds known to have finished on the GPU     */
+  double evals_scheduled;    /* operator evaluations launched so far          */
+  uint64_t arena_bytes;      /* usable arena bytes                            */
+  uint64_t arena_used;       /* bytes held by admitted requests               */
+  int32_t active;            /* requests on the GPU                           */
+  int32_t pending;           /* requests waiting for admission                */
+} sl1m_server_stats_t;
+
+/* arena: device memory owned by the caller (256-byte aligned), kept alive
+ * until sl1m_server_destroy(); max_slots: at most this many requests on the
+ * GPU at once (1..64); round_budget_evals: work per round (<= 0 selects 3e10,
+ * about 10 ms of operator work).  The server creates its own non-blocking
+ * streams. */
+sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
+                               double round_budget_evals, sl1m_server** out);
+
+/* Queue one solve.  problem: as for sl1m_plan_create (FP32, max_rhs <= 1); its
+ * arrays must stay valid until the request is admitted.  vis: complex64
+ * [n_vis] data and img_out: float32 [n_pix] result, both device pointers valid
+ * until the request is done.  Non-blocking apart from reading the problem's
+ * grouping arrays (see sl1m_plan_workspace_bytes).  *ticket identifies the
+ * request.  SL1M_ENOMEM if its footprint exceeds the whole arena. */
+sl1m_status sl1m_server_submit(sl1m_server* server, const sl1m_problem* problem,
+                               const void* vis, const sl1m_solve_params* params,
+                               void* img_out, uint64_t* ticket);
+
+/* One scheduling step: release finished requests, admit waiting ones that fit,
+ * launch the next round (asynchronous; at most 4 rounds are in flight, after
+ * which the step waits for the oldest).  Reports the numbers of active and
+ * waiting requests (either pointer may be NULL). */
+sl1m_status sl1m_server_step(sl1m_server* server, int32_t* n_active, int32_t* n_pending);
+
+/* *done = 1 once the request's image is in img_out and info (host) is final;
+ * times (host, may be NULL): [submit, admit, finish] in seconds since the
+ * server was created (finish = when a step observed the completion). */
+sl1m_status sl1m_server_poll(sl1m_server* server, uint64_t ticket, sl1m_solve_info* info,
+                             int32_t* done, double* times);
+
+/* Cancel a waiting or running request; its memory is released once no
+ * launched round uses it; other requests are unaffected. */
+sl1m_status sl1m_server_cancel(sl1m_server* server, uint64_t ticket);
+
+sl1m_status sl1m_server_stats(sl1m_server* server, sl1m_server_stats_t* out);
+
+/* Waits for launched work, releases host resources (not the arena). */
+sl1m_status sl1m_server_destroy(sl1m_server* server);
 
 /* Message of the last error on this thread ("" if none). */
 const char* sl1m_last_error(void);

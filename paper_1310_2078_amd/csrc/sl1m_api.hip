@@ -166,7 +166,9 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   a.fwd_vpl = nv >= 64LL * kBlock * 4 ? 4 : (nv >= 32LL * kBlock * 2 ? 2 : 1);
   if (a.beam_pair) a.fwd_vpl = 4;
   const int64_t vtiles = (nv + kBlock * a.fwd_vpl - 1) / (kBlock * a.fwd_vpl);
-  int64_t target_chunks = vtiles > 0 ? (4096 + vtiles - 1) / vtiles : 1;
+  const int64_t target_blocks = pr->tile_blocks > 0 ? pr->tile_blocks : 4096;
+  if (pr->tile_blocks < 0) return set_error(SL1M_EINVAL, "tile_blocks must be >= 0");
+  int64_t target_chunks = vtiles > 0 ? (target_blocks + vtiles - 1) / vtiles : 1;
   target_chunks = std::max<int64_t>(1, std::min<int64_t>(64, target_chunks));
   const int64_t cp = std::max<int64_t>(64, (np + target_chunks - 1) / std::max<int64_t>(1, target_chunks));
   a.fd.clear();
@@ -196,7 +198,8 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   }
   const int64_t ptiles = static_cast<int64_t>(a.pd.size() + a.pg.size());
   if (nv > 0 && ptiles > 0) {
-    int64_t want = std::max<int64_t>(1, std::min<int64_t>(64, (4096 + ptiles - 1) / ptiles));
+    int64_t want =
+        std::max<int64_t>(1, std::min<int64_t>(64, (target_blocks + ptiles - 1) / ptiles));
     a.kchunk = std::max<int64_t>(64, (nv + want - 1) / want);
     a.n_achunks = static_cast<int>((nv + a.kchunk - 1) / a.kchunk);
   } else {

@@ -26,53 +26,14 @@
 // the phase reduced as theta - rint(theta) and sincospi/exp in FP64.
 #include <type_traits>
 
-#include "sl1m_internal.h"
+#include "sl1m_device.h"
 
 namespace sl1m {
 
 namespace {
 
-template <typename R>
-struct Cplx;
-template <>
-struct Cplx<float> {
-  using T = float2;
-};
-template <>
-struct Cplx<double> {
-  using T = double2;
-};
-template <typename R>
-using C2 = typename Cplx<R>::T;
+using namespace dev;
 
-constexpr int kSeg = 64;  // inner FP32 accumulation length (two-level sums)
-
-template <typename R>
-__device__ __forceinline__ constexpr double phase_origin() {
-  return std::is_same<R, float>::value ? kMagic : 0.0;
-}
-
-// (cos 2 pi theta, sin 2 pi theta) from t = phase_origin + theta.
-__device__ __forceinline__ void phasor(double t, float& c, float& s) {
-  const uint32_t lo = static_cast<uint32_t>(__double2loint(t));
-  const float f = __uint_as_float((lo & 0x007FFFFFu) | 0x3F800000u);  // 1 + frac(theta)
-  s = __builtin_amdgcn_sinf(f);
-  c = __builtin_amdgcn_cosf(f);
-}
-__device__ __forceinline__ void phasor(double t, double& c, double& s) {
-  const double r = t - rint(t);
-  sincospi(2.0 * r, &s, &c);
-}
-
-// 2^x
-__device__ __forceinline__ float pow2(float x) { return __builtin_amdgcn_exp2f(x); }
-__device__ __forceinline__ double pow2(double x) { return exp2(x); }
-
-// Natural exponent scale used with pow2 for the Gaussian taper.
-template <typename R>
-__device__ __forceinline__ constexpr double taper_scale() {
-  return 1.4426950408889634;  // log2(e): exp(x) = 2^(x log2 e)
-}
 
 // ---------------------------------------------------------------------------
 // forward kernels
@@ -88,79 +49,11 @@ __global__ __launch_bounds__(kBlock) void k_fwd_delta(
     const R* __restrict__ vbeta, const Chunk* __restrict__ chunks, int64_t n_vis,
     C2<R>* __restrict__ part, int row0, int n_rows) {
   const Chunk ch = chunks[blockIdx.y];
-  const int64_t kbase = static_cast<int64_t>(blockIdx.x) * (kBlock * VPL) + threadIdx.x;
-  double u[VPL], v[VPL], w[VPL];
-  R beta[VPL], ore[NR][VPL], oim[NR][VPL];
-#pragma unroll
-  for (int i = 0; i < VPL; ++i) {
-    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
-    const bool ok = k < n_vis;
-    u[i] = ok ? vu[k] : 0.0;
-    v[i] = ok ? vv[k] : 0.0;
-    w[i] = ok ? vw[k] : 0.0;
-    beta[i] = (BEAM && ok) ? vbeta[k] : R(0);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) ore[r][i] = oim[r][i] = R(0);
-  }
-  const double origin = phase_origin<R>();
-  const int jb = static_cast<int>(ch.j0), je = static_cast<int>(ch.j1);
-  for (int j0 = jb; j0 < je; j0 += kSeg) {
-    const int j1 = j0 + kSeg < je ? j0 + kSeg : je;
-    R re[NR][VPL], im[NR][VPL];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < VPL; ++i) re[r][i] = im[r][i] = R(0);
-    for (int j = j0; j < j1; ++j) {
-      const double pl = pix[j].l, pm = pix[j].m, pn = pix[j].c3;
-      R a[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) a[r] = pix[j].scale * xp[r * n_pix + j];
-      const R r2 = BEAM ? pix[j].r2r : R(0);
-#pragma unroll
-      for (int i = 0; i < VPL; ++i) {
-        const double t = fma(w[i], pn, fma(v[i], pm, fma(u[i], pl, origin)));
-        R c, s;
-        phasor(t, c, s);
-        const R b = BEAM ? pow2(beta[i] * r2) : R(1);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const R ai = BEAM ? a[r] * b : a[r];
-          re[r][i] = fma(ai, c, re[r][i]);
-          im[r][i] = fma(-ai, s, im[r][i]);
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < VPL; ++i) {
-        ore[r][i] += re[r][i];
-        oim[r][i] += im[r][i];
-      }
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    C2<R>* out = part + static_cast<int64_t>(r * n_rows + row0 + blockIdx.y) * n_vis;
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-      const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
-      if (k < n_vis) {
-        C2<R> o;
-        o.x = ore[r][i];
-        o.y = oim[r][i];
-        out[k] = o;
-      }
-    }
-  }
+  fwd_delta_tile<R, VPL, BEAM, NR>(pix, xp, n_pix, vu, vv, vw, vbeta, ch, blockIdx.x, n_vis,
+                                   part + static_cast<int64_t>(row0 + blockIdx.y) * n_vis,
+                                   static_cast<int64_t>(n_rows) * n_vis, R(1));
 }
 
-// Gaussian pixels, eq. (samlm4)/(samlm5) in completed-square form:
-//   M = g (1/n) D (1 + i s) exp(-pi sigma^2 D |(u,v) - w (l,m)|^2)
-//       exp(2 pi i [D(-(u l + v m) + (w/2)(r^2 - sigma^4 rho^2)) - w kappa])
-// with s = w sigma^2, D = 1/(1+s^2), kappa = n - 1 + r^2/2 (0 for paraxial).
-// The factor D(1 + i s) is constant per (visibility, segment) and applied once
-// to the segment's sum.
 template <typename R, int VPL, bool BEAM, int NR>
 __global__ __launch_bounds__(kBlock) void k_fwd_gauss(
     const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, int64_t n_pix,
@@ -168,88 +61,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd_gauss(
     const R* __restrict__ vbeta, const Chunk* __restrict__ chunks, int64_t n_vis,
     C2<R>* __restrict__ part, int row0, int n_rows) {
   const Chunk ch = chunks[blockIdx.y];
-  const int64_t kbase = static_cast<int64_t>(blockIdx.x) * (kBlock * VPL) + threadIdx.x;
-  const double sig2 = ch.sigma * ch.sigma;
-  double A[VPL], B[VPL], C[VPL], NW[VPL], E0[VPL];
-  R ur[VPL], vr[VPL], wr[VPL], c1[VPL], Dd[VPL], Ds[VPL], beta[VPL];
-  R ore[NR][VPL], oim[NR][VPL];
-#pragma unroll
-  for (int i = 0; i < VPL; ++i) {
-    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
-    const bool ok = k < n_vis;
-    const double u = ok ? vu[k] : 0.0, v = ok ? vv[k] : 0.0, w = ok ? vw[k] : 0.0;
-    const double s = w * sig2;
-    const double D = 1.0 / (1.0 + s * s);
-    A[i] = -D * u;
-    B[i] = -D * v;
-    C[i] = 0.5 * D * w;
-    NW[i] = -w;
-    E0[i] = phase_origin<R>() - 0.5 * D * w * sig2 * sig2 * (u * u + v * v);
-    ur[i] = static_cast<R>(u);
-    vr[i] = static_cast<R>(v);
-    wr[i] = static_cast<R>(w);
-    c1[i] = static_cast<R>(-M_PI * sig2 * D * taper_scale<R>());
-    Dd[i] = static_cast<R>(D);
-    Ds[i] = static_cast<R>(D * s);
-    beta[i] = (BEAM && ok) ? vbeta[k] : R(0);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) ore[r][i] = oim[r][i] = R(0);
-  }
-  const int jb = static_cast<int>(ch.j0), je = static_cast<int>(ch.j1);
-  for (int j0 = jb; j0 < je; j0 += kSeg) {
-    const int j1 = j0 + kSeg < je ? j0 + kSeg : je;
-    R re[NR][VPL], im[NR][VPL];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < VPL; ++i) re[r][i] = im[r][i] = R(0);
-    for (int j = j0; j < j1; ++j) {
-      const double pl = pix[j].l, pm = pix[j].m, pr2 = pix[j].c3, pk = pix[j].c4;
-      const R lr = pix[j].lr, mr = pix[j].mr;
-      R a[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) a[r] = pix[j].scale * xp[r * n_pix + j];
-      const R r2 = BEAM ? pix[j].r2r : R(0);
-#pragma unroll
-      for (int i = 0; i < VPL; ++i) {
-        const double t = fma(A[i], pl, fma(B[i], pm, fma(C[i], pr2, fma(NW[i], pk, E0[i]))));
-        R c, s;
-        phasor(t, c, s);
-        const R du = fma(-wr[i], lr, ur[i]);
-        const R dv = fma(-wr[i], mr, vr[i]);
-        const R q = fma(du, du, dv * dv);
-        R e = pow2(c1[i] * q);
-        if (BEAM) e *= pow2(beta[i] * r2);
-        const R ec = e * c, es = e * s;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          re[r][i] = fma(a[r], ec, re[r][i]);
-          im[r][i] = fma(a[r], es, im[r][i]);
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < VPL; ++i) {
-        ore[r][i] += re[r][i];
-        oim[r][i] += im[r][i];
-      }
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    C2<R>* out = part + static_cast<int64_t>(r * n_rows + row0 + blockIdx.y) * n_vis;
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-      const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
-      if (k < n_vis) {
-        C2<R> o;
-        o.x = Dd[i] * ore[r][i] - Ds[i] * oim[r][i];
-        o.y = Ds[i] * ore[r][i] + Dd[i] * oim[r][i];
-        out[k] = o;
-      }
-    }
-  }
+  fwd_gauss_tile<R, VPL, BEAM, NR>(pix, xp, n_pix, vu, vv, vw, vbeta, ch, blockIdx.x, n_vis,
+                                   part + static_cast<int64_t>(row0 + blockIdx.y) * n_vis,
+                                   static_cast<int64_t>(n_rows) * n_vis, R(1));
 }
 
 // ---------------------------------------------------------------------------
@@ -268,72 +82,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_delta(
     const double* __restrict__ pc3, const R* __restrict__ pr2, const Chunk* __restrict__ tiles,
     int sub, int64_t kchunk, int64_t n_vis, int64_t n_pix, R* __restrict__ part) {
   const Chunk tl = tiles[blockIdx.x / sub];
-  const int64_t jbase = tl.j0 + static_cast<int64_t>(blockIdx.x % sub) * (kBlock * PPL) + threadIdx.x;
-  const int k0 = static_cast<int>(blockIdx.y * kchunk);
-  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
-  double l[PPL], m[PPL], c3[PPL];
-  R r2[PPL], og[NR][PPL];
-#pragma unroll
-  for (int i = 0; i < PPL; ++i) {
-    const int64_t j = jbase + static_cast<int64_t>(i) * kBlock;
-    const bool ok = j < tl.j1;
-    l[i] = ok ? pl[j] : 0.0;
-    m[i] = ok ? pm[j] : 0.0;
-    c3[i] = ok ? pc3[j] : 0.0;
-    r2[i] = (BEAM && ok) ? pr2[j] : R(0);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) og[r][i] = R(0);
-  }
-  const double origin = phase_origin<R>();
-  for (int kk = k0; kk < k1; kk += kSeg) {
-    const int ke = kk + kSeg < k1 ? kk + kSeg : k1;
-    R g[NR][PPL];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < PPL; ++i) g[r][i] = R(0);
-    for (int k = kk; k < ke; ++k) {
-      const double u = vrec[k].u, v = vrec[k].v, w = vrec[k].w;
-      R rre[NR], rim[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const C2<R> q = rres[static_cast<int64_t>(k) * NR + r];
-        rre[r] = q.x;
-        rim[r] = q.y;
-      }
-      const R bt = BEAM ? vbeta[k] : R(0);
-#pragma unroll
-      for (int i = 0; i < PPL; ++i) {
-        const double t = fma(c3[i], w, fma(m[i], v, fma(l[i], u, origin)));
-        R c, s;
-        phasor(t, c, s);
-        if (BEAM) {
-          const R b = pow2(bt * r2[i]);
-          c *= b;
-          s *= b;
-        }
-        // Re[(c + i s)(rre + i rim)] = c rre - s rim
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          g[r][i] = fma(c, rre[r], g[r][i]);
-          g[r][i] = fma(-s, rim[r], g[r][i]);
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < PPL; ++i) og[r][i] += g[r][i];
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    R* out = part + static_cast<int64_t>(r * gridDim.y + blockIdx.y) * n_pix;
-#pragma unroll
-    for (int i = 0; i < PPL; ++i) {
-      const int64_t j = jbase + static_cast<int64_t>(i) * kBlock;
-      if (j < tl.j1) out[j] = og[r][i];
-    }
-  }
+  adj_delta_tile<R, PPL, BEAM, NR>(vrec, rres, vbeta, pl, pm, pc3, pr2, tl, blockIdx.x % sub,
+                                   blockIdx.y, kchunk, n_vis,
+                                   part + static_cast<int64_t>(blockIdx.y) * n_pix,
+                                   static_cast<int64_t>(gridDim.y) * n_pix);
 }
 
 template <typename R, int PPL, bool BEAM, int NR>
@@ -344,106 +96,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_gauss(
     const Chunk* __restrict__ tiles, int sub, int64_t kchunk, int64_t n_vis, int64_t n_pix,
     R* __restrict__ part) {
   const Chunk tl = tiles[blockIdx.x / sub];
-  const int64_t jbase = tl.j0 + static_cast<int64_t>(blockIdx.x % sub) * (kBlock * PPL) + threadIdx.x;
-  const VisRecG<R>* rec = vrec + static_cast<int64_t>(tl.layer) * n_vis;
-  const C2<R>* res = rres + static_cast<int64_t>(1 + tl.layer) * n_vis * NR;
-  const int k0 = static_cast<int>(blockIdx.y * kchunk);
-  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
-  double l[PPL], m[PPL], c3[PPL], c4[PPL];
-  R lr[PPL], mr[PPL], r2[PPL], og[NR][PPL];
-#pragma unroll
-  for (int i = 0; i < PPL; ++i) {
-    const int64_t j = jbase + static_cast<int64_t>(i) * kBlock;
-    const bool ok = j < tl.j1;
-    l[i] = ok ? pl[j] : 0.0;
-    m[i] = ok ? pm[j] : 0.0;
-    c3[i] = ok ? pc3[j] : 0.0;
-    c4[i] = ok ? pc4[j] : 0.0;
-    lr[i] = static_cast<R>(l[i]);
-    mr[i] = static_cast<R>(m[i]);
-    r2[i] = (BEAM && ok) ? pr2[j] : R(0);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) og[r][i] = R(0);
-  }
-  for (int kk = k0; kk < k1; kk += kSeg) {
-    const int ke = kk + kSeg < k1 ? kk + kSeg : k1;
-    R g[NR][PPL];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < PPL; ++i) g[r][i] = R(0);
-    for (int k = kk; k < ke; ++k) {
-      const double A = rec[k].A, B = rec[k].B, C = rec[k].C, NW = rec[k].NW, E0 = rec[k].E0;
-      const R ur = rec[k].ur, vr = rec[k].vr, wr = rec[k].wr, c1 = rec[k].c1;
-      R rre[NR], rim[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const C2<R> q = res[static_cast<int64_t>(k) * NR + r];
-        rre[r] = q.x;
-        rim[r] = q.y;
-      }
-      const R bt = BEAM ? vbeta[k] : R(0);
-#pragma unroll
-      for (int i = 0; i < PPL; ++i) {
-        const double t = fma(A, l[i], fma(B, m[i], fma(C, c3[i], fma(NW, c4[i], E0))));
-        R c, s;
-        phasor(t, c, s);
-        const R du = fma(-wr, lr[i], ur);
-        const R dv = fma(-wr, mr[i], vr);
-        const R q = fma(du, du, dv * dv);
-        R e = pow2(c1 * q);
-        if (BEAM) e *= pow2(bt * r2[i]);
-        const R ec = e * c, es = e * s;
-        // Re[(c - i s)(rre + i rim)] = c rre + s rim
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          g[r][i] = fma(ec, rre[r], g[r][i]);
-          g[r][i] = fma(es, rim[r], g[r][i]);
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < PPL; ++i) og[r][i] += g[r][i];
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    R* out = part + static_cast<int64_t>(r * gridDim.y + blockIdx.y) * n_pix;
-#pragma unroll
-    for (int i = 0; i < PPL; ++i) {
-      const int64_t j = jbase + static_cast<int64_t>(i) * kBlock;
-      if (j < tl.j1) out[j] = og[r][i];
-    }
-  }
+  adj_gauss_tile<R, PPL, BEAM, NR>(vrec, rres, vbeta, pl, pm, pc3, pc4, pr2, tl, blockIdx.x % sub,
+                                   blockIdx.y, kchunk, n_vis,
+                                   part + static_cast<int64_t>(blockIdx.y) * n_pix,
+                                   static_cast<int64_t>(gridDim.y) * n_pix);
 }
 
 // ---------------------------------------------------------------------------
 // reductions of split-K partials, residual, adjoint records, FISTA update
 // ---------------------------------------------------------------------------
-
-// Writes the adjoint residual records of visibility k for right-hand side r
-// from the complex value (re, im) already including the gain G_k:
-//   slot 0 (delta):          conj(G_k) v
-//   slot 1 + L (Gaussian L): D (1 - i s) conj(G_k) v
-template <typename R>
-__device__ __forceinline__ void write_res(C2<R>* __restrict__ rres, const R* __restrict__ layerDs,
-                                          int n_layers, int64_t n_vis, int nr, int64_t k, int r,
-                                          R gr, R gi, R re, R im) {
-  const R cr = gr * re + gi * im;
-  const R ci = gr * im - gi * re;
-  C2<R> o;
-  o.x = cr;
-  o.y = ci;
-  rres[k * nr + r] = o;
-  for (int L = 0; L < n_layers; ++L) {
-    const R D = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2];
-    const R s = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2 + 1];
-    o.x = D * (cr + s * ci);
-    o.y = D * (ci - s * cr);
-    rres[(static_cast<int64_t>(1 + L) * n_vis + k) * nr + r] = o;
-  }
-}
 
 // vis[r][k] = G_k * sum_c part[r][c][k]  (minus data[r][k] if data != null);
 // writes the adjoint residual records when `rres` is set.
@@ -908,11 +569,19 @@ static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st
       if (p->fwd_vpl == 1) return fwd_launch_t<R, 1, false, 1>(p, xp, st);
       if (p->fwd_vpl == 2) return fwd_launch_t<R, 2, false, 1>(p, xp, st);
       return fwd_launch_t<R, 4, false, 1>(p, xp, st);
+    // several right-hand sides: keep >= 2 visibilities per lane when the plan
+    // has enough visibilities, so each scalar pixel load feeds more work
     case 2:
+      if (p->fwd_vpl >= 4)
+        return bm ? fwd_launch_t<R, 4, true, 2>(p, xp, st) : fwd_launch_t<R, 4, false, 2>(p, xp, st);
       return bm ? fwd_launch_t<R, 2, true, 2>(p, xp, st) : fwd_launch_t<R, 2, false, 2>(p, xp, st);
     case 4:
+      if (p->fwd_vpl >= 2)
+        return bm ? fwd_launch_t<R, 2, true, 4>(p, xp, st) : fwd_launch_t<R, 2, false, 4>(p, xp, st);
       return bm ? fwd_launch_t<R, 1, true, 4>(p, xp, st) : fwd_launch_t<R, 1, false, 4>(p, xp, st);
     case 8:
+      if (p->fwd_vpl >= 2)
+        return bm ? fwd_launch_t<R, 2, true, 8>(p, xp, st) : fwd_launch_t<R, 2, false, 8>(p, xp, st);
       return bm ? fwd_launch_t<R, 1, true, 8>(p, xp, st) : fwd_launch_t<R, 1, false, 8>(p, xp, st);
     default:
       return hipErrorInvalidValue;

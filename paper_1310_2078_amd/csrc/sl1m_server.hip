@@ -1,0 +1,775 @@
+// Continuous-batching server for SL1M solves on one GPU.
+//
+// Many FISTA solves of different sizes share the GPU.  Each admitted request
+// owns a plan and solver state carved from one caller-provided HBM arena
+// (admission by footprint).  Work advances in rounds; a round is one launch of
+// each batched kernel (forward delta/Gaussian, reduce, adjoint
+// delta/Gaussian, update, final), each with a fixed grid whose blocks stride
+// over a table listing every active request's work items for that round.  The
+// item decomposition and every reduction order depend only on the request's
+// own plan, so a request's result is bitwise the same alone and in any mix.
+// Requests submitted while others run join at the next round.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sl1m_device.h"
+#include "sl1m_sched.h"
+
+namespace sl1m {
+namespace {
+
+using namespace dev;
+using sched::Segment;
+
+constexpr int kSrvMaxSlots = 64;
+constexpr int kSrvRing = 4;              // rounds in flight (table buffers)
+constexpr int kSrvTileBlocks = 8192;     // per-request operator split target (work-item count)
+
+struct SegDev {
+  int32_t slot, flags;
+  int64_t begin, end, prefix;
+};
+
+struct TabDev {
+  int64_t total;
+  int32_t n_seg, pad;
+  SegDev seg[kSrvMaxSlots];
+};
+
+// Per-slot device descriptor: pointers into the request's plan and state, plus
+// solver scalars updated by the batched kernels.
+struct ReqDev {
+  const PixRec<float>* pix;
+  const double *vu, *vv, *vw;
+  const float* vgain;
+  const float* vbeta;
+  const VisRecD<float>* visrecD;
+  const VisRecG<float>* visrecG;
+  const float* layerDs;
+  float2* rres;
+  const double *pl, *pm, *pc3, *pc4;
+  const float* pscale;
+  const float* pr2;
+  const int32_t* perm;
+  const Chunk* fchunks;  // delta chunks, then Gaussian chunks
+  const Chunk* ptiles;   // delta tiles, then Gaussian tiles
+  float2* fpart;
+  float* apart;
+  float* x;              // power-iteration vector (unnormalised; true x = xscale * x)
+  float* y;              // FISTA extrapolated point
+  float* img;            // FISTA iterate
+  const float2* data;    // caller's visibilities
+  float* out;            // caller's image
+  double* red;           // partial sums: [vis_blocks] then [2 * pix_blocks]
+  int* flag;             // non-finite values seen
+  int64_t n_pix, n_vis, kchunk, vtiles, vis_blocks, pix_blocks;
+  int32_t n_fchunks, n_fd, n_achunks, n_pd, vpl, ppl, n_layers, beam_pair;
+  double t, inv_L, thr, lam, L, L_safety, rq, xscale, l2, l1, nnz;
+};
+
+__device__ __forceinline__ int find_seg(const TabDev* __restrict__ tab, int64_t w) {
+  int s = 0;
+  while (s + 1 < tab->n_seg && tab->seg[s + 1].prefix <= w) ++s;
+  return s;
+}
+
+__device__ __forceinline__ double srv_block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <bool GAUSS>
+__global__ __launch_bounds__(kBlock) void k_srv_fwd(const TabDev* __restrict__ tab,
+                                                    const ReqDev* __restrict__ reqs) {
+  const int64_t total = tab->total;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const SegDev sg = tab->seg[find_seg(tab, w)];
+    const ReqDev& q = reqs[sg.slot];
+    const int64_t item = sg.begin + (w - sg.prefix);
+    const int64_t c = (GAUSS ? q.n_fd : 0) + item / q.vtiles;
+    const int64_t vt = item % q.vtiles;
+    const Chunk ch = q.fchunks[c];
+    const float* xp = (sg.flags & sched::F_POWER) ? q.x
+                      : (sg.flags & sched::F_OBJECTIVE) ? q.img
+                                                        : q.y;
+    const float xs = (sg.flags & sched::F_POWER) ? static_cast<float>(q.xscale) : 1.0f;
+    float2* row = q.fpart + c * q.n_vis;
+#define SL1M_SRV_FWD(VPL, BEAM)                                                                   \
+  (GAUSS ? fwd_gauss_tile<float, VPL, BEAM, 1>(q.pix, xp, q.n_pix, q.vu, q.vv, q.vw, q.vbeta, ch, \
+                                               vt, q.n_vis, row, 0, xs)                           \
+         : fwd_delta_tile<float, VPL, BEAM, 1>(q.pix, xp, q.n_pix, q.vu, q.vv, q.vw, q.vbeta, ch, \
+                                               vt, q.n_vis, row, 0, xs))
+    if (q.beam_pair)
+      SL1M_SRV_FWD(4, true);
+    else if (q.vpl == 4)
+      SL1M_SRV_FWD(4, false);
+    else if (q.vpl == 2)
+      SL1M_SRV_FWD(2, false);
+    else
+      SL1M_SRV_FWD(1, false);
+#undef SL1M_SRV_FWD
+  }
+}
+
+// Sum of forward partial rows, gain, residual; adjoint residual records, or
+// (objective phase) per-block partials of |V - M I|^2.
+__global__ __launch_bounds__(kBlock) void k_srv_reduce(const TabDev* __restrict__ tab,
+                                                       ReqDev* __restrict__ reqs) {
+  __shared__ double sh[kBlock];
+  const int64_t total = tab->total;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const SegDev sg = tab->seg[find_seg(tab, w)];
+    ReqDev& q = reqs[sg.slot];
+    const int64_t blk = sg.begin + (w - sg.prefix);
+    const int64_t k = blk * kBlock + threadIdx.x;
+    double l2 = 0.0;
+    if (k < q.n_vis) {
+      float re = 0.f, im = 0.f;
+      for (int c = 0; c < q.n_fchunks; ++c) {
+        const float2 v = q.fpart[static_cast<int64_t>(c) * q.n_vis + k];
+        re += v.x;
+        im += v.y;
+      }
+      const float gr = q.vgain ? q.vgain[2 * k] : 1.f, gi = q.vgain ? q.vgain[2 * k + 1] : 0.f;
+      if (q.vgain) {
+        const float tr = gr * re - gi * im;
+        im = gr * im + gi * re;
+        re = tr;
+      }
+      if (sg.flags & (sched::F_FISTA | sched::F_OBJECTIVE)) {
+        re -= q.data[k].x;
+        im -= q.data[k].y;
+      }
+      if (sg.flags & sched::F_OBJECTIVE)
+        l2 = static_cast<double>(re) * re + static_cast<double>(im) * im;
+      else
+        write_res<float>(q.rres, q.layerDs, q.n_layers, q.n_vis, 1, k, 0, gr, gi, re, im);
+    }
+    if (sg.flags & sched::F_OBJECTIVE) {
+      l2 = srv_block_sum(l2, sh);
+      if (threadIdx.x == 0) q.red[blk] = l2;
+    }
+  }
+}
+
+template <bool GAUSS>
+__global__ __launch_bounds__(kBlock) void k_srv_adj(const TabDev* __restrict__ tab,
+                                                    const ReqDev* __restrict__ reqs) {
+  const int64_t total = tab->total;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const SegDev sg = tab->seg[find_seg(tab, w)];
+    const ReqDev& q = reqs[sg.slot];
+    const int64_t item = sg.begin + (w - sg.prefix);
+    const int64_t kc = item % q.n_achunks;
+    const int64_t tile = (GAUSS ? q.n_pd : 0) + item / q.n_achunks;
+    const Chunk tl = q.ptiles[tile];
+    float* row = q.apart + kc * q.n_pix;
+#define SL1M_SRV_ADJ(PPL, BEAM)                                                                     \
+  (GAUSS ? adj_gauss_tile<float, PPL, BEAM, 1>(q.visrecG, q.rres, q.vbeta, q.pl, q.pm, q.pc3,       \
+                                               q.pc4, q.pr2, tl, 0, kc, q.kchunk, q.n_vis, row, 0) \
+         : adj_delta_tile<float, PPL, BEAM, 1>(q.visrecD, q.rres, q.vbeta, q.pl, q.pm, q.pc3,       \
+                                               q.pr2, tl, 0, kc, q.kchunk, q.n_vis, row, 0))
+    if (q.beam_pair)
+      SL1M_SRV_ADJ(4, true);
+    else if (q.ppl == 4)
+      SL1M_SRV_ADJ(4, false);
+    else if (q.ppl == 2)
+      SL1M_SRV_ADJ(2, false);
+    else
+      SL1M_SRV_ADJ(1, false);
+#undef SL1M_SRV_ADJ
+  }
+}
+
+// Per pixel block: FISTA step (threshold + momentum), power-iteration update
+// (x <- g with partial <x, g> and |g|^2), or the objective pass (partial sum
+// and non-zero count, copy of the image to the caller's order).
+__global__ __launch_bounds__(kBlock) void k_srv_update(const TabDev* __restrict__ tab,
+                                                       ReqDev* __restrict__ reqs) {
+  __shared__ double sh[kBlock];
+  const int64_t total = tab->total;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const SegDev sg = tab->seg[find_seg(tab, w)];
+    ReqDev& q = reqs[sg.slot];
+    const int64_t blk = sg.begin + (w - sg.prefix);
+    const int64_t j = blk * kBlock + threadIdx.x;
+    double p0 = 0.0, p1 = 0.0;
+    if (j < q.n_pix) {
+      if (sg.flags & sched::F_OBJECTIVE) {
+        const float v = q.img[j];
+        p0 = v;
+        p1 = v != 0.f ? 1.0 : 0.0;
+        q.out[q.perm[j]] = v;
+      } else {
+        float g = 0.f;
+        for (int c = 0; c < q.n_achunks; ++c) g += q.apart[static_cast<int64_t>(c) * q.n_pix + j];
+        g *= q.pscale[j];
+        if (sg.flags & sched::F_POWER) {
+          const float xo = q.x[j] * static_cast<float>(q.xscale);
+          p0 = static_cast<double>(xo) * g;
+          p1 = static_cast<double>(g) * g;
+          q.x[j] = g;
+        } else {
+          const double t = q.t;
+          const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+          const float beta = static_cast<float>((t - 1.0) / tn);
+          const float z = q.y[j] - g * static_cast<float>(q.inv_L);
+          if (!isfinite(z)) atomicOr(q.flag, 1);
+          const float thr = static_cast<float>(q.thr);
+          const float in = z > thr ? z - thr : 0.f;
+          const float io = q.img[j];
+          q.y[j] = in + beta * (in - io);
+          q.img[j] = in;
+        }
+      }
+    }
+    if (sg.flags & (sched::F_POWER | sched::F_OBJECTIVE)) {
+      p0 = srv_block_sum(p0, sh);
+      p1 = srv_block_sum(p1, sh);
+      if (threadIdx.x == 0) {
+        q.red[q.vis_blocks + 2 * blk] = p0;
+        q.red[q.vis_blocks + 2 * blk + 1] = p1;
+      }
+    }
+  }
+}
+
+// One block per request: fixed-order sums of the partials and the scalar
+// state updates (power step, FISTA momentum, objective terms).
+__global__ __launch_bounds__(kBlock) void k_srv_final(const TabDev* __restrict__ tab,
+                                                      ReqDev* __restrict__ reqs) {
+  __shared__ double sh[kBlock];
+  const int64_t total = tab->total;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const SegDev sg = tab->seg[find_seg(tab, w)];
+    ReqDev& q = reqs[sg.slot];
+    if (sg.flags & sched::F_FISTA) {
+      if (threadIdx.x == 0) q.t = 0.5 * (1.0 + sqrt(1.0 + 4.0 * q.t * q.t));
+      continue;
+    }
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < q.pix_blocks; i += blockDim.x) {
+      a += q.red[q.vis_blocks + 2 * i];
+      b += q.red[q.vis_blocks + 2 * i + 1];
+    }
+    if (sg.flags & sched::F_OBJECTIVE)
+      for (int64_t i = threadIdx.x; i < q.vis_blocks; i += blockDim.x) c += q.red[i];
+    a = srv_block_sum(a, sh);
+    b = srv_block_sum(b, sh);
+    c = srv_block_sum(c, sh);
+    if (threadIdx.x == 0) {
+      if (sg.flags & sched::F_POWER) {
+        q.rq = a;
+        q.xscale = b > 0.0 ? 1.0 / sqrt(b) : 0.0;
+        if (sg.flags & sched::F_LAST_POWER) {
+          q.L = q.L_safety * a;
+          q.inv_L = 1.0 / q.L;
+          q.thr = q.lam / q.L;
+          q.t = 1.0;
+        }
+      } else {
+        q.l2 = 0.5 * c;
+        q.l1 = a;
+        q.nnz = b;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct Ticket {
+  sched::Request req;
+  sl1m_problem problem;
+  const void* vis = nullptr;
+  void* img_out = nullptr;
+  sl1m_solve_params params{};
+  enum State { PENDING, ACTIVE, DONE, CANCELLED } state = PENDING;
+  sl1m_plan* plan = nullptr;
+  size_t arena_off = 0;
+  size_t footprint = 0;
+  sl1m_solve_info info{};
+  double submit_s = 0, admit_s = 0, finish_s = 0;
+  bool freed = true;
+};
+
+}  // namespace
+}  // namespace sl1m
+
+struct sl1m_server {
+  std::mutex mu;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  sl1m::sched::Arena alloc;
+  int max_slots = 0;
+  int grid = 1 << 24;                  // one block per work item (hardware balances the load)
+  double budget = 3e10;                // evals per round, shared by the active requests
+  hipStream_t stream = nullptr;        // rounds (non-blocking, default priority)
+  hipStream_t admit_stream = nullptr;  // plan creation of admitted requests
+  hipEvent_t admit_event = nullptr;
+  sl1m::ReqDev* d_reqs = nullptr;
+  sl1m::TabDev* d_tabs = nullptr;      // [kSrvRing][K_COUNT]
+  sl1m::TabDev* h_tabs = nullptr;      // pinned mirror
+  hipEvent_t ring_event[sl1m::kSrvRing] = {};
+  int64_t ring_round[sl1m::kSrvRing] = {-1, -1, -1, -1};
+  std::vector<int> free_slots;
+  std::map<uint64_t, std::unique_ptr<sl1m::Ticket>> tickets;
+  std::deque<uint64_t> pending;
+  std::vector<uint64_t> active;         // tickets in slot order of admission
+  std::deque<std::pair<int64_t, std::vector<uint64_t>>> finishing;  // round -> tickets
+  uint64_t next_ticket = 1;
+  int64_t round = 0;
+  int64_t completed_round = -1;
+  double evals_scheduled = 0;
+  std::chrono::steady_clock::time_point t0;
+};
+
+namespace sl1m {
+namespace {
+
+double now_s(const sl1m_server* s) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+}
+
+#define SRV_HIP(call, what)                           \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_error(e_, what); \
+  } while (0)
+
+size_t extra_bytes(const sl1m_problem& p) {
+  const size_t np = static_cast<size_t>(p.n_pix), nv = static_cast<size_t>(p.n_vis);
+  const size_t vb = (nv + kBlock - 1) / kBlock, pb = (np + kBlock - 1) / kBlock;
+  return sched::Arena::round_up(4 * np) + sched::Arena::round_up(8 * (vb + 2 * pb + 2)) +
+         sched::Arena::round_up(sizeof(int));
+}
+
+// Releases memory and slot of requests whose last round has completed.
+void harvest(sl1m_server* s) {
+  for (int i = 0; i < kSrvRing; ++i) {
+    if (s->ring_round[i] < 0) continue;
+    const hipError_t q = hipEventQuery(s->ring_event[i]);
+    if (q == hipSuccess) {
+      s->completed_round = std::max(s->completed_round, s->ring_round[i]);
+      s->ring_round[i] = -1;
+    } else if (q == hipErrorNotReady) {
+      (void)hipGetLastError();  // "not ready" is not an error; keep launch checks clean
+    }
+  }
+  // rounds complete in order on one stream: everything up to completed_round is done
+  while (!s->finishing.empty() && s->finishing.front().first <= s->completed_round) {
+    for (uint64_t id : s->finishing.front().second) {
+      Ticket& t = *s->tickets[id];
+      if (t.state != Ticket::ACTIVE) continue;
+      // the round has completed; read through the (non-blocking) admission
+      // stream so that rounds still in flight are not waited for
+      ReqDev q;
+      int nonfinite = 0;
+      hipError_t e = hipMemcpyAsync(&q, s->d_reqs + t.req.slot, sizeof(ReqDev),
+                                    hipMemcpyDeviceToHost, s->admit_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->admit_stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&nonfinite, q.flag, sizeof(int), hipMemcpyDeviceToHost,
+                           s->admit_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->admit_stream);
+      if (e != hipSuccess) {
+        t.info.status = SL1M_EHIP;
+      } else {
+        t.info.iters = t.params.max_iter;
+        t.info.L = q.L;
+        t.info.l2_term = q.l2;
+        t.info.l1_term = q.l1;
+        t.info.F = q.l2 + t.params.lambda * q.l1;
+        t.info.nnz = static_cast<int64_t>(q.nnz);
+        t.info.status = (nonfinite || !std::isfinite(t.info.F)) ? SL1M_EDIVERGED : SL1M_OK;
+      }
+      t.finish_s = now_s(s);
+      t.state = Ticket::DONE;
+    }
+    s->finishing.pop_front();
+  }
+  // free memory of finished or cancelled requests once no in-flight round uses it
+  for (auto it = s->active.begin(); it != s->active.end();) {
+    Ticket& t = *s->tickets[*it];
+    const bool over = t.state == Ticket::DONE || t.state == Ticket::CANCELLED;
+    if (over && t.req.last_round <= s->completed_round) {
+      if (t.plan) sl1m_plan_destroy(t.plan);
+      t.plan = nullptr;
+      s->alloc.release(t.arena_off);
+      s->free_slots.push_back(t.req.slot);
+      t.freed = true;
+      it = s->active.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+sl1m_status admit(sl1m_server* s, Ticket& t) {
+  const sl1m_problem& pr = t.problem;
+  size_t ws = 0;
+  if (sl1m_status st = sl1m_plan_workspace_bytes(&pr, &ws)) return st;
+  const size_t ws_al = sched::Arena::round_up(ws);
+  char* base = s->arena + t.arena_off;
+  sl1m_plan* plan = nullptr;
+  if (sl1m_status st = sl1m_plan_create(&pr, base, ws_al, s->admit_stream, &plan)) return st;
+  t.plan = plan;
+  char* extra = base + ws_al;
+  float* y = reinterpret_cast<float*>(extra);
+  double* red = reinterpret_cast<double*>(extra + sched::Arena::round_up(4 * pr.n_pix));
+  const size_t vb = (pr.n_vis + kBlock - 1) / kBlock, pb = (pr.n_pix + kBlock - 1) / kBlock;
+  int* flag = reinterpret_cast<int*>(reinterpret_cast<char*>(red) +
+                                     sched::Arena::round_up(8 * (vb + 2 * pb + 2)));
+  hipStream_t st = s->admit_stream;
+  SRV_HIP(launch_fill(y, pr.n_pix, 4, st), "zero y");
+  SRV_HIP(launch_fill(plan->img, pr.n_pix, 4, st), "zero I");
+  SRV_HIP(launch_fill(flag, 1, sizeof(int), st), "zero flag");
+  const bool power = !(t.params.L > 0.0);
+  double xscale = 1.0;
+  if (power && pr.n_pix > 0) {
+    SRV_HIP(launch_splitmix_start(plan, t.params.seed, plan->xperm, st), "start vector");
+    SRV_HIP(launch_dot_norm(plan, plan->xperm, plan->xperm, st), "start norm");
+    double h[2];
+    SRV_HIP(hipMemcpyAsync(h, plan->red_out, sizeof(h), hipMemcpyDeviceToHost, st), "read norm");
+    SRV_HIP(hipStreamSynchronize(st), "admission sync");
+    if (!(h[1] > 0.0)) return set_error(SL1M_EINVAL, "power iteration start vector is zero");
+    xscale = 1.0 / std::sqrt(h[1]);
+  }
+  ReqDev q{};
+  q.pix = static_cast<const PixRec<float>*>(plan->pixrec);
+  q.vu = plan->vu;
+  q.vv = plan->vv;
+  q.vw = plan->vw;
+  q.vgain = static_cast<const float*>(plan->vgain);
+  q.vbeta = static_cast<const float*>(plan->vbeta);
+  q.visrecD = static_cast<const VisRecD<float>*>(plan->visrecD);
+  q.visrecG = static_cast<const VisRecG<float>*>(plan->visrecG);
+  q.layerDs = static_cast<const float*>(plan->layerDs);
+  q.rres = static_cast<float2*>(plan->rres);
+  q.pl = plan->pl;
+  q.pm = plan->pm;
+  q.pc3 = plan->pc3;
+  q.pc4 = plan->pc4;
+  q.pscale = static_cast<const float*>(plan->pscale);
+  q.pr2 = static_cast<const float*>(plan->pr2);
+  q.perm = plan->perm;
+  q.fchunks = plan->d_fchunks;
+  q.ptiles = plan->d_ptiles;
+  q.fpart = static_cast<float2*>(plan->fpart);
+  q.apart = static_cast<float*>(plan->apart);
+  q.x = static_cast<float*>(plan->xperm);
+  q.y = y;
+  q.img = static_cast<float*>(plan->img);
+  q.data = static_cast<const float2*>(t.vis);
+  q.out = static_cast<float*>(t.img_out);
+  q.red = red;
+  q.flag = flag;
+  q.n_pix = plan->n_pix;
+  q.n_vis = plan->n_vis;
+  q.kchunk = plan->adj_kchunk;
+  q.vpl = plan->beam_pair ? 4 : plan->fwd_vpl;
+  q.ppl = plan->beam_pair ? 4 : plan->adj_ppl;
+  q.vtiles = (plan->n_vis + kBlock * q.vpl - 1) / (kBlock * q.vpl);
+  q.vis_blocks = static_cast<int64_t>(vb);
+  q.pix_blocks = static_cast<int64_t>(pb);
+  q.n_fchunks = plan->n_fchunks;
+  q.n_fd = static_cast<int32_t>(plan->fchunks_delta.size());
+  q.n_achunks = plan->n_achunks;
+  q.n_pd = static_cast<int32_t>(plan->ptiles_delta.size());
+  q.n_layers = plan->n_layers;
+  q.beam_pair = plan->beam_pair ? 1 : 0;
+  q.t = 1.0;
+  q.lam = t.params.lambda;
+  q.L_safety = t.params.L_safety > 0.0 ? t.params.L_safety : 1.01;
+  q.L = power ? 0.0 : t.params.L;
+  q.inv_L = power ? 0.0 : 1.0 / t.params.L;
+  q.thr = power ? 0.0 : t.params.lambda / t.params.L;
+  q.xscale = xscale;
+  SRV_HIP(hipMemcpyAsync(s->d_reqs + t.req.slot, &q, sizeof(ReqDev), hipMemcpyHostToDevice, st),
+          "upload request descriptor");
+  SRV_HIP(hipStreamSynchronize(st), "admission sync");
+  // work-item counts
+  sched::Shape& sh = t.req.shape;
+  sh.fwd_delta = q.vtiles * q.n_fd;
+  sh.fwd_gauss = q.vtiles * (q.n_fchunks - q.n_fd);
+  const int64_t n_pt = static_cast<int64_t>(plan->ptiles_delta.size() + plan->ptiles_gauss.size());
+  sh.adj_delta = static_cast<int64_t>(q.n_pd) * q.n_achunks;
+  sh.adj_gauss = (n_pt - q.n_pd) * q.n_achunks;
+  sh.vis_blocks = q.vis_blocks;
+  sh.pix_blocks = q.pix_blocks;
+  sh.evals_per_op = static_cast<double>(pr.n_pix) * static_cast<double>(pr.n_vis);
+  sh.power_iters = power ? (t.params.power_iters > 0 ? t.params.power_iters : 30) : 0;
+  sh.max_iter = t.params.max_iter;
+  sched::start_request(t.req);
+  return SL1M_OK;
+}
+
+sl1m_status launch_round(sl1m_server* s) {
+  std::vector<sched::Request*> act;
+  for (uint64_t id : s->active) {
+    Ticket& t = *s->tickets[id];
+    if (t.state == Ticket::ACTIVE) act.push_back(&t.req);
+  }
+  if (act.empty()) return SL1M_OK;
+  const int ring = static_cast<int>(s->round % kSrvRing);
+  if (s->ring_round[ring] >= 0) {  // the buffers are still in use by an older round
+    SRV_HIP(hipEventSynchronize(s->ring_event[ring]), "round sync");
+    s->completed_round = std::max(s->completed_round, s->ring_round[ring]);
+    s->ring_round[ring] = -1;
+  }
+  // each request's share of the round, with a floor so that a crowded round
+  // still moves every request by a useful amount
+  const double share = std::max(s->budget / static_cast<double>(act.size()), s->budget / 32.0);
+  sched::RoundPlan rp;
+  sched::plan_round(act, share, s->round, rp);
+  TabDev* ht = s->h_tabs + ring * sched::K_COUNT;
+  for (int k = 0; k < sched::K_COUNT; ++k) {
+    TabDev& tb = ht[k];
+    tb.n_seg = static_cast<int32_t>(rp.seg[k].size());
+    int64_t pre = 0;
+    for (int i = 0; i < tb.n_seg; ++i) {
+      const Segment& g = rp.seg[k][i];
+      tb.seg[i] = SegDev{g.slot, g.flags, g.begin, g.end, pre};
+      pre += g.end - g.begin;
+    }
+    tb.total = pre;
+  }
+  TabDev* dt = s->d_tabs + ring * sched::K_COUNT;
+  SRV_HIP(hipMemcpyAsync(dt, ht, sizeof(TabDev) * sched::K_COUNT, hipMemcpyHostToDevice, s->stream),
+          "upload round tables");
+  auto go = [&](int k, auto kernel, auto* reqs) -> hipError_t {
+    if (ht[k].total == 0) return hipSuccess;
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>(s->grid, ht[k].total));
+    hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, s->stream, dt + k, reqs);
+    return hipGetLastError();
+  };
+  const ReqDev* cr = s->d_reqs;
+  ReqDev* r = s->d_reqs;
+  SRV_HIP(go(sched::K_FWD_DELTA, k_srv_fwd<false>, cr), "batched forward (delta)");
+  SRV_HIP(go(sched::K_FWD_GAUSS, k_srv_fwd<true>, cr), "batched forward (Gaussian)");
+  SRV_HIP(go(sched::K_REDUCE, k_srv_reduce, r), "batched reduce");
+  SRV_HIP(go(sched::K_ADJ_DELTA, k_srv_adj<false>, cr), "batched adjoint (delta)");
+  SRV_HIP(go(sched::K_ADJ_GAUSS, k_srv_adj<true>, cr), "batched adjoint (Gaussian)");
+  SRV_HIP(go(sched::K_UPDATE, k_srv_update, r), "batched update");
+  SRV_HIP(go(sched::K_FINAL, k_srv_final, r), "batched final");
+  SRV_HIP(hipEventRecord(s->ring_event[ring], s->stream), "record round event");
+  s->ring_round[ring] = s->round;
+  if (!rp.finishing.empty()) s->finishing.emplace_back(s->round, rp.finishing);
+  s->evals_scheduled += rp.evals;  // forward and adjoint item evals
+  ++s->round;
+  return SL1M_OK;
+}
+
+}  // namespace
+}  // namespace sl1m
+
+using namespace sl1m;
+
+extern "C" {
+
+sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
+                               double round_budget_evals, sl1m_server** out) {
+  try {
+    if (!out) return set_error(SL1M_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!arena || reinterpret_cast<uintptr_t>(arena) % 256 != 0)
+      return set_error(SL1M_EINVAL, "arena must be a 256-byte aligned device pointer");
+    if (max_slots < 1 || max_slots > kSrvMaxSlots)
+      return set_error(SL1M_EINVAL, "max_slots must be in [1, 64]");
+    const size_t hdr = sched::Arena::round_up(sizeof(ReqDev) * kSrvMaxSlots) +
+                       sched::Arena::round_up(sizeof(TabDev) * kSrvRing * sched::K_COUNT);
+    if (arena_bytes < hdr + (1u << 20)) return set_error(SL1M_ENOMEM, "arena too small");
+    auto s = std::make_unique<sl1m_server>();
+    s->t0 = std::chrono::steady_clock::now();
+    s->d_reqs = reinterpret_cast<ReqDev*>(arena);
+    s->d_tabs = reinterpret_cast<TabDev*>(static_cast<char*>(arena) +
+                                          sched::Arena::round_up(sizeof(ReqDev) * kSrvMaxSlots));
+    s->arena = static_cast<char*>(arena) + hdr;
+    s->arena_bytes = arena_bytes - hdr;
+    s->alloc.reset(s->arena_bytes);
+    s->max_slots = max_slots;
+    s->budget = round_budget_evals > 0 ? round_budget_evals : 3e10;
+    for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+    SRV_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->h_tabs),
+                          sizeof(TabDev) * kSrvRing * sched::K_COUNT, hipHostMallocDefault),
+            "pinned round tables");
+    SRV_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "round stream");
+    SRV_HIP(hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking), "admission stream");
+    for (auto& e : s->ring_event) SRV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    *out = s.release();
+    return SL1M_OK;
+  } catch (...) {
+    return set_error(SL1M_ENOMEM, "host allocation failed");
+  }
+}
+
+sl1m_status sl1m_server_submit(sl1m_server* s, const sl1m_problem* problem, const void* vis,
+                               const sl1m_solve_params* params, void* img_out,
+                               uint64_t* ticket) {
+  try {
+    if (!s || !problem || !params || !ticket) return set_error(SL1M_EINVAL, "NULL argument");
+    if (problem->precision != SL1M_PREC_FP32)
+      return set_error(SL1M_EINVAL, "the server runs FP32 plans only");
+    if (problem->max_rhs > 1) return set_error(SL1M_EINVAL, "the server solves one image each");
+    if ((problem->n_vis > 0 && !vis) || (problem->n_pix > 0 && !img_out))
+      return set_error(SL1M_EINVAL, "vis or img_out is NULL");
+    if (!(params->lambda >= 0.0) || params->max_iter < 0)
+      return set_error(SL1M_EINVAL, "lambda must be >= 0 and max_iter >= 0");
+    auto t = std::make_unique<Ticket>();
+    t->problem = *problem;
+    t->problem.tile_blocks = problem->tile_blocks > 0 ? problem->tile_blocks : kSrvTileBlocks;
+    size_t ws = 0;
+    if (sl1m_status st = sl1m_plan_workspace_bytes(&t->problem, &ws)) return st;
+    t->footprint = sched::Arena::round_up(ws) + extra_bytes(t->problem);
+    t->vis = vis;
+    t->img_out = img_out;
+    t->params = *params;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (t->footprint > s->alloc.size())
+      return set_error(SL1M_ENOMEM, "request footprint exceeds the server arena");
+    t->submit_s = now_s(s);
+    const uint64_t id = s->next_ticket++;
+    t->req.ticket = id;
+    s->tickets[id] = std::move(t);
+    s->pending.push_back(id);
+    *ticket = id;
+    return SL1M_OK;
+  } catch (...) {
+    return set_error(SL1M_ENOMEM, "host allocation failed");
+  }
+}
+
+sl1m_status sl1m_server_step(sl1m_server* s, int32_t* n_active, int32_t* n_pending) {
+  try {
+    if (!s) return set_error(SL1M_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    harvest(s);
+    // admit pending requests (in submission order) while slots and memory allow
+    for (auto it = s->pending.begin(); it != s->pending.end() && !s->free_slots.empty();) {
+      Ticket& t = *s->tickets[*it];
+      size_t off = 0;
+      if (!s->alloc.alloc(t.footprint, &off)) {
+        ++it;
+        continue;
+      }
+      t.arena_off = off;
+      t.req.slot = s->free_slots.back();
+      s->free_slots.pop_back();
+      t.freed = false;
+      sl1m_status st = admit(s, t);
+      if (st != SL1M_OK) {
+        if (t.plan) sl1m_plan_destroy(t.plan);
+        t.plan = nullptr;
+        s->alloc.release(off);
+        s->free_slots.push_back(t.req.slot);
+        t.freed = true;
+        t.state = Ticket::DONE;
+        t.info.status = st;
+        it = s->pending.erase(it);
+        continue;
+      }
+      t.admit_s = now_s(s);
+      t.state = Ticket::ACTIVE;
+      s->active.push_back(t.req.ticket);
+      it = s->pending.erase(it);
+    }
+    sl1m_status st = launch_round(s);
+    if (n_active) {
+      int32_t a = 0;
+      for (uint64_t id : s->active)
+        if (s->tickets[id]->state == Ticket::ACTIVE) ++a;
+      *n_active = a;
+    }
+    if (n_pending) *n_pending = static_cast<int32_t>(s->pending.size());
+    return st;
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
+}
+
+sl1m_status sl1m_server_poll(sl1m_server* s, uint64_t ticket, sl1m_solve_info* info,
+                             int32_t* done, double* times) {
+  if (!s || !done) return set_error(SL1M_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return set_error(SL1M_EINVAL, "unknown ticket");
+  Ticket& t = *it->second;
+  *done = t.state == Ticket::DONE || t.state == Ticket::CANCELLED;
+  if (info) *info = t.info;
+  if (t.state == Ticket::CANCELLED && info) info->status = SL1M_ECANCELLED;
+  if (times) {
+    times[0] = t.submit_s;
+    times[1] = t.admit_s;
+    times[2] = t.finish_s;
+  }
+  return SL1M_OK;
+}
+
+sl1m_status sl1m_server_cancel(sl1m_server* s, uint64_t ticket) {
+  if (!s) return set_error(SL1M_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return set_error(SL1M_EINVAL, "unknown ticket");
+  Ticket& t = *it->second;
+  if (t.state == Ticket::PENDING) {
+    for (auto p = s->pending.begin(); p != s->pending.end(); ++p)
+      if (*p == ticket) {
+        s->pending.erase(p);
+        break;
+      }
+    t.state = Ticket::CANCELLED;
+  } else if (t.state == Ticket::ACTIVE) {
+    t.req.cancelled = true;
+    t.state = Ticket::CANCELLED;
+  }
+  return SL1M_OK;
+}
+
+sl1m_status sl1m_server_stats(sl1m_server* s, sl1m_server_stats_t* out) {
+  if (!s || !out) return set_error(SL1M_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->rounds = s->round;
+  out->completed_rounds = s->completed_round + 1;
+  out->evals_scheduled = s->evals_scheduled;
+  out->arena_bytes = s->alloc.size();
+  out->arena_used = s->alloc.used_bytes();
+  int32_t a = 0;
+  for (uint64_t id : s->active)
+    if (s->tickets[id]->state == Ticket::ACTIVE) ++a;
+  out->active = a;
+  out->pending = static_cast<int32_t>(s->pending.size());
+  return SL1M_OK;
+}
+
+sl1m_status sl1m_server_destroy(sl1m_server* s) {
+  if (!s) return SL1M_OK;
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->admit_stream);
+  for (auto& kv : s->tickets)
+    if (kv.second->plan) sl1m_plan_destroy(kv.second->plan);
+  for (auto& e : s->ring_event)
+    if (e) (void)hipEventDestroy(e);
+  if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->h_tabs) (void)hipHostFree(s->h_tabs);
+  delete s;
+  return SL1M_OK;
+}
+
+}  // extern "C"

@@ -47,11 +47,25 @@ class Problem(ctypes.Structure):
         ("ant_fwhm", ctypes.c_void_p),
         ("precision", ctypes.c_int32),
         ("max_rhs", ctypes.c_int32),
+        ("tile_blocks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
 class Timing(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("rounds", ctypes.c_int64),
+        ("completed_rounds", ctypes.c_int64),
+        ("evals_scheduled", ctypes.c_double),
+        ("arena_bytes", ctypes.c_uint64),
+        ("arena_used", ctypes.c_uint64),
+        ("active", ctypes.c_int32),
+        ("pending", ctypes.c_int32),
+    ]
 
 
 class SolveParams(ctypes.Structure):
@@ -104,6 +118,16 @@ def lib() -> ctypes.CDLL:
         L.sl1m_adjoint_multi.argtypes = [vp, i32, vp, vp, vp]
         L.sl1m_estimate_L.argtypes = [vp, i32, u64, vp, ctypes.POINTER(dbl), vp]
         L.sl1m_solve.argtypes = [vp, vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(SolveInfo), vp]
+        L.sl1m_server_create.argtypes = [vp, ctypes.c_size_t, i32, dbl, ctypes.POINTER(vp)]
+        L.sl1m_server_submit.argtypes = [vp, ctypes.POINTER(Problem), vp,
+                                         ctypes.POINTER(SolveParams), vp,
+                                         ctypes.POINTER(ctypes.c_uint64)]
+        L.sl1m_server_step.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.sl1m_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(SolveInfo),
+                                       ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+        L.sl1m_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.sl1m_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.sl1m_server_destroy.argtypes = [vp]
         L.sl1m_timing_begin.argtypes = [vp, i32]
         L.sl1m_timing_end.argtypes = [vp, ctypes.POINTER(Timing)]
         L.sl1m_last_error.restype = ctypes.c_char_p
@@ -111,7 +135,9 @@ def lib() -> ctypes.CDLL:
         for name in ("sl1m_plan_workspace_bytes", "sl1m_plan_create", "sl1m_plan_destroy",
                      "sl1m_forward", "sl1m_adjoint", "sl1m_forward_multi",
                      "sl1m_adjoint_multi", "sl1m_estimate_L", "sl1m_solve",
-                     "sl1m_timing_begin", "sl1m_timing_end"):
+                     "sl1m_timing_begin", "sl1m_timing_end", "sl1m_server_create",
+                     "sl1m_server_submit", "sl1m_server_step", "sl1m_server_poll",
+                     "sl1m_server_cancel", "sl1m_server_stats", "sl1m_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -149,7 +175,7 @@ class Plan:
 
     def __init__(self, l, m, u, v, w, sigma=None, kind=None, ant_p=None, ant_q=None,
                  ant_gain=None, ant_fwhm=None, precision: str = "fp32", device="cuda",
-                 stream=None, max_rhs: int = 1):
+                 stream=None, max_rhs: int = 1, tile_blocks: int = 0):
         self.device = torch.device(device)
         self.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
         self.rdtype = torch.float32 if self.precision == PREC_FP32 else torch.float64
@@ -182,7 +208,8 @@ class Plan:
             kind=_ptr(k["kind"]), n_vis=self.n_vis, u=_ptr(k["u"]), v=_ptr(k["v"]),
             w=_ptr(k["w"]), ant_p=_ptr(k["ant_p"]), ant_q=_ptr(k["ant_q"]), n_ant=n_ant,
             ant_gain=_ptr(k["ant_gain"]), ant_fwhm=_ptr(k["ant_fwhm"]),
-            precision=self.precision, max_rhs=int(max_rhs))
+            precision=self.precision, max_rhs=int(max_rhs), tile_blocks=int(tile_blocks),
+            reserved=0)
         self.max_rhs = int(max_rhs)
         nbytes = ctypes.c_size_t(0)
         _check(lib().sl1m_plan_workspace_bytes(ctypes.byref(self._prob), ctypes.byref(nbytes)))
@@ -195,13 +222,14 @@ class Plan:
         self._h = h
 
     @classmethod
-    def from_workload(cls, wl, precision="fp32", device="cuda", with_kinds=True, max_rhs=1):
+    def from_workload(cls, wl, precision="fp32", device="cuda", with_kinds=True, max_rhs=1,
+                      tile_blocks=0):
         kw = {}
         if with_kinds and (np.any(wl.kind != 0) or np.any(wl.sigma != 0)):
             kw = dict(sigma=wl.sigma, kind=wl.kind)
         return cls(wl.l, wl.m, wl.u, wl.v, wl.w, ant_p=wl.ant_p, ant_q=wl.ant_q,
                    ant_gain=wl.ant_gain, ant_fwhm=wl.ant_fwhm, precision=precision,
-                   device=device, max_rhs=max_rhs, **kw)
+                   device=device, max_rhs=max_rhs, tile_blocks=tile_blocks, **kw)
 
     # -- operator -----------------------------------------------------------
     def forward(self, x, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -281,3 +309,116 @@ class Plan:
 
 def version() -> str:
     return lib().sl1m_version().decode()
+
+
+class Server:
+    """Continuous-batching server (sl1m_server_*): many FP32 solves share one
+    GPU.  The arena is a torch uint8 tensor owned by this object; submitted
+    requests keep their device inputs and output alive until done."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 32, round_budget: float = 3e10,
+                 device="cuda"):
+        self.device = torch.device(device)
+        self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(lib().sl1m_server_create(_ptr(self._arena), ctypes.c_size_t(self._arena.numel()),
+                                        int(max_slots), float(round_budget), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, wl, vis, lam: float, max_iter: int, L: float = 0.0,
+               power_iters: int = 30, seed: int = 0, L_safety: float = 1.01) -> int:
+        """wl: a workload-like object (l, m, u, v, w, sigma, kind, gains);
+        vis: complex data [n_vis] (device tensor or array)."""
+        d = self.device
+        keep = dict(
+            l=_dev(wl.l, torch.float64, d), m=_dev(wl.m, torch.float64, d),
+            u=_dev(wl.u, torch.float64, d), v=_dev(wl.v, torch.float64, d),
+            w=_dev(wl.w, torch.float64, d))
+        has_kind = wl.kind is not None and (np.any(np.asarray(wl.kind) != 0) or
+                                            np.any(np.asarray(wl.sigma) != 0))
+        keep["sigma"] = _dev(wl.sigma, torch.float64, d) if has_kind else None
+        keep["kind"] = _dev(wl.kind, torch.uint8, d) if has_kind else None
+        n_ant = 0
+        keep["ant_p"] = _dev(getattr(wl, "ant_p", None), torch.int32, d)
+        keep["ant_q"] = _dev(getattr(wl, "ant_q", None), torch.int32, d)
+        keep["ant_fwhm"] = _dev(getattr(wl, "ant_fwhm", None), torch.float64, d)
+        g = getattr(wl, "ant_gain", None)
+        if g is not None:
+            g = np.asarray(g, np.complex128)
+            keep["ant_gain"] = torch.as_tensor(np.stack([g.real, g.imag], 1).ravel(),
+                                               dtype=torch.float64, device=d)
+            n_ant = g.shape[0]
+        else:
+            keep["ant_gain"] = None
+        if keep["ant_fwhm"] is not None:
+            n_ant = max(n_ant, int(keep["ant_fwhm"].shape[0]))
+        if keep["ant_p"] is not None and n_ant == 0:
+            n_ant = int(max(int(keep["ant_p"].max()), int(keep["ant_q"].max()))) + 1
+        keep["vis"] = _dev(vis, torch.complex64, d)
+        n_pix, n_vis = int(keep["l"].shape[0]), int(keep["u"].shape[0])
+        keep["out"] = torch.zeros(n_pix, dtype=torch.float32, device=d)
+        prob = Problem(n_pix=n_pix, l=_ptr(keep["l"]), m=_ptr(keep["m"]),
+                       sigma=_ptr(keep["sigma"]), kind=_ptr(keep["kind"]), n_vis=n_vis,
+                       u=_ptr(keep["u"]), v=_ptr(keep["v"]), w=_ptr(keep["w"]),
+                       ant_p=_ptr(keep["ant_p"]), ant_q=_ptr(keep["ant_q"]), n_ant=n_ant,
+                       ant_gain=_ptr(keep["ant_gain"]), ant_fwhm=_ptr(keep["ant_fwhm"]),
+                       precision=PREC_FP32, max_rhs=1, tile_blocks=0, reserved=0)
+        prm = SolveParams(lam=float(lam), eps=0.0, max_iter=int(max_iter), check_every=1,
+                          L=float(L), L_safety=float(L_safety), power_iters=int(power_iters),
+                          reserved=0, seed=ctypes.c_uint64(seed))
+        t = ctypes.c_uint64(0)
+        torch.cuda.current_stream(d).synchronize()   # inputs written before the server reads them
+        _check(lib().sl1m_server_submit(self._h, ctypes.byref(prob), _ptr(keep["vis"]),
+                                        ctypes.byref(prm), _ptr(keep["out"]), ctypes.byref(t)))
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def step(self):
+        a, p = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().sl1m_server_step(self._h, ctypes.byref(a), ctypes.byref(p)))
+        return a.value, p.value
+
+    def poll(self, ticket: int):
+        info = SolveInfo()
+        done = ctypes.c_int32(0)
+        times = (ctypes.c_double * 3)()
+        _check(lib().sl1m_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(info),
+                                      ctypes.byref(done), times))
+        return bool(done.value), info.as_dict(), tuple(times)
+
+    def result(self, ticket: int) -> torch.Tensor:
+        return self._keep[ticket]["out"]
+
+    def release(self, ticket: int):
+        """Drop the references kept for a finished request."""
+        self._keep.pop(ticket, None)
+
+    def cancel(self, ticket: int):
+        _check(lib().sl1m_server_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().sl1m_server_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def drain(self, tickets, max_steps: int = 10_000_000):
+        """Step until every ticket is done."""
+        left = set(tickets)
+        for _ in range(max_steps):
+            self.step()
+            left = {t for t in left if not self.poll(t)[0]}
+            if not left:
+                return
+        raise RuntimeError("server did not finish")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sl1m_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

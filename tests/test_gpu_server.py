@@ -1,0 +1,140 @@
+"""GPU tests of the continuous-batching server (through the C ABI).
+
+Results against the FP64 oracle; bitwise equality of a request's image alone
+and in a mix (arrivals while others run, admission by footprint,
+cancellation of a co-scheduled request)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1310_2078_amd import sl1m
+from paper_1310_2078_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GIB = 1 << 30
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _req(seed, n_pix, n_vis, kind=W.PIX_DELTA, sigma=0.0, gains=False, n_src=4):
+    wl = W.small_random(seed, n_pix, n_vis, half_extent=0.1, uv_radius=600.0, w_sigma=80.0,
+                        kind=kind, sigma=sigma, with_gains=gains)
+    rng = np.random.default_rng(seed + 1000)
+    x = np.zeros(n_pix)
+    x[rng.choice(n_pix, n_src, replace=False)] = rng.uniform(0.5, 2.0, n_src)
+    op = O.Operator(O.Problem.from_workload(wl), dense=n_pix * n_vis <= 4_000_000)
+    V = op.forward(x) + 0.01 * (rng.standard_normal(n_vis) + 1j * rng.standard_normal(n_vis))
+    return wl, op, V
+
+
+def test_server_matches_oracle_with_given_L():
+    say("[case] server vs oracle, L given")
+    cases = [_req(1, 700, 1500), _req(2, 900, 1100, kind=W.PIX_GAUSS_WIDE, sigma=3e-3),
+             _req(3, 600, 1300, gains=True)]
+    srv = sl1m.Server(2 * GIB, max_slots=8)
+    tickets = []
+    for wl, op, V in cases:
+        L, _ = O.power_iteration(op, 30)
+        tickets.append((srv.submit(wl, V, 0.05, 40, L=L), L))
+    srv.drain([t for t, _ in tickets])
+    for (wl, op, V), (t, L) in zip(cases, tickets):
+        ok, info, _ = srv.poll(t)
+        ref = O.fista(op, V, L, 0.05, 40)
+        img = srv.result(t).cpu().numpy()
+        err = np.max(np.abs(img - ref.image)) / np.max(ref.image)
+        say(f"    n_pix={wl.n_pix} err/peak {err:.2e} F {info['F']:.6g} vs {ref.F:.6g}")
+        assert ok and info["status"] == 0
+        assert err <= 1e-4
+        assert abs(info["F"] - ref.F) <= 1e-4 * ref.F
+        assert info["nnz"] == ref.nnz
+
+
+def test_server_power_iteration_L():
+    say("[case] server power iteration")
+    wl, op, V = _req(4, 800, 1200)
+    _, rq = O.power_iteration(op, 30, seed=7)
+    srv = sl1m.Server(1 * GIB, max_slots=4)
+    t = srv.submit(wl, V, 0.05, 5, L=0.0, power_iters=30, seed=7)
+    srv.drain([t])
+    info = srv.poll(t)[1]
+    say(f"    L {info['L']:.9g} vs 1.01*rq {1.01 * rq:.9g}")
+    assert abs(info["L"] - 1.01 * rq) <= 1e-5 * rq
+
+
+def _alone(wl, V, **kw):
+    srv = sl1m.Server(2 * GIB, max_slots=4)
+    t = srv.submit(wl, V, 0.05, 30, **kw)
+    srv.drain([t])
+    return srv.result(t).cpu().numpy().copy(), srv.poll(t)[1]
+
+
+def test_alone_equals_in_mix_with_arrivals_and_cancel():
+    """Request X alone vs X arriving while Y runs, with Z cancelled mid-run."""
+    say("[case] alone == in mix")
+    X = _req(5, 1500, 2500)
+    Y = _req(6, 2500, 3000, kind=W.PIX_GAUSS_WIDE, sigma=2e-3)
+    Z = _req(7, 1000, 1000)
+    ax, ix = _alone(X[0], X[2], L=0.0)
+    ay, iy = _alone(Y[0], Y[2], L=0.0)
+    srv = sl1m.Server(2 * GIB, max_slots=8, round_budget=2e7)
+    ty = srv.submit(Y[0], Y[2], 0.05, 30)
+    srv.step()
+    srv.step()
+    tz = srv.submit(Z[0], Z[2], 0.05, 30)
+    srv.step()
+    tx = srv.submit(X[0], X[2], 0.05, 30)
+    for _ in range(5):
+        srv.step()
+    srv.cancel(tz)
+    srv.drain([tx, ty, tz])
+    assert np.array_equal(srv.result(tx).cpu().numpy(), ax)
+    assert np.array_equal(srv.result(ty).cpu().numpy(), ay)
+    assert srv.poll(tx)[1]["F"] == ix["F"] and srv.poll(ty)[1]["L"] == iy["L"]
+    assert srv.poll(tz)[1]["status"] == sl1m.ECANCELLED
+    st = srv.stats()
+    assert st["active"] == 0 and st["pending"] == 0
+
+
+def test_admission_by_footprint():
+    """Two requests that do not fit the arena together: the second waits until
+    the first has finished, and both equal their results alone."""
+    say("[case] admission by footprint")
+    wl = W.small_random(21, 8000, 6000, half_extent=0.1, uv_radius=600.0, w_sigma=80.0)
+    rng = np.random.default_rng(0)
+    V1 = 10 * (rng.standard_normal(wl.n_vis) + 1j * rng.standard_normal(wl.n_vis))
+    V2 = 10 * (rng.standard_normal(wl.n_vis) + 1j * rng.standard_normal(wl.n_vis))
+    probe = sl1m.Plan.from_workload(wl, tile_blocks=8192)
+    fp = probe.workspace_bytes + 4 * wl.n_pix + 8 * (wl.n_vis // 256 + 2 * wl.n_pix // 256 + 8) + 4096
+    probe.close()
+    a1, _ = _alone(wl, V1, L=0.0)
+    a2, _ = _alone(wl, V2, L=0.0)
+    srv = sl1m.Server((2 << 20) + int(1.5 * fp), max_slots=8, round_budget=4e7)
+    t1 = srv.submit(wl, V1, 0.05, 30)
+    t2 = srv.submit(wl, V2, 0.05, 30)
+    a, p = srv.step()
+    say(f"    footprint {fp} B; after first step active={a} pending={p}")
+    assert a == 1 and p == 1
+    srv.drain([t1, t2])
+    assert np.array_equal(srv.result(t1).cpu().numpy(), a1)
+    assert np.array_equal(srv.result(t2).cpu().numpy(), a2)
+
+
+def test_server_close_to_standalone_solve():
+    say("[case] server vs sl1m_solve")
+    wl, op, V = _req(9, 1200, 2000)
+    L, _ = O.power_iteration(op, 30)
+    plan = sl1m.Plan.from_workload(wl)
+    img_s, info_s = plan.solve(V, 0.05, 60, L=L)
+    srv = sl1m.Server(1 * GIB, max_slots=2)
+    t = srv.submit(wl, V, 0.05, 60, L=L)
+    srv.drain([t])
+    img = srv.result(t).cpu().numpy()
+    a = img_s.cpu().numpy()
+    err = np.max(np.abs(img - a)) / np.max(a)
+    say(f"    err/peak {err:.2e}")
+    assert err <= 1e-5
