@@ -211,7 +211,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
-      rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, total;
+      rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -253,6 +253,7 @@ Layout layout(const Analysis& a) {
   L.red = take(8 * 3 * kRedBlocks + 8 * kMaxLayers);
   L.red_out = take(8 * 8);
   L.flag = take(sizeof(int));
+  L.scal = take(8 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -283,6 +284,57 @@ sl1m_status apply_forward(sl1m_plan* p, const void* xp, const void* data, void* 
                           hipStream_t st, int nr = 1) {
   SL1M_HIP(timed(p, 0, st, [&] { return launch_forward(p, xp, nr, st); }), "forward kernel");
   SL1M_HIP(launch_forward_reduce(p, data, out, recs, nr, st), "forward reduce");
+  return SL1M_OK;
+}
+
+// One FISTA iteration (forward at y, residual, adjoint, update, t step); the
+// launch sequence is the same every iteration.
+sl1m_status enqueue_iteration(sl1m_plan* p, const void* vis, hipStream_t st) {
+  sl1m_status s = apply_forward(p, p->xperm, vis, p->res, true, st);
+  if (s) return s;
+  SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
+  SL1M_HIP(timed(p, 2, st, [&] { return launch_fista_update(p, st); }), "fista update");
+  return SL1M_OK;
+}
+
+void release_graph(sl1m_plan* p) {
+  if (p->iter_exec) (void)hipGraphExecDestroy(p->iter_exec);
+  if (p->iter_graph) (void)hipGraphDestroy(p->iter_graph);
+  p->iter_exec = nullptr;
+  p->iter_graph = nullptr;
+  p->iter_vis = nullptr;
+}
+
+// Captures one iteration into a graph (on a private stream: capture records
+// launches without running them) unless one for the same data pointer exists.
+sl1m_status ensure_graph(sl1m_plan* p, const void* vis) {
+  if (p->iter_exec && p->iter_vis == vis) return SL1M_OK;
+  release_graph(p);
+  hipStream_t cs = nullptr;
+  SL1M_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  sl1m_status s = SL1M_OK;
+  if (e == hipSuccess) {
+    s = enqueue_iteration(p, vis, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (s == SL1M_OK && e2 != hipSuccess) s = hip_error(e2, "end capture");
+    if (s == SL1M_OK) {
+      p->iter_graph = g;
+      const hipError_t e3 = hipGraphInstantiate(&p->iter_exec, g, nullptr, nullptr, 0);
+      if (e3 != hipSuccess) s = hip_error(e3, "instantiate graph");
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  } else {
+    s = hip_error(e, "begin capture");
+  }
+  (void)hipStreamDestroy(cs);
+  if (s != SL1M_OK) {
+    release_graph(p);
+    return s;
+  }
+  p->iter_vis = vis;
   return SL1M_OK;
 }
 
@@ -425,6 +477,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->red = reinterpret_cast<double*>(w + L.red);
     p->red_out = reinterpret_cast<double*>(w + L.red_out);
     p->flag = reinterpret_cast<int*>(w + L.flag);
+    p->scal = reinterpret_cast<double*>(w + L.scal);
 
     auto fail = [&](sl1m_status st_) {
       delete p;
@@ -490,7 +543,10 @@ static void timing_release(sl1m_plan* p) {
 }
 
 sl1m_status sl1m_plan_destroy(sl1m_plan* plan) {
-  if (plan) timing_release(plan);
+  if (plan) {
+    timing_release(plan);
+    release_graph(plan);
+  }
   delete plan;
   return SL1M_OK;
 }
@@ -626,24 +682,32 @@ sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* p
       if (!(L > 0.0)) return set_error(SL1M_EINVAL, "estimated L is not positive (M = 0?)");
     }
     info->L = L;
-    const double inv_L = 1.0 / L, thr = prm->lambda / L;
+    const double scal_h[3] = {1.0, 1.0 / L, prm->lambda / L};
+    SL1M_HIP(hipMemcpyAsync(p->scal, scal_h, sizeof(scal_h), hipMemcpyHostToDevice, st),
+             "solver scalars");
     SL1M_HIP(launch_fill(p->xperm, p->n_pix, p->real_bytes, st), "zero y");
     SL1M_HIP(launch_fill(p->img, p->n_pix, p->real_bytes, st), "zero I");
     SL1M_HIP(launch_fill(p->flag, 1, sizeof(int), st), "zero divergence flag");
-    double t = 1.0, F_prev = -1.0;
+    // a captured graph replays the iteration with one launch (not while the
+    // per-kernel timing facility is recording)
+    bool use_graph = !p->timing && prm->max_iter > 1;
+    if (use_graph && ensure_graph(p, vis) != SL1M_OK) {
+      use_graph = false;  // capture unavailable: launch the kernels directly
+      set_error(SL1M_OK, "");
+      (void)hipGetLastError();
+    }
+    double F_prev = -1.0;
     double h[3];
     int32_t k = 0;
     for (k = 1; k <= prm->max_iter; ++k) {
-      const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-      const double beta = (t - 1.0) / tn;
-      sl1m_status s = apply_forward(p, p->xperm, vis, p->res, true, st);
-      if (s) return s;
-      SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
-      SL1M_HIP(timed(p, 2, st, [&] { return launch_fista_update(p, inv_L, thr, beta, st); }),
-               "fista update");
-      t = tn;
+      if (use_graph) {
+        SL1M_HIP(hipGraphLaunch(p->iter_exec, st), "graph launch");
+      } else {
+        sl1m_status s = enqueue_iteration(p, vis, st);
+        if (s) return s;
+      }
       if (prm->eps > 0.0 && k % prm->check_every == 0) {
-        s = apply_forward(p, p->img, vis, p->res, false, st);
+        sl1m_status s = apply_forward(p, p->img, vis, p->res, false, st);
         if (s) return s;
         SL1M_HIP(launch_objective_terms(p, p->res, p->img, st), "objective");
         s = read_red(p, h, 3, st);

@@ -114,6 +114,12 @@ struct sl1m_plan {
   double* red = nullptr;            // reduction scratch [kRedSlots]
   double* red_out = nullptr;        // [8] final reduction results
   int* flag = nullptr;              // domain-check counter
+  double* scal = nullptr;           // FISTA scalars on the device: t_k, 1/L, lambda/L
+
+  // captured FISTA iteration (replayed with hipGraphLaunch)
+  hipGraph_t iter_graph = nullptr;
+  hipGraphExec_t iter_exec = nullptr;
+  const void* iter_vis = nullptr;   // data pointer the captured graph reads
 
   // kernel timing (sl1m_timing_begin/end)
   bool timing = false;
@@ -162,8 +168,8 @@ hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t 
 hipError_t launch_adjoint(sl1m_plan* p, int nr, hipStream_t st);
 hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g_out, bool unpermute, int nr,
                                  hipStream_t st);
-hipError_t launch_fista_update(sl1m_plan* p, double inv_L, double thr, double beta,
-                               hipStream_t st);
+// FISTA update from device scalars p->scal = {t_k, 1/L, lambda/L}, then t_k -> t_{k+1}.
+hipError_t launch_fista_update(sl1m_plan* p, hipStream_t st);
 hipError_t launch_fill(void* dst, size_t n_elems, size_t elem_bytes, hipStream_t st);
 hipError_t launch_splitmix_start(sl1m_plan* p, uint64_t seed, void* dst, hipStream_t st);
 hipError_t launch_scale(sl1m_plan* p, void* x, int64_t n, double a, hipStream_t st);

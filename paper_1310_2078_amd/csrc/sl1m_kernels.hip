@@ -159,15 +159,22 @@ __global__ void k_adj_reduce(const R* __restrict__ part, int n_rows, int64_t n_p
 
 // One FISTA step on permuted vectors (Section "Implementation of SL1M"):
 //   z = y - g / L;  I_k = T^{lambda/L}(z)  (eq. threshp);  y <- I_k + beta (I_k - I_{k-1})
-// with g = scale_j * sum_c part[c][j] and beta = (t_k - 1) / t_{k+1}.
+// with g = scale_j * sum_c part[c][j] and beta = (t_k - 1) / t_{k+1}.  The
+// scalars live on the device (scal[0] = t_k, scal[1] = 1/L, scal[2] = lambda/L)
+// so the iteration's launches are identical every time and can be replayed
+// from a captured graph; k_tstep advances t afterwards.
 // A non-finite z (overflow of a diverging iteration) would be mapped to 0 by
 // the threshold; it is recorded in *flag instead so the solve can report it.
 template <typename R>
 __global__ void k_fista(const R* __restrict__ part, int n_rows, int64_t n_pix,
                         const R* __restrict__ scale, R* __restrict__ y, R* __restrict__ img,
-                        R inv_L, R thr, R beta, int* __restrict__ flag) {
+                        const double* __restrict__ scal, int* __restrict__ flag) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n_pix) return;
+  const double t = scal[0];
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  const R beta = static_cast<R>((t - 1.0) / tn);
+  const R inv_L = static_cast<R>(scal[1]), thr = static_cast<R>(scal[2]);
   R g = R(0);
   for (int c = 0; c < n_rows; ++c) g += part[static_cast<int64_t>(c) * n_pix + j];
   g *= scale[j];
@@ -177,6 +184,11 @@ __global__ void k_fista(const R* __restrict__ part, int n_rows, int64_t n_pix,
   const R io = img[j];
   y[j] = in + beta * (in - io);
   img[j] = in;
+}
+
+// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+__global__ void k_tstep(double* __restrict__ scal) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) scal[0] = 0.5 * (1.0 + sqrt(1.0 + 4.0 * scal[0] * scal[0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -660,18 +672,17 @@ hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g, bool unpermute, int nr, 
 }
 
 template <typename R>
-static hipError_t fista_t(sl1m_plan* p, double inv_L, double thr, double beta, hipStream_t st) {
-  if (p->n_pix == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_fista<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
-                     static_cast<const R*>(p->apart), p->n_achunks, p->n_pix,
-                     static_cast<const R*>(p->pscale), static_cast<R*>(p->xperm),
-                     static_cast<R*>(p->img), static_cast<R>(inv_L), static_cast<R>(thr),
-                     static_cast<R>(beta), p->flag);
+static hipError_t fista_t(sl1m_plan* p, hipStream_t st) {
+  if (p->n_pix > 0)
+    hipLaunchKernelGGL((k_fista<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+                       static_cast<const R*>(p->apart), p->n_achunks, p->n_pix,
+                       static_cast<const R*>(p->pscale), static_cast<R*>(p->xperm),
+                       static_cast<R*>(p->img), p->scal, p->flag);
+  hipLaunchKernelGGL(k_tstep, dim3(1), dim3(64), 0, st, p->scal);
   return hipGetLastError();
 }
-hipError_t launch_fista_update(sl1m_plan* p, double inv_L, double thr, double beta,
-                               hipStream_t st) {
-  return SL1M_DISPATCH_R(p, fista_t, p, inv_L, thr, beta, st);
+hipError_t launch_fista_update(sl1m_plan* p, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, fista_t, p, st);
 }
 
 hipError_t launch_fill(void* dst, size_t n_elems, size_t elem_bytes, hipStream_t st) {

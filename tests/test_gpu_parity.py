@@ -331,3 +331,21 @@ def test_config4_full_size_sampled():
     ident = abs(lhs - rhs) / (np.linalg.norm(Vg) * np.linalg.norm(r))
     say(f"    sampled forward {ef:.3e} adjoint {ea:.3e} identity {ident:.3e}")
     assert ef <= 1e-5 and ea <= 1e-5 and ident <= 1e-5
+
+
+def test_graph_replayed_iteration_equals_direct_launches():
+    """The solve replays a captured graph of one iteration; with kernel timing
+    on it launches the kernels directly. Both give the same image bitwise,
+    also across repeated replays with host work in between."""
+    say("[case] graph vs direct")
+    wl, op, V, L = _config1_data()
+    plan = sl1m.Plan.from_workload(wl)
+    a, ia = plan.solve(V, wl.lam, 60, L=L)
+    a = a.cpu().numpy().copy()
+    b, ib = plan.solve(V, wl.lam, 60, L=L)
+    assert np.array_equal(b.cpu().numpy(), a)
+    plan.timing_begin(256)
+    c, ic = plan.solve(V, wl.lam, 60, L=L)
+    plan.timing_end()
+    assert np.array_equal(c.cpu().numpy(), a)
+    assert ia["F"] == ib["F"] == ic["F"]
