@@ -55,6 +55,53 @@ def load_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
+CALIB_BYTES = 256 << 20
+
+
+def _counter_rows(path):
+    """(kernel name, counter value in bytes) per dispatch from a rocprofv3
+    counter_collection CSV (one row per dispatch and counter)."""
+    import csv
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            name = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("kernel_name") or ""
+            val = r.get("Counter_Value") or r.get("Counter-Value") or r.get("counter_value")
+            if val is None:
+                continue
+            rows.append((name, float(val) * 1024.0))   # FETCH_SIZE / WRITE_SIZE are in KiB
+    return rows
+
+
+def ingest_counters(fetch_csv, write_csv):
+    """Per-launch HBM bytes of the operator kernels, scaled by what the same
+    counters read for the calibration copy of CALIB_BYTES (read once, written
+    once)."""
+    out = {}
+    for counter, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _counter_rows(path)
+        copy = [v for n, v in rows if "copy" in n.lower() or "elementwise" in n.lower()]
+        big = [v for v in copy if v > 0.5 * CALIB_BYTES]
+        if not big:
+            raise SystemExit(f"no calibration copy found in {path}")
+        scale = CALIB_BYTES / (sum(big) / len(big))
+        for key, pat in (("k_fwd_delta<float,4>", "k_fwd_delta<float, 4, false, 1>"),
+                         ("k_adj_delta<float,4>", "k_adj_delta<float, 4, false, 1>")):
+            vals = [v for n, v in rows if pat in n]
+            if vals:
+                rec = out.setdefault(key, {"source_hash": kernel_source_hash()})
+                rec[counter + "_bytes_per_launch"] = scale * sum(vals) / len(vals)
+                rec[counter + "_scale"] = scale
+                rec["launches"] = len(vals)
+    for rec in out.values():
+        rec["bytes_per_launch"] = rec.get("fetch_bytes_per_launch", 0.0) + \
+            rec.get("write_bytes_per_launch", 0.0)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def cpu_baseline(wl, threads: int):
     """The FP64 oracle, untuned, on a bounded sample of the workload: the
     forward for the first 512*threads visibilities (all pixels) and the adjoint
@@ -165,10 +212,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary workloads (config 4, multi-RHS, FP64 config 1)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM counters)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--calib-copy run into profiles/traffic.json and exit")
     ap.add_argument("--profile-ops", type=int, default=0,
                     help="after the timed region, run this many extra forward+adjoint pairs "
                          "(for profiler runs)")
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the multi-GPU pixel sharding is a design, not built)", file=sys.stderr)
@@ -212,6 +267,11 @@ def main():
 
     for _ in range(args.profile_ops):
         plan.adjoint(plan.forward(img))
+    if args.calib_copy:
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)   # an elementwise kernel: reads and writes CALIB_BYTES
     torch.cuda.synchronize()
 
     fwd_n, fwd_ms = tim["forward"]

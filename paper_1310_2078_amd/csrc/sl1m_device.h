@@ -63,6 +63,32 @@ __device__ __forceinline__ constexpr double taper_scale() {
   return 1.4426950408889634;  // log2(e): exp(x) = 2^(x log2 e)
 }
 
+// Read-only view of memory that no thread writes while a kernel runs (pixel
+// records, amplitudes, visibility records, residuals).  Loads through the
+// constant address space with a wavefront-uniform address become scalar loads
+// into SGPRs, also when the pointer itself was loaded from memory (as in the
+// batched serving kernels, where the compiler cannot otherwise prove the data
+// unwritten).  Reads only.
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ ConstPtr<T> as_const(const T* p) {
+  return (ConstPtr<T>)(p);
+}
+
+// Chunk descriptor i of a table, read through the scalar unit.
+__device__ __forceinline__ Chunk load_chunk(const Chunk* table, int64_t i) {
+  const ConstPtr<Chunk> c = as_const(table) + i;
+  Chunk r;
+  r.j0 = c->j0;
+  r.j1 = c->j1;
+  r.sigma = c->sigma;
+  r.seg = c->seg;
+  r.layer = c->layer;
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // operator tiles
 // ---------------------------------------------------------------------------
@@ -77,6 +103,8 @@ __device__ __forceinline__ void fwd_delta_tile(
     const R* __restrict__ vbeta, const Chunk& ch, int64_t vtile, int64_t n_vis,
     C2<R>* __restrict__ out_row, int64_t row_stride, R xscale) {
   const int64_t kbase = vtile * (kBlock * VPL) + threadIdx.x;
+  const ConstPtr<PixRec<R>> cpix = as_const(pix);
+  const ConstPtr<R> cxp = as_const(xp);
   double u[VPL], v[VPL], w[VPL];
   R beta[VPL], ore[NR][VPL], oim[NR][VPL];
 #pragma unroll
@@ -100,11 +128,11 @@ __device__ __forceinline__ void fwd_delta_tile(
 #pragma unroll
       for (int i = 0; i < VPL; ++i) re[r][i] = im[r][i] = R(0);
     for (int j = j0; j < j1; ++j) {
-      const double pl = pix[j].l, pm = pix[j].m, pn = pix[j].c3;
+      const double pl = cpix[j].l, pm = cpix[j].m, pn = cpix[j].c3;
       R a[NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) a[r] = pix[j].scale * xscale * xp[r * n_pix + j];
-      const R r2 = BEAM ? pix[j].r2r : R(0);
+      for (int r = 0; r < NR; ++r) a[r] = cpix[j].scale * xscale * cxp[r * n_pix + j];
+      const R r2 = BEAM ? cpix[j].r2r : R(0);
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
         const double t = fma(w[i], pn, fma(v[i], pm, fma(u[i], pl, origin)));
@@ -156,6 +184,8 @@ __device__ __forceinline__ void fwd_gauss_tile(
     const R* __restrict__ vbeta, const Chunk& ch, int64_t vtile, int64_t n_vis,
     C2<R>* __restrict__ out_row, int64_t row_stride, R xscale) {
   const int64_t kbase = vtile * (kBlock * VPL) + threadIdx.x;
+  const ConstPtr<PixRec<R>> cpix = as_const(pix);
+  const ConstPtr<R> cxp = as_const(xp);
   const double sig2 = ch.sigma * ch.sigma;
   double A[VPL], B[VPL], C[VPL], NW[VPL], E0[VPL];
   R ur[VPL], vr[VPL], wr[VPL], c1[VPL], Dd[VPL], Ds[VPL], beta[VPL];
@@ -191,12 +221,12 @@ __device__ __forceinline__ void fwd_gauss_tile(
 #pragma unroll
       for (int i = 0; i < VPL; ++i) re[r][i] = im[r][i] = R(0);
     for (int j = j0; j < j1; ++j) {
-      const double pl = pix[j].l, pm = pix[j].m, pr2 = pix[j].c3, pk = pix[j].c4;
-      const R lr = pix[j].lr, mr = pix[j].mr;
+      const double pl = cpix[j].l, pm = cpix[j].m, pr2 = cpix[j].c3, pk = cpix[j].c4;
+      const R lr = cpix[j].lr, mr = cpix[j].mr;
       R a[NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) a[r] = pix[j].scale * xscale * xp[r * n_pix + j];
-      const R r2 = BEAM ? pix[j].r2r : R(0);
+      for (int r = 0; r < NR; ++r) a[r] = cpix[j].scale * xscale * cxp[r * n_pix + j];
+      const R r2 = BEAM ? cpix[j].r2r : R(0);
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
         const double t = fma(A[i], pl, fma(B[i], pm, fma(C[i], pr2, fma(NW[i], pk, E0[i]))));
@@ -249,6 +279,9 @@ __device__ __forceinline__ void adj_delta_tile(
     const double* __restrict__ pc3, const R* __restrict__ pr2, const Chunk& tl, int sub_i,
     int64_t kc, int64_t kchunk, int64_t n_vis, R* __restrict__ out_row, int64_t row_stride) {
   const int64_t jbase = tl.j0 + static_cast<int64_t>(sub_i) * (kBlock * PPL) + threadIdx.x;
+  const ConstPtr<VisRecD<R>> cvrec = as_const(vrec);
+  const ConstPtr<R> cres = as_const(reinterpret_cast<const R*>(rres));
+  const ConstPtr<R> cbeta = as_const(vbeta);
   const int k0 = static_cast<int>(kc * kchunk);
   const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
   double l[PPL], m[PPL], c3[PPL];
@@ -273,15 +306,14 @@ __device__ __forceinline__ void adj_delta_tile(
 #pragma unroll
       for (int i = 0; i < PPL; ++i) g[r][i] = R(0);
     for (int k = kk; k < ke; ++k) {
-      const double u = vrec[k].u, v = vrec[k].v, w = vrec[k].w;
+      const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
       R rre[NR], rim[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const C2<R> q = rres[static_cast<int64_t>(k) * NR + r];
-        rre[r] = q.x;
-        rim[r] = q.y;
+        rre[r] = cres[(static_cast<int64_t>(k) * NR + r) * 2];
+        rim[r] = cres[(static_cast<int64_t>(k) * NR + r) * 2 + 1];
       }
-      const R bt = BEAM ? vbeta[k] : R(0);
+      const R bt = BEAM ? cbeta[k] : R(0);
 #pragma unroll
       for (int i = 0; i < PPL; ++i) {
         const double t = fma(c3[i], w, fma(m[i], v, fma(l[i], u, origin)));
@@ -324,8 +356,10 @@ __device__ __forceinline__ void adj_gauss_tile(
     const Chunk& tl, int sub_i, int64_t kc, int64_t kchunk, int64_t n_vis,
     R* __restrict__ out_row, int64_t row_stride) {
   const int64_t jbase = tl.j0 + static_cast<int64_t>(sub_i) * (kBlock * PPL) + threadIdx.x;
-  const VisRecG<R>* rec = vrec + static_cast<int64_t>(tl.layer) * n_vis;
-  const C2<R>* res = rres + static_cast<int64_t>(1 + tl.layer) * n_vis * NR;
+  const ConstPtr<VisRecG<R>> crec = as_const(vrec + static_cast<int64_t>(tl.layer) * n_vis);
+  const ConstPtr<R> cres =
+      as_const(reinterpret_cast<const R*>(rres + static_cast<int64_t>(1 + tl.layer) * n_vis * NR));
+  const ConstPtr<R> cbeta = as_const(vbeta);
   const int k0 = static_cast<int>(kc * kchunk);
   const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
   double l[PPL], m[PPL], c3[PPL], c4[PPL];
@@ -352,16 +386,15 @@ __device__ __forceinline__ void adj_gauss_tile(
 #pragma unroll
       for (int i = 0; i < PPL; ++i) g[r][i] = R(0);
     for (int k = kk; k < ke; ++k) {
-      const double A = rec[k].A, B = rec[k].B, C = rec[k].C, NW = rec[k].NW, E0 = rec[k].E0;
-      const R ur = rec[k].ur, vr = rec[k].vr, wr = rec[k].wr, c1 = rec[k].c1;
+      const double A = crec[k].A, B = crec[k].B, C = crec[k].C, NW = crec[k].NW, E0 = crec[k].E0;
+      const R ur = crec[k].ur, vr = crec[k].vr, wr = crec[k].wr, c1 = crec[k].c1;
       R rre[NR], rim[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const C2<R> q = res[static_cast<int64_t>(k) * NR + r];
-        rre[r] = q.x;
-        rim[r] = q.y;
+        rre[r] = cres[(static_cast<int64_t>(k) * NR + r) * 2];
+        rim[r] = cres[(static_cast<int64_t>(k) * NR + r) * 2 + 1];
       }
-      const R bt = BEAM ? vbeta[k] : R(0);
+      const R bt = BEAM ? cbeta[k] : R(0);
 #pragma unroll
       for (int i = 0; i < PPL; ++i) {
         const double t = fma(A, l[i], fma(B, m[i], fma(C, c3[i], fma(NW, c4[i], E0))));

@@ -31,6 +31,11 @@ using sched::Segment;
 constexpr int kSrvMaxSlots = 64;
 constexpr int kSrvRing = 4;              // rounds in flight (table buffers)
 constexpr int kSrvTileBlocks = 8192;     // per-request operator split target (work-item count)
+// item tables per round: 4 operator kinds x 4 tile variants, then reduce,
+// update, final
+constexpr int kOpVariants = 4;
+constexpr int kTabReduce = 4 * kOpVariants, kTabUpdate = kTabReduce + 1,
+              kTabFinal = kTabReduce + 2, kTabs = kTabReduce + 3;
 
 struct SegDev {
   int32_t slot, flags;
@@ -92,37 +97,32 @@ __device__ __forceinline__ double srv_block_sum(double v, double* sh) {
   return r;
 }
 
-template <bool GAUSS>
+// Work-item variants of the operator kernels (one instantiation each, so a
+// kernel's register allocation is that of its own tile shape):
+//   0: 1 visibility/pixel per lane, 1: 2, 2: 4, 3: 4 with per-pair beams.
+template <bool GAUSS, int VPL, bool BEAM>
 __global__ __launch_bounds__(kBlock) void k_srv_fwd(const TabDev* __restrict__ tab,
                                                     const ReqDev* __restrict__ reqs) {
-  const int64_t total = tab->total;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-    const SegDev sg = tab->seg[find_seg(tab, w)];
-    const ReqDev& q = reqs[sg.slot];
-    const int64_t item = sg.begin + (w - sg.prefix);
-    const int64_t c = (GAUSS ? q.n_fd : 0) + item / q.vtiles;
-    const int64_t vt = item % q.vtiles;
-    const Chunk ch = q.fchunks[c];
-    const float* xp = (sg.flags & sched::F_POWER) ? q.x
-                      : (sg.flags & sched::F_OBJECTIVE) ? q.img
-                                                        : q.y;
-    const float xs = (sg.flags & sched::F_POWER) ? static_cast<float>(q.xscale) : 1.0f;
-    float2* row = q.fpart + c * q.n_vis;
-#define SL1M_SRV_FWD(VPL, BEAM)                                                                   \
-  (GAUSS ? fwd_gauss_tile<float, VPL, BEAM, 1>(q.pix, xp, q.n_pix, q.vu, q.vv, q.vw, q.vbeta, ch, \
-                                               vt, q.n_vis, row, 0, xs)                           \
-         : fwd_delta_tile<float, VPL, BEAM, 1>(q.pix, xp, q.n_pix, q.vu, q.vv, q.vw, q.vbeta, ch, \
-                                               vt, q.n_vis, row, 0, xs))
-    if (q.beam_pair)
-      SL1M_SRV_FWD(4, true);
-    else if (q.vpl == 4)
-      SL1M_SRV_FWD(4, false);
-    else if (q.vpl == 2)
-      SL1M_SRV_FWD(2, false);
-    else
-      SL1M_SRV_FWD(1, false);
-#undef SL1M_SRV_FWD
-  }
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  // item counts stay far below 2^31: decode with 32-bit division; the results
+  // are wavefront-uniform and are moved to scalar registers so that the chunk
+  // and everything indexed by it are read through the scalar unit
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nvt = static_cast<uint32_t>(q.vtiles);
+  const int64_t c = __builtin_amdgcn_readfirstlane(static_cast<int>((GAUSS ? q.n_fd : 0) + item / nvt));
+  const int64_t vt = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nvt));
+  const Chunk ch = load_chunk(q.fchunks, c);
+  const float* xp = (sg.flags & sched::F_POWER) ? q.x : (sg.flags & sched::F_OBJECTIVE) ? q.img : q.y;
+  const float xs = (sg.flags & sched::F_POWER) ? static_cast<float>(q.xscale) : 1.0f;
+  float2* row = q.fpart + c * q.n_vis;
+  if (GAUSS)
+    fwd_gauss_tile<float, VPL, BEAM, 1>(q.pix, xp, q.n_pix, q.vu, q.vv, q.vw, q.vbeta, ch, vt,
+                                        q.n_vis, row, 0, xs);
+  else
+    fwd_delta_tile<float, VPL, BEAM, 1>(q.pix, xp, q.n_pix, q.vu, q.vv, q.vw, q.vbeta, ch, vt,
+                                        q.n_vis, row, 0, xs);
 }
 
 // Sum of forward partial rows, gain, residual; adjoint residual records, or
@@ -130,8 +130,8 @@ __global__ __launch_bounds__(kBlock) void k_srv_fwd(const TabDev* __restrict__ t
 __global__ __launch_bounds__(kBlock) void k_srv_reduce(const TabDev* __restrict__ tab,
                                                        ReqDev* __restrict__ reqs) {
   __shared__ double sh[kBlock];
-  const int64_t total = tab->total;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  {
+    const int64_t w = blockIdx.x;
     const SegDev sg = tab->seg[find_seg(tab, w)];
     ReqDev& q = reqs[sg.slot];
     const int64_t blk = sg.begin + (w - sg.prefix);
@@ -166,33 +166,24 @@ __global__ __launch_bounds__(kBlock) void k_srv_reduce(const TabDev* __restrict_
   }
 }
 
-template <bool GAUSS>
+template <bool GAUSS, int PPL, bool BEAM>
 __global__ __launch_bounds__(kBlock) void k_srv_adj(const TabDev* __restrict__ tab,
                                                     const ReqDev* __restrict__ reqs) {
-  const int64_t total = tab->total;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-    const SegDev sg = tab->seg[find_seg(tab, w)];
-    const ReqDev& q = reqs[sg.slot];
-    const int64_t item = sg.begin + (w - sg.prefix);
-    const int64_t kc = item % q.n_achunks;
-    const int64_t tile = (GAUSS ? q.n_pd : 0) + item / q.n_achunks;
-    const Chunk tl = q.ptiles[tile];
-    float* row = q.apart + kc * q.n_pix;
-#define SL1M_SRV_ADJ(PPL, BEAM)                                                                     \
-  (GAUSS ? adj_gauss_tile<float, PPL, BEAM, 1>(q.visrecG, q.rres, q.vbeta, q.pl, q.pm, q.pc3,       \
-                                               q.pc4, q.pr2, tl, 0, kc, q.kchunk, q.n_vis, row, 0) \
-         : adj_delta_tile<float, PPL, BEAM, 1>(q.visrecD, q.rres, q.vbeta, q.pl, q.pm, q.pc3,       \
-                                               q.pr2, tl, 0, kc, q.kchunk, q.n_vis, row, 0))
-    if (q.beam_pair)
-      SL1M_SRV_ADJ(4, true);
-    else if (q.ppl == 4)
-      SL1M_SRV_ADJ(4, false);
-    else if (q.ppl == 2)
-      SL1M_SRV_ADJ(2, false);
-    else
-      SL1M_SRV_ADJ(1, false);
-#undef SL1M_SRV_ADJ
-  }
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
+  const int64_t tile = __builtin_amdgcn_readfirstlane(static_cast<int>((GAUSS ? q.n_pd : 0) + item / nac));
+  const Chunk tl = load_chunk(q.ptiles, tile);
+  float* row = q.apart + kc * q.n_pix;
+  if (GAUSS)
+    adj_gauss_tile<float, PPL, BEAM, 1>(q.visrecG, q.rres, q.vbeta, q.pl, q.pm, q.pc3, q.pc4,
+                                        q.pr2, tl, 0, kc, q.kchunk, q.n_vis, row, 0);
+  else
+    adj_delta_tile<float, PPL, BEAM, 1>(q.visrecD, q.rres, q.vbeta, q.pl, q.pm, q.pc3, q.pr2, tl,
+                                        0, kc, q.kchunk, q.n_vis, row, 0);
 }
 
 // Per pixel block: FISTA step (threshold + momentum), power-iteration update
@@ -201,8 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_srv_adj(const TabDev* __restrict__ t
 __global__ __launch_bounds__(kBlock) void k_srv_update(const TabDev* __restrict__ tab,
                                                        ReqDev* __restrict__ reqs) {
   __shared__ double sh[kBlock];
-  const int64_t total = tab->total;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  {
+    const int64_t w = blockIdx.x;
     const SegDev sg = tab->seg[find_seg(tab, w)];
     ReqDev& q = reqs[sg.slot];
     const int64_t blk = sg.begin + (w - sg.prefix);
@@ -253,13 +244,13 @@ __global__ __launch_bounds__(kBlock) void k_srv_update(const TabDev* __restrict_
 __global__ __launch_bounds__(kBlock) void k_srv_final(const TabDev* __restrict__ tab,
                                                       ReqDev* __restrict__ reqs) {
   __shared__ double sh[kBlock];
-  const int64_t total = tab->total;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  {
+    const int64_t w = blockIdx.x;
     const SegDev sg = tab->seg[find_seg(tab, w)];
     ReqDev& q = reqs[sg.slot];
     if (sg.flags & sched::F_FISTA) {
       if (threadIdx.x == 0) q.t = 0.5 * (1.0 + sqrt(1.0 + 4.0 * q.t * q.t));
-      continue;
+      return;
     }
     double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t i = threadIdx.x; i < q.pix_blocks; i += blockDim.x) {
@@ -318,14 +309,15 @@ struct sl1m_server {
   size_t arena_bytes = 0;
   sl1m::sched::Arena alloc;
   int max_slots = 0;
-  int grid = 1 << 24;                  // one block per work item (hardware balances the load)
   double budget = 3e10;                // evals per round, shared by the active requests
   hipStream_t stream = nullptr;        // rounds (non-blocking, default priority)
   hipStream_t admit_stream = nullptr;  // plan creation of admitted requests
   hipEvent_t admit_event = nullptr;
   sl1m::ReqDev* d_reqs = nullptr;
-  sl1m::TabDev* d_tabs = nullptr;      // [kSrvRing][K_COUNT]
+  sl1m::TabDev* d_tabs = nullptr;      // [kSrvRing][kTabs]
   sl1m::TabDev* h_tabs = nullptr;      // pinned mirror
+  int8_t fwd_variant[sl1m::kSrvMaxSlots] = {};  // tile variant of each slot's request
+  int8_t adj_variant[sl1m::kSrvMaxSlots] = {};
   hipEvent_t ring_event[sl1m::kSrvRing] = {};
   int64_t ring_round[sl1m::kSrvRing] = {-1, -1, -1, -1};
   std::vector<int> free_slots;
@@ -501,6 +493,9 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   q.inv_L = power ? 0.0 : 1.0 / t.params.L;
   q.thr = power ? 0.0 : t.params.lambda / t.params.L;
   q.xscale = xscale;
+  auto variant = [&](int per_lane) { return plan->beam_pair ? 3 : (per_lane == 4 ? 2 : per_lane == 2 ? 1 : 0); };
+  s->fwd_variant[t.req.slot] = static_cast<int8_t>(variant(q.vpl));
+  s->adj_variant[t.req.slot] = static_cast<int8_t>(variant(q.ppl));
   SRV_HIP(hipMemcpyAsync(s->d_reqs + t.req.slot, &q, sizeof(ReqDev), hipMemcpyHostToDevice, st),
           "upload request descriptor");
   SRV_HIP(hipStreamSynchronize(st), "admission sync");
@@ -538,36 +533,63 @@ sl1m_status launch_round(sl1m_server* s) {
   const double share = std::max(s->budget / static_cast<double>(act.size()), s->budget / 32.0);
   sched::RoundPlan rp;
   sched::plan_round(act, share, s->round, rp);
-  TabDev* ht = s->h_tabs + ring * sched::K_COUNT;
-  for (int k = 0; k < sched::K_COUNT; ++k) {
+  // split the planner's segments into per-(kernel, variant) tables
+  std::vector<Segment> tabs[kTabs];
+  auto route = [&](int kind, int base, const int8_t* var) {
+    for (const Segment& g : rp.seg[kind]) tabs[base + var[g.slot]].push_back(g);
+  };
+  route(sched::K_FWD_DELTA, 0 * kOpVariants, s->fwd_variant);
+  route(sched::K_FWD_GAUSS, 1 * kOpVariants, s->fwd_variant);
+  route(sched::K_ADJ_DELTA, 2 * kOpVariants, s->adj_variant);
+  route(sched::K_ADJ_GAUSS, 3 * kOpVariants, s->adj_variant);
+  tabs[kTabReduce] = rp.seg[sched::K_REDUCE];
+  tabs[kTabUpdate] = rp.seg[sched::K_UPDATE];
+  tabs[kTabFinal] = rp.seg[sched::K_FINAL];
+  TabDev* ht = s->h_tabs + ring * kTabs;
+  for (int k = 0; k < kTabs; ++k) {
     TabDev& tb = ht[k];
-    tb.n_seg = static_cast<int32_t>(rp.seg[k].size());
+    tb.n_seg = static_cast<int32_t>(tabs[k].size());
     int64_t pre = 0;
     for (int i = 0; i < tb.n_seg; ++i) {
-      const Segment& g = rp.seg[k][i];
+      const Segment& g = tabs[k][i];
       tb.seg[i] = SegDev{g.slot, g.flags, g.begin, g.end, pre};
       pre += g.end - g.begin;
     }
     tb.total = pre;
   }
-  TabDev* dt = s->d_tabs + ring * sched::K_COUNT;
-  SRV_HIP(hipMemcpyAsync(dt, ht, sizeof(TabDev) * sched::K_COUNT, hipMemcpyHostToDevice, s->stream),
+  TabDev* dt = s->d_tabs + ring * kTabs;
+  SRV_HIP(hipMemcpyAsync(dt, ht, sizeof(TabDev) * kTabs, hipMemcpyHostToDevice, s->stream),
           "upload round tables");
   auto go = [&](int k, auto kernel, auto* reqs) -> hipError_t {
     if (ht[k].total == 0) return hipSuccess;
-    const unsigned g = static_cast<unsigned>(std::min<int64_t>(s->grid, ht[k].total));
+    const unsigned g = static_cast<unsigned>(ht[k].total);  // one block per item
     hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, s->stream, dt + k, reqs);
     return hipGetLastError();
   };
   const ReqDev* cr = s->d_reqs;
   ReqDev* r = s->d_reqs;
-  SRV_HIP(go(sched::K_FWD_DELTA, k_srv_fwd<false>, cr), "batched forward (delta)");
-  SRV_HIP(go(sched::K_FWD_GAUSS, k_srv_fwd<true>, cr), "batched forward (Gaussian)");
-  SRV_HIP(go(sched::K_REDUCE, k_srv_reduce, r), "batched reduce");
-  SRV_HIP(go(sched::K_ADJ_DELTA, k_srv_adj<false>, cr), "batched adjoint (delta)");
-  SRV_HIP(go(sched::K_ADJ_GAUSS, k_srv_adj<true>, cr), "batched adjoint (Gaussian)");
-  SRV_HIP(go(sched::K_UPDATE, k_srv_update, r), "batched update");
-  SRV_HIP(go(sched::K_FINAL, k_srv_final, r), "batched final");
+  hipError_t e = hipSuccess;
+  // kernel order within a round: forward, reduce, adjoint, update, final
+  if (e == hipSuccess) e = go(0, k_srv_fwd<false, 1, false>, cr);
+  if (e == hipSuccess) e = go(1, k_srv_fwd<false, 2, false>, cr);
+  if (e == hipSuccess) e = go(2, k_srv_fwd<false, 4, false>, cr);
+  if (e == hipSuccess) e = go(3, k_srv_fwd<false, 4, true>, cr);
+  if (e == hipSuccess) e = go(4, k_srv_fwd<true, 1, false>, cr);
+  if (e == hipSuccess) e = go(5, k_srv_fwd<true, 2, false>, cr);
+  if (e == hipSuccess) e = go(6, k_srv_fwd<true, 4, false>, cr);
+  if (e == hipSuccess) e = go(7, k_srv_fwd<true, 4, true>, cr);
+  if (e == hipSuccess) e = go(kTabReduce, k_srv_reduce, r);
+  if (e == hipSuccess) e = go(8, k_srv_adj<false, 1, false>, cr);
+  if (e == hipSuccess) e = go(9, k_srv_adj<false, 2, false>, cr);
+  if (e == hipSuccess) e = go(10, k_srv_adj<false, 4, false>, cr);
+  if (e == hipSuccess) e = go(11, k_srv_adj<false, 4, true>, cr);
+  if (e == hipSuccess) e = go(12, k_srv_adj<true, 1, false>, cr);
+  if (e == hipSuccess) e = go(13, k_srv_adj<true, 2, false>, cr);
+  if (e == hipSuccess) e = go(14, k_srv_adj<true, 4, false>, cr);
+  if (e == hipSuccess) e = go(15, k_srv_adj<true, 4, true>, cr);
+  if (e == hipSuccess) e = go(kTabUpdate, k_srv_update, r);
+  if (e == hipSuccess) e = go(kTabFinal, k_srv_final, r);
+  if (e != hipSuccess) return hip_error(e, "batched round launch");
   SRV_HIP(hipEventRecord(s->ring_event[ring], s->stream), "record round event");
   s->ring_round[ring] = s->round;
   if (!rp.finishing.empty()) s->finishing.emplace_back(s->round, rp.finishing);
@@ -593,7 +615,7 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
     if (max_slots < 1 || max_slots > kSrvMaxSlots)
       return set_error(SL1M_EINVAL, "max_slots must be in [1, 64]");
     const size_t hdr = sched::Arena::round_up(sizeof(ReqDev) * kSrvMaxSlots) +
-                       sched::Arena::round_up(sizeof(TabDev) * kSrvRing * sched::K_COUNT);
+                       sched::Arena::round_up(sizeof(TabDev) * kSrvRing * kTabs);
     if (arena_bytes < hdr + (1u << 20)) return set_error(SL1M_ENOMEM, "arena too small");
     auto s = std::make_unique<sl1m_server>();
     s->t0 = std::chrono::steady_clock::now();
@@ -607,7 +629,7 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
     s->budget = round_budget_evals > 0 ? round_budget_evals : 3e10;
     for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     SRV_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->h_tabs),
-                          sizeof(TabDev) * kSrvRing * sched::K_COUNT, hipHostMallocDefault),
+                          sizeof(TabDev) * kSrvRing * kTabs, hipHostMallocDefault),
             "pinned round tables");
     SRV_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "round stream");
     SRV_HIP(hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking), "admission stream");
