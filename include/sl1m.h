@@ -64,6 +64,28 @@ typedef enum {
 } sl1m_precision;
 
 /*
+ * Evaluation order of the delta-pixel part of the operators.  The element of
+ * eq. (deltam) factorises exactly:
+ *     exp(-2 pi i (u l + v m + w (n - 1)))
+ *       = exp(-2 pi i u l) * exp(-2 pi i v m) * exp(-2 pi i w (n - 1)),
+ * and n - 1 depends on l^2 + m^2 only.  When the delta pixels lie on a product
+ * set symmetric under l -> -l and m -> -m (a centred image grid, or any
+ * subset of one), the four pixels (+-|l|, +-|m|) share the last factor, the
+ * first two come from per-|l| and per-|m| phasors, and one sincos serves four
+ * matrix entries.  The "grid" evaluation uses that; the "direct" evaluation
+ * forms every entry's phase on its own.  Both compute the same operator; they
+ * differ by float32 rounding only.  Applies to float32 plans and single
+ * right-hand-side calls; float64 plans, multi-RHS calls, Gaussian pixels and
+ * per-pair beams always use the direct evaluation.
+ */
+typedef enum {
+  SL1M_GRID_AUTO = 0,    /* grid evaluation when the delta pixels qualify        */
+  SL1M_GRID_OFF = 1,     /* direct evaluation always                             */
+  SL1M_GRID_REQUIRE = 2  /* grid evaluation; SL1M_EINVAL if the pixels do not
+                            qualify (for tests and benchmarks)                   */
+} sl1m_grid_mode;
+
+/*
  * One deconvolution problem.  All arrays are device pointers.
  *  l, m      [n_pix] float64  direction cosines of the pixel centres; the
  *                             paper allows arbitrary (off-grid) positions
@@ -88,6 +110,13 @@ typedef enum {
  *  tile_blocks  number of thread blocks the split of one operator application
  *            aims at (more blocks: more parallelism, larger partial-sum
  *            buffers); 0 means 4096, enough to fill the 256 compute units.
+ *  grid_mode sl1m_grid_mode.  The delta pixels qualify for the grid
+ *            evaluation when (a) the plan is float32 without per-pair beams,
+ *            (b) no two delta pixels share a position, (c) there are at least
+ *            16 distinct |l| values and at least 1024 delta pixels, and
+ *            (d) the product set of distinct |l| and |m| values (padded to a
+ *            multiple of 8 |m| values), times four signs, holds at most 2.5
+ *            times as many positions as there are delta pixels.
  */
 typedef struct {
   int64_t n_pix;
@@ -107,7 +136,7 @@ typedef struct {
   int32_t precision;
   int32_t max_rhs;      /* right-hand sides per operator call: 0 or 1, 2, 4, 8 */
   int32_t tile_blocks;  /* blocks one operator launch aims at; 0 = 4096       */
-  int32_t reserved;
+  int32_t grid_mode;    /* sl1m_grid_mode                                     */
 } sl1m_problem;
 
 typedef struct sl1m_plan sl1m_plan;
@@ -115,7 +144,9 @@ typedef struct sl1m_plan sl1m_plan;
 /* Bytes of device workspace that sl1m_plan_create() needs for `problem`.
  * Reads sigma, kind, ant_p, ant_q and ant_fwhm with blocking device-to-host
  * copies when they are given (the grouping of pixels and the gain mode set the
- * layout); the other arrays are not read.  At most 16 distinct (kind, sigma)
+ * layout), and l and m of the delta pixels unless grid_mode is SL1M_GRID_OFF
+ * or the plan is float64 (the grid evaluation's tables depend on them); the
+ * other arrays are not read.  At most 16 distinct (kind, sigma)
  * Gaussian groups per problem; more gives SL1M_EINVAL. */
 sl1m_status sl1m_plan_workspace_bytes(const sl1m_problem* problem, size_t* bytes);
 
@@ -129,6 +160,27 @@ sl1m_status sl1m_plan_create(const sl1m_problem* problem, void* workspace, size_
                              void* stream, sl1m_plan** out);
 
 sl1m_status sl1m_plan_destroy(sl1m_plan* plan);
+
+/* What a plan decided: evaluation order and split of the operators.  Host
+ * call, no device work.  `info` is a host pointer filled on success. */
+typedef struct {
+  int64_t n_pix, n_vis;
+  int32_t precision;        /* sl1m_precision                                   */
+  int32_t max_rhs;
+  int32_t grid;             /* 1 when single-RHS calls use the grid evaluation  */
+  int32_t grid_abs_l;       /* distinct |l| values of the delta pixels (grid)   */
+  int32_t grid_abs_m;       /* distinct |m| values of the delta pixels (grid)   */
+  int32_t n_layers;         /* Gaussian (kind, sigma) groups                    */
+  int64_t grid_positions;   /* 4 x grid cells evaluated (>= delta pixels)       */
+  int32_t fwd_vpl;          /* visibilities per lane, direct forward            */
+  int32_t adj_ppl;          /* pixels per lane, direct adjoint                  */
+  int32_t n_fchunks;        /* split-K partial rows of the forward (direct)     */
+  int32_t n_fchunks_grid;   /* ... of the forward with the grid evaluation      */
+  int32_t n_achunks;        /* visibility chunks of the adjoint                 */
+  int32_t reserved[5];
+} sl1m_plan_info;
+
+sl1m_status sl1m_plan_query(const sl1m_plan* plan, sl1m_plan_info* info);
 
 /* Forward operator, eq. (sme): vis[k] = sum_j M_kj x[j] with M from eq. (deltam),
  * (samlm4) or (samlm5) per pixel.  x: real [n_pix]; vis: complex [n_vis].

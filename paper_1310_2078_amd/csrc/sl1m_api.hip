@@ -35,6 +35,14 @@ struct Analysis {
   std::vector<Chunk> fd, fg, pd, pg;
   int64_t kchunk = 0;
   int n_achunks = 0;
+  // grid evaluation of the delta pixels
+  bool grid = false;
+  int grid_na = 0, grid_nb = 0, grid_ng = 0;
+  int64_t grid_cells = 0;
+  std::vector<double> grid_la, grid_mb, grid_nu;
+  std::vector<int32_t> grid_slot;
+  std::vector<GridChunk> grid_fc;
+  int grid_vtiles = 0, grid_ablocks = 0;
 };
 
 sl1m_status d2h(void* dst, const void* src, size_t bytes, const char* what) {
@@ -50,6 +58,72 @@ size_t visrecD_bytes(size_t rb) {
 }
 size_t visrecG_bytes(size_t rb) {
   return rb == 8 ? sizeof(VisRecG<double>) : sizeof(VisRecG<float>);
+}
+
+// Decides whether the delta pixels qualify for the grid evaluation and, if
+// so, builds its tables: the distinct |l| and |m| values, each cell's n - 1,
+// and the permuted pixel index of every occupied sign slot.  Returns false
+// with a reason when they do not qualify.
+bool analyze_grid(const sl1m_problem* pr, Analysis& a, const Segment& dseg, std::string& why,
+                  sl1m_status& err) {
+  err = SL1M_OK;
+  if (a.precision != SL1M_PREC_FP32) return why = "the plan is float64", false;
+  if (a.beam_pair) return why = "the plan has per-pair beams", false;
+  if (dseg.count < 1024) return why = "fewer than 1024 delta pixels", false;
+  const int64_t np = a.n_pix, nd = dseg.count;
+  std::vector<double> L(np), M(np);
+  if ((err = d2h(L.data(), pr->l, np * sizeof(double), "read l"))) return false;
+  if ((err = d2h(M.data(), pr->m, np * sizeof(double), "read m"))) return false;
+  std::vector<double> al(nd), am(nd);
+  for (int64_t t = 0; t < nd; ++t) {
+    const int64_t o = a.perm.empty() ? dseg.start + t : a.perm[dseg.start + t];
+    if (!std::isfinite(L[o]) || !std::isfinite(M[o])) return why = "non-finite position", false;
+    al[t] = std::fabs(L[o]);
+    am[t] = std::fabs(M[o]);
+  }
+  std::vector<double> ul(al), um(am);
+  std::sort(ul.begin(), ul.end());
+  ul.erase(std::unique(ul.begin(), ul.end()), ul.end());
+  std::sort(um.begin(), um.end());
+  um.erase(std::unique(um.begin(), um.end()), um.end());
+  const int64_t na = static_cast<int64_t>(ul.size()), nb = static_cast<int64_t>(um.size());
+  if (na < kGridMinA) return why = "fewer than 16 distinct |l| values", false;
+  const int64_t ng = (nb + kGridNB - 1) / kGridNB;
+  const int64_t cells = ng * kGridNB * na;
+  if (2 * 4 * cells > 5 * nd) return why = "the delta pixels fill less than 40% of their grid", false;
+  if (4 * cells > INT32_MAX) return why = "grid too large", false;
+  std::vector<int32_t> slot(4 * cells, -1);
+  for (int64_t t = 0; t < nd; ++t) {
+    const int64_t j = dseg.start + t;  // permuted index
+    const int64_t o = a.perm.empty() ? j : a.perm[j];
+    const int64_t ia = std::lower_bound(ul.begin(), ul.end(), al[t]) - ul.begin();
+    const int64_t ib = std::lower_bound(um.begin(), um.end(), am[t]) - um.begin();
+    const int sgn = (L[o] < 0.0 ? 1 : 0) + (M[o] < 0.0 ? 2 : 0);
+    const int64_t q = ((ib / kGridNB) * na + ia) * kGridNB + ib % kGridNB;
+    int32_t& sl = slot[4 * q + sgn];
+    if (sl >= 0) return why = "two delta pixels share a position", false;
+    sl = static_cast<int32_t>(j);
+  }
+  a.grid_la = ul;
+  a.grid_mb.assign(ng * kGridNB, 0.0);
+  std::copy(um.begin(), um.end(), a.grid_mb.begin());
+  a.grid_nu.assign(cells, 0.0);
+  for (int64_t g = 0; g < ng; ++g)
+    for (int64_t ia = 0; ia < na; ++ia)
+      for (int b = 0; b < kGridNB; ++b) {
+        const double l = ul[ia], m = a.grid_mb[g * kGridNB + b];
+        const double r2 = l * l + m * m;
+        // n - 1 = -r^2 / (1 + n); cells outside the unit disk stay 0 (the
+        // domain check rejects any pixel there)
+        a.grid_nu[(g * na + ia) * kGridNB + b] = r2 < 1.0 ? -r2 / (1.0 + std::sqrt(1.0 - r2)) : 0.0;
+      }
+  a.grid_slot.swap(slot);
+  a.grid_na = static_cast<int>(na);
+  a.grid_nb = static_cast<int>(nb);
+  a.grid_ng = static_cast<int>(ng);
+  a.grid_cells = cells;
+  a.grid = true;
+  return true;
 }
 
 sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
@@ -196,10 +270,41 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
       (s.kind == SL1M_PIX_DELTA ? a.pd : a.pg).push_back(c);
     }
   }
-  const int64_t ptiles = static_cast<int64_t>(a.pd.size() + a.pg.size());
+  // ---- grid evaluation of the delta pixels
+  if (pr->grid_mode < SL1M_GRID_AUTO || pr->grid_mode > SL1M_GRID_REQUIRE)
+    return set_error(SL1M_EINVAL, "unknown grid_mode");
+  a.grid = false;
+  if (pr->grid_mode != SL1M_GRID_OFF && nv > 0) {
+    const Segment* dseg = nullptr;
+    for (const Segment& sg : a.segs)
+      if (sg.kind == SL1M_PIX_DELTA) dseg = &sg;
+    std::string why = "there are no delta pixels";
+    sl1m_status err = SL1M_OK;
+    const bool ok = dseg && analyze_grid(pr, a, *dseg, why, err);
+    if (err) return err;
+    if (!ok && pr->grid_mode == SL1M_GRID_REQUIRE)
+      return set_error(SL1M_EINVAL, "grid evaluation required but " + why);
+  }
+  if (a.grid) {
+    a.grid_vtiles = static_cast<int>((nv + 2 * kBlock - 1) / (2 * kBlock));
+    const int64_t per_split = static_cast<int64_t>(a.grid_vtiles) * a.grid_ng;
+    int64_t split = (target_blocks + per_split - 1) / per_split;
+    split = std::max<int64_t>(1, std::min<int64_t>(split, (a.grid_na + 7) / 8));
+    const int ra = static_cast<int>((a.grid_na + split - 1) / split);
+    a.grid_fc.clear();
+    for (int g = 0; g < a.grid_ng; ++g)
+      for (int i0 = 0; i0 < a.grid_na; i0 += ra)
+        a.grid_fc.push_back(GridChunk{g, i0, std::min(a.grid_na, i0 + ra), 0});
+    const int64_t sets = static_cast<int64_t>(2) * a.grid_ng * a.grid_na;
+    a.grid_ablocks = static_cast<int>((sets + kBlock - 1) / kBlock);
+  }
+
+  // ---- visibility chunks of the adjoint (shared by all of its kernels)
+  const int64_t ptiles = static_cast<int64_t>((a.grid ? a.grid_ablocks : a.pd.size()) + a.pg.size());
   if (nv > 0 && ptiles > 0) {
+    const int64_t cap = a.grid ? 256 : 64;
     int64_t want =
-        std::max<int64_t>(1, std::min<int64_t>(64, (target_blocks + ptiles - 1) / ptiles));
+        std::max<int64_t>(1, std::min<int64_t>(cap, (target_blocks + ptiles - 1) / ptiles));
     a.kchunk = std::max<int64_t>(64, (nv + want - 1) / want);
     a.n_achunks = static_cast<int>((nv + a.kchunk - 1) / a.kchunk);
   } else {
@@ -211,7 +316,8 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
-      rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, total;
+      rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
+      grid_mb, grid_nu, grid_slot, grid_rec, grid_fc, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -245,7 +351,8 @@ Layout layout(const Analysis& a) {
   L.rres = take(2 * rb * (1 + nl) * nv * nr);
   L.layerDs = take(2 * rb * nl * nv);
   L.chunks = take(sizeof(Chunk) * (nfc + npt));
-  L.fpart = take(2 * rb * nfc * nv * nr);
+  const size_t grid_rows = a.grid ? a.grid_fc.size() + a.fg.size() : 0;
+  L.fpart = take(2 * rb * std::max(nfc * nr, grid_rows) * nv);
   L.apart = take(rb * static_cast<size_t>(a.n_achunks) * np * nr);
   L.xperm = take(rb * np * nr);
   L.img = take(rb * np);
@@ -254,6 +361,13 @@ Layout layout(const Analysis& a) {
   L.red_out = take(8 * 8);
   L.flag = take(sizeof(int));
   L.scal = take(8 * sizeof(double));
+  const size_t cells = static_cast<size_t>(a.grid_cells);
+  L.grid_la = take(8 * a.grid_la.size());
+  L.grid_mb = take(8 * a.grid_mb.size());
+  L.grid_nu = take(8 * cells);
+  L.grid_slot = take(4 * 4 * cells);
+  L.grid_rec = take(sizeof(GridRec) * cells);
+  L.grid_fc = take(sizeof(GridChunk) * a.grid_fc.size());
   L.total = off;
   return L;
 }
@@ -443,6 +557,14 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->ptiles_gauss = a.pg;
     p->adj_kchunk = a.kchunk;
     p->n_achunks = a.n_achunks;
+    p->grid = a.grid;
+    p->grid_na = a.grid_na;
+    p->grid_nb = a.grid_nb;
+    p->grid_ng = a.grid_ng;
+    p->grid_cells = a.grid_cells;
+    p->grid_vtiles = a.grid_vtiles;
+    p->grid_fchunks = a.grid_fc;
+    p->grid_ablocks = a.grid_ablocks;
     for (const Segment& sg : a.segs) {
       if (sg.count == 0) continue;
       (sg.kind == SL1M_PIX_DELTA ? p->any_delta : p->any_gauss) = true;
@@ -478,6 +600,14 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->red_out = reinterpret_cast<double*>(w + L.red_out);
     p->flag = reinterpret_cast<int*>(w + L.flag);
     p->scal = reinterpret_cast<double*>(w + L.scal);
+    if (a.grid) {
+      p->grid_la = reinterpret_cast<double*>(w + L.grid_la);
+      p->grid_mb = reinterpret_cast<double*>(w + L.grid_mb);
+      p->grid_nu = reinterpret_cast<double*>(w + L.grid_nu);
+      p->grid_slot = reinterpret_cast<int32_t*>(w + L.grid_slot);
+      p->grid_rec = reinterpret_cast<GridRec*>(w + L.grid_rec);
+      p->d_grid_fchunks = reinterpret_cast<GridChunk*>(w + L.grid_fc);
+    }
 
     auto fail = [&](sl1m_status st_) {
       delete p;
@@ -503,6 +633,17 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     if (e == hipSuccess && p->n_layers)
       e = hipMemcpyAsync(p->red, a.layer_sigma.data(), p->n_layers * sizeof(double),
                          hipMemcpyHostToDevice, st);
+    if (a.grid) {
+      auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes)
+          e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+      };
+      up(p->grid_la, a.grid_la.data(), 8 * a.grid_la.size());
+      up(p->grid_mb, a.grid_mb.data(), 8 * a.grid_mb.size());
+      up(p->grid_nu, a.grid_nu.data(), 8 * a.grid_nu.size());
+      up(p->grid_slot, a.grid_slot.data(), 4 * a.grid_slot.size());
+      up(p->d_grid_fchunks, a.grid_fc.data(), sizeof(GridChunk) * a.grid_fc.size());
+    }
     if (e == hipSuccess) e = launch_fill(p->flag, 1, sizeof(int), st);
     if (e == hipSuccess)
       e = launch_domain_check(p, pr->l, pr->m, pr->sigma, pr->u, pr->v, pr->w, st);
@@ -548,6 +689,29 @@ sl1m_status sl1m_plan_destroy(sl1m_plan* plan) {
     release_graph(plan);
   }
   delete plan;
+  return SL1M_OK;
+}
+
+sl1m_status sl1m_plan_query(const sl1m_plan* p, sl1m_plan_info* info) {
+  if (!p) return set_error(SL1M_EINVAL, "plan is NULL");
+  if (!info) return set_error(SL1M_EINVAL, "info is NULL");
+  sl1m_plan_info r;
+  std::memset(&r, 0, sizeof(r));
+  r.n_pix = p->n_pix;
+  r.n_vis = p->n_vis;
+  r.precision = p->precision;
+  r.max_rhs = p->max_rhs;
+  r.grid = p->grid ? 1 : 0;
+  r.grid_abs_l = p->grid_na;
+  r.grid_abs_m = p->grid_nb;
+  r.n_layers = p->n_layers;
+  r.grid_positions = 4 * p->grid_cells;
+  r.fwd_vpl = p->fwd_vpl;
+  r.adj_ppl = p->adj_ppl;
+  r.n_fchunks = p->n_fchunks;
+  r.n_fchunks_grid = p->grid ? forward_rows(p, 1) : 0;
+  r.n_achunks = p->n_achunks;
+  *info = r;
   return SL1M_OK;
 }
 

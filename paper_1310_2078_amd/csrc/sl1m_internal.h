@@ -63,6 +63,33 @@ struct Chunk {           // a contiguous pixel range inside one segment
   int32_t seg, layer;
 };
 
+// Grid evaluation of the delta pixels.  A grid cell (ia, ib) stands for the
+// four positions (+-|l|_ia, +-|m|_ib); cells are numbered
+//   q = ((ib / kGridNB) * n_a + ia) * kGridNB + ib % kGridNB
+// so the kGridNB cells of one |l| value and one group of |m| values are
+// adjacent.  Sign slots: 0 = (+l, +m), 1 = (-l, +m), 2 = (+l, -m), 3 = (-l, -m);
+// a zero coordinate takes the + slot.
+constexpr int kGridNB = 8;       // |m| values per forward group
+constexpr int kGridNBA = 4;      // |m| values per adjoint lane
+constexpr int kGridKB = 32;      // visibilities per adjoint LDS batch
+constexpr int kGridMaxGL = 18;   // |m| groups one adjoint block touches (n_a >= 16)
+constexpr int kGridMinA = 16;
+
+// Per-call forward record of one cell: n - 1 of the cell and the sign
+// combinations of the four amplitudes x_s (x times 1/n and beam factor):
+//   e1 = x0 + x1 + x2 + x3, e2 = x1 + x2 - x0 - x3,
+//   e3 = x0 + x1 - x2 - x3, e4 = x0 - x1 + x2 - x3;
+// `empty` = 1 when no pixel sits in the cell.
+struct GridRec {
+  double nu;
+  float e1, e2, e3, e4;
+  int32_t empty, pad;
+};
+
+struct GridChunk {       // forward: one |m| group times an |l| range
+  int32_t g, ia0, ia1, pad;
+};
+
 }  // namespace sl1m
 
 struct sl1m_plan {
@@ -88,6 +115,21 @@ struct sl1m_plan {
   std::vector<sl1m::Chunk> ptiles_delta, ptiles_gauss;
   int64_t adj_kchunk = 0;     // visibilities per chunk
   int n_achunks = 0;
+
+  // grid evaluation of the delta pixels (single right-hand side, FP32)
+  bool grid = false;
+  int grid_na = 0, grid_nb = 0;   // distinct |l|, |m| values
+  int grid_ng = 0;                // |m| groups of kGridNB
+  int64_t grid_cells = 0;         // grid_ng * kGridNB * grid_na
+  int grid_vtiles = 0;            // forward visibility tiles (2 per lane)
+  std::vector<sl1m::GridChunk> grid_fchunks;
+  int grid_ablocks = 0;           // adjoint blocks per visibility chunk
+  double* grid_la = nullptr;      // [grid_na] |l|
+  double* grid_mb = nullptr;      // [grid_ng * kGridNB] |m| (0 padded)
+  double* grid_nu = nullptr;      // [grid_cells] n - 1
+  int32_t* grid_slot = nullptr;   // [4 * grid_cells] permuted pixel index or -1
+  sl1m::GridRec* grid_rec = nullptr;        // [grid_cells] per-call records
+  sl1m::GridChunk* d_grid_fchunks = nullptr;
 
   // device buffers (carved from the workspace)
   char* ws = nullptr;
@@ -162,6 +204,8 @@ hipError_t launch_prep_vis(sl1m_plan* p, const double* u, const double* v, const
 // nr = number of right-hand sides (1, 2, 4 or 8); vectors are [nr][n].
 hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, int nr, hipStream_t st);
 hipError_t launch_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st);
+// Partial rows a forward with nr right-hand sides writes (grid or direct split).
+int forward_rows(const sl1m_plan* p, int nr);
 hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool adj_records,
                                  int nr, hipStream_t st);
 hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t st);
@@ -181,6 +225,10 @@ hipError_t launch_copy_real(sl1m_plan* p, const void* src, void* dst, int64_t n,
 hipError_t launch_dot_norm(sl1m_plan* p, const void* a, const void* b, hipStream_t st);
 hipError_t launch_objective_terms(sl1m_plan* p, const void* res, const void* img,
                                   hipStream_t st);
+// grid evaluation (sl1m_grid.hip): delta pixels only, rows [0, grid_fchunks)
+// of the forward partials and every delta pixel of the adjoint partials.
+hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st);
+hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st);
 hipError_t launch_domain_check(sl1m_plan* p, const double* l, const double* m,
                                const double* sigma, const double* u, const double* v,
                                const double* w, hipStream_t st);

@@ -471,14 +471,17 @@ __global__ void k_domain(const double* __restrict__ l, const double* __restrict_
 
 inline unsigned grid1(int64_t n, int b = kBlock) { return static_cast<unsigned>((n + b - 1) / b); }
 
+// Direct-evaluation forward launches.  With `grid` the delta chunks are left
+// to the grid kernels, which own rows [0, grid_fchunks); Gaussian rows follow.
 template <typename R, int VPL, bool BEAM, int NR>
-hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st) {
+hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st, bool grid = false) {
   const int64_t vt = (p->n_vis + kBlock * VPL - 1) / (kBlock * VPL);
   C2<R>* part = static_cast<C2<R>*>(p->fpart);
-  const int nd = static_cast<int>(p->fchunks_delta.size());
+  const int nd = grid ? static_cast<int>(p->grid_fchunks.size())
+                      : static_cast<int>(p->fchunks_delta.size());
   const int ng = static_cast<int>(p->fchunks_gauss.size());
-  const int rows = p->n_fchunks;
-  if (nd > 0) {
+  const int rows = nd + ng;
+  if (nd > 0 && !grid) {
     hipLaunchKernelGGL((k_fwd_delta<R, VPL, BEAM, NR>), dim3(static_cast<unsigned>(vt), nd),
                        dim3(kBlock), 0, st, static_cast<const PixRec<R>*>(p->pixrec),
                        static_cast<const R*>(xp), p->n_pix, p->vu, p->vv, p->vw,
@@ -488,20 +491,22 @@ hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st) {
     hipLaunchKernelGGL((k_fwd_gauss<R, VPL, BEAM, NR>), dim3(static_cast<unsigned>(vt), ng),
                        dim3(kBlock), 0, st, static_cast<const PixRec<R>*>(p->pixrec),
                        static_cast<const R*>(xp), p->n_pix, p->vu, p->vv, p->vw,
-                       static_cast<const R*>(p->vbeta), p->d_fchunks + nd, p->n_vis, part, nd,
-                       rows);
+                       static_cast<const R*>(p->vbeta),
+                       p->d_fchunks + p->fchunks_delta.size(), p->n_vis, part, nd, rows);
   }
   return hipGetLastError();
 }
 
+// Direct-evaluation adjoint launches; with `grid` the delta tiles are left to
+// the grid kernel.
 template <typename R, int PPL, bool BEAM, int NR>
-hipError_t adj_launch_t(sl1m_plan* p, hipStream_t st) {
+hipError_t adj_launch_t(sl1m_plan* p, hipStream_t st, bool grid = false) {
   R* part = static_cast<R*>(p->apart);
   const int nd = static_cast<int>(p->ptiles_delta.size());
   const int ng = static_cast<int>(p->ptiles_gauss.size());
   const int sub = p->adj_ppl / PPL;  // blocks per plan tile
   const C2<R>* rres = static_cast<const C2<R>*>(p->rres);
-  if (nd > 0) {
+  if (nd > 0 && !grid) {
     hipLaunchKernelGGL((k_adj_delta<R, PPL, BEAM, NR>), dim3(nd * sub, p->n_achunks), dim3(kBlock),
                        0, st, static_cast<const VisRecD<R>*>(p->visrecD), rres,
                        static_cast<const R*>(p->vbeta), p->pl, p->pm, p->pc3,
@@ -575,6 +580,14 @@ template <typename R>
 static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
   if (p->n_vis == 0 || p->n_fchunks == 0) return hipSuccess;
   const bool bm = p->beam_pair;
+  if (nr == 1 && p->grid) {
+    // the grid kernels take the delta pixels; Gaussian pixels stay direct
+    hipError_t e = launch_grid_forward(p, xp, st);
+    if (e != hipSuccess || p->fchunks_gauss.empty()) return e;
+    if (p->fwd_vpl == 1) return fwd_launch_t<R, 1, false, 1>(p, xp, st, true);
+    if (p->fwd_vpl == 2) return fwd_launch_t<R, 2, false, 1>(p, xp, st, true);
+    return fwd_launch_t<R, 4, false, 1>(p, xp, st, true);
+  }
   switch (nr) {
     case 1:
       if (bm) return fwd_launch_t<R, 4, true, 1>(p, xp, st);
@@ -603,12 +616,18 @@ hipError_t launch_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st) 
   return SL1M_DISPATCH_R(p, forward_t, p, xp, nr, st);
 }
 
+int forward_rows(const sl1m_plan* p, int nr) {
+  if (nr == 1 && p->grid)
+    return static_cast<int>(p->grid_fchunks.size() + p->fchunks_gauss.size());
+  return p->n_fchunks;
+}
+
 template <typename R>
 static hipError_t fwd_reduce_t(sl1m_plan* p, const void* data, void* out, bool recs, int nr,
                                hipStream_t st) {
   if (p->n_vis == 0) return hipSuccess;
   hipLaunchKernelGGL((k_fwd_reduce<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
-                     static_cast<const C2<R>*>(p->fpart), p->n_fchunks, p->n_vis, nr,
+                     static_cast<const C2<R>*>(p->fpart), forward_rows(p, nr), p->n_vis, nr,
                      static_cast<const R*>(p->vgain), static_cast<const C2<R>*>(data),
                      static_cast<C2<R>*>(out), recs ? static_cast<C2<R>*>(p->rres) : nullptr,
                      static_cast<const R*>(p->layerDs), p->n_layers);
@@ -636,6 +655,13 @@ template <typename R>
 static hipError_t adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
   if (p->n_pix == 0 || p->n_achunks == 0) return hipSuccess;
   const bool bm = p->beam_pair;
+  if (nr == 1 && p->grid) {
+    hipError_t e = launch_grid_adjoint(p, st);
+    if (e != hipSuccess || p->ptiles_gauss.empty()) return e;
+    if (p->adj_ppl == 1) return adj_launch_t<R, 1, false, 1>(p, st, true);
+    if (p->adj_ppl == 2) return adj_launch_t<R, 2, false, 1>(p, st, true);
+    return adj_launch_t<R, 4, false, 1>(p, st, true);
+  }
   switch (nr) {
     case 1:
       if (bm) return adj_launch_t<R, 4, true, 1>(p, st);

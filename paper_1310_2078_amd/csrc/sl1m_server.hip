@@ -656,6 +656,8 @@ sl1m_status sl1m_server_submit(sl1m_server* s, const sl1m_problem* problem, cons
     auto t = std::make_unique<Ticket>();
     t->problem = *problem;
     t->problem.tile_blocks = problem->tile_blocks > 0 ? problem->tile_blocks : kSrvTileBlocks;
+    // the batched kernels evaluate every entry directly
+    t->problem.grid_mode = SL1M_GRID_OFF;
     size_t ws = 0;
     if (sl1m_status st = sl1m_plan_workspace_bytes(&t->problem, &ws)) return st;
     t->footprint = sched::Arena::round_up(ws) + extra_bytes(t->problem);

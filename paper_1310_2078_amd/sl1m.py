@@ -48,7 +48,7 @@ class Problem(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("max_rhs", ctypes.c_int32),
         ("tile_blocks", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("grid_mode", ctypes.c_int32),
     ]
 
 
@@ -128,6 +128,7 @@ def lib() -> ctypes.CDLL:
         L.sl1m_server_cancel.argtypes = [vp, ctypes.c_uint64]
         L.sl1m_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.sl1m_server_destroy.argtypes = [vp]
+        L.sl1m_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.sl1m_timing_begin.argtypes = [vp, i32]
         L.sl1m_timing_end.argtypes = [vp, ctypes.POINTER(Timing)]
         L.sl1m_last_error.restype = ctypes.c_char_p
@@ -135,7 +136,8 @@ def lib() -> ctypes.CDLL:
         for name in ("sl1m_plan_workspace_bytes", "sl1m_plan_create", "sl1m_plan_destroy",
                      "sl1m_forward", "sl1m_adjoint", "sl1m_forward_multi",
                      "sl1m_adjoint_multi", "sl1m_estimate_L", "sl1m_solve",
-                     "sl1m_timing_begin", "sl1m_timing_end", "sl1m_server_create",
+                     "sl1m_timing_begin", "sl1m_timing_end", "sl1m_plan_query",
+                     "sl1m_server_create",
                      "sl1m_server_submit", "sl1m_server_step", "sl1m_server_poll",
                      "sl1m_server_cancel", "sl1m_server_stats", "sl1m_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -165,6 +167,26 @@ def _dev(a, dtype, device):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
 
 
+GRID_AUTO, GRID_OFF, GRID_REQUIRE = 0, 1, 2
+_GRID = {"auto": GRID_AUTO, "off": GRID_OFF, "require": GRID_REQUIRE}
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_pix", ctypes.c_int64), ("n_vis", ctypes.c_int64),
+        ("precision", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
+        ("grid", ctypes.c_int32), ("grid_abs_l", ctypes.c_int32),
+        ("grid_abs_m", ctypes.c_int32), ("n_layers", ctypes.c_int32),
+        ("grid_positions", ctypes.c_int64),
+        ("fwd_vpl", ctypes.c_int32), ("adj_ppl", ctypes.c_int32),
+        ("n_fchunks", ctypes.c_int32), ("n_fchunks_grid", ctypes.c_int32),
+        ("n_achunks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 class Plan:
     """A planned SL1M operator on one GPU.
 
@@ -175,7 +197,7 @@ class Plan:
 
     def __init__(self, l, m, u, v, w, sigma=None, kind=None, ant_p=None, ant_q=None,
                  ant_gain=None, ant_fwhm=None, precision: str = "fp32", device="cuda",
-                 stream=None, max_rhs: int = 1, tile_blocks: int = 0):
+                 stream=None, max_rhs: int = 1, tile_blocks: int = 0, grid: str = "auto"):
         self.device = torch.device(device)
         self.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
         self.rdtype = torch.float32 if self.precision == PREC_FP32 else torch.float64
@@ -209,7 +231,7 @@ class Plan:
             w=_ptr(k["w"]), ant_p=_ptr(k["ant_p"]), ant_q=_ptr(k["ant_q"]), n_ant=n_ant,
             ant_gain=_ptr(k["ant_gain"]), ant_fwhm=_ptr(k["ant_fwhm"]),
             precision=self.precision, max_rhs=int(max_rhs), tile_blocks=int(tile_blocks),
-            reserved=0)
+            grid_mode=_GRID[grid])
         self.max_rhs = int(max_rhs)
         nbytes = ctypes.c_size_t(0)
         _check(lib().sl1m_plan_workspace_bytes(ctypes.byref(self._prob), ctypes.byref(nbytes)))
@@ -223,13 +245,19 @@ class Plan:
 
     @classmethod
     def from_workload(cls, wl, precision="fp32", device="cuda", with_kinds=True, max_rhs=1,
-                      tile_blocks=0):
+                      tile_blocks=0, grid="auto"):
         kw = {}
         if with_kinds and (np.any(wl.kind != 0) or np.any(wl.sigma != 0)):
             kw = dict(sigma=wl.sigma, kind=wl.kind)
         return cls(wl.l, wl.m, wl.u, wl.v, wl.w, ant_p=wl.ant_p, ant_q=wl.ant_q,
                    ant_gain=wl.ant_gain, ant_fwhm=wl.ant_fwhm, precision=precision,
-                   device=device, max_rhs=max_rhs, tile_blocks=tile_blocks, **kw)
+                   device=device, max_rhs=max_rhs, tile_blocks=tile_blocks, grid=grid, **kw)
+
+    def info(self) -> dict:
+        """The plan's decisions (sl1m_plan_query): grid evaluation, splits."""
+        r = PlanInfo()
+        _check(lib().sl1m_plan_query(self._h, ctypes.byref(r)))
+        return r.as_dict()
 
     # -- operator -----------------------------------------------------------
     def forward(self, x, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -363,7 +391,7 @@ class Server:
                        u=_ptr(keep["u"]), v=_ptr(keep["v"]), w=_ptr(keep["w"]),
                        ant_p=_ptr(keep["ant_p"]), ant_q=_ptr(keep["ant_q"]), n_ant=n_ant,
                        ant_gain=_ptr(keep["ant_gain"]), ant_fwhm=_ptr(keep["ant_fwhm"]),
-                       precision=PREC_FP32, max_rhs=1, tile_blocks=0, reserved=0)
+                       precision=PREC_FP32, max_rhs=1, tile_blocks=0, grid_mode=GRID_OFF)
         prm = SolveParams(lam=float(lam), eps=0.0, max_iter=int(max_iter), check_every=1,
                           L=float(L), L_safety=float(L_safety), power_iters=int(power_iters),
                           reserved=0, seed=ctypes.c_uint64(seed))

@@ -48,6 +48,11 @@ def test_host_argument_checks(L):
                       precision=sl1m.PREC_FP32, max_rhs=3)
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
     assert b"max_rhs" in L.sl1m_last_error()
+    pr = sl1m.Problem(n_pix=10, l=fake, m=fake, n_vis=10, u=fake, v=fake, w=fake,
+                      precision=sl1m.PREC_FP32, grid_mode=3)
+    assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    assert b"grid_mode" in L.sl1m_last_error()
+    assert L.sl1m_plan_query(None, None) == sl1m.EINVAL
     pr = sl1m.Problem(n_pix=10, n_vis=10, precision=sl1m.PREC_FP32)   # NULL l, m
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
     assert L.sl1m_forward(None, None, None, None) == sl1m.EINVAL
@@ -56,12 +61,12 @@ def test_host_argument_checks(L):
 
 def test_workspace_size_grows_with_problem(L):
     """Workspace sizing is host arithmetic on the sizes (delta pixels, no
-    kinds or antenna arrays, so no device access)."""
+    kinds or antenna arrays, grid evaluation off, so no device access)."""
     fake = ctypes.c_void_p(0x1000)
 
     def size(n_pix, n_vis, prec=sl1m.PREC_FP32):
         pr = sl1m.Problem(n_pix=n_pix, l=fake, m=fake, n_vis=n_vis, u=fake, v=fake, w=fake,
-                          precision=prec)
+                          precision=prec, grid_mode=sl1m.GRID_OFF)
         b = ctypes.c_size_t(0)
         assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(b)) == 0
         return b.value
@@ -74,7 +79,7 @@ def test_workspace_size_grows_with_problem(L):
     assert b < 2 ** 30             # config-2 workspace stays far below HBM
     fake = ctypes.c_void_p(0x1000)
     pr4 = sl1m.Problem(n_pix=65536, l=fake, m=fake, n_vis=97536, u=fake, v=fake, w=fake,
-                       precision=sl1m.PREC_FP32, max_rhs=4)
+                       precision=sl1m.PREC_FP32, max_rhs=4, grid_mode=sl1m.GRID_OFF)
     b4 = ctypes.c_size_t(0)
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr4), ctypes.byref(b4)) == 0
     assert b4.value > b
