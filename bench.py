@@ -90,7 +90,8 @@ def ingest_counters(fetch_csv, write_csv):
         scale = CALIB_BYTES / (sum(big) / len(big))
         for key, pat in (("k_fwd_delta<float,4>", "k_fwd_delta<float, 4, false, 1>"),
                          ("k_adj_delta<float,4>", "k_adj_delta<float, 4, false, 1>"),
-                         ("k_grid_fwd", "k_grid_fwd"), ("k_grid_adj", "k_grid_adj")):
+                         ("k_grid_fwd_delta", "k_grid_fwd_delta"),
+                         ("k_grid_adj_delta", "k_grid_adj_delta")):
             vals = [v for n, v in rows if pat in n]
             if vals:
                 rec = out.setdefault(key, {"source_hash": kernel_source_hash(key)})
@@ -305,7 +306,8 @@ def main():
     adj_avg = adj_ms / max(adj_n, 1)
     pinfo = plan.info()
     grid = bool(pinfo["grid"])
-    names = ("k_grid_adj", "k_grid_fwd") if grid else ("k_adj_delta<float,4>", "k_fwd_delta<float,4>")
+    names = (("k_grid_adj_delta", "k_grid_fwd_delta") if grid
+             else ("k_adj_delta<float,4>", "k_fwd_delta<float,4>"))
     if adj_avg >= fwd_avg:
         dom, dom_ms, dom_name = "adjoint", adj_avg, names[0]
     else:

@@ -64,19 +64,23 @@ typedef enum {
 } sl1m_precision;
 
 /*
- * Evaluation order of the delta-pixel part of the operators.  The element of
- * eq. (deltam) factorises exactly:
+ * Evaluation order of the operators.  The element of eq. (deltam) factorises
+ * exactly:
  *     exp(-2 pi i (u l + v m + w (n - 1)))
  *       = exp(-2 pi i u l) * exp(-2 pi i v m) * exp(-2 pi i w (n - 1)),
- * and n - 1 depends on l^2 + m^2 only.  When the delta pixels lie on a product
- * set symmetric under l -> -l and m -> -m (a centred image grid, or any
- * subset of one), the four pixels (+-|l|, +-|m|) share the last factor, the
- * first two come from per-|l| and per-|m| phasors, and one sincos serves four
- * matrix entries.  The "grid" evaluation uses that; the "direct" evaluation
- * forms every entry's phase on its own.  Both compute the same operator; they
- * differ by float32 rounding only.  Applies to float32 plans and single
- * right-hand-side calls; float64 plans, multi-RHS calls, Gaussian pixels and
- * per-pair beams always use the direct evaluation.
+ * and n - 1 depends on l^2 + m^2 only.  When the pixels of a segment (the
+ * delta pixels, or one Gaussian (kind, sigma) group) lie on a product set
+ * symmetric under l -> -l and m -> -m (a centred image grid, or a subset of
+ * one), the four positions (+-|l|, +-|m|) share the last factor, the first
+ * two come from per-|l| and per-|m| phasors, and one sincos serves four
+ * matrix entries.  Gaussian pixels, eqs. (samlm4)/(samlm5), factorise the
+ * same way: the taper exp(-pi sigma^2 D |(u,v) - w(l,m)|^2) is a product of
+ * an l part and an m part, the phase is linear in l and m plus terms in
+ * l^2 + m^2.  The "grid" evaluation uses that; the "direct" evaluation forms
+ * every entry on its own.  Both compute the same operator; they differ by
+ * float32 rounding only.  Applies to float32 plans without per-pair beams and
+ * to single right-hand-side calls; float64 plans and multi-RHS calls always
+ * use the direct evaluation, and so do segments that do not qualify.
  */
 typedef enum {
   SL1M_GRID_AUTO = 0,    /* grid evaluation when the delta pixels qualify        */
@@ -110,13 +114,14 @@ typedef enum {
  *  tile_blocks  number of thread blocks the split of one operator application
  *            aims at (more blocks: more parallelism, larger partial-sum
  *            buffers); 0 means 4096, enough to fill the 256 compute units.
- *  grid_mode sl1m_grid_mode.  The delta pixels qualify for the grid
- *            evaluation when (a) the plan is float32 without per-pair beams,
- *            (b) no two delta pixels share a position, (c) there are at least
- *            16 distinct |l| values and at least 1024 delta pixels, and
- *            (d) the product set of distinct |l| and |m| values (padded to a
- *            multiple of 8 |m| values), times four signs, holds at most 2.5
- *            times as many positions as there are delta pixels.
+ *  grid_mode sl1m_grid_mode.  A segment qualifies for the grid evaluation
+ *            when (a) the plan is float32 without per-pair beams, (b) no two
+ *            of its pixels share a position, (c) it has at least 1024 pixels
+ *            with at least 16 distinct |l| values, and (d) the product set of
+ *            its distinct |l| and |m| values (padded to a multiple of 8 |m|
+ *            values), times four signs, holds at most 2.5 times as many
+ *            positions as it has pixels.  SL1M_GRID_REQUIRE needs at least
+ *            one qualifying segment.
  */
 typedef struct {
   int64_t n_pix;
@@ -144,9 +149,9 @@ typedef struct sl1m_plan sl1m_plan;
 /* Bytes of device workspace that sl1m_plan_create() needs for `problem`.
  * Reads sigma, kind, ant_p, ant_q and ant_fwhm with blocking device-to-host
  * copies when they are given (the grouping of pixels and the gain mode set the
- * layout), and l and m of the delta pixels unless grid_mode is SL1M_GRID_OFF
- * or the plan is float64 (the grid evaluation's tables depend on them); the
- * other arrays are not read.  At most 16 distinct (kind, sigma)
+ * layout), and l and m unless grid_mode is SL1M_GRID_OFF, the plan is float64
+ * or no segment has 1024 pixels (the grid evaluation's tables depend on them);
+ * the other arrays are not read.  At most 16 distinct (kind, sigma)
  * Gaussian groups per problem; more gives SL1M_EINVAL. */
 sl1m_status sl1m_plan_workspace_bytes(const sl1m_problem* problem, size_t* bytes);
 
@@ -167,9 +172,9 @@ typedef struct {
   int64_t n_pix, n_vis;
   int32_t precision;        /* sl1m_precision                                   */
   int32_t max_rhs;
-  int32_t grid;             /* 1 when single-RHS calls use the grid evaluation  */
-  int32_t grid_abs_l;       /* distinct |l| values of the delta pixels (grid)   */
-  int32_t grid_abs_m;       /* distinct |m| values of the delta pixels (grid)   */
+  int32_t grid;             /* segments single-RHS calls evaluate on their grid */
+  int32_t grid_abs_l;       /* distinct |l| of the delta segment, if on its grid */
+  int32_t grid_abs_m;       /* distinct |m| of the delta segment, if on its grid */
   int32_t n_layers;         /* Gaussian (kind, sigma) groups                    */
   int64_t grid_positions;   /* 4 x grid cells evaluated (>= delta pixels)       */
   int32_t fwd_vpl;          /* visibilities per lane, direct forward            */

@@ -35,14 +35,16 @@ struct Analysis {
   std::vector<Chunk> fd, fg, pd, pg;
   int64_t kchunk = 0;
   int n_achunks = 0;
-  // grid evaluation of the delta pixels
+  // grid evaluation: segments on the grid path, their concatenated tables,
+  // and the direct chunks of the other segments
   bool grid = false;
-  int grid_na = 0, grid_nb = 0, grid_ng = 0;
+  std::vector<GridSeg> gsegs;
   int64_t grid_cells = 0;
-  std::vector<double> grid_la, grid_mb, grid_nu;
+  std::vector<double> grid_la, grid_mb, grid_c3, grid_c4;
   std::vector<int32_t> grid_slot;
   std::vector<GridChunk> grid_fc;
-  int grid_vtiles = 0, grid_ablocks = 0;
+  int grid_vtiles = 0, grid_frows = 0;
+  std::vector<Chunk> fd1, fg1, pd1, pg1;
 };
 
 sl1m_status d2h(void* dst, const void* src, size_t bytes, const char* what) {
@@ -60,23 +62,22 @@ size_t visrecG_bytes(size_t rb) {
   return rb == 8 ? sizeof(VisRecG<double>) : sizeof(VisRecG<float>);
 }
 
-// Decides whether the delta pixels qualify for the grid evaluation and, if
-// so, builds its tables: the distinct |l| and |m| values, each cell's n - 1,
-// and the permuted pixel index of every occupied sign slot.  Returns false
-// with a reason when they do not qualify.
-bool analyze_grid(const sl1m_problem* pr, Analysis& a, const Segment& dseg, std::string& why,
-                  sl1m_status& err) {
-  err = SL1M_OK;
+// Decides whether the pixels of segment `si` (in permuted order) qualify for
+// the grid evaluation and, if so, appends its tables to the analysis: the
+// distinct |l| and |m| values, per cell n - 1 (delta) or l^2 + m^2 and kappa
+// (Gaussian), and the permuted pixel index of every occupied sign slot.
+// Returns false with a reason when they do not qualify.  L and M hold the
+// caller's l and m (host copies).
+bool analyze_grid(Analysis& a, int si, const std::vector<double>& L, const std::vector<double>& M,
+                  std::string& why) {
+  const Segment& sg = a.segs[si];
   if (a.precision != SL1M_PREC_FP32) return why = "the plan is float64", false;
   if (a.beam_pair) return why = "the plan has per-pair beams", false;
-  if (dseg.count < 1024) return why = "fewer than 1024 delta pixels", false;
-  const int64_t np = a.n_pix, nd = dseg.count;
-  std::vector<double> L(np), M(np);
-  if ((err = d2h(L.data(), pr->l, np * sizeof(double), "read l"))) return false;
-  if ((err = d2h(M.data(), pr->m, np * sizeof(double), "read m"))) return false;
+  if (sg.count < 1024) return why = "fewer than 1024 pixels in the segment", false;
+  const int64_t nd = sg.count;
   std::vector<double> al(nd), am(nd);
   for (int64_t t = 0; t < nd; ++t) {
-    const int64_t o = a.perm.empty() ? dseg.start + t : a.perm[dseg.start + t];
+    const int64_t o = a.perm.empty() ? sg.start + t : a.perm[sg.start + t];
     if (!std::isfinite(L[o]) || !std::isfinite(M[o])) return why = "non-finite position", false;
     al[t] = std::fabs(L[o]);
     am[t] = std::fabs(M[o]);
@@ -90,38 +91,58 @@ bool analyze_grid(const sl1m_problem* pr, Analysis& a, const Segment& dseg, std:
   if (na < kGridMinA) return why = "fewer than 16 distinct |l| values", false;
   const int64_t ng = (nb + kGridNB - 1) / kGridNB;
   const int64_t cells = ng * kGridNB * na;
-  if (2 * 4 * cells > 5 * nd) return why = "the delta pixels fill less than 40% of their grid", false;
-  if (4 * cells > INT32_MAX) return why = "grid too large", false;
+  if (2 * 4 * cells > 5 * nd) return why = "the pixels fill less than 40% of their grid", false;
+  if (4 * (a.grid_cells + cells) > INT32_MAX) return why = "grid too large", false;
   std::vector<int32_t> slot(4 * cells, -1);
   for (int64_t t = 0; t < nd; ++t) {
-    const int64_t j = dseg.start + t;  // permuted index
+    const int64_t j = sg.start + t;  // permuted index
     const int64_t o = a.perm.empty() ? j : a.perm[j];
     const int64_t ia = std::lower_bound(ul.begin(), ul.end(), al[t]) - ul.begin();
     const int64_t ib = std::lower_bound(um.begin(), um.end(), am[t]) - um.begin();
     const int sgn = (L[o] < 0.0 ? 1 : 0) + (M[o] < 0.0 ? 2 : 0);
     const int64_t q = ((ib / kGridNB) * na + ia) * kGridNB + ib % kGridNB;
     int32_t& sl = slot[4 * q + sgn];
-    if (sl >= 0) return why = "two delta pixels share a position", false;
+    if (sl >= 0) return why = "two pixels of the segment share a position", false;
     sl = static_cast<int32_t>(j);
   }
-  a.grid_la = ul;
-  a.grid_mb.assign(ng * kGridNB, 0.0);
-  std::copy(um.begin(), um.end(), a.grid_mb.begin());
-  a.grid_nu.assign(cells, 0.0);
-  for (int64_t g = 0; g < ng; ++g)
+  GridSeg g{};
+  g.seg = si;
+  g.kind = sg.kind;
+  g.layer = sg.layer;
+  g.na = static_cast<int32_t>(na);
+  g.nb = static_cast<int32_t>(nb);
+  g.ng = static_cast<int32_t>(ng);
+  g.cells = cells;
+  g.la_off = static_cast<int64_t>(a.grid_la.size());
+  g.mb_off = static_cast<int64_t>(a.grid_mb.size());
+  g.cell_off = a.grid_cells;
+  a.grid_la.insert(a.grid_la.end(), ul.begin(), ul.end());
+  std::vector<double> mbp(ng * kGridNB, 0.0);
+  std::copy(um.begin(), um.end(), mbp.begin());
+  a.grid_mb.insert(a.grid_mb.end(), mbp.begin(), mbp.end());
+  a.grid_c3.resize(a.grid_cells + cells, 0.0);
+  a.grid_c4.resize(a.grid_cells + cells, 0.0);
+  for (int64_t gi = 0; gi < ng; ++gi)
     for (int64_t ia = 0; ia < na; ++ia)
       for (int b = 0; b < kGridNB; ++b) {
-        const double l = ul[ia], m = a.grid_mb[g * kGridNB + b];
+        const double l = ul[ia], m = mbp[gi * kGridNB + b];
         const double r2 = l * l + m * m;
-        // n - 1 = -r^2 / (1 + n); cells outside the unit disk stay 0 (the
-        // domain check rejects any pixel there)
-        a.grid_nu[(g * na + ia) * kGridNB + b] = r2 < 1.0 ? -r2 / (1.0 + std::sqrt(1.0 - r2)) : 0.0;
+        const int64_t q = a.grid_cells + (gi * na + ia) * kGridNB + b;
+        // n - 1 = -r^2 / (1 + n), kappa = n - 1 + r^2/2 = -r^4 / (2 (1 + n)^2);
+        // cells outside the unit disk stay 0 (the domain check rejects any
+        // pixel there)
+        if (!(r2 < 1.0)) continue;
+        const double n = std::sqrt(1.0 - r2);
+        if (sg.kind == SL1M_PIX_DELTA) {
+          a.grid_c3[q] = -r2 / (1.0 + n);
+        } else {
+          a.grid_c3[q] = r2;
+          a.grid_c4[q] = sg.kind == SL1M_PIX_GAUSS_WIDE ? -(r2 * r2) / (2.0 * (1.0 + n) * (1.0 + n)) : 0.0;
+        }
       }
-  a.grid_slot.swap(slot);
-  a.grid_na = static_cast<int>(na);
-  a.grid_nb = static_cast<int>(nb);
-  a.grid_ng = static_cast<int>(ng);
-  a.grid_cells = cells;
+  a.grid_slot.insert(a.grid_slot.end(), slot.begin(), slot.end());
+  a.grid_cells += cells;
+  a.gsegs.push_back(g);
   a.grid = true;
   return true;
 }
@@ -270,37 +291,65 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
       (s.kind == SL1M_PIX_DELTA ? a.pd : a.pg).push_back(c);
     }
   }
-  // ---- grid evaluation of the delta pixels
+  // ---- grid evaluation, segment by segment
   if (pr->grid_mode < SL1M_GRID_AUTO || pr->grid_mode > SL1M_GRID_REQUIRE)
     return set_error(SL1M_EINVAL, "unknown grid_mode");
   a.grid = false;
-  if (pr->grid_mode != SL1M_GRID_OFF && nv > 0) {
-    const Segment* dseg = nullptr;
-    for (const Segment& sg : a.segs)
-      if (sg.kind == SL1M_PIX_DELTA) dseg = &sg;
-    std::string why = "there are no delta pixels";
-    sl1m_status err = SL1M_OK;
-    const bool ok = dseg && analyze_grid(pr, a, *dseg, why, err);
-    if (err) return err;
-    if (!ok && pr->grid_mode == SL1M_GRID_REQUIRE)
+  if (pr->grid_mode != SL1M_GRID_OFF && nv > 0 && np > 0) {
+    std::string why = "no segment has 1024 pixels";
+    if (a.precision != SL1M_PREC_FP32) why = "the plan is float64";
+    else if (a.beam_pair) why = "the plan has per-pair beams";
+    bool any_big = false;
+    for (const Segment& sg : a.segs) any_big = any_big || sg.count >= 1024;
+    if (any_big && a.precision == SL1M_PREC_FP32 && !a.beam_pair) {
+      std::vector<double> L(np), M(np);
+      if (sl1m_status e = d2h(L.data(), pr->l, np * sizeof(double), "read l")) return e;
+      if (sl1m_status e = d2h(M.data(), pr->m, np * sizeof(double), "read m")) return e;
+      for (int si = 0; si < static_cast<int>(a.segs.size()); ++si) {
+        std::string w;
+        if (!analyze_grid(a, si, L, M, w) && a.segs[si].count >= 1024) why = w;
+      }
+    }
+    if (!a.grid && pr->grid_mode == SL1M_GRID_REQUIRE)
       return set_error(SL1M_EINVAL, "grid evaluation required but " + why);
   }
   if (a.grid) {
+    std::vector<char> on(a.segs.size(), 0);
+    for (const GridSeg& g : a.gsegs) on[g.seg] = 1;
+    a.fd1.clear();
+    a.fg1.clear();
+    a.pd1.clear();
+    a.pg1.clear();
+    for (const Chunk& c : a.fd) if (!on[c.seg]) a.fd1.push_back(c);
+    for (const Chunk& c : a.fg) if (!on[c.seg]) a.fg1.push_back(c);
+    for (const Chunk& c : a.pd) if (!on[c.seg]) a.pd1.push_back(c);
+    for (const Chunk& c : a.pg) if (!on[c.seg]) a.pg1.push_back(c);
     a.grid_vtiles = static_cast<int>((nv + 2 * kBlock - 1) / (2 * kBlock));
-    const int64_t per_split = static_cast<int64_t>(a.grid_vtiles) * a.grid_ng;
-    int64_t split = (target_blocks + per_split - 1) / per_split;
-    split = std::max<int64_t>(1, std::min<int64_t>(split, (a.grid_na + 7) / 8));
-    const int ra = static_cast<int>((a.grid_na + split - 1) / split);
+    int64_t ng_total = 0;
+    for (const GridSeg& g : a.gsegs) ng_total += g.ng;
+    const int64_t per_split = static_cast<int64_t>(a.grid_vtiles) * ng_total;
     a.grid_fc.clear();
-    for (int g = 0; g < a.grid_ng; ++g)
-      for (int i0 = 0; i0 < a.grid_na; i0 += ra)
-        a.grid_fc.push_back(GridChunk{g, i0, std::min(a.grid_na, i0 + ra), 0});
-    const int64_t sets = static_cast<int64_t>(2) * a.grid_ng * a.grid_na;
-    a.grid_ablocks = static_cast<int>((sets + kBlock - 1) / kBlock);
+    for (GridSeg& g : a.gsegs) {
+      int64_t split = (target_blocks + per_split - 1) / per_split;
+      split = std::max<int64_t>(1, std::min<int64_t>(split, (g.na + 7) / 8));
+      const int ra = static_cast<int>((g.na + split - 1) / split);
+      g.fc0 = static_cast<int32_t>(a.grid_fc.size());
+      for (int gi = 0; gi < g.ng; ++gi)
+        for (int i0 = 0; i0 < g.na; i0 += ra)
+          a.grid_fc.push_back(GridChunk{gi, i0, std::min<int>(g.na, i0 + ra), 0});
+      g.nfc = static_cast<int32_t>(a.grid_fc.size()) - g.fc0;
+      const int64_t sets = static_cast<int64_t>(2) * g.ng * g.na;
+      g.ablocks = static_cast<int32_t>((sets + kBlock - 1) / kBlock);
+    }
+    a.grid_frows = static_cast<int>(a.grid_fc.size());
   }
 
   // ---- visibility chunks of the adjoint (shared by all of its kernels)
-  const int64_t ptiles = static_cast<int64_t>((a.grid ? a.grid_ablocks : a.pd.size()) + a.pg.size());
+  int64_t ptiles = static_cast<int64_t>(a.pd.size() + a.pg.size());
+  if (a.grid) {
+    ptiles = static_cast<int64_t>(a.pd1.size() + a.pg1.size());
+    for (const GridSeg& g : a.gsegs) ptiles += g.ablocks;
+  }
   if (nv > 0 && ptiles > 0) {
     const int64_t cap = a.grid ? 256 : 64;
     int64_t want =
@@ -317,7 +366,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
       rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
-      grid_mb, grid_nu, grid_slot, grid_rec, grid_fc, total;
+      grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -350,8 +399,9 @@ Layout layout(const Analysis& a) {
   L.visrecG = take(visrecG_bytes(rb) * nl * nv);
   L.rres = take(2 * rb * (1 + nl) * nv * nr);
   L.layerDs = take(2 * rb * nl * nv);
-  L.chunks = take(sizeof(Chunk) * (nfc + npt));
-  const size_t grid_rows = a.grid ? a.grid_fc.size() + a.fg.size() : 0;
+  L.chunks = take(sizeof(Chunk) * (nfc + npt + a.fd1.size() + a.fg1.size() + a.pd1.size() +
+                                   a.pg1.size()));
+  const size_t grid_rows = a.grid ? a.grid_fc.size() + a.fd1.size() + a.fg1.size() : 0;
   L.fpart = take(2 * rb * std::max(nfc * nr, grid_rows) * nv);
   L.apart = take(rb * static_cast<size_t>(a.n_achunks) * np * nr);
   L.xperm = take(rb * np * nr);
@@ -364,7 +414,8 @@ Layout layout(const Analysis& a) {
   const size_t cells = static_cast<size_t>(a.grid_cells);
   L.grid_la = take(8 * a.grid_la.size());
   L.grid_mb = take(8 * a.grid_mb.size());
-  L.grid_nu = take(8 * cells);
+  L.grid_c3 = take(8 * cells);
+  L.grid_c4 = take(8 * cells);
   L.grid_slot = take(4 * 4 * cells);
   L.grid_rec = take(sizeof(GridRec) * cells);
   L.grid_fc = take(sizeof(GridChunk) * a.grid_fc.size());
@@ -558,13 +609,15 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->adj_kchunk = a.kchunk;
     p->n_achunks = a.n_achunks;
     p->grid = a.grid;
-    p->grid_na = a.grid_na;
-    p->grid_nb = a.grid_nb;
-    p->grid_ng = a.grid_ng;
+    p->grid_segs = a.gsegs;
     p->grid_cells = a.grid_cells;
     p->grid_vtiles = a.grid_vtiles;
+    p->grid_frows = a.grid_frows;
     p->grid_fchunks = a.grid_fc;
-    p->grid_ablocks = a.grid_ablocks;
+    p->fd1 = a.fd1;
+    p->fg1 = a.fg1;
+    p->pd1 = a.pd1;
+    p->pg1 = a.pg1;
     for (const Segment& sg : a.segs) {
       if (sg.count == 0) continue;
       (sg.kind == SL1M_PIX_DELTA ? p->any_delta : p->any_gauss) = true;
@@ -591,6 +644,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->layerDs = p->n_layers ? w + L.layerDs : nullptr;
     p->d_fchunks = reinterpret_cast<Chunk*>(w + L.chunks);
     p->d_ptiles = p->d_fchunks + p->n_fchunks;
+    p->d_chunks1 = p->d_ptiles + a.pd.size() + a.pg.size();
     p->fpart = w + L.fpart;
     p->apart = w + L.apart;
     p->xperm = w + L.xperm;
@@ -603,9 +657,10 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     if (a.grid) {
       p->grid_la = reinterpret_cast<double*>(w + L.grid_la);
       p->grid_mb = reinterpret_cast<double*>(w + L.grid_mb);
-      p->grid_nu = reinterpret_cast<double*>(w + L.grid_nu);
+      p->grid_c3 = reinterpret_cast<double*>(w + L.grid_c3);
+      p->grid_c4 = reinterpret_cast<double*>(w + L.grid_c4);
       p->grid_slot = reinterpret_cast<int32_t*>(w + L.grid_slot);
-      p->grid_rec = reinterpret_cast<GridRec*>(w + L.grid_rec);
+      p->grid_rec = w + L.grid_rec;
       p->d_grid_fchunks = reinterpret_cast<GridChunk*>(w + L.grid_fc);
     }
 
@@ -624,6 +679,10 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     chunks.insert(chunks.end(), a.fg.begin(), a.fg.end());
     chunks.insert(chunks.end(), a.pd.begin(), a.pd.end());
     chunks.insert(chunks.end(), a.pg.begin(), a.pg.end());
+    chunks.insert(chunks.end(), a.fd1.begin(), a.fd1.end());
+    chunks.insert(chunks.end(), a.fg1.begin(), a.fg1.end());
+    chunks.insert(chunks.end(), a.pd1.begin(), a.pd1.end());
+    chunks.insert(chunks.end(), a.pg1.begin(), a.pg1.end());
     hipError_t e = hipSuccess;
     if (!perm.empty())
       e = hipMemcpyAsync(p->perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, st);
@@ -640,7 +699,8 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       };
       up(p->grid_la, a.grid_la.data(), 8 * a.grid_la.size());
       up(p->grid_mb, a.grid_mb.data(), 8 * a.grid_mb.size());
-      up(p->grid_nu, a.grid_nu.data(), 8 * a.grid_nu.size());
+      up(p->grid_c3, a.grid_c3.data(), 8 * a.grid_c3.size());
+      up(p->grid_c4, a.grid_c4.data(), 8 * a.grid_c4.size());
       up(p->grid_slot, a.grid_slot.data(), 4 * a.grid_slot.size());
       up(p->d_grid_fchunks, a.grid_fc.data(), sizeof(GridChunk) * a.grid_fc.size());
     }
@@ -701,9 +761,12 @@ sl1m_status sl1m_plan_query(const sl1m_plan* p, sl1m_plan_info* info) {
   r.n_vis = p->n_vis;
   r.precision = p->precision;
   r.max_rhs = p->max_rhs;
-  r.grid = p->grid ? 1 : 0;
-  r.grid_abs_l = p->grid_na;
-  r.grid_abs_m = p->grid_nb;
+  r.grid = static_cast<int32_t>(p->grid_segs.size());
+  for (const GridSeg& g : p->grid_segs)
+    if (g.kind == SL1M_PIX_DELTA) {
+      r.grid_abs_l = g.na;
+      r.grid_abs_m = g.nb;
+    }
   r.n_layers = p->n_layers;
   r.grid_positions = 4 * p->grid_cells;
   r.fwd_vpl = p->fwd_vpl;

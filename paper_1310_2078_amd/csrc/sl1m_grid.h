@@ -1,0 +1,428 @@
+// Grid evaluation of the operators (gfx950, float32 plans): device tiles
+// shared by the per-plan kernels (sl1m_grid.hip).
+//
+// Delta pixels, eq. (deltam) without gains:
+//   M_kj = exp(-2 pi i (u_k l_j + v_k m_j + w_k nu_j)),  nu_j = n_j - 1,
+// factorises into A_k(l) B_k(m) C_k(nu) with A = exp(-2 pi i u l),
+// B = exp(-2 pi i v m), C = exp(-2 pi i w nu).  nu depends on l^2 + m^2 only,
+// so the four positions (+-|l|, +-|m|) of a cell share C, and a sign flip of
+// l or m conjugates A or B.  With A = ac - i as, B = bc - i bs, C = cc - i cs
+// and x_s the amplitudes of the cell's sign slots (0 = (+,+), 1 = (-,+),
+// 2 = (+,-), 3 = (-,-)):
+//   forward  sum_s x_s M_s = C (ReS - i ImS'),
+//            ReS = ac bc e1 + as bs e2,  ImS' = ac bs e3 + as bc e4
+//            (e1..e4 are the sign combinations of GridRec);
+//   adjoint  z = conj(C) r, G1 = sum bc ac z1, G2 = sum bs as z1,
+//            G3 = sum bs ac z2, G4 = sum bc as z2;
+//            g0 = G1-G2-G3-G4, g1 = G1+G2-G3+G4, g2 = G1+G2+G3-G4, g3 = G1-G2+G3+G4.
+//
+// Gaussian pixels, eq. (samlm4)/(samlm5) in the completed-square form of the
+// direct kernels (entry = e exp(2 pi i theta) times D (1 + i s) per visibility
+// and layer, theta = A l + B m + C r^2 + NW kappa + E0 with A = -D u,
+// B = -D v):  the taper exp(c (u - w l)^2) exp(c (v - w m)^2) separates too, but
+// is not even in l or m, so per (visibility, |l|) the pair
+//   a+ = T(u - w|l|) exp(2 pi i A|l|),  a- = T(u + w|l|) exp(-2 pi i A|l|)
+// and per (visibility, |m|) the pair b+, b- are formed, and per cell
+// gamma = exp(2 pi i (C r^2 + NW kappa + E0)):
+//   forward  sum_s x_s M_s = gamma (b+ (x0 a+ + x1 a-) + b- (x2 a+ + x3 a-));
+//   adjoint  Z = conj(gamma) r', Y+- = conj(b+-) Z,
+//            g0 = Re conj(a+) Y+, g1 = Re conj(a-) Y+, g2 = Re conj(a+) Y-,
+//            g3 = Re conj(a-) Y-.
+//
+// Phases use the same exact reduction as the direct kernels (FP64 FMAs from
+// kMagic, low 23 mantissa bits into 1.0f).
+#pragma once
+
+#include "sl1m_device.h"
+
+namespace sl1m {
+namespace dev {
+
+constexpr int kGridVPL = 2;    // forward visibilities per lane
+constexpr int kGridSegIA = 8;  // forward: |l| values per inner FP32 sum
+
+// ---------------------------------------------------------------------------
+// forward tiles: lanes own kGridVPL visibilities of tile `vtile` and sweep the
+// chunk's cells (one |m| group of kGridNB values times an |l| range) in a
+// wavefront-uniform order; cell records are read through the scalar unit.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void grid_fwd_delta_tile(
+    const GridRec* __restrict__ rec, const double* __restrict__ la,
+    const double* __restrict__ mb, const GridChunk& ch, int na, const double* __restrict__ vu,
+    const double* __restrict__ vv, const double* __restrict__ vw, int64_t vtile, int64_t n_vis,
+    float2* __restrict__ out) {
+  const ConstPtr<GridRec> crec = as_const(rec);
+  const ConstPtr<double> cla = as_const(la);
+  const ConstPtr<double> cmb = as_const(mb);
+  const int g = ch.g;
+  const int64_t kbase = vtile * (kBlock * kGridVPL) + threadIdx.x;
+  const double origin = kMagic;
+  double u[kGridVPL], w[kGridVPL];
+  float bc[kGridNB][kGridVPL], bs[kGridNB][kGridVPL];
+  float ore[kGridVPL], oim[kGridVPL];
+#pragma unroll
+  for (int i = 0; i < kGridVPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    const bool ok = k < n_vis;
+    u[i] = ok ? vu[k] : 0.0;
+    const double v = ok ? vv[k] : 0.0;
+    w[i] = ok ? vw[k] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kGridNB; ++b) phasor(fma(v, cmb[g * kGridNB + b], origin), bc[b][i], bs[b][i]);
+    ore[i] = oim[i] = 0.0f;
+  }
+  for (int s0 = ch.ia0; s0 < ch.ia1; s0 += kGridSegIA) {
+    const int s1 = s0 + kGridSegIA < ch.ia1 ? s0 + kGridSegIA : ch.ia1;
+    float re[kGridVPL], imn[kGridVPL];
+#pragma unroll
+    for (int i = 0; i < kGridVPL; ++i) re[i] = imn[i] = 0.0f;
+    for (int ia = s0; ia < s1; ++ia) {
+      const double l = cla[ia];
+      float ac[kGridVPL], as[kGridVPL];
+#pragma unroll
+      for (int i = 0; i < kGridVPL; ++i) phasor(fma(u[i], l, origin), ac[i], as[i]);
+      const int q0 = (g * na + ia) * kGridNB;
+#pragma unroll
+      for (int b = 0; b < kGridNB; ++b) {
+        if (crec[q0 + b].empty) continue;  // wavefront-uniform
+        const double nu = crec[q0 + b].nu;
+        const float e1 = crec[q0 + b].e1, e2 = crec[q0 + b].e2;
+        const float e3 = crec[q0 + b].e3, e4 = crec[q0 + b].e4;
+#pragma unroll
+        for (int i = 0; i < kGridVPL; ++i) {
+          float cc, cs;
+          phasor(fma(w[i], nu, origin), cc, cs);
+          const float rs = fmaf(ac[i] * bc[b][i], e1, as[i] * bs[b][i] * e2);
+          const float is = fmaf(ac[i] * bs[b][i], e3, as[i] * bc[b][i] * e4);
+          re[i] = fmaf(cc, rs, re[i]);
+          re[i] = fmaf(-cs, is, re[i]);
+          imn[i] = fmaf(cc, is, imn[i]);
+          imn[i] = fmaf(cs, rs, imn[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kGridVPL; ++i) {
+      ore[i] += re[i];
+      oim[i] += imn[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kGridVPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    if (k < n_vis) out[k] = make_float2(ore[i], -oim[i]);
+  }
+}
+
+// `vrec` and `Ds` are the layer's per-visibility records and (D, s) pairs.
+__device__ __forceinline__ void grid_fwd_gauss_tile(
+    const GridRecG* __restrict__ rec, const double* __restrict__ la,
+    const double* __restrict__ mb, const GridChunk& ch, int na,
+    const VisRecG<float>* __restrict__ vrec, const float* __restrict__ Ds, int64_t vtile,
+    int64_t n_vis, float2* __restrict__ out) {
+  const ConstPtr<GridRecG> crec = as_const(rec);
+  const ConstPtr<double> cla = as_const(la);
+  const ConstPtr<double> cmb = as_const(mb);
+  const int g = ch.g;
+  const int64_t kbase = vtile * (kBlock * kGridVPL) + threadIdx.x;
+  const double origin = kMagic;
+  double A[kGridVPL], C[kGridVPL], NW[kGridVPL], E0[kGridVPL];
+  float ur[kGridVPL], wr[kGridVPL], c1[kGridVPL];
+  float bpr[kGridNB][kGridVPL], bpi[kGridNB][kGridVPL];
+  float bmr[kGridNB][kGridVPL], bmi[kGridNB][kGridVPL];
+  float ore[kGridVPL], oim[kGridVPL];
+#pragma unroll
+  for (int i = 0; i < kGridVPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    const bool ok = k < n_vis;
+    const int64_t kk = ok ? k : 0;
+    A[i] = vrec[kk].A;
+    C[i] = vrec[kk].C;
+    NW[i] = vrec[kk].NW;
+    E0[i] = vrec[kk].E0;
+    ur[i] = vrec[kk].ur;
+    wr[i] = vrec[kk].wr;
+    c1[i] = vrec[kk].c1;
+    const double B = vrec[kk].B;
+    const float vr = vrec[kk].vr;
+#pragma unroll
+    for (int b = 0; b < kGridNB; ++b) {
+      const double m = cmb[g * kGridNB + b];
+      float cb, sb;
+      phasor(fma(B, m, origin), cb, sb);
+      const float mr = static_cast<float>(m);
+      const float dp = fmaf(-wr[i], mr, vr), dm = fmaf(wr[i], mr, vr);
+      const float tp = pow2(c1[i] * (dp * dp)), tm = pow2(c1[i] * (dm * dm));
+      bpr[b][i] = tp * cb;
+      bpi[b][i] = tp * sb;
+      bmr[b][i] = tm * cb;
+      bmi[b][i] = -tm * sb;
+    }
+    ore[i] = oim[i] = 0.0f;
+  }
+  for (int s0 = ch.ia0; s0 < ch.ia1; s0 += kGridSegIA) {
+    const int s1 = s0 + kGridSegIA < ch.ia1 ? s0 + kGridSegIA : ch.ia1;
+    float re[kGridVPL], im[kGridVPL];
+#pragma unroll
+    for (int i = 0; i < kGridVPL; ++i) re[i] = im[i] = 0.0f;
+    for (int ia = s0; ia < s1; ++ia) {
+      const double l = cla[ia];
+      const float lr = static_cast<float>(l);
+      float apr[kGridVPL], api[kGridVPL], amr[kGridVPL], ami[kGridVPL];
+#pragma unroll
+      for (int i = 0; i < kGridVPL; ++i) {
+        float ca, sa;
+        phasor(fma(A[i], l, origin), ca, sa);
+        const float dp = fmaf(-wr[i], lr, ur[i]), dm = fmaf(wr[i], lr, ur[i]);
+        const float tp = pow2(c1[i] * (dp * dp)), tm = pow2(c1[i] * (dm * dm));
+        apr[i] = tp * ca;
+        api[i] = tp * sa;
+        amr[i] = tm * ca;
+        ami[i] = -tm * sa;
+      }
+      const int q0 = (g * na + ia) * kGridNB;
+#pragma unroll
+      for (int b = 0; b < kGridNB; ++b) {
+        const double r2 = crec[q0 + b].r2, kap = crec[q0 + b].kappa;
+        const float x0 = crec[q0 + b].x[0], x1 = crec[q0 + b].x[1];
+        const float x2 = crec[q0 + b].x[2], x3 = crec[q0 + b].x[3];
+#pragma unroll
+        for (int i = 0; i < kGridVPL; ++i) {
+          float cg, sg;
+          phasor(fma(C[i], r2, fma(NW[i], kap, E0[i])), cg, sg);
+          const float Ur = fmaf(x0, apr[i], x1 * amr[i]), Ui = fmaf(x0, api[i], x1 * ami[i]);
+          const float Wr = fmaf(x2, apr[i], x3 * amr[i]), Wi = fmaf(x2, api[i], x3 * ami[i]);
+          const float Sr = fmaf(bpr[b][i], Ur, fmaf(-bpi[b][i], Ui, fmaf(bmr[b][i], Wr, -bmi[b][i] * Wi)));
+          const float Si = fmaf(bpr[b][i], Ui, fmaf(bpi[b][i], Ur, fmaf(bmr[b][i], Wi, bmi[b][i] * Wr)));
+          re[i] = fmaf(cg, Sr, re[i]);
+          re[i] = fmaf(-sg, Si, re[i]);
+          im[i] = fmaf(cg, Si, im[i]);
+          im[i] = fmaf(sg, Sr, im[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kGridVPL; ++i) {
+      ore[i] += re[i];
+      oim[i] += im[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kGridVPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    if (k < n_vis) {
+      const float D = Ds[2 * k], Dsv = D * Ds[2 * k + 1];
+      out[k] = make_float2(D * ore[i] - Dsv * oim[i], Dsv * ore[i] + D * oim[i]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint tiles: block `blk` of lane-sets t = g4 * na + ia, each owning the
+// kGridNBA cells (ia, g4 * kGridNBA + bi) and their 16 sign slots, against
+// visibility chunk kc.  Visibility records and residuals are wavefront-uniform
+// scalar loads; the per-|m| factors of the block's |m| groups are formed once
+// per batch of visibilities by the whole block and read from LDS.  Writes
+// Re sum_k conj(M_kj) r_k into out_row[j] for every pixel j of the cells.
+// Every thread of the block must call a tile (it synchronises the block).
+// ---------------------------------------------------------------------------
+
+struct LaneSet {
+  bool active;
+  int gl0, n_gl, gl, ia, qbase;
+};
+
+__device__ __forceinline__ LaneSet lane_set(int64_t blk, int na, int ng4) {
+  LaneSet r;
+  const int64_t n_sets = static_cast<int64_t>(ng4) * na;
+  const int64_t t0 = blk * kBlock;
+  const int64_t t = t0 + threadIdx.x;
+  r.active = t < n_sets;
+  r.gl0 = static_cast<int>(t0 / na);
+  const int64_t tlast = t0 + kBlock - 1 < n_sets ? t0 + kBlock - 1 : n_sets - 1;
+  r.n_gl = static_cast<int>(tlast / na) - r.gl0 + 1;
+  if (r.n_gl > kGridMaxGL) r.n_gl = kGridMaxGL;  // plans keep na >= kGridMinA: never binds
+  const int g4 = r.active ? static_cast<int>(t / na) : r.gl0;
+  r.ia = r.active ? static_cast<int>(t % na) : 0;
+  r.gl = g4 - r.gl0;
+  r.qbase = ((g4 / 2) * na + r.ia) * kGridNB + (g4 % 2) * kGridNBA;
+  return r;
+}
+
+__device__ __forceinline__ void grid_write(const LaneSet& ls, const int32_t* __restrict__ slot,
+                                           const float (&gs)[kGridNBA][4],
+                                           float* __restrict__ out_row) {
+  if (!ls.active) return;
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) {
+    const int64_t q = ls.qbase + bi;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int32_t j = slot[4 * q + s];
+      if (j >= 0) out_row[j] = gs[bi][s];
+    }
+  }
+}
+
+__device__ __forceinline__ void grid_adj_delta_tile(
+    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ vv, const double* __restrict__ la, const double* __restrict__ mb,
+    const double* __restrict__ nu, const int32_t* __restrict__ slot, int na, int ng4,
+    int64_t blk, int64_t kc, int64_t kchunk, int64_t n_vis, float* __restrict__ out_row,
+    float2 (*bsh)[kGridMaxGL][kGridNBA]) {
+  const LaneSet ls = lane_set(blk, na, ng4);
+  const double l = la[ls.ia];
+  double nuv[kGridNBA];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) nuv[bi] = ls.active ? nu[ls.qbase + bi] : 0.0;
+  const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
+  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
+  const double origin = kMagic;
+  const int k0 = static_cast<int>(kc * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  float o1[kGridNBA], o2[kGridNBA], o3[kGridNBA], o4[kGridNBA];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) o1[bi] = o2[bi] = o3[bi] = o4[bi] = 0.0f;
+  const int fill = kGridKB * ls.n_gl * kGridNBA;
+  for (int kb = k0; kb < k1; kb += kGridKB) {
+    __syncthreads();  // the previous batch's reads are done
+    for (int e = threadIdx.x; e < fill; e += kBlock) {
+      const int kk = e / (ls.n_gl * kGridNBA);
+      const int rem = e - kk * (ls.n_gl * kGridNBA);
+      const int gg = rem / kGridNBA, bi = rem - gg * kGridNBA;
+      const int k = kb + kk;
+      float c = 0.0f, s = 0.0f;
+      if (k < k1) phasor(fma(vv[k], mb[(ls.gl0 + gg) * kGridNBA + bi], origin), c, s);
+      bsh[kk][gg][bi] = make_float2(c, s);
+    }
+    __syncthreads();
+    const int ke = kb + kGridKB < k1 ? kb + kGridKB : k1;
+    float G1[kGridNBA], G2[kGridNBA], G3[kGridNBA], G4[kGridNBA];
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi) G1[bi] = G2[bi] = G3[bi] = G4[bi] = 0.0f;
+    for (int k = kb; k < ke; ++k) {
+      const double u = cvrec[k].u, w = cvrec[k].w;
+      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
+      float ac, as;
+      phasor(fma(u, l, origin), ac, as);
+      const float2* bp = &bsh[k - kb][ls.gl][0];
+#pragma unroll
+      for (int bi = 0; bi < kGridNBA; ++bi) {
+        const float2 bb = bp[bi];
+        float cc, cs;
+        phasor(fma(w, nuv[bi], origin), cc, cs);
+        const float z1 = fmaf(cc, rr, -cs * ri);
+        const float z2 = fmaf(cc, ri, cs * rr);
+        G1[bi] = fmaf(bb.x, ac * z1, G1[bi]);
+        G2[bi] = fmaf(bb.y, as * z1, G2[bi]);
+        G3[bi] = fmaf(bb.y, ac * z2, G3[bi]);
+        G4[bi] = fmaf(bb.x, as * z2, G4[bi]);
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi) {
+      o1[bi] += G1[bi];
+      o2[bi] += G2[bi];
+      o3[bi] += G3[bi];
+      o4[bi] += G4[bi];
+    }
+  }
+  float gs[kGridNBA][4];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) {
+    gs[bi][0] = o1[bi] - o2[bi] - o3[bi] - o4[bi];
+    gs[bi][1] = o1[bi] + o2[bi] - o3[bi] + o4[bi];
+    gs[bi][2] = o1[bi] + o2[bi] + o3[bi] - o4[bi];
+    gs[bi][3] = o1[bi] - o2[bi] + o3[bi] + o4[bi];
+  }
+  grid_write(ls, slot, gs, out_row);
+}
+
+// `vrec` and `rres` are the layer's records and residuals (D (1 - i s) conj(G) r).
+__device__ __forceinline__ void grid_adj_gauss_tile(
+    const VisRecG<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ r2c,
+    const double* __restrict__ kapc, const int32_t* __restrict__ slot, int na, int ng4,
+    int64_t blk, int64_t kc, int64_t kchunk, int64_t n_vis, float* __restrict__ out_row,
+    float4 (*bsh)[kGridMaxGL][kGridNBA]) {
+  const LaneSet ls = lane_set(blk, na, ng4);
+  const double l = la[ls.ia];
+  const float lr = static_cast<float>(l);
+  double r2[kGridNBA], kap[kGridNBA];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) {
+    r2[bi] = ls.active ? r2c[ls.qbase + bi] : 0.0;
+    kap[bi] = ls.active ? kapc[ls.qbase + bi] : 0.0;
+  }
+  const ConstPtr<VisRecG<float>> crec = as_const(vrec);
+  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
+  const double origin = kMagic;
+  const int k0 = static_cast<int>(kc * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  float og[kGridNBA][4];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) og[bi][s] = 0.0f;
+  const int fill = kGridKBG * ls.n_gl * kGridNBA;
+  for (int kb = k0; kb < k1; kb += kGridKBG) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < fill; e += kBlock) {
+      const int kk = e / (ls.n_gl * kGridNBA);
+      const int rem = e - kk * (ls.n_gl * kGridNBA);
+      const int gg = rem / kGridNBA, bi = rem - gg * kGridNBA;
+      const int k = kb + kk;
+      float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (k < k1) {
+        const double m = mb[(ls.gl0 + gg) * kGridNBA + bi];
+        float cb, sb;
+        phasor(fma(vrec[k].B, m, origin), cb, sb);
+        const float mr = static_cast<float>(m), w = vrec[k].wr, v = vrec[k].vr, c = vrec[k].c1;
+        const float dp = fmaf(-w, mr, v), dm = fmaf(w, mr, v);
+        const float tp = pow2(c * (dp * dp)), tm = pow2(c * (dm * dm));
+        val = make_float4(tp * cb, tp * sb, tm * cb, -tm * sb);  // b+, b-
+      }
+      bsh[kk][gg][bi] = val;
+    }
+    __syncthreads();
+    const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
+    float g[kGridNBA][4];
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) g[bi][s] = 0.0f;
+    for (int k = kb; k < ke; ++k) {
+      const double A = crec[k].A, C = crec[k].C, NW = crec[k].NW, E0 = crec[k].E0;
+      const float ur = crec[k].ur, wr = crec[k].wr, c1 = crec[k].c1;
+      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
+      float ca, sa;
+      phasor(fma(A, l, origin), ca, sa);
+      const float dp = fmaf(-wr, lr, ur), dm = fmaf(wr, lr, ur);
+      const float tp = pow2(c1 * (dp * dp)), tm = pow2(c1 * (dm * dm));
+      const float apr = tp * ca, api = tp * sa, amr = tm * ca, ami = -tm * sa;
+      const float4* bp = &bsh[k - kb][ls.gl][0];
+#pragma unroll
+      for (int bi = 0; bi < kGridNBA; ++bi) {
+        const float4 bb = bp[bi];
+        float cg, sg;
+        phasor(fma(C, r2[bi], fma(NW, kap[bi], E0)), cg, sg);
+        const float zr = fmaf(cg, rr, sg * ri), zi = fmaf(cg, ri, -sg * rr);
+        const float ypr = fmaf(bb.x, zr, bb.y * zi), ypi = fmaf(bb.x, zi, -bb.y * zr);
+        const float ymr = fmaf(bb.z, zr, bb.w * zi), ymi = fmaf(bb.z, zi, -bb.w * zr);
+        g[bi][0] = fmaf(apr, ypr, fmaf(api, ypi, g[bi][0]));
+        g[bi][1] = fmaf(amr, ypr, fmaf(ami, ypi, g[bi][1]));
+        g[bi][2] = fmaf(apr, ymr, fmaf(api, ymi, g[bi][2]));
+        g[bi][3] = fmaf(amr, ymr, fmaf(ami, ymi, g[bi][3]));
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) og[bi][s] += g[bi][s];
+  }
+  grid_write(ls, slot, og, out_row);
+}
+
+}  // namespace dev
+}  // namespace sl1m

@@ -63,19 +63,23 @@ struct Chunk {           // a contiguous pixel range inside one segment
   int32_t seg, layer;
 };
 
-// Grid evaluation of the delta pixels.  A grid cell (ia, ib) stands for the
-// four positions (+-|l|_ia, +-|m|_ib); cells are numbered
+// Grid evaluation.  A segment of pixels (the delta pixels, or one Gaussian
+// (kind, sigma) layer) whose positions lie on a product set of |l| and |m|
+// values symmetric under l -> -l and m -> -m is evaluated per grid cell: cell
+// (ia, ib) stands for the four positions (+-|l|_ia, +-|m|_ib).  Cells are
+// numbered
 //   q = ((ib / kGridNB) * n_a + ia) * kGridNB + ib % kGridNB
 // so the kGridNB cells of one |l| value and one group of |m| values are
 // adjacent.  Sign slots: 0 = (+l, +m), 1 = (-l, +m), 2 = (+l, -m), 3 = (-l, -m);
 // a zero coordinate takes the + slot.
 constexpr int kGridNB = 8;       // |m| values per forward group
 constexpr int kGridNBA = 4;      // |m| values per adjoint lane
-constexpr int kGridKB = 32;      // visibilities per adjoint LDS batch
+constexpr int kGridKB = 32;      // visibilities per adjoint LDS batch (delta)
+constexpr int kGridKBG = 16;     // visibilities per adjoint LDS batch (Gaussian)
 constexpr int kGridMaxGL = 18;   // |m| groups one adjoint block touches (n_a >= 16)
 constexpr int kGridMinA = 16;
 
-// Per-call forward record of one cell: n - 1 of the cell and the sign
+// Per-call forward record of one delta cell: n - 1 of the cell and the sign
 // combinations of the four amplitudes x_s (x times 1/n and beam factor):
 //   e1 = x0 + x1 + x2 + x3, e2 = x1 + x2 - x0 - x3,
 //   e3 = x0 + x1 - x2 - x3, e4 = x0 - x1 + x2 - x3;
@@ -86,8 +90,30 @@ struct GridRec {
   int32_t empty, pad;
 };
 
+// Per-call forward record of one Gaussian cell: l^2 + m^2, kappa = n - 1 +
+// r^2/2 (0 for paraxial pixels) and the amplitudes of the four sign slots.
+struct GridRecG {
+  double r2, kappa;
+  float x[4];
+};
+static_assert(sizeof(GridRec) == sizeof(GridRecG), "grid records share one buffer");
+
 struct GridChunk {       // forward: one |m| group times an |l| range
   int32_t g, ia0, ia1, pad;
+};
+
+// One segment on the grid path and where its tables live in the plan's
+// concatenated grid arrays.
+struct GridSeg {
+  int32_t seg;           // index into the plan's segments
+  int32_t kind;          // sl1m_pixel_kind
+  int32_t layer;         // Gaussian layer (-1 for delta)
+  int32_t na, nb, ng;    // distinct |l|, distinct |m|, |m| groups of kGridNB
+  int64_t cells;         // ng * kGridNB * na
+  int64_t la_off, mb_off, cell_off;
+  int32_t fc0, nfc;      // forward chunks [fc0, fc0 + nfc) = partial rows
+  int32_t ablocks;       // adjoint blocks of kBlock lane-sets
+  int32_t pad;
 };
 
 }  // namespace sl1m
@@ -116,20 +142,23 @@ struct sl1m_plan {
   int64_t adj_kchunk = 0;     // visibilities per chunk
   int n_achunks = 0;
 
-  // grid evaluation of the delta pixels (single right-hand side, FP32)
+  // grid evaluation (single right-hand side, FP32): segments on the grid path
+  // and the direct chunks of the other segments
   bool grid = false;
-  int grid_na = 0, grid_nb = 0;   // distinct |l|, |m| values
-  int grid_ng = 0;                // |m| groups of kGridNB
-  int64_t grid_cells = 0;         // grid_ng * kGridNB * grid_na
+  std::vector<sl1m::GridSeg> grid_segs;
+  int64_t grid_cells = 0;         // all grid segments
   int grid_vtiles = 0;            // forward visibility tiles (2 per lane)
+  int grid_frows = 0;             // forward partial rows of the grid segments
   std::vector<sl1m::GridChunk> grid_fchunks;
-  int grid_ablocks = 0;           // adjoint blocks per visibility chunk
-  double* grid_la = nullptr;      // [grid_na] |l|
-  double* grid_mb = nullptr;      // [grid_ng * kGridNB] |m| (0 padded)
-  double* grid_nu = nullptr;      // [grid_cells] n - 1
-  int32_t* grid_slot = nullptr;   // [4 * grid_cells] permuted pixel index or -1
-  sl1m::GridRec* grid_rec = nullptr;        // [grid_cells] per-call records
+  std::vector<sl1m::Chunk> fd1, fg1, pd1, pg1;
+  double* grid_la = nullptr;      // |l| values of every grid segment
+  double* grid_mb = nullptr;      // |m| values (0 padded to groups of kGridNB)
+  double* grid_c3 = nullptr;      // per cell: n - 1 (delta) or l^2 + m^2 (Gaussian)
+  double* grid_c4 = nullptr;      // per cell: kappa (wide-field Gaussian) or 0
+  int32_t* grid_slot = nullptr;   // [4 * cells] permuted pixel index or -1
+  void* grid_rec = nullptr;       // [cells] per-call GridRec / GridRecG records
   sl1m::GridChunk* d_grid_fchunks = nullptr;
+  sl1m::Chunk* d_chunks1 = nullptr;         // fd1 | fg1 | pd1 | pg1
 
   // device buffers (carved from the workspace)
   char* ws = nullptr;
@@ -225,8 +254,8 @@ hipError_t launch_copy_real(sl1m_plan* p, const void* src, void* dst, int64_t n,
 hipError_t launch_dot_norm(sl1m_plan* p, const void* a, const void* b, hipStream_t st);
 hipError_t launch_objective_terms(sl1m_plan* p, const void* res, const void* img,
                                   hipStream_t st);
-// grid evaluation (sl1m_grid.hip): delta pixels only, rows [0, grid_fchunks)
-// of the forward partials and every delta pixel of the adjoint partials.
+// grid evaluation (sl1m_grid.hip): the grid segments' forward partial rows
+// [0, grid_frows) and every pixel of the grid segments in the adjoint partials.
 hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st);
 hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st);
 hipError_t launch_domain_check(sl1m_plan* p, const double* l, const double* m,

@@ -142,18 +142,40 @@ __global__ void k_fwd_reduce(const C2<R>* __restrict__ part, int n_rows, int64_t
   }
 }
 
-// g[r][perm[j]] (or g[r][j]) = scale_j * sum_c part[r][c][j].
+// Split-K row sums of the adjoint partials for the 64 pixels of block
+// blockIdx.x: wavefront w of the 4 adds rows c = w, w + 4, ... of right-hand
+// side r; the four partial sums meet in LDS and are combined in a fixed order
+// by wavefront 0, which gets the result (other wavefronts get 0).  Every
+// thread of the block must call it (it synchronises the block).
+constexpr int kRowPix = 64;
+static_assert(kBlock == 4 * kRowPix, "row_sum uses four wavefronts of kRowPix lanes");
 template <typename R>
-__global__ void k_adj_reduce(const R* __restrict__ part, int n_rows, int64_t n_pix, int nr,
-                             const R* __restrict__ scale, const int32_t* __restrict__ perm,
-                             R* __restrict__ out) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n_pix) return;
-  const int64_t dst = perm ? perm[j] : j;
+__device__ __forceinline__ R row_sum(const R* __restrict__ part, int n_rows, int64_t n_pix, int r,
+                                     int64_t j, R (*sh)[kRowPix]) {
+  const int wv = threadIdx.x / kRowPix, ln = threadIdx.x % kRowPix;
+  R g = R(0);
+  if (j < n_pix)
+    for (int c = wv; c < n_rows; c += 4) g += part[static_cast<int64_t>(r * n_rows + c) * n_pix + j];
+  sh[wv][ln] = g;
+  __syncthreads();
+  const R t = wv == 0 ? (sh[0][ln] + sh[1][ln]) + (sh[2][ln] + sh[3][ln]) : R(0);
+  __syncthreads();
+  return t;
+}
+
+// g[r][perm[j]] (or g[r][j]) = scale_j * sum_c part[r][c][j]; blocks of
+// kBlock threads cover kRowPix pixels.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_adj_reduce(const R* __restrict__ part, int n_rows,
+                                                       int64_t n_pix, int nr,
+                                                       const R* __restrict__ scale,
+                                                       const int32_t* __restrict__ perm,
+                                                       R* __restrict__ out) {
+  __shared__ R sh[4][kRowPix];
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kRowPix + threadIdx.x % kRowPix;
   for (int r = 0; r < nr; ++r) {
-    R g = R(0);
-    for (int c = 0; c < n_rows; ++c) g += part[static_cast<int64_t>(r * n_rows + c) * n_pix + j];
-    out[r * n_pix + dst] = g * scale[j];
+    const R g = row_sum<R>(part, n_rows, n_pix, r, j, sh);
+    if (threadIdx.x < kRowPix && j < n_pix) out[r * n_pix + (perm ? perm[j] : j)] = g * scale[j];
   }
 }
 
@@ -166,17 +188,19 @@ __global__ void k_adj_reduce(const R* __restrict__ part, int n_rows, int64_t n_p
 // A non-finite z (overflow of a diverging iteration) would be mapped to 0 by
 // the threshold; it is recorded in *flag instead so the solve can report it.
 template <typename R>
-__global__ void k_fista(const R* __restrict__ part, int n_rows, int64_t n_pix,
-                        const R* __restrict__ scale, R* __restrict__ y, R* __restrict__ img,
-                        const double* __restrict__ scal, int* __restrict__ flag) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n_pix) return;
+__global__ __launch_bounds__(kBlock) void k_fista(const R* __restrict__ part, int n_rows,
+                                                  int64_t n_pix, const R* __restrict__ scale,
+                                                  R* __restrict__ y, R* __restrict__ img,
+                                                  const double* __restrict__ scal,
+                                                  int* __restrict__ flag) {
+  __shared__ R sh[4][kRowPix];
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kRowPix + threadIdx.x % kRowPix;
+  R g = row_sum<R>(part, n_rows, n_pix, 0, j, sh);
+  if (threadIdx.x >= kRowPix || j >= n_pix) return;
   const double t = scal[0];
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
   const R beta = static_cast<R>((t - 1.0) / tn);
   const R inv_L = static_cast<R>(scal[1]), thr = static_cast<R>(scal[2]);
-  R g = R(0);
-  for (int c = 0; c < n_rows; ++c) g += part[static_cast<int64_t>(c) * n_pix + j];
   g *= scale[j];
   const R z = y[j] - g * inv_L;
   if (!isfinite(z)) atomicOr(flag, 1);
@@ -471,53 +495,56 @@ __global__ void k_domain(const double* __restrict__ l, const double* __restrict_
 
 inline unsigned grid1(int64_t n, int b = kBlock) { return static_cast<unsigned>((n + b - 1) / b); }
 
-// Direct-evaluation forward launches.  With `grid` the delta chunks are left
-// to the grid kernels, which own rows [0, grid_fchunks); Gaussian rows follow.
+// Direct-evaluation forward launches.  With `grid` only the segments that are
+// not on the grid path are evaluated here (chunk lists fd1, fg1), into the
+// partial rows after the grid segments' rows.
 template <typename R, int VPL, bool BEAM, int NR>
 hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st, bool grid = false) {
   const int64_t vt = (p->n_vis + kBlock * VPL - 1) / (kBlock * VPL);
   C2<R>* part = static_cast<C2<R>*>(p->fpart);
-  const int nd = grid ? static_cast<int>(p->grid_fchunks.size())
-                      : static_cast<int>(p->fchunks_delta.size());
-  const int ng = static_cast<int>(p->fchunks_gauss.size());
-  const int rows = nd + ng;
-  if (nd > 0 && !grid) {
+  const Chunk* dch = grid ? p->d_chunks1 : p->d_fchunks;
+  const int nd = static_cast<int>(grid ? p->fd1.size() : p->fchunks_delta.size());
+  const int ng = static_cast<int>(grid ? p->fg1.size() : p->fchunks_gauss.size());
+  const int row0 = grid ? p->grid_frows : 0;
+  const int rows = row0 + nd + ng;
+  if (nd > 0) {
     hipLaunchKernelGGL((k_fwd_delta<R, VPL, BEAM, NR>), dim3(static_cast<unsigned>(vt), nd),
                        dim3(kBlock), 0, st, static_cast<const PixRec<R>*>(p->pixrec),
                        static_cast<const R*>(xp), p->n_pix, p->vu, p->vv, p->vw,
-                       static_cast<const R*>(p->vbeta), p->d_fchunks, p->n_vis, part, 0, rows);
+                       static_cast<const R*>(p->vbeta), dch, p->n_vis, part, row0, rows);
   }
   if (ng > 0) {
     hipLaunchKernelGGL((k_fwd_gauss<R, VPL, BEAM, NR>), dim3(static_cast<unsigned>(vt), ng),
                        dim3(kBlock), 0, st, static_cast<const PixRec<R>*>(p->pixrec),
                        static_cast<const R*>(xp), p->n_pix, p->vu, p->vv, p->vw,
-                       static_cast<const R*>(p->vbeta),
-                       p->d_fchunks + p->fchunks_delta.size(), p->n_vis, part, nd, rows);
+                       static_cast<const R*>(p->vbeta), dch + nd, p->n_vis, part, row0 + nd,
+                       rows);
   }
   return hipGetLastError();
 }
 
-// Direct-evaluation adjoint launches; with `grid` the delta tiles are left to
-// the grid kernel.
+// Direct-evaluation adjoint launches; with `grid` only the tiles of segments
+// that are not on the grid path (pd1, pg1).
 template <typename R, int PPL, bool BEAM, int NR>
 hipError_t adj_launch_t(sl1m_plan* p, hipStream_t st, bool grid = false) {
   R* part = static_cast<R*>(p->apart);
-  const int nd = static_cast<int>(p->ptiles_delta.size());
-  const int ng = static_cast<int>(p->ptiles_gauss.size());
+  const Chunk* dt = grid ? p->d_chunks1 + p->fd1.size() + p->fg1.size() : p->d_ptiles;
+  const int nd = static_cast<int>(grid ? p->pd1.size() : p->ptiles_delta.size());
+  const int ng = static_cast<int>(grid ? p->pg1.size() : p->ptiles_gauss.size());
   const int sub = p->adj_ppl / PPL;  // blocks per plan tile
   const C2<R>* rres = static_cast<const C2<R>*>(p->rres);
-  if (nd > 0 && !grid) {
+  if (nd > 0) {
     hipLaunchKernelGGL((k_adj_delta<R, PPL, BEAM, NR>), dim3(nd * sub, p->n_achunks), dim3(kBlock),
                        0, st, static_cast<const VisRecD<R>*>(p->visrecD), rres,
                        static_cast<const R*>(p->vbeta), p->pl, p->pm, p->pc3,
-                       static_cast<const R*>(p->pr2), p->d_ptiles, sub, p->adj_kchunk, p->n_vis,
+                       static_cast<const R*>(p->pr2), dt, sub, p->adj_kchunk, p->n_vis,
                        p->n_pix, part);
   }
   if (ng > 0) {
     hipLaunchKernelGGL((k_adj_gauss<R, PPL, BEAM, NR>), dim3(ng * sub, p->n_achunks), dim3(kBlock),
                        0, st, static_cast<const VisRecG<R>*>(p->visrecG), rres,
                        static_cast<const R*>(p->vbeta), p->pl, p->pm, p->pc3, p->pc4,
-                       static_cast<const R*>(p->pr2), p->d_ptiles + nd, sub, p->adj_kchunk,
+                       static_cast<const R*>(p->pr2), dt + nd, sub, p->adj_kchunk,
                        p->n_vis, p->n_pix, part);
   }
   return hipGetLastError();
@@ -581,9 +608,9 @@ static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st
   if (p->n_vis == 0 || p->n_fchunks == 0) return hipSuccess;
   const bool bm = p->beam_pair;
   if (nr == 1 && p->grid) {
-    // the grid kernels take the delta pixels; Gaussian pixels stay direct
+    // grid segments first, then the direct segments (no per-pair beams here)
     hipError_t e = launch_grid_forward(p, xp, st);
-    if (e != hipSuccess || p->fchunks_gauss.empty()) return e;
+    if (e != hipSuccess || (p->fd1.empty() && p->fg1.empty())) return e;
     if (p->fwd_vpl == 1) return fwd_launch_t<R, 1, false, 1>(p, xp, st, true);
     if (p->fwd_vpl == 2) return fwd_launch_t<R, 2, false, 1>(p, xp, st, true);
     return fwd_launch_t<R, 4, false, 1>(p, xp, st, true);
@@ -617,8 +644,7 @@ hipError_t launch_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st) 
 }
 
 int forward_rows(const sl1m_plan* p, int nr) {
-  if (nr == 1 && p->grid)
-    return static_cast<int>(p->grid_fchunks.size() + p->fchunks_gauss.size());
+  if (nr == 1 && p->grid) return static_cast<int>(p->grid_frows + p->fd1.size() + p->fg1.size());
   return p->n_fchunks;
 }
 
@@ -657,7 +683,7 @@ static hipError_t adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
   const bool bm = p->beam_pair;
   if (nr == 1 && p->grid) {
     hipError_t e = launch_grid_adjoint(p, st);
-    if (e != hipSuccess || p->ptiles_gauss.empty()) return e;
+    if (e != hipSuccess || (p->pd1.empty() && p->pg1.empty())) return e;
     if (p->adj_ppl == 1) return adj_launch_t<R, 1, false, 1>(p, st, true);
     if (p->adj_ppl == 2) return adj_launch_t<R, 2, false, 1>(p, st, true);
     return adj_launch_t<R, 4, false, 1>(p, st, true);
@@ -687,7 +713,7 @@ hipError_t launch_adjoint(sl1m_plan* p, int nr, hipStream_t st) {
 template <typename R>
 static hipError_t adj_reduce_t(sl1m_plan* p, void* g, bool unpermute, int nr, hipStream_t st) {
   if (p->n_pix == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_adj_reduce<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+  hipLaunchKernelGGL((k_adj_reduce<R>), dim3(grid1(p->n_pix, kRowPix)), dim3(kBlock), 0, st,
                      static_cast<const R*>(p->apart), p->n_achunks, p->n_pix, nr,
                      static_cast<const R*>(p->pscale), unpermute ? p->perm : nullptr,
                      static_cast<R*>(g));
@@ -700,7 +726,7 @@ hipError_t launch_adjoint_reduce(sl1m_plan* p, void* g, bool unpermute, int nr, 
 template <typename R>
 static hipError_t fista_t(sl1m_plan* p, hipStream_t st) {
   if (p->n_pix > 0)
-    hipLaunchKernelGGL((k_fista<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_fista<R>), dim3(grid1(p->n_pix, kRowPix)), dim3(kBlock), 0, st,
                        static_cast<const R*>(p->apart), p->n_achunks, p->n_pix,
                        static_cast<const R*>(p->pscale), static_cast<R*>(p->xperm),
                        static_cast<R*>(p->img), p->scal, p->flag);

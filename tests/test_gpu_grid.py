@@ -50,10 +50,14 @@ def _odd_grid(n_side, half_extent):
     return L.ravel(), M.ravel()
 
 
-SEEDS = {"config1": 0, "odd45": 1, "disk64": 2, "rect80x24_gains": 3, "grid_plus_gauss": 4}
+SEEDS = {"config1": 0, "odd45": 1, "disk64": 2, "rect80x24_gains": 3, "grid_plus_gauss": 4,
+         "gauss_wide48_gains": 5, "gauss_parax_odd41": 6, "layers_mixed": 7,
+         "gauss_truncated50": 8}
 
 
 def _case(name):
+    """Gaussian cases take sigma so that pi sigma^2 |(u,v)|^2 is of order 1-10
+    over their visibilities (the taper neither flat nor vanishing)."""
     rng = np.random.default_rng(SEEDS[name])
     if name == "config1":
         return W.config1()
@@ -85,13 +89,46 @@ def _case(name):
         perm = rng.permutation(l.size + ng)   # interleave the kinds in caller order
         return _with_pixels(wl, np.concatenate([l, lg])[perm], np.concatenate([m, mg])[perm],
                             sig[perm], kinds[perm])
+    if name == "gauss_wide48_gains":
+        wl = W.small_random(15, 10, 2600, uv_radius=900.0, w_sigma=250.0, with_gains=True)
+        l, m, d = W.grid_pixels(48, 0.2)
+        return _with_pixels(wl, l, m, np.full(l.size, 1.5e-3),
+                            np.full(l.size, W.PIX_GAUSS_WIDE, np.uint8))
+    if name == "gauss_parax_odd41":
+        wl = W.small_random(16, 10, 2111, uv_radius=700.0, w_sigma=200.0)
+        l, m = _odd_grid(41, 0.15)
+        return _with_pixels(wl, l, m, np.full(l.size, 1.2e-3),
+                            np.full(l.size, W.PIX_GAUSS_PARAXIAL, np.uint8))
+    if name == "layers_mixed":
+        # delta 64^2 and wide-field 32^2 grids qualify; the paraxial 16^2 grid
+        # is too small and stays direct; caller order interleaves all three
+        wl = W.small_random(17, 10, 1800, uv_radius=800.0, w_sigma=200.0, with_gains=True)
+        parts = []
+        for n_side, kind, sig in ((64, W.PIX_DELTA, 0.0), (32, W.PIX_GAUSS_WIDE, 2e-3),
+                                  (16, W.PIX_GAUSS_PARAXIAL, 3e-3)):
+            l, m, d = W.grid_pixels(n_side, 0.2)
+            sg = np.full(l.size, sig)
+            parts.append((l, m, sg, np.full(l.size, kind, np.uint8)))
+        l, m, sg, kd = (np.concatenate([q[i] for q in parts]) for i in range(4))
+        perm = rng.permutation(l.size)
+        return _with_pixels(wl, l[perm], m[perm], sg[perm], kd[perm])
+    if name == "gauss_truncated50":
+        # a serving-stream-like request: row-major grid truncated mid-row
+        wl = W.small_random(18, 10, 2900, uv_radius=500.0, w_sigma=50.0)
+        l, m, d = W.grid_pixels(50, 0.05)
+        n = 2321
+        return _with_pixels(wl, l[:n], m[:n], np.full(n, 2.0 * d),
+                            np.full(n, W.PIX_GAUSS_WIDE, np.uint8))
     raise KeyError(name)
 
 
-CASES = ["config1", "odd45", "disk64", "rect80x24_gains", "grid_plus_gauss"]
+# case -> number of segments on the grid path
+CASES = {"config1": 1, "odd45": 1, "disk64": 1, "rect80x24_gains": 1, "grid_plus_gauss": 1,
+         "gauss_wide48_gains": 1, "gauss_parax_odd41": 1, "layers_mixed": 2,
+         "gauss_truncated50": 1}
 
 
-@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("name", list(CASES))
 def test_grid_and_direct_match_oracle(name):
     wl = _case(name)
     say(f"[case] grid {name} n_pix={wl.n_pix} n_vis={wl.n_vis}")
@@ -105,7 +142,7 @@ def test_grid_and_direct_match_oracle(name):
     for mode in ("require", "off"):
         plan = sl1m.Plan.from_workload(wl, grid=mode)
         info = plan.info()
-        assert info["grid"] == (1 if mode == "require" else 0)
+        assert info["grid"] == (CASES[name] if mode == "require" else 0)
         V = plan.forward(x).cpu().numpy()
         g = plan.adjoint(r).cpu().numpy()
         ef, ea = rel(V, Vo), rel(g, go)
@@ -182,6 +219,38 @@ def test_grid_config2_full_size_against_direct():
     p = O.Problem.from_workload(wl)
     ks = np.arange(0, wl.n_vis, 211)
     js = np.arange(0, wl.n_pix, 127)
+    ef = rel(Vg[ks], O.forward_rows(p, x, ks))
+    ea = rel(gg[js], O.adjoint_cols(p, r, js))
+    say(f"    grid vs direct forward {rel(Vg, Vd):.3e} adjoint {rel(gg, gd):.3e}; "
+        f"grid vs oracle sampled forward {ef:.3e} adjoint {ea:.3e}")
+    assert rel(Vg, Vd) <= TOL and rel(gg, gd) <= TOL
+    assert ef <= TOL and ea <= TOL
+
+
+def test_grid_config4_full_size_against_direct():
+    """Config 4 at full size (1024^2 delta grid and 512^2, 256^2, 128^2
+    Gaussian layers, direction-dependent gains): all four segments on the grid
+    path; every output against the direct evaluation, sampled outputs against
+    the oracle."""
+    wl = W.config4()
+    say(f"[case] grid config4 full n_pix={wl.n_pix} n_vis={wl.n_vis}")
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(wl.n_pix)
+    r = rng.standard_normal(wl.n_vis) + 1j * rng.standard_normal(wl.n_vis)
+    pg = sl1m.Plan.from_workload(wl, grid="require")
+    info = pg.info()
+    say(f"    info {info}")
+    assert info["grid"] == 4
+    Vg = pg.forward(x).cpu().numpy()
+    gg = pg.adjoint(r).cpu().numpy()
+    pg.close()
+    pd = sl1m.Plan.from_workload(wl, grid="off")
+    Vd = pd.forward(x).cpu().numpy()
+    gd = pd.adjoint(r).cpu().numpy()
+    pd.close()
+    p = O.Problem.from_workload(wl)
+    ks = np.arange(0, wl.n_vis, 4099)
+    js = np.concatenate([np.arange(0, 1024 * 1024, 10007), np.arange(1024 * 1024, wl.n_pix, 2003)])
     ef = rel(Vg[ks], O.forward_rows(p, x, ks))
     ea = rel(gg[js], O.adjoint_cols(p, r, js))
     say(f"    grid vs direct forward {rel(Vg, Vd):.3e} adjoint {rel(gg, gd):.3e}; "
