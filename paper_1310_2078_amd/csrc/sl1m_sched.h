@@ -7,8 +7,9 @@
 //   POWER step 0 .. P-1  (only when no L is given),
 //   FISTA iteration 1 .. K,
 //   OBJECTIVE (forward on the final image, objective terms, output copy).
-// Every phase is "forward items -> reduce -> adjoint items -> update -> final"
-// (OBJECTIVE has no adjoint).  Kernels of one round run in that order, so a
+// Every phase is "[prep] -> forward items -> reduce -> adjoint items -> update
+// -> final" (OBJECTIVE has no adjoint; prep, which builds per-call records from
+// the phase's input vector, only for requests that need it).  Kernels of one round run in that order, so a
 // request may cover a whole phase in one round when its work fits the per-round
 // budget; larger requests spread the forward and adjoint items of a phase over
 // several rounds.  A request never starts a new phase in the round that
@@ -91,7 +92,14 @@ class Arena {
   std::map<size_t, size_t> free_, used_;
 };
 
-enum Kernel { K_FWD_DELTA = 0, K_FWD_GAUSS, K_REDUCE, K_ADJ_DELTA, K_ADJ_GAUSS, K_UPDATE, K_FINAL, K_COUNT };
+enum Kernel {
+  K_FWD_DELTA = 0, K_FWD_GAUSS, K_REDUCE, K_ADJ_DELTA, K_ADJ_GAUSS, K_UPDATE, K_FINAL, K_PREP,
+  K_COUNT
+};
+
+// Order in which the kernels of one round run.
+constexpr Kernel kRoundOrder[K_COUNT] = {K_PREP,      K_FWD_DELTA, K_FWD_GAUSS, K_REDUCE,
+                                         K_ADJ_DELTA, K_ADJ_GAUSS, K_UPDATE,    K_FINAL};
 
 // Segment flags (what the batched kernels do for the segment's request).
 enum : int32_t {
@@ -109,6 +117,7 @@ struct Shape {
   int64_t adj_delta = 0, adj_gauss = 0;  // adjoint items
   int64_t vis_blocks = 0;                // reduce items
   int64_t pix_blocks = 0;                // update items
+  int64_t prep_blocks = 0;               // prep items at the start of each forward (0 = none)
   double evals_per_op = 0;               // N_p * N_v
   int32_t power_iters = 0;               // 0 when L is given
   int32_t max_iter = 0;
@@ -212,6 +221,7 @@ inline void plan_round(std::vector<Request*>& active, double budget, int64_t rou
     double left = budget;
     r->last_round = round;
     if (!r->in_adjoint) {
+      if (r->cursor == 0 && s.prep_blocks > 0) add_seg(rp, K_PREP, r->slot, fl, 0, s.prep_blocks);
       int64_t take = nf - r->cursor;
       if (ev_f > 0) take = std::min<int64_t>(take, std::max<int64_t>(1, static_cast<int64_t>(left / ev_f)));
       if (take > 0) {

@@ -19,7 +19,7 @@
 #include <string>
 #include <vector>
 
-#include "sl1m_device.h"
+#include "sl1m_grid.h"
 #include "sl1m_sched.h"
 
 namespace sl1m {
@@ -31,11 +31,14 @@ using sched::Segment;
 constexpr int kSrvMaxSlots = 64;
 constexpr int kSrvRing = 4;              // rounds in flight (table buffers)
 constexpr int kSrvTileBlocks = 8192;     // per-request operator split target (work-item count)
-// item tables per round: 4 operator kinds x 4 tile variants, then reduce,
-// update, final
-constexpr int kOpVariants = 4;
+// item tables per round: 4 operator kinds x 5 variants (4 direct tile shapes,
+// then the grid evaluation), then reduce, update, final and the grid prep
+// (delta, Gaussian)
+constexpr int kOpVariants = 5;
+constexpr int kGridVariant = 4;
 constexpr int kTabReduce = 4 * kOpVariants, kTabUpdate = kTabReduce + 1,
-              kTabFinal = kTabReduce + 2, kTabs = kTabReduce + 3;
+              kTabFinal = kTabReduce + 2, kTabPrepD = kTabReduce + 3, kTabPrepG = kTabReduce + 4,
+              kTabs = kTabReduce + 5;
 
 struct SegDev {
   int32_t slot, flags;
@@ -77,6 +80,16 @@ struct ReqDev {
   int64_t n_pix, n_vis, kchunk, vtiles, vis_blocks, pix_blocks;
   int32_t n_fchunks, n_fd, n_achunks, n_pd, vpl, ppl, n_layers, beam_pair;
   double t, inv_L, thr, lam, L, L_safety, rq, xscale, l2, l1, nnz;
+  // grid evaluation (requests whose pixels form one grid segment)
+  const double *g_la, *g_mb, *g_c3, *g_c4;
+  const int32_t* g_slot;
+  void* g_rec;                     // GridRec / GridRecG per cell
+  const GridChunk* g_fchunks;
+  const VisRecG<float>* g_vrec;    // the layer's records (Gaussian)
+  const float* g_Ds;               // the layer's (D, s) pairs (Gaussian)
+  const float2* g_lres;            // the layer's residual records
+  int64_t g_cells;
+  int32_t g_na, g_ng, g_vtiles, g_pad;
 };
 
 __device__ __forceinline__ int find_seg(const TabDev* __restrict__ tab, int64_t w) {
@@ -281,6 +294,95 @@ __global__ __launch_bounds__(kBlock) void k_srv_final(const TabDev* __restrict__
   }
 }
 
+// Grid evaluation.  Prep: the per-call cell records of the phase's input
+// vector (power step: x scaled by xscale; FISTA: y; objective: I), one block
+// per kBlock cells.
+template <bool GAUSS>
+__global__ __launch_bounds__(kBlock) void k_srv_gprep(const TabDev* __restrict__ tab,
+                                                      const ReqDev* __restrict__ reqs) {
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const int64_t c = (sg.begin + (w - sg.prefix)) * kBlock + threadIdx.x;
+  if (c >= q.g_cells) return;
+  const float* xp = (sg.flags & sched::F_POWER) ? q.x : (sg.flags & sched::F_OBJECTIVE) ? q.img : q.y;
+  const float xs = (sg.flags & sched::F_POWER) ? static_cast<float>(q.xscale) : 1.0f;
+  float x[4];
+  int32_t empty = 1;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int32_t j = q.g_slot[4 * c + s];
+    x[s] = j >= 0 ? q.pscale[j] * xs * xp[j] : 0.0f;
+    if (j >= 0) empty = 0;
+  }
+  if (GAUSS) {
+    GridRecG r;
+    r.r2 = q.g_c3[c];
+    r.kappa = q.g_c4[c];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) r.x[s] = x[s];
+    static_cast<GridRecG*>(q.g_rec)[c] = r;
+  } else {
+    GridRec r;
+    r.nu = q.g_c3[c];
+    r.e1 = (x[0] + x[1]) + (x[2] + x[3]);
+    r.e2 = (x[1] + x[2]) - (x[0] + x[3]);
+    r.e3 = (x[0] + x[1]) - (x[2] + x[3]);
+    r.e4 = (x[0] - x[1]) + (x[2] - x[3]);
+    r.empty = empty;
+    r.pad = 0;
+    static_cast<GridRec*>(q.g_rec)[c] = r;
+  }
+}
+
+// Forward items (grid chunk, visibility tile); partial row = grid chunk.
+template <bool GAUSS>
+__global__ __launch_bounds__(kBlock) void k_srv_gfwd(const TabDev* __restrict__ tab,
+                                                     const ReqDev* __restrict__ reqs) {
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nvt = static_cast<uint32_t>(q.g_vtiles);
+  const int64_t c = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nvt));
+  const int64_t vt = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nvt));
+  const ConstPtr<GridChunk> cc = as_const(q.g_fchunks) + c;
+  GridChunk ch;
+  ch.g = cc->g;
+  ch.ia0 = cc->ia0;
+  ch.ia1 = cc->ia1;
+  float2* row = q.fpart + c * q.n_vis;
+  if (GAUSS)
+    grid_fwd_gauss_tile(static_cast<const GridRecG*>(q.g_rec), q.g_la, q.g_mb, ch, q.g_na,
+                        q.g_vrec, q.g_Ds, vt, q.n_vis, row);
+  else
+    grid_fwd_delta_tile(static_cast<const GridRec*>(q.g_rec), q.g_la, q.g_mb, ch, q.g_na, q.vu,
+                        q.vv, q.vw, vt, q.n_vis, row);
+}
+
+// Adjoint items (lane-set block, visibility chunk); partial row = chunk.
+template <bool GAUSS>
+__global__ __launch_bounds__(kBlock) void k_srv_gadj(const TabDev* __restrict__ tab,
+                                                     const ReqDev* __restrict__ reqs) {
+  __shared__ float4 lds[kGridKBG * kGridMaxGL * kGridNBA];
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
+  const int64_t blk = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nac));
+  float* row = q.apart + kc * q.n_pix;
+  if (GAUSS)
+    grid_adj_gauss_tile(q.g_vrec, q.g_lres, q.g_la, q.g_mb, q.g_c3, q.g_c4, q.g_slot, q.g_na,
+                        2 * q.g_ng, blk, kc, q.kchunk, q.n_vis, row,
+                        reinterpret_cast<float4(*)[kGridMaxGL][kGridNBA]>(lds));
+  else
+    grid_adj_delta_tile(q.visrecD, q.rres, q.vv, q.g_la, q.g_mb, q.g_c3, q.g_slot, q.g_na,
+                        2 * q.g_ng, blk, kc, q.kchunk, q.n_vis, row,
+                        reinterpret_cast<float2(*)[kGridMaxGL][kGridNBA]>(lds));
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -298,6 +400,7 @@ struct Ticket {
   sl1m_solve_info info{};
   double submit_s = 0, admit_s = 0, finish_s = 0;
   bool freed = true;
+  bool grid_allowed = false;
 };
 
 }  // namespace
@@ -318,6 +421,7 @@ struct sl1m_server {
   sl1m::TabDev* h_tabs = nullptr;      // pinned mirror
   int8_t fwd_variant[sl1m::kSrvMaxSlots] = {};  // tile variant of each slot's request
   int8_t adj_variant[sl1m::kSrvMaxSlots] = {};
+  int8_t grid_kind[sl1m::kSrvMaxSlots] = {};    // 0 direct, 1 grid delta, 2 grid Gaussian
   hipEvent_t ring_event[sl1m::kSrvRing] = {};
   int64_t ring_round[sl1m::kSrvRing] = {-1, -1, -1, -1};
   std::vector<int> free_slots;
@@ -415,12 +519,26 @@ void harvest(sl1m_server* s) {
 
 sl1m_status admit(sl1m_server* s, Ticket& t) {
   const sl1m_problem& pr = t.problem;
-  size_t ws = 0;
-  if (sl1m_status st = sl1m_plan_workspace_bytes(&pr, &ws)) return st;
-  const size_t ws_al = sched::Arena::round_up(ws);
+  const size_t ws_al = t.footprint - extra_bytes(pr);
   char* base = s->arena + t.arena_off;
   sl1m_plan* plan = nullptr;
-  if (sl1m_status st = sl1m_plan_create(&pr, base, ws_al, s->admit_stream, &plan)) return st;
+  int gkind = 0;
+  if (t.grid_allowed) {
+    sl1m_problem pg = pr;
+    pg.grid_mode = SL1M_GRID_AUTO;
+    if (sl1m_status st = sl1m_plan_create(&pg, base, ws_al, s->admit_stream, &plan)) return st;
+    const bool pure = plan->grid_segs.size() == 1 && plan->fd1.empty() && plan->fg1.empty() &&
+                      plan->pd1.empty() && plan->pg1.empty();
+    if (pure) {
+      gkind = plan->grid_segs[0].kind == SL1M_PIX_DELTA ? 1 : 2;
+    } else {
+      sl1m_plan_destroy(plan);
+      plan = nullptr;
+    }
+  }
+  if (!plan) {
+    if (sl1m_status st = sl1m_plan_create(&pr, base, ws_al, s->admit_stream, &plan)) return st;
+  }
   t.plan = plan;
   char* extra = base + ws_al;
   float* y = reinterpret_cast<float*>(extra);
@@ -480,8 +598,28 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   q.vtiles = (plan->n_vis + kBlock * q.vpl - 1) / (kBlock * q.vpl);
   q.vis_blocks = static_cast<int64_t>(vb);
   q.pix_blocks = static_cast<int64_t>(pb);
-  q.n_fchunks = plan->n_fchunks;
+  q.n_fchunks = forward_rows(plan, 1);
   q.n_fd = static_cast<int32_t>(plan->fchunks_delta.size());
+  if (gkind) {
+    const GridSeg& g = plan->grid_segs[0];
+    q.g_la = plan->grid_la + g.la_off;
+    q.g_mb = plan->grid_mb + g.mb_off;
+    q.g_c3 = plan->grid_c3 + g.cell_off;
+    q.g_c4 = plan->grid_c4 + g.cell_off;
+    q.g_slot = plan->grid_slot + 4 * g.cell_off;
+    q.g_rec = static_cast<char*>(plan->grid_rec) + sizeof(GridRec) * g.cell_off;
+    q.g_fchunks = plan->d_grid_fchunks + g.fc0;
+    if (gkind == 2) {
+      q.g_vrec = static_cast<const VisRecG<float>*>(plan->visrecG) +
+                 static_cast<int64_t>(g.layer) * plan->n_vis;
+      q.g_Ds = static_cast<const float*>(plan->layerDs) + static_cast<int64_t>(g.layer) * 2 * plan->n_vis;
+      q.g_lres = static_cast<const float2*>(plan->rres) + static_cast<int64_t>(1 + g.layer) * plan->n_vis;
+    }
+    q.g_cells = g.cells;
+    q.g_na = g.na;
+    q.g_ng = g.ng;
+    q.g_vtiles = plan->grid_vtiles;
+  }
   q.n_achunks = plan->n_achunks;
   q.n_pd = static_cast<int32_t>(plan->ptiles_delta.size());
   q.n_layers = plan->n_layers;
@@ -494,18 +632,32 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   q.thr = power ? 0.0 : t.params.lambda / t.params.L;
   q.xscale = xscale;
   auto variant = [&](int per_lane) { return plan->beam_pair ? 3 : (per_lane == 4 ? 2 : per_lane == 2 ? 1 : 0); };
-  s->fwd_variant[t.req.slot] = static_cast<int8_t>(variant(q.vpl));
-  s->adj_variant[t.req.slot] = static_cast<int8_t>(variant(q.ppl));
+  s->fwd_variant[t.req.slot] = static_cast<int8_t>(gkind ? kGridVariant : variant(q.vpl));
+  s->adj_variant[t.req.slot] = static_cast<int8_t>(gkind ? kGridVariant : variant(q.ppl));
+  s->grid_kind[t.req.slot] = static_cast<int8_t>(gkind);
   SRV_HIP(hipMemcpyAsync(s->d_reqs + t.req.slot, &q, sizeof(ReqDev), hipMemcpyHostToDevice, st),
           "upload request descriptor");
   SRV_HIP(hipStreamSynchronize(st), "admission sync");
   // work-item counts
   sched::Shape& sh = t.req.shape;
-  sh.fwd_delta = q.vtiles * q.n_fd;
-  sh.fwd_gauss = q.vtiles * (q.n_fchunks - q.n_fd);
-  const int64_t n_pt = static_cast<int64_t>(plan->ptiles_delta.size() + plan->ptiles_gauss.size());
-  sh.adj_delta = static_cast<int64_t>(q.n_pd) * q.n_achunks;
-  sh.adj_gauss = (n_pt - q.n_pd) * q.n_achunks;
+  if (gkind) {
+    // one grid segment: all items are of its kind
+    const GridSeg& g = plan->grid_segs[0];
+    const int64_t nf = static_cast<int64_t>(g.nfc) * q.g_vtiles;
+    const int64_t na = static_cast<int64_t>(g.ablocks) * q.n_achunks;
+    sh.fwd_delta = gkind == 1 ? nf : 0;
+    sh.fwd_gauss = gkind == 2 ? nf : 0;
+    sh.adj_delta = gkind == 1 ? na : 0;
+    sh.adj_gauss = gkind == 2 ? na : 0;
+    sh.prep_blocks = (g.cells + kBlock - 1) / kBlock;
+  } else {
+    sh.fwd_delta = q.vtiles * q.n_fd;
+    sh.fwd_gauss = q.vtiles * (q.n_fchunks - q.n_fd);
+    const int64_t n_pt = static_cast<int64_t>(plan->ptiles_delta.size() + plan->ptiles_gauss.size());
+    sh.adj_delta = static_cast<int64_t>(q.n_pd) * q.n_achunks;
+    sh.adj_gauss = (n_pt - q.n_pd) * q.n_achunks;
+    sh.prep_blocks = 0;
+  }
   sh.vis_blocks = q.vis_blocks;
   sh.pix_blocks = q.pix_blocks;
   sh.evals_per_op = static_cast<double>(pr.n_pix) * static_cast<double>(pr.n_vis);
@@ -545,6 +697,8 @@ sl1m_status launch_round(sl1m_server* s) {
   tabs[kTabReduce] = rp.seg[sched::K_REDUCE];
   tabs[kTabUpdate] = rp.seg[sched::K_UPDATE];
   tabs[kTabFinal] = rp.seg[sched::K_FINAL];
+  for (const Segment& g : rp.seg[sched::K_PREP])
+    tabs[s->grid_kind[g.slot] == 2 ? kTabPrepG : kTabPrepD].push_back(g);
   TabDev* ht = s->h_tabs + ring * kTabs;
   for (int k = 0; k < kTabs; ++k) {
     TabDev& tb = ht[k];
@@ -569,24 +723,30 @@ sl1m_status launch_round(sl1m_server* s) {
   const ReqDev* cr = s->d_reqs;
   ReqDev* r = s->d_reqs;
   hipError_t e = hipSuccess;
-  // kernel order within a round: forward, reduce, adjoint, update, final
+  // kernel order within a round: prep, forward, reduce, adjoint, update, final
+  if (e == hipSuccess) e = go(kTabPrepD, k_srv_gprep<false>, cr);
+  if (e == hipSuccess) e = go(kTabPrepG, k_srv_gprep<true>, cr);
   if (e == hipSuccess) e = go(0, k_srv_fwd<false, 1, false>, cr);
   if (e == hipSuccess) e = go(1, k_srv_fwd<false, 2, false>, cr);
   if (e == hipSuccess) e = go(2, k_srv_fwd<false, 4, false>, cr);
   if (e == hipSuccess) e = go(3, k_srv_fwd<false, 4, true>, cr);
-  if (e == hipSuccess) e = go(4, k_srv_fwd<true, 1, false>, cr);
-  if (e == hipSuccess) e = go(5, k_srv_fwd<true, 2, false>, cr);
-  if (e == hipSuccess) e = go(6, k_srv_fwd<true, 4, false>, cr);
-  if (e == hipSuccess) e = go(7, k_srv_fwd<true, 4, true>, cr);
+  if (e == hipSuccess) e = go(kGridVariant, k_srv_gfwd<false>, cr);
+  if (e == hipSuccess) e = go(kOpVariants + 0, k_srv_fwd<true, 1, false>, cr);
+  if (e == hipSuccess) e = go(kOpVariants + 1, k_srv_fwd<true, 2, false>, cr);
+  if (e == hipSuccess) e = go(kOpVariants + 2, k_srv_fwd<true, 4, false>, cr);
+  if (e == hipSuccess) e = go(kOpVariants + 3, k_srv_fwd<true, 4, true>, cr);
+  if (e == hipSuccess) e = go(kOpVariants + kGridVariant, k_srv_gfwd<true>, cr);
   if (e == hipSuccess) e = go(kTabReduce, k_srv_reduce, r);
-  if (e == hipSuccess) e = go(8, k_srv_adj<false, 1, false>, cr);
-  if (e == hipSuccess) e = go(9, k_srv_adj<false, 2, false>, cr);
-  if (e == hipSuccess) e = go(10, k_srv_adj<false, 4, false>, cr);
-  if (e == hipSuccess) e = go(11, k_srv_adj<false, 4, true>, cr);
-  if (e == hipSuccess) e = go(12, k_srv_adj<true, 1, false>, cr);
-  if (e == hipSuccess) e = go(13, k_srv_adj<true, 2, false>, cr);
-  if (e == hipSuccess) e = go(14, k_srv_adj<true, 4, false>, cr);
-  if (e == hipSuccess) e = go(15, k_srv_adj<true, 4, true>, cr);
+  if (e == hipSuccess) e = go(2 * kOpVariants + 0, k_srv_adj<false, 1, false>, cr);
+  if (e == hipSuccess) e = go(2 * kOpVariants + 1, k_srv_adj<false, 2, false>, cr);
+  if (e == hipSuccess) e = go(2 * kOpVariants + 2, k_srv_adj<false, 4, false>, cr);
+  if (e == hipSuccess) e = go(2 * kOpVariants + 3, k_srv_adj<false, 4, true>, cr);
+  if (e == hipSuccess) e = go(2 * kOpVariants + kGridVariant, k_srv_gadj<false>, cr);
+  if (e == hipSuccess) e = go(3 * kOpVariants + 0, k_srv_adj<true, 1, false>, cr);
+  if (e == hipSuccess) e = go(3 * kOpVariants + 1, k_srv_adj<true, 2, false>, cr);
+  if (e == hipSuccess) e = go(3 * kOpVariants + 2, k_srv_adj<true, 4, false>, cr);
+  if (e == hipSuccess) e = go(3 * kOpVariants + 3, k_srv_adj<true, 4, true>, cr);
+  if (e == hipSuccess) e = go(3 * kOpVariants + kGridVariant, k_srv_gadj<true>, cr);
   if (e == hipSuccess) e = go(kTabUpdate, k_srv_update, r);
   if (e == hipSuccess) e = go(kTabFinal, k_srv_final, r);
   if (e != hipSuccess) return hip_error(e, "batched round launch");
@@ -656,11 +816,17 @@ sl1m_status sl1m_server_submit(sl1m_server* s, const sl1m_problem* problem, cons
     auto t = std::make_unique<Ticket>();
     t->problem = *problem;
     t->problem.tile_blocks = problem->tile_blocks > 0 ? problem->tile_blocks : kSrvTileBlocks;
-    // the batched kernels evaluate every entry directly
+    // the batched kernels take the grid evaluation for a request whose pixels
+    // form one qualifying grid segment and the direct one otherwise; the
+    // footprint covers either plan (decided at admission)
+    size_t ws = 0, ws_off = 0;
+    if (problem->grid_mode != SL1M_GRID_OFF) {
+      if (sl1m_status st = sl1m_plan_workspace_bytes(&t->problem, &ws)) return st;
+    }
     t->problem.grid_mode = SL1M_GRID_OFF;
-    size_t ws = 0;
-    if (sl1m_status st = sl1m_plan_workspace_bytes(&t->problem, &ws)) return st;
-    t->footprint = sched::Arena::round_up(ws) + extra_bytes(t->problem);
+    if (sl1m_status st = sl1m_plan_workspace_bytes(&t->problem, &ws_off)) return st;
+    t->grid_allowed = problem->grid_mode != SL1M_GRID_OFF;
+    t->footprint = sched::Arena::round_up(std::max(ws, ws_off)) + extra_bytes(t->problem);
     t->vis = vis;
     t->img_out = img_out;
     t->params = *params;

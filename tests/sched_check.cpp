@@ -83,6 +83,7 @@ static void planner_tests() {
       s.adj_delta = rng() % 25; s.adj_gauss = rng() % 15;
       if (s.adj_delta + s.adj_gauss == 0) s.adj_gauss = 1;
       s.vis_blocks = 1 + rng() % 9; s.pix_blocks = 1 + rng() % 9;
+      s.prep_blocks = rng() % 3;
       s.evals_per_op = 1e5 * (1 + rng() % 1000);
       s.power_iters = rng() % 4; s.max_iter = rng() % 6;
       reqs[i].slot = i; reqs[i].ticket = 100 + i;
@@ -94,7 +95,7 @@ static void planner_tests() {
     std::vector<Request*> act;
     for (auto& r : reqs) act.push_back(&r);
     // per request state machine mirror
-    struct M { int phase = 0; int64_t f = 0, a = 0; bool red = false; int finals = 0; bool done = false; };
+    struct M { int phase = 0; int64_t f = 0, a = 0; bool red = false, prep = false; int finals = 0; bool done = false; };
     std::vector<M> m(nreq);
     RoundPlan rp;
     int64_t round = 0;
@@ -106,7 +107,8 @@ static void planner_tests() {
       plan_round(act, budget, round, rp);
       CHECK(!rp.seg[K_FINAL].empty() || !rp.seg[K_FWD_DELTA].empty() || !rp.seg[K_FWD_GAUSS].empty() ||
             !rp.seg[K_ADJ_DELTA].empty() || !rp.seg[K_ADJ_GAUSS].empty());
-      for (int k = 0; k < K_COUNT; ++k) {
+      for (int ki = 0; ki < K_COUNT; ++ki) {
+        const int k = kRoundOrder[ki];
         std::set<int> seen;
         for (const Segment& g : rp.seg[k]) {
           CHECK(g.begin < g.end);
@@ -116,9 +118,15 @@ static void planner_tests() {
           CHECK(!st.done);
           CHECK(!reqs[g.slot].cancelled || round < cancel_at + 1);
           switch (k) {
+            case K_PREP:
+              CHECK(s.prep_blocks > 0 && !st.prep && !st.red && st.f == 0);
+              CHECK(g.begin == 0 && g.end == s.prep_blocks);
+              st.prep = true; break;
             case K_FWD_DELTA:
+              CHECK(s.prep_blocks == 0 || st.prep);
               CHECK(!st.red && g.begin == st.f && g.end <= s.fwd_delta); st.f = g.end; break;
             case K_FWD_GAUSS:
+              CHECK(s.prep_blocks == 0 || st.prep);
               CHECK(!st.red && g.begin + s.fwd_delta == st.f && g.end <= s.fwd_gauss);
               st.f = g.end + s.fwd_delta; break;
             case K_REDUCE:
@@ -145,7 +153,7 @@ static void planner_tests() {
               CHECK(((g.flags & F_FISTA) != 0) == is_fista);
               CHECK(obj == (!is_power && !is_fista));
               CHECK(((g.flags & F_LAST_POWER) != 0) == (is_power && expect_phase + 1 == s.power_iters));
-              st.phase++; st.f = 0; st.a = 0; st.red = false;
+              st.phase++; st.f = 0; st.a = 0; st.red = false; st.prep = false;
               if (obj) st.done = true;
               break;
             }

@@ -138,3 +138,80 @@ def test_server_close_to_standalone_solve():
     err = np.max(np.abs(img - a)) / np.max(a)
     say(f"    err/peak {err:.2e}")
     assert err <= 1e-5
+
+
+def _grid_req(seed, n_side, kind=W.PIX_DELTA, sigma=0.0, n_vis=2000, gains=False, n_src=4):
+    """A request on a centred n_side^2 grid over +-0.1 (grid evaluation)."""
+    wl = W.small_random(seed, 10, n_vis, half_extent=0.1, uv_radius=600.0, w_sigma=80.0,
+                        with_gains=gains)
+    l, m, _ = W.grid_pixels(n_side, 0.1)
+    wl.l, wl.m = l, m
+    wl.sigma = np.full(l.size, sigma)
+    wl.kind = np.full(l.size, kind, np.uint8)
+    rng = np.random.default_rng(seed + 1000)
+    x = np.zeros(l.size)
+    x[rng.choice(l.size, n_src, replace=False)] = rng.uniform(0.5, 2.0, n_src)
+    op = O.Operator(O.Problem.from_workload(wl), dense=l.size * n_vis <= 4_000_000)
+    V = op.forward(x) + 0.01 * (rng.standard_normal(n_vis) + 1j * rng.standard_normal(n_vis))
+    return wl, op, V
+
+
+def test_server_grid_requests_match_oracle():
+    """Requests whose pixels form one grid segment run the batched grid
+    kernels (prep, forward, adjoint); results against the oracle's FISTA."""
+    say("[case] server grid requests vs oracle")
+    cases = [_grid_req(31, 40), _grid_req(32, 36, kind=W.PIX_GAUSS_WIDE, sigma=2e-3, gains=True),
+             _grid_req(33, 34, kind=W.PIX_GAUSS_PARAXIAL, sigma=1.5e-3)]
+    for wl, _, _ in cases:
+        assert sl1m.Plan.from_workload(wl, grid="require").info()["grid"] == 1
+    srv = sl1m.Server(2 * GIB, max_slots=8)
+    tickets = []
+    for wl, op, V in cases:
+        L, _ = O.power_iteration(op, 30)
+        tickets.append((srv.submit(wl, V, 0.05, 40, L=L), L))
+    srv.drain([t for t, _ in tickets])
+    for (wl, op, V), (t, L) in zip(cases, tickets):
+        ok, info, _ = srv.poll(t)
+        ref = O.fista(op, V, L, 0.05, 40)
+        img = srv.result(t).cpu().numpy()
+        err = np.max(np.abs(img - ref.image)) / np.max(ref.image)
+        say(f"    n_pix={wl.n_pix} kind={wl.kind[0]} err/peak {err:.2e} F {info['F']:.6g} vs {ref.F:.6g}")
+        assert ok and info["status"] == 0
+        assert err <= 1e-4
+        assert abs(info["F"] - ref.F) <= 1e-4 * ref.F
+
+
+def test_server_grid_alone_equals_in_mix():
+    """Grid delta, grid Gaussian and a direct (irregular) request in one mix,
+    with power iteration and a cancellation: each image bitwise equal to the
+    same request alone, and close to the standalone grid solve."""
+    say("[case] server grid alone == in mix")
+    X = _grid_req(41, 48)
+    Y = _grid_req(42, 40, kind=W.PIX_GAUSS_WIDE, sigma=2e-3)
+    Z = _req(43, 1500, 1800)
+    ax, ix = _alone(X[0], X[2], L=0.0)
+    ay, iy = _alone(Y[0], Y[2], L=0.0)
+    az, _ = _alone(Z[0], Z[2], L=0.0)
+    srv = sl1m.Server(2 * GIB, max_slots=8, round_budget=2e7)
+    tz = srv.submit(Z[0], Z[2], 0.05, 30)
+    srv.step()
+    ty = srv.submit(Y[0], Y[2], 0.05, 30)
+    srv.step()
+    tx = srv.submit(X[0], X[2], 0.05, 30)
+    w = srv.submit(Z[0], Z[2], 0.05, 30)     # cancelled while it runs
+    for _ in range(4):
+        srv.step()
+    srv.cancel(w)
+    srv.drain([tx, ty, tz, w])
+    assert np.array_equal(srv.result(tx).cpu().numpy(), ax)
+    assert np.array_equal(srv.result(ty).cpu().numpy(), ay)
+    assert np.array_equal(srv.result(tz).cpu().numpy(), az)
+    assert srv.poll(tx)[1]["F"] == ix["F"] and srv.poll(ty)[1]["L"] == iy["L"]
+    assert srv.poll(w)[1]["status"] == sl1m.ECANCELLED
+    for (wl, _, V), img, info in ((X, ax, ix), (Y, ay, iy)):
+        plan = sl1m.Plan.from_workload(wl, grid="require")
+        ref, _ = plan.solve(V, 0.05, 30, L=info["L"])
+        ref = ref.cpu().numpy()
+        err = np.max(np.abs(img - ref)) / np.max(ref)
+        say(f"    n_pix={wl.n_pix} server vs standalone grid solve err/peak {err:.2e}")
+        assert err <= 1e-5
