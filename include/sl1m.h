@@ -282,11 +282,14 @@ sl1m_status sl1m_timing_end(sl1m_plan* plan, sl1m_timing* out /* host */);
  * (admission by footprint; a request waits while its footprint does not fit
  * or no slot is free).  Work advances in rounds: one launch of each batched
  * kernel covers the work items of every active request.  A round holds about
- * `round_budget_evals` pixel-visibility evaluations: each of the n active
- * requests advances by at most max(budget / n, budget / 32) evaluations (at
- * least one work item, never past the end of its current phase), so small
- * requests finish a whole FISTA iteration per round while large ones advance
- * part of one.  A request's arithmetic and
+ * `round_budget_evals` pixel-visibility evaluations: under the FAIR policy
+ * each of the n active requests advances by at most max(budget / n,
+ * budget / 32) evaluations (at least one work item, never past the end of its
+ * current phase), so small requests finish a whole FISTA iteration per round
+ * while large ones advance part of one; under OLDEST_FIRST the earliest
+ * admitted request may take the whole budget and the others budget / 64.
+ * A request whose pixels form one grid segment (see sl1m_grid_mode) runs the
+ * grid evaluation; other requests the direct one.  A request's arithmetic and
  * summation order depend only on its own problem: its image is bitwise the
  * same alone and in any mix.  FP32 plans, one right-hand side; the solve runs
  * the power iteration when params->L <= 0, then params->max_iter FISTA
@@ -311,6 +314,16 @@ typedef struct {
  * streams. */
 sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
                                double round_budget_evals, sl1m_server** out);
+
+typedef enum {
+  SL1M_SERVE_FAIR = 0,         /* equal shares of each round (default)          */
+  SL1M_SERVE_OLDEST_FIRST = 1  /* the earliest admitted request first, a floor of
+                                  work for the others                           */
+} sl1m_serve_policy;
+
+/* Selects how rounds are shared from the next round on.  SL1M_EINVAL for an
+ * unknown policy.  Results do not depend on the policy. */
+sl1m_status sl1m_server_set_policy(sl1m_server* server, int32_t policy);
 
 /* Queue one solve.  problem: as for sl1m_plan_create (FP32, max_rhs <= 1); its
  * arrays must stay valid until the request is admitted.  vis: complex64

@@ -141,6 +141,7 @@ struct Request {
   int64_t last_round = -1;   // last round that used the request's memory
   int64_t done_round = -1;   // round whose completion finishes the request
   int32_t phases_run = 0;
+  double share = 0;          // operator evals this request may take per round (0: the round's budget)
 };
 
 struct RoundPlan {
@@ -205,8 +206,8 @@ inline void add_split(RoundPlan& rp, Kernel kd, Kernel kg, int32_t slot, int32_t
 }
 
 // Plans one round: every active (not cancelled, not done) request advances
-// by at most `budget` operator evals (at least one item), never past the end
-// of its current phase.
+// by at most its `share` (or `budget` when the share is 0) operator evals, at
+// least one item, never past the end of its current phase.
 inline void plan_round(std::vector<Request*>& active, double budget, int64_t round,
                        RoundPlan& rp) {
   rp.clear();
@@ -218,7 +219,7 @@ inline void plan_round(std::vector<Request*>& active, double budget, int64_t rou
     const int64_t na = s.adj_delta + s.adj_gauss;
     const double ev_f = nf > 0 ? s.evals_per_op / static_cast<double>(nf) : 0.0;
     const double ev_a = na > 0 ? s.evals_per_op / static_cast<double>(na) : 0.0;
-    double left = budget;
+    double left = r->share > 0 ? r->share : budget;
     r->last_round = round;
     if (!r->in_adjoint) {
       if (r->cursor == 0 && s.prep_blocks > 0) add_seg(rp, K_PREP, r->slot, fl, 0, s.prep_blocks);

@@ -413,6 +413,7 @@ struct sl1m_server {
   sl1m::sched::Arena alloc;
   int max_slots = 0;
   double budget = 3e10;                // evals per round, shared by the active requests
+  int policy = SL1M_SERVE_FAIR;        // how the round budget is shared
   hipStream_t stream = nullptr;        // rounds (non-blocking, default priority)
   hipStream_t admit_stream = nullptr;  // plan creation of admitted requests
   hipEvent_t admit_event = nullptr;
@@ -680,11 +681,16 @@ sl1m_status launch_round(sl1m_server* s) {
     s->completed_round = std::max(s->completed_round, s->ring_round[ring]);
     s->ring_round[ring] = -1;
   }
-  // each request's share of the round, with a floor so that a crowded round
-  // still moves every request by a useful amount
-  const double share = std::max(s->budget / static_cast<double>(act.size()), s->budget / 32.0);
+  // each request's share of the round.  FAIR: equal shares with a floor so
+  // that a crowded round still moves every request by a useful amount.
+  // OLDEST_FIRST: the earliest admitted request takes the whole budget, the
+  // others a floor of budget/64 each (act is in admission order).
+  const double fair = std::max(s->budget / static_cast<double>(act.size()), s->budget / 32.0);
+  for (size_t i = 0; i < act.size(); ++i)
+    act[i]->share = s->policy == SL1M_SERVE_OLDEST_FIRST ? (i == 0 ? s->budget : s->budget / 64.0)
+                                                          : fair;
   sched::RoundPlan rp;
-  sched::plan_round(act, share, s->round, rp);
+  sched::plan_round(act, fair, s->round, rp);
   // split the planner's segments into per-(kernel, variant) tables
   std::vector<Segment> tabs[kTabs];
   auto route = [&](int kind, int base, const int8_t* var) {
@@ -843,6 +849,15 @@ sl1m_status sl1m_server_submit(sl1m_server* s, const sl1m_problem* problem, cons
   } catch (...) {
     return set_error(SL1M_ENOMEM, "host allocation failed");
   }
+}
+
+sl1m_status sl1m_server_set_policy(sl1m_server* s, int32_t policy) {
+  if (!s) return set_error(SL1M_EINVAL, "server is NULL");
+  if (policy != SL1M_SERVE_FAIR && policy != SL1M_SERVE_OLDEST_FIRST)
+    return set_error(SL1M_EINVAL, "unknown serving policy");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->policy = policy;
+  return SL1M_OK;
 }
 
 sl1m_status sl1m_server_step(sl1m_server* s, int32_t* n_active, int32_t* n_pending) {

@@ -70,8 +70,9 @@ def _summary(lat, total_s, evals):
 
 
 def run_batched(arrivals, reqs, data, device, arena_bytes=48 << 30, max_slots=32,
-                round_budget=3e10, log=None):
-    srv = sl1m.Server(arena_bytes, max_slots=max_slots, round_budget=round_budget, device=device)
+                round_budget=3e10, policy="fair", log=None):
+    srv = sl1m.Server(arena_bytes, max_slots=max_slots, round_budget=round_budget, device=device,
+                      policy=policy)
     n = len(reqs)
     lat = [None] * n
     open_t = {}
@@ -144,6 +145,8 @@ def main():
     ap.add_argument("--mode", choices=["both", "batched", "unbatched"], default="both")
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--budget", type=float, default=3e10)
+    ap.add_argument("--policy", choices=["fair", "oldest"], default="fair",
+                    help="how the batched server shares each round")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     dev = torch.device("cuda:0")
@@ -154,7 +157,9 @@ def main():
            "offered_evals": sum(request_evals(r) for r in reqs)}
     if args.mode in ("both", "batched"):
         res["batched"], _ = run_batched(arrivals, reqs, data, dev, max_slots=args.slots,
-                                        round_budget=args.budget, log=sys.stderr)
+                                        round_budget=args.budget, policy=args.policy,
+                                        log=sys.stderr)
+        res["batched"].update(policy=args.policy, slots=args.slots, budget=args.budget)
         print(f"[serve] batched {res['batched']}", file=sys.stderr, flush=True)
     if args.mode in ("both", "unbatched"):
         res["unbatched"], _ = run_unbatched(arrivals, reqs, data, dev, log=sys.stderr)

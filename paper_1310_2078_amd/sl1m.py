@@ -126,6 +126,7 @@ def lib() -> ctypes.CDLL:
         L.sl1m_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(SolveInfo),
                                        ctypes.POINTER(i32), ctypes.POINTER(dbl)]
         L.sl1m_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.sl1m_server_set_policy.argtypes = [vp, i32]
         L.sl1m_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.sl1m_server_destroy.argtypes = [vp]
         L.sl1m_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -139,7 +140,8 @@ def lib() -> ctypes.CDLL:
                      "sl1m_timing_begin", "sl1m_timing_end", "sl1m_plan_query",
                      "sl1m_server_create",
                      "sl1m_server_submit", "sl1m_server_step", "sl1m_server_poll",
-                     "sl1m_server_cancel", "sl1m_server_stats", "sl1m_server_destroy"):
+                     "sl1m_server_cancel", "sl1m_server_stats", "sl1m_server_destroy",
+                     "sl1m_server_set_policy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -344,8 +346,10 @@ class Server:
     GPU.  The arena is a torch uint8 tensor owned by this object; submitted
     requests keep their device inputs and output alive until done."""
 
+    POLICIES = {"fair": 0, "oldest": 1}
+
     def __init__(self, arena_bytes: int, max_slots: int = 32, round_budget: float = 3e10,
-                 device="cuda"):
+                 device="cuda", policy: str = "fair"):
         self.device = torch.device(device)
         self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
@@ -353,6 +357,11 @@ class Server:
                                         int(max_slots), float(round_budget), ctypes.byref(h)))
         self._h = h
         self._keep = {}
+        self.set_policy(policy)
+
+    def set_policy(self, policy: str):
+        """"fair" (equal round shares) or "oldest" (oldest request first)."""
+        _check(lib().sl1m_server_set_policy(self._h, self.POLICIES[policy]))
 
     def submit(self, wl, vis, lam: float, max_iter: int, L: float = 0.0,
                power_iters: int = 30, seed: int = 0, L_safety: float = 1.01,

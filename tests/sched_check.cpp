@@ -87,6 +87,7 @@ static void planner_tests() {
       s.evals_per_op = 1e5 * (1 + rng() % 1000);
       s.power_iters = rng() % 4; s.max_iter = rng() % 6;
       reqs[i].slot = i; reqs[i].ticket = 100 + i;
+      if (rng() % 2) reqs[i].share = 1e5 * (1 + rng() % 300);   // per-request share
       start_request(reqs[i]);
     }
     const double budget = 1e5 * (1 + rng() % 300);

@@ -181,18 +181,20 @@ def test_server_grid_requests_match_oracle():
         assert abs(info["F"] - ref.F) <= 1e-4 * ref.F
 
 
-def test_server_grid_alone_equals_in_mix():
+@pytest.mark.parametrize("policy", ["fair", "oldest"])
+def test_server_grid_alone_equals_in_mix(policy):
     """Grid delta, grid Gaussian and a direct (irregular) request in one mix,
-    with power iteration and a cancellation: each image bitwise equal to the
-    same request alone, and close to the standalone grid solve."""
-    say("[case] server grid alone == in mix")
+    with power iteration and a cancellation, under either round policy: each
+    image bitwise equal to the same request alone, and close to the
+    standalone grid solve."""
+    say(f"[case] server grid alone == in mix, policy {policy}")
     X = _grid_req(41, 48)
     Y = _grid_req(42, 40, kind=W.PIX_GAUSS_WIDE, sigma=2e-3)
     Z = _req(43, 1500, 1800)
     ax, ix = _alone(X[0], X[2], L=0.0)
     ay, iy = _alone(Y[0], Y[2], L=0.0)
     az, _ = _alone(Z[0], Z[2], L=0.0)
-    srv = sl1m.Server(2 * GIB, max_slots=8, round_budget=2e7)
+    srv = sl1m.Server(2 * GIB, max_slots=8, round_budget=2e7, policy=policy)
     tz = srv.submit(Z[0], Z[2], 0.05, 30)
     srv.step()
     ty = srv.submit(Y[0], Y[2], 0.05, 30)
