@@ -242,6 +242,8 @@ def main():
     ap.add_argument("--grid", choices=["auto", "off", "require"], default="auto",
                     help="evaluation of the delta pixels: grid factorisation when the pixels "
                          "qualify (auto), always direct (off)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the plan's default launch shapes instead of tuning them first")
     ap.add_argument("--profile-ops", type=int, default=0,
                     help="after the timed region, run this many extra forward+adjoint pairs "
                          "(for profiler runs)")
@@ -265,6 +267,17 @@ def main():
     print(f"[bench] config2 n_pix={n_pix} n_vis={n_vis} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
     plan = sl1m.Plan.from_workload(wl, device=dev, grid=args.grid)
+    tuning = None
+    if not args.no_tune:
+        # launch shapes from the autotuner (sl1m_tune), restricted to the
+        # requested evaluation
+        tuning = plan.tune(reps=3)
+        if args.grid != "auto" and tuning["grid"] != args.grid:
+            tuning = None
+        else:
+            plan.close()
+            plan = sl1m.Plan.from_workload(wl, device=dev, tuning=tuning)
+        print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
     noise = torch.as_tensor(wl.noise, dtype=torch.complex64, device=dev)
     V = plan.forward(wl.x_true) + noise            # synthetic data, not timed
 
@@ -334,6 +347,7 @@ def main():
             "n_vis": n_vis,
             "evals_per_step": 2 * n_pix * n_vis,
             "evaluation": "grid" if grid else "direct",
+            "tuning": tuning,
         },
         "l1_solve_time_s": elapsed,
         "solve": {

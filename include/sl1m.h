@@ -142,6 +142,8 @@ typedef struct {
   int32_t max_rhs;      /* right-hand sides per operator call: 0 or 1, 2, 4, 8 */
   int32_t tile_blocks;  /* blocks one operator launch aims at; 0 = 4096       */
   int32_t grid_mode;    /* sl1m_grid_mode                                     */
+  int32_t fwd_vpl;      /* direct forward: visibilities per lane 1, 2, 4; 0 = plan's choice */
+  int32_t adj_ppl;      /* direct adjoint: pixels per lane 1, 2, 4; 0 = plan's choice      */
 } sl1m_problem;
 
 typedef struct sl1m_plan sl1m_plan;
@@ -165,6 +167,32 @@ sl1m_status sl1m_plan_create(const sl1m_problem* problem, void* workspace, size_
                              void* stream, sl1m_plan** out);
 
 sl1m_status sl1m_plan_destroy(sl1m_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * Autotuning of a problem's launch shapes.  sl1m_tune builds candidate plans of
+ * `problem` one after another in `workspace` (size from
+ * sl1m_tune_workspace_bytes) and times `reps` forward and adjoint applications
+ * of each with HIP events on `stream`: the grid evaluation on and off (when
+ * some segment qualifies), split targets tile_blocks of 1024 .. 16384 blocks,
+ * and for direct plans 1, 2 or 4 visibilities (forward) and pixels (adjoint)
+ * per lane.  The fastest forward + adjoint pair is returned in *out (host);
+ * copy its fields into the problem before sl1m_plan_create.  The problem's
+ * own tile_blocks, grid_mode, fwd_vpl and adj_ppl are ignored (all are
+ * searched).  Synchronises `stream` after every candidate; the workspace holds
+ * nothing useful afterwards.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+  int32_t tile_blocks, grid_mode, fwd_vpl, adj_ppl;  /* the choice                */
+  double forward_ms, adjoint_ms;          /* median per application, the choice  */
+  double default_forward_ms;              /* ... with every field left at 0      */
+  double default_adjoint_ms;
+  int32_t candidates;                     /* configurations timed                */
+  int32_t reserved[3];
+} sl1m_tuning;
+
+sl1m_status sl1m_tune_workspace_bytes(const sl1m_problem* problem, size_t* bytes);
+sl1m_status sl1m_tune(const sl1m_problem* problem, void* workspace, size_t workspace_bytes,
+                      int32_t reps, void* stream, sl1m_tuning* out);
 
 /* What a plan decided: evaluation order and split of the operators.  Host
  * call, no device work.  `info` is a host pointer filled on success. */

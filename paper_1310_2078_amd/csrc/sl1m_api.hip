@@ -258,8 +258,12 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 
   // ---- tiling
   const int64_t nv = pr->n_vis;
+  auto lane_ok = [](int32_t v) { return v == 0 || v == 1 || v == 2 || v == 4; };
+  if (!lane_ok(pr->fwd_vpl) || !lane_ok(pr->adj_ppl))
+    return set_error(SL1M_EINVAL, "fwd_vpl and adj_ppl must be 0, 1, 2 or 4");
   a.fwd_vpl = nv >= 64LL * kBlock * 4 ? 4 : (nv >= 32LL * kBlock * 2 ? 2 : 1);
-  if (a.beam_pair) a.fwd_vpl = 4;
+  if (pr->fwd_vpl) a.fwd_vpl = pr->fwd_vpl;
+  if (a.beam_pair) a.fwd_vpl = 4;  // the per-pair-beam kernels exist for 4 per lane only
   const int64_t vtiles = (nv + kBlock * a.fwd_vpl - 1) / (kBlock * a.fwd_vpl);
   const int64_t target_blocks = pr->tile_blocks > 0 ? pr->tile_blocks : 4096;
   if (pr->tile_blocks < 0) return set_error(SL1M_EINVAL, "tile_blocks must be >= 0");
@@ -280,6 +284,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     a.fg.clear();
   }
   a.adj_ppl = np >= 64LL * kBlock * 4 ? 4 : (np >= 32LL * kBlock * 2 ? 2 : 1);
+  if (pr->adj_ppl) a.adj_ppl = pr->adj_ppl;
   if (a.beam_pair) a.adj_ppl = 4;
   const int64_t tp = static_cast<int64_t>(kBlock) * a.adj_ppl;
   a.pd.clear();
@@ -750,6 +755,188 @@ sl1m_status sl1m_plan_destroy(sl1m_plan* plan) {
   }
   delete plan;
   return SL1M_OK;
+}
+
+namespace {
+
+// Candidate launch shapes for sl1m_tune: (grid mode, split target) with the
+// plan's own lane counts, then lane counts for the best direct split.
+std::vector<sl1m_problem> tune_stage1(const sl1m_problem& base, bool grid_possible) {
+  std::vector<sl1m_problem> c;
+  for (int g : {SL1M_GRID_AUTO, SL1M_GRID_OFF}) {
+    if (g == SL1M_GRID_AUTO && !grid_possible) continue;
+    for (int tb : {1024, 2048, 4096, 8192, 16384}) {
+      sl1m_problem p = base;
+      p.grid_mode = g;
+      p.tile_blocks = tb;
+      p.fwd_vpl = 0;
+      p.adj_ppl = 0;
+      c.push_back(p);
+    }
+  }
+  return c;
+}
+
+struct TuneTimes {
+  double fwd_ms = 0, adj_ms = 0;
+};
+
+double median(std::vector<float> v) {
+  std::sort(v.begin(), v.end());
+  return v.empty() ? 0.0 : v[v.size() / 2];
+}
+
+// Builds the plan of `pr` in the workspace and times `reps` forward and
+// adjoint applications (after one warm-up of each).
+sl1m_status tune_one(const sl1m_problem& pr, void* ws, size_t bytes, int reps, hipStream_t st,
+                     TuneTimes& out) {
+  sl1m_plan* p = nullptr;
+  if (sl1m_status s = sl1m_plan_create(&pr, ws, bytes, st, &p)) return s;
+  std::vector<hipEvent_t> ev(2 * (2 * reps + 2), nullptr);
+  sl1m_status res = SL1M_OK;
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  if (e == hipSuccess) e = launch_splitmix_start(p, 12345, p->xperm, st);
+  std::vector<float> tf, ta;
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+    hipEvent_t* q = &ev[4 * r];
+    e = hipEventRecord(q[0], st);
+    if (e == hipSuccess) e = launch_forward(p, p->xperm, 1, st);
+    if (e == hipSuccess) e = launch_forward_reduce(p, nullptr, p->res, true, 1, st);
+    if (e == hipSuccess) e = hipEventRecord(q[1], st);
+    if (e == hipSuccess) e = hipEventRecord(q[2], st);
+    if (e == hipSuccess) e = launch_adjoint(p, 1, st);
+    if (e == hipSuccess) e = launch_adjoint_reduce(p, p->img, false, 1, st);
+    if (e == hipSuccess) e = hipEventRecord(q[3], st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (int r = 1; r <= reps && e == hipSuccess; ++r) {  // r = 0 is the warm-up
+    float a = 0, b = 0;
+    e = hipEventElapsedTime(&a, ev[4 * r], ev[4 * r + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[4 * r + 2], ev[4 * r + 3]);
+    tf.push_back(a);
+    ta.push_back(b);
+  }
+  if (e != hipSuccess) res = hip_error(e, "tuning run");
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
+  sl1m_plan_destroy(p);
+  out.fwd_ms = median(tf);
+  out.adj_ms = median(ta);
+  return res;
+}
+
+}  // namespace
+
+sl1m_status sl1m_tune_workspace_bytes(const sl1m_problem* problem, size_t* bytes) {
+  try {
+    if (!problem || !bytes) return set_error(SL1M_EINVAL, "NULL argument");
+    // every plan sl1m_tune may build: the default, (grid mode, split) with the
+    // plan's lane counts, and direct plans with every lane count and split
+    size_t mx = 0;
+    auto need = [&](int g, int tb, int vpl, int ppl) -> sl1m_status {
+      sl1m_problem p = *problem;
+      p.max_rhs = 1;
+      p.grid_mode = g;
+      p.tile_blocks = tb;
+      p.fwd_vpl = vpl;
+      p.adj_ppl = ppl;
+      size_t b = 0;
+      if (sl1m_status s = sl1m_plan_workspace_bytes(&p, &b)) return s;
+      mx = std::max(mx, b);
+      return SL1M_OK;
+    };
+    if (sl1m_status s = need(SL1M_GRID_AUTO, 0, 0, 0)) return s;
+    for (int tb : {1024, 2048, 4096, 8192, 16384}) {
+      if (sl1m_status s = need(SL1M_GRID_AUTO, tb, 0, 0)) return s;
+      for (int vpl : {0, 1, 2, 4})
+        for (int ppl : {0, 1, 2, 4})
+          if (sl1m_status s = need(SL1M_GRID_OFF, tb, vpl, ppl)) return s;
+    }
+    *bytes = mx;
+    return SL1M_OK;
+  } catch (...) {
+    return set_error(SL1M_ENOMEM, "host allocation failed");
+  }
+}
+
+sl1m_status sl1m_tune(const sl1m_problem* problem, void* workspace, size_t workspace_bytes,
+                      int32_t reps, void* stream, sl1m_tuning* out) {
+  try {
+    if (!problem || !out) return set_error(SL1M_EINVAL, "NULL argument");
+    if (reps < 1 || reps > 100) return set_error(SL1M_EINVAL, "reps must be in [1, 100]");
+    size_t need = 0;
+    if (sl1m_status s = sl1m_tune_workspace_bytes(problem, &need)) return s;
+    if (workspace_bytes < need)
+      return set_error(SL1M_ENOMEM, "workspace smaller than sl1m_tune_workspace_bytes()");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    sl1m_problem base = *problem;
+    base.max_rhs = 1;
+    // does any segment qualify for the grid evaluation?
+    bool grid_possible = false;
+    {
+      Analysis a;
+      sl1m_problem p = base;
+      p.grid_mode = SL1M_GRID_AUTO;
+      p.tile_blocks = 0;
+      p.fwd_vpl = p.adj_ppl = 0;
+      if (sl1m_status s = analyze(&p, a)) return s;
+      grid_possible = a.grid;
+    }
+    sl1m_tuning r;
+    std::memset(&r, 0, sizeof(r));
+    double best = 1e300;
+    auto consider = [&](const sl1m_problem& p, const TuneTimes& t) {
+      ++r.candidates;
+      if (t.fwd_ms + t.adj_ms < best) {
+        best = t.fwd_ms + t.adj_ms;
+        r.tile_blocks = p.tile_blocks;
+        r.grid_mode = p.grid_mode;
+        r.fwd_vpl = p.fwd_vpl;
+        r.adj_ppl = p.adj_ppl;
+        r.forward_ms = t.fwd_ms;
+        r.adjoint_ms = t.adj_ms;
+      }
+    };
+    {
+      sl1m_problem p = base;
+      p.grid_mode = SL1M_GRID_AUTO;
+      p.tile_blocks = 0;
+      p.fwd_vpl = p.adj_ppl = 0;
+      TuneTimes t;
+      if (sl1m_status s = tune_one(p, workspace, workspace_bytes, reps, st, t)) return s;
+      r.default_forward_ms = t.fwd_ms;
+      r.default_adjoint_ms = t.adj_ms;
+      consider(p, t);
+    }
+    for (const sl1m_problem& p : tune_stage1(base, grid_possible)) {
+      TuneTimes t;
+      if (sl1m_status s = tune_one(p, workspace, workspace_bytes, reps, st, t)) return s;
+      consider(p, t);
+    }
+    // lane counts of the direct kernels at the best direct split
+    if (r.grid_mode == SL1M_GRID_OFF || !grid_possible) {
+      const int tb = r.tile_blocks;
+      for (int vpl : {1, 2, 4})
+        for (int ppl : {1, 2, 4}) {
+          sl1m_problem p = base;
+          p.grid_mode = SL1M_GRID_OFF;
+          p.tile_blocks = tb;
+          p.fwd_vpl = vpl;
+          p.adj_ppl = ppl;
+          TuneTimes t;
+          if (sl1m_status s = tune_one(p, workspace, workspace_bytes, reps, st, t)) return s;
+          consider(p, t);
+        }
+    }
+    *out = r;
+    return SL1M_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(SL1M_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
 }
 
 sl1m_status sl1m_plan_query(const sl1m_plan* p, sl1m_plan_info* info) {

@@ -49,6 +49,8 @@ class Problem(ctypes.Structure):
         ("max_rhs", ctypes.c_int32),
         ("tile_blocks", ctypes.c_int32),
         ("grid_mode", ctypes.c_int32),
+        ("fwd_vpl", ctypes.c_int32),
+        ("adj_ppl", ctypes.c_int32),
     ]
 
 
@@ -130,6 +132,9 @@ def lib() -> ctypes.CDLL:
         L.sl1m_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.sl1m_server_destroy.argtypes = [vp]
         L.sl1m_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.sl1m_tune_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]
+        L.sl1m_tune.argtypes = [ctypes.POINTER(Problem), vp, ctypes.c_size_t, i32, vp,
+                                ctypes.POINTER(Tuning)]
         L.sl1m_timing_begin.argtypes = [vp, i32]
         L.sl1m_timing_end.argtypes = [vp, ctypes.POINTER(Timing)]
         L.sl1m_last_error.restype = ctypes.c_char_p
@@ -138,6 +143,7 @@ def lib() -> ctypes.CDLL:
                      "sl1m_forward", "sl1m_adjoint", "sl1m_forward_multi",
                      "sl1m_adjoint_multi", "sl1m_estimate_L", "sl1m_solve",
                      "sl1m_timing_begin", "sl1m_timing_end", "sl1m_plan_query",
+                     "sl1m_tune_workspace_bytes", "sl1m_tune",
                      "sl1m_server_create",
                      "sl1m_server_submit", "sl1m_server_step", "sl1m_server_poll",
                      "sl1m_server_cancel", "sl1m_server_stats", "sl1m_server_destroy",
@@ -173,6 +179,21 @@ GRID_AUTO, GRID_OFF, GRID_REQUIRE = 0, 1, 2
 _GRID = {"auto": GRID_AUTO, "off": GRID_OFF, "require": GRID_REQUIRE}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("tile_blocks", ctypes.c_int32), ("grid_mode", ctypes.c_int32),
+        ("fwd_vpl", ctypes.c_int32), ("adj_ppl", ctypes.c_int32),
+        ("forward_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double),
+        ("default_forward_ms", ctypes.c_double), ("default_adjoint_ms", ctypes.c_double),
+        ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+    ]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d["grid"] = {v: k for k, v in _GRID.items()}[d["grid_mode"]]
+        return d
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("n_pix", ctypes.c_int64), ("n_vis", ctypes.c_int64),
@@ -199,7 +220,8 @@ class Plan:
 
     def __init__(self, l, m, u, v, w, sigma=None, kind=None, ant_p=None, ant_q=None,
                  ant_gain=None, ant_fwhm=None, precision: str = "fp32", device="cuda",
-                 stream=None, max_rhs: int = 1, tile_blocks: int = 0, grid: str = "auto"):
+                 stream=None, max_rhs: int = 1, tile_blocks: int = 0, grid: str = "auto",
+                 fwd_vpl: int = 0, adj_ppl: int = 0):
         self.device = torch.device(device)
         self.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
         self.rdtype = torch.float32 if self.precision == PREC_FP32 else torch.float64
@@ -233,7 +255,7 @@ class Plan:
             w=_ptr(k["w"]), ant_p=_ptr(k["ant_p"]), ant_q=_ptr(k["ant_q"]), n_ant=n_ant,
             ant_gain=_ptr(k["ant_gain"]), ant_fwhm=_ptr(k["ant_fwhm"]),
             precision=self.precision, max_rhs=int(max_rhs), tile_blocks=int(tile_blocks),
-            grid_mode=_GRID[grid])
+            grid_mode=_GRID[grid], fwd_vpl=int(fwd_vpl), adj_ppl=int(adj_ppl))
         self.max_rhs = int(max_rhs)
         nbytes = ctypes.c_size_t(0)
         _check(lib().sl1m_plan_workspace_bytes(ctypes.byref(self._prob), ctypes.byref(nbytes)))
@@ -247,13 +269,34 @@ class Plan:
 
     @classmethod
     def from_workload(cls, wl, precision="fp32", device="cuda", with_kinds=True, max_rhs=1,
-                      tile_blocks=0, grid="auto"):
+                      tile_blocks=0, grid="auto", tuning=None):
+        """Plan of a workload; `tuning` (a dict from Plan.tune) sets the split,
+        the evaluation and the lane counts."""
+        if tuning is not None:
+            tile_blocks = tuning["tile_blocks"]
+            grid = tuning["grid"]
+            kw_lanes = dict(fwd_vpl=tuning["fwd_vpl"], adj_ppl=tuning["adj_ppl"])
+        else:
+            kw_lanes = {}
         kw = {}
         if with_kinds and (np.any(wl.kind != 0) or np.any(wl.sigma != 0)):
             kw = dict(sigma=wl.sigma, kind=wl.kind)
         return cls(wl.l, wl.m, wl.u, wl.v, wl.w, ant_p=wl.ant_p, ant_q=wl.ant_q,
                    ant_gain=wl.ant_gain, ant_fwhm=wl.ant_fwhm, precision=precision,
-                   device=device, max_rhs=max_rhs, tile_blocks=tile_blocks, grid=grid, **kw)
+                   device=device, max_rhs=max_rhs, tile_blocks=tile_blocks, grid=grid,
+                   **kw_lanes, **kw)
+
+    def tune(self, reps: int = 3, stream=None) -> dict:
+        """Times candidate launch shapes of this plan's problem (sl1m_tune) in a
+        scratch workspace and returns the fastest; pass it to
+        Plan.from_workload(..., tuning=...)."""
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().sl1m_tune_workspace_bytes(ctypes.byref(self._prob), ctypes.byref(nbytes)))
+        ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        t = Tuning()
+        _check(lib().sl1m_tune(ctypes.byref(self._prob), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                               int(reps), _stream(stream), ctypes.byref(t)))
+        return t.as_dict()
 
     def info(self) -> dict:
         """The plan's decisions (sl1m_plan_query): grid evaluation, splits."""

@@ -53,6 +53,11 @@ def test_host_argument_checks(L):
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
     assert b"grid_mode" in L.sl1m_last_error()
     assert L.sl1m_plan_query(None, None) == sl1m.EINVAL
+    pr = sl1m.Problem(n_pix=10, l=fake, m=fake, n_vis=10, u=fake, v=fake, w=fake,
+                      precision=sl1m.PREC_FP32, grid_mode=sl1m.GRID_OFF, fwd_vpl=3)
+    assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    assert b"fwd_vpl" in L.sl1m_last_error()
+    assert L.sl1m_tune(None, None, 0, 1, None, None) == sl1m.EINVAL
     pr = sl1m.Problem(n_pix=10, n_vis=10, precision=sl1m.PREC_FP32)   # NULL l, m
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
     assert L.sl1m_forward(None, None, None, None) == sl1m.EINVAL
