@@ -43,6 +43,7 @@ struct Analysis {
   std::vector<double> grid_la, grid_mb, grid_c3, grid_c4;
   std::vector<int32_t> grid_slot;
   std::vector<GridChunk> grid_fc;
+  std::vector<GridPairBlock> grid_pb;
   int grid_vtiles = 0, grid_frows = 0;
   std::vector<Chunk> fd1, fg1, pd1, pg1;
 };
@@ -107,6 +108,7 @@ bool analyze_grid(Analysis& a, int si, const std::vector<double>& L, const std::
   }
   GridSeg g{};
   g.seg = si;
+  g.square = sg.kind == SL1M_PIX_DELTA && ul == um ? 1 : 0;
   g.kind = sg.kind;
   g.layer = sg.layer;
   g.na = static_cast<int32_t>(na);
@@ -334,17 +336,58 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     for (const GridSeg& g : a.gsegs) ng_total += g.ng;
     const int64_t per_split = static_cast<int64_t>(a.grid_vtiles) * ng_total;
     a.grid_fc.clear();
+    a.grid_pb.clear();
     for (GridSeg& g : a.gsegs) {
       int64_t split = (target_blocks + per_split - 1) / per_split;
       split = std::max<int64_t>(1, std::min<int64_t>(split, (g.na + 7) / 8));
       const int ra = static_cast<int>((g.na + split - 1) / split);
       g.fc0 = static_cast<int32_t>(a.grid_fc.size());
-      for (int gi = 0; gi < g.ng; ++gi)
-        for (int i0 = 0; i0 < g.na; i0 += ra)
-          a.grid_fc.push_back(GridChunk{gi, i0, std::min<int>(g.na, i0 + ra), 0});
+      if (!g.square) {
+        for (int gi = 0; gi < g.ng; ++gi)
+          for (int i0 = 0; i0 < g.na; i0 += ra)
+            a.grid_fc.push_back(GridChunk{gi, i0, std::min<int>(g.na, i0 + ra), 0});
+        g.nfs = static_cast<int32_t>(a.grid_fc.size()) - g.fc0;
+        const int64_t sets = static_cast<int64_t>(2) * g.ng * g.na;
+        g.ablocks = static_cast<int32_t>((sets + kBlock - 1) / kBlock);
+        g.pblocks = 0;
+      } else {
+        // forward: each group's diagonal block one cell at a time, then pairs
+        // (cell and its mirror) for the |l| values beyond the group, in ranges
+        // of about half the single-cell split (a pair is two cells of work)
+        for (int gi = 0; gi < g.ng; ++gi)
+          if (kGridNB * gi < g.na)
+            a.grid_fc.push_back(GridChunk{gi, kGridNB * gi, std::min(g.na, kGridNB * (gi + 1)), 0});
+        g.nfs = static_cast<int32_t>(a.grid_fc.size()) - g.fc0;
+        const int rp = std::max(8, ra / 2);
+        for (int gi = 0; gi < g.ng; ++gi)
+          for (int i0 = kGridNB * (gi + 1); i0 < g.na; i0 += rp)
+            a.grid_fc.push_back(GridChunk{gi, i0, std::min<int>(g.na, i0 + rp), 0});
+        // adjoint: diagonal lane-sets (one per |l| index), then pair blocks of
+        // the rows g4 (ia from kGridNBA (g4 + 1) to na), at most kBlock
+        // lane-sets and kGridMaxGL groups each
+        g.ablocks = static_cast<int32_t>((g.na + kBlock - 1) / kBlock);
+        g.pb0 = static_cast<int32_t>(a.grid_pb.size());
+        GridPairBlock cur{0, 0, 0, 0};
+        for (int g4 = 0; g4 < 2 * g.ng; ++g4) {
+          for (int pos = kGridNBA * (g4 + 1); pos < g.na;) {
+            if (cur.count == kBlock || (cur.count > 0 && g4 - cur.g4 + 1 > kGridMaxGL)) {
+              a.grid_pb.push_back(cur);
+              cur = GridPairBlock{0, 0, 0, 0};
+            }
+            if (cur.count == 0) {
+              cur.g4 = g4;
+              cur.ia = pos;
+            }
+            const int take = std::min(g.na - pos, kBlock - cur.count);
+            cur.count += take;
+            cur.n_gl = g4 - cur.g4 + 1;
+            pos += take;
+          }
+        }
+        if (cur.count > 0) a.grid_pb.push_back(cur);
+        g.pblocks = static_cast<int32_t>(a.grid_pb.size()) - g.pb0;
+      }
       g.nfc = static_cast<int32_t>(a.grid_fc.size()) - g.fc0;
-      const int64_t sets = static_cast<int64_t>(2) * g.ng * g.na;
-      g.ablocks = static_cast<int32_t>((sets + kBlock - 1) / kBlock);
     }
     a.grid_frows = static_cast<int>(a.grid_fc.size());
   }
@@ -353,7 +396,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   int64_t ptiles = static_cast<int64_t>(a.pd.size() + a.pg.size());
   if (a.grid) {
     ptiles = static_cast<int64_t>(a.pd1.size() + a.pg1.size());
-    for (const GridSeg& g : a.gsegs) ptiles += g.ablocks;
+    for (const GridSeg& g : a.gsegs) ptiles += g.ablocks + g.pblocks;
   }
   if (nv > 0 && ptiles > 0) {
     const int64_t cap = a.grid ? 256 : 64;
@@ -371,7 +414,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
       rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
-      grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, total;
+      grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -424,6 +467,7 @@ Layout layout(const Analysis& a) {
   L.grid_slot = take(4 * 4 * cells);
   L.grid_rec = take(sizeof(GridRec) * cells);
   L.grid_fc = take(sizeof(GridChunk) * a.grid_fc.size());
+  L.grid_pb = take(sizeof(GridPairBlock) * a.grid_pb.size());
   L.total = off;
   return L;
 }
@@ -667,6 +711,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       p->grid_slot = reinterpret_cast<int32_t*>(w + L.grid_slot);
       p->grid_rec = w + L.grid_rec;
       p->d_grid_fchunks = reinterpret_cast<GridChunk*>(w + L.grid_fc);
+      p->d_grid_pblocks = reinterpret_cast<GridPairBlock*>(w + L.grid_pb);
     }
 
     auto fail = [&](sl1m_status st_) {
@@ -708,6 +753,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       up(p->grid_c4, a.grid_c4.data(), 8 * a.grid_c4.size());
       up(p->grid_slot, a.grid_slot.data(), 4 * a.grid_slot.size());
       up(p->d_grid_fchunks, a.grid_fc.data(), sizeof(GridChunk) * a.grid_fc.size());
+      up(p->d_grid_pblocks, a.grid_pb.data(), sizeof(GridPairBlock) * a.grid_pb.size());
     }
     if (e == hipSuccess) e = launch_fill(p->flag, 1, sizeof(int), st);
     if (e == hipSuccess)

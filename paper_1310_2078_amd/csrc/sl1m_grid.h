@@ -115,6 +115,96 @@ __device__ __forceinline__ void grid_fwd_delta_tile(
   }
 }
 
+// Square delta grid, pair chunk: for every |l| index ia of the chunk and b of
+// the group, the cells (ia, b) and (b, ia) (when b < na) share C.  The partner
+// cell has A at |l|_b = |m|_b and B at |m|_ia = |l|_ia.  `mb` is the padded
+// |m| table (equal to |l| where defined).
+__device__ __forceinline__ void grid_fwd_delta_pairs_tile(
+    const GridRec* __restrict__ rec, const double* __restrict__ la,
+    const double* __restrict__ mb, const GridChunk& ch, int na, const double* __restrict__ vu,
+    const double* __restrict__ vv, const double* __restrict__ vw, int64_t vtile, int64_t n_vis,
+    float2* __restrict__ out) {
+  const ConstPtr<GridRec> crec = as_const(rec);
+  const ConstPtr<double> cla = as_const(la);
+  const ConstPtr<double> cmb = as_const(mb);
+  const int g = ch.g;
+  const int64_t kbase = vtile * (kBlock * kGridVPL) + threadIdx.x;
+  const double origin = kMagic;
+  double u[kGridVPL], v[kGridVPL], w[kGridVPL];
+  float bc[kGridNB][kGridVPL], bs[kGridNB][kGridVPL];   // B at |m|_b
+  float pc[kGridNB][kGridVPL], ps[kGridNB][kGridVPL];   // A at |l|_b (partner)
+  float ore[kGridVPL], oim[kGridVPL];
+#pragma unroll
+  for (int i = 0; i < kGridVPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    const bool ok = k < n_vis;
+    u[i] = ok ? vu[k] : 0.0;
+    v[i] = ok ? vv[k] : 0.0;
+    w[i] = ok ? vw[k] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kGridNB; ++b) {
+      const double m = cmb[g * kGridNB + b];
+      phasor(fma(v[i], m, origin), bc[b][i], bs[b][i]);
+      phasor(fma(u[i], m, origin), pc[b][i], ps[b][i]);
+    }
+    ore[i] = oim[i] = 0.0f;
+  }
+  for (int s0 = ch.ia0; s0 < ch.ia1; s0 += kGridSegIA) {
+    const int s1 = s0 + kGridSegIA < ch.ia1 ? s0 + kGridSegIA : ch.ia1;
+    float re[kGridVPL], imn[kGridVPL];
+#pragma unroll
+    for (int i = 0; i < kGridVPL; ++i) re[i] = imn[i] = 0.0f;
+    for (int ia = s0; ia < s1; ++ia) {
+      const double l = cla[ia];
+      float ac[kGridVPL], as[kGridVPL], qc[kGridVPL], qs[kGridVPL];  // A at |l|_ia, B at |m|_ia
+#pragma unroll
+      for (int i = 0; i < kGridVPL; ++i) {
+        phasor(fma(u[i], l, origin), ac[i], as[i]);
+        phasor(fma(v[i], l, origin), qc[i], qs[i]);
+      }
+      const int q0 = (g * na + ia) * kGridNB;
+      const int qp0 = ((ia / kGridNB) * na) * kGridNB + ia % kGridNB;
+#pragma unroll
+      for (int b = 0; b < kGridNB; ++b) {
+        const int bb = g * kGridNB + b;  // wavefront-uniform
+        const bool two = bb < na;
+        const int qp = qp0 + bb * kGridNB;
+        if (crec[q0 + b].empty && (!two || crec[qp].empty)) continue;
+        const double nu = crec[q0 + b].nu;
+        const float e1 = crec[q0 + b].e1, e2 = crec[q0 + b].e2;
+        const float e3 = crec[q0 + b].e3, e4 = crec[q0 + b].e4;
+        const float f1 = two ? crec[qp].e1 : 0.0f, f2 = two ? crec[qp].e2 : 0.0f;
+        const float f3 = two ? crec[qp].e3 : 0.0f, f4 = two ? crec[qp].e4 : 0.0f;
+#pragma unroll
+        for (int i = 0; i < kGridVPL; ++i) {
+          float cc, cs;
+          phasor(fma(w[i], nu, origin), cc, cs);
+          const float rs = fmaf(ac[i] * bc[b][i], e1,
+                                fmaf(as[i] * bs[b][i], e2,
+                                     fmaf(pc[b][i] * qc[i], f1, ps[b][i] * qs[i] * f2)));
+          const float is = fmaf(ac[i] * bs[b][i], e3,
+                                fmaf(as[i] * bc[b][i], e4,
+                                     fmaf(pc[b][i] * qs[i], f3, ps[b][i] * qc[i] * f4)));
+          re[i] = fmaf(cc, rs, re[i]);
+          re[i] = fmaf(-cs, is, re[i]);
+          imn[i] = fmaf(cc, is, imn[i]);
+          imn[i] = fmaf(cs, rs, imn[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kGridVPL; ++i) {
+      ore[i] += re[i];
+      oim[i] += imn[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kGridVPL; ++i) {
+    const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
+    if (k < n_vis) out[k] = make_float2(ore[i], -oim[i]);
+  }
+}
+
 // `vrec` and `Ds` are the layer's per-visibility records and (D, s) pairs.
 __device__ __forceinline__ void grid_fwd_gauss_tile(
     const GridRecG* __restrict__ rec, const double* __restrict__ la,
@@ -337,6 +427,193 @@ __device__ __forceinline__ void grid_adj_delta_tile(
     gs[bi][3] = o1[bi] - o2[bi] + o3[bi] + o4[bi];
   }
   grid_write(ls, slot, gs, out_row);
+}
+
+// Square delta grid, diagonal blocks: lane t owns |l| index ia = t and the
+// kGridNBA cells (ia, kGridNBA * (ia / kGridNBA) + bi); together the lanes
+// cover every cell whose indices fall in one group.  B is formed per lane
+// (these cells are a few percent of the grid).
+__device__ __forceinline__ void grid_adj_delta_diag_tile(
+    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ nu,
+    const int32_t* __restrict__ slot, int na, int64_t blk, int64_t kc, int64_t kchunk,
+    int64_t n_vis, float* __restrict__ out_row) {
+  const int64_t t = blk * kBlock + threadIdx.x;
+  if (t >= na) return;  // no block-wide synchronisation in this tile
+  const int ia = static_cast<int>(t), g4 = ia / kGridNBA;
+  LaneSet ls;
+  ls.active = true;
+  ls.ia = ia;
+  ls.qbase = ((g4 / 2) * na + ia) * kGridNB + (g4 % 2) * kGridNBA;
+  const double l = la[ia];
+  double nuv[kGridNBA], m[kGridNBA];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) {
+    nuv[bi] = nu[ls.qbase + bi];
+    m[bi] = mb[g4 * kGridNBA + bi];
+  }
+  const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
+  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
+  const double origin = kMagic;
+  const int k0 = static_cast<int>(kc * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  float o1[kGridNBA], o2[kGridNBA], o3[kGridNBA], o4[kGridNBA];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) o1[bi] = o2[bi] = o3[bi] = o4[bi] = 0.0f;
+  for (int kb = k0; kb < k1; kb += kSeg) {
+    const int ke = kb + kSeg < k1 ? kb + kSeg : k1;
+    float G1[kGridNBA], G2[kGridNBA], G3[kGridNBA], G4[kGridNBA];
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi) G1[bi] = G2[bi] = G3[bi] = G4[bi] = 0.0f;
+    for (int k = kb; k < ke; ++k) {
+      const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
+      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
+      float ac, as;
+      phasor(fma(u, l, origin), ac, as);
+#pragma unroll
+      for (int bi = 0; bi < kGridNBA; ++bi) {
+        float bc, bs, cc, cs;
+        phasor(fma(v, m[bi], origin), bc, bs);
+        phasor(fma(w, nuv[bi], origin), cc, cs);
+        const float z1 = fmaf(cc, rr, -cs * ri);
+        const float z2 = fmaf(cc, ri, cs * rr);
+        G1[bi] = fmaf(bc, ac * z1, G1[bi]);
+        G2[bi] = fmaf(bs, as * z1, G2[bi]);
+        G3[bi] = fmaf(bs, ac * z2, G3[bi]);
+        G4[bi] = fmaf(bc, as * z2, G4[bi]);
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi) {
+      o1[bi] += G1[bi];
+      o2[bi] += G2[bi];
+      o3[bi] += G3[bi];
+      o4[bi] += G4[bi];
+    }
+  }
+  float gs[kGridNBA][4];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) {
+    gs[bi][0] = o1[bi] - o2[bi] - o3[bi] - o4[bi];
+    gs[bi][1] = o1[bi] + o2[bi] - o3[bi] + o4[bi];
+    gs[bi][2] = o1[bi] + o2[bi] + o3[bi] - o4[bi];
+    gs[bi][3] = o1[bi] - o2[bi] + o3[bi] + o4[bi];
+  }
+  grid_write(ls, slot, gs, out_row);
+}
+
+// Square delta grid, pair blocks: lane-set (g4, ia) with ia beyond group g4
+// owns the cells (ia, kGridNBA * g4 + bi) and their partners
+// (kGridNBA * g4 + bi, ia).  The block's per-|m| factors B and the partners'
+// A (both at |m|_b = |l|_b) come from LDS; A and B at index ia per lane.
+__device__ __forceinline__ void grid_adj_delta_pairs_tile(
+    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
+    const double* __restrict__ mb, const double* __restrict__ nu,
+    const int32_t* __restrict__ slot, int na, const GridPairBlock& pb, int64_t kc,
+    int64_t kchunk, int64_t n_vis, float* __restrict__ out_row,
+    float4 (*bsh)[kGridMaxGL][kGridNBA]) {
+  // position of this lane in the block's row-major walk over (g4, ia)
+  int g4 = pb.g4, ia = pb.ia + static_cast<int>(threadIdx.x);
+  const bool active = static_cast<int>(threadIdx.x) < pb.count;
+  while (active && ia >= na) {
+    ++g4;
+    ia = ia - na + kGridNBA * (g4 + 1);
+  }
+  if (!active) {
+    g4 = pb.g4;
+    ia = 0;
+  }
+  const int gl = g4 - pb.g4;
+  const int qbase = ((g4 / 2) * na + ia) * kGridNB + (g4 % 2) * kGridNBA;
+  const double l = la[ia];
+  double nuv[kGridNBA];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) nuv[bi] = active ? nu[qbase + bi] : 0.0;
+  const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
+  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
+  const double origin = kMagic;
+  const int k0 = static_cast<int>(kc * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  float o[kGridNBA][8];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[bi][j] = 0.0f;
+  const int fill = kGridKBG * pb.n_gl * kGridNBA;
+  for (int kb = k0; kb < k1; kb += kGridKBG) {
+    __syncthreads();  // the previous batch's reads are done
+    for (int e = threadIdx.x; e < fill; e += kBlock) {
+      const int kk = e / (pb.n_gl * kGridNBA);
+      const int rem = e - kk * (pb.n_gl * kGridNBA);
+      const int gg = rem / kGridNBA, bi = rem - gg * kGridNBA;
+      const int k = kb + kk;
+      float bc = 0.0f, bs = 0.0f, ac = 0.0f, as = 0.0f;
+      if (k < k1) {
+        const double m = mb[(pb.g4 + gg) * kGridNBA + bi];
+        phasor(fma(vv[k], m, origin), bc, bs);
+        phasor(fma(vu[k], m, origin), ac, as);
+      }
+      bsh[kk][gg][bi] = make_float4(bc, bs, ac, as);
+    }
+    __syncthreads();
+    const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
+    float G[kGridNBA][8];
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) G[bi][j] = 0.0f;
+    for (int k = kb; k < ke; ++k) {
+      const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
+      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
+      float ac, as, qc, qs;  // A and B at index ia
+      phasor(fma(u, l, origin), ac, as);
+      phasor(fma(v, l, origin), qc, qs);
+      const float4* bp = &bsh[k - kb][gl][0];
+#pragma unroll
+      for (int bi = 0; bi < kGridNBA; ++bi) {
+        const float4 bb = bp[bi];  // B at b (x, y), A at b (z, w)
+        float cc, cs;
+        phasor(fma(w, nuv[bi], origin), cc, cs);
+        const float z1 = fmaf(cc, rr, -cs * ri);
+        const float z2 = fmaf(cc, ri, cs * rr);
+        // cell (ia, b): A at ia, B at b
+        G[bi][0] = fmaf(bb.x, ac * z1, G[bi][0]);
+        G[bi][1] = fmaf(bb.y, as * z1, G[bi][1]);
+        G[bi][2] = fmaf(bb.y, ac * z2, G[bi][2]);
+        G[bi][3] = fmaf(bb.x, as * z2, G[bi][3]);
+        // cell (b, ia): A at b, B at ia
+        G[bi][4] = fmaf(qc, bb.z * z1, G[bi][4]);
+        G[bi][5] = fmaf(qs, bb.w * z1, G[bi][5]);
+        G[bi][6] = fmaf(qs, bb.z * z2, G[bi][6]);
+        G[bi][7] = fmaf(qc, bb.w * z2, G[bi][7]);
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) o[bi][j] += G[bi][j];
+  }
+  if (!active) return;
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) {
+    const int64_t q = qbase + bi;
+    const int b = kGridNBA * g4 + bi;
+    const int64_t qp = (static_cast<int64_t>(ia / kGridNB) * na + b) * kGridNB + ia % kGridNB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && b >= na) break;  // padding |m| value: no partner cell
+      const float* G = &o[bi][4 * h];
+      const float gs[4] = {G[0] - G[1] - G[2] - G[3], G[0] + G[1] - G[2] + G[3],
+                           G[0] + G[1] + G[2] - G[3], G[0] - G[1] + G[2] + G[3]};
+      const int64_t qq = h ? qp : q;
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int32_t j = slot[4 * qq + s2];
+        if (j >= 0) out_row[j] = gs[s2];
+      }
+    }
+  }
 }
 
 // `vrec` and `rres` are the layer's records and residuals (D (1 - i s) conj(G) r).

@@ -69,6 +69,20 @@ __global__ __launch_bounds__(kBlock) void k_grid_fwd_delta(
                       part + static_cast<int64_t>(blockIdx.y) * n_vis);
 }
 
+__global__ __launch_bounds__(kBlock) void k_grid_fwd_delta_pairs(
+    const GridRec* __restrict__ rec, const double* __restrict__ la, const double* __restrict__ mb,
+    const GridChunk* __restrict__ chunks, int na, const double* __restrict__ vu,
+    const double* __restrict__ vv, const double* __restrict__ vw, int64_t n_vis,
+    float2* __restrict__ part) {
+  const ConstPtr<GridChunk> cc = as_const(chunks) + blockIdx.y;
+  GridChunk ch;
+  ch.g = cc->g;
+  ch.ia0 = cc->ia0;
+  ch.ia1 = cc->ia1;
+  grid_fwd_delta_pairs_tile(rec, la, mb, ch, na, vu, vv, vw, blockIdx.x, n_vis,
+                            part + static_cast<int64_t>(blockIdx.y) * n_vis);
+}
+
 __global__ __launch_bounds__(kBlock) void k_grid_fwd_gauss(
     const GridRecG* __restrict__ rec, const double* __restrict__ la,
     const double* __restrict__ mb, const GridChunk* __restrict__ chunks, int na,
@@ -96,6 +110,32 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_delta(
   __shared__ float2 bsh[kGridKB][kGridMaxGL][kGridNBA];
   grid_adj_delta_tile(vrec, rres, vv, la, mb, nu, slot, na, ng4, blockIdx.x, blockIdx.y, kchunk,
                       n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix, bsh);
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_adj_delta_diag(
+    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ nu,
+    const int32_t* __restrict__ slot, int na, int64_t kchunk, int64_t n_vis,
+    float* __restrict__ part, int64_t n_pix) {
+  grid_adj_delta_diag_tile(vrec, rres, la, mb, nu, slot, na, blockIdx.x, blockIdx.y, kchunk, n_vis,
+                           part + static_cast<int64_t>(blockIdx.y) * n_pix);
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_adj_delta_pairs(
+    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
+    const double* __restrict__ mb, const double* __restrict__ nu,
+    const int32_t* __restrict__ slot, int na, const GridPairBlock* __restrict__ blocks,
+    int64_t kchunk, int64_t n_vis, float* __restrict__ part, int64_t n_pix) {
+  __shared__ float4 bsh[kGridKBG][kGridMaxGL][kGridNBA];
+  const ConstPtr<GridPairBlock> cb = as_const(blocks) + blockIdx.x;
+  GridPairBlock pb;
+  pb.g4 = cb->g4;
+  pb.ia = cb->ia;
+  pb.count = cb->count;
+  pb.n_gl = cb->n_gl;
+  grid_adj_delta_pairs_tile(vrec, rres, vu, vv, la, mb, nu, slot, na, pb, blockIdx.y, kchunk,
+                            n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix, bsh);
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_adj_gauss(
@@ -129,8 +169,16 @@ hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
       GridRec* rec = static_cast<GridRec*>(p->grid_rec) + co;
       hipLaunchKernelGGL(k_grid_prep_delta, dim3(blocks_for(g.cells)), dim3(kBlock), 0, st, x,
                          scale, slot, p->grid_c3 + co, g.cells, rec);
-      hipLaunchKernelGGL(k_grid_fwd_delta, grid, dim3(kBlock), 0, st, rec, la, mb, ch, g.na, p->vu,
-                         p->vv, p->vw, p->n_vis, rows);
+      // single-cell chunks, then (square grids) pair chunks
+      const unsigned vt = static_cast<unsigned>(p->grid_vtiles);
+      if (g.nfs > 0)
+        hipLaunchKernelGGL(k_grid_fwd_delta, dim3(vt, static_cast<unsigned>(g.nfs)), dim3(kBlock),
+                           0, st, rec, la, mb, ch, g.na, p->vu, p->vv, p->vw, p->n_vis, rows);
+      if (g.nfc > g.nfs)
+        hipLaunchKernelGGL(k_grid_fwd_delta_pairs,
+                           dim3(vt, static_cast<unsigned>(g.nfc - g.nfs)), dim3(kBlock), 0, st,
+                           rec, la, mb, ch + g.nfs, g.na, p->vu, p->vv, p->vw, p->n_vis,
+                           rows + static_cast<int64_t>(g.nfs) * p->n_vis);
     } else {
       GridRecG* rec = static_cast<GridRecG*>(p->grid_rec) + co;
       hipLaunchKernelGGL(k_grid_prep_gauss, dim3(blocks_for(g.cells)), dim3(kBlock), 0, st, x,
@@ -155,7 +203,18 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st) {
     const double* mb = p->grid_mb + g.mb_off;
     const int32_t* slot = p->grid_slot + 4 * co;
     const dim3 grid(static_cast<unsigned>(g.ablocks), static_cast<unsigned>(p->n_achunks));
-    if (g.kind == SL1M_PIX_DELTA) {
+    if (g.kind == SL1M_PIX_DELTA && g.square) {
+      const VisRecD<float>* vrec = static_cast<const VisRecD<float>*>(p->visrecD);
+      if (g.ablocks > 0)
+        hipLaunchKernelGGL(k_grid_adj_delta_diag, grid, dim3(kBlock), 0, st, vrec, rres, la, mb,
+                           p->grid_c3 + co, slot, g.na, p->adj_kchunk, p->n_vis, part, p->n_pix);
+      if (g.pblocks > 0)
+        hipLaunchKernelGGL(k_grid_adj_delta_pairs,
+                           dim3(static_cast<unsigned>(g.pblocks), static_cast<unsigned>(p->n_achunks)),
+                           dim3(kBlock), 0, st, vrec, rres, p->vu, p->vv, la, mb, p->grid_c3 + co,
+                           slot, g.na, p->d_grid_pblocks + g.pb0, p->adj_kchunk, p->n_vis, part,
+                           p->n_pix);
+    } else if (g.kind == SL1M_PIX_DELTA) {
       hipLaunchKernelGGL(k_grid_adj_delta, grid, dim3(kBlock), 0, st,
                          static_cast<const VisRecD<float>*>(p->visrecD), rres, p->vv, la, mb,
                          p->grid_c3 + co, slot, g.na, 2 * g.ng, p->adj_kchunk, p->n_vis, part,

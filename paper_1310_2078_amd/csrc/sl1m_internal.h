@@ -102,6 +102,18 @@ struct GridChunk {       // forward: one |m| group times an |l| range
   int32_t g, ia0, ia1, pad;
 };
 
+// Square delta grids (the |l| values equal the |m| values): cells (a, b) and
+// (b, a) have the same l^2 + m^2 and share C.  The cells of each group's
+// diagonal block (a and b in one group) are evaluated one by one; every other
+// cell as half of a pair (a, b) + (b, a) with a beyond b's group.  Adjoint
+// pair blocks: lane-sets (g4, ia) with ia >= kGridNBA * (g4 + 1), row-major,
+// at most kBlock lane-sets and kGridMaxGL groups per block.
+struct GridPairBlock {
+  int32_t g4, ia;        // first lane-set of the block
+  int32_t count;         // lane-sets in the block
+  int32_t n_gl;          // groups the block touches
+};
+
 // One segment on the grid path and where its tables live in the plan's
 // concatenated grid arrays.
 struct GridSeg {
@@ -112,7 +124,10 @@ struct GridSeg {
   int64_t cells;         // ng * kGridNB * na
   int64_t la_off, mb_off, cell_off;
   int32_t fc0, nfc;      // forward chunks [fc0, fc0 + nfc) = partial rows
-  int32_t ablocks;       // adjoint blocks of kBlock lane-sets
+  int32_t nfs;           // the first nfs chunks take cells one by one, the rest in pairs
+  int32_t square;        // 1: square delta grid (pairs)
+  int32_t ablocks;       // adjoint blocks: all lane-sets (not square) or the diagonal blocks
+  int32_t pblocks, pb0;  // square: pair blocks, first entry in the pair-block table
   int32_t pad;
 };
 
@@ -158,6 +173,7 @@ struct sl1m_plan {
   int32_t* grid_slot = nullptr;   // [4 * cells] permuted pixel index or -1
   void* grid_rec = nullptr;       // [cells] per-call GridRec / GridRecG records
   sl1m::GridChunk* d_grid_fchunks = nullptr;
+  sl1m::GridPairBlock* d_grid_pblocks = nullptr;
   sl1m::Chunk* d_chunks1 = nullptr;         // fd1 | fg1 | pd1 | pg1
 
   // device buffers (carved from the workspace)

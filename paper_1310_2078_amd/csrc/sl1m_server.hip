@@ -31,11 +31,13 @@ using sched::Segment;
 constexpr int kSrvMaxSlots = 64;
 constexpr int kSrvRing = 4;              // rounds in flight (table buffers)
 constexpr int kSrvTileBlocks = 8192;     // per-request operator split target (work-item count)
-// item tables per round: 4 operator kinds x 5 variants (4 direct tile shapes,
-// then the grid evaluation), then reduce, update, final and the grid prep
-// (delta, Gaussian)
-constexpr int kOpVariants = 5;
-constexpr int kGridVariant = 4;
+// item tables per round: 4 operator kinds x 6 variants (4 direct tile shapes,
+// the grid evaluation, the square-grid evaluation), then reduce, update, final
+// and the grid prep (delta, Gaussian).  A square delta grid request files its
+// single-cell forward chunks and diagonal adjoint blocks under the delta
+// kinds and its pair chunks and pair blocks under the Gaussian kinds.
+constexpr int kOpVariants = 6;
+constexpr int kGridVariant = 4, kSquareVariant = 5;
 constexpr int kTabReduce = 4 * kOpVariants, kTabUpdate = kTabReduce + 1,
               kTabFinal = kTabReduce + 2, kTabPrepD = kTabReduce + 3, kTabPrepG = kTabReduce + 4,
               kTabs = kTabReduce + 5;
@@ -88,8 +90,9 @@ struct ReqDev {
   const VisRecG<float>* g_vrec;    // the layer's records (Gaussian)
   const float* g_Ds;               // the layer's (D, s) pairs (Gaussian)
   const float2* g_lres;            // the layer's residual records
+  const GridPairBlock* g_pblocks;  // square grids: adjoint pair blocks
   int64_t g_cells;
-  int32_t g_na, g_ng, g_vtiles, g_pad;
+  int32_t g_na, g_ng, g_vtiles, g_nfs;
 };
 
 __device__ __forceinline__ int find_seg(const TabDev* __restrict__ tab, int64_t w) {
@@ -383,6 +386,59 @@ __global__ __launch_bounds__(kBlock) void k_srv_gadj(const TabDev* __restrict__ 
                         reinterpret_cast<float2(*)[kGridMaxGL][kGridNBA]>(lds));
 }
 
+// Square delta grids: pair forward chunks (items over chunks nfs.., rows
+// nfs..), diagonal adjoint blocks and pair adjoint blocks.
+__global__ __launch_bounds__(kBlock) void k_srv_gfwd_pairs(const TabDev* __restrict__ tab,
+                                                           const ReqDev* __restrict__ reqs) {
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nvt = static_cast<uint32_t>(q.g_vtiles);
+  const int64_t c = __builtin_amdgcn_readfirstlane(static_cast<int>(q.g_nfs + item / nvt));
+  const int64_t vt = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nvt));
+  const ConstPtr<GridChunk> cc = as_const(q.g_fchunks) + c;
+  GridChunk ch;
+  ch.g = cc->g;
+  ch.ia0 = cc->ia0;
+  ch.ia1 = cc->ia1;
+  grid_fwd_delta_pairs_tile(static_cast<const GridRec*>(q.g_rec), q.g_la, q.g_mb, ch, q.g_na,
+                            q.vu, q.vv, q.vw, vt, q.n_vis, q.fpart + c * q.n_vis);
+}
+
+__global__ __launch_bounds__(kBlock) void k_srv_gadj_diag(const TabDev* __restrict__ tab,
+                                                          const ReqDev* __restrict__ reqs) {
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
+  const int64_t blk = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nac));
+  grid_adj_delta_diag_tile(q.visrecD, q.rres, q.g_la, q.g_mb, q.g_c3, q.g_slot, q.g_na, blk, kc,
+                           q.kchunk, q.n_vis, q.apart + kc * q.n_pix);
+}
+
+__global__ __launch_bounds__(kBlock) void k_srv_gadj_pairs(const TabDev* __restrict__ tab,
+                                                           const ReqDev* __restrict__ reqs) {
+  __shared__ float4 lds[kGridKBG][kGridMaxGL][kGridNBA];
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
+  const int64_t bi = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nac));
+  const ConstPtr<GridPairBlock> cb = as_const(q.g_pblocks) + bi;
+  GridPairBlock pb;
+  pb.g4 = cb->g4;
+  pb.ia = cb->ia;
+  pb.count = cb->count;
+  pb.n_gl = cb->n_gl;
+  grid_adj_delta_pairs_tile(q.visrecD, q.rres, q.vu, q.vv, q.g_la, q.g_mb, q.g_c3, q.g_slot,
+                            q.g_na, pb, kc, q.kchunk, q.n_vis, q.apart + kc * q.n_pix, lds);
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -616,10 +672,13 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
       q.g_Ds = static_cast<const float*>(plan->layerDs) + static_cast<int64_t>(g.layer) * 2 * plan->n_vis;
       q.g_lres = static_cast<const float2*>(plan->rres) + static_cast<int64_t>(1 + g.layer) * plan->n_vis;
     }
+    q.g_pblocks = plan->d_grid_pblocks + g.pb0;
     q.g_cells = g.cells;
     q.g_na = g.na;
     q.g_ng = g.ng;
     q.g_vtiles = plan->grid_vtiles;
+    q.g_nfs = g.nfs;
+    if (g.square) gkind = 3;
   }
   q.n_achunks = plan->n_achunks;
   q.n_pd = static_cast<int32_t>(plan->ptiles_delta.size());
@@ -633,15 +692,25 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   q.thr = power ? 0.0 : t.params.lambda / t.params.L;
   q.xscale = xscale;
   auto variant = [&](int per_lane) { return plan->beam_pair ? 3 : (per_lane == 4 ? 2 : per_lane == 2 ? 1 : 0); };
-  s->fwd_variant[t.req.slot] = static_cast<int8_t>(gkind ? kGridVariant : variant(q.vpl));
-  s->adj_variant[t.req.slot] = static_cast<int8_t>(gkind ? kGridVariant : variant(q.ppl));
-  s->grid_kind[t.req.slot] = static_cast<int8_t>(gkind);
+  const int gvar = gkind == 3 ? kSquareVariant : kGridVariant;
+  s->fwd_variant[t.req.slot] = static_cast<int8_t>(gkind ? gvar : variant(q.vpl));
+  s->adj_variant[t.req.slot] = static_cast<int8_t>(gkind ? gvar : variant(q.ppl));
+  s->grid_kind[t.req.slot] = static_cast<int8_t>(gkind == 3 ? 1 : gkind);
   SRV_HIP(hipMemcpyAsync(s->d_reqs + t.req.slot, &q, sizeof(ReqDev), hipMemcpyHostToDevice, st),
           "upload request descriptor");
   SRV_HIP(hipStreamSynchronize(st), "admission sync");
   // work-item counts
   sched::Shape& sh = t.req.shape;
-  if (gkind) {
+  if (gkind == 3) {
+    // square delta grid: singles/diagonal under the delta kinds, pairs under
+    // the Gaussian kinds (routed to the square-grid variant)
+    const GridSeg& g = plan->grid_segs[0];
+    sh.fwd_delta = static_cast<int64_t>(g.nfs) * q.g_vtiles;
+    sh.fwd_gauss = static_cast<int64_t>(g.nfc - g.nfs) * q.g_vtiles;
+    sh.adj_delta = static_cast<int64_t>(g.ablocks) * q.n_achunks;
+    sh.adj_gauss = static_cast<int64_t>(g.pblocks) * q.n_achunks;
+    sh.prep_blocks = (g.cells + kBlock - 1) / kBlock;
+  } else if (gkind) {
     // one grid segment: all items are of its kind
     const GridSeg& g = plan->grid_segs[0];
     const int64_t nf = static_cast<int64_t>(g.nfc) * q.g_vtiles;
@@ -737,22 +806,26 @@ sl1m_status launch_round(sl1m_server* s) {
   if (e == hipSuccess) e = go(2, k_srv_fwd<false, 4, false>, cr);
   if (e == hipSuccess) e = go(3, k_srv_fwd<false, 4, true>, cr);
   if (e == hipSuccess) e = go(kGridVariant, k_srv_gfwd<false>, cr);
+  if (e == hipSuccess) e = go(kSquareVariant, k_srv_gfwd<false>, cr);
   if (e == hipSuccess) e = go(kOpVariants + 0, k_srv_fwd<true, 1, false>, cr);
   if (e == hipSuccess) e = go(kOpVariants + 1, k_srv_fwd<true, 2, false>, cr);
   if (e == hipSuccess) e = go(kOpVariants + 2, k_srv_fwd<true, 4, false>, cr);
   if (e == hipSuccess) e = go(kOpVariants + 3, k_srv_fwd<true, 4, true>, cr);
   if (e == hipSuccess) e = go(kOpVariants + kGridVariant, k_srv_gfwd<true>, cr);
+  if (e == hipSuccess) e = go(kOpVariants + kSquareVariant, k_srv_gfwd_pairs, cr);
   if (e == hipSuccess) e = go(kTabReduce, k_srv_reduce, r);
   if (e == hipSuccess) e = go(2 * kOpVariants + 0, k_srv_adj<false, 1, false>, cr);
   if (e == hipSuccess) e = go(2 * kOpVariants + 1, k_srv_adj<false, 2, false>, cr);
   if (e == hipSuccess) e = go(2 * kOpVariants + 2, k_srv_adj<false, 4, false>, cr);
   if (e == hipSuccess) e = go(2 * kOpVariants + 3, k_srv_adj<false, 4, true>, cr);
   if (e == hipSuccess) e = go(2 * kOpVariants + kGridVariant, k_srv_gadj<false>, cr);
+  if (e == hipSuccess) e = go(2 * kOpVariants + kSquareVariant, k_srv_gadj_diag, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 0, k_srv_adj<true, 1, false>, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 1, k_srv_adj<true, 2, false>, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 2, k_srv_adj<true, 4, false>, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 3, k_srv_adj<true, 4, true>, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + kGridVariant, k_srv_gadj<true>, cr);
+  if (e == hipSuccess) e = go(3 * kOpVariants + kSquareVariant, k_srv_gadj_pairs, cr);
   if (e == hipSuccess) e = go(kTabUpdate, k_srv_update, r);
   if (e == hipSuccess) e = go(kTabFinal, k_srv_final, r);
   if (e != hipSuccess) return hip_error(e, "batched round launch");
