@@ -90,8 +90,10 @@ def ingest_counters(fetch_csv, write_csv):
         scale = CALIB_BYTES / (sum(big) / len(big))
         for key, pat in (("k_fwd_delta<float,4>", "k_fwd_delta<float, 4, false, 1>"),
                          ("k_adj_delta<float,4>", "k_adj_delta<float, 4, false, 1>"),
-                         ("k_grid_fwd_delta", "k_grid_fwd_delta"),
-                         ("k_grid_adj_delta", "k_grid_adj_delta")):
+                         ("k_grid_fwd_delta_pairs", "k_grid_fwd_delta_pairs"),
+                         ("k_grid_adj_delta_pairs", "k_grid_adj_delta_pairs"),
+                         ("k_grid_fwd_delta", "k_grid_fwd_delta("),
+                         ("k_grid_adj_delta", "k_grid_adj_delta(")):
             vals = [v for n, v in rows if pat in n]
             if vals:
                 rec = out.setdefault(key, {"source_hash": kernel_source_hash(key)})
@@ -319,8 +321,12 @@ def main():
     adj_avg = adj_ms / max(adj_n, 1)
     pinfo = plan.info()
     grid = bool(pinfo["grid"])
-    names = (("k_grid_adj_delta", "k_grid_fwd_delta") if grid
-             else ("k_adj_delta<float,4>", "k_fwd_delta<float,4>"))
+    if grid and pinfo["grid_pairs"]:
+        names = ("k_grid_adj_delta_pairs", "k_grid_fwd_delta_pairs")
+    elif grid:
+        names = ("k_grid_adj_delta", "k_grid_fwd_delta")
+    else:
+        names = ("k_adj_delta<float,4>", "k_fwd_delta<float,4>")
     if adj_avg >= fwd_avg:
         dom, dom_ms, dom_name = "adjoint", adj_avg, names[0]
     else:
@@ -377,7 +383,8 @@ def main():
             "flop_per_eval": FLOP_PER_EVAL_DELTA,
             "evals_per_launch": n_pix * n_vis,
             "accounting": "canonical delta-eval FLOPs (14 per entry); the grid evaluation "
-                          "issues about 6 FP32-FMA-equivalent slots per entry" if grid else
+                          "issues fewer instructions per entry (one sincos per 4 entries, "
+                          "per 8 for mirrored pairs)" if grid else
                           "canonical delta-eval FLOPs (14 per entry)",
         },
     }

@@ -210,7 +210,8 @@ typedef struct {
   int32_t n_fchunks;        /* split-K partial rows of the forward (direct)     */
   int32_t n_fchunks_grid;   /* ... of the forward with the grid evaluation      */
   int32_t n_achunks;        /* visibility chunks of the adjoint                 */
-  int32_t reserved[5];
+  int32_t grid_pairs;       /* grid segments evaluated as mirrored cell pairs   */
+  int32_t reserved[4];
 } sl1m_plan_info;
 
 sl1m_status sl1m_plan_query(const sl1m_plan* plan, sl1m_plan_info* info);

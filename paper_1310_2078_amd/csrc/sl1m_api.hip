@@ -44,6 +44,7 @@ struct Analysis {
   std::vector<int32_t> grid_slot;
   std::vector<GridChunk> grid_fc;
   std::vector<GridPairBlock> grid_pb;
+  std::vector<int2> grid_gb;   // Gaussian adjoint blocks (segment, block)
   int grid_vtiles = 0, grid_frows = 0;
   std::vector<Chunk> fd1, fg1, pd1, pg1;
 };
@@ -390,6 +391,10 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
       g.nfc = static_cast<int32_t>(a.grid_fc.size()) - g.fc0;
     }
     a.grid_frows = static_cast<int>(a.grid_fc.size());
+    a.grid_gb.clear();
+    for (int si = 0; si < static_cast<int>(a.gsegs.size()); ++si)
+      if (a.gsegs[si].kind != SL1M_PIX_DELTA)
+        for (int b = 0; b < a.gsegs[si].ablocks; ++b) a.grid_gb.push_back(int2{si, b});
   }
 
   // ---- visibility chunks of the adjoint (shared by all of its kernels)
@@ -414,7 +419,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
       rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
-      grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, total;
+      grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -468,6 +473,8 @@ Layout layout(const Analysis& a) {
   L.grid_rec = take(sizeof(GridRec) * cells);
   L.grid_fc = take(sizeof(GridChunk) * a.grid_fc.size());
   L.grid_pb = take(sizeof(GridPairBlock) * a.grid_pb.size());
+  L.grid_segs = take(sizeof(GridSeg) * a.gsegs.size());
+  L.grid_gb = take(sizeof(int2) * a.grid_gb.size());
   L.total = off;
   return L;
 }
@@ -712,6 +719,9 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       p->grid_rec = w + L.grid_rec;
       p->d_grid_fchunks = reinterpret_cast<GridChunk*>(w + L.grid_fc);
       p->d_grid_pblocks = reinterpret_cast<GridPairBlock*>(w + L.grid_pb);
+      p->d_grid_segs = reinterpret_cast<GridSeg*>(w + L.grid_segs);
+      p->d_grid_gblocks = reinterpret_cast<int2*>(w + L.grid_gb);
+      p->grid_gblocks = static_cast<int>(a.grid_gb.size());
     }
 
     auto fail = [&](sl1m_status st_) {
@@ -754,6 +764,8 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       up(p->grid_slot, a.grid_slot.data(), 4 * a.grid_slot.size());
       up(p->d_grid_fchunks, a.grid_fc.data(), sizeof(GridChunk) * a.grid_fc.size());
       up(p->d_grid_pblocks, a.grid_pb.data(), sizeof(GridPairBlock) * a.grid_pb.size());
+      up(p->d_grid_segs, a.gsegs.data(), sizeof(GridSeg) * a.gsegs.size());
+      up(p->d_grid_gblocks, a.grid_gb.data(), sizeof(int2) * a.grid_gb.size());
     }
     if (e == hipSuccess) e = launch_fill(p->flag, 1, sizeof(int), st);
     if (e == hipSuccess)
@@ -1007,6 +1019,7 @@ sl1m_status sl1m_plan_query(const sl1m_plan* p, sl1m_plan_info* info) {
   r.n_fchunks = p->n_fchunks;
   r.n_fchunks_grid = p->grid ? forward_rows(p, 1) : 0;
   r.n_achunks = p->n_achunks;
+  for (const GridSeg& g : p->grid_segs) r.grid_pairs += g.square ? 1 : 0;
   *info = r;
   return SL1M_OK;
 }

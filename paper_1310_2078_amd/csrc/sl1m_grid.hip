@@ -1,7 +1,8 @@
 // Grid evaluation of the operators (gfx950, float32 plans): kernels and
 // launchers.  The factorisation and the tiles are in sl1m_grid.h.  Every
-// segment on the grid path gets one forward and one adjoint launch (a plan
-// has at most 17 segments: the delta pixels and 16 Gaussian layers).
+// segment on the grid path gets a prep launch and its forward and adjoint
+// launches (two each for a square delta grid: single cells and pairs); a plan
+// has at most 17 segments, the delta pixels and 16 Gaussian layers.
 #include "sl1m_grid.h"
 
 namespace sl1m {
@@ -138,14 +139,24 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_delta_pairs(
                             n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix, bsh);
 }
 
-__global__ __launch_bounds__(kBlock) void k_grid_adj_gauss(
+// All Gaussian grid segments in one launch: block x of the (block, chunk)
+// grid maps to (segment, block within the segment) through `gblocks`, so a
+// plan with several small layers still fills the GPU with one launch.
+__global__ __launch_bounds__(kBlock) void k_grid_adj_gauss_multi(
+    const int2* __restrict__ gblocks, const GridSeg* __restrict__ segs,
     const VisRecG<float>* __restrict__ vrec, const float2* __restrict__ rres,
-    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ r2,
-    const double* __restrict__ kap, const int32_t* __restrict__ slot, int na, int ng4,
-    int64_t kchunk, int64_t n_vis, float* __restrict__ part, int64_t n_pix) {
+    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ c3,
+    const double* __restrict__ c4, const int32_t* __restrict__ slot, int64_t kchunk,
+    int64_t n_vis, float* __restrict__ part, int64_t n_pix) {
   __shared__ float4 bsh[kGridKBG][kGridMaxGL][kGridNBA];
-  grid_adj_gauss_tile(vrec, rres, la, mb, r2, kap, slot, na, ng4, blockIdx.x, blockIdx.y, kchunk,
-                      n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix, bsh);
+  const ConstPtr<int2> cgb = as_const(gblocks) + blockIdx.x;
+  const int si = cgb->x, blk = cgb->y;
+  const ConstPtr<GridSeg> cs = as_const(segs) + si;
+  const int64_t co = cs->cell_off, layer = cs->layer;
+  grid_adj_gauss_tile(vrec + layer * n_vis, rres + (1 + layer) * n_vis, la + cs->la_off,
+                      mb + cs->mb_off, c3 + co, c4 + co, slot + 4 * co, cs->na, 2 * cs->ng, blk,
+                      blockIdx.y, kchunk, n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix,
+                      bsh);
 }
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
@@ -219,16 +230,17 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st) {
                          static_cast<const VisRecD<float>*>(p->visrecD), rres, p->vv, la, mb,
                          p->grid_c3 + co, slot, g.na, 2 * g.ng, p->adj_kchunk, p->n_vis, part,
                          p->n_pix);
-    } else {
-      const VisRecG<float>* vrec =
-          static_cast<const VisRecG<float>*>(p->visrecG) + static_cast<int64_t>(g.layer) * p->n_vis;
-      // residual records of layer L (single right-hand side): slot 1 + L
-      const float2* lres = rres + static_cast<int64_t>(1 + g.layer) * p->n_vis;
-      hipLaunchKernelGGL(k_grid_adj_gauss, grid, dim3(kBlock), 0, st, vrec, lres, la, mb,
-                         p->grid_c3 + co, p->grid_c4 + co, slot, g.na, 2 * g.ng, p->adj_kchunk,
-                         p->n_vis, part, p->n_pix);
     }
   }
+  // every Gaussian grid segment in one launch (residual records of layer L,
+  // single right-hand side: slot 1 + L)
+  if (p->grid_gblocks > 0)
+    hipLaunchKernelGGL(k_grid_adj_gauss_multi,
+                       dim3(static_cast<unsigned>(p->grid_gblocks), static_cast<unsigned>(p->n_achunks)),
+                       dim3(kBlock), 0, st, p->d_grid_gblocks, p->d_grid_segs,
+                       static_cast<const VisRecG<float>*>(p->visrecG), rres, p->grid_la,
+                       p->grid_mb, p->grid_c3, p->grid_c4, p->grid_slot, p->adj_kchunk, p->n_vis,
+                       part, p->n_pix);
   return hipGetLastError();
 }
 

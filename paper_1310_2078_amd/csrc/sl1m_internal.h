@@ -174,6 +174,9 @@ struct sl1m_plan {
   void* grid_rec = nullptr;       // [cells] per-call GridRec / GridRecG records
   sl1m::GridChunk* d_grid_fchunks = nullptr;
   sl1m::GridPairBlock* d_grid_pblocks = nullptr;
+  sl1m::GridSeg* d_grid_segs = nullptr;     // device copy of grid_segs
+  int2* d_grid_gblocks = nullptr;           // Gaussian adjoint blocks: (segment, block)
+  int grid_gblocks = 0;
   sl1m::Chunk* d_chunks1 = nullptr;         // fd1 | fg1 | pd1 | pg1
 
   // device buffers (carved from the workspace)

@@ -203,7 +203,8 @@ class PlanInfo(ctypes.Structure):
         ("grid_positions", ctypes.c_int64),
         ("fwd_vpl", ctypes.c_int32), ("adj_ppl", ctypes.c_int32),
         ("n_fchunks", ctypes.c_int32), ("n_fchunks_grid", ctypes.c_int32),
-        ("n_achunks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+        ("n_achunks", ctypes.c_int32), ("grid_pairs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
     def as_dict(self):
