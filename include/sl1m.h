@@ -316,7 +316,10 @@ sl1m_status sl1m_timing_end(sl1m_plan* plan, sl1m_timing* out /* host */);
  * budget / 32) evaluations (at least one work item, never past the end of its
  * current phase), so small requests finish a whole FISTA iteration per round
  * while large ones advance part of one; under OLDEST_FIRST the earliest
- * admitted request may take the whole budget and the others budget / 64.
+ * admitted request may take the whole budget, requests of at most 32 budgets
+ * of work in total budget / 4, and the others budget / 64 (close to
+ * first-come-first-served for the tail, small requests not queued behind
+ * large ones).
  * A request whose pixels form one grid segment (see sl1m_grid_mode) runs the
  * grid evaluation; other requests the direct one.  A request's arithmetic and
  * summation order depend only on its own problem: its image is bitwise the
@@ -346,8 +349,8 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
 
 typedef enum {
   SL1M_SERVE_FAIR = 0,         /* equal shares of each round (default)          */
-  SL1M_SERVE_OLDEST_FIRST = 1  /* the earliest admitted request first, a floor of
-                                  work for the others                           */
+  SL1M_SERVE_OLDEST_FIRST = 1  /* the earliest admitted request first, small
+                                  requests expedited, a floor for the others    */
 } sl1m_serve_policy;
 
 /* Selects how rounds are shared from the next round on.  SL1M_EINVAL for an
