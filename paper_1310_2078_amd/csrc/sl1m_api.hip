@@ -45,6 +45,7 @@ struct Analysis {
   std::vector<GridChunk> grid_fc;
   std::vector<GridPairBlock> grid_pb;
   std::vector<int2> grid_gb;   // Gaussian adjoint blocks (segment, block)
+  int64_t grid_pairs = 0;      // pair records of all square segments
   int grid_vtiles = 0, grid_frows = 0;
   std::vector<Chunk> fd1, fg1, pd1, pg1;
 };
@@ -338,6 +339,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     const int64_t per_split = static_cast<int64_t>(a.grid_vtiles) * ng_total;
     a.grid_fc.clear();
     a.grid_pb.clear();
+    a.grid_pairs = 0;
     for (GridSeg& g : a.gsegs) {
       int64_t split = (target_blocks + per_split - 1) / per_split;
       split = std::max<int64_t>(1, std::min<int64_t>(split, (g.na + 7) / 8));
@@ -352,25 +354,21 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
         g.ablocks = static_cast<int32_t>((sets + kBlock - 1) / kBlock);
         g.pblocks = 0;
       } else {
-        // forward: each group's diagonal block one cell at a time, then pairs
-        // (cell and its mirror) for the |l| values beyond the group, in ranges
-        // of about half the single-cell split (a pair is two cells of work)
-        for (int gi = 0; gi < g.ng; ++gi)
-          if (kGridNB * gi < g.na)
-            a.grid_fc.push_back(GridChunk{gi, kGridNB * gi, std::min(g.na, kGridNB * (gi + 1)), 0});
-        g.nfs = static_cast<int32_t>(a.grid_fc.size()) - g.fc0;
+        // forward: pair records of the |l| values from each group's first one
+        // on, in ranges of about half the single-cell split (a pair is two
+        // cells of work)
+        g.nfs = 0;
         const int rp = std::max(8, ra / 2);
         for (int gi = 0; gi < g.ng; ++gi)
-          for (int i0 = kGridNB * (gi + 1); i0 < g.na; i0 += rp)
+          for (int i0 = kGridNB * gi; i0 < g.na; i0 += rp)
             a.grid_fc.push_back(GridChunk{gi, i0, std::min<int>(g.na, i0 + rp), 0});
-        // adjoint: diagonal lane-sets (one per |l| index), then pair blocks of
-        // the rows g4 (ia from kGridNBA (g4 + 1) to na), at most kBlock
-        // lane-sets and kGridMaxGL groups each
-        g.ablocks = static_cast<int32_t>((g.na + kBlock - 1) / kBlock);
+        // adjoint: pair blocks of the rows g4 (ia from kGridNBA g4 to na), at
+        // most kBlock lane-sets and kGridMaxGL groups each
+        g.ablocks = 0;
         g.pb0 = static_cast<int32_t>(a.grid_pb.size());
         GridPairBlock cur{0, 0, 0, 0};
         for (int g4 = 0; g4 < 2 * g.ng; ++g4) {
-          for (int pos = kGridNBA * (g4 + 1); pos < g.na;) {
+          for (int pos = kGridNBA * g4; pos < g.na;) {
             if (cur.count == kBlock || (cur.count > 0 && g4 - cur.g4 + 1 > kGridMaxGL)) {
               a.grid_pb.push_back(cur);
               cur = GridPairBlock{0, 0, 0, 0};
@@ -387,6 +385,11 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
         }
         if (cur.count > 0) a.grid_pb.push_back(cur);
         g.pblocks = static_cast<int32_t>(a.grid_pb.size()) - g.pb0;
+        // pair records of the forward: groups g with kGridNB g < na
+        const int gp = (g.na + kGridNB - 1) / kGridNB;
+        g.pr_off = a.grid_pairs;
+        g.n_pairs = pair_rec_base(gp, g.na);
+        a.grid_pairs += g.n_pairs;
       }
       g.nfc = static_cast<int32_t>(a.grid_fc.size()) - g.fc0;
     }
@@ -419,7 +422,8 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
       rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
-      grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb, total;
+      grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb,
+      grid_prec, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -475,6 +479,7 @@ Layout layout(const Analysis& a) {
   L.grid_pb = take(sizeof(GridPairBlock) * a.grid_pb.size());
   L.grid_segs = take(sizeof(GridSeg) * a.gsegs.size());
   L.grid_gb = take(sizeof(int2) * a.grid_gb.size());
+  L.grid_prec = take(sizeof(GridPairRec) * static_cast<size_t>(a.grid_pairs));
   L.total = off;
   return L;
 }
@@ -722,6 +727,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       p->d_grid_segs = reinterpret_cast<GridSeg*>(w + L.grid_segs);
       p->d_grid_gblocks = reinterpret_cast<int2*>(w + L.grid_gb);
       p->grid_gblocks = static_cast<int>(a.grid_gb.size());
+      p->grid_prec = reinterpret_cast<GridPairRec*>(w + L.grid_prec);
     }
 
     auto fail = [&](sl1m_status st_) {

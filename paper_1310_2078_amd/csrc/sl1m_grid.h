@@ -85,7 +85,9 @@ __device__ __forceinline__ void grid_fwd_delta_tile(
       const int q0 = (g * na + ia) * kGridNB;
 #pragma unroll
       for (int b = 0; b < kGridNB; ++b) {
-        if (crec[q0 + b].empty) continue;  // wavefront-uniform
+        // no test of `empty` here: a branch on it would make every record
+        // cost two scalar-load round trips, and an empty cell's amplitudes
+        // are zero, so it adds exactly nothing
         const double nu = crec[q0 + b].nu;
         const float e1 = crec[q0 + b].e1, e2 = crec[q0 + b].e2;
         const float e3 = crec[q0 + b].e3, e4 = crec[q0 + b].e4;
@@ -115,16 +117,66 @@ __device__ __forceinline__ void grid_fwd_delta_tile(
   }
 }
 
+// Writes pair record p of a square delta grid (layout of GridPairRec) from
+// the amplitudes x_j = xs * scale_j * xp_j of the two cells' sign slots.
+__device__ __forceinline__ void grid_write_pair_rec(int64_t p, int na,
+                                                    const int32_t* __restrict__ slot,
+                                                    const double* __restrict__ nu,
+                                                    const float* __restrict__ xp,
+                                                    const float* __restrict__ pscale, float xs,
+                                                    GridPairRec* __restrict__ rec) {
+  // groups with records: kGridNB g < na; the record offsets increase over them
+  const int ngroups = (na + kGridNB - 1) / kGridNB;
+  int g = 0;
+  while (g + 1 < ngroups && pair_rec_base(g + 1, na) <= p) ++g;
+  const int64_t li = p - pair_rec_base(g, na);
+  const int ia = kGridNB * g + static_cast<int>(li / kGridNB);
+  const int b = static_cast<int>(li % kGridNB), bb = kGridNB * g + b;
+  const int64_t q = (static_cast<int64_t>(g) * na + ia) * kGridNB + b;
+  float x[4], y[4];
+  int32_t empty = 1;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int32_t j = bb <= ia ? slot[4 * q + s] : -1;
+    x[s] = j >= 0 ? pscale[j] * xs * xp[j] : 0.0f;
+    empty &= j < 0 ? 1 : 0;
+    y[s] = 0.0f;
+  }
+  if (bb < ia) {
+    const int64_t qp = (static_cast<int64_t>(ia / kGridNB) * na + bb) * kGridNB + ia % kGridNB;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int32_t j = slot[4 * qp + s];
+      y[s] = j >= 0 ? pscale[j] * xs * xp[j] : 0.0f;
+      empty &= j < 0 ? 1 : 0;
+    }
+  }
+  GridPairRec r;
+  r.nu = nu[q];
+  r.e1 = (x[0] + x[1]) + (x[2] + x[3]);
+  r.e2 = (x[1] + x[2]) - (x[0] + x[3]);
+  r.e3 = (x[0] + x[1]) - (x[2] + x[3]);
+  r.e4 = (x[0] - x[1]) + (x[2] - x[3]);
+  r.f1 = (y[0] + y[1]) + (y[2] + y[3]);
+  r.f2 = (y[1] + y[2]) - (y[0] + y[3]);
+  r.f3 = (y[0] + y[1]) - (y[2] + y[3]);
+  r.f4 = (y[0] - y[1]) + (y[2] - y[3]);
+  r.empty = empty;
+  r.pad = 0;
+  rec[p] = r;
+}
+
 // Square delta grid, pair chunk: for every |l| index ia of the chunk and b of
-// the group, the cells (ia, b) and (b, ia) (when b < na) share C.  The partner
+// the group, the cells (ia, b) and (b, ia) (when b < na) share C; their
+// amplitudes come from one pair record (GridPairRec).  The partner
 // cell has A at |l|_b = |m|_b and B at |m|_ia = |l|_ia.  `mb` is the padded
 // |m| table (equal to |l| where defined).
 __device__ __forceinline__ void grid_fwd_delta_pairs_tile(
-    const GridRec* __restrict__ rec, const double* __restrict__ la,
+    const GridPairRec* __restrict__ rec, const double* __restrict__ la,
     const double* __restrict__ mb, const GridChunk& ch, int na, const double* __restrict__ vu,
     const double* __restrict__ vv, const double* __restrict__ vw, int64_t vtile, int64_t n_vis,
     float2* __restrict__ out) {
-  const ConstPtr<GridRec> crec = as_const(rec);
+  const ConstPtr<GridPairRec> crec = as_const(rec);
   const ConstPtr<double> cla = as_const(la);
   const ConstPtr<double> cmb = as_const(mb);
   const int g = ch.g;
@@ -162,19 +214,14 @@ __device__ __forceinline__ void grid_fwd_delta_pairs_tile(
         phasor(fma(u[i], l, origin), ac[i], as[i]);
         phasor(fma(v[i], l, origin), qc[i], qs[i]);
       }
-      const int q0 = (g * na + ia) * kGridNB;
-      const int qp0 = ((ia / kGridNB) * na) * kGridNB + ia % kGridNB;
+      const int p0 = static_cast<int>(pair_rec_base(g, na)) + (ia - kGridNB * g) * kGridNB;
 #pragma unroll
       for (int b = 0; b < kGridNB; ++b) {
-        const int bb = g * kGridNB + b;  // wavefront-uniform
-        const bool two = bb < na;
-        const int qp = qp0 + bb * kGridNB;
-        if (crec[q0 + b].empty && (!two || crec[qp].empty)) continue;
-        const double nu = crec[q0 + b].nu;
-        const float e1 = crec[q0 + b].e1, e2 = crec[q0 + b].e2;
-        const float e3 = crec[q0 + b].e3, e4 = crec[q0 + b].e4;
-        const float f1 = two ? crec[qp].e1 : 0.0f, f2 = two ? crec[qp].e2 : 0.0f;
-        const float f3 = two ? crec[qp].e3 : 0.0f, f4 = two ? crec[qp].e4 : 0.0f;
+        const double nu = crec[p0 + b].nu;
+        const float e1 = crec[p0 + b].e1, e2 = crec[p0 + b].e2;
+        const float e3 = crec[p0 + b].e3, e4 = crec[p0 + b].e4;
+        const float f1 = crec[p0 + b].f1, f2 = crec[p0 + b].f2;
+        const float f3 = crec[p0 + b].f3, f4 = crec[p0 + b].f4;  // (no `empty` test, as above)
 #pragma unroll
         for (int i = 0; i < kGridVPL; ++i) {
           float cc, cs;
@@ -429,82 +476,9 @@ __device__ __forceinline__ void grid_adj_delta_tile(
   grid_write(ls, slot, gs, out_row);
 }
 
-// Square delta grid, diagonal blocks: lane t owns |l| index ia = t and the
-// kGridNBA cells (ia, kGridNBA * (ia / kGridNBA) + bi); together the lanes
-// cover every cell whose indices fall in one group.  B is formed per lane
-// (these cells are a few percent of the grid).
-__device__ __forceinline__ void grid_adj_delta_diag_tile(
-    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
-    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ nu,
-    const int32_t* __restrict__ slot, int na, int64_t blk, int64_t kc, int64_t kchunk,
-    int64_t n_vis, float* __restrict__ out_row) {
-  const int64_t t = blk * kBlock + threadIdx.x;
-  if (t >= na) return;  // no block-wide synchronisation in this tile
-  const int ia = static_cast<int>(t), g4 = ia / kGridNBA;
-  LaneSet ls;
-  ls.active = true;
-  ls.ia = ia;
-  ls.qbase = ((g4 / 2) * na + ia) * kGridNB + (g4 % 2) * kGridNBA;
-  const double l = la[ia];
-  double nuv[kGridNBA], m[kGridNBA];
-#pragma unroll
-  for (int bi = 0; bi < kGridNBA; ++bi) {
-    nuv[bi] = nu[ls.qbase + bi];
-    m[bi] = mb[g4 * kGridNBA + bi];
-  }
-  const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
-  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
-  const double origin = kMagic;
-  const int k0 = static_cast<int>(kc * kchunk);
-  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
-  float o1[kGridNBA], o2[kGridNBA], o3[kGridNBA], o4[kGridNBA];
-#pragma unroll
-  for (int bi = 0; bi < kGridNBA; ++bi) o1[bi] = o2[bi] = o3[bi] = o4[bi] = 0.0f;
-  for (int kb = k0; kb < k1; kb += kSeg) {
-    const int ke = kb + kSeg < k1 ? kb + kSeg : k1;
-    float G1[kGridNBA], G2[kGridNBA], G3[kGridNBA], G4[kGridNBA];
-#pragma unroll
-    for (int bi = 0; bi < kGridNBA; ++bi) G1[bi] = G2[bi] = G3[bi] = G4[bi] = 0.0f;
-    for (int k = kb; k < ke; ++k) {
-      const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
-      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
-      float ac, as;
-      phasor(fma(u, l, origin), ac, as);
-#pragma unroll
-      for (int bi = 0; bi < kGridNBA; ++bi) {
-        float bc, bs, cc, cs;
-        phasor(fma(v, m[bi], origin), bc, bs);
-        phasor(fma(w, nuv[bi], origin), cc, cs);
-        const float z1 = fmaf(cc, rr, -cs * ri);
-        const float z2 = fmaf(cc, ri, cs * rr);
-        G1[bi] = fmaf(bc, ac * z1, G1[bi]);
-        G2[bi] = fmaf(bs, as * z1, G2[bi]);
-        G3[bi] = fmaf(bs, ac * z2, G3[bi]);
-        G4[bi] = fmaf(bc, as * z2, G4[bi]);
-      }
-    }
-#pragma unroll
-    for (int bi = 0; bi < kGridNBA; ++bi) {
-      o1[bi] += G1[bi];
-      o2[bi] += G2[bi];
-      o3[bi] += G3[bi];
-      o4[bi] += G4[bi];
-    }
-  }
-  float gs[kGridNBA][4];
-#pragma unroll
-  for (int bi = 0; bi < kGridNBA; ++bi) {
-    gs[bi][0] = o1[bi] - o2[bi] - o3[bi] - o4[bi];
-    gs[bi][1] = o1[bi] + o2[bi] - o3[bi] + o4[bi];
-    gs[bi][2] = o1[bi] + o2[bi] + o3[bi] - o4[bi];
-    gs[bi][3] = o1[bi] - o2[bi] + o3[bi] + o4[bi];
-  }
-  grid_write(ls, slot, gs, out_row);
-}
-
-// Square delta grid, pair blocks: lane-set (g4, ia) with ia beyond group g4
-// owns the cells (ia, kGridNBA * g4 + bi) and their partners
-// (kGridNBA * g4 + bi, ia).  The block's per-|m| factors B and the partners'
+// Square delta grid, pair blocks: lane-set (g4, ia) with ia >= kGridNBA g4
+// owns the cells (ia, b) and their mirrors (b, ia), b = kGridNBA g4 + bi
+// (written as GridPairBlock describes).  The block's per-|m| factors B and the partners'
 // A (both at |m|_b = |l|_b) come from LDS; A and B at index ia per lane.
 __device__ __forceinline__ void grid_adj_delta_pairs_tile(
     const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
@@ -518,7 +492,7 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
   const bool active = static_cast<int>(threadIdx.x) < pb.count;
   while (active && ia >= na) {
     ++g4;
-    ia = ia - na + kGridNBA * (g4 + 1);
+    ia = ia - na + kGridNBA * g4;
   }
   if (!active) {
     g4 = pb.g4;
@@ -602,7 +576,9 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
     const int64_t qp = (static_cast<int64_t>(ia / kGridNB) * na + b) * kGridNB + ia % kGridNB;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      if (h == 1 && b >= na) break;  // padding |m| value: no partner cell
+      // the cell when b <= ia, its mirror when b < ia (other cells belong to
+      // the lane-set of the mirror)
+      if (h == 0 ? b > ia : b >= ia) continue;
       const float* G = &o[bi][4 * h];
       const float gs[4] = {G[0] - G[1] - G[2] - G[3], G[0] + G[1] - G[2] + G[3],
                            G[0] + G[1] + G[2] - G[3], G[0] - G[1] + G[2] + G[3]};

@@ -37,6 +37,15 @@ __global__ void k_grid_prep_delta(const float* __restrict__ xp, const float* __r
   rec[q] = r;
 }
 
+// Per-call pair records of a square delta segment.
+__global__ void k_grid_prep_pairs(const float* __restrict__ xp, const float* __restrict__ pscale,
+                                  const int32_t* __restrict__ slot, const double* __restrict__ nu,
+                                  int na, int64_t n_pairs, GridPairRec* __restrict__ rec) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  grid_write_pair_rec(p, na, slot, nu, xp, pscale, 1.0f, rec);
+}
+
 // Per-call forward records of a Gaussian segment.
 __global__ void k_grid_prep_gauss(const float* __restrict__ xp, const float* __restrict__ pscale,
                                   const int32_t* __restrict__ slot, const double* __restrict__ r2,
@@ -71,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_fwd_delta(
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_fwd_delta_pairs(
-    const GridRec* __restrict__ rec, const double* __restrict__ la, const double* __restrict__ mb,
+    const GridPairRec* __restrict__ rec, const double* __restrict__ la, const double* __restrict__ mb,
     const GridChunk* __restrict__ chunks, int na, const double* __restrict__ vu,
     const double* __restrict__ vv, const double* __restrict__ vw, int64_t n_vis,
     float2* __restrict__ part) {
@@ -113,16 +122,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_delta(
                       n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix, bsh);
 }
 
-__global__ __launch_bounds__(kBlock) void k_grid_adj_delta_diag(
-    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
-    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ nu,
-    const int32_t* __restrict__ slot, int na, int64_t kchunk, int64_t n_vis,
-    float* __restrict__ part, int64_t n_pix) {
-  grid_adj_delta_diag_tile(vrec, rres, la, mb, nu, slot, na, blockIdx.x, blockIdx.y, kchunk, n_vis,
-                           part + static_cast<int64_t>(blockIdx.y) * n_pix);
-}
-
-__global__ __launch_bounds__(kBlock) void k_grid_adj_delta_pairs(
+// Square delta grid adjoint: one pair block per block x (GridPairBlock).
+__global__ __launch_bounds__(kBlock) void k_grid_adj_delta_square(
     const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
     const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
     const double* __restrict__ mb, const double* __restrict__ nu,
@@ -185,11 +186,15 @@ hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
       if (g.nfs > 0)
         hipLaunchKernelGGL(k_grid_fwd_delta, dim3(vt, static_cast<unsigned>(g.nfs)), dim3(kBlock),
                            0, st, rec, la, mb, ch, g.na, p->vu, p->vv, p->vw, p->n_vis, rows);
-      if (g.nfc > g.nfs)
+      if (g.nfc > g.nfs) {
+        GridPairRec* prec = p->grid_prec + g.pr_off;
+        hipLaunchKernelGGL(k_grid_prep_pairs, dim3(blocks_for(g.n_pairs)), dim3(kBlock), 0, st, x,
+                           scale, slot, p->grid_c3 + co, g.na, g.n_pairs, prec);
         hipLaunchKernelGGL(k_grid_fwd_delta_pairs,
                            dim3(vt, static_cast<unsigned>(g.nfc - g.nfs)), dim3(kBlock), 0, st,
-                           rec, la, mb, ch + g.nfs, g.na, p->vu, p->vv, p->vw, p->n_vis,
+                           prec, la, mb, ch + g.nfs, g.na, p->vu, p->vv, p->vw, p->n_vis,
                            rows + static_cast<int64_t>(g.nfs) * p->n_vis);
+      }
     } else {
       GridRecG* rec = static_cast<GridRecG*>(p->grid_rec) + co;
       hipLaunchKernelGGL(k_grid_prep_gauss, dim3(blocks_for(g.cells)), dim3(kBlock), 0, st, x,
@@ -215,16 +220,12 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st) {
     const int32_t* slot = p->grid_slot + 4 * co;
     const dim3 grid(static_cast<unsigned>(g.ablocks), static_cast<unsigned>(p->n_achunks));
     if (g.kind == SL1M_PIX_DELTA && g.square) {
-      const VisRecD<float>* vrec = static_cast<const VisRecD<float>*>(p->visrecD);
-      if (g.ablocks > 0)
-        hipLaunchKernelGGL(k_grid_adj_delta_diag, grid, dim3(kBlock), 0, st, vrec, rres, la, mb,
-                           p->grid_c3 + co, slot, g.na, p->adj_kchunk, p->n_vis, part, p->n_pix);
       if (g.pblocks > 0)
-        hipLaunchKernelGGL(k_grid_adj_delta_pairs,
+        hipLaunchKernelGGL(k_grid_adj_delta_square,
                            dim3(static_cast<unsigned>(g.pblocks), static_cast<unsigned>(p->n_achunks)),
-                           dim3(kBlock), 0, st, vrec, rres, p->vu, p->vv, la, mb, p->grid_c3 + co,
-                           slot, g.na, p->d_grid_pblocks + g.pb0, p->adj_kchunk, p->n_vis, part,
-                           p->n_pix);
+                           dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD),
+                           rres, p->vu, p->vv, la, mb, p->grid_c3 + co, slot, g.na,
+                           p->d_grid_pblocks + g.pb0, p->adj_kchunk, p->n_vis, part, p->n_pix);
     } else if (g.kind == SL1M_PIX_DELTA) {
       hipLaunchKernelGGL(k_grid_adj_delta, grid, dim3(kBlock), 0, st,
                          static_cast<const VisRecD<float>*>(p->visrecD), rres, p->vv, la, mb,

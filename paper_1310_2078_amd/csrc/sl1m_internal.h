@@ -98,16 +98,36 @@ struct GridRecG {
 };
 static_assert(sizeof(GridRec) == sizeof(GridRecG), "grid records share one buffer");
 
+// Per-call forward record of a mirrored pair (square delta grids), for |l|
+// index ia and |m| index bb = kGridNB g + b: bb < ia: cell (ia, bb) (e) and
+// its mirror (bb, ia) (f), which share n - 1; bb == ia: the cell alone (f = 0);
+// bb > ia: nothing (zero record; the mirror's own record covers the cell).
+// Records are ordered as the forward sweeps them: group g, then ia from
+// kGridNB g to n_a - 1, then b; group g starts at record
+// kGridNB (g n_a - (kGridNB / 2) g (g - 1)).
+struct GridPairRec {
+  double nu;
+  float e1, e2, e3, e4;
+  float f1, f2, f3, f4;
+  int32_t empty, pad;
+};
+
+__host__ __device__ inline int64_t pair_rec_base(int g, int na) {
+  return static_cast<int64_t>(kGridNB) *
+         (static_cast<int64_t>(g) * na - (kGridNB / 2) * static_cast<int64_t>(g) * (g - 1));
+}
+
 struct GridChunk {       // forward: one |m| group times an |l| range
   int32_t g, ia0, ia1, pad;
 };
 
 // Square delta grids (the |l| values equal the |m| values): cells (a, b) and
-// (b, a) have the same l^2 + m^2 and share C.  The cells of each group's
-// diagonal block (a and b in one group) are evaluated one by one; every other
-// cell as half of a pair (a, b) + (b, a) with a beyond b's group.  Adjoint
-// pair blocks: lane-sets (g4, ia) with ia >= kGridNBA * (g4 + 1), row-major,
-// at most kBlock lane-sets and kGridMaxGL groups per block.
+// (b, a) have the same l^2 + m^2 and share C, so every cell off the diagonal
+// is evaluated as half of a pair (a, b) + (b, a) with a > b, and each
+// diagonal cell alone.  Adjoint pair blocks: lane-sets (g4, ia) with
+// ia >= kGridNBA g4, row-major, at most kBlock lane-sets and kGridMaxGL
+// groups per block; lane-set (g4, ia) writes cell (ia, b) when b <= ia and the
+// mirror (b, ia) when b < ia, b = kGridNBA g4 + bi.
 struct GridPairBlock {
   int32_t g4, ia;        // first lane-set of the block
   int32_t count;         // lane-sets in the block
@@ -124,11 +144,11 @@ struct GridSeg {
   int64_t cells;         // ng * kGridNB * na
   int64_t la_off, mb_off, cell_off;
   int32_t fc0, nfc;      // forward chunks [fc0, fc0 + nfc) = partial rows
-  int32_t nfs;           // the first nfs chunks take cells one by one, the rest in pairs
+  int32_t nfs;           // chunks taking cells one by one (all, unless square)
   int32_t square;        // 1: square delta grid (pairs)
-  int32_t ablocks;       // adjoint blocks: all lane-sets (not square) or the diagonal blocks
+  int32_t ablocks;       // adjoint blocks of lane-sets (not square)
   int32_t pblocks, pb0;  // square: pair blocks, first entry in the pair-block table
-  int32_t pad;
+  int64_t pr_off, n_pairs;  // square: pair records [pr_off, pr_off + n_pairs)
 };
 
 }  // namespace sl1m
@@ -172,6 +192,7 @@ struct sl1m_plan {
   double* grid_c4 = nullptr;      // per cell: kappa (wide-field Gaussian) or 0
   int32_t* grid_slot = nullptr;   // [4 * cells] permuted pixel index or -1
   void* grid_rec = nullptr;       // [cells] per-call GridRec / GridRecG records
+  sl1m::GridPairRec* grid_prec = nullptr;   // per-call pair records (square grids)
   sl1m::GridChunk* d_grid_fchunks = nullptr;
   sl1m::GridPairBlock* d_grid_pblocks = nullptr;
   sl1m::GridSeg* d_grid_segs = nullptr;     // device copy of grid_segs

@@ -34,8 +34,7 @@ constexpr int kSrvTileBlocks = 8192;     // per-request operator split target (w
 // item tables per round: 4 operator kinds x 6 variants (4 direct tile shapes,
 // the grid evaluation, the square-grid evaluation), then reduce, update, final
 // and the grid prep (delta, Gaussian).  A square delta grid request files its
-// single-cell forward chunks and diagonal adjoint blocks under the delta
-// kinds and its pair chunks and pair blocks under the Gaussian kinds.
+// pair chunks and pair blocks under the Gaussian kinds.
 constexpr int kOpVariants = 6;
 constexpr int kGridVariant = 4, kSquareVariant = 5;
 constexpr int kTabReduce = 4 * kOpVariants, kTabUpdate = kTabReduce + 1,
@@ -91,6 +90,8 @@ struct ReqDev {
   const float* g_Ds;               // the layer's (D, s) pairs (Gaussian)
   const float2* g_lres;            // the layer's residual records
   const GridPairBlock* g_pblocks;  // square grids: adjoint pair blocks
+  GridPairRec* g_prec;             // square grids: forward pair records
+  int64_t g_npairs;
   int64_t g_cells;
   int32_t g_na, g_ng, g_vtiles, g_nfs;
 };
@@ -307,9 +308,11 @@ __global__ __launch_bounds__(kBlock) void k_srv_gprep(const TabDev* __restrict__
   const SegDev sg = tab->seg[find_seg(tab, w)];
   const ReqDev& q = reqs[sg.slot];
   const int64_t c = (sg.begin + (w - sg.prefix)) * kBlock + threadIdx.x;
-  if (c >= q.g_cells) return;
   const float* xp = (sg.flags & sched::F_POWER) ? q.x : (sg.flags & sched::F_OBJECTIVE) ? q.img : q.y;
   const float xs = (sg.flags & sched::F_POWER) ? static_cast<float>(q.xscale) : 1.0f;
+  if (!GAUSS && c < q.g_npairs)  // square grids: pair records too
+    grid_write_pair_rec(c, q.g_na, q.g_slot, q.g_c3, xp, q.pscale, xs, q.g_prec);
+  if (c >= q.g_cells) return;
   float x[4];
   int32_t empty = 1;
 #pragma unroll
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_srv_gadj(const TabDev* __restrict__ 
 }
 
 // Square delta grids: pair forward chunks (items over chunks nfs.., rows
-// nfs..), diagonal adjoint blocks and pair adjoint blocks.
+// nfs..) and pair adjoint blocks.
 __global__ __launch_bounds__(kBlock) void k_srv_gfwd_pairs(const TabDev* __restrict__ tab,
                                                            const ReqDev* __restrict__ reqs) {
   const int64_t w = blockIdx.x;
@@ -402,21 +405,8 @@ __global__ __launch_bounds__(kBlock) void k_srv_gfwd_pairs(const TabDev* __restr
   ch.g = cc->g;
   ch.ia0 = cc->ia0;
   ch.ia1 = cc->ia1;
-  grid_fwd_delta_pairs_tile(static_cast<const GridRec*>(q.g_rec), q.g_la, q.g_mb, ch, q.g_na,
-                            q.vu, q.vv, q.vw, vt, q.n_vis, q.fpart + c * q.n_vis);
-}
-
-__global__ __launch_bounds__(kBlock) void k_srv_gadj_diag(const TabDev* __restrict__ tab,
-                                                          const ReqDev* __restrict__ reqs) {
-  const int64_t w = blockIdx.x;
-  const SegDev sg = tab->seg[find_seg(tab, w)];
-  const ReqDev& q = reqs[sg.slot];
-  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
-  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
-  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
-  const int64_t blk = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nac));
-  grid_adj_delta_diag_tile(q.visrecD, q.rres, q.g_la, q.g_mb, q.g_c3, q.g_slot, q.g_na, blk, kc,
-                           q.kchunk, q.n_vis, q.apart + kc * q.n_pix);
+  grid_fwd_delta_pairs_tile(q.g_prec, q.g_la, q.g_mb, ch, q.g_na, q.vu, q.vv, q.vw, vt, q.n_vis,
+                            q.fpart + c * q.n_vis);
 }
 
 __global__ __launch_bounds__(kBlock) void k_srv_gadj_pairs(const TabDev* __restrict__ tab,
@@ -673,6 +663,8 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
       q.g_lres = static_cast<const float2*>(plan->rres) + static_cast<int64_t>(1 + g.layer) * plan->n_vis;
     }
     q.g_pblocks = plan->d_grid_pblocks + g.pb0;
+    q.g_prec = g.square ? plan->grid_prec + g.pr_off : nullptr;
+    q.g_npairs = g.square ? g.n_pairs : 0;
     q.g_cells = g.cells;
     q.g_na = g.na;
     q.g_ng = g.ng;
@@ -702,14 +694,14 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   // work-item counts
   sched::Shape& sh = t.req.shape;
   if (gkind == 3) {
-    // square delta grid: singles/diagonal under the delta kinds, pairs under
-    // the Gaussian kinds (routed to the square-grid variant)
+    // square delta grid: pair items under the Gaussian kinds (routed to the
+    // square-grid variant); no single-cell items
     const GridSeg& g = plan->grid_segs[0];
     sh.fwd_delta = static_cast<int64_t>(g.nfs) * q.g_vtiles;
     sh.fwd_gauss = static_cast<int64_t>(g.nfc - g.nfs) * q.g_vtiles;
     sh.adj_delta = static_cast<int64_t>(g.ablocks) * q.n_achunks;
     sh.adj_gauss = static_cast<int64_t>(g.pblocks) * q.n_achunks;
-    sh.prep_blocks = (g.cells + kBlock - 1) / kBlock;
+    sh.prep_blocks = (std::max(g.cells, g.n_pairs) + kBlock - 1) / kBlock;
   } else if (gkind) {
     // one grid segment: all items are of its kind
     const GridSeg& g = plan->grid_segs[0];
@@ -826,7 +818,6 @@ sl1m_status launch_round(sl1m_server* s) {
   if (e == hipSuccess) e = go(2 * kOpVariants + 2, k_srv_adj<false, 4, false>, cr);
   if (e == hipSuccess) e = go(2 * kOpVariants + 3, k_srv_adj<false, 4, true>, cr);
   if (e == hipSuccess) e = go(2 * kOpVariants + kGridVariant, k_srv_gadj<false>, cr);
-  if (e == hipSuccess) e = go(2 * kOpVariants + kSquareVariant, k_srv_gadj_diag, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 0, k_srv_adj<true, 1, false>, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 1, k_srv_adj<true, 2, false>, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 2, k_srv_adj<true, 4, false>, cr);
