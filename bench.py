@@ -91,7 +91,7 @@ def ingest_counters(fetch_csv, write_csv):
         for key, pat in (("k_fwd_delta<float,4>", "k_fwd_delta<float, 4, false, 1>"),
                          ("k_adj_delta<float,4>", "k_adj_delta<float, 4, false, 1>"),
                          ("k_grid_fwd_delta_pairs", "k_grid_fwd_delta_pairs"),
-                         ("k_grid_adj_delta_pairs", "k_grid_adj_delta_pairs"),
+                         ("k_grid_adj_delta_square", "k_grid_adj_delta_square"),
                          ("k_grid_fwd_delta", "k_grid_fwd_delta("),
                          ("k_grid_adj_delta", "k_grid_adj_delta(")):
             vals = [v for n, v in rows if pat in n]
@@ -211,7 +211,7 @@ def extras(plan2, wl2, dev):
         "adjoint_kernel_ms": t4["adjoint"][1] / max(t4["adjoint"][0], 1),
         "evals_per_s": 2 * wl4.n_pix * wl4.n_vis / (tf + ta),
         "fista_iteration_s_est": tf + ta,
-        "algorithmic_tflops": 2 * flops / (tf + ta) / 1e12}
+        "canonical_tflops": 2 * flops / (tf + ta) / 1e12}
     del p4, x4, V4, g4
     # config 1: plain SL1M in FP64 (100 iterations + 30 power steps)
     wl1 = W.config1()
@@ -322,7 +322,7 @@ def main():
     pinfo = plan.info()
     grid = bool(pinfo["grid"])
     if grid and pinfo["grid_pairs"]:
-        names = ("k_grid_adj_delta_pairs", "k_grid_fwd_delta_pairs")
+        names = ("k_grid_adj_delta_square", "k_grid_fwd_delta_pairs")
     elif grid:
         names = ("k_grid_adj_delta", "k_grid_fwd_delta")
     else:
@@ -331,6 +331,7 @@ def main():
         dom, dom_ms, dom_name = "adjoint", adj_avg, names[0]
     else:
         dom, dom_ms, dom_name = "forward", fwd_avg, names[1]
+    exec_flop = 4.5 if (grid and pinfo["grid_pairs"]) else 6.0 if grid else float(FLOP_PER_EVAL_DELTA)
     flops = FLOP_PER_EVAL_DELTA * n_pix * n_vis
     achieved = flops / (dom_ms * 1e-3) / 1e12
     out = {
@@ -382,9 +383,15 @@ def main():
             "traffic": load_traffic(dom_name),
             "flop_per_eval": FLOP_PER_EVAL_DELTA,
             "evals_per_launch": n_pix * n_vis,
-            "accounting": "canonical delta-eval FLOPs (14 per entry); the grid evaluation "
-                          "issues fewer instructions per entry (one sincos per 4 entries, "
-                          "per 8 for mirrored pairs)" if grid else
+            # the same counting rules applied to the work the kernel executes:
+            # a mirrored pair of cells (8 entries) takes 36 FLOP, a single cell
+            # (4 entries) 24, a direct entry 14
+            "executed_flop_per_eval": exec_flop,
+            "executed_achieved": exec_flop * n_pix * n_vis / (dom_ms * 1e-3) / 1e12,
+            "executed_frac": exec_flop * n_pix * n_vis / (dom_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+            "accounting": "achieved/frac: canonical delta-eval FLOPs (14 per entry, the "
+                          "direct evaluation); executed_*: the grid evaluation's own count "
+                          "(one sincos per 4 entries, per 8 for mirrored pairs)" if grid else
                           "canonical delta-eval FLOPs (14 per entry)",
         },
     }

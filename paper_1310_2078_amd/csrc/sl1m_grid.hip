@@ -179,8 +179,9 @@ hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
     const dim3 grid(static_cast<unsigned>(p->grid_vtiles), static_cast<unsigned>(g.nfc));
     if (g.kind == SL1M_PIX_DELTA) {
       GridRec* rec = static_cast<GridRec*>(p->grid_rec) + co;
-      hipLaunchKernelGGL(k_grid_prep_delta, dim3(blocks_for(g.cells)), dim3(kBlock), 0, st, x,
-                         scale, slot, p->grid_c3 + co, g.cells, rec);
+      if (g.nfs > 0)  // cell records (a square grid's forward reads pair records only)
+        hipLaunchKernelGGL(k_grid_prep_delta, dim3(blocks_for(g.cells)), dim3(kBlock), 0, st, x,
+                           scale, slot, p->grid_c3 + co, g.cells, rec);
       // single-cell chunks, then (square grids) pair chunks
       const unsigned vt = static_cast<unsigned>(p->grid_vtiles);
       if (g.nfs > 0)
