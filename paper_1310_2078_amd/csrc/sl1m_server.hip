@@ -459,7 +459,7 @@ struct sl1m_server {
   sl1m::sched::Arena alloc;
   int max_slots = 0;
   double budget = 3e10;                // evals per round, shared by the active requests
-  int policy = SL1M_SERVE_FAIR;        // how the round budget is shared
+  int policy = SL1M_SERVE_OLDEST_FIRST;  // how the round budget is shared
   hipStream_t stream = nullptr;        // rounds (non-blocking, default priority)
   hipStream_t admit_stream = nullptr;  // plan creation of admitted requests
   hipEvent_t admit_event = nullptr;
