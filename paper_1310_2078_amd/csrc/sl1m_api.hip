@@ -110,7 +110,7 @@ bool analyze_grid(Analysis& a, int si, const std::vector<double>& L, const std::
   }
   GridSeg g{};
   g.seg = si;
-  g.square = sg.kind == SL1M_PIX_DELTA && ul == um ? 1 : 0;
+  g.square = ul == um ? 1 : 0;
   g.kind = sg.kind;
   g.layer = sg.layer;
   g.na = static_cast<int32_t>(na);
@@ -395,9 +395,12 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     }
     a.grid_frows = static_cast<int>(a.grid_fc.size());
     a.grid_gb.clear();
-    for (int si = 0; si < static_cast<int>(a.gsegs.size()); ++si)
-      if (a.gsegs[si].kind != SL1M_PIX_DELTA)
-        for (int b = 0; b < a.gsegs[si].ablocks; ++b) a.grid_gb.push_back(int2{si, b});
+    for (int si = 0; si < static_cast<int>(a.gsegs.size()); ++si) {
+      const GridSeg& g = a.gsegs[si];
+      if (g.kind == SL1M_PIX_DELTA) continue;
+      const int nb = g.square ? g.pblocks : g.ablocks;
+      for (int b = 0; b < nb; ++b) a.grid_gb.push_back(int2{si, b});
+    }
   }
 
   // ---- visibility chunks of the adjoint (shared by all of its kernels)

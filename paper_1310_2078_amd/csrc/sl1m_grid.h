@@ -117,14 +117,20 @@ __device__ __forceinline__ void grid_fwd_delta_tile(
   }
 }
 
-// Writes pair record p of a square delta grid (layout of GridPairRec) from
-// the amplitudes x_j = xs * scale_j * xp_j of the two cells' sign slots.
-__device__ __forceinline__ void grid_write_pair_rec(int64_t p, int na,
-                                                    const int32_t* __restrict__ slot,
-                                                    const double* __restrict__ nu,
-                                                    const float* __restrict__ xp,
-                                                    const float* __restrict__ pscale, float xs,
-                                                    GridPairRec* __restrict__ rec) {
+// Pair record p of a square grid: its group g, |l| index ia, member b and
+// |m| index bb = kGridNB g + b; the amplitudes x_j = xs * scale_j * xp_j of
+// the cell's (x) and the mirror's (y) sign slots (zero where the pair rules
+// of GridPairRec leave them out); cell index q of (ia, bb).
+struct PairSlots {
+  int64_t q;
+  float x[4], y[4];
+  int32_t empty;
+};
+
+__device__ __forceinline__ PairSlots grid_pair_slots(int64_t p, int na,
+                                                     const int32_t* __restrict__ slot,
+                                                     const float* __restrict__ xp,
+                                                     const float* __restrict__ pscale, float xs) {
   // groups with records: kGridNB g < na; the record offsets increase over them
   const int ngroups = (na + kGridNB - 1) / kGridNB;
   int g = 0;
@@ -132,25 +138,40 @@ __device__ __forceinline__ void grid_write_pair_rec(int64_t p, int na,
   const int64_t li = p - pair_rec_base(g, na);
   const int ia = kGridNB * g + static_cast<int>(li / kGridNB);
   const int b = static_cast<int>(li % kGridNB), bb = kGridNB * g + b;
-  const int64_t q = (static_cast<int64_t>(g) * na + ia) * kGridNB + b;
-  float x[4], y[4];
-  int32_t empty = 1;
+  PairSlots r;
+  r.q = (static_cast<int64_t>(g) * na + ia) * kGridNB + b;
+  r.empty = 1;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const int32_t j = bb <= ia ? slot[4 * q + s] : -1;
-    x[s] = j >= 0 ? pscale[j] * xs * xp[j] : 0.0f;
-    empty &= j < 0 ? 1 : 0;
-    y[s] = 0.0f;
+    const int32_t j = bb <= ia ? slot[4 * r.q + s] : -1;
+    r.x[s] = j >= 0 ? pscale[j] * xs * xp[j] : 0.0f;
+    r.empty &= j < 0 ? 1 : 0;
+    r.y[s] = 0.0f;
   }
   if (bb < ia) {
     const int64_t qp = (static_cast<int64_t>(ia / kGridNB) * na + bb) * kGridNB + ia % kGridNB;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int32_t j = slot[4 * qp + s];
-      y[s] = j >= 0 ? pscale[j] * xs * xp[j] : 0.0f;
-      empty &= j < 0 ? 1 : 0;
+      r.y[s] = j >= 0 ? pscale[j] * xs * xp[j] : 0.0f;
+      r.empty &= j < 0 ? 1 : 0;
     }
   }
+  return r;
+}
+
+// Writes pair record p of a square delta grid (GridPairRec).
+__device__ __forceinline__ void grid_write_pair_rec(int64_t p, int na,
+                                                    const int32_t* __restrict__ slot,
+                                                    const double* __restrict__ nu,
+                                                    const float* __restrict__ xp,
+                                                    const float* __restrict__ pscale, float xs,
+                                                    GridPairRec* __restrict__ rec) {
+  const PairSlots ps = grid_pair_slots(p, na, slot, xp, pscale, xs);
+  const float* x = ps.x;
+  const float* y = ps.y;
+  const int32_t empty = ps.empty;
+  const int64_t q = ps.q;
   GridPairRec r;
   r.nu = nu[q];
   r.e1 = (x[0] + x[1]) + (x[2] + x[3]);
@@ -163,6 +184,23 @@ __device__ __forceinline__ void grid_write_pair_rec(int64_t p, int na,
   r.f4 = (y[0] - y[1]) + (y[2] - y[3]);
   r.empty = empty;
   r.pad = 0;
+  rec[p] = r;
+}
+
+// Writes pair record p of a square Gaussian grid (GridPairRecG).
+__device__ __forceinline__ void grid_write_pair_rec_gauss(
+    int64_t p, int na, const int32_t* __restrict__ slot, const double* __restrict__ r2c,
+    const double* __restrict__ kapc, const float* __restrict__ xp,
+    const float* __restrict__ pscale, float xs, GridPairRecG* __restrict__ rec) {
+  const PairSlots ps = grid_pair_slots(p, na, slot, xp, pscale, xs);
+  GridPairRecG r;
+  r.r2 = r2c[ps.q];
+  r.kappa = kapc[ps.q];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    r.x[s] = ps.x[s];
+    r.y[s] = ps.y[s];
+  }
   rec[p] = r;
 }
 
@@ -249,6 +287,100 @@ __device__ __forceinline__ void grid_fwd_delta_pairs_tile(
   for (int i = 0; i < kGridVPL; ++i) {
     const int64_t k = kbase + static_cast<int64_t>(i) * kBlock;
     if (k < n_vis) out[k] = make_float2(ore[i], -oim[i]);
+  }
+}
+
+// Square Gaussian grid, pair chunk, one visibility per lane: for |l| index
+// ia and group member b, the cell (ia, bb) and its mirror (bb, ia) share
+// gamma; the cell takes a+- at |l|_ia and b+- at |m|_bb, the mirror a+- at
+// |l|_bb = |m|_bb and b+- at |m|_ia = |l|_ia.  Amplitudes from one pair record
+// (GridPairRecG).  `vrec` and `Ds` as for grid_fwd_gauss_tile.
+__device__ __forceinline__ void grid_fwd_gauss_pairs_tile(
+    const GridPairRecG* __restrict__ rec, const double* __restrict__ la,
+    const double* __restrict__ mb, const GridChunk& ch, int na,
+    const VisRecG<float>* __restrict__ vrec, const float* __restrict__ Ds, int64_t vtile,
+    int64_t n_vis, float2* __restrict__ out) {
+  const ConstPtr<GridPairRecG> crec = as_const(rec);
+  const ConstPtr<double> cla = as_const(la);
+  const ConstPtr<double> cmb = as_const(mb);
+  const int g = ch.g;
+  const int64_t k = vtile * kBlock + threadIdx.x;
+  const bool ok = k < n_vis;
+  const int64_t kk = ok ? k : 0;
+  const double origin = kMagic;
+  const double A = vrec[kk].A, B = vrec[kk].B, C = vrec[kk].C, NW = vrec[kk].NW, E0 = vrec[kk].E0;
+  const float ur = vrec[kk].ur, vr = vrec[kk].vr, wr = vrec[kk].wr, c1 = vrec[kk].c1;
+  // per member b: the cell's b+- at |m|_bb and the mirror's a+- at the same value
+  float bpr[kGridNB], bpi[kGridNB], bmr[kGridNB], bmi[kGridNB];
+  float mpr[kGridNB], mpi[kGridNB], mmr[kGridNB], mmi[kGridNB];
+#pragma unroll
+  for (int b = 0; b < kGridNB; ++b) {
+    const double m = cmb[g * kGridNB + b];
+    const float mr = static_cast<float>(m);
+    float cb, sb, ca, sa;
+    phasor(fma(B, m, origin), cb, sb);
+    phasor(fma(A, m, origin), ca, sa);
+    const float dvp = fmaf(-wr, mr, vr), dvm = fmaf(wr, mr, vr);
+    const float dup = fmaf(-wr, mr, ur), dum = fmaf(wr, mr, ur);
+    const float tvp = pow2(c1 * (dvp * dvp)), tvm = pow2(c1 * (dvm * dvm));
+    const float tup = pow2(c1 * (dup * dup)), tum = pow2(c1 * (dum * dum));
+    bpr[b] = tvp * cb;
+    bpi[b] = tvp * sb;
+    bmr[b] = tvm * cb;
+    bmi[b] = -tvm * sb;
+    mpr[b] = tup * ca;
+    mpi[b] = tup * sa;
+    mmr[b] = tum * ca;
+    mmi[b] = -tum * sa;
+  }
+  float ore = 0.0f, oim = 0.0f;
+  for (int s0 = ch.ia0; s0 < ch.ia1; s0 += kGridSegIA) {
+    const int s1 = s0 + kGridSegIA < ch.ia1 ? s0 + kGridSegIA : ch.ia1;
+    float re = 0.0f, im = 0.0f;
+    for (int ia = s0; ia < s1; ++ia) {
+      const double l = cla[ia];
+      const float lr = static_cast<float>(l);
+      float ca, sa, cb, sb;
+      phasor(fma(A, l, origin), ca, sa);
+      phasor(fma(B, l, origin), cb, sb);
+      const float dup = fmaf(-wr, lr, ur), dum = fmaf(wr, lr, ur);
+      const float dvp = fmaf(-wr, lr, vr), dvm = fmaf(wr, lr, vr);
+      const float tup = pow2(c1 * (dup * dup)), tum = pow2(c1 * (dum * dum));
+      const float tvp = pow2(c1 * (dvp * dvp)), tvm = pow2(c1 * (dvm * dvm));
+      const float apr = tup * ca, api = tup * sa, amr = tum * ca, ami = -tum * sa;  // cell a+-
+      const float qpr = tvp * cb, qpi = tvp * sb, qmr = tvm * cb, qmi = -tvm * sb;  // mirror b+-
+      const int p0 = static_cast<int>(pair_rec_base(g, na)) + (ia - kGridNB * g) * kGridNB;
+#pragma unroll
+      for (int b = 0; b < kGridNB; ++b) {
+        const double r2 = crec[p0 + b].r2, kap = crec[p0 + b].kappa;
+        const float x0 = crec[p0 + b].x[0], x1 = crec[p0 + b].x[1];
+        const float x2 = crec[p0 + b].x[2], x3 = crec[p0 + b].x[3];
+        const float y0 = crec[p0 + b].y[0], y1 = crec[p0 + b].y[1];
+        const float y2 = crec[p0 + b].y[2], y3 = crec[p0 + b].y[3];
+        float cg, sg;
+        phasor(fma(C, r2, fma(NW, kap, E0)), cg, sg);
+        // cell: b+ (x0 a+ + x1 a-) + b- (x2 a+ + x3 a-)
+        const float Ur = fmaf(x0, apr, x1 * amr), Ui = fmaf(x0, api, x1 * ami);
+        const float Wr = fmaf(x2, apr, x3 * amr), Wi = fmaf(x2, api, x3 * ami);
+        // mirror: qb+ (y0 ma+ + y1 ma-) + qb- (y2 ma+ + y3 ma-)
+        const float Vr = fmaf(y0, mpr[b], y1 * mmr[b]), Vi = fmaf(y0, mpi[b], y1 * mmi[b]);
+        const float Xr = fmaf(y2, mpr[b], y3 * mmr[b]), Xi = fmaf(y2, mpi[b], y3 * mmi[b]);
+        const float Sr = fmaf(bpr[b], Ur, fmaf(-bpi[b], Ui, fmaf(bmr[b], Wr, fmaf(-bmi[b], Wi,
+                         fmaf(qpr, Vr, fmaf(-qpi, Vi, fmaf(qmr, Xr, -qmi * Xi)))))));
+        const float Si = fmaf(bpr[b], Ui, fmaf(bpi[b], Ur, fmaf(bmr[b], Wi, fmaf(bmi[b], Wr,
+                         fmaf(qpr, Vi, fmaf(qpi, Vr, fmaf(qmr, Xi, qmi * Xr)))))));
+        re = fmaf(cg, Sr, re);
+        re = fmaf(-sg, Si, re);
+        im = fmaf(cg, Si, im);
+        im = fmaf(sg, Sr, im);
+      }
+    }
+    ore += re;
+    oim += im;
+  }
+  if (ok) {
+    const float D = Ds[2 * k], Dsv = D * Ds[2 * k + 1];
+    out[k] = make_float2(D * ore - Dsv * oim, Dsv * ore + D * oim);
   }
 }
 
@@ -675,6 +807,140 @@ __device__ __forceinline__ void grid_adj_gauss_tile(
       for (int s = 0; s < 4; ++s) og[bi][s] += g[bi][s];
   }
   grid_write(ls, slot, og, out_row);
+}
+
+// Square Gaussian grid, pair blocks (GridPairBlock): lane-set (g4, ia) owns
+// the cells (ia, b) and mirrors (b, ia), b = kGridNBA g4 + bi.  LDS holds, per
+// visibility of the batch and |m| value of the block's groups, the cells'
+// b+- and the mirrors' a+- (both at that value); the lane forms a+- at |l|_ia
+// for its cells and b+- at |m|_ia for its mirrors.  Writes as for the delta
+// pair blocks.  `vrec`, `rres` are the layer's.
+__device__ __forceinline__ void grid_adj_gauss_pairs_tile(
+    const VisRecG<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ r2c,
+    const double* __restrict__ kapc, const int32_t* __restrict__ slot, int na,
+    const GridPairBlock& pb, int64_t kc, int64_t kchunk, int64_t n_vis,
+    float* __restrict__ out_row, float4 (*bsh)[kGridMaxGL][kGridNBA][2]) {
+  int g4 = pb.g4, ia = pb.ia + static_cast<int>(threadIdx.x);
+  const bool active = static_cast<int>(threadIdx.x) < pb.count;
+  while (active && ia >= na) {
+    ++g4;
+    ia = ia - na + kGridNBA * g4;
+  }
+  if (!active) {
+    g4 = pb.g4;
+    ia = 0;
+  }
+  const int gl = g4 - pb.g4;
+  const int qbase = ((g4 / 2) * na + ia) * kGridNB + (g4 % 2) * kGridNBA;
+  const double l = la[ia];
+  const float lr = static_cast<float>(l);
+  double r2[kGridNBA], kap[kGridNBA];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) {
+    r2[bi] = active ? r2c[qbase + bi] : 0.0;
+    kap[bi] = active ? kapc[qbase + bi] : 0.0;
+  }
+  const ConstPtr<VisRecG<float>> crec = as_const(vrec);
+  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
+  const double origin = kMagic;
+  const int k0 = static_cast<int>(kc * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  float o[kGridNBA][8];
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[bi][j] = 0.0f;
+  const int fill = kGridKBG * pb.n_gl * kGridNBA;
+  for (int kb = k0; kb < k1; kb += kGridKBG) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < fill; e += kBlock) {
+      const int kk = e / (pb.n_gl * kGridNBA);
+      const int rem = e - kk * (pb.n_gl * kGridNBA);
+      const int gg = rem / kGridNBA, bi = rem - gg * kGridNBA;
+      const int k = kb + kk;
+      float4 bv = make_float4(0.0f, 0.0f, 0.0f, 0.0f), av = bv;
+      if (k < k1) {
+        const double m = mb[(pb.g4 + gg) * kGridNBA + bi];
+        const float mr = static_cast<float>(m), w = vrec[k].wr, c = vrec[k].c1;
+        float cb, sb, ca, sa;
+        phasor(fma(vrec[k].B, m, origin), cb, sb);
+        phasor(fma(vrec[k].A, m, origin), ca, sa);
+        const float dvp = fmaf(-w, mr, vrec[k].vr), dvm = fmaf(w, mr, vrec[k].vr);
+        const float dup = fmaf(-w, mr, vrec[k].ur), dum = fmaf(w, mr, vrec[k].ur);
+        const float tvp = pow2(c * (dvp * dvp)), tvm = pow2(c * (dvm * dvm));
+        const float tup = pow2(c * (dup * dup)), tum = pow2(c * (dum * dum));
+        bv = make_float4(tvp * cb, tvp * sb, tvm * cb, -tvm * sb);  // cell b+, b-
+        av = make_float4(tup * ca, tup * sa, tum * ca, -tum * sa);  // mirror a+, a-
+      }
+      bsh[kk][gg][bi][0] = bv;
+      bsh[kk][gg][bi][1] = av;
+    }
+    __syncthreads();
+    const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
+    float G[kGridNBA][8];
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) G[bi][j] = 0.0f;
+    for (int k = kb; k < ke; ++k) {
+      const double A = crec[k].A, B = crec[k].B, C = crec[k].C, NW = crec[k].NW, E0 = crec[k].E0;
+      const float ur = crec[k].ur, vr = crec[k].vr, wr = crec[k].wr, c1 = crec[k].c1;
+      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
+      float ca, sa, cb, sb;
+      phasor(fma(A, l, origin), ca, sa);
+      phasor(fma(B, l, origin), cb, sb);
+      const float dup = fmaf(-wr, lr, ur), dum = fmaf(wr, lr, ur);
+      const float dvp = fmaf(-wr, lr, vr), dvm = fmaf(wr, lr, vr);
+      const float tup = pow2(c1 * (dup * dup)), tum = pow2(c1 * (dum * dum));
+      const float tvp = pow2(c1 * (dvp * dvp)), tvm = pow2(c1 * (dvm * dvm));
+      const float apr = tup * ca, api = tup * sa, amr = tum * ca, ami = -tum * sa;  // cell a+-
+      const float qpr = tvp * cb, qpi = tvp * sb, qmr = tvm * cb, qmi = -tvm * sb;  // mirror b+-
+#pragma unroll
+      for (int bi = 0; bi < kGridNBA; ++bi) {
+        const float4 bb = bsh[k - kb][gl][bi][0];  // cell b+- at |m|_b
+        const float4 ma = bsh[k - kb][gl][bi][1];  // mirror a+- at |l|_b
+        float cg, sg;
+        phasor(fma(C, r2[bi], fma(NW, kap[bi], E0)), cg, sg);
+        const float zr = fmaf(cg, rr, sg * ri), zi = fmaf(cg, ri, -sg * rr);
+        // cell: Y+- = conj(b+-) Z, g = Re conj(a) Y
+        const float ypr = fmaf(bb.x, zr, bb.y * zi), ypi = fmaf(bb.x, zi, -bb.y * zr);
+        const float ymr = fmaf(bb.z, zr, bb.w * zi), ymi = fmaf(bb.z, zi, -bb.w * zr);
+        G[bi][0] = fmaf(apr, ypr, fmaf(api, ypi, G[bi][0]));
+        G[bi][1] = fmaf(amr, ypr, fmaf(ami, ypi, G[bi][1]));
+        G[bi][2] = fmaf(apr, ymr, fmaf(api, ymi, G[bi][2]));
+        G[bi][3] = fmaf(amr, ymr, fmaf(ami, ymi, G[bi][3]));
+        // mirror: Y'+- = conj(qb+-) Z, g' = Re conj(ma) Y'
+        const float wpr = fmaf(qpr, zr, qpi * zi), wpi = fmaf(qpr, zi, -qpi * zr);
+        const float wmr = fmaf(qmr, zr, qmi * zi), wmi = fmaf(qmr, zi, -qmi * zr);
+        G[bi][4] = fmaf(ma.x, wpr, fmaf(ma.y, wpi, G[bi][4]));
+        G[bi][5] = fmaf(ma.z, wpr, fmaf(ma.w, wpi, G[bi][5]));
+        G[bi][6] = fmaf(ma.x, wmr, fmaf(ma.y, wmi, G[bi][6]));
+        G[bi][7] = fmaf(ma.z, wmr, fmaf(ma.w, wmi, G[bi][7]));
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < kGridNBA; ++bi)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) o[bi][j] += G[bi][j];
+  }
+  if (!active) return;
+#pragma unroll
+  for (int bi = 0; bi < kGridNBA; ++bi) {
+    const int64_t q = qbase + bi;
+    const int b = kGridNBA * g4 + bi;
+    const int64_t qp = (static_cast<int64_t>(ia / kGridNB) * na + b) * kGridNB + ia % kGridNB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 0 ? b > ia : b >= ia) continue;
+      const int64_t qq = h ? qp : q;
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int32_t j = slot[4 * qq + s2];
+        if (j >= 0) out_row[j] = o[bi][4 * h + s2];
+      }
+    }
+  }
 }
 
 }  // namespace dev

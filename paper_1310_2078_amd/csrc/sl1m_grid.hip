@@ -46,6 +46,17 @@ __global__ void k_grid_prep_pairs(const float* __restrict__ xp, const float* __r
   grid_write_pair_rec(p, na, slot, nu, xp, pscale, 1.0f, rec);
 }
 
+__global__ void k_grid_prep_pairs_gauss(const float* __restrict__ xp,
+                                        const float* __restrict__ pscale,
+                                        const int32_t* __restrict__ slot,
+                                        const double* __restrict__ r2,
+                                        const double* __restrict__ kap, int na, int64_t n_pairs,
+                                        GridPairRecG* __restrict__ rec) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  grid_write_pair_rec_gauss(p, na, slot, r2, kap, xp, pscale, 1.0f, rec);
+}
+
 // Per-call forward records of a Gaussian segment.
 __global__ void k_grid_prep_gauss(const float* __restrict__ xp, const float* __restrict__ pscale,
                                   const int32_t* __restrict__ slot, const double* __restrict__ r2,
@@ -107,6 +118,20 @@ __global__ __launch_bounds__(kBlock) void k_grid_fwd_gauss(
                       part + static_cast<int64_t>(blockIdx.y) * n_vis);
 }
 
+__global__ __launch_bounds__(kBlock) void k_grid_fwd_gauss_pairs(
+    const GridPairRecG* __restrict__ rec, const double* __restrict__ la,
+    const double* __restrict__ mb, const GridChunk* __restrict__ chunks, int na,
+    const VisRecG<float>* __restrict__ vrec, const float* __restrict__ Ds, int64_t n_vis,
+    float2* __restrict__ part) {
+  const ConstPtr<GridChunk> cc = as_const(chunks) + blockIdx.y;
+  GridChunk ch;
+  ch.g = cc->g;
+  ch.ia0 = cc->ia0;
+  ch.ia1 = cc->ia1;
+  grid_fwd_gauss_pairs_tile(rec, la, mb, ch, na, vrec, Ds, blockIdx.x, n_vis,
+                            part + static_cast<int64_t>(blockIdx.y) * n_vis);
+}
+
 // Adjoint: block (lane-set block, visibility chunk); partial row = blockIdx.y.
 constexpr size_t kGridLds = sizeof(float2) * kGridKB * kGridMaxGL * kGridNBA;
 static_assert(kGridLds == sizeof(float4) * kGridKBG * kGridMaxGL * kGridNBA,
@@ -142,22 +167,38 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_delta_square(
 
 // All Gaussian grid segments in one launch: block x of the (block, chunk)
 // grid maps to (segment, block within the segment) through `gblocks`, so a
-// plan with several small layers still fills the GPU with one launch.
+// plan with several small layers still fills the GPU with one launch.  For a
+// square segment the block is a pair block (index into `pblocks` from the
+// segment's pb0).
 __global__ __launch_bounds__(kBlock) void k_grid_adj_gauss_multi(
     const int2* __restrict__ gblocks, const GridSeg* __restrict__ segs,
-    const VisRecG<float>* __restrict__ vrec, const float2* __restrict__ rres,
-    const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ c3,
-    const double* __restrict__ c4, const int32_t* __restrict__ slot, int64_t kchunk,
-    int64_t n_vis, float* __restrict__ part, int64_t n_pix) {
-  __shared__ float4 bsh[kGridKBG][kGridMaxGL][kGridNBA];
+    const GridPairBlock* __restrict__ pblocks, const VisRecG<float>* __restrict__ vrec,
+    const float2* __restrict__ rres, const double* __restrict__ la,
+    const double* __restrict__ mb, const double* __restrict__ c3, const double* __restrict__ c4,
+    const int32_t* __restrict__ slot, int64_t kchunk, int64_t n_vis, float* __restrict__ part,
+    int64_t n_pix) {
+  __shared__ float4 bsh[kGridKBG][kGridMaxGL][kGridNBA][2];
   const ConstPtr<int2> cgb = as_const(gblocks) + blockIdx.x;
   const int si = cgb->x, blk = cgb->y;
   const ConstPtr<GridSeg> cs = as_const(segs) + si;
   const int64_t co = cs->cell_off, layer = cs->layer;
-  grid_adj_gauss_tile(vrec + layer * n_vis, rres + (1 + layer) * n_vis, la + cs->la_off,
-                      mb + cs->mb_off, c3 + co, c4 + co, slot + 4 * co, cs->na, 2 * cs->ng, blk,
-                      blockIdx.y, kchunk, n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix,
-                      bsh);
+  float* row = part + static_cast<int64_t>(blockIdx.y) * n_pix;
+  if (cs->square) {
+    const ConstPtr<GridPairBlock> cb = as_const(pblocks) + cs->pb0 + blk;
+    GridPairBlock pb;
+    pb.g4 = cb->g4;
+    pb.ia = cb->ia;
+    pb.count = cb->count;
+    pb.n_gl = cb->n_gl;
+    grid_adj_gauss_pairs_tile(vrec + layer * n_vis, rres + (1 + layer) * n_vis, la + cs->la_off,
+                              mb + cs->mb_off, c3 + co, c4 + co, slot + 4 * co, cs->na, pb,
+                              blockIdx.y, kchunk, n_vis, row, bsh);
+  } else {
+    grid_adj_gauss_tile(vrec + layer * n_vis, rres + (1 + layer) * n_vis, la + cs->la_off,
+                        mb + cs->mb_off, c3 + co, c4 + co, slot + 4 * co, cs->na, 2 * cs->ng, blk,
+                        blockIdx.y, kchunk, n_vis, row,
+                        reinterpret_cast<float4(*)[kGridMaxGL][kGridNBA]>(&bsh[0][0][0][0]));
+  }
 }
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
@@ -197,14 +238,25 @@ hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
                            rows + static_cast<int64_t>(g.nfs) * p->n_vis);
       }
     } else {
-      GridRecG* rec = static_cast<GridRecG*>(p->grid_rec) + co;
-      hipLaunchKernelGGL(k_grid_prep_gauss, dim3(blocks_for(g.cells)), dim3(kBlock), 0, st, x,
-                         scale, slot, p->grid_c3 + co, p->grid_c4 + co, g.cells, rec);
       const VisRecG<float>* vrec =
           static_cast<const VisRecG<float>*>(p->visrecG) + static_cast<int64_t>(g.layer) * p->n_vis;
       const float* Ds = static_cast<const float*>(p->layerDs) + static_cast<int64_t>(g.layer) * 2 * p->n_vis;
-      hipLaunchKernelGGL(k_grid_fwd_gauss, grid, dim3(kBlock), 0, st, rec, la, mb, ch, g.na, vrec,
-                         Ds, p->n_vis, rows);
+      if (g.square) {
+        // mirrored pairs, one visibility per lane
+        GridPairRecG* prec = reinterpret_cast<GridPairRecG*>(p->grid_prec + g.pr_off);
+        hipLaunchKernelGGL(k_grid_prep_pairs_gauss, dim3(blocks_for(g.n_pairs)), dim3(kBlock), 0,
+                           st, x, scale, slot, p->grid_c3 + co, p->grid_c4 + co, g.na, g.n_pairs,
+                           prec);
+        hipLaunchKernelGGL(k_grid_fwd_gauss_pairs,
+                           dim3(static_cast<unsigned>(blocks_for(p->n_vis)), static_cast<unsigned>(g.nfc)),
+                           dim3(kBlock), 0, st, prec, la, mb, ch, g.na, vrec, Ds, p->n_vis, rows);
+      } else {
+        GridRecG* rec = static_cast<GridRecG*>(p->grid_rec) + co;
+        hipLaunchKernelGGL(k_grid_prep_gauss, dim3(blocks_for(g.cells)), dim3(kBlock), 0, st, x,
+                           scale, slot, p->grid_c3 + co, p->grid_c4 + co, g.cells, rec);
+        hipLaunchKernelGGL(k_grid_fwd_gauss, grid, dim3(kBlock), 0, st, rec, la, mb, ch, g.na,
+                           vrec, Ds, p->n_vis, rows);
+      }
     }
   }
   return hipGetLastError();
@@ -239,7 +291,7 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st) {
   if (p->grid_gblocks > 0)
     hipLaunchKernelGGL(k_grid_adj_gauss_multi,
                        dim3(static_cast<unsigned>(p->grid_gblocks), static_cast<unsigned>(p->n_achunks)),
-                       dim3(kBlock), 0, st, p->d_grid_gblocks, p->d_grid_segs,
+                       dim3(kBlock), 0, st, p->d_grid_gblocks, p->d_grid_segs, p->d_grid_pblocks,
                        static_cast<const VisRecG<float>*>(p->visrecG), rres, p->grid_la,
                        p->grid_mb, p->grid_c3, p->grid_c4, p->grid_slot, p->adj_kchunk, p->n_vis,
                        part, p->n_pix);

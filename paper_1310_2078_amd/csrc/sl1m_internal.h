@@ -112,6 +112,14 @@ struct GridPairRec {
   int32_t empty, pad;
 };
 
+// The same for a square Gaussian grid: l^2 + m^2 and kappa of the pair, the
+// amplitudes of the cell's (x) and the mirror's (y) sign slots.
+struct GridPairRecG {
+  double r2, kappa;
+  float x[4], y[4];
+};
+static_assert(sizeof(GridPairRecG) == sizeof(GridPairRec), "pair records share one buffer");
+
 __host__ __device__ inline int64_t pair_rec_base(int g, int na) {
   return static_cast<int64_t>(kGridNB) *
          (static_cast<int64_t>(g) * na - (kGridNB / 2) * static_cast<int64_t>(g) * (g - 1));

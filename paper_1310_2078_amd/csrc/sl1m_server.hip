@@ -33,8 +33,9 @@ constexpr int kSrvRing = 4;              // rounds in flight (table buffers)
 constexpr int kSrvTileBlocks = 8192;     // per-request operator split target (work-item count)
 // item tables per round: 4 operator kinds x 6 variants (4 direct tile shapes,
 // the grid evaluation, the square-grid evaluation), then reduce, update, final
-// and the grid prep (delta, Gaussian).  A square delta grid request files its
-// pair chunks and pair blocks under the Gaussian kinds.
+// and the grid prep (delta, Gaussian).  Square grid requests use the
+// square variant: a delta one files its pair chunks and pair blocks under the
+// Gaussian kinds, a Gaussian one under the delta kinds.
 constexpr int kOpVariants = 6;
 constexpr int kGridVariant = 4, kSquareVariant = 5;
 constexpr int kTabReduce = 4 * kOpVariants, kTabUpdate = kTabReduce + 1,
@@ -310,8 +311,13 @@ __global__ __launch_bounds__(kBlock) void k_srv_gprep(const TabDev* __restrict__
   const int64_t c = (sg.begin + (w - sg.prefix)) * kBlock + threadIdx.x;
   const float* xp = (sg.flags & sched::F_POWER) ? q.x : (sg.flags & sched::F_OBJECTIVE) ? q.img : q.y;
   const float xs = (sg.flags & sched::F_POWER) ? static_cast<float>(q.xscale) : 1.0f;
-  if (!GAUSS && c < q.g_npairs)  // square grids: pair records too
-    grid_write_pair_rec(c, q.g_na, q.g_slot, q.g_c3, xp, q.pscale, xs, q.g_prec);
+  if (c < q.g_npairs) {  // square grids: pair records too
+    if (GAUSS)
+      grid_write_pair_rec_gauss(c, q.g_na, q.g_slot, q.g_c3, q.g_c4, xp, q.pscale, xs,
+                                reinterpret_cast<GridPairRecG*>(q.g_prec));
+    else
+      grid_write_pair_rec(c, q.g_na, q.g_slot, q.g_c3, xp, q.pscale, xs, q.g_prec);
+  }
   if (c >= q.g_cells) return;
   float x[4];
   int32_t empty = 1;
@@ -427,6 +433,46 @@ __global__ __launch_bounds__(kBlock) void k_srv_gadj_pairs(const TabDev* __restr
   pb.n_gl = cb->n_gl;
   grid_adj_delta_pairs_tile(q.visrecD, q.rres, q.vu, q.vv, q.g_la, q.g_mb, q.g_c3, q.g_slot,
                             q.g_na, pb, kc, q.kchunk, q.n_vis, q.apart + kc * q.n_pix, lds);
+}
+
+// Square Gaussian grids: pair forward chunks (one visibility per lane) and
+// pair adjoint blocks.
+__global__ __launch_bounds__(kBlock) void k_srv_ggfwd_pairs(const TabDev* __restrict__ tab,
+                                                            const ReqDev* __restrict__ reqs) {
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nvt = static_cast<uint32_t>(q.g_vtiles);
+  const int64_t c = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nvt));
+  const int64_t vt = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nvt));
+  const ConstPtr<GridChunk> cc = as_const(q.g_fchunks) + c;
+  GridChunk ch;
+  ch.g = cc->g;
+  ch.ia0 = cc->ia0;
+  ch.ia1 = cc->ia1;
+  grid_fwd_gauss_pairs_tile(reinterpret_cast<const GridPairRecG*>(q.g_prec), q.g_la, q.g_mb, ch,
+                            q.g_na, q.g_vrec, q.g_Ds, vt, q.n_vis, q.fpart + c * q.n_vis);
+}
+
+__global__ __launch_bounds__(kBlock) void k_srv_ggadj_pairs(const TabDev* __restrict__ tab,
+                                                            const ReqDev* __restrict__ reqs) {
+  __shared__ float4 lds[kGridKBG][kGridMaxGL][kGridNBA][2];
+  const int64_t w = blockIdx.x;
+  const SegDev sg = tab->seg[find_seg(tab, w)];
+  const ReqDev& q = reqs[sg.slot];
+  const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
+  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
+  const int64_t bi = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nac));
+  const ConstPtr<GridPairBlock> cb = as_const(q.g_pblocks) + bi;
+  GridPairBlock pb;
+  pb.g4 = cb->g4;
+  pb.ia = cb->ia;
+  pb.count = cb->count;
+  pb.n_gl = cb->n_gl;
+  grid_adj_gauss_pairs_tile(q.g_vrec, q.g_lres, q.g_la, q.g_mb, q.g_c3, q.g_c4, q.g_slot, q.g_na,
+                            pb, kc, q.kchunk, q.n_vis, q.apart + kc * q.n_pix, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -670,7 +716,10 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
     q.g_ng = g.ng;
     q.g_vtiles = plan->grid_vtiles;
     q.g_nfs = g.nfs;
-    if (g.square) gkind = 3;
+    if (g.square) {
+      gkind = gkind == 1 ? 3 : 4;  // square delta, square Gaussian
+      if (gkind == 4) q.g_vtiles = static_cast<int32_t>((plan->n_vis + kBlock - 1) / kBlock);
+    }
   }
   q.n_achunks = plan->n_achunks;
   q.n_pd = static_cast<int32_t>(plan->ptiles_delta.size());
@@ -684,23 +733,26 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   q.thr = power ? 0.0 : t.params.lambda / t.params.L;
   q.xscale = xscale;
   auto variant = [&](int per_lane) { return plan->beam_pair ? 3 : (per_lane == 4 ? 2 : per_lane == 2 ? 1 : 0); };
-  const int gvar = gkind == 3 ? kSquareVariant : kGridVariant;
+  const int gvar = gkind >= 3 ? kSquareVariant : kGridVariant;
   s->fwd_variant[t.req.slot] = static_cast<int8_t>(gkind ? gvar : variant(q.vpl));
   s->adj_variant[t.req.slot] = static_cast<int8_t>(gkind ? gvar : variant(q.ppl));
-  s->grid_kind[t.req.slot] = static_cast<int8_t>(gkind == 3 ? 1 : gkind);
+  s->grid_kind[t.req.slot] = static_cast<int8_t>(gkind == 3 ? 1 : gkind == 4 ? 2 : gkind);
   SRV_HIP(hipMemcpyAsync(s->d_reqs + t.req.slot, &q, sizeof(ReqDev), hipMemcpyHostToDevice, st),
           "upload request descriptor");
   SRV_HIP(hipStreamSynchronize(st), "admission sync");
   // work-item counts
   sched::Shape& sh = t.req.shape;
-  if (gkind == 3) {
-    // square delta grid: pair items under the Gaussian kinds (routed to the
-    // square-grid variant); no single-cell items
+  if (gkind >= 3) {
+    // square grid: pair items only, under the Gaussian kinds for a delta grid
+    // and under the delta kinds for a Gaussian grid (routed to the square
+    // variant's kernels)
     const GridSeg& g = plan->grid_segs[0];
-    sh.fwd_delta = static_cast<int64_t>(g.nfs) * q.g_vtiles;
-    sh.fwd_gauss = static_cast<int64_t>(g.nfc - g.nfs) * q.g_vtiles;
-    sh.adj_delta = static_cast<int64_t>(g.ablocks) * q.n_achunks;
-    sh.adj_gauss = static_cast<int64_t>(g.pblocks) * q.n_achunks;
+    const int64_t nf = static_cast<int64_t>(g.nfc) * q.g_vtiles;
+    const int64_t na = static_cast<int64_t>(g.pblocks) * q.n_achunks;
+    sh.fwd_delta = gkind == 4 ? nf : 0;
+    sh.fwd_gauss = gkind == 3 ? nf : 0;
+    sh.adj_delta = gkind == 4 ? na : 0;
+    sh.adj_gauss = gkind == 3 ? na : 0;
     sh.prep_blocks = (std::max(g.cells, g.n_pairs) + kBlock - 1) / kBlock;
   } else if (gkind) {
     // one grid segment: all items are of its kind
@@ -805,7 +857,7 @@ sl1m_status launch_round(sl1m_server* s) {
   if (e == hipSuccess) e = go(2, k_srv_fwd<false, 4, false>, cr);
   if (e == hipSuccess) e = go(3, k_srv_fwd<false, 4, true>, cr);
   if (e == hipSuccess) e = go(kGridVariant, k_srv_gfwd<false>, cr);
-  if (e == hipSuccess) e = go(kSquareVariant, k_srv_gfwd<false>, cr);
+  if (e == hipSuccess) e = go(kSquareVariant, k_srv_ggfwd_pairs, cr);
   if (e == hipSuccess) e = go(kOpVariants + 0, k_srv_fwd<true, 1, false>, cr);
   if (e == hipSuccess) e = go(kOpVariants + 1, k_srv_fwd<true, 2, false>, cr);
   if (e == hipSuccess) e = go(kOpVariants + 2, k_srv_fwd<true, 4, false>, cr);
@@ -818,6 +870,7 @@ sl1m_status launch_round(sl1m_server* s) {
   if (e == hipSuccess) e = go(2 * kOpVariants + 2, k_srv_adj<false, 4, false>, cr);
   if (e == hipSuccess) e = go(2 * kOpVariants + 3, k_srv_adj<false, 4, true>, cr);
   if (e == hipSuccess) e = go(2 * kOpVariants + kGridVariant, k_srv_gadj<false>, cr);
+  if (e == hipSuccess) e = go(2 * kOpVariants + kSquareVariant, k_srv_ggadj_pairs, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 0, k_srv_adj<true, 1, false>, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 1, k_srv_adj<true, 2, false>, cr);
   if (e == hipSuccess) e = go(3 * kOpVariants + 2, k_srv_adj<true, 4, false>, cr);

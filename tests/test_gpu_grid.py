@@ -52,7 +52,7 @@ def _odd_grid(n_side, half_extent):
 
 SEEDS = {"config1": 0, "odd45": 1, "disk64": 2, "rect80x24_gains": 3, "grid_plus_gauss": 4,
          "gauss_wide48_gains": 5, "gauss_parax_odd41": 6, "layers_mixed": 7,
-         "gauss_truncated50": 8}
+         "gauss_truncated50": 8, "gauss_rect72x30": 9}
 
 
 def _case(name):
@@ -119,13 +119,24 @@ def _case(name):
         n = 2321
         return _with_pixels(wl, l[:n], m[:n], np.full(n, 2.0 * d),
                             np.full(n, W.PIX_GAUSS_WIDE, np.uint8))
+    if name == "gauss_rect72x30":
+        # rectangular: the |l| and |m| sets differ, so cells are not paired
+        wl = W.small_random(19, 10, 2333, uv_radius=800.0, w_sigma=150.0, with_gains=True)
+        d = 0.005
+        L, M = np.meshgrid((np.arange(72) - 36) * d, (np.arange(30) - 15) * d)
+        n = L.size
+        return _with_pixels(wl, L.ravel(), M.ravel(), np.full(n, 1.5e-3),
+                            np.full(n, W.PIX_GAUSS_WIDE, np.uint8))
     raise KeyError(name)
 
 
 # case -> number of segments on the grid path
 CASES = {"config1": 1, "odd45": 1, "disk64": 1, "rect80x24_gains": 1, "grid_plus_gauss": 1,
          "gauss_wide48_gains": 1, "gauss_parax_odd41": 1, "layers_mixed": 2,
-         "gauss_truncated50": 1}
+         "gauss_truncated50": 1, "gauss_rect72x30": 1}
+# cases whose grid segments are all square (evaluated as mirrored pairs)
+SQUARE = {"config1", "odd45", "disk64", "grid_plus_gauss", "gauss_wide48_gains",
+          "gauss_parax_odd41", "layers_mixed", "gauss_truncated50"}
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -143,6 +154,8 @@ def test_grid_and_direct_match_oracle(name):
         plan = sl1m.Plan.from_workload(wl, grid=mode)
         info = plan.info()
         assert info["grid"] == (CASES[name] if mode == "require" else 0)
+        if mode == "require":
+            assert info["grid_pairs"] == (info["grid"] if name in SQUARE else 0)
         V = plan.forward(x).cpu().numpy()
         g = plan.adjoint(r).cpu().numpy()
         ef, ea = rel(V, Vo), rel(g, go)
