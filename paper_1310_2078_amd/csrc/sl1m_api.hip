@@ -404,15 +404,34 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   }
 
   // ---- visibility chunks of the adjoint (shared by all of its kernels)
+  // The launches of one adjoint run one after another, so besides the plan's
+  // block target every launch should have enough blocks of its own: the
+  // smallest launch gets at least kMinLaunchBlocks (grid plans; within the
+  // chunk cap).
+  constexpr int64_t kMinLaunchBlocks = 2048;
   int64_t ptiles = static_cast<int64_t>(a.pd.size() + a.pg.size());
+  int64_t min_launch = 0;
   if (a.grid) {
     ptiles = static_cast<int64_t>(a.pd1.size() + a.pg1.size());
-    for (const GridSeg& g : a.gsegs) ptiles += g.ablocks + g.pblocks;
+    std::vector<int64_t> launches = {static_cast<int64_t>(a.pd1.size()),
+                                     static_cast<int64_t>(a.pg1.size())};
+    int64_t gauss = 0;
+    for (const GridSeg& g : a.gsegs) {
+      ptiles += g.ablocks + g.pblocks;
+      if (g.kind == SL1M_PIX_DELTA)
+        launches.push_back(g.ablocks + g.pblocks);
+      else
+        gauss += g.ablocks + g.pblocks;  // one launch for every Gaussian grid segment
+    }
+    launches.push_back(gauss);
+    for (int64_t b : launches)
+      if (b > 0) min_launch = min_launch ? std::min(min_launch, b) : b;
   }
   if (nv > 0 && ptiles > 0) {
     const int64_t cap = a.grid ? 256 : 64;
-    int64_t want =
-        std::max<int64_t>(1, std::min<int64_t>(cap, (target_blocks + ptiles - 1) / ptiles));
+    int64_t want = (target_blocks + ptiles - 1) / ptiles;
+    if (min_launch > 0) want = std::max(want, (kMinLaunchBlocks + min_launch - 1) / min_launch);
+    want = std::max<int64_t>(1, std::min<int64_t>(cap, want));
     a.kchunk = std::max<int64_t>(64, (nv + want - 1) / want);
     a.n_achunks = static_cast<int>((nv + a.kchunk - 1) / a.kchunk);
   } else {
