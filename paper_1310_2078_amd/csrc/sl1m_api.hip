@@ -843,6 +843,8 @@ sl1m_status sl1m_plan_destroy(sl1m_plan* plan) {
   return SL1M_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Candidate launch shapes for sl1m_tune: (grid mode, split target) with the
@@ -914,6 +916,8 @@ sl1m_status tune_one(const sl1m_problem& pr, void* ws, size_t bytes, int reps, h
 }
 
 }  // namespace
+
+extern "C" {
 
 sl1m_status sl1m_tune_workspace_bytes(const sl1m_problem* problem, size_t* bytes) {
   try {

@@ -89,6 +89,34 @@ __device__ __forceinline__ Chunk load_chunk(const Chunk* table, int64_t i) {
   return r;
 }
 
+// acc += p[0], p[stride], ..., p[(n - 1) * stride], in this order.  Four
+// terms are loaded before any of them is added, so a thread waits for one
+// memory round trip per four terms instead of one per term; the sum is the
+// plain loop's, bit for bit.
+__device__ __forceinline__ void acc_add(float& a, float v) { a += v; }
+__device__ __forceinline__ void acc_add(double& a, double v) { a += v; }
+__device__ __forceinline__ void acc_add(float2& a, float2 v) {
+  a.x += v.x;
+  a.y += v.y;
+}
+__device__ __forceinline__ void acc_add(double2& a, double2 v) {
+  a.x += v.x;
+  a.y += v.y;
+}
+template <typename T>
+__device__ __forceinline__ void strided_sum(const T* __restrict__ p, int n, int64_t stride, T& acc) {
+  int c = 0;
+  for (; c + 4 <= n; c += 4) {
+    const T a0 = p[c * stride], a1 = p[(c + 1) * stride];
+    const T a2 = p[(c + 2) * stride], a3 = p[(c + 3) * stride];
+    acc_add(acc, a0);
+    acc_add(acc, a1);
+    acc_add(acc, a2);
+    acc_add(acc, a3);
+  }
+  for (; c < n; ++c) acc_add(acc, p[c * stride]);
+}
+
 // ---------------------------------------------------------------------------
 // operator tiles
 // ---------------------------------------------------------------------------

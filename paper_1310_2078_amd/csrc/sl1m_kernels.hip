@@ -117,12 +117,11 @@ __global__ void k_fwd_reduce(const C2<R>* __restrict__ part, int n_rows, int64_t
   if (k >= n_vis) return;
   const R gr = gain ? gain[2 * k] : R(1), gi = gain ? gain[2 * k + 1] : R(0);
   for (int r = 0; r < nr; ++r) {
-    R re = R(0), im = R(0);
-    for (int c = 0; c < n_rows; ++c) {
-      const C2<R> q = part[static_cast<int64_t>(r * n_rows + c) * n_vis + k];
-      re += q.x;
-      im += q.y;
-    }
+    C2<R> acc;
+    acc.x = R(0);
+    acc.y = R(0);
+    strided_sum<C2<R>>(part + static_cast<int64_t>(r * n_rows) * n_vis + k, n_rows, n_vis, acc);
+    R re = acc.x, im = acc.y;
     if (gain) {
       const R tr = gr * re - gi * im;
       im = gr * im + gi * re;
@@ -154,8 +153,9 @@ __device__ __forceinline__ R row_sum(const R* __restrict__ part, int n_rows, int
                                      int64_t j, R (*sh)[kRowPix]) {
   const int wv = threadIdx.x / kRowPix, ln = threadIdx.x % kRowPix;
   R g = R(0);
-  if (j < n_pix)
-    for (int c = wv; c < n_rows; c += 4) g += part[static_cast<int64_t>(r * n_rows + c) * n_pix + j];
+  if (j < n_pix && wv < n_rows)
+    strided_sum<R>(part + static_cast<int64_t>(r * n_rows + wv) * n_pix + j, (n_rows - wv + 3) / 4,
+                   4 * n_pix, g);
   sh[wv][ln] = g;
   __syncthreads();
   const R t = wv == 0 ? (sh[0][ln] + sh[1][ln]) + (sh[2][ln] + sh[3][ln]) : R(0);

@@ -30,6 +30,10 @@ using sched::Segment;
 
 constexpr int kSrvMaxSlots = 64;
 constexpr int kSrvRing = 4;              // rounds in flight (table buffers)
+// A round runs as two lanes on two streams: requests with Gaussian pixels in
+// one, the others in the second.  Lanes share no request, so their launches
+// may overlap: the tail of one lane's kernel is filled by the other's blocks.
+constexpr int kSrvLanes = 2;
 constexpr int kSrvTileBlocks = 8192;     // per-request operator split target (work-item count)
 // item tables per round: 4 operator kinds x 6 variants (4 direct tile shapes,
 // the grid evaluation, the square-grid evaluation), then reduce, update, final
@@ -80,7 +84,7 @@ struct ReqDev {
   double* red;           // partial sums: [vis_blocks] then [2 * pix_blocks]
   int* flag;             // non-finite values seen
   int64_t n_pix, n_vis, kchunk, vtiles, vis_blocks, pix_blocks;
-  int32_t n_fchunks, n_fd, n_achunks, n_pd, vpl, ppl, n_layers, beam_pair;
+  int32_t n_fchunks, n_fd, n_achunks, n_pd, n_pg, vpl, ppl, n_layers, beam_pair;
   double t, inv_L, thr, lam, L, L_safety, rq, xscale, l2, l1, nnz;
   // grid evaluation (requests whose pixels form one grid segment)
   const double *g_la, *g_mb, *g_c3, *g_c4;
@@ -95,12 +99,18 @@ struct ReqDev {
   int64_t g_npairs;
   int64_t g_cells;
   int32_t g_na, g_ng, g_vtiles, g_nfs;
+  int32_t g_ablk, g_pad;           // adjoint blocks (lane-set or pair blocks)
 };
 
+// Segment of work item w: lane i of each wavefront tests segment i (a table
+// has at most kSrvMaxSlots = 64 of them, their prefixes non-decreasing), and
+// the number of segments starting at or before w, less one, is the index --
+// one vector load per block instead of a chain of dependent scalar loads.
+static_assert(kSrvMaxSlots <= 64, "one segment per lane of a wavefront");
 __device__ __forceinline__ int find_seg(const TabDev* __restrict__ tab, int64_t w) {
-  int s = 0;
-  while (s + 1 < tab->n_seg && tab->seg[s + 1].prefix <= w) ++s;
-  return s;
+  const int lane = threadIdx.x % 64;
+  const bool hit = lane < tab->n_seg && tab->seg[lane].prefix <= w;
+  return __popcll(__ballot(hit)) - 1;
 }
 
 __device__ __forceinline__ double srv_block_sum(double v, double* sh) {
@@ -156,12 +166,9 @@ __global__ __launch_bounds__(kBlock) void k_srv_reduce(const TabDev* __restrict_
     const int64_t k = blk * kBlock + threadIdx.x;
     double l2 = 0.0;
     if (k < q.n_vis) {
-      float re = 0.f, im = 0.f;
-      for (int c = 0; c < q.n_fchunks; ++c) {
-        const float2 v = q.fpart[static_cast<int64_t>(c) * q.n_vis + k];
-        re += v.x;
-        im += v.y;
-      }
+      float2 acc = make_float2(0.f, 0.f);
+      strided_sum<float2>(q.fpart + k, q.n_fchunks, q.n_vis, acc);
+      float re = acc.x, im = acc.y;
       const float gr = q.vgain ? q.vgain[2 * k] : 1.f, gi = q.vgain ? q.vgain[2 * k + 1] : 0.f;
       if (q.vgain) {
         const float tr = gr * re - gi * im;
@@ -191,9 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_srv_adj(const TabDev* __restrict__ t
   const SegDev sg = tab->seg[find_seg(tab, w)];
   const ReqDev& q = reqs[sg.slot];
   const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
-  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
-  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
-  const int64_t tile = __builtin_amdgcn_readfirstlane(static_cast<int>((GAUSS ? q.n_pd : 0) + item / nac));
+  // pixel tiles fastest: the blocks running together share a visibility chunk
+  const uint32_t nt = static_cast<uint32_t>(GAUSS ? q.n_pg : q.n_pd);
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nt));
+  const int64_t tile = __builtin_amdgcn_readfirstlane(static_cast<int>((GAUSS ? q.n_pd : 0) + item % nt));
   const Chunk tl = load_chunk(q.ptiles, tile);
   float* row = q.apart + kc * q.n_pix;
   if (GAUSS)
@@ -207,15 +215,59 @@ __global__ __launch_bounds__(kBlock) void k_srv_adj(const TabDev* __restrict__ t
 // Per pixel block: FISTA step (threshold + momentum), power-iteration update
 // (x <- g with partial <x, g> and |g|^2), or the objective pass (partial sum
 // and non-zero count, copy of the image to the caller's order).
+// The adjoint partial rows are summed for the block's kBlock pixels by its
+// four wavefronts: wavefront w adds rows c = w, w + 4, ... for four pixels per
+// lane (64 apart, so every load is one contiguous 256-byte line per
+// wavefront), and the four partial sums of a pixel meet in LDS as
+// (s0 + s1) + (s2 + s3) -- the order of the per-plan FISTA kernel.
 __global__ __launch_bounds__(kBlock) void k_srv_update(const TabDev* __restrict__ tab,
                                                        ReqDev* __restrict__ reqs) {
+  static_assert(kBlock == 256, "four wavefronts of 64 lanes");
   __shared__ double sh[kBlock];
+  __shared__ float srow[4][kBlock];
   {
     const int64_t w = blockIdx.x;
     const SegDev sg = tab->seg[find_seg(tab, w)];
     ReqDev& q = reqs[sg.slot];
     const int64_t blk = sg.begin + (w - sg.prefix);
-    const int64_t j = blk * kBlock + threadIdx.x;
+    const int64_t j0 = blk * kBlock;
+    const int64_t j = j0 + threadIdx.x;
+    if (!(sg.flags & sched::F_OBJECTIVE)) {  // uniform over the block
+      const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+      float g4[4] = {0.f, 0.f, 0.f, 0.f};
+      const int nr = q.n_achunks;
+      if (wv < nr) {
+        // rows wv, wv + 4, ...: four rows of the four pixels are loaded
+        // before they are added (sixteen loads per round trip); every pixel
+        // still adds its rows in order
+        const int cnt = (nr - wv + 3) / 4;
+        const int64_t stride = 4 * q.n_pix;
+        const float* base = q.apart + static_cast<int64_t>(wv) * q.n_pix + j0 + ln;
+        bool ok[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) ok[s4] = j0 + ln + 64 * s4 < q.n_pix;
+        int c = 0;
+        for (; c + 4 <= cnt; c += 4) {
+          float a[4][4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+              a[r][s4] = ok[s4] ? base[(c + r) * stride + 64 * s4] : 0.f;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) g4[s4] += a[r][s4];
+        }
+        for (; c < cnt; ++c)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+            if (ok[s4]) g4[s4] += base[c * stride + 64 * s4];
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) srow[wv][ln + 64 * s4] = g4[s4];
+    }
+    __syncthreads();
     double p0 = 0.0, p1 = 0.0;
     if (j < q.n_pix) {
       if (sg.flags & sched::F_OBJECTIVE) {
@@ -224,8 +276,8 @@ __global__ __launch_bounds__(kBlock) void k_srv_update(const TabDev* __restrict_
         p1 = v != 0.f ? 1.0 : 0.0;
         q.out[q.perm[j]] = v;
       } else {
-        float g = 0.f;
-        for (int c = 0; c < q.n_achunks; ++c) g += q.apart[static_cast<int64_t>(c) * q.n_pix + j];
+        const int t = threadIdx.x;
+        float g = (srow[0][t] + srow[1][t]) + (srow[2][t] + srow[3][t]);
         g *= q.pscale[j];
         if (sg.flags & sched::F_POWER) {
           const float xo = q.x[j] * static_cast<float>(q.xscale);
@@ -381,9 +433,9 @@ __global__ __launch_bounds__(kBlock) void k_srv_gadj(const TabDev* __restrict__ 
   const SegDev sg = tab->seg[find_seg(tab, w)];
   const ReqDev& q = reqs[sg.slot];
   const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
-  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
-  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
-  const int64_t blk = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nac));
+  const uint32_t nb = static_cast<uint32_t>(q.g_ablk);  // blocks fastest
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nb));
+  const int64_t blk = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nb));
   float* row = q.apart + kc * q.n_pix;
   if (GAUSS)
     grid_adj_gauss_tile(q.g_vrec, q.g_lres, q.g_la, q.g_mb, q.g_c3, q.g_c4, q.g_slot, q.g_na,
@@ -422,9 +474,9 @@ __global__ __launch_bounds__(kBlock) void k_srv_gadj_pairs(const TabDev* __restr
   const SegDev sg = tab->seg[find_seg(tab, w)];
   const ReqDev& q = reqs[sg.slot];
   const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
-  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
-  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
-  const int64_t bi = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nac));
+  const uint32_t nb = static_cast<uint32_t>(q.g_ablk);  // blocks fastest
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nb));
+  const int64_t bi = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nb));
   const ConstPtr<GridPairBlock> cb = as_const(q.g_pblocks) + bi;
   GridPairBlock pb;
   pb.g4 = cb->g4;
@@ -462,9 +514,9 @@ __global__ __launch_bounds__(kBlock) void k_srv_ggadj_pairs(const TabDev* __rest
   const SegDev sg = tab->seg[find_seg(tab, w)];
   const ReqDev& q = reqs[sg.slot];
   const uint32_t item = static_cast<uint32_t>(sg.begin + (w - sg.prefix));
-  const uint32_t nac = static_cast<uint32_t>(q.n_achunks);
-  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nac));
-  const int64_t bi = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nac));
+  const uint32_t nb = static_cast<uint32_t>(q.g_ablk);  // blocks fastest
+  const int64_t kc = __builtin_amdgcn_readfirstlane(static_cast<int>(item / nb));
+  const int64_t bi = __builtin_amdgcn_readfirstlane(static_cast<int>(item % nb));
   const ConstPtr<GridPairBlock> cb = as_const(q.g_pblocks) + bi;
   GridPairBlock pb;
   pb.g4 = cb->g4;
@@ -507,14 +559,17 @@ struct sl1m_server {
   double budget = 3e10;                // evals per round, shared by the active requests
   int policy = SL1M_SERVE_OLDEST_FIRST;  // how the round budget is shared
   hipStream_t stream = nullptr;        // rounds (non-blocking, default priority)
+  hipStream_t lane_stream = nullptr;   // the second lane of each round
+  hipEvent_t lane_event[sl1m::kSrvRing] = {};  // end of the second lane's round
   hipStream_t admit_stream = nullptr;  // plan creation of admitted requests
   hipEvent_t admit_event = nullptr;
   sl1m::ReqDev* d_reqs = nullptr;
-  sl1m::TabDev* d_tabs = nullptr;      // [kSrvRing][kTabs]
+  sl1m::TabDev* d_tabs = nullptr;      // [kSrvRing][kSrvLanes][kTabs]
   sl1m::TabDev* h_tabs = nullptr;      // pinned mirror
   int8_t fwd_variant[sl1m::kSrvMaxSlots] = {};  // tile variant of each slot's request
   int8_t adj_variant[sl1m::kSrvMaxSlots] = {};
   int8_t grid_kind[sl1m::kSrvMaxSlots] = {};    // 0 direct, 1 grid delta, 2 grid Gaussian
+  int8_t lane[sl1m::kSrvMaxSlots] = {};         // lane of each slot's request
   hipEvent_t ring_event[sl1m::kSrvRing] = {};
   int64_t ring_round[sl1m::kSrvRing] = {-1, -1, -1, -1};
   std::vector<int> free_slots;
@@ -549,11 +604,21 @@ size_t extra_bytes(const sl1m_problem& p) {
          sched::Arena::round_up(sizeof(int));
 }
 
+// State of ring slot i's round: hipSuccess once it has ended on both lanes.
+// Both events are recorded every round, also by a lane without work in it,
+// and each lane's stream runs its rounds in order, so every earlier round has
+// ended too.
+hipError_t ring_query(sl1m_server* s, int i) {
+  hipError_t q = hipEventQuery(s->ring_event[i]);
+  if (q == hipSuccess) q = hipEventQuery(s->lane_event[i]);
+  return q;
+}
+
 // Releases memory and slot of requests whose last round has completed.
 void harvest(sl1m_server* s) {
   for (int i = 0; i < kSrvRing; ++i) {
     if (s->ring_round[i] < 0) continue;
-    const hipError_t q = hipEventQuery(s->ring_event[i]);
+    const hipError_t q = ring_query(s, i);
     if (q == hipSuccess) {
       s->completed_round = std::max(s->completed_round, s->ring_round[i]);
       s->ring_round[i] = -1;
@@ -561,7 +626,7 @@ void harvest(sl1m_server* s) {
       (void)hipGetLastError();  // "not ready" is not an error; keep launch checks clean
     }
   }
-  // rounds complete in order on one stream: everything up to completed_round is done
+  // rounds complete in order on each lane: everything up to completed_round is done
   while (!s->finishing.empty() && s->finishing.front().first <= s->completed_round) {
     for (uint64_t id : s->finishing.front().second) {
       Ticket& t = *s->tickets[id];
@@ -716,6 +781,7 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
     q.g_ng = g.ng;
     q.g_vtiles = plan->grid_vtiles;
     q.g_nfs = g.nfs;
+    q.g_ablk = static_cast<int32_t>(g.square ? g.pblocks : g.ablocks);
     if (g.square) {
       gkind = gkind == 1 ? 3 : 4;  // square delta, square Gaussian
       if (gkind == 4) q.g_vtiles = static_cast<int32_t>((plan->n_vis + kBlock - 1) / kBlock);
@@ -723,6 +789,7 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   }
   q.n_achunks = plan->n_achunks;
   q.n_pd = static_cast<int32_t>(plan->ptiles_delta.size());
+  q.n_pg = static_cast<int32_t>(plan->ptiles_gauss.size());
   q.n_layers = plan->n_layers;
   q.beam_pair = plan->beam_pair ? 1 : 0;
   q.t = 1.0;
@@ -737,6 +804,8 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   s->fwd_variant[t.req.slot] = static_cast<int8_t>(gkind ? gvar : variant(q.vpl));
   s->adj_variant[t.req.slot] = static_cast<int8_t>(gkind ? gvar : variant(q.ppl));
   s->grid_kind[t.req.slot] = static_cast<int8_t>(gkind == 3 ? 1 : gkind == 4 ? 2 : gkind);
+  s->lane[t.req.slot] = static_cast<int8_t>(
+      s->grid_kind[t.req.slot] == 2 || (gkind == 0 && !plan->ptiles_gauss.empty()) ? 1 : 0);
   SRV_HIP(hipMemcpyAsync(s->d_reqs + t.req.slot, &q, sizeof(ReqDev), hipMemcpyHostToDevice, st),
           "upload request descriptor");
   SRV_HIP(hipStreamSynchronize(st), "admission sync");
@@ -791,6 +860,7 @@ sl1m_status launch_round(sl1m_server* s) {
   const int ring = static_cast<int>(s->round % kSrvRing);
   if (s->ring_round[ring] >= 0) {  // the buffers are still in use by an older round
     SRV_HIP(hipEventSynchronize(s->ring_event[ring]), "round sync");
+    SRV_HIP(hipEventSynchronize(s->lane_event[ring]), "round sync");
     s->completed_round = std::max(s->completed_round, s->ring_round[ring]);
     s->ring_round[ring] = -1;
   }
@@ -811,75 +881,88 @@ sl1m_status launch_round(sl1m_server* s) {
   }
   sched::RoundPlan rp;
   sched::plan_round(act, fair, s->round, rp);
-  // split the planner's segments into per-(kernel, variant) tables
-  std::vector<Segment> tabs[kTabs];
+  // split the planner's segments into per-(lane, kernel, variant) tables
+  std::vector<Segment> tabs[kSrvLanes][kTabs];
   auto route = [&](int kind, int base, const int8_t* var) {
-    for (const Segment& g : rp.seg[kind]) tabs[base + var[g.slot]].push_back(g);
+    for (const Segment& g : rp.seg[kind]) tabs[s->lane[g.slot]][base + var[g.slot]].push_back(g);
+  };
+  auto route1 = [&](int kind, int tab) {
+    for (const Segment& g : rp.seg[kind]) tabs[s->lane[g.slot]][tab].push_back(g);
   };
   route(sched::K_FWD_DELTA, 0 * kOpVariants, s->fwd_variant);
   route(sched::K_FWD_GAUSS, 1 * kOpVariants, s->fwd_variant);
   route(sched::K_ADJ_DELTA, 2 * kOpVariants, s->adj_variant);
   route(sched::K_ADJ_GAUSS, 3 * kOpVariants, s->adj_variant);
-  tabs[kTabReduce] = rp.seg[sched::K_REDUCE];
-  tabs[kTabUpdate] = rp.seg[sched::K_UPDATE];
-  tabs[kTabFinal] = rp.seg[sched::K_FINAL];
+  route1(sched::K_REDUCE, kTabReduce);
+  route1(sched::K_UPDATE, kTabUpdate);
+  route1(sched::K_FINAL, kTabFinal);
   for (const Segment& g : rp.seg[sched::K_PREP])
-    tabs[s->grid_kind[g.slot] == 2 ? kTabPrepG : kTabPrepD].push_back(g);
-  TabDev* ht = s->h_tabs + ring * kTabs;
-  for (int k = 0; k < kTabs; ++k) {
-    TabDev& tb = ht[k];
-    tb.n_seg = static_cast<int32_t>(tabs[k].size());
-    int64_t pre = 0;
-    for (int i = 0; i < tb.n_seg; ++i) {
-      const Segment& g = tabs[k][i];
-      tb.seg[i] = SegDev{g.slot, g.flags, g.begin, g.end, pre};
-      pre += g.end - g.begin;
+    tabs[s->lane[g.slot]][s->grid_kind[g.slot] == 2 ? kTabPrepG : kTabPrepD].push_back(g);
+  for (int ln = 0; ln < kSrvLanes; ++ln) {
+    TabDev* ht = s->h_tabs + (ring * kSrvLanes + ln) * kTabs;
+    int64_t items = 0;
+    for (int k = 0; k < kTabs; ++k) {
+      TabDev& tb = ht[k];
+      tb.n_seg = static_cast<int32_t>(tabs[ln][k].size());
+      int64_t pre = 0;
+      for (int i = 0; i < tb.n_seg; ++i) {
+        const Segment& g = tabs[ln][k][i];
+        tb.seg[i] = SegDev{g.slot, g.flags, g.begin, g.end, pre};
+        pre += g.end - g.begin;
+      }
+      tb.total = pre;
+      items += pre;
     }
-    tb.total = pre;
+    if (items == 0) continue;
+    hipStream_t st = ln == 0 ? s->stream : s->lane_stream;
+    TabDev* dt = s->d_tabs + (ring * kSrvLanes + ln) * kTabs;
+    SRV_HIP(hipMemcpyAsync(dt, ht, sizeof(TabDev) * kTabs, hipMemcpyHostToDevice, st),
+            "upload round tables");
+    auto go = [&](int k, auto kernel, auto* reqs) -> hipError_t {
+      if (ht[k].total == 0) return hipSuccess;
+      const unsigned g = static_cast<unsigned>(ht[k].total);  // one block per item
+      hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, st, dt + k, reqs);
+      return hipGetLastError();
+    };
+    const ReqDev* cr = s->d_reqs;
+    ReqDev* r = s->d_reqs;
+    hipError_t e = hipSuccess;
+    // kernel order within a lane: prep, forward, reduce, adjoint, update, final
+    if (e == hipSuccess) e = go(kTabPrepD, k_srv_gprep<false>, cr);
+    if (e == hipSuccess) e = go(kTabPrepG, k_srv_gprep<true>, cr);
+    if (e == hipSuccess) e = go(0, k_srv_fwd<false, 1, false>, cr);
+    if (e == hipSuccess) e = go(1, k_srv_fwd<false, 2, false>, cr);
+    if (e == hipSuccess) e = go(2, k_srv_fwd<false, 4, false>, cr);
+    if (e == hipSuccess) e = go(3, k_srv_fwd<false, 4, true>, cr);
+    if (e == hipSuccess) e = go(kGridVariant, k_srv_gfwd<false>, cr);
+    if (e == hipSuccess) e = go(kSquareVariant, k_srv_ggfwd_pairs, cr);
+    if (e == hipSuccess) e = go(kOpVariants + 0, k_srv_fwd<true, 1, false>, cr);
+    if (e == hipSuccess) e = go(kOpVariants + 1, k_srv_fwd<true, 2, false>, cr);
+    if (e == hipSuccess) e = go(kOpVariants + 2, k_srv_fwd<true, 4, false>, cr);
+    if (e == hipSuccess) e = go(kOpVariants + 3, k_srv_fwd<true, 4, true>, cr);
+    if (e == hipSuccess) e = go(kOpVariants + kGridVariant, k_srv_gfwd<true>, cr);
+    if (e == hipSuccess) e = go(kOpVariants + kSquareVariant, k_srv_gfwd_pairs, cr);
+    if (e == hipSuccess) e = go(kTabReduce, k_srv_reduce, r);
+    if (e == hipSuccess) e = go(2 * kOpVariants + 0, k_srv_adj<false, 1, false>, cr);
+    if (e == hipSuccess) e = go(2 * kOpVariants + 1, k_srv_adj<false, 2, false>, cr);
+    if (e == hipSuccess) e = go(2 * kOpVariants + 2, k_srv_adj<false, 4, false>, cr);
+    if (e == hipSuccess) e = go(2 * kOpVariants + 3, k_srv_adj<false, 4, true>, cr);
+    if (e == hipSuccess) e = go(2 * kOpVariants + kGridVariant, k_srv_gadj<false>, cr);
+    if (e == hipSuccess) e = go(2 * kOpVariants + kSquareVariant, k_srv_ggadj_pairs, cr);
+    if (e == hipSuccess) e = go(3 * kOpVariants + 0, k_srv_adj<true, 1, false>, cr);
+    if (e == hipSuccess) e = go(3 * kOpVariants + 1, k_srv_adj<true, 2, false>, cr);
+    if (e == hipSuccess) e = go(3 * kOpVariants + 2, k_srv_adj<true, 4, false>, cr);
+    if (e == hipSuccess) e = go(3 * kOpVariants + 3, k_srv_adj<true, 4, true>, cr);
+    if (e == hipSuccess) e = go(3 * kOpVariants + kGridVariant, k_srv_gadj<true>, cr);
+    if (e == hipSuccess) e = go(3 * kOpVariants + kSquareVariant, k_srv_gadj_pairs, cr);
+    if (e == hipSuccess) e = go(kTabUpdate, k_srv_update, r);
+    if (e == hipSuccess) e = go(kTabFinal, k_srv_final, r);
+    if (e != hipSuccess) return hip_error(e, "batched round launch");
   }
-  TabDev* dt = s->d_tabs + ring * kTabs;
-  SRV_HIP(hipMemcpyAsync(dt, ht, sizeof(TabDev) * kTabs, hipMemcpyHostToDevice, s->stream),
-          "upload round tables");
-  auto go = [&](int k, auto kernel, auto* reqs) -> hipError_t {
-    if (ht[k].total == 0) return hipSuccess;
-    const unsigned g = static_cast<unsigned>(ht[k].total);  // one block per item
-    hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, s->stream, dt + k, reqs);
-    return hipGetLastError();
-  };
-  const ReqDev* cr = s->d_reqs;
-  ReqDev* r = s->d_reqs;
-  hipError_t e = hipSuccess;
-  // kernel order within a round: prep, forward, reduce, adjoint, update, final
-  if (e == hipSuccess) e = go(kTabPrepD, k_srv_gprep<false>, cr);
-  if (e == hipSuccess) e = go(kTabPrepG, k_srv_gprep<true>, cr);
-  if (e == hipSuccess) e = go(0, k_srv_fwd<false, 1, false>, cr);
-  if (e == hipSuccess) e = go(1, k_srv_fwd<false, 2, false>, cr);
-  if (e == hipSuccess) e = go(2, k_srv_fwd<false, 4, false>, cr);
-  if (e == hipSuccess) e = go(3, k_srv_fwd<false, 4, true>, cr);
-  if (e == hipSuccess) e = go(kGridVariant, k_srv_gfwd<false>, cr);
-  if (e == hipSuccess) e = go(kSquareVariant, k_srv_ggfwd_pairs, cr);
-  if (e == hipSuccess) e = go(kOpVariants + 0, k_srv_fwd<true, 1, false>, cr);
-  if (e == hipSuccess) e = go(kOpVariants + 1, k_srv_fwd<true, 2, false>, cr);
-  if (e == hipSuccess) e = go(kOpVariants + 2, k_srv_fwd<true, 4, false>, cr);
-  if (e == hipSuccess) e = go(kOpVariants + 3, k_srv_fwd<true, 4, true>, cr);
-  if (e == hipSuccess) e = go(kOpVariants + kGridVariant, k_srv_gfwd<true>, cr);
-  if (e == hipSuccess) e = go(kOpVariants + kSquareVariant, k_srv_gfwd_pairs, cr);
-  if (e == hipSuccess) e = go(kTabReduce, k_srv_reduce, r);
-  if (e == hipSuccess) e = go(2 * kOpVariants + 0, k_srv_adj<false, 1, false>, cr);
-  if (e == hipSuccess) e = go(2 * kOpVariants + 1, k_srv_adj<false, 2, false>, cr);
-  if (e == hipSuccess) e = go(2 * kOpVariants + 2, k_srv_adj<false, 4, false>, cr);
-  if (e == hipSuccess) e = go(2 * kOpVariants + 3, k_srv_adj<false, 4, true>, cr);
-  if (e == hipSuccess) e = go(2 * kOpVariants + kGridVariant, k_srv_gadj<false>, cr);
-  if (e == hipSuccess) e = go(2 * kOpVariants + kSquareVariant, k_srv_ggadj_pairs, cr);
-  if (e == hipSuccess) e = go(3 * kOpVariants + 0, k_srv_adj<true, 1, false>, cr);
-  if (e == hipSuccess) e = go(3 * kOpVariants + 1, k_srv_adj<true, 2, false>, cr);
-  if (e == hipSuccess) e = go(3 * kOpVariants + 2, k_srv_adj<true, 4, false>, cr);
-  if (e == hipSuccess) e = go(3 * kOpVariants + 3, k_srv_adj<true, 4, true>, cr);
-  if (e == hipSuccess) e = go(3 * kOpVariants + kGridVariant, k_srv_gadj<true>, cr);
-  if (e == hipSuccess) e = go(3 * kOpVariants + kSquareVariant, k_srv_gadj_pairs, cr);
-  if (e == hipSuccess) e = go(kTabUpdate, k_srv_update, r);
-  if (e == hipSuccess) e = go(kTabFinal, k_srv_final, r);
-  if (e != hipSuccess) return hip_error(e, "batched round launch");
+  // the lanes do not wait for each other: the round has ended once both of
+  // its events have (recorded also on a lane without work in this round, so
+  // that they cover that lane's earlier rounds)
+  SRV_HIP(hipEventRecord(s->lane_event[ring], s->lane_stream), "record lane event");
   SRV_HIP(hipEventRecord(s->ring_event[ring], s->stream), "record round event");
   s->ring_round[ring] = s->round;
   if (!rp.finishing.empty()) s->finishing.emplace_back(s->round, rp.finishing);
@@ -905,7 +988,7 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
     if (max_slots < 1 || max_slots > kSrvMaxSlots)
       return set_error(SL1M_EINVAL, "max_slots must be in [1, 64]");
     const size_t hdr = sched::Arena::round_up(sizeof(ReqDev) * kSrvMaxSlots) +
-                       sched::Arena::round_up(sizeof(TabDev) * kSrvRing * kTabs);
+                       sched::Arena::round_up(sizeof(TabDev) * kSrvRing * kSrvLanes * kTabs);
     if (arena_bytes < hdr + (1u << 20)) return set_error(SL1M_ENOMEM, "arena too small");
     auto s = std::make_unique<sl1m_server>();
     s->t0 = std::chrono::steady_clock::now();
@@ -919,11 +1002,13 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
     s->budget = round_budget_evals > 0 ? round_budget_evals : 3e10;
     for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     SRV_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->h_tabs),
-                          sizeof(TabDev) * kSrvRing * kTabs, hipHostMallocDefault),
+                          sizeof(TabDev) * kSrvRing * kSrvLanes * kTabs, hipHostMallocDefault),
             "pinned round tables");
     SRV_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "round stream");
+    SRV_HIP(hipStreamCreateWithFlags(&s->lane_stream, hipStreamNonBlocking), "lane stream");
     SRV_HIP(hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking), "admission stream");
     for (auto& e : s->ring_event) SRV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    for (auto& e : s->lane_event) SRV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
     *out = s.release();
     return SL1M_OK;
   } catch (...) {
@@ -1089,11 +1174,15 @@ sl1m_status sl1m_server_stats(sl1m_server* s, sl1m_server_stats_t* out) {
 sl1m_status sl1m_server_destroy(sl1m_server* s) {
   if (!s) return SL1M_OK;
   (void)hipStreamSynchronize(s->stream);
+  if (s->lane_stream) (void)hipStreamSynchronize(s->lane_stream);
   (void)hipStreamSynchronize(s->admit_stream);
   for (auto& kv : s->tickets)
     if (kv.second->plan) sl1m_plan_destroy(kv.second->plan);
   for (auto& e : s->ring_event)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : s->lane_event)
+    if (e) (void)hipEventDestroy(e);
+  if (s->lane_stream) (void)hipStreamDestroy(s->lane_stream);
   if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->h_tabs) (void)hipHostFree(s->h_tabs);

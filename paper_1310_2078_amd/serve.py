@@ -70,7 +70,7 @@ def _summary(lat, total_s, evals):
 
 
 def run_batched(arrivals, reqs, data, device, arena_bytes=48 << 30, max_slots=32,
-                round_budget=3e10, policy="oldest", log=None):
+                round_budget=3e10, policy="oldest", tile_blocks=0, log=None):
     srv = sl1m.Server(arena_bytes, max_slots=max_slots, round_budget=round_budget, device=device,
                       policy=policy)
     n = len(reqs)
@@ -84,7 +84,8 @@ def run_batched(arrivals, reqs, data, device, arena_bytes=48 << 30, max_slots=32
         now = time.perf_counter() - t0
         while nxt < n and arrivals[nxt] <= now:
             dev, V = data[nxt]
-            t = srv.submit(dev, V, dev.lam, dev.n_iter, L=0.0, power_iters=dev.power_iters)
+            t = srv.submit(dev, V, dev.lam, dev.n_iter, L=0.0, power_iters=dev.power_iters,
+                           tile_blocks=tile_blocks)
             open_t[t] = nxt
             nxt += 1
         active, pending = srv.step()
@@ -145,6 +146,8 @@ def main():
     ap.add_argument("--mode", choices=["both", "batched", "unbatched"], default="both")
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--budget", type=float, default=3e10)
+    ap.add_argument("--tile-blocks", type=int, default=0,
+                    help="per-request operator split target in the server (0: its default)")
     ap.add_argument("--policy", choices=["fair", "oldest"], default="oldest",
                     help="how the batched server shares each round")
     ap.add_argument("--out", default=None)
@@ -158,8 +161,10 @@ def main():
     if args.mode in ("both", "batched"):
         res["batched"], _ = run_batched(arrivals, reqs, data, dev, max_slots=args.slots,
                                         round_budget=args.budget, policy=args.policy,
+                                        tile_blocks=args.tile_blocks,
                                         log=sys.stderr)
-        res["batched"].update(policy=args.policy, slots=args.slots, budget=args.budget)
+        res["batched"].update(policy=args.policy, slots=args.slots, budget=args.budget,
+                              tile_blocks=args.tile_blocks)
         print(f"[serve] batched {res['batched']}", file=sys.stderr, flush=True)
     if args.mode in ("both", "unbatched"):
         res["unbatched"], _ = run_unbatched(arrivals, reqs, data, dev, log=sys.stderr)

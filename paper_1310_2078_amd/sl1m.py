@@ -409,11 +409,12 @@ class Server:
 
     def submit(self, wl, vis, lam: float, max_iter: int, L: float = 0.0,
                power_iters: int = 30, seed: int = 0, L_safety: float = 1.01,
-               grid: str = "auto") -> int:
+               grid: str = "auto", tile_blocks: int = 0) -> int:
         """wl: a workload-like object (l, m, u, v, w, sigma, kind, gains);
         vis: complex data [n_vis] (device tensor or array).  grid: "auto"
         lets a request whose pixels form one grid segment use the grid
-        evaluation; "off" evaluates every entry directly."""
+        evaluation; "off" evaluates every entry directly.  tile_blocks: the
+        request's operator split target (0: the server's default)."""
         d = self.device
         keep = dict(
             l=_dev(wl.l, torch.float64, d), m=_dev(wl.m, torch.float64, d),
@@ -447,7 +448,8 @@ class Server:
                        u=_ptr(keep["u"]), v=_ptr(keep["v"]), w=_ptr(keep["w"]),
                        ant_p=_ptr(keep["ant_p"]), ant_q=_ptr(keep["ant_q"]), n_ant=n_ant,
                        ant_gain=_ptr(keep["ant_gain"]), ant_fwhm=_ptr(keep["ant_fwhm"]),
-                       precision=PREC_FP32, max_rhs=1, tile_blocks=0, grid_mode=_GRID[grid])
+                       precision=PREC_FP32, max_rhs=1, tile_blocks=int(tile_blocks),
+                       grid_mode=_GRID[grid])
         prm = SolveParams(lam=float(lam), eps=0.0, max_iter=int(max_iter), check_every=1,
                           L=float(L), L_safety=float(L_safety), power_iters=int(power_iters),
                           reserved=0, seed=ctypes.c_uint64(seed))
