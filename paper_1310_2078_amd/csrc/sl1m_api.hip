@@ -151,6 +151,51 @@ bool analyze_grid(Analysis& a, int si, const std::vector<double>& L, const std::
   return true;
 }
 
+// Visibility chunk count of a grid plan's adjoint (default split).  Every
+// block of an adjoint launch runs kchunk visibilities through its four
+// wavefronts, and the device keeps `slots` wavefronts of that kernel resident
+// at once, so a launch takes about ceil(waves x chunks / slots) rounds of
+// kchunk visibilities.  The count minimises the sum of that over the plan's
+// adjoint launches (a launch whose last round is mostly empty wastes up to a
+// round); ties go to fewer chunks (fewer partial rows to add).
+int64_t grid_adjoint_chunks(const Analysis& a, int64_t nv, int64_t cap) {
+  constexpr int64_t kFallbackSlots = 256 * 4 * 4;  // 256 CUs, 4 SIMDs, 4 waves
+  auto slots = [&](int which) {
+    const int64_t s = grid_adj_wave_slots(which);
+    return s > 0 ? s : kFallbackSlots;
+  };
+  std::vector<std::pair<int64_t, int64_t>> launches;  // (wavefronts per chunk, slots)
+  const int64_t s_cells = slots(0), s_pairs = slots(1), s_gauss = slots(2);
+  // direct tiles of a grid plan: kernels of about the cell kernel's size
+  if (!a.pd1.empty()) launches.emplace_back(4 * static_cast<int64_t>(a.pd1.size()), s_cells);
+  if (!a.pg1.empty()) launches.emplace_back(4 * static_cast<int64_t>(a.pg1.size()), s_cells);
+  int64_t gauss = 0;
+  for (const GridSeg& g : a.gsegs) {
+    if (g.kind != SL1M_PIX_DELTA)
+      gauss += 4 * static_cast<int64_t>(g.ablocks + g.pblocks);
+    else if (g.pblocks > 0)
+      launches.emplace_back(4 * static_cast<int64_t>(g.pblocks), s_pairs);
+    else if (g.ablocks > 0)
+      launches.emplace_back(4 * static_cast<int64_t>(g.ablocks), s_cells);
+  }
+  if (gauss > 0) launches.emplace_back(gauss, s_gauss);
+  int64_t best = 1;
+  double best_t = -1.0;
+  for (int64_t c = 1; c <= cap; ++c) {
+    const int64_t kc = std::max<int64_t>(64, (nv + c - 1) / c);
+    const int64_t n = (nv + kc - 1) / kc;
+    if (n != c) continue;  // the same chunks as a smaller count
+    double t = 0.0;
+    for (const auto& l : launches)
+      t += static_cast<double>((l.first * n + l.second - 1) / l.second) * static_cast<double>(kc);
+    if (best_t < 0.0 || t < best_t) {
+      best_t = t;
+      best = c;
+    }
+  }
+  return best;
+}
+
 sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   if (!pr) return set_error(SL1M_EINVAL, "problem is NULL");
   if (pr->n_pix < 0 || pr->n_vis < 0) return set_error(SL1M_EINVAL, "negative size");
@@ -432,6 +477,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     int64_t want = (target_blocks + ptiles - 1) / ptiles;
     if (min_launch > 0) want = std::max(want, (kMinLaunchBlocks + min_launch - 1) / min_launch);
     want = std::max<int64_t>(1, std::min<int64_t>(cap, want));
+    if (a.grid && pr->tile_blocks == 0) want = grid_adjoint_chunks(a, nv, cap);
     a.kchunk = std::max<int64_t>(64, (nv + want - 1) / want);
     a.n_achunks = static_cast<int>((nv + a.kchunk - 1) / a.kchunk);
   } else {
