@@ -489,7 +489,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
-      rres, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
+      rres, rpol, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
       grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb,
       grid_prec, total;
 };
@@ -523,6 +523,7 @@ Layout layout(const Analysis& a) {
   L.visrecD = take(visrecD_bytes(rb) * nv);
   L.visrecG = take(visrecG_bytes(rb) * nl * nv);
   L.rres = take(2 * rb * (1 + nl) * nv * nr);
+  L.rpol = take(a.grid ? sizeof(ResPolar) * nv : 0);
   L.layerDs = take(2 * rb * nl * nv);
   L.chunks = take(sizeof(Chunk) * (nfc + npt + a.fd1.size() + a.fg1.size() + a.pd1.size() +
                                    a.pg1.size()));
@@ -770,6 +771,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->visrecD = w + L.visrecD;
     p->visrecG = p->n_layers ? w + L.visrecG : nullptr;
     p->rres = w + L.rres;
+    p->rpol = a.grid ? reinterpret_cast<ResPolar*>(w + L.rpol) : nullptr;
     p->layerDs = p->n_layers ? w + L.layerDs : nullptr;
     p->d_fchunks = reinterpret_cast<Chunk*>(w + L.chunks);
     p->d_ptiles = p->d_fchunks + p->n_fchunks;

@@ -465,13 +465,22 @@ __device__ __forceinline__ void adj_gauss_tile(
 template <typename R>
 __device__ __forceinline__ void write_res(C2<R>* __restrict__ rres, const R* __restrict__ layerDs,
                                           int n_layers, int64_t n_vis, int nr, int64_t k, int r,
-                                          R gr, R gi, R re, R im) {
+                                          R gr, R gi, R re, R im,
+                                          ResPolar* __restrict__ rpol = nullptr) {
   const R cr = gr * re + gi * im;
   const R ci = gr * im - gi * re;
   C2<R> o;
   o.x = cr;
   o.y = ci;
   rres[k * nr + r] = o;
+  if (rpol && r == 0) {  // polar form of the delta record (single right-hand side)
+    const double xr = static_cast<double>(cr), xi = static_cast<double>(ci);
+    ResPolar q;
+    q.org = kMagic + atan2(xi, xr) * 0.15915494309189535;  // 1 / (2 pi)
+    q.mag = static_cast<float>(sqrt(xr * xr + xi * xi));
+    q.pad = 0.0f;
+    rpol[k] = q;
+  }
   for (int L = 0; L < n_layers; ++L) {
     const R D = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2];
     const R s = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2 + 1];

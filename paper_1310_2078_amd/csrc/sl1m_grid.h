@@ -613,7 +613,7 @@ __device__ __forceinline__ void grid_adj_delta_tile(
 // (written as GridPairBlock describes).  The block's per-|m| factors B and the partners'
 // A (both at |m|_b = |l|_b) come from LDS; A and B at index ia per lane.
 __device__ __forceinline__ void grid_adj_delta_pairs_tile(
-    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const VisRecD<float>* __restrict__ vrec, const ResPolar* __restrict__ rpol,
     const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
     const double* __restrict__ mb, const double* __restrict__ nu,
     const int32_t* __restrict__ slot, int na, const GridPairBlock& pb, int64_t kc,
@@ -637,7 +637,7 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
 #pragma unroll
   for (int bi = 0; bi < kGridNBA; ++bi) nuv[bi] = active ? nu[qbase + bi] : 0.0;
   const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
-  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
+  const ConstPtr<ResPolar> cpol = as_const(rpol);
   const double origin = kMagic;
   const int k0 = static_cast<int>(kc * kchunk);
   const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
@@ -670,29 +670,35 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
 #pragma unroll
       for (int j = 0; j < 8; ++j) G[bi][j] = 0.0f;
     for (int k = kb; k < ke; ++k) {
+      // z = C r = |r| e^{2 pi i (w nu + arg r / 2 pi)}: the residual's phase
+      // rides in the phasor's origin, its modulus on the lane's own factors
+      // (a real factor, unchanged by the sign flips that conjugate A or B)
       const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
-      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
-      float ac, as, qc, qs;  // A and B at index ia
+      const double org = cpol[k].org;
+      const float mag = cpol[k].mag;
+      float ac, as, qc, qs;  // |r| A and |r| B at index ia
       phasor(fma(u, l, origin), ac, as);
       phasor(fma(v, l, origin), qc, qs);
+      ac *= mag;
+      as *= mag;
+      qc *= mag;
+      qs *= mag;
       const float4* bp = &bsh[k - kb][gl][0];
 #pragma unroll
       for (int bi = 0; bi < kGridNBA; ++bi) {
         const float4 bb = bp[bi];  // B at b (x, y), A at b (z, w)
-        float cc, cs;
-        phasor(fma(w, nuv[bi], origin), cc, cs);
-        const float z1 = fmaf(cc, rr, -cs * ri);
-        const float z2 = fmaf(cc, ri, cs * rr);
+        float cc, cs;              // z / |r|
+        phasor(fma(w, nuv[bi], org), cc, cs);
         // cell (ia, b): A at ia, B at b
-        G[bi][0] = fmaf(bb.x, ac * z1, G[bi][0]);
-        G[bi][1] = fmaf(bb.y, as * z1, G[bi][1]);
-        G[bi][2] = fmaf(bb.y, ac * z2, G[bi][2]);
-        G[bi][3] = fmaf(bb.x, as * z2, G[bi][3]);
+        G[bi][0] = fmaf(bb.x, ac * cc, G[bi][0]);
+        G[bi][1] = fmaf(bb.y, as * cc, G[bi][1]);
+        G[bi][2] = fmaf(bb.y, ac * cs, G[bi][2]);
+        G[bi][3] = fmaf(bb.x, as * cs, G[bi][3]);
         // cell (b, ia): A at b, B at ia
-        G[bi][4] = fmaf(qc, bb.z * z1, G[bi][4]);
-        G[bi][5] = fmaf(qs, bb.w * z1, G[bi][5]);
-        G[bi][6] = fmaf(qs, bb.z * z2, G[bi][6]);
-        G[bi][7] = fmaf(qc, bb.w * z2, G[bi][7]);
+        G[bi][4] = fmaf(qc, bb.z * cc, G[bi][4]);
+        G[bi][5] = fmaf(qs, bb.w * cc, G[bi][5]);
+        G[bi][6] = fmaf(qs, bb.z * cs, G[bi][6]);
+        G[bi][7] = fmaf(qc, bb.w * cs, G[bi][7]);
       }
     }
 #pragma unroll

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_delta(
 
 // Square delta grid adjoint: one pair block per block x (GridPairBlock).
 __global__ __launch_bounds__(kBlock) void k_grid_adj_delta_square(
-    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const VisRecD<float>* __restrict__ vrec, const ResPolar* __restrict__ rpol,
     const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
     const double* __restrict__ mb, const double* __restrict__ nu,
     const int32_t* __restrict__ slot, int na, const GridPairBlock* __restrict__ blocks,
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_delta_square(
   pb.ia = cb->ia;
   pb.count = cb->count;
   pb.n_gl = cb->n_gl;
-  grid_adj_delta_pairs_tile(vrec, rres, vu, vv, la, mb, nu, slot, na, pb, blockIdx.y, kchunk,
+  grid_adj_delta_pairs_tile(vrec, rpol, vu, vv, la, mb, nu, slot, na, pb, blockIdx.y, kchunk,
                             n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix, bsh);
 }
 
@@ -277,7 +277,7 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st) {
         hipLaunchKernelGGL(k_grid_adj_delta_square,
                            dim3(static_cast<unsigned>(g.pblocks), static_cast<unsigned>(p->n_achunks)),
                            dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD),
-                           rres, p->vu, p->vv, la, mb, p->grid_c3 + co, slot, g.na,
+                           p->rpol, p->vu, p->vv, la, mb, p->grid_c3 + co, slot, g.na,
                            p->d_grid_pblocks + g.pb0, p->adj_kchunk, p->n_vis, part, p->n_pix);
     } else if (g.kind == SL1M_PIX_DELTA) {
       hipLaunchKernelGGL(k_grid_adj_delta, grid, dim3(kBlock), 0, st,

@@ -41,6 +41,14 @@ struct VisRecD {
   double u, v, w, pad;
 };
 
+// Delta residual record of the square-grid adjoint in polar form: the
+// residual's phase folded into the phase origin of the per-cell phasor,
+// org = kMagic + arg(r) / (2 pi) (turns), and mag = |r|.
+struct ResPolar {
+  double org;
+  float mag, pad;
+};
+
 // Per-(layer, visibility) record for Gaussian adjoint kernels.  The phase is
 // psi = A l + B m + C r^2 + NW kappa + E0 (turns, E0 carries kMagic in FP32
 // mode); the taper is exp(c1 * ((u - w l)^2 + (v - w m)^2)).
@@ -222,6 +230,7 @@ struct sl1m_plan {
   void* visrecD = nullptr;          // VisRecD<R>[n_vis]
   void* visrecG = nullptr;          // VisRecG<R>[n_layers*n_vis]
   void* rres = nullptr;             // C2<R>[(1+n_layers)][n_vis][max_rhs] adjoint residuals
+  sl1m::ResPolar* rpol = nullptr;   // [n_vis] delta residuals in polar form (grid plans)
   void* layerDs = nullptr;          // R[2*n_layers*n_vis]: D and s
   sl1m::Chunk* d_fchunks = nullptr; // device copies of the chunk tables
   sl1m::Chunk* d_ptiles = nullptr;

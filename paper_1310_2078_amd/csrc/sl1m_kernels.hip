@@ -107,12 +107,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_gauss(
 // ---------------------------------------------------------------------------
 
 // vis[r][k] = G_k * sum_c part[r][c][k]  (minus data[r][k] if data != null);
-// writes the adjoint residual records when `rres` is set.
+// writes the adjoint residual records when `rres` is set (and the delta
+// record's polar form when `rpol` is).
 template <typename R>
 __global__ void k_fwd_reduce(const C2<R>* __restrict__ part, int n_rows, int64_t n_vis, int nr,
                              const R* __restrict__ gain, const C2<R>* __restrict__ data,
                              C2<R>* __restrict__ out, C2<R>* __restrict__ rres,
-                             const R* __restrict__ layerDs, int n_layers) {
+                             const R* __restrict__ layerDs, int n_layers,
+                             ResPolar* __restrict__ rpol) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n_vis) return;
   const R gr = gain ? gain[2 * k] : R(1), gi = gain ? gain[2 * k + 1] : R(0);
@@ -137,7 +139,7 @@ __global__ void k_fwd_reduce(const C2<R>* __restrict__ part, int n_rows, int64_t
       o.y = im;
       out[r * n_vis + k] = o;
     }
-    if (rres) write_res<R>(rres, layerDs, n_layers, n_vis, nr, k, r, gr, gi, re, im);
+    if (rres) write_res<R>(rres, layerDs, n_layers, n_vis, nr, k, r, gr, gi, re, im, rpol);
   }
 }
 
@@ -331,13 +333,14 @@ __global__ void k_prep_vis(const double* __restrict__ u, const double* __restric
 template <typename R>
 __global__ void k_adj_prep(const C2<R>* __restrict__ r, int64_t n_vis, int nr,
                            const R* __restrict__ gain, C2<R>* __restrict__ rres,
-                           const R* __restrict__ layerDs, int n_layers) {
+                           const R* __restrict__ layerDs, int n_layers,
+                           ResPolar* __restrict__ rpol) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n_vis) return;
   const R gr = gain ? gain[2 * k] : R(1), gi = gain ? gain[2 * k + 1] : R(0);
   for (int q = 0; q < nr; ++q) {
     const C2<R> v = r[q * n_vis + k];
-    write_res<R>(rres, layerDs, n_layers, n_vis, nr, k, q, gr, gi, v.x, v.y);
+    write_res<R>(rres, layerDs, n_layers, n_vis, nr, k, q, gr, gi, v.x, v.y, rpol);
   }
 }
 
@@ -656,7 +659,8 @@ static hipError_t fwd_reduce_t(sl1m_plan* p, const void* data, void* out, bool r
                      static_cast<const C2<R>*>(p->fpart), forward_rows(p, nr), p->n_vis, nr,
                      static_cast<const R*>(p->vgain), static_cast<const C2<R>*>(data),
                      static_cast<C2<R>*>(out), recs ? static_cast<C2<R>*>(p->rres) : nullptr,
-                     static_cast<const R*>(p->layerDs), p->n_layers);
+                     static_cast<const R*>(p->layerDs), p->n_layers,
+                     recs && nr == 1 ? p->rpol : nullptr);
   return hipGetLastError();
 }
 hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool recs, int nr,
@@ -670,7 +674,7 @@ static hipError_t adj_prep_t(sl1m_plan* p, const void* r, int nr, hipStream_t st
   hipLaunchKernelGGL((k_adj_prep<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
                      static_cast<const C2<R>*>(r), p->n_vis, nr, static_cast<const R*>(p->vgain),
                      static_cast<C2<R>*>(p->rres), static_cast<const R*>(p->layerDs),
-                     p->n_layers);
+                     p->n_layers, nr == 1 ? p->rpol : nullptr);
   return hipGetLastError();
 }
 hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t st) {

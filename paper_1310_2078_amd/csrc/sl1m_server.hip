@@ -68,6 +68,7 @@ struct ReqDev {
   const VisRecG<float>* visrecG;
   const float* layerDs;
   float2* rres;
+  ResPolar* rpol;        // delta residuals in polar form (square delta grids)
   const double *pl, *pm, *pc3, *pc4;
   const float* pscale;
   const float* pr2;
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_srv_reduce(const TabDev* __restrict_
       if (sg.flags & sched::F_OBJECTIVE)
         l2 = static_cast<double>(re) * re + static_cast<double>(im) * im;
       else
-        write_res<float>(q.rres, q.layerDs, q.n_layers, q.n_vis, 1, k, 0, gr, gi, re, im);
+        write_res<float>(q.rres, q.layerDs, q.n_layers, q.n_vis, 1, k, 0, gr, gi, re, im, q.rpol);
     }
     if (sg.flags & sched::F_OBJECTIVE) {
       l2 = srv_block_sum(l2, sh);
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_srv_gadj_pairs(const TabDev* __restr
   pb.ia = cb->ia;
   pb.count = cb->count;
   pb.n_gl = cb->n_gl;
-  grid_adj_delta_pairs_tile(q.visrecD, q.rres, q.vu, q.vv, q.g_la, q.g_mb, q.g_c3, q.g_slot,
+  grid_adj_delta_pairs_tile(q.visrecD, q.rpol, q.vu, q.vv, q.g_la, q.g_mb, q.g_c3, q.g_slot,
                             q.g_na, pb, kc, q.kchunk, q.n_vis, q.apart + kc * q.n_pix, lds);
 }
 
@@ -730,6 +731,7 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   q.visrecG = static_cast<const VisRecG<float>*>(plan->visrecG);
   q.layerDs = static_cast<const float*>(plan->layerDs);
   q.rres = static_cast<float2*>(plan->rres);
+  q.rpol = plan->rpol;
   q.pl = plan->pl;
   q.pm = plan->pm;
   q.pc3 = plan->pc3;
