@@ -35,9 +35,10 @@ FLOP_PER_EVAL_DELTA = 14            # phase 3 FMA, reduction 2, sin+cos 2, accum
 def kernel_source_hash(kernel: str) -> str:
     """Hash of the sources that define `kernel` (its counters go stale when
     they change)."""
-    main = "sl1m_grid.hip" if kernel.startswith("k_grid") else "sl1m_kernels.hip"
+    files = (["sl1m_grid.hip", "sl1m_grid.h"] if kernel.startswith("k_grid")
+             else ["sl1m_kernels.hip"]) + ["sl1m_internal.h", "sl1m_device.h"]
     h = hashlib.sha256()
-    for f in (main, "sl1m_internal.h", "sl1m_device.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1310_2078_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

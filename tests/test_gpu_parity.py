@@ -91,13 +91,16 @@ def test_mixed_kinds_and_layers(prec):
     _check_ops(wl, prec, "mixed kinds/layers")
 
 
-def test_config2_full_size_sampled():
-    """Config 2 at full size in the benchmark's launch configuration: sampled
-    visibilities (every 97th) and pixels (every 61st) against the oracle, and
-    the adjoint identity on the full GPU vectors."""
+@pytest.mark.parametrize("tile_blocks", [0, 4096, 8192])
+def test_config2_full_size_sampled(tile_blocks):
+    """Config 2 at full size in the benchmark's launch configurations (the
+    default split and the splits its tuner picks from): sampled visibilities
+    (every 97th) and pixels (every 61st) against the oracle, and the adjoint
+    identity on the full GPU vectors."""
     wl = W.config2()
-    say(f"[case] config2 full n_pix={wl.n_pix} n_vis={wl.n_vis}")
-    plan = sl1m.Plan.from_workload(wl)
+    say(f"[case] config2 full n_pix={wl.n_pix} n_vis={wl.n_vis} tile_blocks={tile_blocks}")
+    plan = sl1m.Plan.from_workload(wl, tile_blocks=tile_blocks)
+    say(f"    info {plan.info()}")
     p = O.Problem.from_workload(wl)
     x, r = _rand(7, wl.n_pix, wl.n_vis)
     Vg = plan.forward(x).cpu().numpy()
