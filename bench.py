@@ -177,17 +177,22 @@ def extras(plan2, wl2, dev):
     # multi-RHS: 4 right-hand sides (Stokes I, Q, U, V) at config 2's shape
     rng = np.random.default_rng(5)
     X = torch.as_tensor(rng.standard_normal((4, wl2.n_pix)), dtype=torch.float32, device=dev)
-    pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=4)
-    Vm = pm.forward_multi(X)
-    tf = _time_ops(pm, lambda: pm.forward_multi(X, out=Vm), 3)
-    G = torch.empty((4, wl2.n_pix), dtype=torch.float32, device=dev)
-    ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), 3)
     ev = wl2.n_pix * wl2.n_vis
-    ex["config2_shape_multi_rhs4"] = {
-        "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
-        "phasor_evals_per_s": 2 * ev / (tf + ta),
-        "rhs_products_per_s": 8 * ev / (tf + ta)}
-    del pm, Vm, G, X
+    for grid in ("auto", "off"):
+        pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=4, grid=grid)
+        Vm = pm.forward_multi(X)
+        tf = _time_ops(pm, lambda: pm.forward_multi(X, out=Vm), 5)
+        G = torch.empty((4, wl2.n_pix), dtype=torch.float32, device=dev)
+        ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), 5)
+        rec = {"evaluation": "grid" if pm.info()["grid_multi"] >= 4 else "direct",
+               "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+               "phasor_evals_per_s": 2 * ev / (tf + ta),
+               "rhs_products_per_s": 8 * ev / (tf + ta)}
+        ex["config2_shape_multi_rhs4" if grid == "auto" else
+           "config2_shape_multi_rhs4_direct"] = rec
+        pm.close()
+        del pm, Vm, G
+    del X
     # config 4: multiscale Gaussian pixels with direction-dependent gains
     wl4 = W.config4()
     t0 = time.perf_counter()

@@ -78,9 +78,12 @@ typedef enum {
  * an l part and an m part, the phase is linear in l and m plus terms in
  * l^2 + m^2.  The "grid" evaluation uses that; the "direct" evaluation forms
  * every entry on its own.  Both compute the same operator; they differ by
- * float32 rounding only.  Applies to float32 plans without per-pair beams and
- * to single right-hand-side calls; float64 plans and multi-RHS calls always
- * use the direct evaluation, and so do segments that do not qualify.
+ * float32 rounding only.  Applies to float32 plans without per-pair beams:
+ * to single right-hand-side calls, and to multi-RHS calls of 2 or 4 sides when
+ * every grid segment of the plan is a square delta grid (the forward shares
+ * each phasor among the sides; sl1m_plan_info.grid_multi); float64 plans,
+ * other multi-RHS calls and segments that do not qualify use the direct
+ * evaluation.
  */
 typedef enum {
   SL1M_GRID_AUTO = 0,    /* grid evaluation when the delta pixels qualify        */
@@ -211,7 +214,10 @@ typedef struct {
   int32_t n_fchunks_grid;   /* ... of the forward with the grid evaluation      */
   int32_t n_achunks;        /* visibility chunks of the adjoint                 */
   int32_t grid_pairs;       /* grid segments evaluated as mirrored cell pairs   */
-  int32_t reserved[4];
+  int32_t grid_multi;       /* multi-RHS calls of 2 (and 4) sides up to this
+                               count evaluate on the grid (every grid segment
+                               a square delta grid); 0: direct evaluation     */
+  int32_t reserved[3];
 } sl1m_plan_info;
 
 sl1m_status sl1m_plan_query(const sl1m_plan* plan, sl1m_plan_info* info);

@@ -38,6 +38,7 @@ struct Analysis {
   // grid evaluation: segments on the grid path, their concatenated tables,
   // and the direct chunks of the other segments
   bool grid = false;
+  int grid_multi = 0;  // largest multi-RHS count (2 or 4) on the grid path; 0: none
   std::vector<GridSeg> gsegs;
   int64_t grid_cells = 0;
   std::vector<double> grid_la, grid_mb, grid_c3, grid_c4;
@@ -439,6 +440,12 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
       g.nfc = static_cast<int32_t>(a.grid_fc.size()) - g.fc0;
     }
     a.grid_frows = static_cast<int>(a.grid_fc.size());
+    // several right-hand sides take the grid path when every grid segment is
+    // a square delta grid (pair records with the amplitudes of each side)
+    bool all_square_delta = true;
+    for (const GridSeg& g : a.gsegs)
+      all_square_delta = all_square_delta && g.square && g.kind == SL1M_PIX_DELTA;
+    a.grid_multi = all_square_delta ? (a.max_rhs >= 4 ? 4 : a.max_rhs >= 2 ? 2 : 0) : 0;
     a.grid_gb.clear();
     for (int si = 0; si < static_cast<int>(a.gsegs.size()); ++si) {
       const GridSeg& g = a.gsegs[si];
@@ -491,7 +498,7 @@ struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
       rres, rpol, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
       grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb,
-      grid_prec, total;
+      grid_prec, grid_precm, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -523,12 +530,12 @@ Layout layout(const Analysis& a) {
   L.visrecD = take(visrecD_bytes(rb) * nv);
   L.visrecG = take(visrecG_bytes(rb) * nl * nv);
   L.rres = take(2 * rb * (1 + nl) * nv * nr);
-  L.rpol = take(a.grid ? sizeof(ResPolar) * nv : 0);
+  L.rpol = take(a.grid ? sizeof(ResPolar) * nv * std::max<size_t>(1, a.grid_multi) : 0);
   L.layerDs = take(2 * rb * nl * nv);
   L.chunks = take(sizeof(Chunk) * (nfc + npt + a.fd1.size() + a.fg1.size() + a.pd1.size() +
                                    a.pg1.size()));
   const size_t grid_rows = a.grid ? a.grid_fc.size() + a.fd1.size() + a.fg1.size() : 0;
-  L.fpart = take(2 * rb * std::max(nfc * nr, grid_rows) * nv);
+  L.fpart = take(2 * rb * std::max(nfc * nr, grid_rows * std::max<size_t>(1, a.grid_multi)) * nv);
   L.apart = take(rb * static_cast<size_t>(a.n_achunks) * np * nr);
   L.xperm = take(rb * np * nr);
   L.img = take(rb * np);
@@ -549,6 +556,9 @@ Layout layout(const Analysis& a) {
   L.grid_segs = take(sizeof(GridSeg) * a.gsegs.size());
   L.grid_gb = take(sizeof(int2) * a.grid_gb.size());
   L.grid_prec = take(sizeof(GridPairRec) * static_cast<size_t>(a.grid_pairs));
+  L.grid_precm = take(a.grid_multi ? sizeof(float) * static_cast<size_t>(2 + 8 * a.grid_multi) *
+                                         static_cast<size_t>(a.grid_pairs)
+                                   : 0);
   L.total = off;
   return L;
 }
@@ -739,6 +749,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->adj_kchunk = a.kchunk;
     p->n_achunks = a.n_achunks;
     p->grid = a.grid;
+    p->grid_multi = a.grid_multi;
     p->grid_segs = a.gsegs;
     p->grid_cells = a.grid_cells;
     p->grid_vtiles = a.grid_vtiles;
@@ -798,6 +809,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       p->d_grid_gblocks = reinterpret_cast<int2*>(w + L.grid_gb);
       p->grid_gblocks = static_cast<int>(a.grid_gb.size());
       p->grid_prec = reinterpret_cast<GridPairRec*>(w + L.grid_prec);
+      p->grid_precm = a.grid_multi ? reinterpret_cast<float*>(w + L.grid_precm) : nullptr;
     }
 
     auto fail = [&](sl1m_status st_) {
@@ -1100,6 +1112,7 @@ sl1m_status sl1m_plan_query(const sl1m_plan* p, sl1m_plan_info* info) {
   r.n_fchunks_grid = p->grid ? forward_rows(p, 1) : 0;
   r.n_achunks = p->n_achunks;
   for (const GridSeg& g : p->grid_segs) r.grid_pairs += g.square ? 1 : 0;
+  r.grid_multi = p->grid_multi;
   *info = r;
   return SL1M_OK;
 }

@@ -473,13 +473,13 @@ __device__ __forceinline__ void write_res(C2<R>* __restrict__ rres, const R* __r
   o.x = cr;
   o.y = ci;
   rres[k * nr + r] = o;
-  if (rpol && r == 0) {  // polar form of the delta record (single right-hand side)
+  if (rpol) {  // polar form of the delta record, [r][n_vis]
     const double xr = static_cast<double>(cr), xi = static_cast<double>(ci);
     ResPolar q;
     q.org = kMagic + atan2(xi, xr) * 0.15915494309189535;  // 1 / (2 pi)
     q.mag = static_cast<float>(sqrt(xr * xr + xi * xi));
     q.pad = 0.0f;
-    rpol[k] = q;
+    rpol[static_cast<int64_t>(r) * n_vis + k] = q;
   }
   for (int L = 0; L < n_layers; ++L) {
     const R D = layerDs[(static_cast<int64_t>(L) * n_vis + k) * 2];

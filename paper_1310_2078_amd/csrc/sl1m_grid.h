@@ -290,6 +290,115 @@ __device__ __forceinline__ void grid_fwd_delta_pairs_tile(
   }
 }
 
+// Several right-hand sides on a square delta grid (the paper solves every
+// polarisation through the same matrix): pair record p holds nu (FP64) and,
+// per right-hand side r, the cell's and the mirror's sign combinations
+// e1..e4, f1..f4 -- pair_rec_floats<NR>() floats, 8 + 32 NR bytes.
+template <int NR>
+__host__ __device__ constexpr int pair_rec_floats() {
+  return 2 + 8 * NR;
+}
+
+template <int NR>
+__device__ __forceinline__ void grid_write_pair_rec_multi(int64_t p, int na,
+                                                          const int32_t* __restrict__ slot,
+                                                          const double* __restrict__ nu,
+                                                          const float* __restrict__ xp,
+                                                          int64_t n_pix,
+                                                          const float* __restrict__ pscale,
+                                                          float* __restrict__ rec) {
+  float* o = rec + p * pair_rec_floats<NR>();
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const PairSlots ps = grid_pair_slots(p, na, slot, xp + r * n_pix, pscale, 1.0f);
+    const float* x = ps.x;
+    const float* y = ps.y;
+    if (r == 0) *reinterpret_cast<double*>(o) = nu[ps.q];
+    float* e = o + 2 + 8 * r;
+    e[0] = (x[0] + x[1]) + (x[2] + x[3]);
+    e[1] = (x[1] + x[2]) - (x[0] + x[3]);
+    e[2] = (x[0] + x[1]) - (x[2] + x[3]);
+    e[3] = (x[0] - x[1]) + (x[2] - x[3]);
+    e[4] = (y[0] + y[1]) + (y[2] + y[3]);
+    e[5] = (y[1] + y[2]) - (y[0] + y[3]);
+    e[6] = (y[0] + y[1]) - (y[2] + y[3]);
+    e[7] = (y[0] - y[1]) + (y[2] - y[3]);
+  }
+}
+
+// Forward pair chunk for NR right-hand sides, one visibility per lane: the
+// phasors (A, B at |l|_ia and at the group's values, C per pair) and the eight
+// products of A and B factors are formed once and shared by every right-hand
+// side; right-hand side r adds its amplitude combinations (twelve FP32
+// operations per pair).  Partial row of right-hand side r at out + r rhs_stride.
+template <int NR>
+__device__ __forceinline__ void grid_fwd_delta_pairs_multi_tile(
+    const float* __restrict__ rec, const double* __restrict__ la, const double* __restrict__ mb,
+    const GridChunk& ch, int na, const double* __restrict__ vu, const double* __restrict__ vv,
+    const double* __restrict__ vw, int64_t vtile, int64_t n_vis, float2* __restrict__ out,
+    int64_t rhs_stride) {
+  constexpr int kF = pair_rec_floats<NR>();
+  const ConstPtr<float> crec = as_const(rec);
+  const ConstPtr<double> cla = as_const(la);
+  const ConstPtr<double> cmb = as_const(mb);
+  const int g = ch.g;
+  const int64_t k = vtile * kBlock + threadIdx.x;
+  const bool ok = k < n_vis;
+  const double origin = kMagic;
+  const double u = ok ? vu[k] : 0.0, v = ok ? vv[k] : 0.0, w = ok ? vw[k] : 0.0;
+  float bc[kGridNB], bs[kGridNB];  // B at |m|_b
+  float pc[kGridNB], ps[kGridNB];  // A at |l|_b (partner)
+#pragma unroll
+  for (int b = 0; b < kGridNB; ++b) {
+    const double m = cmb[g * kGridNB + b];
+    phasor(fma(v, m, origin), bc[b], bs[b]);
+    phasor(fma(u, m, origin), pc[b], ps[b]);
+  }
+  float ore[NR], oim[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) ore[r] = oim[r] = 0.0f;
+  for (int s0 = ch.ia0; s0 < ch.ia1; s0 += kGridSegIA) {
+    const int s1 = s0 + kGridSegIA < ch.ia1 ? s0 + kGridSegIA : ch.ia1;
+    float re[NR], imn[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) re[r] = imn[r] = 0.0f;
+    for (int ia = s0; ia < s1; ++ia) {
+      const double l = cla[ia];
+      float ac, as, qc, qs;  // A at |l|_ia, B at |m|_ia
+      phasor(fma(u, l, origin), ac, as);
+      phasor(fma(v, l, origin), qc, qs);
+      const int64_t p0 = pair_rec_base(g, na) + static_cast<int64_t>(ia - kGridNB * g) * kGridNB;
+#pragma unroll
+      for (int b = 0; b < kGridNB; ++b) {
+        const ConstPtr<float> rp = crec + (p0 + b) * kF;
+        const double nu = *reinterpret_cast<ConstPtr<double>>(rp);
+        float cc, cs;
+        phasor(fma(w, nu, origin), cc, cs);
+        const float p1 = ac * bc[b], p2 = as * bs[b], p3 = pc[b] * qc, p4 = ps[b] * qs;
+        const float q1 = ac * bs[b], q2 = as * bc[b], q3 = pc[b] * qs, q4 = ps[b] * qc;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const ConstPtr<float> e = rp + 2 + 8 * r;
+          const float rs = fmaf(p1, e[0], fmaf(p2, e[1], fmaf(p3, e[4], p4 * e[5])));
+          const float is = fmaf(q1, e[2], fmaf(q2, e[3], fmaf(q3, e[6], q4 * e[7])));
+          re[r] = fmaf(cc, rs, re[r]);
+          re[r] = fmaf(-cs, is, re[r]);
+          imn[r] = fmaf(cc, is, imn[r]);
+          imn[r] = fmaf(cs, rs, imn[r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      ore[r] += re[r];
+      oim[r] += imn[r];
+    }
+  }
+  if (ok)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) out[r * rhs_stride + k] = make_float2(ore[r], -oim[r]);
+}
+
 // Square Gaussian grid, pair chunk, one visibility per lane: for |l| index
 // ia and group member b, the cell (ia, bb) and its mirror (bb, ia) share
 // gamma; the cell takes a+- at |l|_ia and b+- at |m|_bb, the mirror a+- at

@@ -203,6 +203,36 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_gauss_multi(
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
+// Multi-RHS pair records of a square delta segment (xp: [r][n_pix]).
+template <int NR>
+__global__ void k_grid_prep_pairs_multi(const float* __restrict__ xp, int64_t n_pix,
+                                        const float* __restrict__ pscale,
+                                        const int32_t* __restrict__ slot,
+                                        const double* __restrict__ nu, int na, int64_t n_pairs,
+                                        float* __restrict__ rec) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  grid_write_pair_rec_multi<NR>(p, na, slot, nu, xp, n_pix, pscale, rec);
+}
+
+// Multi-RHS forward: block (visibility tile of kBlock, pair chunk); partial
+// row blockIdx.y of right-hand side r at rows + r rhs_stride.
+template <int NR>
+__global__ __launch_bounds__(kBlock) void k_grid_fwd_delta_pairs_multi(
+    const float* __restrict__ rec, const double* __restrict__ la, const double* __restrict__ mb,
+    const GridChunk* __restrict__ chunks, int na, const double* __restrict__ vu,
+    const double* __restrict__ vv, const double* __restrict__ vw, int64_t n_vis,
+    float2* __restrict__ rows, int64_t rhs_stride) {
+  const ConstPtr<GridChunk> cc = as_const(chunks) + blockIdx.y;
+  GridChunk ch;
+  ch.g = cc->g;
+  ch.ia0 = cc->ia0;
+  ch.ia1 = cc->ia1;
+  grid_fwd_delta_pairs_multi_tile<NR>(rec, la, mb, ch, na, vu, vv, vw, blockIdx.x, n_vis,
+                                      rows + static_cast<int64_t>(blockIdx.y) * n_vis,
+                                      rhs_stride);
+}
+
 }  // namespace
 
 hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
@@ -295,6 +325,61 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st) {
                        static_cast<const VisRecG<float>*>(p->visrecG), rres, p->grid_la,
                        p->grid_mb, p->grid_c3, p->grid_c4, p->grid_slot, p->adj_kchunk, p->n_vis,
                        part, p->n_pix);
+  return hipGetLastError();
+}
+
+bool grid_multi_ok(const sl1m_plan* p, int nr) {
+  return p->grid && p->grid_multi > 0 && (nr == 2 || nr == 4) && nr <= p->grid_multi;
+}
+
+template <int NR>
+static hipError_t grid_forward_multi_t(sl1m_plan* p, const float* x, hipStream_t st) {
+  const float* scale = static_cast<const float*>(p->pscale);
+  float2* part = static_cast<float2*>(p->fpart);
+  const int64_t rhs_stride = static_cast<int64_t>(forward_rows(p, NR)) * p->n_vis;
+  const unsigned vt = static_cast<unsigned>(blocks_for(p->n_vis));
+  for (const GridSeg& g : p->grid_segs) {
+    const int64_t co = g.cell_off;
+    float* rec = p->grid_precm + static_cast<int64_t>(pair_rec_floats<NR>()) * g.pr_off;
+    hipLaunchKernelGGL(k_grid_prep_pairs_multi<NR>, dim3(blocks_for(g.n_pairs)), dim3(kBlock), 0,
+                       st, x, p->n_pix, scale, p->grid_slot + 4 * co, p->grid_c3 + co, g.na,
+                       g.n_pairs, rec);
+    hipLaunchKernelGGL(k_grid_fwd_delta_pairs_multi<NR>, dim3(vt, static_cast<unsigned>(g.nfc)),
+                       dim3(kBlock), 0, st, rec, p->grid_la + g.la_off, p->grid_mb + g.mb_off,
+                       p->d_grid_fchunks + g.fc0, g.na, p->vu, p->vv, p->vw, p->n_vis,
+                       part + static_cast<int64_t>(g.fc0) * p->n_vis, rhs_stride);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_forward_multi(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
+  if (p->n_vis == 0) return hipSuccess;
+  if (!grid_multi_ok(p, nr)) return hipErrorInvalidValue;
+  const float* x = static_cast<const float*>(xp);
+  return nr == 2 ? grid_forward_multi_t<2>(p, x, st) : grid_forward_multi_t<4>(p, x, st);
+}
+
+// One pair-adjoint launch per right-hand side: the tile is at its issue
+// limit with the residual's phase in the per-cell phasor, which a shared
+// phasor for several sides would give up.
+hipError_t launch_grid_adjoint_multi(sl1m_plan* p, int nr, hipStream_t st) {
+  if (p->n_achunks == 0) return hipSuccess;
+  if (!grid_multi_ok(p, nr)) return hipErrorInvalidValue;
+  for (int r = 0; r < nr; ++r) {
+    float* part = static_cast<float*>(p->apart) +
+                  static_cast<int64_t>(r) * p->n_achunks * p->n_pix;
+    for (const GridSeg& g : p->grid_segs) {
+      if (g.pblocks == 0) continue;
+      const int64_t co = g.cell_off;
+      hipLaunchKernelGGL(k_grid_adj_delta_square,
+                         dim3(static_cast<unsigned>(g.pblocks), static_cast<unsigned>(p->n_achunks)),
+                         dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD),
+                         p->rpol + static_cast<int64_t>(r) * p->n_vis, p->vu, p->vv,
+                         p->grid_la + g.la_off, p->grid_mb + g.mb_off, p->grid_c3 + co,
+                         p->grid_slot + 4 * co, g.na, p->d_grid_pblocks + g.pb0, p->adj_kchunk,
+                         p->n_vis, part, p->n_pix);
+    }
+  }
   return hipGetLastError();
 }
 

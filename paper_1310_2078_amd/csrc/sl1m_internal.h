@@ -196,6 +196,7 @@ struct sl1m_plan {
   // grid evaluation (single right-hand side, FP32): segments on the grid path
   // and the direct chunks of the other segments
   bool grid = false;
+  int grid_multi = 0;             // 2 or 4: multi-RHS calls of up to this many sides on the grid
   std::vector<sl1m::GridSeg> grid_segs;
   int64_t grid_cells = 0;         // all grid segments
   int grid_vtiles = 0;            // forward visibility tiles (2 per lane)
@@ -209,6 +210,7 @@ struct sl1m_plan {
   int32_t* grid_slot = nullptr;   // [4 * cells] permuted pixel index or -1
   void* grid_rec = nullptr;       // [cells] per-call GridRec / GridRecG records
   sl1m::GridPairRec* grid_prec = nullptr;   // per-call pair records (square grids)
+  float* grid_precm = nullptr;               // multi-RHS pair records (square delta grids)
   sl1m::GridChunk* d_grid_fchunks = nullptr;
   sl1m::GridPairBlock* d_grid_pblocks = nullptr;
   sl1m::GridSeg* d_grid_segs = nullptr;     // device copy of grid_segs
@@ -315,6 +317,13 @@ hipError_t launch_objective_terms(sl1m_plan* p, const void* res, const void* img
 // [0, grid_frows) and every pixel of the grid segments in the adjoint partials.
 hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st);
 hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st);
+// Several right-hand sides (nr = 2 or 4; plans whose grid segments are all
+// square delta grids): forward partial rows [r][forward_rows][n_vis] of the
+// grid segments, adjoint partials [r][n_achunks][n_pix] from the polar
+// residual records [r][n_vis].
+bool grid_multi_ok(const sl1m_plan* p, int nr);
+hipError_t launch_grid_forward_multi(sl1m_plan* p, const void* xp, int nr, hipStream_t st);
+hipError_t launch_grid_adjoint_multi(sl1m_plan* p, int nr, hipStream_t st);
 // Wavefronts the current device keeps resident at once for a grid adjoint
 // kernel (blocks per CU allowed by its registers and LDS, x 4 wavefronts,
 // x CUs); which: 0 delta cells, 1 square delta pairs, 2 Gaussian.  0 when the

@@ -618,6 +618,12 @@ static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st
     if (p->fwd_vpl == 2) return fwd_launch_t<R, 2, false, 1>(p, xp, st, true);
     return fwd_launch_t<R, 4, false, 1>(p, xp, st, true);
   }
+  if (grid_multi_ok(p, nr)) {
+    hipError_t e = launch_grid_forward_multi(p, xp, nr, st);
+    if (e != hipSuccess || (p->fd1.empty() && p->fg1.empty())) return e;
+    if (nr == 2) return fwd_launch_t<R, 2, false, 2>(p, xp, st, true);
+    return fwd_launch_t<R, 1, false, 4>(p, xp, st, true);
+  }
   switch (nr) {
     case 1:
       if (bm) return fwd_launch_t<R, 4, true, 1>(p, xp, st);
@@ -647,7 +653,8 @@ hipError_t launch_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st) 
 }
 
 int forward_rows(const sl1m_plan* p, int nr) {
-  if (nr == 1 && p->grid) return static_cast<int>(p->grid_frows + p->fd1.size() + p->fg1.size());
+  if ((nr == 1 && p->grid) || grid_multi_ok(p, nr))
+    return static_cast<int>(p->grid_frows + p->fd1.size() + p->fg1.size());
   return p->n_fchunks;
 }
 
@@ -660,7 +667,7 @@ static hipError_t fwd_reduce_t(sl1m_plan* p, const void* data, void* out, bool r
                      static_cast<const R*>(p->vgain), static_cast<const C2<R>*>(data),
                      static_cast<C2<R>*>(out), recs ? static_cast<C2<R>*>(p->rres) : nullptr,
                      static_cast<const R*>(p->layerDs), p->n_layers,
-                     recs && nr == 1 ? p->rpol : nullptr);
+                     recs && (nr == 1 || grid_multi_ok(p, nr)) ? p->rpol : nullptr);
   return hipGetLastError();
 }
 hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool recs, int nr,
@@ -674,7 +681,7 @@ static hipError_t adj_prep_t(sl1m_plan* p, const void* r, int nr, hipStream_t st
   hipLaunchKernelGGL((k_adj_prep<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
                      static_cast<const C2<R>*>(r), p->n_vis, nr, static_cast<const R*>(p->vgain),
                      static_cast<C2<R>*>(p->rres), static_cast<const R*>(p->layerDs),
-                     p->n_layers, nr == 1 ? p->rpol : nullptr);
+                     p->n_layers, nr == 1 || grid_multi_ok(p, nr) ? p->rpol : nullptr);
   return hipGetLastError();
 }
 hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t st) {
@@ -691,6 +698,12 @@ static hipError_t adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
     if (p->adj_ppl == 1) return adj_launch_t<R, 1, false, 1>(p, st, true);
     if (p->adj_ppl == 2) return adj_launch_t<R, 2, false, 1>(p, st, true);
     return adj_launch_t<R, 4, false, 1>(p, st, true);
+  }
+  if (grid_multi_ok(p, nr)) {
+    hipError_t e = launch_grid_adjoint_multi(p, nr, st);
+    if (e != hipSuccess || (p->pd1.empty() && p->pg1.empty())) return e;
+    if (nr == 2) return adj_launch_t<R, 1, false, 2>(p, st, true);
+    return adj_launch_t<R, 1, false, 4>(p, st, true);
   }
   switch (nr) {
     case 1:

@@ -204,7 +204,7 @@ class PlanInfo(ctypes.Structure):
         ("fwd_vpl", ctypes.c_int32), ("adj_ppl", ctypes.c_int32),
         ("n_fchunks", ctypes.c_int32), ("n_fchunks_grid", ctypes.c_int32),
         ("n_achunks", ctypes.c_int32), ("grid_pairs", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("grid_multi", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
     ]
 
     def as_dict(self):

@@ -270,3 +270,45 @@ def test_grid_config4_full_size_against_direct():
         f"grid vs oracle sampled forward {ef:.3e} adjoint {ea:.3e}")
     assert rel(Vg, Vd) <= TOL and rel(gg, gd) <= TOL
     assert ef <= TOL and ea <= TOL
+
+
+# case -> whether multi-RHS calls of 2 and 4 sides take the grid evaluation
+# (every grid segment a square delta grid; the Gaussian pixels of
+# grid_plus_gauss stay direct in the same call)
+MULTI = {"config1": 4, "odd45": 4, "disk64": 4, "grid_plus_gauss": 4, "rect80x24_gains": 0,
+         "layers_mixed": 0}
+
+
+@pytest.mark.parametrize("name", list(MULTI))
+def test_grid_multi_rhs(name):
+    """Multi-RHS calls (2 and 4 sides, as the paper's polarisations through one
+    matrix): every side against the oracle, and equal to the plan's
+    single-side call of that side -- bitwise where every pixel is on the grid
+    (the same tiles, rows and summation order), within 1e-6 where direct
+    tiles of other pixels take part (their multi-RHS instantiations may round
+    differently)."""
+    wl = _case(name)
+    say(f"[case] grid multi-RHS {name} n_pix={wl.l.size} n_vis={wl.u.size}")
+    plan = sl1m.Plan.from_workload(wl, max_rhs=4)
+    info = plan.info()
+    say(f"    info {info}")
+    assert info["grid_multi"] == MULTI[name]
+    p = O.Problem.from_workload(wl)
+    rng = np.random.default_rng(SEEDS[name] + 50)
+    X = rng.standard_normal((4, wl.l.size))
+    Rr = rng.standard_normal((4, wl.u.size)) + 1j * rng.standard_normal((4, wl.u.size))
+    for nr in (2, 4):
+        Vg = plan.forward_multi(X[:nr]).cpu().numpy()
+        gg = plan.adjoint_multi(Rr[:nr]).cpu().numpy()
+        Vo = O.forward(p, X[:nr])
+        go = O.adjoint(p, Rr[:nr])
+        for r in range(nr):
+            ef, ea = rel(Vg[r], Vo[r]), rel(gg[r], go[r])
+            say(f"    nr={nr} side {r}: forward {ef:.3e} adjoint {ea:.3e}")
+            assert ef <= TOL and ea <= TOL
+            V1 = plan.forward(X[r]).cpu().numpy()
+            g1 = plan.adjoint(Rr[r]).cpu().numpy()
+            if MULTI[name] and name != "grid_plus_gauss":
+                assert np.array_equal(V1, Vg[r]) and np.array_equal(g1, gg[r])
+            else:
+                assert rel(Vg[r], V1) <= 1e-6 and rel(gg[r], g1) <= 1e-6
