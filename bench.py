@@ -44,9 +44,13 @@ def kernel_source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
+PLAN_KEYS = ("n_fchunks_grid", "n_achunks", "fwd_vpl", "adj_ppl")
+
+
+def load_traffic(kernel: str, plan_shape=None):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
+    taken on the current kernel source and (when recorded) with the same
+    operator split as the timed plan; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -55,6 +59,8 @@ def load_traffic(kernel: str):
         return None
     rec = d.get(kernel)
     if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    if plan_shape is not None and rec.get("plan") not in (None, plan_shape):
         return None
     return rec.get("bytes_per_launch")
 
@@ -77,11 +83,16 @@ def _counter_rows(path):
     return rows
 
 
-def ingest_counters(fetch_csv, write_csv):
+def ingest_counters(fetch_csv, write_csv, bench_log=None):
     """Per-launch HBM bytes of the operator kernels, scaled by what the same
     counters read for the calibration copy of CALIB_BYTES (read once, written
-    once)."""
+    once); with the counted runs' bench output, the plan's split is recorded."""
     out = {}
+    shape = None
+    if bench_log:
+        with open(bench_log) as fh:
+            last = [ln for ln in fh if ln.startswith("{")][-1]
+        shape = json.loads(last)["config"].get("plan")
     for counter, path in (("fetch", fetch_csv), ("write", write_csv)):
         rows = _counter_rows(path)
         copy = [v for n, v in rows if "copy" in n.lower() or "elementwise" in n.lower()]
@@ -98,6 +109,8 @@ def ingest_counters(fetch_csv, write_csv):
             vals = [v for n, v in rows if pat in n]
             if vals:
                 rec = out.setdefault(key, {"source_hash": kernel_source_hash(key)})
+                if shape is not None:
+                    rec["plan"] = shape
                 rec[counter + "_bytes_per_launch"] = scale * sum(vals) / len(vals)
                 rec[counter + "_scale"] = scale
                 rec["launches"] = len(vals)
@@ -244,19 +257,26 @@ def main():
                     help="skip the secondary workloads (config 4, multi-RHS, FP64 config 1)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM counters)")
-    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
-                         "--calib-copy run into profiles/traffic.json and exit")
+    ap.add_argument("--ingest-counters", nargs="+", metavar="PATH",
+                    help="FETCH_CSV WRITE_CSV [BENCH_OUT]: turn two rocprofv3 --pmc counter CSVs "
+                         "(FETCH_SIZE, WRITE_SIZE) of a --calib-copy run into "
+                         "profiles/traffic.json (with the run's plan split, read from its "
+                         "output line) and exit")
     ap.add_argument("--grid", choices=["auto", "off", "require"], default="auto",
                     help="evaluation of the delta pixels: grid factorisation when the pixels "
                          "qualify (auto), always direct (off)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the plan's default launch shapes instead of tuning them first")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON of a tuning choice (the config.tuning of an earlier line): use it "
+                         "instead of tuning")
     ap.add_argument("--profile-ops", type=int, default=0,
                     help="after the timed region, run this many extra forward+adjoint pairs "
                          "(for profiler runs)")
     args = ap.parse_args()
     if args.ingest_counters:
+        if len(args.ingest_counters) not in (2, 3):
+            ap.error("--ingest-counters takes FETCH_CSV WRITE_CSV [BENCH_OUT]")
         ingest_counters(*args.ingest_counters)
         return
     if args.gpus != 1:
@@ -276,10 +296,15 @@ def main():
           file=sys.stderr, flush=True)
     plan = sl1m.Plan.from_workload(wl, device=dev, grid=args.grid)
     tuning = None
-    if not args.no_tune:
+    if args.tuning:
+        # a fixed choice (e.g. the one a timed run printed), for profiler runs
+        tuning = json.loads(args.tuning)
+        plan.close()
+        plan = sl1m.Plan.from_workload(wl, device=dev, tuning=tuning)
+    elif not args.no_tune:
         # launch shapes from the autotuner (sl1m_tune), restricted to the
         # requested evaluation
-        tuning = plan.tune(reps=3)
+        tuning = plan.tune(reps=7)
         if args.grid != "auto" and tuning["grid"] != args.grid:
             tuning = None
         else:
@@ -326,6 +351,7 @@ def main():
     fwd_avg = fwd_ms / max(fwd_n, 1)
     adj_avg = adj_ms / max(adj_n, 1)
     pinfo = plan.info()
+    plan_shape = {k: pinfo[k] for k in PLAN_KEYS}
     grid = bool(pinfo["grid"])
     if grid and pinfo["grid_pairs"]:
         names = ("k_grid_adj_delta_square", "k_grid_fwd_delta_pairs")
@@ -361,6 +387,7 @@ def main():
             "evals_per_step": 2 * n_pix * n_vis,
             "evaluation": "grid" if grid else "direct",
             "tuning": tuning,
+            "plan": plan_shape,
         },
         "l1_solve_time_s": elapsed,
         "solve": {
@@ -386,7 +413,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": load_traffic(dom_name),
+            "traffic": load_traffic(dom_name, plan_shape),
             "flop_per_eval": FLOP_PER_EVAL_DELTA,
             "evals_per_launch": n_pix * n_vis,
             # the same counting rules applied to the work the kernel executes:

@@ -178,8 +178,10 @@ sl1m_status sl1m_plan_destroy(sl1m_plan* plan);
  * of each with HIP events on `stream`: the grid evaluation on and off (when
  * some segment qualifies), split targets tile_blocks of 1024 .. 16384 blocks,
  * and for direct plans 1, 2 or 4 visibilities (forward) and pixels (adjoint)
- * per lane.  The fastest forward + adjoint pair is returned in *out (host);
- * copy its fields into the problem before sl1m_plan_create.  The problem's
+ * per lane.  The fastest forward + adjoint pair is returned in *out (host),
+ * where a candidate replaces the earlier choice (first: every field left at 0)
+ * only when at least 1 % faster; copy its fields into the problem before
+ * sl1m_plan_create.  The problem's
  * own tile_blocks, grid_mode, fwd_vpl and adj_ppl are ignored (all are
  * searched).  Synchronises `stream` after every candidate; the workspace holds
  * nothing useful afterwards.

@@ -383,25 +383,4 @@ hipError_t launch_grid_adjoint_multi(sl1m_plan* p, int nr, hipStream_t st) {
   return hipGetLastError();
 }
 
-int64_t grid_adj_wave_slots(int which) {
-  int dev = 0, cus = 0, nb = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  hipError_t e;
-  if (which == 0)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grid_adj_delta, kBlock, 0);
-  else if (which == 1)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grid_adj_delta_square, kBlock, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grid_adj_gauss_multi, kBlock, 0);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  return static_cast<int64_t>(nb) * (kBlock / 64) * cus;
-}
-
 }  // namespace sl1m

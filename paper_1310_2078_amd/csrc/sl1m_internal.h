@@ -324,11 +324,6 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st);
 bool grid_multi_ok(const sl1m_plan* p, int nr);
 hipError_t launch_grid_forward_multi(sl1m_plan* p, const void* xp, int nr, hipStream_t st);
 hipError_t launch_grid_adjoint_multi(sl1m_plan* p, int nr, hipStream_t st);
-// Wavefronts the current device keeps resident at once for a grid adjoint
-// kernel (blocks per CU allowed by its registers and LDS, x 4 wavefronts,
-// x CUs); which: 0 delta cells, 1 square delta pairs, 2 Gaussian.  0 when the
-// runtime cannot tell (no device).
-int64_t grid_adj_wave_slots(int which);
 hipError_t launch_domain_check(sl1m_plan* p, const double* l, const double* m,
                                const double* sigma, const double* u, const double* v,
                                const double* w, hipStream_t st);
