@@ -60,8 +60,13 @@ def load_traffic(kernel: str, plan_shape=None):
     rec = d.get(kernel)
     if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
         return None
-    if plan_shape is not None and rec.get("plan") not in (None, plan_shape):
-        return None
+    rec_plan = rec.get("plan")
+    if plan_shape is not None and rec_plan is not None:
+        # the fields of the kernel's own operator (the adjoint's traffic does
+        # not depend on the forward split, and the other way round)
+        keys = ("n_achunks", "adj_ppl") if "adj" in kernel else ("n_fchunks_grid", "fwd_vpl")
+        if any(rec_plan.get(k) != plan_shape.get(k) for k in keys):
+            return None
     return rec.get("bytes_per_launch")
 
 
