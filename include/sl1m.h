@@ -324,10 +324,10 @@ sl1m_status sl1m_timing_end(sl1m_plan* plan, sl1m_timing* out /* host */);
  * budget / 32) evaluations (at least one work item, never past the end of its
  * current phase), so small requests finish a whole FISTA iteration per round
  * while large ones advance part of one; under OLDEST_FIRST the earliest
- * admitted request may take the whole budget, requests of at most 32 budgets
- * of work in total budget / 4, and the others budget / 64 (close to
- * first-come-first-served for the tail, small requests not queued behind
- * large ones).
+ * admitted request may take the whole budget, requests of at most 128 budgets
+ * of work in total budget / 4, and the others budget / 1024 (close to
+ * first-come-first-served for the large requests, small requests not queued
+ * behind them).
  * A request whose pixels form one grid segment (see sl1m_grid_mode) runs the
  * grid evaluation; other requests the direct one.  A request's arithmetic and
  * summation order depend only on its own problem: its image is bitwise the

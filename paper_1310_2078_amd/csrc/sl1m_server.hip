@@ -869,15 +869,16 @@ sl1m_status launch_round(sl1m_server* s) {
   // each request's share of the round.  FAIR: equal shares with a floor so
   // that a crowded round still moves every request by a useful amount.
   // OLDEST_FIRST: the earliest admitted request takes the whole budget (act
-  // is in admission order), small requests (at most 32 budgets of work in
-  // total) a quarter of it, the others a floor of budget/64.
+  // is in admission order), small requests (at most 128 budgets of work in
+  // total) a quarter of it, the others a floor of budget/1024 (close to
+  // first-come-first-served among the large ones).
   const double fair = std::max(s->budget / static_cast<double>(act.size()), s->budget / 32.0);
   for (size_t i = 0; i < act.size(); ++i) {
     const sched::Shape& sh = act[i]->shape;
     const double total = sh.evals_per_op * (2.0 * (sh.power_iters + sh.max_iter) + 1.0);
     if (s->policy == SL1M_SERVE_OLDEST_FIRST)
-      act[i]->share = i == 0 ? s->budget : total <= 32.0 * s->budget ? s->budget / 4.0
-                                                                      : s->budget / 64.0;
+      act[i]->share = i == 0 ? s->budget : total <= 128.0 * s->budget ? s->budget / 4.0
+                                                                       : s->budget / 1024.0;
     else
       act[i]->share = fair;
   }
