@@ -32,15 +32,42 @@ PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector peak (published)
 FLOP_PER_EVAL_DELTA = 14            # phase 3 FMA, reduction 2, sin+cos 2, accumulate 2 FMA
 
 
+def _function_text(src: str, name: str) -> str:
+    """The definition of kernel `name` (signature through its closing brace)."""
+    i = src.find(f"void {name}(")
+    if i < 0:
+        return ""
+    j = src.index("{", i)
+    depth = 0
+    for k in range(j, len(src)):
+        depth += {"{": 1, "}": -1}.get(src[k], 0)
+        if depth == 0:
+            return src[i:k + 1]
+    return src[i:]
+
+
 def kernel_source_hash(kernel: str) -> str:
-    """Hash of the sources that define `kernel` (its counters go stale when
-    they change)."""
-    files = (["sl1m_grid.hip", "sl1m_grid.h"] if kernel.startswith("k_grid")
-             else ["sl1m_kernels.hip"]) + ["sl1m_internal.h", "sl1m_device.h"]
+    """Hash of the device code `kernel` is compiled from: its own definition,
+    the tile and device headers, and the records and constants that precede
+    the plan struct in sl1m_internal.h (its counters go stale when any of them
+    changes; host code in the same files does not count)."""
+    csrc = os.path.join(ROOT, "paper_1310_2078_amd", "csrc")
+
+    def read(f):
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            return fh.read()
+
+    base = kernel.split("<")[0]
+    grid = kernel.startswith("k_grid")
+    parts = [_function_text(read("sl1m_grid.hip" if grid else "sl1m_kernels.hip"), base)]
+    if grid:
+        parts.append(read("sl1m_grid.h"))
+    parts.append(read("sl1m_device.h"))
+    internal = read("sl1m_internal.h")
+    parts.append(internal[:internal.find("struct sl1m_plan {")])
     h = hashlib.sha256()
-    for f in files:
-        with open(os.path.join(ROOT, "paper_1310_2078_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for t in parts:
+        h.update(t.encode())
     return h.hexdigest()[:16]
 
 
@@ -192,6 +219,21 @@ def extras(plan2, wl2, dev):
         "evals_per_s": 2.0 * wl2.n_pix * wl2.n_vis * 20 / td}
     pdir.close()
     del pdir, Vd
+    # warm start from the dirty image (Section "Acceleration strategies"):
+    # relative objective gap after k iterations, cold against warm, with F*
+    # from a 400-iteration cold solve
+    V2 = plan2.forward(wl2.x_true) + torch.as_tensor(wl2.noise, dtype=torch.complex64, device=dev)
+    L2 = 1.01 * plan2.estimate_L(wl2.power_iters, seed=0)
+    _, ref = plan2.solve(V2, wl2.lam, 400, L=L2)
+    D = plan2.dirty_image(V2)
+    gaps = {}
+    for k in (10, 30, 100):
+        _, c = plan2.solve(V2, wl2.lam, k, L=L2)
+        _, w = plan2.solve(V2, wl2.lam, k, L=L2, x0=D)
+        gaps[str(k)] = {"cold": (c["F"] - ref["F"]) / ref["F"],
+                        "dirty_start": (w["F"] - ref["F"]) / ref["F"]}
+    ex["config2_warm_start"] = {"F_star_400_iterations": ref["F"], "relative_gap": gaps}
+    del V2, D
     # multi-RHS: 4 right-hand sides (Stokes I, Q, U, V) at config 2's shape
     rng = np.random.default_rng(5)
     X = torch.as_tensor(rng.standard_normal((4, wl2.n_pix)), dtype=torch.float32, device=dev)

@@ -294,6 +294,24 @@ typedef struct {
 sl1m_status sl1m_solve(sl1m_plan* plan, const void* vis, const sl1m_solve_params* params,
                        void* img_out, sl1m_solve_info* info, void* stream);
 
+/* Warm start (Section "Acceleration strategies": starting from the dirty
+ * image, or from an upscaled coarser solution, cuts the iterations, not the
+ * cost of one).  The iteration of sl1m_solve from y_1 = I_0 = x0 instead of
+ * 0 (t_1 = 1, so the first momentum coefficient is 0).  x0: device, real
+ * [n_pix], caller order; not NULL when n_pix > 0 (SL1M_EINVAL); it may alias
+ * img_out.  Otherwise as sl1m_solve. */
+sl1m_status sl1m_solve_from(sl1m_plan* plan, const void* vis, const void* x0,
+                            const sl1m_solve_params* params, void* img_out,
+                            sl1m_solve_info* info, void* stream);
+
+/* Dirty image, the warm start the paper names: img_out[j] =
+ * max(0, Re(M^H V)_j / n_vis) (device, real [n_pix], caller order); for unit
+ * gains a point source of flux S at pixel j gives S / n_j^2 there.  The
+ * division by n_vis and the clip at 0 (the solution is positive) are this
+ * library's choice; the paper does not state a normalisation.  Asynchronous
+ * on `stream`. */
+sl1m_status sl1m_dirty_image(sl1m_plan* plan, const void* vis, void* img_out, void* stream);
+
 /* Kernel timing (tracing).  Between sl1m_timing_begin() and sl1m_timing_end()
  * the plan records a pair of HIP events around every launch of its operator
  * kernels on the launch stream (at most max_launches launches per kind; later

@@ -38,6 +38,11 @@ Readings taken where the paper is garbled (each also listed in the design doc):
   antenna data means unit gain.
 * R6 (termination): stop when |F_k - F_prev| <= eps * F_prev between two
   consecutive checks (every `check_every` iterations); eps = 0 disables it.
+* R16 (warm start, Section "Acceleration strategies"): the paper starts the
+  iteration from the dirty image without stating its normalisation.  The
+  dirty image here is max(0, Re(M^H V) / N_v) (a unit-gain point source of
+  flux S gives S / n^2 at its pixel; the clip keeps the start positive), and
+  a warm start from I_0 runs the printed iteration with y_1 = I_0, t_1 = 1.
 
 Indices follow the notation j = pixel, k = visibility; phases are in turns.
 """
@@ -446,6 +451,24 @@ def fista(op, V, L: float, lam: float, n_iter: int, eps: float = 0.0,
     return FistaResult(image=I, iters=k - k0, L=L, F=F, l2_term=l2, l1_term=l1,
                        nnz=int(np.count_nonzero(I)), converged=converged, history=hist,
                        state=(k, t, I_prev, y))
+
+
+def dirty_image(op, V):
+    """The dirty image, the starting point Section "Acceleration strategies"
+    names: max(0, Re(M^H V) / N_v) (reading R16)."""
+    op = _as_op(op)
+    D = op.adjoint(np.asarray(V, np.complex128)) / op.p.n_vis
+    return np.maximum(D, 0.0)
+
+
+def fista_from(op, V, L: float, lam: float, n_iter: int, I0, eps: float = 0.0,
+               check_every: int = 1, keep_history: bool = False):
+    """Warm start (Section "Acceleration strategies"): the printed iteration
+    from y_1 = I_0 instead of 0, t_1 = 1 (so the first momentum coefficient
+    (t_1 - 1)/t_2 is 0 and I_0 enters only through y_1)."""
+    I0 = np.asarray(I0, np.float64)
+    return fista(op, V, L, lam, n_iter, eps=eps, check_every=check_every,
+                 keep_history=keep_history, state=(0, 1.0, I0.copy(), I0.copy()))
 
 
 def kkt_residual(op, V, I, lam):

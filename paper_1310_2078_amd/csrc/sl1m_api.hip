@@ -1183,8 +1183,10 @@ sl1m_status sl1m_estimate_L(sl1m_plan* p, int32_t iters, uint64_t seed, const vo
   }
 }
 
-sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* prm,
-                       void* img_out, sl1m_solve_info* info, void* stream) {
+// The FISTA solve from I_0 = x0 (caller order; NULL: I_0 = 0).
+static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
+                              const sl1m_solve_params* prm, void* img_out, sl1m_solve_info* info,
+                              void* stream) {
   try {
     if (sl1m_status s = check_plan(p)) return s;
     if (!prm || !info) return set_error(SL1M_EINVAL, "params or info is NULL");
@@ -1212,8 +1214,14 @@ sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* p
     const double scal_h[3] = {1.0, 1.0 / L, prm->lambda / L};
     SL1M_HIP(hipMemcpyAsync(p->scal, scal_h, sizeof(scal_h), hipMemcpyHostToDevice, st),
              "solver scalars");
-    SL1M_HIP(launch_fill(p->xperm, p->n_pix, p->real_bytes, st), "zero y");
-    SL1M_HIP(launch_fill(p->img, p->n_pix, p->real_bytes, st), "zero I");
+    if (x0) {
+      // warm start: y_1 = I_0 = x0 (the first momentum coefficient is 0)
+      SL1M_HIP(launch_gather(p, x0, p->xperm, 1, st), "start image");
+      SL1M_HIP(launch_copy_real(p, p->xperm, p->img, p->n_pix, st), "start image");
+    } else {
+      SL1M_HIP(launch_fill(p->xperm, p->n_pix, p->real_bytes, st), "zero y");
+      SL1M_HIP(launch_fill(p->img, p->n_pix, p->real_bytes, st), "zero I");
+    }
     SL1M_HIP(launch_fill(p->flag, 1, sizeof(int), st), "zero divergence flag");
     // a captured graph replays the iteration with one launch (not while the
     // per-kernel timing facility is recording)
@@ -1268,6 +1276,39 @@ sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* p
                        "the iteration produced non-finite values (is L too small?)");
     }
     info->status = SL1M_OK;
+    return SL1M_OK;
+  } catch (...) {
+    return set_error(SL1M_EINVAL, "unexpected host error");
+  }
+}
+
+sl1m_status sl1m_solve(sl1m_plan* p, const void* vis, const sl1m_solve_params* prm,
+                       void* img_out, sl1m_solve_info* info, void* stream) {
+  return solve_impl(p, vis, nullptr, prm, img_out, info, stream);
+}
+
+sl1m_status sl1m_solve_from(sl1m_plan* p, const void* vis, const void* x0,
+                            const sl1m_solve_params* prm, void* img_out, sl1m_solve_info* info,
+                            void* stream) {
+  if (p && p->n_pix > 0 && !x0) return set_error(SL1M_EINVAL, "x0 is NULL");
+  return solve_impl(p, vis, p && p->n_pix > 0 ? x0 : nullptr, prm, img_out, info, stream);
+}
+
+sl1m_status sl1m_dirty_image(sl1m_plan* p, const void* vis, void* img_out, void* stream) {
+  try {
+    if (sl1m_status s = check_plan(p)) return s;
+    if ((p->n_vis > 0 && !vis) || (p->n_pix > 0 && !img_out))
+      return set_error(SL1M_EINVAL, "vis or img_out is NULL");
+    hipStream_t st = S(stream);
+    if (p->n_vis == 0) {
+      SL1M_HIP(launch_fill(img_out, p->n_pix, p->real_bytes, st), "zero image");
+      return SL1M_OK;
+    }
+    SL1M_HIP(launch_adjoint_prep(p, vis, 1, st), "adjoint prep");
+    SL1M_HIP(launch_adjoint(p, 1, st), "adjoint kernel");
+    SL1M_HIP(launch_adjoint_reduce(p, p->img, false, 1, st), "adjoint reduce");
+    SL1M_HIP(launch_dirty_out(p, p->img, img_out, 1.0 / static_cast<double>(p->n_vis), st),
+             "dirty image");
     return SL1M_OK;
   } catch (...) {
     return set_error(SL1M_EINVAL, "unexpected host error");

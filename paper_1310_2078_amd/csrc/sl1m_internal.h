@@ -307,6 +307,8 @@ hipError_t launch_splitmix_start(sl1m_plan* p, uint64_t seed, void* dst, hipStre
 hipError_t launch_scale(sl1m_plan* p, void* x, int64_t n, double a, hipStream_t st);
 hipError_t launch_unpermute(sl1m_plan* p, const void* src, void* dst, hipStream_t st);
 hipError_t launch_copy_real(sl1m_plan* p, const void* src, void* dst, int64_t n, hipStream_t st);
+// dst[perm[j]] = max(0, a * src[j]) (src permuted, dst in the caller's order)
+hipError_t launch_dirty_out(sl1m_plan* p, const void* src, void* dst, double a, hipStream_t st);
 // Fixed-order FP64 reductions; results land in p->red_out.
 //   dot_norm: red_out[0] = <a, b>, red_out[1] = <b, b>            (real [n_pix])
 //   objective: red_out[0] = 1/2 |res|^2, red_out[1] = sum I, red_out[2] = nnz

@@ -360,6 +360,16 @@ __global__ void k_unpermute(const R* __restrict__ src, const int32_t* __restrict
   if (j < n) dst[perm[j]] = src[j];
 }
 
+// Dirty image in the caller's order: dst[perm[j]] = max(0, src[j] * a).
+template <typename R>
+__global__ void k_dirty_out(const R* __restrict__ src, const int32_t* __restrict__ perm,
+                            int64_t n, double a, R* __restrict__ dst) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const R v = src[j] * static_cast<R>(a);
+  dst[perm[j]] = v > R(0) ? v : R(0);
+}
+
 template <typename R>
 __global__ void k_copy(const R* __restrict__ src, int64_t n, R* __restrict__ dst) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -793,6 +803,17 @@ static hipError_t unpermute_t(sl1m_plan* p, const void* src, void* dst, hipStrea
 }
 hipError_t launch_unpermute(sl1m_plan* p, const void* src, void* dst, hipStream_t st) {
   return SL1M_DISPATCH_R(p, unpermute_t, p, src, dst, st);
+}
+
+template <typename R>
+static hipError_t dirty_out_t(sl1m_plan* p, const void* src, void* dst, double a, hipStream_t st) {
+  if (p->n_pix == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_dirty_out<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+                     static_cast<const R*>(src), p->perm, p->n_pix, a, static_cast<R*>(dst));
+  return hipGetLastError();
+}
+hipError_t launch_dirty_out(sl1m_plan* p, const void* src, void* dst, double a, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, dirty_out_t, p, src, dst, a, st);
 }
 
 template <typename R>

@@ -120,6 +120,9 @@ def lib() -> ctypes.CDLL:
         L.sl1m_adjoint_multi.argtypes = [vp, i32, vp, vp, vp]
         L.sl1m_estimate_L.argtypes = [vp, i32, u64, vp, ctypes.POINTER(dbl), vp]
         L.sl1m_solve.argtypes = [vp, vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(SolveInfo), vp]
+        L.sl1m_solve_from.argtypes = [vp, vp, vp, ctypes.POINTER(SolveParams), vp,
+                                      ctypes.POINTER(SolveInfo), vp]
+        L.sl1m_dirty_image.argtypes = [vp, vp, vp, vp]
         L.sl1m_server_create.argtypes = [vp, ctypes.c_size_t, i32, dbl, ctypes.POINTER(vp)]
         L.sl1m_server_submit.argtypes = [vp, ctypes.POINTER(Problem), vp,
                                          ctypes.POINTER(SolveParams), vp,
@@ -142,6 +145,7 @@ def lib() -> ctypes.CDLL:
         for name in ("sl1m_plan_workspace_bytes", "sl1m_plan_create", "sl1m_plan_destroy",
                      "sl1m_forward", "sl1m_adjoint", "sl1m_forward_multi",
                      "sl1m_adjoint_multi", "sl1m_estimate_L", "sl1m_solve",
+                     "sl1m_solve_from", "sl1m_dirty_image",
                      "sl1m_timing_begin", "sl1m_timing_end", "sl1m_plan_query",
                      "sl1m_tune_workspace_bytes", "sl1m_tune",
                      "sl1m_server_create",
@@ -347,7 +351,11 @@ class Plan:
 
     def solve(self, vis, lam: float, max_iter: int, L: float = 0.0, eps: float = 0.0,
               check_every: int = 1, power_iters: int = 30, seed: int = 0,
-              L_safety: float = 1.01, out: Optional[torch.Tensor] = None, stream=None):
+              L_safety: float = 1.01, out: Optional[torch.Tensor] = None, stream=None,
+              x0=None):
+        """FISTA solve (sl1m_solve); with x0 (real [n_pix]) the warm start
+        sl1m_solve_from, e.g. from dirty_image() or an upscaled coarser
+        solution."""
         vis = _dev(vis, self.cdtype, self.device)
         if out is None:
             out = torch.empty(self.n_pix, dtype=self.rdtype, device=self.device)
@@ -355,9 +363,22 @@ class Plan:
                           check_every=int(check_every), L=float(L), L_safety=float(L_safety),
                           power_iters=int(power_iters), reserved=0, seed=ctypes.c_uint64(seed))
         info = SolveInfo()
-        _check(lib().sl1m_solve(self._h, _ptr(vis), ctypes.byref(prm), _ptr(out),
-                                ctypes.byref(info), _stream(stream)))
+        if x0 is None:
+            _check(lib().sl1m_solve(self._h, _ptr(vis), ctypes.byref(prm), _ptr(out),
+                                    ctypes.byref(info), _stream(stream)))
+        else:
+            x0 = _dev(x0, self.rdtype, self.device)
+            _check(lib().sl1m_solve_from(self._h, _ptr(vis), _ptr(x0), ctypes.byref(prm),
+                                         _ptr(out), ctypes.byref(info), _stream(stream)))
         return out, info.as_dict()
+
+    def dirty_image(self, vis, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """max(0, Re(M^H V) / n_vis) in the caller's pixel order (sl1m_dirty_image)."""
+        vis = _dev(vis, self.cdtype, self.device)
+        if out is None:
+            out = torch.empty(self.n_pix, dtype=self.rdtype, device=self.device)
+        _check(lib().sl1m_dirty_image(self._h, _ptr(vis), _ptr(out), _stream(stream)))
+        return out
 
     def timing_begin(self, max_launches: int = 4096):
         _check(lib().sl1m_timing_begin(self._h, int(max_launches)))

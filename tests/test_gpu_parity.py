@@ -352,3 +352,38 @@ def test_graph_replayed_iteration_equals_direct_launches():
     plan.timing_end()
     assert np.array_equal(c.cpu().numpy(), a)
     assert ia["F"] == ib["F"] == ic["F"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_dirty_image_and_warm_start_match_oracle(prec):
+    """Warm starts (Section "Acceleration strategies"): the dirty image
+    max(0, Re(M^H V) / N_v) against the oracle's, then 30 FISTA iterations
+    from it and from a positive random image against the oracle's warm-started
+    iteration (same L).  Config 1 runs on the grid evaluation in FP32."""
+    say(f"[case] dirty image and warm start {prec}")
+    wl, op, V, L = _config1_data()
+    plan = sl1m.Plan.from_workload(wl, precision=prec)
+    Dg = plan.dirty_image(V).cpu().numpy()
+    Do = O.dirty_image(op, V)
+    ed = rel(Dg, Do)
+    say(f"    dirty image rel err {ed:.3e}")
+    assert ed <= TOL[prec] and np.all(Dg >= 0)
+    starts = {"dirty": Do, "random": np.abs(np.random.default_rng(8).standard_normal(wl.n_pix)) * 0.1}
+    for name, I0 in starts.items():
+        ref = O.fista_from(op, V, L, wl.lam, 30, I0)
+        img, info = plan.solve(V, wl.lam, 30, L=L, x0=I0)
+        err = np.max(np.abs(img.cpu().numpy() - ref.image)) / np.max(ref.image)
+        say(f"    from {name}: image err/peak {err:.3e}  F gpu {info['F']:.8g} oracle {ref.F:.8g}")
+        assert err <= (1e-4 if prec == "fp32" else 1e-10)
+        assert abs(info["F"] - ref.F) <= (1e-4 if prec == "fp32" else 1e-10) * ref.F
+    # x0 is required for a warm start (NULL through the C call)
+    import ctypes
+    with pytest.raises(sl1m.SL1MError):
+        info = sl1m.SolveInfo()
+        prm = sl1m.SolveParams(lam=wl.lam, eps=0.0, max_iter=2, check_every=1, L=L,
+                               L_safety=1.01, power_iters=30, reserved=0,
+                               seed=ctypes.c_uint64(0))
+        out = torch.empty(wl.n_pix, dtype=plan.rdtype, device=plan.device)
+        Vt = torch.as_tensor(V, dtype=plan.cdtype, device=plan.device)
+        sl1m._check(sl1m.lib().sl1m_solve_from(plan._h, Vt.data_ptr(), None, ctypes.byref(prm),
+                                               out.data_ptr(), ctypes.byref(info), None))

@@ -167,3 +167,30 @@ def test_fista_mutations_are_caught(monkeypatch, kw, pins):
     monkeypatch.setattr(OM, "fista", bad)
     for name in pins:
         assert _fails(getattr(P, name)), f"{kw} not caught by {name}"
+
+
+def test_warm_start_mutations_are_caught(monkeypatch):
+    """A dirty image normalised by 2 N_v, or without its clip, and a warm start
+    that ignores I_0 (starts from y_1 = 0) are each caught."""
+    def dirty_half(op, V):
+        op = OM._as_op(op)
+        return np.maximum(op.adjoint(np.asarray(V, np.complex128)) / (2 * op.p.n_vis), 0.0)
+
+    monkeypatch.setattr(O, "dirty_image", dirty_half)
+    assert _fails(P.test_dirty_image_of_point_source_closed_form)
+    monkeypatch.undo()
+
+    def dirty_noclip(op, V):
+        op = OM._as_op(op)
+        return op.adjoint(np.asarray(V, np.complex128)) / op.p.n_vis
+
+    monkeypatch.setattr(O, "dirty_image", dirty_noclip)
+    assert _fails(P.test_dirty_image_of_point_source_closed_form)
+    monkeypatch.undo()
+
+    def from_zero(op, V, L, lam, n_iter, I0, **kw):
+        return OM.fista(op, V, L, lam, n_iter, **kw)
+
+    monkeypatch.setattr(O, "fista_from", from_zero)
+    assert _fails(P.test_warm_start_at_the_minimiser_stays_there)
+    assert _fails(P.test_warm_start_first_iterate_closed_form)

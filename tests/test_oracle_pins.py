@@ -503,3 +503,66 @@ def test_fista_second_iterate_is_plain_step():
     I1 = res.history[0]
     expect = O.threshold_pos(I1 - op.adjoint(op.forward(I1) - V) / L, lam / L)
     np.testing.assert_allclose(res.history[1], expect, rtol=1e-14, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# warm starts (Section "Acceleration strategies", reading R16)
+# --------------------------------------------------------------------------
+
+def test_dirty_image_of_point_source_closed_form():
+    """Unit gains, one point source of flux S at pixel s, no noise: every
+    |M_ks|^2 = 1/n_s^2, so Re(M^H V)_s / N_v = S / n_s^2 whatever the uv
+    coverage; elsewhere the dirty image is the (clipped) normalised beam."""
+    rng = np.random.default_rng(41)
+    l = rng.uniform(-0.4, 0.4, 30)
+    m = rng.uniform(-0.4, 0.4, 30)
+    u, v = rng.uniform(-300, 300, (2, 400))
+    w = rng.normal(0, 40, 400)
+    p = _prob(l, m, u, v, w)
+    op = O.Operator(p, dense=True)
+    s, S = 7, 2.5
+    x = np.zeros(30)
+    x[s] = S
+    D = O.dirty_image(op, op.forward(x))
+    n_s = math.sqrt(1.0 - l[s] ** 2 - m[s] ** 2)
+    assert D[s] == pytest.approx(S / n_s ** 2, rel=1e-12)
+    # the beam at other pixels: Re sum_k M_kj conj-weighted / N_v, by brute force
+    beam = np.array([np.mean((np.conj(op.M[:, j]) * op.M[:, s]).real) for j in range(30)]) * S
+    np.testing.assert_allclose(D, np.maximum(beam, 0.0), rtol=0, atol=1e-12)
+    assert np.all(D >= 0)
+
+
+def test_warm_start_at_the_minimiser_stays_there():
+    """The LASSO minimiser (certified by KKT) is a fixed point of the
+    proximal-gradient step; a warm start from it stays there (y_1 = I_0, and
+    the first momentum coefficient is 0).  A start that ignored I_0 would
+    move to the first cold iterate instead."""
+    p, x = _small_solve_problem(n_vis=60, seed=33)
+    op = O.Operator(p, dense=True)
+    rng = np.random.default_rng(0)
+    V = op.forward(x) + 0.05 * (rng.standard_normal(p.n_vis) + 1j * rng.standard_normal(p.n_vis))
+    lam = 0.3
+    L, _ = O.power_iteration(op, 100)
+    star = O.fista(op, V, L, lam, 4000).image
+    assert O.kkt_residual(op, V, star, lam) < 1e-6
+    res = O.fista_from(op, V, L, lam, 5, star, keep_history=True)
+    for I in res.history:
+        np.testing.assert_allclose(I, star, rtol=0, atol=1e-6)
+    cold1 = O.fista(op, V, L, lam, 1).image
+    assert np.max(np.abs(cold1 - star)) > 1e-3
+
+
+def test_warm_start_first_iterate_closed_form():
+    """From I_0: I_1 = T^{lam/L}(I_0 - Re M^H (M I_0 - V) / L), and the second
+    step's y_2 = I_1 (momentum coefficient (t_1 - 1)/t_2 = 0)."""
+    p, x = _small_solve_problem()
+    op = O.Operator(p, dense=True)
+    V = op.forward(x)
+    L, _ = O.power_iteration(op, 50)
+    lam = 0.5
+    I0 = np.abs(np.random.default_rng(5).standard_normal(p.n_pix))
+    res = O.fista_from(op, V, L, lam, 2, I0, keep_history=True)
+    I1 = O.threshold_pos(I0 - op.adjoint(op.forward(I0) - V) / L, lam / L)
+    np.testing.assert_allclose(res.history[0], I1, rtol=1e-13, atol=1e-14)
+    I2 = O.threshold_pos(I1 - op.adjoint(op.forward(I1) - V) / L, lam / L)
+    np.testing.assert_allclose(res.history[1], I2, rtol=1e-13, atol=1e-14)
