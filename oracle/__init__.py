@@ -1,2 +1,3 @@
 """FP64 CPU oracle for SL1M (test infrastructure only; see sl1m_oracle)."""
 from .sl1m_oracle import *  # noqa: F401,F403
+from . import quadtree  # noqa: F401  (adaptive refinement, reading R17)
