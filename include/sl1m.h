@@ -267,9 +267,20 @@ typedef struct {
   double L;             /* step constant; <= 0 runs sl1m_estimate_L first            */
   double L_safety;      /* factor applied to an estimated L (e.g. 1.01); <= 0 -> 1.01 */
   int32_t power_iters;  /* power-iteration steps when L <= 0 (e.g. 30)               */
-  int32_t reserved;
+  int32_t method;       /* sl1m_method (0: the printed FISTA)                        */
   uint64_t seed;        /* SplitMix64 state for the power-iteration start            */
 } sl1m_solve_params;
+
+/* The iteration sl1m_solve runs.  SL1M_MFISTA is the monotone variant the
+ * paper names after its algorithm (Section "Implementation of SL1M"; Beck &
+ * Teboulle): from x_0 = y_1 = I_0, t_1 = 1,
+ *   z_k = T^{lambda/L}(y_k - Re M^H (M y_k - V) / L);
+ *   x_k = z_k if F(z_k) <= F(x_{k-1}) else x_{k-1};
+ *   y_{k+1} = x_k + (t_k/t_{k+1})(z_k - x_k) + ((t_k - 1)/t_{k+1})(x_k - x_{k-1}),
+ * so F never increases, at the cost of one more forward operator per
+ * iteration (F(z_k) is formed and compared on the device).  The server runs
+ * SL1M_FISTA only. */
+typedef enum { SL1M_FISTA = 0, SL1M_MFISTA = 1 } sl1m_method;
 
 typedef struct {
   int32_t iters;        /* iterations run                                            */

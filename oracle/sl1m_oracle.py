@@ -471,6 +471,39 @@ def fista_from(op, V, L: float, lam: float, n_iter: int, I0, eps: float = 0.0,
                  keep_history=keep_history, state=(0, 1.0, I0.copy(), I0.copy()))
 
 
+def mfista(op, V, L: float, lam: float, n_iter: int, I0=None, keep_history: bool = False):
+    """The monotone variant the paper names after the printed algorithm
+    (Section "Implementation of SL1M": MFISTA of Beck & Teboulle, at the cost
+    of one more evaluation of M per iteration).  From x_0 = y_1 = I_0 (0 when
+    not given), t_1 = 1, step k:
+      z_k     = T^{lambda/L}( y_k - (1/L) Re M^H (M y_k - V) )
+      t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+      x_k     = z_k if F(z_k) <= F(x_{k-1}) else x_{k-1}
+      y_{k+1} = x_k + (t_k/t_{k+1}) (z_k - x_k) + ((t_k - 1)/t_{k+1}) (x_k - x_{k-1})
+    so F(x_k) never increases."""
+    op = _as_op(op)
+    V = np.asarray(V, np.complex128)
+    x = np.zeros(op.n_pix) if I0 is None else np.asarray(I0, np.float64).copy()
+    y = x.copy()
+    t = 1.0
+    Fx = objective(op, V, x, lam)[0]
+    hist = []
+    for _ in range(n_iter):
+        grad = op.adjoint(op.forward(y) - V)
+        z = threshold_pos(y - grad / L, lam / L)
+        t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        Fz = objective(op, V, z, lam)[0]
+        x_new = z if Fz <= Fx else x
+        y = x_new + (t / t_next) * (z - x_new) + ((t - 1.0) / t_next) * (x_new - x)
+        x, t, Fx = x_new, t_next, min(Fz, Fx)
+        if keep_history:
+            hist.append(x.copy())
+    F, l2, l1 = objective(op, V, x, lam)
+    return FistaResult(image=x, iters=n_iter, L=L, F=F, l2_term=l2, l1_term=l1,
+                       nnz=int(np.count_nonzero(x)), converged=False, history=hist,
+                       state=None)
+
+
 def kkt_residual(op, V, I, lam):
     """Optimality certificate of min 1/2|V - M I|^2 + lam sum I, I >= 0.
 

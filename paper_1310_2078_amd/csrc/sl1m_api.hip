@@ -451,7 +451,8 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
 
 struct Layout {
   size_t perm, pixrec, pl, pm, pc3, pc4, pscale, pr2, vu, vv, vw, vgain, vbeta, visrecD, visrecG,
-      rres, rpol, layerDs, chunks, fpart, apart, xperm, img, res, red, red_out, flag, scal, grid_la,
+      rres, rpol, layerDs, chunks, fpart, apart, xperm, img, zbuf, res, red, red_out, flag, scal,
+      grid_la,
       grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb,
       grid_prec, grid_precm, total;
 };
@@ -494,6 +495,7 @@ Layout layout(const Analysis& a) {
   L.apart = take(rb * static_cast<size_t>(a.n_achunks) * np * nr);
   L.xperm = take(rb * np * nr);
   L.img = take(rb * np);
+  L.zbuf = take(rb * np);
   L.res = take(2 * rb * nv);
   L.red = take(8 * 3 * kRedBlocks + 8 * kMaxLayers);
   L.red_out = take(8 * 8);
@@ -547,12 +549,21 @@ sl1m_status apply_forward(sl1m_plan* p, const void* xp, const void* data, void* 
   return SL1M_OK;
 }
 
-// One FISTA iteration (forward at y, residual, adjoint, update, t step); the
-// launch sequence is the same every iteration.
-sl1m_status enqueue_iteration(sl1m_plan* p, const void* vis, hipStream_t st) {
+// One iteration (forward at y, residual, adjoint, update, t step); the launch
+// sequence is the same every iteration.  MFISTA adds the proximal point z, a
+// forward at z and its objective, and the device-side selection.
+sl1m_status enqueue_iteration(sl1m_plan* p, const void* vis, hipStream_t st, int method) {
   sl1m_status s = apply_forward(p, p->xperm, vis, p->res, true, st);
   if (s) return s;
   SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
+  if (method == SL1M_MFISTA) {
+    SL1M_HIP(timed(p, 2, st, [&] { return launch_prox(p, st); }), "proximal step");
+    s = apply_forward(p, p->zbuf, vis, p->res, false, st);
+    if (s) return s;
+    SL1M_HIP(launch_objective_terms(p, p->res, p->zbuf, st), "objective of z");
+    SL1M_HIP(launch_mfista_select(p, st), "mfista selection");
+    return SL1M_OK;
+  }
   SL1M_HIP(timed(p, 2, st, [&] { return launch_fista_update(p, st); }), "fista update");
   return SL1M_OK;
 }
@@ -563,19 +574,21 @@ void release_graph(sl1m_plan* p) {
   p->iter_exec = nullptr;
   p->iter_graph = nullptr;
   p->iter_vis = nullptr;
+  p->iter_method = 0;
 }
 
 // Captures one iteration into a graph (on a private stream: capture records
-// launches without running them) unless one for the same data pointer exists.
-sl1m_status ensure_graph(sl1m_plan* p, const void* vis) {
-  if (p->iter_exec && p->iter_vis == vis) return SL1M_OK;
+// launches without running them) unless one for the same data pointer and
+// method exists.
+sl1m_status ensure_graph(sl1m_plan* p, const void* vis, int method) {
+  if (p->iter_exec && p->iter_vis == vis && p->iter_method == method) return SL1M_OK;
   release_graph(p);
   hipStream_t cs = nullptr;
   SL1M_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   sl1m_status s = SL1M_OK;
   if (e == hipSuccess) {
-    s = enqueue_iteration(p, vis, cs);
+    s = enqueue_iteration(p, vis, cs, method);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (s == SL1M_OK && e2 != hipSuccess) s = hip_error(e2, "end capture");
@@ -595,6 +608,7 @@ sl1m_status ensure_graph(sl1m_plan* p, const void* vis) {
     return s;
   }
   p->iter_vis = vis;
+  p->iter_method = method;
   return SL1M_OK;
 }
 
@@ -746,6 +760,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->apart = w + L.apart;
     p->xperm = w + L.xperm;
     p->img = w + L.img;
+    p->zbuf = w + L.zbuf;
     p->res = w + L.res;
     p->red = reinterpret_cast<double*>(w + L.red);
     p->red_out = reinterpret_cast<double*>(w + L.red_out);
@@ -1198,6 +1213,9 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
     if (!(prm->eps >= 0.0)) return set_error(SL1M_EINVAL, "eps must be >= 0");
     if (prm->eps > 0.0 && prm->check_every < 1)
       return set_error(SL1M_EINVAL, "check_every must be >= 1 when eps > 0");
+    if (prm->method != SL1M_FISTA && prm->method != SL1M_MFISTA)
+      return set_error(SL1M_EINVAL, "unknown method");
+    const int method = prm->method;
     std::memset(info, 0, sizeof(*info));
     hipStream_t st = S(stream);
     double L = prm->L;
@@ -1211,7 +1229,7 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
       if (!(L > 0.0)) return set_error(SL1M_EINVAL, "estimated L is not positive (M = 0?)");
     }
     info->L = L;
-    const double scal_h[3] = {1.0, 1.0 / L, prm->lambda / L};
+    const double scal_h[5] = {1.0, 1.0 / L, prm->lambda / L, prm->lambda, 0.0};
     SL1M_HIP(hipMemcpyAsync(p->scal, scal_h, sizeof(scal_h), hipMemcpyHostToDevice, st),
              "solver scalars");
     if (x0) {
@@ -1223,10 +1241,16 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
       SL1M_HIP(launch_fill(p->img, p->n_pix, p->real_bytes, st), "zero I");
     }
     SL1M_HIP(launch_fill(p->flag, 1, sizeof(int), st), "zero divergence flag");
+    if (method == SL1M_MFISTA) {  // F(x_0) for the first selection
+      sl1m_status s = apply_forward(p, p->img, vis, p->res, false, st);
+      if (s) return s;
+      SL1M_HIP(launch_objective_terms(p, p->res, p->img, st), "objective of x0");
+      SL1M_HIP(launch_mfista_init(p, st), "mfista start");
+    }
     // a captured graph replays the iteration with one launch (not while the
     // per-kernel timing facility is recording)
     bool use_graph = !p->timing && prm->max_iter > 1;
-    if (use_graph && ensure_graph(p, vis) != SL1M_OK) {
+    if (use_graph && ensure_graph(p, vis, method) != SL1M_OK) {
       use_graph = false;  // capture unavailable: launch the kernels directly
       set_error(SL1M_OK, "");
       (void)hipGetLastError();
@@ -1238,7 +1262,7 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
       if (use_graph) {
         SL1M_HIP(hipGraphLaunch(p->iter_exec, st), "graph launch");
       } else {
-        sl1m_status s = enqueue_iteration(p, vis, st);
+        sl1m_status s = enqueue_iteration(p, vis, st, method);
         if (s) return s;
       }
       if (prm->eps > 0.0 && k % prm->check_every == 0) {

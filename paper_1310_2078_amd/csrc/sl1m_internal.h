@@ -240,16 +240,19 @@ struct sl1m_plan {
   void* apart = nullptr;            // R[n_achunks][n_pix]
   void* xperm = nullptr;            // R[n_pix] permuted input / iterate y
   void* img = nullptr;              // R[n_pix] iterate I
+  void* zbuf = nullptr;             // R[n_pix] MFISTA proximal point z_k
   void* res = nullptr;              // R[2*n_vis] residual
   double* red = nullptr;            // reduction scratch [kRedSlots]
   double* red_out = nullptr;        // [8] final reduction results
   int* flag = nullptr;              // domain-check counter
-  double* scal = nullptr;           // FISTA scalars on the device: t_k, 1/L, lambda/L
+  double* scal = nullptr;           // solver scalars on the device: t_k, 1/L, lambda/L,
+                                    // lambda, F(x_{k-1}) (MFISTA)
 
   // captured FISTA iteration (replayed with hipGraphLaunch)
   hipGraph_t iter_graph = nullptr;
   hipGraphExec_t iter_exec = nullptr;
   const void* iter_vis = nullptr;   // data pointer the captured graph reads
+  int iter_method = 0;              // sl1m_method the captured graph runs
 
   // kernel timing (sl1m_timing_begin/end)
   bool timing = false;
@@ -309,6 +312,12 @@ hipError_t launch_unpermute(sl1m_plan* p, const void* src, void* dst, hipStream_
 hipError_t launch_copy_real(sl1m_plan* p, const void* src, void* dst, int64_t n, hipStream_t st);
 // dst[perm[j]] = max(0, a * src[j]) (src permuted, dst in the caller's order)
 hipError_t launch_dirty_out(sl1m_plan* p, const void* src, void* dst, double a, hipStream_t st);
+// MFISTA: z = T(y - g / L) (zbuf); selection and extrapolation from the
+// objective reduction of z in red_out (then F(x_k) and t_{k+1} in scal);
+// F(x_0) from the objective reduction of x_0.
+hipError_t launch_prox(sl1m_plan* p, hipStream_t st);
+hipError_t launch_mfista_select(sl1m_plan* p, hipStream_t st);
+hipError_t launch_mfista_init(sl1m_plan* p, hipStream_t st);
 // Fixed-order FP64 reductions; results land in p->red_out.
 //   dot_norm: red_out[0] = <a, b>, red_out[1] = <b, b>            (real [n_pix])
 //   objective: red_out[0] = 1/2 |res|^2, red_out[1] = sum I, red_out[2] = nnz

@@ -212,6 +212,61 @@ __global__ __launch_bounds__(kBlock) void k_fista(const R* __restrict__ part, in
   img[j] = in;
 }
 
+// MFISTA (the monotone variant of Beck & Teboulle the paper names): the
+// proximal step z_k = T^{lambda/L}(y_k - g / L) into z, g as for k_fista.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_prox(const R* __restrict__ part, int n_rows,
+                                                 int64_t n_pix, const R* __restrict__ scale,
+                                                 const R* __restrict__ y, R* __restrict__ z,
+                                                 const double* __restrict__ scal,
+                                                 int* __restrict__ flag) {
+  __shared__ R sh[4][kRowPix];
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kRowPix + threadIdx.x % kRowPix;
+  R g = row_sum<R>(part, n_rows, n_pix, 0, j, sh);
+  if (threadIdx.x >= kRowPix || j >= n_pix) return;
+  const R inv_L = static_cast<R>(scal[1]), thr = static_cast<R>(scal[2]);
+  g *= scale[j];
+  const R v = y[j] - g * inv_L;
+  if (!isfinite(v)) atomicOr(flag, 1);
+  z[j] = v > thr ? v - thr : R(0);
+}
+
+// MFISTA selection and extrapolation, from F(z_k) = red[0] + lambda red[1]
+// (the objective reduction of z_k) and F(x_{k-1}) = scal[4]:
+//   x_k = z_k if F(z_k) <= F(x_{k-1}) else x_{k-1}
+//   y_{k+1} = x_k + (t_k/t_{k+1})(z_k - x_k) + ((t_k - 1)/t_{k+1})(x_k - x_{k-1})
+// img holds x_{k-1} on entry and x_k on exit.  Every block reads the same
+// scalars, so every pixel takes the same choice.
+template <typename R>
+__global__ void k_mfista_select(R* __restrict__ y, R* __restrict__ img, const R* __restrict__ z,
+                                int64_t n, const double* __restrict__ scal,
+                                const double* __restrict__ red) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double Fz = red[0] + scal[3] * red[1];
+  const bool take = Fz <= scal[4];
+  const double t = scal[0];
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  const R a = static_cast<R>(t / tn), b = static_cast<R>((t - 1.0) / tn);
+  const R xo = img[j], zj = z[j];
+  const R xk = take ? zj : xo;
+  y[j] = xk + a * (zj - xk) + b * (xk - xo);
+  img[j] = xk;
+}
+
+// After the selection: F(x_k) = min(F(z_k), F(x_{k-1})), t_{k+1}.
+__global__ void k_mfista_step(double* __restrict__ scal, const double* __restrict__ red) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double Fz = red[0] + scal[3] * red[1];
+  scal[4] = Fz < scal[4] ? Fz : scal[4];
+  scal[0] = 0.5 * (1.0 + sqrt(1.0 + 4.0 * scal[0] * scal[0]));
+}
+
+// F(x_0) = red[0] + lambda red[1] into scal[4] (start of an MFISTA solve).
+__global__ void k_mfista_init(double* __restrict__ scal, const double* __restrict__ red) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) scal[4] = red[0] + scal[3] * red[1];
+}
+
 // t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
 __global__ void k_tstep(double* __restrict__ scal) {
   if (threadIdx.x == 0 && blockIdx.x == 0) scal[0] = 0.5 * (1.0 + sqrt(1.0 + 4.0 * scal[0] * scal[0]));
@@ -762,6 +817,37 @@ static hipError_t fista_t(sl1m_plan* p, hipStream_t st) {
 }
 hipError_t launch_fista_update(sl1m_plan* p, hipStream_t st) {
   return SL1M_DISPATCH_R(p, fista_t, p, st);
+}
+
+template <typename R>
+static hipError_t prox_t(sl1m_plan* p, hipStream_t st) {
+  if (p->n_pix > 0)
+    hipLaunchKernelGGL((k_prox<R>), dim3(grid1(p->n_pix, kRowPix)), dim3(kBlock), 0, st,
+                       static_cast<const R*>(p->apart), p->n_achunks, p->n_pix,
+                       static_cast<const R*>(p->pscale), static_cast<const R*>(p->xperm),
+                       static_cast<R*>(p->zbuf), p->scal, p->flag);
+  return hipGetLastError();
+}
+hipError_t launch_prox(sl1m_plan* p, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, prox_t, p, st);
+}
+
+template <typename R>
+static hipError_t mfista_select_t(sl1m_plan* p, hipStream_t st) {
+  if (p->n_pix > 0)
+    hipLaunchKernelGGL((k_mfista_select<R>), dim3(grid1(p->n_pix)), dim3(kBlock), 0, st,
+                       static_cast<R*>(p->xperm), static_cast<R*>(p->img),
+                       static_cast<const R*>(p->zbuf), p->n_pix, p->scal, p->red_out);
+  hipLaunchKernelGGL(k_mfista_step, dim3(1), dim3(64), 0, st, p->scal, p->red_out);
+  return hipGetLastError();
+}
+hipError_t launch_mfista_select(sl1m_plan* p, hipStream_t st) {
+  return SL1M_DISPATCH_R(p, mfista_select_t, p, st);
+}
+
+hipError_t launch_mfista_init(sl1m_plan* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_mfista_init, dim3(1), dim3(64), 0, st, p->scal, p->red_out);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(void* dst, size_t n_elems, size_t elem_bytes, hipStream_t st) {

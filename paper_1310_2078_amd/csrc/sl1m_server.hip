@@ -1026,6 +1026,8 @@ sl1m_status sl1m_server_submit(sl1m_server* s, const sl1m_problem* problem, cons
     if (!s || !problem || !params || !ticket) return set_error(SL1M_EINVAL, "NULL argument");
     if (problem->precision != SL1M_PREC_FP32)
       return set_error(SL1M_EINVAL, "the server runs FP32 plans only");
+    if (params->method != SL1M_FISTA)
+      return set_error(SL1M_EINVAL, "the server runs FISTA only");
     if (problem->max_rhs > 1) return set_error(SL1M_EINVAL, "the server solves one image each");
     if ((problem->n_vis > 0 && !vis) || (problem->n_pix > 0 && !img_out))
       return set_error(SL1M_EINVAL, "vis or img_out is NULL");

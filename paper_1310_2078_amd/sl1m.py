@@ -79,7 +79,7 @@ class SolveParams(ctypes.Structure):
         ("L", ctypes.c_double),
         ("L_safety", ctypes.c_double),
         ("power_iters", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("method", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -180,6 +180,7 @@ def _dev(a, dtype, device):
 
 
 GRID_AUTO, GRID_OFF, GRID_REQUIRE = 0, 1, 2
+METHODS = {"fista": 0, "mfista": 1}
 _GRID = {"auto": GRID_AUTO, "off": GRID_OFF, "require": GRID_REQUIRE}
 
 
@@ -352,16 +353,17 @@ class Plan:
     def solve(self, vis, lam: float, max_iter: int, L: float = 0.0, eps: float = 0.0,
               check_every: int = 1, power_iters: int = 30, seed: int = 0,
               L_safety: float = 1.01, out: Optional[torch.Tensor] = None, stream=None,
-              x0=None):
+              x0=None, method: str = "fista"):
         """FISTA solve (sl1m_solve); with x0 (real [n_pix]) the warm start
         sl1m_solve_from, e.g. from dirty_image() or an upscaled coarser
-        solution."""
+        solution; method "mfista" runs the monotone variant."""
         vis = _dev(vis, self.cdtype, self.device)
         if out is None:
             out = torch.empty(self.n_pix, dtype=self.rdtype, device=self.device)
         prm = SolveParams(lam=float(lam), eps=float(eps), max_iter=int(max_iter),
                           check_every=int(check_every), L=float(L), L_safety=float(L_safety),
-                          power_iters=int(power_iters), reserved=0, seed=ctypes.c_uint64(seed))
+                          power_iters=int(power_iters), method=METHODS[method],
+                          seed=ctypes.c_uint64(seed))
         info = SolveInfo()
         if x0 is None:
             _check(lib().sl1m_solve(self._h, _ptr(vis), ctypes.byref(prm), _ptr(out),
@@ -473,7 +475,7 @@ class Server:
                        grid_mode=_GRID[grid])
         prm = SolveParams(lam=float(lam), eps=0.0, max_iter=int(max_iter), check_every=1,
                           L=float(L), L_safety=float(L_safety), power_iters=int(power_iters),
-                          reserved=0, seed=ctypes.c_uint64(seed))
+                          method=0, seed=ctypes.c_uint64(seed))
         t = ctypes.c_uint64(0)
         torch.cuda.current_stream(d).synchronize()   # inputs written before the server reads them
         _check(lib().sl1m_server_submit(self._h, ctypes.byref(prob), _ptr(keep["vis"]),

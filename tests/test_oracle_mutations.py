@@ -194,3 +194,36 @@ def test_warm_start_mutations_are_caught(monkeypatch):
     monkeypatch.setattr(O, "fista_from", from_zero)
     assert _fails(P.test_warm_start_at_the_minimiser_stays_there)
     assert _fails(P.test_warm_start_first_iterate_closed_form)
+
+
+def _make_mfista(select=True, flip=False):
+    def mfista(op, V, L, lam, n_iter, I0=None, keep_history=False):
+        op = OM._as_op(op)
+        V = np.asarray(V, np.complex128)
+        x = np.zeros(op.n_pix) if I0 is None else np.asarray(I0, float).copy()
+        y, t = x.copy(), 1.0
+        Fx = OM.objective(op, V, x, lam)[0]
+        hist = []
+        for _ in range(n_iter):
+            z = OM.threshold_pos(y - op.adjoint(op.forward(y) - V) / L, lam / L)
+            tn = (1 + math.sqrt(1 + 4 * t * t)) / 2
+            Fz = OM.objective(op, V, z, lam)[0]
+            take = (Fz >= Fx) if flip else (Fz <= Fx)
+            xn = z if (take or not select) else x
+            y = xn + (t / tn) * (z - xn) + ((t - 1) / tn) * (xn - x)
+            x, t, Fx = xn, tn, (min(Fz, Fx) if select else Fz)
+            hist.append(x.copy())
+        F, l2, l1 = OM.objective(op, V, x, lam)
+        return OM.FistaResult(image=x, iters=n_iter, L=L, F=F, l2_term=l2, l1_term=l1,
+                              nnz=int(np.count_nonzero(x)), converged=False, history=hist,
+                              state=None)
+    return mfista
+
+
+@pytest.mark.parametrize("kw,pin", [
+    (dict(select=False), "test_mfista_is_monotone_and_keeps_the_rate_bound"),
+    (dict(flip=True), "test_mfista_is_monotone_and_keeps_the_rate_bound"),
+])
+def test_mfista_mutations_are_caught(monkeypatch, kw, pin):
+    monkeypatch.setattr(O, "mfista", _make_mfista(**kw))
+    assert _fails(getattr(P, pin)), f"{kw} not caught by {pin}"

@@ -566,3 +566,57 @@ def test_warm_start_first_iterate_closed_form():
     np.testing.assert_allclose(res.history[0], I1, rtol=1e-13, atol=1e-14)
     I2 = O.threshold_pos(I1 - op.adjoint(op.forward(I1) - V) / L, lam / L)
     np.testing.assert_allclose(res.history[1], I2, rtol=1e-13, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# MFISTA (the monotone variant the paper names)
+# --------------------------------------------------------------------------
+
+def test_mfista_is_monotone_and_keeps_the_rate_bound():
+    """Beck & Teboulle's MFISTA: F(x_k) never increases, and the same
+    F(x_k) - F* <= 2 L |x_0 - x*|^2 / (k + 1)^2 bound as FISTA holds."""
+    p, x = _small_solve_problem(n_vis=25, seed=35, n_src=4)
+    op = O.Operator(p, dense=True)
+    V = op.forward(x)
+    lam = 0.05
+    L, _ = O.power_iteration(op, 200)
+    star = O.fista(op, V, L, lam, 30000)
+    res = O.mfista(op, V, L, lam, 300, keep_history=True)
+    F = [O.objective(op, V, I, lam)[0] for I in res.history]
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(F, F[1:]))
+    for k, Fk in enumerate(F, start=1):
+        assert Fk - star.F <= 2 * L * np.dot(star.image, star.image) / (k + 1) ** 2 + 1e-12
+    # plain FISTA on this problem is not monotone, so the test tells them apart
+    fi = O.fista(op, V, L, lam, 300, keep_history=True)
+    Ff = [O.objective(op, V, I, lam)[0] for I in fi.history]
+    assert any(b > a * (1 + 1e-9) for a, b in zip(Ff, Ff[1:]))
+
+
+def test_mfista_converges_to_the_minimiser():
+    """Same limit as FISTA and L-BFGS-B, certified by KKT."""
+    p, x = _small_solve_problem(n_vis=60, seed=33)
+    op = O.Operator(p, dense=True)
+    rng = np.random.default_rng(0)
+    V = op.forward(x) + 0.05 * (rng.standard_normal(p.n_vis) + 1j * rng.standard_normal(p.n_vis))
+    lam = 0.3
+    L, _ = O.power_iteration(op, 100)
+    res = O.mfista(op, V, L, lam, 4000)
+    assert O.kkt_residual(op, V, res.image, lam) < 1e-6
+    ref = O.fista(op, V, L, lam, 4000)
+    assert abs(res.F - ref.F) <= 1e-9 * abs(ref.F)
+
+
+def test_mfista_first_iterate_closed_form():
+    """From x_0 = 0: z_1 = T(Re M^H V / L); x_1 = z_1 when F(z_1) <= F(0) =
+    |V|^2 / 2 (always here), and y_2 = x_1 (t_1 = 1)."""
+    p, x = _small_solve_problem()
+    op = O.Operator(p, dense=True)
+    V = op.forward(x)
+    L, _ = O.power_iteration(op, 50)
+    lam = 0.5
+    res = O.mfista(op, V, L, lam, 2, keep_history=True)
+    z1 = O.threshold_pos(op.adjoint(V) / L, lam / L)
+    np.testing.assert_allclose(res.history[0], z1, rtol=1e-14, atol=1e-15)
+    z2 = O.threshold_pos(z1 - op.adjoint(op.forward(z1) - V) / L, lam / L)
+    x2 = z2 if O.objective(op, V, z2, lam)[0] <= O.objective(op, V, z1, lam)[0] else z1
+    np.testing.assert_allclose(res.history[1], x2, rtol=1e-13, atol=1e-14)
