@@ -486,7 +486,7 @@ Layout layout(const Analysis& a) {
   L.visrecD = take(visrecD_bytes(rb) * nv);
   L.visrecG = take(visrecG_bytes(rb) * nl * nv);
   L.rres = take(2 * rb * (1 + nl) * nv * nr);
-  L.rpol = take(a.grid ? sizeof(ResPolar) * nv * std::max<size_t>(1, a.grid_multi) : 0);
+  L.rpol = take(a.grid ? sizeof(ResPolar) * nv : 0);
   L.layerDs = take(2 * rb * nl * nv);
   L.chunks = take(sizeof(Chunk) * (nfc + npt + a.fd1.size() + a.fg1.size() + a.pd1.size() +
                                    a.pg1.size()));

@@ -719,8 +719,57 @@ __device__ __forceinline__ void grid_adj_delta_tile(
 
 // Square delta grid, pair blocks: lane-set (g4, ia) with ia >= kGridNBA g4
 // owns the cells (ia, b) and their mirrors (b, ia), b = kGridNBA g4 + bi
-// (written as GridPairBlock describes).  The block's per-|m| factors B and the partners'
-// A (both at |m|_b = |l|_b) come from LDS; A and B at index ia per lane.
+// (written as GridPairBlock describes).
+struct PairLane {
+  bool active;
+  int g4, ia, gl, qbase;
+};
+
+// Position of this thread in the pair block's row-major walk over (g4, ia).
+__device__ __forceinline__ PairLane pair_lane(const GridPairBlock& pb, int na) {
+  PairLane r;
+  r.g4 = pb.g4;
+  r.ia = pb.ia + static_cast<int>(threadIdx.x);
+  r.active = static_cast<int>(threadIdx.x) < pb.count;
+  while (r.active && r.ia >= na) {
+    ++r.g4;
+    r.ia = r.ia - na + kGridNBA * r.g4;
+  }
+  if (!r.active) {
+    r.g4 = pb.g4;
+    r.ia = 0;
+  }
+  r.gl = r.g4 - pb.g4;
+  r.qbase = ((r.g4 / 2) * na + r.ia) * kGridNB + (r.g4 % 2) * kGridNBA;
+  return r;
+}
+
+// Sign-slot values of cell (ia, b), b = kGridNBA g4 + bi, from G[0..3] and of
+// its mirror (b, ia) from G[4..7]: the cell when b <= ia, the mirror when
+// b < ia (other cells belong to the lane-set of the mirror).
+__device__ __forceinline__ void pair_write(const PairLane& pl, int na, int bi,
+                                           const float* G8, const int32_t* __restrict__ slot,
+                                           float* __restrict__ out_row) {
+  const int64_t q = pl.qbase + bi;
+  const int b = kGridNBA * pl.g4 + bi;
+  const int64_t qp = (static_cast<int64_t>(pl.ia / kGridNB) * na + b) * kGridNB + pl.ia % kGridNB;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h == 0 ? b > pl.ia : b >= pl.ia) continue;
+    const float* G = G8 + 4 * h;
+    const float gs[4] = {G[0] - G[1] - G[2] - G[3], G[0] + G[1] - G[2] + G[3],
+                         G[0] + G[1] + G[2] - G[3], G[0] - G[1] + G[2] + G[3]};
+    const int64_t qq = h ? qp : q;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int32_t j = slot[4 * qq + s2];
+      if (j >= 0) out_row[j] = gs[s2];
+    }
+  }
+}
+
+// One right-hand side: the block's per-|m| factors B and the partners' A
+// (both at |m|_b = |l|_b) come from LDS; A and B at index ia per lane.
 __device__ __forceinline__ void grid_adj_delta_pairs_tile(
     const VisRecD<float>* __restrict__ vrec, const ResPolar* __restrict__ rpol,
     const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
@@ -728,23 +777,13 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
     const int32_t* __restrict__ slot, int na, const GridPairBlock& pb, int64_t kc,
     int64_t kchunk, int64_t n_vis, float* __restrict__ out_row,
     float4 (*bsh)[kGridMaxGL][kGridNBA]) {
-  // position of this lane in the block's row-major walk over (g4, ia)
-  int g4 = pb.g4, ia = pb.ia + static_cast<int>(threadIdx.x);
-  const bool active = static_cast<int>(threadIdx.x) < pb.count;
-  while (active && ia >= na) {
-    ++g4;
-    ia = ia - na + kGridNBA * g4;
-  }
-  if (!active) {
-    g4 = pb.g4;
-    ia = 0;
-  }
-  const int gl = g4 - pb.g4;
-  const int qbase = ((g4 / 2) * na + ia) * kGridNB + (g4 % 2) * kGridNBA;
-  const double l = la[ia];
+  const PairLane pl = pair_lane(pb, na);
+  const bool active = pl.active;
+  const int gl = pl.gl;
+  const double l = la[pl.ia];
   double nuv[kGridNBA];
 #pragma unroll
-  for (int bi = 0; bi < kGridNBA; ++bi) nuv[bi] = active ? nu[qbase + bi] : 0.0;
+  for (int bi = 0; bi < kGridNBA; ++bi) nuv[bi] = active ? nu[pl.qbase + bi] : 0.0;
   const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
   const ConstPtr<ResPolar> cpol = as_const(rpol);
   const double origin = kMagic;
@@ -817,26 +856,116 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
   }
   if (!active) return;
 #pragma unroll
-  for (int bi = 0; bi < kGridNBA; ++bi) {
-    const int64_t q = qbase + bi;
-    const int b = kGridNBA * g4 + bi;
-    const int64_t qp = (static_cast<int64_t>(ia / kGridNB) * na + b) * kGridNB + ia % kGridNB;
+  for (int bi = 0; bi < kGridNBA; ++bi) pair_write(pl, na, bi, o[bi], slot, out_row);
+}
+
+// NR right-hand sides sharing every phasor: z_r = C r_r in Cartesian form
+// (the polar form above puts the residual's phase into C, which one C for
+// several sides cannot carry), then the eight products per cell pair are
+// formed once and scaled per side.  A block covers the NBI cells
+// b = kGridNBA g4 + bo + bi (0 <= bi < NBI) of each lane-set, so the
+// accumulators stay at 16 NBI NR per lane; kGridNBA / NBI blocks with
+// bo = 0, NBI, ... cover the lane-set.  `rres` holds the residual records
+// [n_vis][NR]; side r goes to out + r rstride.
+template <int NR, int NBI>
+__device__ __forceinline__ void grid_adj_delta_pairs_multi_tile(
+    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
+    const double* __restrict__ mb, const double* __restrict__ nu,
+    const int32_t* __restrict__ slot, int na, const GridPairBlock& pb, int bo, int64_t kc,
+    int64_t kchunk, int64_t n_vis, float* __restrict__ out, int64_t rstride,
+    float4 (*bsh)[kGridMaxGL][NBI]) {
+  static_assert(kGridNBA % NBI == 0, "NBI divides the cells of a lane-set");
+  const PairLane pl = pair_lane(pb, na);
+  const double l = la[pl.ia];
+  double nuv[NBI];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      // the cell when b <= ia, its mirror when b < ia (other cells belong to
-      // the lane-set of the mirror)
-      if (h == 0 ? b > ia : b >= ia) continue;
-      const float* G = &o[bi][4 * h];
-      const float gs[4] = {G[0] - G[1] - G[2] - G[3], G[0] + G[1] - G[2] + G[3],
-                           G[0] + G[1] + G[2] - G[3], G[0] - G[1] + G[2] + G[3]};
-      const int64_t qq = h ? qp : q;
+  for (int bi = 0; bi < NBI; ++bi) nuv[bi] = pl.active ? nu[pl.qbase + bo + bi] : 0.0;
+  const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
+  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
+  const double origin = kMagic;
+  const int k0 = static_cast<int>(kc * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  float o[NBI][NR][8];
 #pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        const int32_t j = slot[4 * qq + s2];
-        if (j >= 0) out_row[j] = gs[s2];
+  for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) o[bi][r][j] = 0.0f;
+  const int fill = kGridKBG * pb.n_gl * NBI;
+  for (int kb = k0; kb < k1; kb += kGridKBG) {
+    __syncthreads();  // the previous batch's reads are done
+    for (int e = threadIdx.x; e < fill; e += kBlock) {
+      const int kk = e / (pb.n_gl * NBI);
+      const int rem = e - kk * (pb.n_gl * NBI);
+      const int gg = rem / NBI, bi = rem - gg * NBI;
+      const int k = kb + kk;
+      float bc = 0.0f, bs = 0.0f, ac = 0.0f, as = 0.0f;
+      if (k < k1) {
+        const double m = mb[(pb.g4 + gg) * kGridNBA + bo + bi];
+        phasor(fma(vv[k], m, origin), bc, bs);
+        phasor(fma(vu[k], m, origin), ac, as);
+      }
+      bsh[kk][gg][bi] = make_float4(bc, bs, ac, as);
+    }
+    __syncthreads();
+    const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
+    float G[NBI][NR][8];
+#pragma unroll
+    for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) G[bi][r][j] = 0.0f;
+    for (int k = kb; k < ke; ++k) {
+      const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
+      float rr[NR], ri[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        rr[r] = cres[2 * (static_cast<int64_t>(k) * NR + r)];
+        ri[r] = cres[2 * (static_cast<int64_t>(k) * NR + r) + 1];
+      }
+      float ac, as, qc, qs;  // A and B at index ia
+      phasor(fma(u, l, origin), ac, as);
+      phasor(fma(v, l, origin), qc, qs);
+      const float4* bp = &bsh[k - kb][pl.gl][0];
+#pragma unroll
+      for (int bi = 0; bi < NBI; ++bi) {
+        const float4 bb = bp[bi];  // B at b (x, y), A at b (z, w)
+        float cc, cs;              // C
+        phasor(fma(w, nuv[bi], origin), cc, cs);
+        // cell (ia, b): A at ia, B at b; cell (b, ia): A at b, B at ia
+        const float p0 = bb.x * ac, p1 = bb.y * as, p2 = bb.y * ac, p3 = bb.x * as;
+        const float p4 = qc * bb.z, p5 = qs * bb.w, p6 = qs * bb.z, p7 = qc * bb.w;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const float z1 = fmaf(cc, rr[r], -cs * ri[r]);
+          const float z2 = fmaf(cc, ri[r], cs * rr[r]);
+          float* g = G[bi][r];
+          g[0] = fmaf(p0, z1, g[0]);
+          g[1] = fmaf(p1, z1, g[1]);
+          g[2] = fmaf(p2, z2, g[2]);
+          g[3] = fmaf(p3, z2, g[3]);
+          g[4] = fmaf(p4, z1, g[4]);
+          g[5] = fmaf(p5, z1, g[5]);
+          g[6] = fmaf(p6, z2, g[6]);
+          g[7] = fmaf(p7, z2, g[7]);
+        }
       }
     }
+#pragma unroll
+    for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[bi][r][j] += G[bi][r][j];
   }
+  if (!pl.active) return;
+#pragma unroll
+  for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) pair_write(pl, na, bo + bi, o[bi][r], slot, out + r * rstride);
 }
 
 // `vrec` and `rres` are the layer's records and residuals (D (1 - i s) conj(G) r).

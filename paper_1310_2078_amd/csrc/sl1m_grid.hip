@@ -165,6 +165,28 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_delta_square(
                             n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix, bsh);
 }
 
+// Square delta grid, NR right-hand sides sharing the phasors (residual
+// records [n_vis][NR] of the delta slot); blockIdx.z picks the NBI cells of
+// each lane-set, side r of chunk y goes to part + r rstride + y n_pix.
+template <int NR, int NBI>
+__global__ __launch_bounds__(kBlock) void k_grid_adj_delta_square_multi(
+    const VisRecD<float>* __restrict__ vrec, const float2* __restrict__ rres,
+    const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
+    const double* __restrict__ mb, const double* __restrict__ nu,
+    const int32_t* __restrict__ slot, int na, const GridPairBlock* __restrict__ blocks,
+    int64_t kchunk, int64_t n_vis, float* __restrict__ part, int64_t n_pix, int64_t rstride) {
+  __shared__ float4 bsh[kGridKBG][kGridMaxGL][NBI];
+  const ConstPtr<GridPairBlock> cb = as_const(blocks) + blockIdx.x;
+  GridPairBlock pb;
+  pb.g4 = cb->g4;
+  pb.ia = cb->ia;
+  pb.count = cb->count;
+  pb.n_gl = cb->n_gl;
+  grid_adj_delta_pairs_multi_tile<NR, NBI>(
+      vrec, rres, vu, vv, la, mb, nu, slot, na, pb, static_cast<int>(blockIdx.z) * NBI,
+      blockIdx.y, kchunk, n_vis, part + static_cast<int64_t>(blockIdx.y) * n_pix, rstride, bsh);
+}
+
 // All Gaussian grid segments in one launch: block x of the (block, chunk)
 // grid maps to (segment, block within the segment) through `gblocks`, so a
 // plan with several small layers still fills the GPU with one launch.  For a
@@ -359,28 +381,28 @@ hipError_t launch_grid_forward_multi(sl1m_plan* p, const void* xp, int nr, hipSt
   return nr == 2 ? grid_forward_multi_t<2>(p, x, st) : grid_forward_multi_t<4>(p, x, st);
 }
 
-// One pair-adjoint launch per right-hand side: the tile is at its issue
-// limit with the residual's phase in the per-cell phasor, which a shared
-// phasor for several sides would give up.
+template <int NR, int NBI>
+static hipError_t grid_adjoint_multi_t(sl1m_plan* p, hipStream_t st) {
+  const int64_t rstride = static_cast<int64_t>(p->n_achunks) * p->n_pix;
+  for (const GridSeg& g : p->grid_segs) {
+    if (g.pblocks == 0) continue;
+    const int64_t co = g.cell_off;
+    hipLaunchKernelGGL((k_grid_adj_delta_square_multi<NR, NBI>),
+                       dim3(static_cast<unsigned>(g.pblocks), static_cast<unsigned>(p->n_achunks),
+                            static_cast<unsigned>(kGridNBA / NBI)),
+                       dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD),
+                       static_cast<const float2*>(p->rres), p->vu, p->vv, p->grid_la + g.la_off,
+                       p->grid_mb + g.mb_off, p->grid_c3 + co, p->grid_slot + 4 * co, g.na,
+                       p->d_grid_pblocks + g.pb0, p->adj_kchunk, p->n_vis,
+                       static_cast<float*>(p->apart), p->n_pix, rstride);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_grid_adjoint_multi(sl1m_plan* p, int nr, hipStream_t st) {
   if (p->n_achunks == 0) return hipSuccess;
   if (!grid_multi_ok(p, nr)) return hipErrorInvalidValue;
-  for (int r = 0; r < nr; ++r) {
-    float* part = static_cast<float*>(p->apart) +
-                  static_cast<int64_t>(r) * p->n_achunks * p->n_pix;
-    for (const GridSeg& g : p->grid_segs) {
-      if (g.pblocks == 0) continue;
-      const int64_t co = g.cell_off;
-      hipLaunchKernelGGL(k_grid_adj_delta_square,
-                         dim3(static_cast<unsigned>(g.pblocks), static_cast<unsigned>(p->n_achunks)),
-                         dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD),
-                         p->rpol + static_cast<int64_t>(r) * p->n_vis, p->vu, p->vv,
-                         p->grid_la + g.la_off, p->grid_mb + g.mb_off, p->grid_c3 + co,
-                         p->grid_slot + 4 * co, g.na, p->d_grid_pblocks + g.pb0, p->adj_kchunk,
-                         p->n_vis, part, p->n_pix);
-    }
-  }
-  return hipGetLastError();
+  return nr == 2 ? grid_adjoint_multi_t<2, 2>(p, st) : grid_adjoint_multi_t<4, 2>(p, st);
 }
 
 }  // namespace sl1m

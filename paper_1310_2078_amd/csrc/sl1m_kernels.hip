@@ -732,7 +732,7 @@ static hipError_t fwd_reduce_t(sl1m_plan* p, const void* data, void* out, bool r
                      static_cast<const R*>(p->vgain), static_cast<const C2<R>*>(data),
                      static_cast<C2<R>*>(out), recs ? static_cast<C2<R>*>(p->rres) : nullptr,
                      static_cast<const R*>(p->layerDs), p->n_layers,
-                     recs && (nr == 1 || grid_multi_ok(p, nr)) ? p->rpol : nullptr);
+                     recs && nr == 1 ? p->rpol : nullptr);
   return hipGetLastError();
 }
 hipError_t launch_forward_reduce(sl1m_plan* p, const void* data, void* out, bool recs, int nr,
@@ -746,7 +746,7 @@ static hipError_t adj_prep_t(sl1m_plan* p, const void* r, int nr, hipStream_t st
   hipLaunchKernelGGL((k_adj_prep<R>), dim3(grid1(p->n_vis)), dim3(kBlock), 0, st,
                      static_cast<const C2<R>*>(r), p->n_vis, nr, static_cast<const R*>(p->vgain),
                      static_cast<C2<R>*>(p->rres), static_cast<const R*>(p->layerDs),
-                     p->n_layers, nr == 1 || grid_multi_ok(p, nr) ? p->rpol : nullptr);
+                     p->n_layers, nr == 1 ? p->rpol : nullptr);
   return hipGetLastError();
 }
 hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t st) {

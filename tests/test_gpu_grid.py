@@ -283,10 +283,13 @@ MULTI = {"config1": 4, "odd45": 4, "disk64": 4, "grid_plus_gauss": 4, "rect80x24
 def test_grid_multi_rhs(name):
     """Multi-RHS calls (2 and 4 sides, as the paper's polarisations through one
     matrix): every side against the oracle, and equal to the plan's
-    single-side call of that side -- bitwise where every pixel is on the grid
-    (the same tiles, rows and summation order), within 1e-6 where direct
-    tiles of other pixels take part (their multi-RHS instantiations may round
-    differently)."""
+    single-side call of that side.  The forward is bitwise equal where every
+    pixel is on the grid (the same tiles, rows and summation order), within
+    1e-6 where direct tiles of other pixels take part (their multi-RHS
+    instantiations may round differently).  The adjoint's shared-phasor tile
+    forms C r in Cartesian form where the single-side tile folds the
+    residual's phase into C, so the two agree to FP32 rounding of each
+    entry: within 1e-6 (norm-relative)."""
     wl = _case(name)
     say(f"[case] grid multi-RHS {name} n_pix={wl.l.size} n_vis={wl.u.size}")
     plan = sl1m.Plan.from_workload(wl, max_rhs=4)
@@ -308,7 +311,10 @@ def test_grid_multi_rhs(name):
             assert ef <= TOL and ea <= TOL
             V1 = plan.forward(X[r]).cpu().numpy()
             g1 = plan.adjoint(Rr[r]).cpu().numpy()
+            say(f"    nr={nr} side {r}: multi vs single forward {rel(Vg[r], V1):.3e} "
+                f"adjoint {rel(gg[r], g1):.3e}")
             if MULTI[name] and name != "grid_plus_gauss":
-                assert np.array_equal(V1, Vg[r]) and np.array_equal(g1, gg[r])
+                assert np.array_equal(V1, Vg[r])
             else:
-                assert rel(Vg[r], V1) <= 1e-6 and rel(gg[r], g1) <= 1e-6
+                assert rel(Vg[r], V1) <= 1e-6
+            assert rel(gg[r], g1) <= 1e-6
