@@ -263,6 +263,18 @@ def extras(plan2, wl2, dev):
            "config2_shape_multi_rhs4_direct"] = rec
         pm.close()
         del pm, Vm, G
+    # the same four sides on the matrix cores (float16 / bfloat16 operands)
+    for prec in ("mfma_f16", "mfma_bf16"):
+        pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=4, precision=prec)
+        Vm = pm.forward_multi(X)
+        tf = _time_ops(pm, lambda: pm.forward_multi(X, out=Vm), 5)
+        G = torch.empty((4, wl2.n_pix), dtype=torch.float32, device=dev)
+        ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), 5)
+        ex[f"config2_shape_multi_rhs4_{prec}"] = {
+            "evaluation": "direct, MFMA 4x4x4", "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+            "phasor_evals_per_s": 2 * ev / (tf + ta), "rhs_products_per_s": 8 * ev / (tf + ta)}
+        pm.close()
+        del pm, Vm, G
     del X
     # config 4: multiscale Gaussian pixels with direction-dependent gains
     wl4 = W.config4()

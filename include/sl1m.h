@@ -27,8 +27,8 @@
  *  - Calls that share a plan must not run concurrently (the plan's workspace
  *    holds per-call scratch such as split-K partial sums).
  *  - Real/complex element types follow the plan's precision: float32 and
- *    complex64 (interleaved re, im) for SL1M_PREC_FP32, float64 and
- *    complex128 for SL1M_PREC_FP64.
+ *    complex64 (interleaved re, im) for SL1M_PREC_FP32 and the MFMA
+ *    precisions, float64 and complex128 for SL1M_PREC_FP64.
  */
 #ifndef SL1M_H_
 #define SL1M_H_
@@ -58,10 +58,39 @@ typedef enum {
 } sl1m_pixel_kind;
 
 typedef enum {
-  SL1M_PREC_FP64 = 0, /* everything in float64                                   */
-  SL1M_PREC_FP32 = 1  /* float64 phase with exact reduction to [-1/2, 1/2] turn;
-                         sincos, gains and accumulation in float32                */
+  SL1M_PREC_FP64 = 0,      /* everything in float64                              */
+  SL1M_PREC_FP32 = 1,      /* float64 phase with exact reduction to [-1/2, 1/2]
+                              turn; sincos, gains and accumulation in float32   */
+  SL1M_PREC_MFMA_F16 = 2,  /* the FP32 plan's phase and sincos; the matrix
+                              entries and the images / residuals they multiply
+                              rounded to float16 and contracted on the matrix
+                              cores, float32 accumulation (see below)           */
+  SL1M_PREC_MFMA_BF16 = 3  /* as SL1M_PREC_MFMA_F16 with bfloat16 operands      */
 } sl1m_precision;
+
+/*
+ * Matrix-core precisions.  The paper treats the polarisations of one
+ * observation as independent problems through the same matrix (Section
+ * "Defining the direct solution"); with R right-hand sides the operators are
+ * products of the N_v x N_p matrix with an N_p x R (forward) or N_v x R
+ * (adjoint) matrix, and these plans contract them with the gfx950 MFMA
+ * v_mfma_f32_4x4x4_16b (16 blocks of 4 x 4 x 4; four right-hand sides per
+ * instruction, 4 pixels or visibilities per step, each lane forming the
+ * entries of its own visibility (forward) or pixel (adjoint) from the FP64
+ * phase).  Per call the images (times the pixel amplitude) or the residual
+ * records are scaled by a power of two that brings their largest magnitude
+ * into [2^13, 2^14) and rounded to the operand type; the result is scaled
+ * back exactly.  Error per entry of the result: at most
+ * (2u + N 2^-24 + 2^-17) sum_j |M_kj x_j| (forward; the adjoint likewise over
+ * k), u = 2^-11 (float16) or 2^-8 (bfloat16) the operands' rounding, N the
+ * length of the sum (float32 accumulation), 2^-17 the float32 entry itself;
+ * float16 operands below 2^-14 of the scale add at most 2^-38 of the largest
+ * operand per term (subnormal spacing).  Only delta pixels (every pixel
+ * SL1M_PIX_DELTA) and gains without per-pair beam widths are accepted
+ * (SL1M_EINVAL otherwise); there is no grid evaluation, tuning or serving
+ * with these precisions.  Real and complex arrays at the ABI are float32 and
+ * complex64 as for SL1M_PREC_FP32.
+ */
 
 /*
  * Evaluation order of the operators.  The element of eq. (deltam) factorises

@@ -35,6 +35,8 @@ struct Analysis {
   std::vector<Chunk> fd, fg, pd, pg;
   int64_t kchunk = 0;
   int n_achunks = 0;
+  int n_mfchunks = 0;         // matrix-core plans: forward chunks of mf_chunk pixels
+  int64_t mf_chunk = 0, mf_np4 = 0, mf_nv4 = 0;
   // grid evaluation: segments on the grid path, their concatenated tables,
   // and the direct chunks of the other segments
   bool grid = false;
@@ -157,8 +159,9 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   if (pr->n_pix < 0 || pr->n_vis < 0) return set_error(SL1M_EINVAL, "negative size");
   if (pr->n_pix > INT32_MAX || pr->n_vis > INT32_MAX)
     return set_error(SL1M_EINVAL, "n_pix and n_vis must be below 2^31");
-  if (pr->precision != SL1M_PREC_FP32 && pr->precision != SL1M_PREC_FP64)
+  if (pr->precision < SL1M_PREC_FP64 || pr->precision > SL1M_PREC_MFMA_BF16)
     return set_error(SL1M_EINVAL, "unknown precision");
+  const bool mfma = pr->precision == SL1M_PREC_MFMA_F16 || pr->precision == SL1M_PREC_MFMA_BF16;
   if (pr->n_pix > 0 && (!pr->l || !pr->m)) return set_error(SL1M_EINVAL, "l or m is NULL");
   if (pr->n_vis > 0 && (!pr->u || !pr->v || !pr->w))
     return set_error(SL1M_EINVAL, "u, v or w is NULL");
@@ -228,6 +231,8 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     for (int64_t j = 0; j < np && identity; ++j) identity = a.perm[j] == j;
     if (identity) a.perm.clear();
   }
+  if (mfma && a.segs.size() != 1)
+    return set_error(SL1M_EINVAL, "the MFMA precisions evaluate delta pixels only");
 
   // ---- gains
   a.has_gain = pr->ant_p != nullptr && pr->n_vis > 0;
@@ -260,6 +265,8 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
         a.beam_pair = true;
     }
   }
+  if (mfma && a.beam_pair)
+    return set_error(SL1M_EINVAL, "the MFMA precisions need one beam width for all antennas");
 
   // ---- tiling
   const int64_t nv = pr->n_vis;
@@ -307,7 +314,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   a.grid = false;
   if (pr->grid_mode != SL1M_GRID_OFF && nv > 0 && np > 0) {
     std::string why = "no segment has 1024 pixels";
-    if (a.precision != SL1M_PREC_FP32) why = "the plan is float64";
+    if (a.precision != SL1M_PREC_FP32) why = "the plan's precision is not SL1M_PREC_FP32";
     else if (a.beam_pair) why = "the plan has per-pair beams";
     bool any_big = false;
     for (const Segment& sg : a.segs) any_big = any_big || sg.count >= 1024;
@@ -446,6 +453,35 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     a.kchunk = 0;
     a.n_achunks = 0;
   }
+  // matrix-core plans: 32-pixel (forward) and 32-visibility (adjoint) steps
+  // of 4 x 4 x 4 blocks, fwd_vpl visibilities / adj_ppl pixels per lane;
+  // chunks that give each launch kMinLaunchBlocks blocks
+  if (mfma) {
+    // lanes per thread: two entries per scalar record load measured best at
+    // config 2's shape for 1 to 4 sides, four pixels per lane for 8 sides'
+    // adjoint (float16, 65,536 x 97,536)
+    if (!pr->fwd_vpl) a.fwd_vpl = nv >= 2LL * 64 * kBlock ? 2 : 1;
+    if (!pr->adj_ppl) a.adj_ppl = np >= 2LL * 64 * kBlock ? (a.max_rhs > 4 ? 4 : 2) : 1;
+    auto up32 = [](int64_t x) { return (x + 31) / 32 * 32; };
+    const int64_t np32 = up32(np), nv32 = up32(nv);
+    a.mf_np4 = np32 / 4;
+    a.mf_nv4 = nv32 / 4;
+    a.n_mfchunks = 0;
+    a.mf_chunk = 0;
+    a.kchunk = 0;
+    a.n_achunks = 0;
+    if (np > 0 && nv > 0) {
+      const int64_t vt = (nv + kBlock * a.fwd_vpl - 1) / (kBlock * a.fwd_vpl);
+      const int64_t nf = std::max<int64_t>(1, std::min<int64_t>(np32 / 32, (kMinLaunchBlocks + vt - 1) / vt));
+      a.mf_chunk = up32((np32 + nf - 1) / nf);
+      a.n_mfchunks = static_cast<int>((np32 + a.mf_chunk - 1) / a.mf_chunk);
+      const int64_t pt = (np + kBlock * a.adj_ppl - 1) / (kBlock * a.adj_ppl);
+      const int64_t na = std::max<int64_t>(
+          1, std::min<int64_t>({256, nv32 / 32, (kMinLaunchBlocks + pt - 1) / pt}));
+      a.kchunk = up32((nv32 + na - 1) / na);
+      a.n_achunks = static_cast<int>((nv32 + a.kchunk - 1) / a.kchunk);
+    }
+  }
   return SL1M_OK;
 }
 
@@ -454,7 +490,7 @@ struct Layout {
       rres, rpol, layerDs, chunks, fpart, apart, xperm, img, zbuf, res, red, red_out, flag, scal,
       grid_la,
       grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb,
-      grid_prec, grid_precm, total;
+      grid_prec, grid_precm, mx, mr, mred, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -471,7 +507,9 @@ Layout layout(const Analysis& a) {
   const size_t nfc = a.fd.size() + a.fg.size();
   const size_t npt = a.pd.size() + a.pg.size();
   L.perm = take(4 * np);
-  L.pixrec = take(pixrec_bytes(rb) * np);
+  // matrix-core plans read records in steps of 32: padded with zero records
+  const bool mf = a.precision >= SL1M_PREC_MFMA_F16;
+  L.pixrec = take(pixrec_bytes(rb) * (mf ? 4 * static_cast<size_t>(a.mf_np4) : np));
   L.pl = take(8 * np);
   L.pm = take(8 * np);
   L.pc3 = take(8 * np);
@@ -483,7 +521,7 @@ Layout layout(const Analysis& a) {
   L.vw = take(8 * nv);
   L.vgain = take(a.has_gain ? 2 * rb * nv : 0);
   L.vbeta = take(a.beam_pair ? rb * nv : 0);
-  L.visrecD = take(visrecD_bytes(rb) * nv);
+  L.visrecD = take(visrecD_bytes(rb) * (mf ? 4 * static_cast<size_t>(a.mf_nv4) : nv));
   L.visrecG = take(visrecG_bytes(rb) * nl * nv);
   L.rres = take(2 * rb * (1 + nl) * nv * nr);
   L.rpol = take(a.grid ? sizeof(ResPolar) * nv : 0);
@@ -491,7 +529,10 @@ Layout layout(const Analysis& a) {
   L.chunks = take(sizeof(Chunk) * (nfc + npt + a.fd1.size() + a.fg1.size() + a.pd1.size() +
                                    a.pg1.size()));
   const size_t grid_rows = a.grid ? a.grid_fc.size() + a.fd1.size() + a.fg1.size() : 0;
-  L.fpart = take(2 * rb * std::max(nfc * nr, grid_rows * std::max<size_t>(1, a.grid_multi)) * nv);
+  L.fpart = take(2 * rb *
+                 std::max({nfc * nr, grid_rows * std::max<size_t>(1, a.grid_multi),
+                           static_cast<size_t>(a.n_mfchunks) * nr}) *
+                 nv);
   L.apart = take(rb * static_cast<size_t>(a.n_achunks) * np * nr);
   L.xperm = take(rb * np * nr);
   L.img = take(rb * np);
@@ -516,6 +557,10 @@ Layout layout(const Analysis& a) {
   L.grid_precm = take(a.grid_multi ? sizeof(float) * static_cast<size_t>(2 + 8 * a.grid_multi) *
                                          static_cast<size_t>(a.grid_pairs)
                                    : 0);
+  const size_t ngm = mf ? (nr + 3) / 4 : 0;  // groups of 4 sides
+  L.mx = take(2 * 16 * ngm * static_cast<size_t>(a.mf_np4));
+  L.mr = take(2 * 32 * ngm * static_cast<size_t>(a.mf_nv4));
+  L.mred = take(ngm ? sizeof(float) * (2 * 256 + 4) : 0);
   L.total = off;
   return L;
 }
@@ -717,6 +762,11 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->ptiles_gauss = a.pg;
     p->adj_kchunk = a.kchunk;
     p->n_achunks = a.n_achunks;
+    p->mfma = a.precision >= SL1M_PREC_MFMA_F16 ? a.precision : 0;
+    p->n_mfchunks = a.n_mfchunks;
+    p->mf_chunk = a.mf_chunk;
+    p->mf_np4 = a.mf_np4;
+    p->mf_nv4 = a.mf_nv4;
     p->grid = a.grid;
     p->grid_multi = a.grid_multi;
     p->grid_segs = a.gsegs;
@@ -766,6 +816,11 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->red_out = reinterpret_cast<double*>(w + L.red_out);
     p->flag = reinterpret_cast<int*>(w + L.flag);
     p->scal = reinterpret_cast<double*>(w + L.scal);
+    if (p->mfma) {
+      p->mx = reinterpret_cast<uint16_t*>(w + L.mx);
+      p->mr = reinterpret_cast<uint16_t*>(w + L.mr);
+      p->mred = reinterpret_cast<float*>(w + L.mred);
+    }
     if (a.grid) {
       p->grid_la = reinterpret_cast<double*>(w + L.grid_la);
       p->grid_mb = reinterpret_cast<double*>(w + L.grid_mb);
@@ -835,6 +890,15 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     if (e == hipSuccess)
       e = launch_fill(p->apart, static_cast<size_t>(p->n_achunks) * p->n_pix * p->max_rhs, a.rb,
                       st);
+    if (p->mfma) {  // zero records past the last pixel / visibility (steps of 32)
+      const size_t pr_b = sizeof(PixRec<float>), vr_b = sizeof(VisRecD<float>);
+      const size_t pad_p = static_cast<size_t>(4 * a.mf_np4 - a.n_pix) * pr_b;
+      const size_t pad_v = static_cast<size_t>(4 * a.mf_nv4 - a.n_vis) * vr_b;
+      if (e == hipSuccess && pad_p)
+        e = launch_fill(static_cast<char*>(p->pixrec) + a.n_pix * pr_b, pad_p / 4, 4, st);
+      if (e == hipSuccess && pad_v)
+        e = launch_fill(static_cast<char*>(p->visrecD) + a.n_vis * vr_b, pad_v / 4, 4, st);
+    }
     int bad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&bad, p->flag, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -952,6 +1016,8 @@ extern "C" {
 sl1m_status sl1m_tune_workspace_bytes(const sl1m_problem* problem, size_t* bytes) {
   try {
     if (!problem || !bytes) return set_error(SL1M_EINVAL, "NULL argument");
+    if (problem->precision == SL1M_PREC_MFMA_F16 || problem->precision == SL1M_PREC_MFMA_BF16)
+      return set_error(SL1M_EINVAL, "the MFMA precisions have no tuned launch shapes");
     // every plan sl1m_tune may build: the default, (grid mode, split) with the
     // plan's lane counts, and direct plans with every lane count and split
     size_t mx = 0;

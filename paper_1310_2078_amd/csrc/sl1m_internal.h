@@ -192,6 +192,16 @@ struct sl1m_plan {
   std::vector<sl1m::Chunk> ptiles_delta, ptiles_gauss;
   int64_t adj_kchunk = 0;     // visibilities per chunk
   int n_achunks = 0;
+  // matrix-core plans (SL1M_PREC_MFMA_*): forward chunks of mf_chunk pixels and
+  // adjoint chunks of adj_kchunk visibilities (multiples of 32); images and
+  // residual records are packed into the operand type on every call
+  int mfma = 0;               // 0, or the plan's MFMA precision
+  int n_mfchunks = 0;
+  int64_t mf_chunk = 0;
+  int64_t mf_np4 = 0, mf_nv4 = 0;  // pixels, visibilities padded to 32, over 4
+  uint16_t* mx = nullptr;     // packed images [NG][np4][4 sides][4 pixels]
+  uint16_t* mr = nullptr;     // packed residuals [NG][nv4][4 sides][re, -im][4 visibilities]
+  float* mred = nullptr;      // block maxima [2][256], then inverse scales [2]
 
   // grid evaluation (single right-hand side, FP32): segments on the grid path
   // and the direct chunks of the other segments
@@ -333,6 +343,10 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st);
 // grid segments, adjoint partials [r][n_achunks][n_pix] from the polar
 // residual records [r][n_vis].
 bool grid_multi_ok(const sl1m_plan* p, int nr);
+// matrix-core operator launches (packing included); partial rows as the
+// direct kernels'
+hipError_t launch_mfma_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st);
+hipError_t launch_mfma_adjoint(sl1m_plan* p, int nr, hipStream_t st);
 hipError_t launch_grid_forward_multi(sl1m_plan* p, const void* xp, int nr, hipStream_t st);
 hipError_t launch_grid_adjoint_multi(sl1m_plan* p, int nr, hipStream_t st);
 hipError_t launch_domain_check(sl1m_plan* p, const double* l, const double* m,

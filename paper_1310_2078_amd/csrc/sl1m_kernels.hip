@@ -673,6 +673,7 @@ hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, int nr, hipStrea
 
 template <typename R>
 static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
+  if (p->mfma) return launch_mfma_forward(p, xp, nr, st);
   if (p->n_vis == 0 || p->n_fchunks == 0) return hipSuccess;
   const bool bm = p->beam_pair;
   if (nr == 1 && p->grid) {
@@ -718,6 +719,7 @@ hipError_t launch_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st) 
 }
 
 int forward_rows(const sl1m_plan* p, int nr) {
+  if (p->mfma) return p->n_mfchunks;
   if ((nr == 1 && p->grid) || grid_multi_ok(p, nr))
     return static_cast<int>(p->grid_frows + p->fd1.size() + p->fg1.size());
   return p->n_fchunks;
@@ -755,6 +757,7 @@ hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t 
 
 template <typename R>
 static hipError_t adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
+  if (p->mfma) return launch_mfma_adjoint(p, nr, st);
   if (p->n_pix == 0 || p->n_achunks == 0) return hipSuccess;
   const bool bm = p->beam_pair;
   if (nr == 1 && p->grid) {

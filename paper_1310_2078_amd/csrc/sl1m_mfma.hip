@@ -1,0 +1,438 @@
+// Matrix-core evaluation of the operators (SL1M_PREC_MFMA_F16 / _BF16, delta
+// pixels) for gfx950.
+//
+// With R right-hand sides (the paper's independent polarisations through one
+// matrix, Section "Defining the direct solution") the forward is the product
+// of the N_v x N_p matrix M with the N_p x R images and the adjoint
+// Re(M^H r) that of the N_p x N_v matrix with the N_v x R residuals.  Both
+// run on v_mfma_f32_4x4x4_16b: 16 blocks of D(4x4) += A(4x4) B(4x4), lane
+// L = i + 4b holding row i of A of block b (four K values) and lane
+// L = j + 4b column j of B and of D (D's four rows in its four registers).
+// Here every block shares the same four K indices (pixels in the forward,
+// visibilities in the adjoint) and the same B (the four sides of those four
+// K values), so
+//   * A row i of block b is the lane's own visibility (forward) or pixel
+//     (adjoint): each lane forms its four entries of M from the FP64 phase
+//     u l + v m + w (n - 1) exactly as the FP32 kernels do (FMAs from kMagic,
+//     low mantissa bits into 1.0f, v_sin/v_cos in turns), the K index being
+//     wavefront-uniform so that its coordinates are scalar loads;
+//   * cos and sin of the entries are two A operands against one B
+//     (forward: V_re = sum c x, V_im = -sum s x; adjoint: g = sum c r_re +
+//     s (-r_im), the two products chained into one accumulator);
+//   * D(b, i, j) of lane j + 4b is side j at visibility / pixel 4b + i.
+// B is the per-call packed image or residual (power-of-two scaled into the
+// operand range, rounded once), eight 4-value steps per lane loaded ahead of
+// the 32-index block that uses them.  Partial rows and their reduction are
+// those of the direct kernels: forward [side][chunk][n_vis] complex (pixel
+// amplitudes inside), adjoint [side][chunk][n_pix] (amplitudes applied by
+// the reduction).
+#include "sl1m_device.h"
+
+namespace sl1m {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kMfmaRedBlocks = 256;  // blocks of the max-magnitude pass
+
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// operand type: storage as 16-bit words, conversion, the MFMA
+template <int PREC>
+struct MOp;
+
+template <>
+struct MOp<SL1M_PREC_MFMA_F16> {
+  typedef h4_t vec;
+  static __device__ __forceinline__ f4_t mma(vec a, vec b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint16_t bits(float x) {
+    return __builtin_bit_cast(uint16_t, static_cast<_Float16>(x));
+  }
+};
+
+template <>
+struct MOp<SL1M_PREC_MFMA_BF16> {
+  typedef s4_t vec;
+  static __device__ __forceinline__ f4_t mma(vec a, vec b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint16_t bits(float x) {
+    return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
+  }
+};
+
+template <typename V>
+__device__ __forceinline__ V as_vec(uint2 w) {
+  return __builtin_bit_cast(V, w);
+}
+
+// Four float32 values to one operand (two v_cvt_pk per four values).
+typedef __bf16 b4_t __attribute__((ext_vector_type(4)));
+template <int PREC>
+__device__ __forceinline__ typename MOp<PREC>::vec pack4(f4_t v) {
+  if constexpr (PREC == SL1M_PREC_MFMA_F16)
+    return __builtin_convertvector(v, h4_t);
+  else
+    return __builtin_bit_cast(s4_t, __builtin_convertvector(v, b4_t));
+}
+
+// Power of two s with max * s in [2^13, 2^14) (1 for a zero or non-finite
+// maximum): operands stay inside float16's range with 2 bits of headroom for
+// the rounding of the largest one.
+__device__ __forceinline__ float op_scale(float mx) {
+  if (!(mx > 0.0f) || !isfinite(mx)) return 1.0f;
+  int ex;
+  frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+  int e = 14 - ex;
+  e = e < -120 ? -120 : (e > 120 ? 120 : e);
+  return ldexpf(1.0f, e);
+}
+
+// Wavefront maximum through cross-lane shuffles, then the block's in LDS.
+__device__ __forceinline__ float block_max(float v) {
+  __shared__ float wm[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float m = wm[0];
+#pragma unroll
+  for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, wm[w]);
+  __syncthreads();
+  return m;
+}
+
+// Block maxima of |x[r][j] scale[j]| (scale may be null: |x[i]|) over n values.
+__global__ __launch_bounds__(kBlock) void k_mfma_absmax(const float* __restrict__ x, int64_t n,
+                                                        const float* __restrict__ scale,
+                                                        int64_t n_scale, float* __restrict__ out) {
+  float m = 0.0f;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const float v = scale ? x[i] * scale[i % n_scale] : x[i];
+    // a NaN counts as infinite (fmaxf would drop it): the scale falls back to 1
+    m = fmaxf(m, v != v ? __builtin_inff() : fabsf(v));
+  }
+  m = block_max(m);
+  if (threadIdx.x == 0) out[blockIdx.x] = m;
+}
+
+// The maximum of the kMfmaRedBlocks block maxima (every block of the packing
+// kernels recomputes it; block 0 stores the inverse scale for the operator).
+__device__ __forceinline__ float max_of_blocks(const float* __restrict__ bm) {
+  static_assert(kMfmaRedBlocks == kBlock, "one block maximum per thread");
+  const float v = bm[threadIdx.x];
+  return block_max(v != v ? __builtin_inff() : v);
+}
+
+// Images: out[((g np4 + s) 4 + j) 4 + e] = x[4g + j][4s + e] scale[4s + e] c,
+// zero past n_pix or nr.  One thread per (g, s, j).
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_mfma_pack_x(const float* __restrict__ x,
+                                                        const float* __restrict__ scale,
+                                                        int64_t n_pix, int nr, int64_t np4,
+                                                        int ng, const float* __restrict__ bm,
+                                                        float* __restrict__ inv_out,
+                                                        uint16_t* __restrict__ out) {
+  const float c = op_scale(max_of_blocks(bm));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *inv_out = 1.0f / c;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= static_cast<int64_t>(ng) * np4 * 4) return;
+  const int j = static_cast<int>(t & 3);
+  const int64_t s = (t >> 2) % np4;
+  const int g = static_cast<int>((t >> 2) / np4);
+  const int r = 4 * g + j;
+  uint16_t w[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t px = 4 * s + e;
+    const float v = (r < nr && px < n_pix) ? x[r * n_pix + px] * scale[px] * c : 0.0f;
+    w[e] = MOp<PREC>::bits(v);
+  }
+  uint2 o;
+  o.x = static_cast<uint32_t>(w[0]) | (static_cast<uint32_t>(w[1]) << 16);
+  o.y = static_cast<uint32_t>(w[2]) | (static_cast<uint32_t>(w[3]) << 16);
+  reinterpret_cast<uint2*>(out)[t] = o;
+}
+
+// Residual records rres[k][nr] (complex): out[(((g nv4 + s) 4 + j) 2 + h) 4 + e]
+// = (h ? -Im : Re) rres[4s + e][4g + j] c, zero past n_vis or nr.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_mfma_pack_r(const float2* __restrict__ rres,
+                                                        int64_t n_vis, int nr, int64_t nv4,
+                                                        int ng, const float* __restrict__ bm,
+                                                        float* __restrict__ inv_out,
+                                                        uint16_t* __restrict__ out) {
+  const float c = op_scale(max_of_blocks(bm));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *inv_out = 1.0f / c;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= static_cast<int64_t>(ng) * nv4 * 4) return;
+  const int j = static_cast<int>(t & 3);
+  const int64_t s = (t >> 2) % nv4;
+  const int g = static_cast<int>((t >> 2) / nv4);
+  const int r = 4 * g + j;
+  uint16_t re[4], im[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t k = 4 * s + e;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (r < nr && k < n_vis) v = rres[k * nr + r];
+    re[e] = MOp<PREC>::bits(v.x * c);
+    im[e] = MOp<PREC>::bits(-v.y * c);
+  }
+  uint4 o;
+  o.x = static_cast<uint32_t>(re[0]) | (static_cast<uint32_t>(re[1]) << 16);
+  o.y = static_cast<uint32_t>(re[2]) | (static_cast<uint32_t>(re[3]) << 16);
+  o.z = static_cast<uint32_t>(im[0]) | (static_cast<uint32_t>(im[1]) << 16);
+  o.w = static_cast<uint32_t>(im[2]) | (static_cast<uint32_t>(im[3]) << 16);
+  reinterpret_cast<uint4*>(out)[t] = o;
+}
+
+// Forward: a wavefront owns 64 VPL visibilities (lane L: wbase + 64 v + L,
+// v < VPL, one A operand each, so every scalar pixel record feeds VPL
+// entries per lane); blockIdx.y = pixel chunk [y pchunk, min((y + 1) pchunk,
+// 4 np4)) in 32-pixel blocks (pchunk a multiple of 32).  Pixels past n_pix
+// have zero images and zero records.
+template <int PREC, int NG, int VPL>
+__global__ __launch_bounds__(kBlock) void k_fwd_mfma(
+    const PixRec<float>* __restrict__ pix, const uint16_t* __restrict__ xh, int64_t np4,
+    const double* __restrict__ vu, const double* __restrict__ vv,
+    const double* __restrict__ vw, int64_t n_vis, int64_t pchunk,
+    const float* __restrict__ inv, float2* __restrict__ part, int n_rows, int nr) {
+  typedef typename MOp<PREC>::vec V;
+  const int lane = threadIdx.x & 63;
+  const int64_t wbase =
+      (static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6)) * (64 * VPL);
+  double u[VPL], v[VPL], w[VPL];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) {
+    const int64_t k = wbase + 64 * q + lane < n_vis ? wbase + 64 * q + lane : n_vis - 1;
+    u[q] = vu[k];
+    v[q] = vv[k];
+    w[q] = vw[k];
+  }
+  const int jcol = lane & 3;
+  const ConstPtr<PixRec<float>> cpix = as_const(pix);
+  const uint2* xb = reinterpret_cast<const uint2*>(xh);
+  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * pchunk;
+  const int64_t j1 = j0 + pchunk < 4 * np4 ? j0 + pchunk : 4 * np4;
+  const double origin = kMagic;
+  f4_t are[VPL][NG], aim[VPL][NG];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) are[q][g] = aim[q][g] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t jb = j0; jb < j1; jb += 32) {
+    uint2 bw[NG][8];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) bw[g][s] = xb[(g * np4 + jb / 4 + s) * 4 + jcol];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      f4_t cv[VPL], sv[VPL];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t jp = jb + 4 * s + e;  // records padded to 4 np4 (zeros)
+        const double pl = cpix[jp].l, pm = cpix[jp].m, pn = cpix[jp].c3;
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) {
+          const double t = fma(w[q], pn, fma(v[q], pm, fma(u[q], pl, origin)));
+          float c, sn;
+          phasor(t, c, sn);
+          cv[q][e] = c;
+          sv[q][e] = -sn;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        const V ac = pack4<PREC>(cv[q]), as = pack4<PREC>(sv[q]);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          const V b = as_vec<V>(bw[g][s]);
+          are[q][g] = MOp<PREC>::mma(ac, b, are[q][g]);
+          aim[q][g] = MOp<PREC>::mma(as, b, aim[q][g]);
+        }
+      }
+    }
+  }
+  const float sc = *inv;
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) {
+    const int64_t kb = wbase + 64 * q + (lane & ~3);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int r = 4 * g + jcol;
+      if (r >= nr) continue;
+      float2* out = part + (static_cast<int64_t>(r) * n_rows + blockIdx.y) * n_vis;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (kb + i < n_vis) out[kb + i] = make_float2(are[q][g][i] * sc, aim[q][g][i] * sc);
+    }
+  }
+}
+
+// Adjoint: a wavefront owns 64 PPL pixels (lane L: wbase + 64 q + L),
+// blockIdx.y = visibility chunk [y kchunk, min((y + 1) kchunk, 4 nv4)) in
+// 32-visibility blocks.  Visibilities past n_vis have zero residuals and
+// zero records.
+template <int PREC, int NG, int PPL>
+__global__ __launch_bounds__(kBlock) void k_adj_mfma(
+    const VisRecD<float>* __restrict__ vrec, const uint16_t* __restrict__ rh, int64_t nv4,
+    const double* __restrict__ pl, const double* __restrict__ pm,
+    const double* __restrict__ pc3, int64_t n_pix, int64_t kchunk,
+    const float* __restrict__ inv, float* __restrict__ part, int n_rows, int nr) {
+  typedef typename MOp<PREC>::vec V;
+  const int lane = threadIdx.x & 63;
+  const int64_t wbase =
+      (static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6)) * (64 * PPL);
+  double l[PPL], m[PPL], nu[PPL];
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    const int64_t j = wbase + 64 * q + lane < n_pix ? wbase + 64 * q + lane : n_pix - 1;
+    l[q] = pl[j];
+    m[q] = pm[j];
+    nu[q] = pc3[j];
+  }
+  const int jcol = lane & 3;
+  const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
+  const uint4* rb = reinterpret_cast<const uint4*>(rh);
+  const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kchunk;
+  const int64_t k1 = k0 + kchunk < 4 * nv4 ? k0 + kchunk : 4 * nv4;
+  const double origin = kMagic;
+  f4_t acc[PPL][NG];
+#pragma unroll
+  for (int q = 0; q < PPL; ++q)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[q][g] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t kb = k0; kb < k1; kb += 32) {
+    uint4 bw[NG][8];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) bw[g][s] = rb[(g * nv4 + kb / 4 + s) * 4 + jcol];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      f4_t cv[PPL], sv[PPL];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t kp = kb + 4 * s + e;  // records padded to 4 nv4 (zeros)
+        const double u = cvrec[kp].u, v = cvrec[kp].v, w = cvrec[kp].w;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          const double t = fma(w, nu[q], fma(v, m[q], fma(u, l[q], origin)));
+          float c, sn;
+          phasor(t, c, sn);
+          cv[q][e] = c;
+          sv[q][e] = sn;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) {
+        const V ac = pack4<PREC>(cv[q]), as = pack4<PREC>(sv[q]);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          const uint4 b = bw[g][s];
+          acc[q][g] = MOp<PREC>::mma(ac, as_vec<V>(make_uint2(b.x, b.y)), acc[q][g]);
+          acc[q][g] = MOp<PREC>::mma(as, as_vec<V>(make_uint2(b.z, b.w)), acc[q][g]);
+        }
+      }
+    }
+  }
+  const float sc = *inv;
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    const int64_t jb = wbase + 64 * q + (lane & ~3);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int r = 4 * g + jcol;
+      if (r >= nr) continue;
+      float* out = part + (static_cast<int64_t>(r) * n_rows + blockIdx.y) * n_pix;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (jb + i < n_pix) out[jb + i] = acc[q][g][i] * sc;
+    }
+  }
+}
+
+inline unsigned nblocks(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+template <int PREC, int NG, int VPL>
+hipError_t mfma_forward_t(sl1m_plan* p, const float* xp, int nr, hipStream_t st) {
+  const int64_t np = p->n_pix, n = static_cast<int64_t>(nr) * np;
+  hipLaunchKernelGGL(k_mfma_absmax, dim3(kMfmaRedBlocks), dim3(kBlock), 0, st, xp, n,
+                     static_cast<const float*>(p->pscale), np, p->mred);
+  hipLaunchKernelGGL((k_mfma_pack_x<PREC>), dim3(nblocks(NG * p->mf_np4 * 4)), dim3(kBlock), 0,
+                     st, xp, static_cast<const float*>(p->pscale), np, nr, p->mf_np4, NG,
+                     p->mred, p->mred + 2 * kMfmaRedBlocks, p->mx);
+  const unsigned vt = static_cast<unsigned>((p->n_vis + kBlock * VPL - 1) / (kBlock * VPL));
+  hipLaunchKernelGGL((k_fwd_mfma<PREC, NG, VPL>), dim3(vt, static_cast<unsigned>(p->n_mfchunks)),
+                     dim3(kBlock), 0, st, static_cast<const PixRec<float>*>(p->pixrec), p->mx,
+                     p->mf_np4, p->vu, p->vv, p->vw, p->n_vis, p->mf_chunk,
+                     p->mred + 2 * kMfmaRedBlocks, static_cast<float2*>(p->fpart),
+                     p->n_mfchunks, nr);
+  return hipGetLastError();
+}
+
+template <int PREC, int NG, int PPL>
+hipError_t mfma_adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
+  const int64_t nv = p->n_vis;
+  const float* rres = static_cast<const float*>(p->rres);  // delta slot: [n_vis][nr] complex
+  hipLaunchKernelGGL(k_mfma_absmax, dim3(kMfmaRedBlocks), dim3(kBlock), 0, st, rres,
+                     2 * nr * nv, static_cast<const float*>(nullptr), int64_t{1},
+                     p->mred + kMfmaRedBlocks);
+  hipLaunchKernelGGL((k_mfma_pack_r<PREC>), dim3(nblocks(NG * p->mf_nv4 * 4)), dim3(kBlock), 0,
+                     st, reinterpret_cast<const float2*>(rres), nv, nr, p->mf_nv4, NG,
+                     p->mred + kMfmaRedBlocks, p->mred + 2 * kMfmaRedBlocks + 1, p->mr);
+  const unsigned pt = static_cast<unsigned>((p->n_pix + kBlock * PPL - 1) / (kBlock * PPL));
+  hipLaunchKernelGGL((k_adj_mfma<PREC, NG, PPL>), dim3(pt, static_cast<unsigned>(p->n_achunks)),
+                     dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD), p->mr,
+                     p->mf_nv4, p->pl, p->pm, p->pc3, p->n_pix, p->adj_kchunk,
+                     p->mred + 2 * kMfmaRedBlocks + 1, static_cast<float*>(p->apart),
+                     p->n_achunks, nr);
+  return hipGetLastError();
+}
+
+template <int PREC, int NG>
+hipError_t mfma_forward_v(sl1m_plan* p, const float* xp, int nr, hipStream_t st) {
+  if (p->fwd_vpl == 1) return mfma_forward_t<PREC, NG, 1>(p, xp, nr, st);
+  if (p->fwd_vpl == 2) return mfma_forward_t<PREC, NG, 2>(p, xp, nr, st);
+  return mfma_forward_t<PREC, NG, 4>(p, xp, nr, st);
+}
+
+template <int PREC, int NG>
+hipError_t mfma_adjoint_v(sl1m_plan* p, int nr, hipStream_t st) {
+  if (p->adj_ppl == 1) return mfma_adjoint_t<PREC, NG, 1>(p, nr, st);
+  if (p->adj_ppl == 2) return mfma_adjoint_t<PREC, NG, 2>(p, nr, st);
+  return mfma_adjoint_t<PREC, NG, 4>(p, nr, st);
+}
+
+}  // namespace
+
+hipError_t launch_mfma_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
+  if (p->n_vis == 0 || p->n_mfchunks == 0) return hipSuccess;
+  if (nr < 1 || nr > 8 || nr > p->max_rhs) return hipErrorInvalidValue;
+  const float* x = static_cast<const float*>(xp);
+  if (p->mfma == SL1M_PREC_MFMA_F16)
+    return nr <= 4 ? mfma_forward_v<SL1M_PREC_MFMA_F16, 1>(p, x, nr, st)
+                   : mfma_forward_v<SL1M_PREC_MFMA_F16, 2>(p, x, nr, st);
+  return nr <= 4 ? mfma_forward_v<SL1M_PREC_MFMA_BF16, 1>(p, x, nr, st)
+                 : mfma_forward_v<SL1M_PREC_MFMA_BF16, 2>(p, x, nr, st);
+}
+
+hipError_t launch_mfma_adjoint(sl1m_plan* p, int nr, hipStream_t st) {
+  if (p->n_pix == 0 || p->n_achunks == 0) return hipSuccess;
+  if (nr < 1 || nr > 8 || nr > p->max_rhs) return hipErrorInvalidValue;
+  if (p->mfma == SL1M_PREC_MFMA_F16)
+    return nr <= 4 ? mfma_adjoint_v<SL1M_PREC_MFMA_F16, 1>(p, nr, st)
+                   : mfma_adjoint_v<SL1M_PREC_MFMA_F16, 2>(p, nr, st);
+  return nr <= 4 ? mfma_adjoint_v<SL1M_PREC_MFMA_BF16, 1>(p, nr, st)
+                 : mfma_adjoint_v<SL1M_PREC_MFMA_BF16, 2>(p, nr, st);
+}
+
+}  // namespace sl1m

@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libsl1m.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, EDIVERGED, ECANCELLED = 0, -1, -2, -3, -4, -5, -6
 PIX_DELTA, PIX_GAUSS_PARAXIAL, PIX_GAUSS_WIDE = 0, 1, 2
-PREC_FP64, PREC_FP32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_MFMA_F16, PREC_MFMA_BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "mfma_f16": PREC_MFMA_F16,
+              "mfma_bf16": PREC_MFMA_BF16}
 
 _lib = None
 
@@ -221,7 +223,9 @@ class Plan:
 
     Inputs are NumPy arrays or torch tensors; they are copied to the device
     and kept alive with the plan.  ``precision`` is "fp32" (FP64 phase,
-    FP32 sincos/accumulation) or "fp64".
+    FP32 sincos/accumulation), "fp64", or "mfma_f16" / "mfma_bf16" (the FP32
+    entries and the images or residuals rounded to float16 / bfloat16 and
+    contracted on the matrix cores; delta pixels only).
     """
 
     def __init__(self, l, m, u, v, w, sigma=None, kind=None, ant_p=None, ant_q=None,
@@ -229,9 +233,9 @@ class Plan:
                  stream=None, max_rhs: int = 1, tile_blocks: int = 0, grid: str = "auto",
                  fwd_vpl: int = 0, adj_ppl: int = 0):
         self.device = torch.device(device)
-        self.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
-        self.rdtype = torch.float32 if self.precision == PREC_FP32 else torch.float64
-        self.cdtype = torch.complex64 if self.precision == PREC_FP32 else torch.complex128
+        self.precision = PRECISIONS[precision]
+        self.rdtype = torch.float64 if self.precision == PREC_FP64 else torch.float32
+        self.cdtype = torch.complex128 if self.precision == PREC_FP64 else torch.complex64
         d = self.device
         self._keep = dict(
             l=_dev(l, torch.float64, d), m=_dev(m, torch.float64, d),
@@ -275,7 +279,7 @@ class Plan:
 
     @classmethod
     def from_workload(cls, wl, precision="fp32", device="cuda", with_kinds=True, max_rhs=1,
-                      tile_blocks=0, grid="auto", tuning=None):
+                      tile_blocks=0, grid="auto", tuning=None, fwd_vpl=0, adj_ppl=0):
         """Plan of a workload; `tuning` (a dict from Plan.tune) sets the split,
         the evaluation and the lane counts."""
         if tuning is not None:
@@ -283,7 +287,7 @@ class Plan:
             grid = tuning["grid"]
             kw_lanes = dict(fwd_vpl=tuning["fwd_vpl"], adj_ppl=tuning["adj_ppl"])
         else:
-            kw_lanes = {}
+            kw_lanes = dict(fwd_vpl=fwd_vpl, adj_ppl=adj_ppl)
         kw = {}
         if with_kinds and (np.any(wl.kind != 0) or np.any(wl.sigma != 0)):
             kw = dict(sigma=wl.sigma, kind=wl.kind)
