@@ -16,6 +16,7 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -301,6 +302,25 @@ def extras(plan2, wl2, dev):
         "evals_per_s": 2 * wl4.n_pix * wl4.n_vis / (tf + ta),
         "fista_iteration_s_est": tf + ta,
         "canonical_tflops": 2 * flops / (tf + ta) / 1e12}
+    # one GPU's share of config 4 split over 8 GPUs by visibilities (every 8th
+    # record, all pixels: the grid evaluation keeps its square pixel grid)
+    ws = dataclasses.replace(wl4, u=wl4.u[::8], v=wl4.v[::8], w=wl4.w[::8],
+                             ant_p=wl4.ant_p[::8], ant_q=wl4.ant_q[::8], noise=None)
+    ps = sl1m.Plan.from_workload(ws, device=dev)
+    Vs = ps.forward(x4)
+    gsh = torch.empty(wl4.n_pix, dtype=torch.float32, device=dev)
+    ps.timing_begin(16)
+    tfs = _time_ops(ps, lambda: ps.forward(x4, out=Vs), 3)
+    tas = _time_ops(ps, lambda: ps.adjoint(Vs, out=gsh), 3)
+    tsh = ps.timing_end()
+    rate_s = 2 * ws.n_pix * ws.n_vis / (tfs + tas)
+    ex["config4_shard_1_of_8_by_visibilities"] = {
+        "n_pix": ws.n_pix, "n_vis": ws.n_vis, "forward_ms": tfs * 1e3, "adjoint_ms": tas * 1e3,
+        "forward_kernel_ms": tsh["forward"][1] / max(tsh["forward"][0], 1),
+        "adjoint_kernel_ms": tsh["adjoint"][1] / max(tsh["adjoint"][0], 1),
+        "evals_per_s": rate_s, "rate_vs_full_config4": rate_s / ex["config4"]["evals_per_s"]}
+    ps.close()
+    del ps, Vs, gsh
     # the config 4 L1 solve: data = the point sources through the operator plus
     # the 50 extended sources as a fine FP64 sum of delta points (not the
     # Gaussian-pixel model) plus noise; L from 30 power steps; 100 iterations

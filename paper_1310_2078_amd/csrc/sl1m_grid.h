@@ -39,6 +39,7 @@ namespace sl1m {
 namespace dev {
 
 constexpr int kGridVPL = 2;    // forward visibilities per lane
+constexpr int kGridKBM = 32;   // visibilities per LDS batch of the multi-RHS pair adjoint
 constexpr int kGridSegIA = 8;  // forward: |l| values per inner FP32 sum
 
 // ---------------------------------------------------------------------------
@@ -606,6 +607,25 @@ __device__ __forceinline__ void grid_fwd_gauss_tile(
 // Every thread of the block must call a tile (it synchronises the block).
 // ---------------------------------------------------------------------------
 
+// LDS fill of an adjoint block's per-|m| tables: thread t fills the batch rows
+// kk = t / G, t / G + S, ... (S = kBlock / G) of the block's slot t % G, where
+// G is the number of |m| slots (at most kGridMaxGL kGridNBA = 72, so S >= 3);
+// threads t >= S G take no part.  The slot's |m| value stays in a register
+// and no index is divided per entry.
+struct FillSlot {
+  int slot, row0, step;
+  bool on;
+};
+
+__device__ __forceinline__ FillSlot fill_slot(int G) {
+  FillSlot f;
+  f.step = kBlock / G;
+  f.slot = static_cast<int>(threadIdx.x) % G;
+  f.row0 = static_cast<int>(threadIdx.x) / G;
+  f.on = f.row0 < f.step;
+  return f;
+}
+
 struct LaneSet {
   bool active;
   int gl0, n_gl, gl, ia, qbase;
@@ -662,17 +682,18 @@ __device__ __forceinline__ void grid_adj_delta_tile(
   float o1[kGridNBA], o2[kGridNBA], o3[kGridNBA], o4[kGridNBA];
 #pragma unroll
   for (int bi = 0; bi < kGridNBA; ++bi) o1[bi] = o2[bi] = o3[bi] = o4[bi] = 0.0f;
-  const int fill = kGridKB * ls.n_gl * kGridNBA;
+  const FillSlot fs = fill_slot(ls.n_gl * kGridNBA);
+  const int fgg = fs.slot / kGridNBA, fbi = fs.slot % kGridNBA;
+  const double fm = fs.on ? mb[(ls.gl0 + fgg) * kGridNBA + fbi] : 0.0;
   for (int kb = k0; kb < k1; kb += kGridKB) {
     __syncthreads();  // the previous batch's reads are done
-    for (int e = threadIdx.x; e < fill; e += kBlock) {
-      const int kk = e / (ls.n_gl * kGridNBA);
-      const int rem = e - kk * (ls.n_gl * kGridNBA);
-      const int gg = rem / kGridNBA, bi = rem - gg * kGridNBA;
-      const int k = kb + kk;
-      float c = 0.0f, s = 0.0f;
-      if (k < k1) phasor(fma(vv[k], mb[(ls.gl0 + gg) * kGridNBA + bi], origin), c, s);
-      bsh[kk][gg][bi] = make_float2(c, s);
+    if (fs.on) {
+      for (int kk = fs.row0; kk < kGridKB; kk += fs.step) {
+        const int k = kb + kk;
+        float c = 0.0f, s = 0.0f;
+        if (k < k1) phasor(fma(vv[k], fm, origin), c, s);
+        bsh[kk][fgg][fbi] = make_float2(c, s);
+      }
     }
     __syncthreads();
     const int ke = kb + kGridKB < k1 ? kb + kGridKB : k1;
@@ -794,21 +815,21 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
   for (int bi = 0; bi < kGridNBA; ++bi)
 #pragma unroll
     for (int j = 0; j < 8; ++j) o[bi][j] = 0.0f;
-  const int fill = kGridKBG * pb.n_gl * kGridNBA;
+  const FillSlot fs = fill_slot(pb.n_gl * kGridNBA);
+  const int fgg = fs.slot / kGridNBA, fbi = fs.slot % kGridNBA;
+  const double fm = fs.on ? mb[(pb.g4 + fgg) * kGridNBA + fbi] : 0.0;
   for (int kb = k0; kb < k1; kb += kGridKBG) {
     __syncthreads();  // the previous batch's reads are done
-    for (int e = threadIdx.x; e < fill; e += kBlock) {
-      const int kk = e / (pb.n_gl * kGridNBA);
-      const int rem = e - kk * (pb.n_gl * kGridNBA);
-      const int gg = rem / kGridNBA, bi = rem - gg * kGridNBA;
-      const int k = kb + kk;
-      float bc = 0.0f, bs = 0.0f, ac = 0.0f, as = 0.0f;
-      if (k < k1) {
-        const double m = mb[(pb.g4 + gg) * kGridNBA + bi];
-        phasor(fma(vv[k], m, origin), bc, bs);
-        phasor(fma(vu[k], m, origin), ac, as);
+    if (fs.on) {
+      for (int kk = fs.row0; kk < kGridKBG; kk += fs.step) {
+        const int k = kb + kk;
+        float bc = 0.0f, bs = 0.0f, ac = 0.0f, as = 0.0f;
+        if (k < k1) {
+          phasor(fma(vv[k], fm, origin), bc, bs);
+          phasor(fma(vu[k], fm, origin), ac, as);
+        }
+        bsh[kk][fgg][fbi] = make_float4(bc, bs, ac, as);
       }
-      bsh[kk][gg][bi] = make_float4(bc, bs, ac, as);
     }
     __syncthreads();
     const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
@@ -893,24 +914,24 @@ __device__ __forceinline__ void grid_adj_delta_pairs_multi_tile(
     for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int j = 0; j < 8; ++j) o[bi][r][j] = 0.0f;
-  const int fill = kGridKBG * pb.n_gl * NBI;
-  for (int kb = k0; kb < k1; kb += kGridKBG) {
+  const FillSlot fs = fill_slot(pb.n_gl * NBI);
+  const int fgg = fs.slot / NBI, fbi = fs.slot % NBI;
+  const double fm = fs.on ? mb[(pb.g4 + fgg) * kGridNBA + bo + fbi] : 0.0;
+  for (int kb = k0; kb < k1; kb += kGridKBM) {
     __syncthreads();  // the previous batch's reads are done
-    for (int e = threadIdx.x; e < fill; e += kBlock) {
-      const int kk = e / (pb.n_gl * NBI);
-      const int rem = e - kk * (pb.n_gl * NBI);
-      const int gg = rem / NBI, bi = rem - gg * NBI;
-      const int k = kb + kk;
-      float bc = 0.0f, bs = 0.0f, ac = 0.0f, as = 0.0f;
-      if (k < k1) {
-        const double m = mb[(pb.g4 + gg) * kGridNBA + bo + bi];
-        phasor(fma(vv[k], m, origin), bc, bs);
-        phasor(fma(vu[k], m, origin), ac, as);
+    if (fs.on) {
+      for (int kk = fs.row0; kk < kGridKBM; kk += fs.step) {
+        const int k = kb + kk;
+        float bc = 0.0f, bs = 0.0f, ac = 0.0f, as = 0.0f;
+        if (k < k1) {
+          phasor(fma(vv[k], fm, origin), bc, bs);
+          phasor(fma(vu[k], fm, origin), ac, as);
+        }
+        bsh[kk][fgg][fbi] = make_float4(bc, bs, ac, as);
       }
-      bsh[kk][gg][bi] = make_float4(bc, bs, ac, as);
     }
     __syncthreads();
-    const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
+    const int ke = kb + kGridKBM < k1 ? kb + kGridKBM : k1;
     float G[NBI][NR][8];
 #pragma unroll
     for (int bi = 0; bi < NBI; ++bi)
@@ -994,25 +1015,26 @@ __device__ __forceinline__ void grid_adj_gauss_tile(
   for (int bi = 0; bi < kGridNBA; ++bi)
 #pragma unroll
     for (int s = 0; s < 4; ++s) og[bi][s] = 0.0f;
-  const int fill = kGridKBG * ls.n_gl * kGridNBA;
+  const FillSlot fs = fill_slot(ls.n_gl * kGridNBA);
+  const int fgg = fs.slot / kGridNBA, fbi = fs.slot % kGridNBA;
+  const double m = fs.on ? mb[(ls.gl0 + fgg) * kGridNBA + fbi] : 0.0;
+  const float mr = static_cast<float>(m);
   for (int kb = k0; kb < k1; kb += kGridKBG) {
     __syncthreads();
-    for (int e = threadIdx.x; e < fill; e += kBlock) {
-      const int kk = e / (ls.n_gl * kGridNBA);
-      const int rem = e - kk * (ls.n_gl * kGridNBA);
-      const int gg = rem / kGridNBA, bi = rem - gg * kGridNBA;
-      const int k = kb + kk;
-      float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (k < k1) {
-        const double m = mb[(ls.gl0 + gg) * kGridNBA + bi];
-        float cb, sb;
-        phasor(fma(vrec[k].B, m, origin), cb, sb);
-        const float mr = static_cast<float>(m), w = vrec[k].wr, v = vrec[k].vr, c = vrec[k].c1;
-        const float dp = fmaf(-w, mr, v), dm = fmaf(w, mr, v);
-        const float tp = pow2(c * (dp * dp)), tm = pow2(c * (dm * dm));
-        val = make_float4(tp * cb, tp * sb, tm * cb, -tm * sb);  // b+, b-
+    if (fs.on) {
+      for (int kk = fs.row0; kk < kGridKBG; kk += fs.step) {
+        const int k = kb + kk;
+        float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (k < k1) {
+          float cb, sb;
+          phasor(fma(vrec[k].B, m, origin), cb, sb);
+          const float w = vrec[k].wr, v = vrec[k].vr, c = vrec[k].c1;
+          const float dp = fmaf(-w, mr, v), dm = fmaf(w, mr, v);
+          const float tp = pow2(c * (dp * dp)), tm = pow2(c * (dm * dm));
+          val = make_float4(tp * cb, tp * sb, tm * cb, -tm * sb);  // b+, b-
+        }
+        bsh[kk][fgg][fbi] = val;
       }
-      bsh[kk][gg][bi] = val;
     }
     __syncthreads();
     const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
@@ -1095,30 +1117,31 @@ __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
   for (int bi = 0; bi < kGridNBA; ++bi)
 #pragma unroll
     for (int j = 0; j < 8; ++j) o[bi][j] = 0.0f;
-  const int fill = kGridKBG * pb.n_gl * kGridNBA;
+  const FillSlot fs = fill_slot(pb.n_gl * kGridNBA);
+  const int fgg = fs.slot / kGridNBA, fbi = fs.slot % kGridNBA;
+  const double m = fs.on ? mb[(pb.g4 + fgg) * kGridNBA + fbi] : 0.0;
+  const float mr = static_cast<float>(m);
   for (int kb = k0; kb < k1; kb += kGridKBG) {
     __syncthreads();
-    for (int e = threadIdx.x; e < fill; e += kBlock) {
-      const int kk = e / (pb.n_gl * kGridNBA);
-      const int rem = e - kk * (pb.n_gl * kGridNBA);
-      const int gg = rem / kGridNBA, bi = rem - gg * kGridNBA;
-      const int k = kb + kk;
-      float4 bv = make_float4(0.0f, 0.0f, 0.0f, 0.0f), av = bv;
-      if (k < k1) {
-        const double m = mb[(pb.g4 + gg) * kGridNBA + bi];
-        const float mr = static_cast<float>(m), w = vrec[k].wr, c = vrec[k].c1;
-        float cb, sb, ca, sa;
-        phasor(fma(vrec[k].B, m, origin), cb, sb);
-        phasor(fma(vrec[k].A, m, origin), ca, sa);
-        const float dvp = fmaf(-w, mr, vrec[k].vr), dvm = fmaf(w, mr, vrec[k].vr);
-        const float dup = fmaf(-w, mr, vrec[k].ur), dum = fmaf(w, mr, vrec[k].ur);
-        const float tvp = pow2(c * (dvp * dvp)), tvm = pow2(c * (dvm * dvm));
-        const float tup = pow2(c * (dup * dup)), tum = pow2(c * (dum * dum));
-        bv = make_float4(tvp * cb, tvp * sb, tvm * cb, -tvm * sb);  // cell b+, b-
-        av = make_float4(tup * ca, tup * sa, tum * ca, -tum * sa);  // mirror a+, a-
+    if (fs.on) {
+      for (int kk = fs.row0; kk < kGridKBG; kk += fs.step) {
+        const int k = kb + kk;
+        float4 bv = make_float4(0.0f, 0.0f, 0.0f, 0.0f), av = bv;
+        if (k < k1) {
+          const float w = vrec[k].wr, c = vrec[k].c1;
+          float cb, sb, ca, sa;
+          phasor(fma(vrec[k].B, m, origin), cb, sb);
+          phasor(fma(vrec[k].A, m, origin), ca, sa);
+          const float dvp = fmaf(-w, mr, vrec[k].vr), dvm = fmaf(w, mr, vrec[k].vr);
+          const float dup = fmaf(-w, mr, vrec[k].ur), dum = fmaf(w, mr, vrec[k].ur);
+          const float tvp = pow2(c * (dvp * dvp)), tvm = pow2(c * (dvm * dvm));
+          const float tup = pow2(c * (dup * dup)), tum = pow2(c * (dum * dum));
+          bv = make_float4(tvp * cb, tvp * sb, tvm * cb, -tvm * sb);  // cell b+, b-
+          av = make_float4(tup * ca, tup * sa, tum * ca, -tum * sa);  // mirror a+, a-
+        }
+        bsh[kk][fgg][fbi][0] = bv;
+        bsh[kk][fgg][fbi][1] = av;
       }
-      bsh[kk][gg][bi][0] = bv;
-      bsh[kk][gg][bi][1] = av;
     }
     __syncthreads();
     const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj_delta_square_multi(
     const double* __restrict__ mb, const double* __restrict__ nu,
     const int32_t* __restrict__ slot, int na, const GridPairBlock* __restrict__ blocks,
     int64_t kchunk, int64_t n_vis, float* __restrict__ part, int64_t n_pix, int64_t rstride) {
-  __shared__ float4 bsh[kGridKBG][kGridMaxGL][NBI];
+  __shared__ float4 bsh[kGridKBM][kGridMaxGL][NBI];
   const ConstPtr<GridPairBlock> cb = as_const(blocks) + blockIdx.x;
   GridPairBlock pb;
   pb.g4 = cb->g4;
