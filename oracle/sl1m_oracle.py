@@ -18,7 +18,7 @@ images using L1 minimisation"):
 * FISTA with the positive threshold -- Section "Implementation of SL1M",
                               the printed algorithm and eq. (threshp)
 
-Readings taken where the paper is garbled (each also listed in the design doc):
+Readings taken where the paper is garbled, silent or at odds with itself:
 
 * R1 (eq. samlm4/samlm5 prefactor): the pixel shape eq. (gaus) already has
   unit integral, so the integral over it yields 1/(1 - i w sigma^2); the extra

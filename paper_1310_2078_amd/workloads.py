@@ -22,7 +22,9 @@ Workloads (sizes as stated in the docstrings of the builders):
                256 antennas, 409,600 visibilities, direction-dependent gains.
 * ``config5``  a stream of 256 requests with log-uniform sizes.
 
-Recipe choices that the paper leaves open are listed in the design doc.
+Where the paper leaves a recipe choice open (array layout, flux law, noise
+level, the uvw transform of a textbook), the choice is the one stated at
+each generator below.
 """
 from __future__ import annotations
 
