@@ -72,6 +72,20 @@ def kernel_source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
+# Inner-loop instruction mix of the kernels that can dominate the iteration
+# (counted in their gfx950 assembly): entries per wavefront unit of work, then
+# FP32-rate (FP32 arithmetic, bit operations, integer), FP64 and sin/cos
+# wave64 instructions per unit.  The pair adjoint's unit is a wavefront and a
+# visibility (64 lanes x 32 entries), the pair forward's a wavefront and a
+# (pair record, visibility) (64 lanes x 8 entries, with the per-|l| phasors
+# spread over the 8 records), the direct kernels' a wavefront and an entry.
+SLOT_MIX = {
+    "k_grid_adj_delta_square": (2048, 76, 6, 12),
+    "k_grid_fwd_delta_pairs": (512, 21.25, 1.25, 2.5),
+    "k_adj_delta<float,4>": (64, 3, 3, 2),
+    "k_fwd_delta<float,4>": (64, 3, 3, 2),
+}
+
 PLAN_KEYS = ("n_fchunks_grid", "n_achunks", "fwd_vpl", "adj_ppl")
 
 
@@ -573,6 +587,19 @@ def main():
                           "canonical delta-eval FLOPs (14 per entry)",
         },
     }
+    # issue-slot roofline of the dominant kernel: its inner loop's instruction
+    # mix (from its gfx950 assembly) priced at the issue rates measured now
+    if dom_name in SLOT_MIX:
+        rates = sl1m.issue_rates(dev)
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        per_unit, n32, n64, ntr = SLOT_MIX[dom_name]
+        t_model = (n_pix * n_vis / per_unit) / cus * (
+            n32 / rates["fp32_fma"] + n64 / rates["fp64_fma"] + ntr / rates["sin_cos"])
+        out["roofline"]["slots"] = {
+            "unit": "wave64 instructions per s per CU", "rates": rates, "cus": cus,
+            "mix_per_unit": {"entries": per_unit, "fp32_rate": n32, "fp64": n64,
+                             "sin_cos": ntr},
+            "model_ms": t_model * 1e3, "frac": t_model * 1e3 / dom_ms}
     if not args.no_extras:
         out["extras"] = extras(plan, wl, dev)
     if not args.no_cpu_baseline:

@@ -455,6 +455,22 @@ sl1m_status sl1m_server_stats(sl1m_server* server, sl1m_server_stats_t* out);
 /* Waits for launched work, releases host resources (not the arena). */
 sl1m_status sl1m_server_destroy(sl1m_server* server);
 
+/* Issue rates of the instruction classes the operator kernels consist of.
+ * Every matrix entry is evaluated from its closed form (Section "On-the-fly
+ * computation versus in-memory computation"), so the operators are bound by
+ * instruction issue, and an issue-slot roofline needs the rates of the
+ * running GPU.  sl1m_issue_rates runs, on `stream`, one warm-up and one
+ * timed kernel per class (eight independent dependency chains per lane,
+ * 32 wavefronts per compute unit, 65,536 instructions of the class per
+ * lane), synchronises, and writes rates[0..3] = wave64 instructions per
+ * second per compute unit of v_fma_f32, v_fma_f64, v_sin_f32 (v_cos_f32
+ * issues alike) and v_exp_f32.  `scratch` is device memory of at least
+ * sl1m_issue_scratch_bytes() (one float per thread; contents overwritten);
+ * `rates` is host memory of 4 doubles.  SL1M_ENOMEM when the scratch is
+ * too small, SL1M_EHIP on a launch or event failure. */
+sl1m_status sl1m_issue_scratch_bytes(size_t* bytes);
+sl1m_status sl1m_issue_rates(void* scratch, size_t scratch_bytes, double* rates, void* stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char* sl1m_last_error(void);
 

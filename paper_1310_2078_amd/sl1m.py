@@ -142,6 +142,8 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(Tuning)]
         L.sl1m_timing_begin.argtypes = [vp, i32]
         L.sl1m_timing_end.argtypes = [vp, ctypes.POINTER(Timing)]
+        L.sl1m_issue_scratch_bytes.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+        L.sl1m_issue_rates.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(dbl), vp]
         L.sl1m_last_error.restype = ctypes.c_char_p
         L.sl1m_version.restype = ctypes.c_char_p
         for name in ("sl1m_plan_workspace_bytes", "sl1m_plan_create", "sl1m_plan_destroy",
@@ -153,7 +155,7 @@ def lib() -> ctypes.CDLL:
                      "sl1m_server_create",
                      "sl1m_server_submit", "sl1m_server_step", "sl1m_server_poll",
                      "sl1m_server_cancel", "sl1m_server_stats", "sl1m_server_destroy",
-                     "sl1m_server_set_policy"):
+                     "sl1m_server_set_policy", "sl1m_issue_scratch_bytes", "sl1m_issue_rates"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -171,6 +173,18 @@ def _ptr(t: Optional[torch.Tensor]):
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def issue_rates(device="cuda", stream=None) -> dict:
+    """Wave64 instructions per second per compute unit of the instruction
+    classes the operators are made of (sl1m_issue_rates)."""
+    L = lib()
+    nb = ctypes.c_size_t()
+    _check(L.sl1m_issue_scratch_bytes(ctypes.byref(nb)))
+    buf = torch.empty(max(1, nb.value // 4), dtype=torch.float32, device=torch.device(device))
+    r = (ctypes.c_double * 4)()
+    _check(L.sl1m_issue_rates(ctypes.c_void_p(buf.data_ptr()), nb, r, _stream(stream)))
+    return {"fp32_fma": r[0], "fp64_fma": r[1], "sin_cos": r[2], "exp": r[3]}
 
 
 def _dev(a, dtype, device):
