@@ -790,7 +790,10 @@ __device__ __forceinline__ void pair_write(const PairLane& pl, int na, int bi,
 }
 
 // One right-hand side: the block's per-|m| factors B and the partners' A
-// (both at |m|_b = |l|_b) come from LDS; A and B at index ia per lane.
+// (both at |m|_b = |l|_b) come from LDS; A and B at index ia per lane.  Each
+// of the 32 sums runs over the chunk's visibilities in one float32
+// accumulator (no per-batch partial sums: 32 fewer registers, a fifth
+// wavefront per SIMD); the chunks' sums are added by the reduction.
 __device__ __forceinline__ void grid_adj_delta_pairs_tile(
     const VisRecD<float>* __restrict__ vrec, const ResPolar* __restrict__ rpol,
     const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
@@ -833,11 +836,7 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
     }
     __syncthreads();
     const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
-    float G[kGridNBA][8];
-#pragma unroll
-    for (int bi = 0; bi < kGridNBA; ++bi)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) G[bi][j] = 0.0f;
+    float (&G)[kGridNBA][8] = o;  // one running sum per chunk (see above)
     for (int k = kb; k < ke; ++k) {
       // z = C r = |r| e^{2 pi i (w nu + arg r / 2 pi)}: the residual's phase
       // rides in the phasor's origin, its modulus on the lane's own factors
@@ -870,10 +869,6 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
         G[bi][7] = fmaf(qc, bb.w * cs, G[bi][7]);
       }
     }
-#pragma unroll
-    for (int bi = 0; bi < kGridNBA; ++bi)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) o[bi][j] += G[bi][j];
   }
   if (!active) return;
 #pragma unroll
@@ -932,13 +927,7 @@ __device__ __forceinline__ void grid_adj_delta_pairs_multi_tile(
     }
     __syncthreads();
     const int ke = kb + kGridKBM < k1 ? kb + kGridKBM : k1;
-    float G[NBI][NR][8];
-#pragma unroll
-    for (int bi = 0; bi < NBI; ++bi)
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) G[bi][r][j] = 0.0f;
+    float (&G)[NBI][NR][8] = o;  // one running sum per chunk, as the single tile
     for (int k = kb; k < ke; ++k) {
       const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
       float rr[NR], ri[NR];
@@ -975,12 +964,6 @@ __device__ __forceinline__ void grid_adj_delta_pairs_multi_tile(
         }
       }
     }
-#pragma unroll
-    for (int bi = 0; bi < NBI; ++bi)
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) o[bi][r][j] += G[bi][r][j];
   }
   if (!pl.active) return;
 #pragma unroll
@@ -1145,11 +1128,7 @@ __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
     }
     __syncthreads();
     const int ke = kb + kGridKBG < k1 ? kb + kGridKBG : k1;
-    float G[kGridNBA][8];
-#pragma unroll
-    for (int bi = 0; bi < kGridNBA; ++bi)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) G[bi][j] = 0.0f;
+    float (&G)[kGridNBA][8] = o;  // one running sum per chunk, as the delta pair tile
     for (int k = kb; k < ke; ++k) {
       const double A = crec[k].A, B = crec[k].B, C = crec[k].C, NW = crec[k].NW, E0 = crec[k].E0;
       const float ur = crec[k].ur, vr = crec[k].vr, wr = crec[k].wr, c1 = crec[k].c1;
@@ -1186,10 +1165,6 @@ __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
         G[bi][7] = fmaf(ma.z, wmr, fmaf(ma.w, wmi, G[bi][7]));
       }
     }
-#pragma unroll
-    for (int bi = 0; bi < kGridNBA; ++bi)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) o[bi][j] += G[bi][j];
   }
   if (!active) return;
 #pragma unroll
