@@ -341,7 +341,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     for (const Chunk& c : a.fg) if (!on[c.seg]) a.fg1.push_back(c);
     for (const Chunk& c : a.pd) if (!on[c.seg]) a.pd1.push_back(c);
     for (const Chunk& c : a.pg) if (!on[c.seg]) a.pg1.push_back(c);
-    a.grid_vtiles = static_cast<int>((nv + 2 * kBlock - 1) / (2 * kBlock));
+    a.grid_vtiles = static_cast<int>((nv + kGridVPL * kBlock - 1) / (kGridVPL * kBlock));
     int64_t ng_total = 0;
     for (const GridSeg& g : a.gsegs) ng_total += g.ng;
     const int64_t per_split = static_cast<int64_t>(a.grid_vtiles) * ng_total;

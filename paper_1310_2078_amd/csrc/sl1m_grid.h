@@ -38,7 +38,6 @@
 namespace sl1m {
 namespace dev {
 
-constexpr int kGridVPL = 2;    // forward visibilities per lane
 constexpr int kGridKBM = 32;   // visibilities per LDS batch of the multi-RHS pair adjoint
 constexpr int kGridSegIA = 8;  // forward: |l| values per inner FP32 sum
 

@@ -80,6 +80,7 @@ struct Chunk {           // a contiguous pixel range inside one segment
 // so the kGridNB cells of one |l| value and one group of |m| values are
 // adjacent.  Sign slots: 0 = (+l, +m), 1 = (-l, +m), 2 = (+l, -m), 3 = (-l, -m);
 // a zero coordinate takes the + slot.
+constexpr int kGridVPL = 1;      // visibilities per lane of the grid forward
 constexpr int kGridNB = 8;       // |m| values per forward group
 constexpr int kGridNBA = 4;      // |m| values per adjoint lane
 constexpr int kGridKB = 32;      // visibilities per adjoint LDS batch (delta)
@@ -209,7 +210,7 @@ struct sl1m_plan {
   int grid_multi = 0;             // 2 or 4: multi-RHS calls of up to this many sides on the grid
   std::vector<sl1m::GridSeg> grid_segs;
   int64_t grid_cells = 0;         // all grid segments
-  int grid_vtiles = 0;            // forward visibility tiles (2 per lane)
+  int grid_vtiles = 0;            // forward visibility tiles (kGridVPL per lane)
   int grid_frows = 0;             // forward partial rows of the grid segments
   std::vector<sl1m::GridChunk> grid_fchunks;
   std::vector<sl1m::Chunk> fd1, fg1, pd1, pg1;
