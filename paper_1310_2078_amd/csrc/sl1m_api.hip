@@ -421,8 +421,9 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   // The launches of one adjoint run one after another, so besides the plan's
   // block target every launch should have enough blocks of its own: the
   // smallest launch gets at least kMinLaunchBlocks (grid plans; within the
-  // chunk cap), eight times the 1024 blocks an MI355X keeps resident of these
-  // kernels, so that its last, partly filled round is a small part of it.
+  // chunk cap), six to eight times the 1024-1280 blocks an MI355X keeps
+  // resident of these kernels (4 or 5 wavefronts per SIMD), so that its last,
+  // partly filled round is a small part of it.
   constexpr int64_t kMinLaunchBlocks = 8192;
   int64_t ptiles = static_cast<int64_t>(a.pd.size() + a.pg.size());
   int64_t min_launch = 0;
