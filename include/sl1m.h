@@ -464,8 +464,9 @@ sl1m_status sl1m_server_destroy(sl1m_server* server);
  * 32 wavefronts per compute unit, 65,536 instructions of the class per
  * lane), synchronises, and writes rates[0..3] = wave64 instructions per
  * second per compute unit of v_fma_f32, v_fma_f64, v_sin_f32 (v_cos_f32
- * issues alike) and v_exp_f32.  `scratch` is device memory of at least
- * sl1m_issue_scratch_bytes() (one float per thread; contents overwritten);
+ * issues alike) and v_exp_f32 on the current device.  `scratch` is memory
+ * of that device, at least sl1m_issue_scratch_bytes() (one float per
+ * thread; contents overwritten; the caller owns it);
  * `rates` is host memory of 4 doubles.  SL1M_ENOMEM when the scratch is
  * too small, SL1M_EHIP on a launch or event failure. */
 sl1m_status sl1m_issue_scratch_bytes(size_t* bytes);
