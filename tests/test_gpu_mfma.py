@@ -234,3 +234,21 @@ def test_mfma_rejects():
     plan = sl1m.Plan.from_workload(wl, precision="mfma_f16", max_rhs=2)
     with pytest.raises(sl1m.SL1MError):
         plan.forward_multi(np.zeros((4, 300)))
+
+
+@pytest.mark.parametrize("prec", ["mfma_f16", "mfma_bf16"])
+def test_mfma_empty_inputs(prec):
+    """No pixels: the forward is all zeros; no visibilities: the adjoint is all
+    zeros and the forward empty (no packing or matrix-core launch runs)."""
+    say(f"[case] mfma empty inputs {prec}")
+    wl = W.small_random(1, 10, 20)
+    e1 = W.Workload("np0", wl.l[:0], wl.m[:0], wl.sigma[:0], wl.kind[:0], wl.u, wl.v, wl.w)
+    plan = sl1m.Plan.from_workload(e1, precision=prec, max_rhs=4)
+    V = plan.forward_multi(np.zeros((4, 0))).cpu().numpy()
+    assert V.shape == (4, 20) and np.all(V == 0)
+    e2 = W.Workload("nv0", wl.l, wl.m, wl.sigma, wl.kind, wl.u[:0], wl.v[:0], wl.w[:0])
+    plan = sl1m.Plan.from_workload(e2, precision=prec, max_rhs=4)
+    g = plan.adjoint_multi(np.zeros((4, 0), complex)).cpu().numpy()
+    assert g.shape == (4, 10) and np.all(g == 0)
+    V = plan.forward(np.ones(10)).cpu().numpy()
+    assert V.shape == (0,)
