@@ -174,8 +174,11 @@ typedef struct {
   int32_t max_rhs;      /* right-hand sides per operator call: 0 or 1, 2, 4, 8 */
   int32_t tile_blocks;  /* blocks one operator launch aims at; 0 = 4096       */
   int32_t grid_mode;    /* sl1m_grid_mode                                     */
-  int32_t fwd_vpl;      /* direct forward: visibilities per lane 1, 2, 4; 0 = plan's choice */
-  int32_t adj_ppl;      /* direct adjoint: pixels per lane 1, 2, 4; 0 = plan's choice      */
+  int32_t fwd_vpl;      /* direct forward: visibilities per lane 1, 2, 4; 0 = plan's choice
+                           (matrix-core precisions: visibilities per lane of the MFMA
+                           forward, each one A operand)                                 */
+  int32_t adj_ppl;      /* direct adjoint: pixels per lane 1, 2, 4; 0 = plan's choice
+                           (matrix-core precisions: pixels per lane of the MFMA adjoint) */
 } sl1m_problem;
 
 typedef struct sl1m_plan sl1m_plan;
