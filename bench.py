@@ -278,6 +278,22 @@ def extras(plan2, wl2, dev):
            "config2_shape_multi_rhs4_direct"] = rec
         pm.close()
         del pm, Vm, G
+    # eight sides: grid evaluation (FP32) against the matrix cores (FP16)
+    X8 = torch.as_tensor(np.random.default_rng(8).standard_normal((8, wl2.n_pix)),
+                         dtype=torch.float32, device=dev)
+    rec8 = {}
+    for label, kw in (("grid", {}), ("mfma_f16", {"precision": "mfma_f16"})):
+        pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=8, **kw)
+        Vm = pm.forward_multi(X8)
+        tf = _time_ops(pm, lambda: pm.forward_multi(X8, out=Vm), 5)
+        G = torch.empty((8, wl2.n_pix), dtype=torch.float32, device=dev)
+        ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), 5)
+        rec8[label] = {"forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+                       "rhs_products_per_s": 16 * ev / (tf + ta)}
+        pm.close()
+        del pm, Vm, G
+    ex["config2_shape_multi_rhs8"] = rec8
+    del X8
     # the same four sides on the matrix cores (float16 / bfloat16 operands)
     for prec in ("mfma_f16", "mfma_bf16"):
         pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=4, precision=prec)

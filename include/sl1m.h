@@ -108,7 +108,7 @@ typedef enum {
  * l^2 + m^2.  The "grid" evaluation uses that; the "direct" evaluation forms
  * every entry on its own.  Both compute the same operator; they differ by
  * float32 rounding only.  Applies to float32 plans without per-pair beams:
- * to single right-hand-side calls, and to multi-RHS calls of 2 or 4 sides when
+ * to single right-hand-side calls, and to multi-RHS calls of 2, 4 or 8 sides when
  * every grid segment of the plan is a square delta grid (the forward shares
  * each phasor among the sides; sl1m_plan_info.grid_multi); float64 plans,
  * other multi-RHS calls and segments that do not qualify use the direct
@@ -248,9 +248,9 @@ typedef struct {
   int32_t n_fchunks_grid;   /* ... of the forward with the grid evaluation      */
   int32_t n_achunks;        /* visibility chunks of the adjoint                 */
   int32_t grid_pairs;       /* grid segments evaluated as mirrored cell pairs   */
-  int32_t grid_multi;       /* multi-RHS calls of 2 (and 4) sides up to this
-                               count evaluate on the grid (every grid segment
-                               a square delta grid); 0: direct evaluation     */
+  int32_t grid_multi;       /* multi-RHS calls of 2, 4 (and 8) sides up to
+                               this count evaluate on the grid (every grid
+                               segment a square delta grid); 0: direct        */
   int32_t reserved[3];
 } sl1m_plan_info;
 

@@ -40,7 +40,7 @@ struct Analysis {
   // grid evaluation: segments on the grid path, their concatenated tables,
   // and the direct chunks of the other segments
   bool grid = false;
-  int grid_multi = 0;  // largest multi-RHS count (2 or 4) on the grid path; 0: none
+  int grid_multi = 0;  // largest multi-RHS count (2, 4 or 8) on the grid path; 0: none
   std::vector<GridSeg> gsegs;
   int64_t grid_cells = 0;
   std::vector<double> grid_la, grid_mb, grid_c3, grid_c4;
@@ -407,7 +407,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     bool all_square_delta = true;
     for (const GridSeg& g : a.gsegs)
       all_square_delta = all_square_delta && g.square && g.kind == SL1M_PIX_DELTA;
-    a.grid_multi = all_square_delta ? (a.max_rhs >= 4 ? 4 : a.max_rhs >= 2 ? 2 : 0) : 0;
+    a.grid_multi = all_square_delta ? (a.max_rhs >= 8 ? 8 : a.max_rhs >= 4 ? 4 : a.max_rhs >= 2 ? 2 : 0) : 0;
     a.grid_gb.clear();
     for (int si = 0; si < static_cast<int>(a.gsegs.size()); ++si) {
       const GridSeg& g = a.gsegs[si];

@@ -351,7 +351,7 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st) {
 }
 
 bool grid_multi_ok(const sl1m_plan* p, int nr) {
-  return p->grid && p->grid_multi > 0 && (nr == 2 || nr == 4) && nr <= p->grid_multi;
+  return p->grid && p->grid_multi > 0 && (nr == 2 || nr == 4 || nr == 8) && nr <= p->grid_multi;
 }
 
 template <int NR>
@@ -378,7 +378,8 @@ hipError_t launch_grid_forward_multi(sl1m_plan* p, const void* xp, int nr, hipSt
   if (p->n_vis == 0) return hipSuccess;
   if (!grid_multi_ok(p, nr)) return hipErrorInvalidValue;
   const float* x = static_cast<const float*>(xp);
-  return nr == 2 ? grid_forward_multi_t<2>(p, x, st) : grid_forward_multi_t<4>(p, x, st);
+  if (nr == 2) return grid_forward_multi_t<2>(p, x, st);
+  return nr == 4 ? grid_forward_multi_t<4>(p, x, st) : grid_forward_multi_t<8>(p, x, st);
 }
 
 template <int NR, int NBI>
@@ -402,7 +403,8 @@ static hipError_t grid_adjoint_multi_t(sl1m_plan* p, hipStream_t st) {
 hipError_t launch_grid_adjoint_multi(sl1m_plan* p, int nr, hipStream_t st) {
   if (p->n_achunks == 0) return hipSuccess;
   if (!grid_multi_ok(p, nr)) return hipErrorInvalidValue;
-  return nr == 2 ? grid_adjoint_multi_t<2, 2>(p, st) : grid_adjoint_multi_t<4, 2>(p, st);
+  if (nr == 2) return grid_adjoint_multi_t<2, 2>(p, st);
+  return nr == 4 ? grid_adjoint_multi_t<4, 2>(p, st) : grid_adjoint_multi_t<8, 1>(p, st);
 }
 
 }  // namespace sl1m

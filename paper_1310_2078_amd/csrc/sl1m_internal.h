@@ -207,7 +207,7 @@ struct sl1m_plan {
   // grid evaluation (single right-hand side, FP32): segments on the grid path
   // and the direct chunks of the other segments
   bool grid = false;
-  int grid_multi = 0;             // 2 or 4: multi-RHS calls of up to this many sides on the grid
+  int grid_multi = 0;             // 2, 4 or 8: multi-RHS calls of up to this many sides on the grid
   std::vector<sl1m::GridSeg> grid_segs;
   int64_t grid_cells = 0;         // all grid segments
   int grid_vtiles = 0;            // forward visibility tiles (kGridVPL per lane)

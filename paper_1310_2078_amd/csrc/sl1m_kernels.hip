@@ -688,7 +688,8 @@ static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st
     hipError_t e = launch_grid_forward_multi(p, xp, nr, st);
     if (e != hipSuccess || (p->fd1.empty() && p->fg1.empty())) return e;
     if (nr == 2) return fwd_launch_t<R, 2, false, 2>(p, xp, st, true);
-    return fwd_launch_t<R, 1, false, 4>(p, xp, st, true);
+    if (nr == 4) return fwd_launch_t<R, 1, false, 4>(p, xp, st, true);
+    return fwd_launch_t<R, 1, false, 8>(p, xp, st, true);
   }
   switch (nr) {
     case 1:
@@ -771,7 +772,8 @@ static hipError_t adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
     hipError_t e = launch_grid_adjoint_multi(p, nr, st);
     if (e != hipSuccess || (p->pd1.empty() && p->pg1.empty())) return e;
     if (nr == 2) return adj_launch_t<R, 1, false, 2>(p, st, true);
-    return adj_launch_t<R, 1, false, 4>(p, st, true);
+    if (nr == 4) return adj_launch_t<R, 1, false, 4>(p, st, true);
+    return adj_launch_t<R, 1, false, 8>(p, st, true);
   }
   switch (nr) {
     case 1:

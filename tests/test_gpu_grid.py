@@ -275,13 +275,13 @@ def test_grid_config4_full_size_against_direct():
 # case -> whether multi-RHS calls of 2 and 4 sides take the grid evaluation
 # (every grid segment a square delta grid; the Gaussian pixels of
 # grid_plus_gauss stay direct in the same call)
-MULTI = {"config1": 4, "odd45": 4, "disk64": 4, "grid_plus_gauss": 4, "rect80x24_gains": 0,
+MULTI = {"config1": 8, "odd45": 8, "disk64": 8, "grid_plus_gauss": 8, "rect80x24_gains": 0,
          "layers_mixed": 0}
 
 
 @pytest.mark.parametrize("name", list(MULTI))
 def test_grid_multi_rhs(name):
-    """Multi-RHS calls (2 and 4 sides, as the paper's polarisations through one
+    """Multi-RHS calls (2, 4 and 8 sides, as the paper's polarisations through one
     matrix): every side against the oracle, and equal to the plan's
     single-side call of that side.  The forward is bitwise equal where every
     pixel is on the grid (the same tiles, rows and summation order), within
@@ -292,15 +292,15 @@ def test_grid_multi_rhs(name):
     entry: within 1e-6 (norm-relative)."""
     wl = _case(name)
     say(f"[case] grid multi-RHS {name} n_pix={wl.l.size} n_vis={wl.u.size}")
-    plan = sl1m.Plan.from_workload(wl, max_rhs=4)
+    plan = sl1m.Plan.from_workload(wl, max_rhs=8)
     info = plan.info()
     say(f"    info {info}")
     assert info["grid_multi"] == MULTI[name]
     p = O.Problem.from_workload(wl)
     rng = np.random.default_rng(SEEDS[name] + 50)
-    X = rng.standard_normal((4, wl.l.size))
-    Rr = rng.standard_normal((4, wl.u.size)) + 1j * rng.standard_normal((4, wl.u.size))
-    for nr in (2, 4):
+    X = rng.standard_normal((8, wl.l.size))
+    Rr = rng.standard_normal((8, wl.u.size)) + 1j * rng.standard_normal((8, wl.u.size))
+    for nr in (2, 4, 8):
         Vg = plan.forward_multi(X[:nr]).cpu().numpy()
         gg = plan.adjoint_multi(Rr[:nr]).cpu().numpy()
         Vo = O.forward(p, X[:nr])
