@@ -88,3 +88,36 @@ def test_workspace_size_grows_with_problem(L):
     b4 = ctypes.c_size_t(0)
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr4), ctypes.byref(b4)) == 0
     assert b4.value > b
+
+
+def test_matrix_core_workspace_and_issue_rate_checks(L):
+    """Matrix-core plans size extra packed-operand buffers (host arithmetic:
+    delta pixels, no kinds or antennas); the issue-rate entry points reject
+    NULL arguments before touching the device."""
+    fake = ctypes.c_void_p(0x1000)
+
+    def size(prec, max_rhs, n_pix=65536, n_vis=97536):
+        pr = sl1m.Problem(n_pix=n_pix, l=fake, m=fake, n_vis=n_vis, u=fake, v=fake, w=fake,
+                          precision=prec, grid_mode=sl1m.GRID_OFF, max_rhs=max_rhs)
+        b = ctypes.c_size_t(0)
+        assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(b)) == 0
+        return b.value
+
+    for prec in (sl1m.PREC_MFMA_F16, sl1m.PREC_MFMA_BF16):
+        assert size(prec, 4) > 0
+        # eight sides pack two groups of four: at least 16 B more per pixel
+        # (images) and 32 B more per visibility (residual records)
+        assert size(prec, 8) - size(prec, 4) >= 16 * 65536 + 32 * 97536
+    # ragged sizes pad to multiples of 32 without failing
+    assert size(sl1m.PREC_MFMA_F16, 1, n_pix=1000, n_vis=1999) > 0
+    nbytes = ctypes.c_size_t(0)
+    assert L.sl1m_issue_scratch_bytes(None) == sl1m.EINVAL
+    assert L.sl1m_issue_rates(None, 0, None, None) == sl1m.EINVAL
+    pr = sl1m.Problem(n_pix=10, l=fake, m=fake, n_vis=10, u=fake, v=fake, w=fake,
+                      precision=4)
+    assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    assert b"precision" in L.sl1m_last_error()
+    pr = sl1m.Problem(n_pix=10, l=fake, m=fake, n_vis=10, u=fake, v=fake, w=fake,
+                      precision=sl1m.PREC_MFMA_F16)
+    assert L.sl1m_tune_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    assert b"MFMA" in L.sl1m_last_error()
