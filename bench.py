@@ -456,7 +456,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the multi-GPU pixel sharding is a design, not built)", file=sys.stderr)
+              "(sharding over several GPUs, by visibilities for grid plans and by pixels otherwise, is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
