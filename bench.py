@@ -86,6 +86,8 @@ SLOT_MIX = {
     "k_fwd_delta<float,4>": (64, 3, 3, 2),
 }
 
+HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E, published
+
 PLAN_KEYS = ("n_fchunks_grid", "n_achunks", "fwd_vpl", "adj_ppl")
 
 
@@ -578,6 +580,13 @@ def main():
             "forward_avg_ms": fwd_avg,
             "adjoint_avg_ms": adj_avg,
             "fista_update_avg_ms": fis_ms / max(fis_n, 1),
+            # the update reads the adjoint's split-K rows (n_achunks x 4 B per
+            # pixel) plus scale, y and I, and writes y and I: algorithmic HBM
+            # bytes per launch over its measured time, against 8 TB/s
+            "fista_update_hbm_gbs": n_pix * (4 * pinfo["n_achunks"] + 20)
+                                    / (fis_ms / max(fis_n, 1) * 1e-3) / 1e9,
+            "fista_update_hbm_frac": n_pix * (4 * pinfo["n_achunks"] + 20)
+                                     / (fis_ms / max(fis_n, 1) * 1e-3) / HBM_PEAK_BPS,
             "forward_evals_per_s": n_pix * n_vis / (fwd_avg * 1e-3),
             "adjoint_evals_per_s": n_pix * n_vis / (adj_avg * 1e-3),
         },
