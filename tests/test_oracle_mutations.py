@@ -114,6 +114,41 @@ def test_gain_mutation_is_caught(monkeypatch):
     assert _fails(P.test_gain_power_beam_fwhm_and_reductions)
 
 
+def test_pair_beam_width_mutation_is_caught(monkeypatch):
+    """A pair gain that takes antenna p's beam width for both voltage
+    patterns (g = c_p conj(c_q) exp(-4 ln2 r^2 / F_p^2))."""
+    def one_width(p, ks, js):
+        if p.ant_p is None:
+            return None
+        ap = np.asarray(p.ant_p)[ks]
+        aq = np.asarray(p.ant_q)[ks]
+        c = np.asarray(p.ant_gain, np.complex128)
+        F = np.asarray(p.ant_fwhm, np.float64)
+        r2 = (p.l[js] ** 2 + p.m[js] ** 2)[None, :]
+        return (c[ap] * np.conj(c[aq]))[:, None] * np.exp(-4 * math.log(2) * r2 / F[ap][:, None] ** 2)
+
+    monkeypatch.setattr(OM, "gain_block", one_width)
+    assert _fails(P.test_gain_with_distinct_beam_widths_is_a_product_of_voltage_patterns)
+
+
+def test_kkt_residual_mutations_are_caught(monkeypatch):
+    """A certificate that always reports 0, and one that forgets the
+    off-support condition."""
+    for mod in (O, OM):
+        monkeypatch.setattr(mod, "kkt_residual", lambda op, V, I, lam: 0.0)
+    assert _fails(P.test_kkt_residual_on_constructed_points)
+    monkeypatch.undo()
+
+    def on_support_only(op, V, I, lam):
+        G = op.adjoint(np.asarray(V, np.complex128) - op.forward(I))
+        on = I > 0
+        return float(np.max(np.abs(G[on] - lam))) if np.any(on) else 0.0
+
+    for mod in (O, OM):
+        monkeypatch.setattr(mod, "kkt_residual", on_support_only)
+    assert _fails(P.test_kkt_residual_on_constructed_points)
+
+
 def test_adjoint_mutation_is_caught(monkeypatch):
     def adjoint_cols_noconj(p, r, js=None):
         r = np.asarray(r, np.complex128)

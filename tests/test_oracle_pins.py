@@ -335,6 +335,41 @@ def test_gain_power_beam_fwhm_and_reductions():
     np.testing.assert_allclose(Mg, cpq * beam * Mp, rtol=1e-13, atol=1e-15)
 
 
+def test_gain_with_distinct_beam_widths_is_a_product_of_voltage_patterns():
+    """Antennas with different primary beams (eq. samdelta's per-visibility
+    gain, reading R5): the pair gain is the product of the two antennas'
+    voltage patterns, so (a) its power is the geometric mean of the two
+    antennas' own power beams, |g_pq|^2 = |g_pp| |g_qq|, each of which is
+    pinned by its half-power width above; (b) swapping the antennas
+    conjugates it, g_qp = conj(g_pq); (c) its phase is that of c_p conj(c_q)
+    (voltage patterns are real).  A pair gain that used one antenna's width
+    for both factors breaks (a) and (b)."""
+    F = np.array([0.3, 0.55, 0.42])
+    c = np.array([1.1 * np.exp(0.3j), 0.9 * np.exp(-0.2j), 1.0 + 0j])
+    rng = np.random.default_rng(41)
+    l = rng.uniform(-0.3, 0.3, 40)
+    m = rng.uniform(-0.3, 0.3, 40)
+    # visibilities: every ordered pair (p, q) including p == q; w = 0 and
+    # u = v = 0 so the matrix entry is the gain times 1/n
+    pairs = [(a, b) for a in range(3) for b in range(3)]
+    ap = np.array([a for a, _ in pairs])
+    aq = np.array([b for _, b in pairs])
+    z = np.zeros(len(pairs))
+    p = _prob(l, m, z, z, z, ant_p=ap, ant_q=aq, ant_gain=c, ant_fwhm=F)
+    n = np.sqrt(1.0 - l * l - m * m)
+    G = O.matrix_block(p, np.arange(len(pairs)), np.arange(40)) * n[None, :]
+    row = {pq: G[i] for i, pq in enumerate(pairs)}
+    for a in range(3):
+        for b in range(3):
+            if a == b:
+                continue
+            np.testing.assert_allclose(np.abs(row[(a, b)]) ** 2,
+                                       np.abs(row[(a, a)]) * np.abs(row[(b, b)]), rtol=1e-13)
+            np.testing.assert_allclose(row[(b, a)], np.conj(row[(a, b)]), rtol=1e-13)
+            np.testing.assert_allclose(np.angle(row[(a, b)]),
+                                       np.full(40, np.angle(c[a] * np.conj(c[b]))), atol=1e-13)
+
+
 # --------------------------------------------------------------------------
 # step size: largest eigenvalue
 # --------------------------------------------------------------------------
@@ -427,6 +462,28 @@ def test_fista_converges_to_library_minimiser_and_satisfies_kkt():
     assert abs(res.F - ref.fun) <= 1e-7 * abs(ref.fun)
     assert O.kkt_residual(op, V, res.image, lam) < 1e-6
     assert res.F == pytest.approx(res.l2_term + lam * res.l1_term)
+
+
+def test_kkt_residual_on_constructed_points():
+    """The optimality certificate on points whose violation is known by hand.
+    With M the 2 x 2 identity (entries set directly), V = (3, 0.2) and
+    lambda = 0.5, G = Re M^H (V - M I) = V - I: at I = (2.5, 0) G = (0.5, 0.2),
+    optimal (residual 0); at I = (2, 0) G = (1, 0.2), the support's
+    condition G = lambda is off by 0.5; at I = (2.5, 0) with V_2 = 1.3 the
+    off-support condition G <= lambda is off by 0.8; at I = (3.5, 0.1) both
+    pixels are on the support and G = (-0.5, 0.1) misses lambda by 1.0 and
+    0.4, so the residual is 1.0."""
+    p = _prob([0.0, 0.1], [0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [0.0, 0.0])
+    op = O.Operator(p, dense=True)
+    op.M = np.eye(2, dtype=np.complex128)
+    lam = 0.5
+    cases = [((3.0, 0.2), (2.5, 0.0), 0.0),
+             ((3.0, 0.2), (2.0, 0.0), 0.5),
+             ((3.0, 1.3), (2.5, 0.0), 0.8),
+             ((3.0, 0.2), (3.5, 0.1), 1.0)]
+    for V, I, want in cases:
+        got = O.kkt_residual(op, np.array(V, complex), np.array(I), lam)
+        assert abs(got - want) < 1e-14, (V, I, got, want)
 
 
 def test_fista_rate_bound():
