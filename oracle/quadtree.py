@@ -67,10 +67,13 @@ def refine(l, m, h, image, frac: float, h_min: float):
 
 
 def quadtree_solve(problem_of, V, lam: float, n0: int, half: float, levels: int, iters: int,
-                   h_min: float, frac: float = 0.01, power_iters: int = 30):
+                   h_min: float, frac: float = 0.01, power_iters: int = 30, eps: float = 0.0,
+                   check_every: int = 5):
     """Runs `levels` levels; problem_of(l, m, sigma, kind) gives the oracle
-    Problem of a pixel set against the observation's visibilities.  Returns a
-    list with, per level, the cells, the start image, L and the image."""
+    Problem of a pixel set against the observation's visibilities.  Each level
+    runs at most `iters` iterations, fewer with eps > 0 (the relative-change
+    rule, reading R6).  Returns a list with, per level, the cells, the start
+    image, L and the image."""
     l, m, h = level0_cells(n0, half, h_min / 2.0)
     out = []
     x0 = None
@@ -79,7 +82,7 @@ def quadtree_solve(problem_of, V, lam: float, n0: int, half: float, levels: int,
         op = O.Operator(problem_of(l, m, sigma, kind))
         L, _ = O.power_iteration(op, power_iters)
         start = O.dirty_image(op, V) if x0 is None else x0
-        res = O.fista_from(op, V, L, lam, iters, start)
+        res = O.fista_from(op, V, L, lam, iters, start, eps=eps, check_every=check_every)
         out.append({"l": l, "m": m, "h": h, "start": start, "L": L, "image": res.image,
                     "F": res.F})
         if lev + 1 < levels:

@@ -404,13 +404,14 @@ class FistaResult:
     l2_term: float
     l1_term: float
     nnz: int
-    converged: bool
+    converged: int         # 0, 1 (objective rule) or 2 (non-zero-count rule)
     history: list
     state: tuple
 
 
 def fista(op, V, L: float, lam: float, n_iter: int, eps: float = 0.0,
-          check_every: int = 1, keep_history: bool = False, state=None):
+          check_every: int = 1, keep_history: bool = False, state=None,
+          nnz_eps: float = 0.0):
     """The printed FISTA iteration (Section "Implementation of SL1M").
 
     Step 0: y_1 = I_0 = 0, t_1 = 1.  Step k:
@@ -419,7 +420,10 @@ def fista(op, V, L: float, lam: float, n_iter: int, eps: float = 0.0,
       y_{k+1} = I_k + ((t_k - 1)/t_{k+1}) (I_k - I_{k-1})
     `state` = (k, t_k, I_{k-1}, y_k) resumes a previous run exactly.
     Stops early when eps > 0 and the relative change of F between two checks
-    is at most eps (R6).
+    is at most eps (R6), or when nnz_eps > 0 and the number of non-zero
+    pixels changed by less than nnz_eps * max(previous count, 1) between two
+    checks (the paper's second stopping rule, same section); `converged` is
+    then 1 or 2.
     """
     op = _as_op(op)
     V = np.asarray(V, np.complex128)
@@ -430,6 +434,7 @@ def fista(op, V, L: float, lam: float, n_iter: int, eps: float = 0.0,
         I_prev, y = I_prev.copy(), y.copy()
     hist = []
     F_prev = None
+    nnz_prev = None
     converged = False
     I = I_prev
     k = k0
@@ -441,12 +446,17 @@ def fista(op, V, L: float, lam: float, n_iter: int, eps: float = 0.0,
         I_prev, t = I, t_next
         if keep_history:
             hist.append(I.copy())
-        if eps > 0.0 and (k - k0) % check_every == 0:
+        if (eps > 0.0 or nnz_eps > 0.0) and (k - k0) % check_every == 0:
             F_k = objective(op, V, I, lam)[0]
-            if F_prev is not None and abs(F_k - F_prev) <= eps * F_prev:
-                converged = True
+            nnz_k = int(np.count_nonzero(I))
+            if eps > 0.0 and F_prev is not None and abs(F_k - F_prev) <= eps * F_prev:
+                converged = 1
                 break
-            F_prev = F_k
+            if nnz_eps > 0.0 and nnz_prev is not None and \
+                    abs(nnz_k - nnz_prev) < nnz_eps * max(nnz_prev, 1):
+                converged = 2
+                break
+            F_prev, nnz_prev = F_k, nnz_k
     F, l2, l1 = objective(op, V, I, lam)
     return FistaResult(image=I, iters=k - k0, L=L, F=F, l2_term=l2, l1_term=l1,
                        nnz=int(np.count_nonzero(I)), converged=converged, history=hist,

@@ -548,6 +548,30 @@ def test_termination_by_relative_change():
     assert off.iters == 300 and not off.converged
 
 
+def test_termination_by_nonzero_count():
+    """The second stopping rule of Section "Implementation of SL1M" (a small
+    change in the number of non-zero pixels), brute-forced from the iterate
+    history: the run stops at the first check k (every 5 iterations) whose
+    count differs from the previous check's by less than nnz_eps times it,
+    and returns that iterate."""
+    p, x = _small_solve_problem(seed=45)
+    op = O.Operator(p, dense=True)
+    V = op.forward(x) + 0.01 * np.random.default_rng(46).standard_normal(p.n_vis)
+    L, _ = O.power_iteration(op, 30)
+    full = O.fista(op, V, L, 0.05, 400, keep_history=True)
+    counts = [int(np.count_nonzero(I)) for I in full.history]
+    for nnz_eps in (1e-9, 0.05):
+        res = O.fista(op, V, L, 0.05, 400, check_every=5, nnz_eps=nnz_eps)
+        checks = list(range(5, 401, 5))
+        stop = next((k for a, k in zip(checks, checks[1:])
+                     if abs(counts[k - 1] - counts[a - 1]) < nnz_eps * max(counts[a - 1], 1)),
+                    None)
+        assert stop is not None and res.converged == 2 and res.iters == stop
+        np.testing.assert_array_equal(res.image, full.history[stop - 1])
+    off = O.fista(op, V, L, 0.05, 60, check_every=5)
+    assert off.iters == 60 and not off.converged
+
+
 def test_fista_second_iterate_is_plain_step():
     """t_1 = 1 makes the first extrapolation vanish: y_2 = I_1, so
     I_2 = T^{lam/L}(I_1 - Re M^H (M I_1 - V) / L)."""
