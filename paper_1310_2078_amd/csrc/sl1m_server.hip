@@ -1128,8 +1128,13 @@ sl1m_status sl1m_server_poll(sl1m_server* s, uint64_t ticket, sl1m_solve_info* i
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->tickets.find(ticket);
   if (it == s->tickets.end()) return set_error(SL1M_EINVAL, "unknown ticket");
+  // rounds already launched may still read a cancelled request's data and
+  // write its image: it is done only once they have all completed and its
+  // memory has been released (harvest), so the caller may then free vis and
+  // img_out
+  harvest(s);
   Ticket& t = *it->second;
-  *done = t.state == Ticket::DONE || t.state == Ticket::CANCELLED;
+  *done = t.state == Ticket::DONE || (t.state == Ticket::CANCELLED && t.freed);
   if (info) *info = t.info;
   if (t.state == Ticket::CANCELLED && info) info->status = SL1M_ECANCELLED;
   if (times) {

@@ -90,7 +90,18 @@ def test_alone_equals_in_mix_with_arrivals_and_cancel():
     tx = srv.submit(X[0], X[2], 0.05, 30)
     for _ in range(5):
         srv.step()
+    # every active request takes part in every round, so Z's last round is the
+    # last one launched before the cancel; Z may be reported done (its vis and
+    # img_out free to reuse) only once that round has completed
+    r_cancel = srv.stats()["rounds"]
     srv.cancel(tz)
+    for _ in range(1_000_000):
+        if srv.poll(tz)[0]:
+            assert srv.stats()["completed_rounds"] >= r_cancel
+            break
+        srv.step()
+    else:
+        raise AssertionError("cancelled request never reported done")
     srv.drain([tx, ty, tz])
     assert np.array_equal(srv.result(tx).cpu().numpy(), ax)
     assert np.array_equal(srv.result(ty).cpu().numpy(), ay)
@@ -217,3 +228,53 @@ def test_server_grid_alone_equals_in_mix(policy):
         err = np.max(np.abs(img - ref)) / np.max(ref)
         say(f"    n_pix={wl.n_pix} server vs standalone grid solve err/peak {err:.2e}")
         assert err <= 1e-5
+
+
+def test_served_request_at_config5_largest_size():
+    """A request at the top of the serving stream's ranges: 262,144
+    wide-field Gaussian pixels (sigma = 2 spacings) on the stream's truncated
+    row-major grid over +-0.05 and 200,000 visibilities, 200 iterations.  The
+    served image against the same solve through sl1m_solve on a plan in
+    caller memory (same L), within 1e-5 of the peak; that plan's operators
+    against the oracle on sampled outputs (norm-relative 1e-5 and the
+    element-wise bound)."""
+    import elementwise as E
+    wl = W.config5_request(0, np_range=(262144, 262144), nv_range=(200_000, 200_000))
+    wl.kind = np.full(wl.n_pix, W.PIX_GAUSS_WIDE, np.uint8)
+    wl.sigma = np.full(wl.n_pix, 2.0 * wl.meta["delta"])
+    say(f"[case] served request n_pix={wl.n_pix} n_vis={wl.n_vis} Gaussian, 200 iterations")
+    plan = sl1m.Plan.from_workload(wl)
+    say(f"    plan info {plan.info()}")
+    p = O.Problem.from_workload(wl)
+    rng = np.random.default_rng(77)
+    x = rng.standard_normal(wl.n_pix)
+    r = rng.standard_normal(wl.n_vis) + 1j * rng.standard_normal(wl.n_vis)
+    ks = np.arange(0, wl.n_vis, 2003)
+    js = np.arange(0, wl.n_pix, 2621)
+    Vg = plan.forward(x).cpu().numpy()[ks]
+    gg = plan.adjoint(r).cpu().numpy()[js]
+    Vo, go = O.forward_rows(p, x, ks), O.adjoint_cols(p, r, js)
+    ef = np.linalg.norm(Vg - Vo) / np.linalg.norm(Vo)
+    ea = np.linalg.norm(gg - go) / np.linalg.norm(go)
+    wf = E.worst_ratio(Vg, Vo, E.abs_forward_rows(p, x, ks), wl.n_pix)
+    wa = E.worst_ratio(gg, go, E.abs_adjoint_cols(p, r, js), wl.n_vis)
+    say(f"    plan vs oracle sampled forward {ef:.3e} adjoint {ea:.3e} "
+        f"element-wise {wf:.3e} {wa:.3e}")
+    assert ef <= 1e-5 and ea <= 1e-5 and wf <= 1.0 and wa <= 1.0
+    V = plan.forward(wl.x_true) + torch.as_tensor(wl.noise, dtype=torch.complex64,
+                                                  device=plan.device)
+    L = 1.01 * plan.estimate_L(30, seed=0)
+    img_s, info_s = plan.solve(V, wl.lam, wl.n_iter, L=L)
+    img_s = img_s.cpu().numpy()
+    plan.close()
+    srv = sl1m.Server(8 * GIB, max_slots=4)
+    t = srv.submit(wl, V, wl.lam, wl.n_iter, L=L)
+    srv.drain([t])
+    ok, info, _ = srv.poll(t)
+    img = srv.result(t).cpu().numpy()
+    err = float(np.max(np.abs(img - img_s))) / float(np.max(img_s))
+    say(f"    served vs sl1m_solve err/peak {err:.2e}  F {info['F']:.9g} vs {info_s['F']:.9g}")
+    assert ok and info["status"] == 0
+    assert err <= 1e-5
+    assert abs(info["F"] - info_s["F"]) <= 1e-5 * info_s["F"]
+    srv.close()
