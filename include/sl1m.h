@@ -301,6 +301,11 @@ typedef struct {
   int32_t power_iters;  /* power-iteration steps when L <= 0 (e.g. 30)               */
   int32_t method;       /* sl1m_method (0: the printed FISTA)                        */
   uint64_t seed;        /* SplitMix64 state for the power-iteration start            */
+  double nnz_eps;       /* stop when |nnz_k - nnz_prev| < nnz_eps max(nnz_prev, 1)
+                           between two checks (the paper's other stopping rule: a
+                           small change in the number of non-zero pixels); 0
+                           disables.  Checks run every check_every iterations when
+                           eps > 0 or nnz_eps > 0.                                   */
 } sl1m_solve_params;
 
 /* The iteration sl1m_solve runs.  SL1M_MFISTA is the monotone variant the
@@ -316,7 +321,7 @@ typedef enum { SL1M_FISTA = 0, SL1M_MFISTA = 1 } sl1m_method;
 
 typedef struct {
   int32_t iters;        /* iterations run                                            */
-  int32_t converged;    /* 1 if stopped by eps                                       */
+  int32_t converged;    /* 1 if stopped by eps, 2 if stopped by nnz_eps              */
   double L;             /* step constant used                                        */
   double F;             /* objective at the returned image                           */
   double l2_term;       /* 1/2 |V - M I|^2                                           */
@@ -326,11 +331,14 @@ typedef struct {
   int32_t reserved;
 } sl1m_solve_info;
 
-/* FISTA with the positive threshold of eq. (threshp):
- *   y_1 = I_0 = 0, t_1 = 1;
- *   I_k = T^{lambda/L}(y_k - Re M^H (M y_k - V) / L);
- *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2;
- *   y_{k+1} = I_k + ((t_k - 1)/t_{k+1}) (I_k - I_{k-1}).
+/* The L1 solve of Section "Implementation of SL1M" (FISTA, Beck & Teboulle
+ * 2009, with the positive threshold of eq. (threshp)), started from a zero
+ * image.  One iteration is one captured graph: the forward operator at the
+ * extrapolated point y, the residual against V, the adjoint, then one fused
+ * update kernel that takes the gradient step of size 1/L, applies the
+ * positive threshold lambda/L, forms the next extrapolated point with the
+ * momentum weight of the step sequence t_k, and advances t_k; t_k, 1/L and
+ * lambda/L live on the device, so every replay is the same graph.
  * vis: complex [n_vis] data V; img_out: real [n_pix] final I; info: host.
  * Synchronises at the end (and at each objective check when eps > 0).
  * Returns SL1M_EDIVERGED if the final objective is not finite. */
@@ -347,6 +355,28 @@ sl1m_status sl1m_solve_from(sl1m_plan* plan, const void* vis, const void* x0,
                             const sl1m_solve_params* params, void* img_out,
                             sl1m_solve_info* info, void* stream);
 
+/* Iteration state of the FISTA solve after iteration k (the paper's
+ * iteration is fully determined by it, with L and lambda): the image I_k and
+ * the extrapolated point y_{k+1} (device, real [n_pix], caller order, owned
+ * by the caller) and the step-sequence value t_{k+1}; k counts the
+ * iterations run so far.  t = 0 marks a fresh start from I_0 = img. */
+typedef struct {
+  void* img;
+  void* y;
+  double t;
+  int64_t k;
+} sl1m_fista_state;
+
+/* Checkpoint and exact resume: runs params->max_iter iterations starting
+ * from *state (a fresh start from state->img when state->t == 0) and leaves
+ * in *state the state after the last one (img, y, t updated, k advanced by
+ * info->iters).  A solve of K1 + K2 iterations equals a resume of K1
+ * followed by a resume of K2, bit for bit.  FISTA only (SL1M_EINVAL for
+ * MFISTA); state arrays may not alias img_out.  Otherwise as sl1m_solve. */
+sl1m_status sl1m_solve_resume(sl1m_plan* plan, const void* vis, sl1m_fista_state* state,
+                              const sl1m_solve_params* params, void* img_out,
+                              sl1m_solve_info* info, void* stream);
+
 /* Dirty image, the warm start the paper names: img_out[j] =
  * max(0, Re(M^H V)_j / n_vis) (device, real [n_pix], caller order); for unit
  * gains a point source of flux S at pixel j gives S / n_j^2 there.  The
@@ -361,10 +391,15 @@ sl1m_status sl1m_dirty_image(sl1m_plan* plan, const void* vis, void* img_out, vo
  * launches are not timed).  sl1m_timing_end() synchronises on the recorded
  * events and reports, per kind, the number of timed launches and the sum of
  * their durations in milliseconds.  Kinds: 0 = forward operator kernels,
- * 1 = adjoint operator kernels, 2 = FISTA vector update. */
+ * 1 = adjoint operator kernels, 2 = FISTA vector update; and single launches
+ * of the grid evaluation inside kinds 0 and 1: 3 = delta forward
+ * (k_grid_fwd_delta_pairs or k_grid_fwd_delta), 4 = delta adjoint
+ * (k_grid_adj_delta_square or k_grid_adj_delta), 5 = Gaussian forward (one
+ * launch per layer), 6 = Gaussian adjoint (every layer in one launch);
+ * 7 is unused. */
 typedef struct {
-  int64_t launches[4];
-  double total_ms[4];
+  int64_t launches[8];
+  double total_ms[8];
 } sl1m_timing;
 
 sl1m_status sl1m_timing_begin(sl1m_plan* plan, int32_t max_launches);
@@ -444,6 +479,9 @@ sl1m_status sl1m_server_submit(sl1m_server* server, const sl1m_problem* problem,
 sl1m_status sl1m_server_step(sl1m_server* server, int32_t* n_active, int32_t* n_pending);
 
 /* *done = 1 once the request's image is in img_out and info (host) is final;
+ * for a cancelled request, once no launched round can still read its vis or
+ * write its img_out (its memory has been released), so both may then be
+ * freed; poll itself releases requests whose rounds have completed;
  * times (host, may be NULL): [submit, admit, finish] in seconds since the
  * server was created (finish = when a step observed the completion). */
 sl1m_status sl1m_server_poll(sl1m_server* server, uint64_t ticket, sl1m_solve_info* info,

@@ -590,7 +590,7 @@ sl1m_status read_red(sl1m_plan* p, double* host, int n, hipStream_t st) {
 // combined into `out` (caller order) minus `data` if given.
 sl1m_status apply_forward(sl1m_plan* p, const void* xp, const void* data, void* out, bool recs,
                           hipStream_t st, int nr = 1) {
-  SL1M_HIP(timed(p, 0, st, [&] { return launch_forward(p, xp, nr, st); }), "forward kernel");
+  SL1M_HIP(timed(p, T_FWD, st, [&] { return launch_forward(p, xp, nr, st); }), "forward kernel");
   SL1M_HIP(launch_forward_reduce(p, data, out, recs, nr, st), "forward reduce");
   return SL1M_OK;
 }
@@ -601,16 +601,16 @@ sl1m_status apply_forward(sl1m_plan* p, const void* xp, const void* data, void* 
 sl1m_status enqueue_iteration(sl1m_plan* p, const void* vis, hipStream_t st, int method) {
   sl1m_status s = apply_forward(p, p->xperm, vis, p->res, true, st);
   if (s) return s;
-  SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
+  SL1M_HIP(timed(p, T_ADJ, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
   if (method == SL1M_MFISTA) {
-    SL1M_HIP(timed(p, 2, st, [&] { return launch_prox(p, st); }), "proximal step");
+    SL1M_HIP(timed(p, T_UPDATE, st, [&] { return launch_prox(p, st); }), "proximal step");
     s = apply_forward(p, p->zbuf, vis, p->res, false, st);
     if (s) return s;
     SL1M_HIP(launch_objective_terms(p, p->res, p->zbuf, st), "objective of z");
     SL1M_HIP(launch_mfista_select(p, st), "mfista selection");
     return SL1M_OK;
   }
-  SL1M_HIP(timed(p, 2, st, [&] { return launch_fista_update(p, st); }), "fista update");
+  SL1M_HIP(timed(p, T_UPDATE, st, [&] { return launch_fista_update(p, st); }), "fista update");
   return SL1M_OK;
 }
 
@@ -674,7 +674,7 @@ sl1m_status power_iteration(sl1m_plan* p, int32_t iters, uint64_t seed, const vo
   for (int32_t it = 0; it < iters; ++it) {
     s = apply_forward(p, p->xperm, nullptr, p->res, true, st);
     if (s) return s;
-    SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
+    SL1M_HIP(timed(p, T_ADJ, st, [&] { return launch_adjoint(p, 1, st); }), "adjoint kernel");
     SL1M_HIP(launch_adjoint_reduce(p, p->img, false, 1, st), "adjoint reduce");
     SL1M_HIP(launch_dot_norm(p, p->xperm, p->img, st), "rayleigh");
     s = read_red(p, h, 2, st);
@@ -1183,7 +1183,7 @@ sl1m_status sl1m_timing_end(sl1m_plan* p, sl1m_timing* out) {
   if (!out) return set_error(SL1M_EINVAL, "out is NULL");
   std::memset(out, 0, sizeof(*out));
   if (!p->timing) return set_error(SL1M_EINVAL, "timing was not started");
-  for (int kind = 0; kind < 3; ++kind) {
+  for (int kind = 0; kind < kTimingKinds; ++kind) {
     double total = 0.0;
     for (int i = 0; i < p->tcount[kind]; ++i) {
       hipEvent_t a = p->tev[kind][2 * i], b = p->tev[kind][2 * i + 1];
@@ -1226,7 +1226,7 @@ static sl1m_status adjoint_impl(sl1m_plan* p, int32_t nr, const void* r, void* g
       return set_error(SL1M_EINVAL, "r or g is NULL");
     hipStream_t st = S(stream);
     SL1M_HIP(launch_adjoint_prep(p, r, nr, st), "adjoint prep");
-    SL1M_HIP(timed(p, 1, st, [&] { return launch_adjoint(p, nr, st); }), "adjoint kernel");
+    SL1M_HIP(timed(p, T_ADJ, st, [&] { return launch_adjoint(p, nr, st); }), "adjoint kernel");
     SL1M_HIP(launch_adjoint_reduce(p, g, true, nr, st), "adjoint reduce");
     return SL1M_OK;
   } catch (...) {
@@ -1265,10 +1265,12 @@ sl1m_status sl1m_estimate_L(sl1m_plan* p, int32_t iters, uint64_t seed, const vo
   }
 }
 
-// The FISTA solve from I_0 = x0 (caller order; NULL: I_0 = 0).
+// The FISTA solve from I_0 = x0 (caller order; NULL: I_0 = 0), or, with
+// `state`, from an exported iteration state (its image, extrapolated point
+// and t), which on return holds the state after the last iteration.
 static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
                               const sl1m_solve_params* prm, void* img_out, sl1m_solve_info* info,
-                              void* stream) {
+                              void* stream, sl1m_fista_state* state = nullptr) {
   try {
     if (sl1m_status s = check_plan(p)) return s;
     if (!prm || !info) return set_error(SL1M_EINVAL, "params or info is NULL");
@@ -1278,11 +1280,21 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
       return set_error(SL1M_EINVAL, "lambda must be finite and >= 0");
     if (prm->max_iter < 0) return set_error(SL1M_EINVAL, "max_iter must be >= 0");
     if (!(prm->eps >= 0.0)) return set_error(SL1M_EINVAL, "eps must be >= 0");
-    if (prm->eps > 0.0 && prm->check_every < 1)
-      return set_error(SL1M_EINVAL, "check_every must be >= 1 when eps > 0");
+    if (!(prm->nnz_eps >= 0.0)) return set_error(SL1M_EINVAL, "nnz_eps must be >= 0");
+    const bool checks = prm->eps > 0.0 || prm->nnz_eps > 0.0;
+    if (checks && prm->check_every < 1)
+      return set_error(SL1M_EINVAL, "check_every must be >= 1 when eps or nnz_eps > 0");
     if (prm->method != SL1M_FISTA && prm->method != SL1M_MFISTA)
       return set_error(SL1M_EINVAL, "unknown method");
     const int method = prm->method;
+    if (state) {
+      if (method != SL1M_FISTA) return set_error(SL1M_EINVAL, "resume supports SL1M_FISTA only");
+      if (p->n_pix > 0 && (!state->img || !state->y))
+        return set_error(SL1M_EINVAL, "state img or y is NULL");
+      if (state->t != 0.0 && !(state->t >= 1.0 && std::isfinite(state->t)))
+        return set_error(SL1M_EINVAL, "state t must be 0 (fresh start) or >= 1");
+      if (state->k < 0) return set_error(SL1M_EINVAL, "state k must be >= 0");
+    }
     std::memset(info, 0, sizeof(*info));
     hipStream_t st = S(stream);
     double L = prm->L;
@@ -1296,10 +1308,20 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
       if (!(L > 0.0)) return set_error(SL1M_EINVAL, "estimated L is not positive (M = 0?)");
     }
     info->L = L;
-    const double scal_h[5] = {1.0, 1.0 / L, prm->lambda / L, prm->lambda, 0.0};
+    const bool resume = state && state->t >= 1.0;
+    const double scal_h[5] = {resume ? state->t : 1.0, 1.0 / L, prm->lambda / L, prm->lambda,
+                              0.0};
     SL1M_HIP(hipMemcpyAsync(p->scal, scal_h, sizeof(scal_h), hipMemcpyHostToDevice, st),
              "solver scalars");
-    if (x0) {
+    if (resume) {
+      // the state after iteration k: I_k, y_{k+1} and t_{k+1}
+      SL1M_HIP(launch_gather(p, state->img, p->img, 1, st), "resume image");
+      SL1M_HIP(launch_gather(p, state->y, p->xperm, 1, st), "resume extrapolated point");
+    } else if (state) {
+      // a fresh start from the state's image (y_1 = I_0)
+      SL1M_HIP(launch_gather(p, state->img, p->xperm, 1, st), "start image");
+      SL1M_HIP(launch_copy_real(p, p->xperm, p->img, p->n_pix, st), "start image");
+    } else if (x0) {
       // warm start: y_1 = I_0 = x0 (the first momentum coefficient is 0)
       SL1M_HIP(launch_gather(p, x0, p->xperm, 1, st), "start image");
       SL1M_HIP(launch_copy_real(p, p->xperm, p->img, p->n_pix, st), "start image");
@@ -1322,7 +1344,7 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
       set_error(SL1M_OK, "");
       (void)hipGetLastError();
     }
-    double F_prev = -1.0;
+    double F_prev = -1.0, nnz_prev = -1.0;
     double h[3];
     int32_t k = 0;
     for (k = 1; k <= prm->max_iter; ++k) {
@@ -1332,19 +1354,28 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
         sl1m_status s = enqueue_iteration(p, vis, st, method);
         if (s) return s;
       }
-      if (prm->eps > 0.0 && k % prm->check_every == 0) {
+      if (checks && k % prm->check_every == 0) {
         sl1m_status s = apply_forward(p, p->img, vis, p->res, false, st);
         if (s) return s;
         SL1M_HIP(launch_objective_terms(p, p->res, p->img, st), "objective");
         s = read_red(p, h, 3, st);
         if (s) return s;
         const double F = h[0] + prm->lambda * h[1];
+        const double nnz = h[2];
         if (!std::isfinite(F)) break;
-        if (F_prev >= 0.0 && std::fabs(F - F_prev) <= prm->eps * F_prev) {
+        // the two stopping rules of Section "Implementation of SL1M": a small
+        // change of the objective, or of the number of non-zero pixels
+        if (prm->eps > 0.0 && F_prev >= 0.0 && std::fabs(F - F_prev) <= prm->eps * F_prev) {
           info->converged = 1;
           break;
         }
+        if (prm->nnz_eps > 0.0 && nnz_prev >= 0.0 &&
+            std::fabs(nnz - nnz_prev) < prm->nnz_eps * std::max(nnz_prev, 1.0)) {
+          info->converged = 2;
+          break;
+        }
         F_prev = F;
+        nnz_prev = nnz;
       }
     }
     info->iters = std::min(k, prm->max_iter);
@@ -1352,6 +1383,13 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
     if (s) return s;
     SL1M_HIP(launch_objective_terms(p, p->res, p->img, st), "objective");
     SL1M_HIP(launch_unpermute(p, p->img, img_out, st), "unpermute image");
+    double t_next = 0.0;
+    if (state) {
+      SL1M_HIP(launch_unpermute(p, p->img, state->img, st), "export image");
+      SL1M_HIP(launch_unpermute(p, p->xperm, state->y, st), "export extrapolated point");
+      SL1M_HIP(hipMemcpyAsync(&t_next, p->scal, sizeof(double), hipMemcpyDeviceToHost, st),
+               "read t");
+    }
     int nonfinite = 0;
     SL1M_HIP(hipMemcpyAsync(&nonfinite, p->flag, sizeof(int), hipMemcpyDeviceToHost, st),
              "read divergence flag");
@@ -1361,6 +1399,10 @@ static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
     info->l1_term = h[1];
     info->nnz = static_cast<int64_t>(h[2]);
     info->F = h[0] + prm->lambda * h[1];
+    if (state) {
+      state->t = t_next;
+      state->k += info->iters;
+    }
     if (!std::isfinite(info->F) || nonfinite) {
       info->status = SL1M_EDIVERGED;
       return set_error(SL1M_EDIVERGED,
@@ -1383,6 +1425,13 @@ sl1m_status sl1m_solve_from(sl1m_plan* p, const void* vis, const void* x0,
                             void* stream) {
   if (p && p->n_pix > 0 && !x0) return set_error(SL1M_EINVAL, "x0 is NULL");
   return solve_impl(p, vis, p && p->n_pix > 0 ? x0 : nullptr, prm, img_out, info, stream);
+}
+
+sl1m_status sl1m_solve_resume(sl1m_plan* p, const void* vis, sl1m_fista_state* state,
+                              const sl1m_solve_params* prm, void* img_out, sl1m_solve_info* info,
+                              void* stream) {
+  if (!state) return set_error(SL1M_EINVAL, "state is NULL");
+  return solve_impl(p, vis, nullptr, prm, img_out, info, stream, state);
 }
 
 sl1m_status sl1m_dirty_image(sl1m_plan* p, const void* vis, void* img_out, void* stream) {

@@ -277,17 +277,27 @@ hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
                            scale, slot, p->grid_c3 + co, g.cells, rec);
       // single-cell chunks, then (square grids) pair chunks
       const unsigned vt = static_cast<unsigned>(p->grid_vtiles);
-      if (g.nfs > 0)
-        hipLaunchKernelGGL(k_grid_fwd_delta, dim3(vt, static_cast<unsigned>(g.nfs)), dim3(kBlock),
-                           0, st, rec, la, mb, ch, g.na, p->vu, p->vv, p->vw, p->n_vis, rows);
+      if (g.nfs > 0) {
+        hipError_t e = timed(p, T_GRID_FWD_DELTA, st, [&] {
+          hipLaunchKernelGGL(k_grid_fwd_delta, dim3(vt, static_cast<unsigned>(g.nfs)),
+                             dim3(kBlock), 0, st, rec, la, mb, ch, g.na, p->vu, p->vv, p->vw,
+                             p->n_vis, rows);
+          return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+      }
       if (g.nfc > g.nfs) {
         GridPairRec* prec = p->grid_prec + g.pr_off;
         hipLaunchKernelGGL(k_grid_prep_pairs, dim3(blocks_for(g.n_pairs)), dim3(kBlock), 0, st, x,
                            scale, slot, p->grid_c3 + co, g.na, g.n_pairs, prec);
-        hipLaunchKernelGGL(k_grid_fwd_delta_pairs,
-                           dim3(vt, static_cast<unsigned>(g.nfc - g.nfs)), dim3(kBlock), 0, st,
-                           prec, la, mb, ch + g.nfs, g.na, p->vu, p->vv, p->vw, p->n_vis,
-                           rows + static_cast<int64_t>(g.nfs) * p->n_vis);
+        hipError_t e = timed(p, T_GRID_FWD_DELTA, st, [&] {
+          hipLaunchKernelGGL(k_grid_fwd_delta_pairs,
+                             dim3(vt, static_cast<unsigned>(g.nfc - g.nfs)), dim3(kBlock), 0, st,
+                             prec, la, mb, ch + g.nfs, g.na, p->vu, p->vv, p->vw, p->n_vis,
+                             rows + static_cast<int64_t>(g.nfs) * p->n_vis);
+          return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
       }
     } else {
       const VisRecG<float>* vrec =
@@ -299,15 +309,24 @@ hipError_t launch_grid_forward(sl1m_plan* p, const void* xp, hipStream_t st) {
         hipLaunchKernelGGL(k_grid_prep_pairs_gauss, dim3(blocks_for(g.n_pairs)), dim3(kBlock), 0,
                            st, x, scale, slot, p->grid_c3 + co, p->grid_c4 + co, g.na, g.n_pairs,
                            prec);
-        hipLaunchKernelGGL(k_grid_fwd_gauss_pairs,
-                           dim3(static_cast<unsigned>(blocks_for(p->n_vis)), static_cast<unsigned>(g.nfc)),
-                           dim3(kBlock), 0, st, prec, la, mb, ch, g.na, vrec, Ds, p->n_vis, rows);
+        hipError_t e = timed(p, T_GRID_FWD_GAUSS, st, [&] {
+          hipLaunchKernelGGL(k_grid_fwd_gauss_pairs,
+                             dim3(static_cast<unsigned>(blocks_for(p->n_vis)),
+                                  static_cast<unsigned>(g.nfc)),
+                             dim3(kBlock), 0, st, prec, la, mb, ch, g.na, vrec, Ds, p->n_vis, rows);
+          return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
       } else {
         GridRecG* rec = static_cast<GridRecG*>(p->grid_rec) + co;
         hipLaunchKernelGGL(k_grid_prep_gauss, dim3(blocks_for(g.cells)), dim3(kBlock), 0, st, x,
                            scale, slot, p->grid_c3 + co, p->grid_c4 + co, g.cells, rec);
-        hipLaunchKernelGGL(k_grid_fwd_gauss, grid, dim3(kBlock), 0, st, rec, la, mb, ch, g.na,
-                           vrec, Ds, p->n_vis, rows);
+        hipError_t e = timed(p, T_GRID_FWD_GAUSS, st, [&] {
+          hipLaunchKernelGGL(k_grid_fwd_gauss, grid, dim3(kBlock), 0, st, rec, la, mb, ch, g.na,
+                             vrec, Ds, p->n_vis, rows);
+          return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
       }
     }
   }
@@ -325,28 +344,44 @@ hipError_t launch_grid_adjoint(sl1m_plan* p, hipStream_t st) {
     const int32_t* slot = p->grid_slot + 4 * co;
     const dim3 grid(static_cast<unsigned>(g.ablocks), static_cast<unsigned>(p->n_achunks));
     if (g.kind == SL1M_PIX_DELTA && g.square) {
-      if (g.pblocks > 0)
-        hipLaunchKernelGGL(k_grid_adj_delta_square,
-                           dim3(static_cast<unsigned>(g.pblocks), static_cast<unsigned>(p->n_achunks)),
-                           dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD),
-                           p->rpol, p->vu, p->vv, la, mb, p->grid_c3 + co, slot, g.na,
-                           p->d_grid_pblocks + g.pb0, p->adj_kchunk, p->n_vis, part, p->n_pix);
+      if (g.pblocks > 0) {
+        hipError_t e = timed(p, T_GRID_ADJ_DELTA, st, [&] {
+          hipLaunchKernelGGL(k_grid_adj_delta_square,
+                             dim3(static_cast<unsigned>(g.pblocks),
+                                  static_cast<unsigned>(p->n_achunks)),
+                             dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD),
+                             p->rpol, p->vu, p->vv, la, mb, p->grid_c3 + co, slot, g.na,
+                             p->d_grid_pblocks + g.pb0, p->adj_kchunk, p->n_vis, part, p->n_pix);
+          return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+      }
     } else if (g.kind == SL1M_PIX_DELTA) {
-      hipLaunchKernelGGL(k_grid_adj_delta, grid, dim3(kBlock), 0, st,
-                         static_cast<const VisRecD<float>*>(p->visrecD), rres, p->vv, la, mb,
-                         p->grid_c3 + co, slot, g.na, 2 * g.ng, p->adj_kchunk, p->n_vis, part,
-                         p->n_pix);
+      hipError_t e = timed(p, T_GRID_ADJ_DELTA, st, [&] {
+        hipLaunchKernelGGL(k_grid_adj_delta, grid, dim3(kBlock), 0, st,
+                           static_cast<const VisRecD<float>*>(p->visrecD), rres, p->vv, la, mb,
+                           p->grid_c3 + co, slot, g.na, 2 * g.ng, p->adj_kchunk, p->n_vis, part,
+                           p->n_pix);
+        return hipGetLastError();
+      });
+      if (e != hipSuccess) return e;
     }
   }
   // every Gaussian grid segment in one launch (residual records of layer L,
   // single right-hand side: slot 1 + L)
-  if (p->grid_gblocks > 0)
-    hipLaunchKernelGGL(k_grid_adj_gauss_multi,
-                       dim3(static_cast<unsigned>(p->grid_gblocks), static_cast<unsigned>(p->n_achunks)),
-                       dim3(kBlock), 0, st, p->d_grid_gblocks, p->d_grid_segs, p->d_grid_pblocks,
-                       static_cast<const VisRecG<float>*>(p->visrecG), rres, p->grid_la,
-                       p->grid_mb, p->grid_c3, p->grid_c4, p->grid_slot, p->adj_kchunk, p->n_vis,
-                       part, p->n_pix);
+  if (p->grid_gblocks > 0) {
+    hipError_t e = timed(p, T_GRID_ADJ_GAUSS, st, [&] {
+      hipLaunchKernelGGL(k_grid_adj_gauss_multi,
+                         dim3(static_cast<unsigned>(p->grid_gblocks),
+                              static_cast<unsigned>(p->n_achunks)),
+                         dim3(kBlock), 0, st, p->d_grid_gblocks, p->d_grid_segs,
+                         p->d_grid_pblocks, static_cast<const VisRecG<float>*>(p->visrecG), rres,
+                         p->grid_la, p->grid_mb, p->grid_c3, p->grid_c4, p->grid_slot,
+                         p->adj_kchunk, p->n_vis, part, p->n_pix);
+      return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

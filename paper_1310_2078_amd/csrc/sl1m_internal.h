@@ -170,6 +170,15 @@ struct GridSeg {
 
 }  // namespace sl1m
 
+namespace sl1m {
+// timing kinds (sl1m_timing): 0 forward, 1 adjoint, 2 FISTA update, then the
+// grid kernels by launch: 3 delta forward, 4 delta adjoint, 5 Gaussian
+// forward (one launch per layer), 6 Gaussian adjoint (all layers)
+constexpr int kTimingKinds = 8;
+enum TimingKind { T_FWD = 0, T_ADJ = 1, T_UPDATE = 2, T_GRID_FWD_DELTA = 3,
+                  T_GRID_ADJ_DELTA = 4, T_GRID_FWD_GAUSS = 5, T_GRID_ADJ_GAUSS = 6 };
+}  // namespace sl1m
+
 struct sl1m_plan {
   int device = 0;
   int64_t n_pix = 0, n_vis = 0;
@@ -268,8 +277,8 @@ struct sl1m_plan {
   // kernel timing (sl1m_timing_begin/end)
   bool timing = false;
   int timing_cap = 0;
-  std::vector<hipEvent_t> tev[4];   // pairs (start, stop) per kind
-  int tcount[4] = {0, 0, 0, 0};
+  std::vector<hipEvent_t> tev[sl1m::kTimingKinds];   // pairs (start, stop) per kind
+  int tcount[sl1m::kTimingKinds] = {};
 };
 
 namespace sl1m {

@@ -79,8 +79,12 @@ def quadtree_solve(u, v, w, vis, lam: float, n0: int, half: float, levels: int, 
                    h_min: float, frac: float = 0.01, power_iters: int = 30, ant_p=None,
                    ant_q=None, ant_gain=None, ant_fwhm=None, precision: str = "fp32",
                    device="cuda", max_cells: Optional[int] = None,
-                   on_level: Optional[Callable[[Level], None]] = None) -> List[Level]:
-    """Runs up to `levels` levels (fewer when a level would exceed max_cells)."""
+                   on_level: Optional[Callable[[Level], None]] = None, eps: float = 0.0,
+                   check_every: int = 5) -> List[Level]:
+    """Runs up to `levels` levels (fewer when a level would exceed max_cells).
+    Each level runs at most `iters` iterations; with eps > 0 it stops earlier
+    on a relative change of the objective of at most eps between checks every
+    `check_every` iterations (the rule of Section "Implementation of SL1M")."""
     dev = torch.device(device)
     V = sl1m._dev(vis, torch.complex64 if precision == "fp32" else torch.complex128, dev)
     l, m, h = first_cells(n0, half, 0.5 * h_min)
@@ -93,7 +97,8 @@ def quadtree_solve(u, v, w, vis, lam: float, n0: int, half: float, levels: int, 
                          ant_gain=ant_gain, ant_fwhm=ant_fwhm, precision=precision, device=dev)
         start = plan.dirty_image(V) if x0 is None else \
             torch.as_tensor(x0, dtype=plan.rdtype, device=dev)
-        img, info = plan.solve(V, lam, iters, L=0.0, power_iters=power_iters, x0=start)
+        img, info = plan.solve(V, lam, iters, L=0.0, power_iters=power_iters, x0=start,
+                               eps=eps, check_every=check_every)
         image = img.double().cpu().numpy()
         start_np = start.double().cpu().numpy()
         plan.close()

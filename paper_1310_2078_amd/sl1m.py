@@ -57,7 +57,7 @@ class Problem(ctypes.Structure):
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
+    _fields_ = [("launches", ctypes.c_int64 * 8), ("total_ms", ctypes.c_double * 8)]
 
 
 class ServerStats(ctypes.Structure):
@@ -83,6 +83,16 @@ class SolveParams(ctypes.Structure):
         ("power_iters", ctypes.c_int32),
         ("method", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("nnz_eps", ctypes.c_double),
+    ]
+
+
+class FistaState(ctypes.Structure):
+    _fields_ = [
+        ("img", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("t", ctypes.c_double),
+        ("k", ctypes.c_int64),
     ]
 
 
@@ -125,6 +135,9 @@ def lib() -> ctypes.CDLL:
         L.sl1m_solve_from.argtypes = [vp, vp, vp, ctypes.POINTER(SolveParams), vp,
                                       ctypes.POINTER(SolveInfo), vp]
         L.sl1m_dirty_image.argtypes = [vp, vp, vp, vp]
+        L.sl1m_solve_resume.argtypes = [vp, vp, ctypes.POINTER(FistaState),
+                                        ctypes.POINTER(SolveParams), vp,
+                                        ctypes.POINTER(SolveInfo), vp]
         L.sl1m_server_create.argtypes = [vp, ctypes.c_size_t, i32, dbl, ctypes.POINTER(vp)]
         L.sl1m_server_submit.argtypes = [vp, ctypes.POINTER(Problem), vp,
                                          ctypes.POINTER(SolveParams), vp,
@@ -149,7 +162,7 @@ def lib() -> ctypes.CDLL:
         for name in ("sl1m_plan_workspace_bytes", "sl1m_plan_create", "sl1m_plan_destroy",
                      "sl1m_forward", "sl1m_adjoint", "sl1m_forward_multi",
                      "sl1m_adjoint_multi", "sl1m_estimate_L", "sl1m_solve",
-                     "sl1m_solve_from", "sl1m_dirty_image",
+                     "sl1m_solve_from", "sl1m_solve_resume", "sl1m_dirty_image",
                      "sl1m_timing_begin", "sl1m_timing_end", "sl1m_plan_query",
                      "sl1m_tune_workspace_bytes", "sl1m_tune",
                      "sl1m_server_create",
@@ -371,17 +384,19 @@ class Plan:
     def solve(self, vis, lam: float, max_iter: int, L: float = 0.0, eps: float = 0.0,
               check_every: int = 1, power_iters: int = 30, seed: int = 0,
               L_safety: float = 1.01, out: Optional[torch.Tensor] = None, stream=None,
-              x0=None, method: str = "fista"):
+              x0=None, method: str = "fista", nnz_eps: float = 0.0):
         """FISTA solve (sl1m_solve); with x0 (real [n_pix]) the warm start
         sl1m_solve_from, e.g. from dirty_image() or an upscaled coarser
-        solution; method "mfista" runs the monotone variant."""
+        solution; method "mfista" runs the monotone variant.  eps / nnz_eps
+        stop on a small relative change of the objective / of the non-zero
+        count between checks every check_every iterations."""
         vis = _dev(vis, self.cdtype, self.device)
         if out is None:
             out = torch.empty(self.n_pix, dtype=self.rdtype, device=self.device)
         prm = SolveParams(lam=float(lam), eps=float(eps), max_iter=int(max_iter),
                           check_every=int(check_every), L=float(L), L_safety=float(L_safety),
                           power_iters=int(power_iters), method=METHODS[method],
-                          seed=ctypes.c_uint64(seed))
+                          seed=ctypes.c_uint64(seed), nnz_eps=float(nnz_eps))
         info = SolveInfo()
         if x0 is None:
             _check(lib().sl1m_solve(self._h, _ptr(vis), ctypes.byref(prm), _ptr(out),
@@ -391,6 +406,33 @@ class Plan:
             _check(lib().sl1m_solve_from(self._h, _ptr(vis), _ptr(x0), ctypes.byref(prm),
                                          _ptr(out), ctypes.byref(info), _stream(stream)))
         return out, info.as_dict()
+
+    def solve_resume(self, vis, lam: float, max_iter: int, L: float, state=None,
+                     out: Optional[torch.Tensor] = None, stream=None):
+        """Checkpointed FISTA (sl1m_solve_resume): runs max_iter iterations
+        from `state` (None: a fresh start from a zero image) and returns
+        (image, info, state); state = {"img", "y" (device tensors, caller
+        order), "t", "k"} is the iteration state after the last iteration."""
+        vis = _dev(vis, self.cdtype, self.device)
+        if out is None:
+            out = torch.empty(self.n_pix, dtype=self.rdtype, device=self.device)
+        if state is None:
+            state = {"img": torch.zeros(self.n_pix, dtype=self.rdtype, device=self.device),
+                     "y": torch.zeros(self.n_pix, dtype=self.rdtype, device=self.device),
+                     "t": 0.0, "k": 0}
+        else:
+            state = {"img": state["img"].clone(), "y": state["y"].clone(), "t": state["t"],
+                     "k": state["k"]}
+        st = FistaState(img=_ptr(state["img"]), y=_ptr(state["y"]), t=float(state["t"]),
+                        k=int(state["k"]))
+        prm = SolveParams(lam=float(lam), eps=0.0, max_iter=int(max_iter), check_every=1,
+                          L=float(L), L_safety=1.01, power_iters=30, method=0,
+                          seed=ctypes.c_uint64(0), nnz_eps=0.0)
+        info = SolveInfo()
+        _check(lib().sl1m_solve_resume(self._h, _ptr(vis), ctypes.byref(st), ctypes.byref(prm),
+                                       _ptr(out), ctypes.byref(info), _stream(stream)))
+        state["t"], state["k"] = float(st.t), int(st.k)
+        return out, info.as_dict(), state
 
     def dirty_image(self, vis, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """max(0, Re(M^H V) / n_vis) in the caller's pixel order (sl1m_dirty_image)."""
@@ -404,10 +446,12 @@ class Plan:
         _check(lib().sl1m_timing_begin(self._h, int(max_launches)))
 
     def timing_end(self):
-        """Returns {kind: (launches, total_ms)} for forward, adjoint, fista."""
+        """Returns {kind: (launches, total_ms)} for the forward and adjoint
+        operator kernels, the FISTA update and the grid kernels by launch."""
         t = Timing()
         _check(lib().sl1m_timing_end(self._h, ctypes.byref(t)))
-        names = ("forward", "adjoint", "fista")
+        names = ("forward", "adjoint", "fista", "grid_fwd_delta", "grid_adj_delta",
+                 "grid_fwd_gauss", "grid_adj_gauss")
         return {n: (int(t.launches[i]), float(t.total_ms[i])) for i, n in enumerate(names)}
 
     def close(self):
@@ -493,7 +537,7 @@ class Server:
                        grid_mode=_GRID[grid])
         prm = SolveParams(lam=float(lam), eps=0.0, max_iter=int(max_iter), check_every=1,
                           L=float(L), L_safety=float(L_safety), power_iters=int(power_iters),
-                          method=0, seed=ctypes.c_uint64(seed))
+                          method=0, seed=ctypes.c_uint64(seed), nnz_eps=0.0)
         t = ctypes.c_uint64(0)
         torch.cuda.current_stream(d).synchronize()   # inputs written before the server reads them
         _check(lib().sl1m_server_submit(self._h, ctypes.byref(prob), _ptr(keep["vis"]),

@@ -3,7 +3,8 @@
 The grid evaluation computes the same operator as the direct one (the
 element of eq. (deltam) factorised into per-|l|, per-|m| and per-radius
 phasors).  Each case checks both evaluations against the FP64 oracle at the
-FP32 operator tolerance (norm-relative 1e-5) and that the plan took the path
+FP32 operator tolerance (norm-relative 1e-5, and every output within its
+element-wise bound, tests/elementwise.py) and that the plan took the path
 the case is about.  Sizes span several tiles, end in ragged tails (|m| groups
 of 8 that do not divide the |m| count, visibility counts that are not
 multiples of the tile) and cover the degenerate cells (the l = 0 and m = 0
@@ -14,6 +15,7 @@ import sys
 import numpy as np
 import pytest
 
+import elementwise as E
 import oracle as O
 from paper_1310_2078_amd import sl1m
 from paper_1310_2078_amd import workloads as W
@@ -149,6 +151,7 @@ def test_grid_and_direct_match_oracle(name):
     p = O.Problem.from_workload(wl)
     Vo = O.forward(p, x)
     go = O.adjoint(p, r)
+    mf, ma = E.abs_forward_rows(p, x), E.abs_adjoint_cols(p, r)
     out = {}
     for mode in ("require", "off"):
         plan = sl1m.Plan.from_workload(wl, grid=mode)
@@ -159,8 +162,12 @@ def test_grid_and_direct_match_oracle(name):
         V = plan.forward(x).cpu().numpy()
         g = plan.adjoint(r).cpu().numpy()
         ef, ea = rel(V, Vo), rel(g, go)
-        say(f"    {mode:8s} forward {ef:.3e} adjoint {ea:.3e} info {info}")
+        wf = E.worst_ratio(V, Vo, mf, wl.n_pix)
+        wa = E.worst_ratio(g, go, ma, wl.n_vis)
+        say(f"    {mode:8s} forward {ef:.3e} adjoint {ea:.3e} element-wise {wf:.3e} {wa:.3e} "
+            f"info {info}")
         assert ef <= TOL and ea <= TOL
+        assert wf <= 1.0 and wa <= 1.0
         out[mode] = (V, g)
         plan.close()
     say(f"    grid vs direct forward {rel(out['require'][0], out['off'][0]):.3e} "
@@ -232,12 +239,17 @@ def test_grid_config2_full_size_against_direct():
     p = O.Problem.from_workload(wl)
     ks = np.arange(0, wl.n_vis, 211)
     js = np.arange(0, wl.n_pix, 127)
-    ef = rel(Vg[ks], O.forward_rows(p, x, ks))
-    ea = rel(gg[js], O.adjoint_cols(p, r, js))
+    Vo, go = O.forward_rows(p, x, ks), O.adjoint_cols(p, r, js)
+    ef = rel(Vg[ks], Vo)
+    ea = rel(gg[js], go)
+    wf = E.worst_ratio(Vg[ks], Vo, E.abs_forward_rows(p, x, ks), wl.n_pix)
+    wa = E.worst_ratio(gg[js], go, E.abs_adjoint_cols(p, r, js), wl.n_vis)
     say(f"    grid vs direct forward {rel(Vg, Vd):.3e} adjoint {rel(gg, gd):.3e}; "
-        f"grid vs oracle sampled forward {ef:.3e} adjoint {ea:.3e}")
+        f"grid vs oracle sampled forward {ef:.3e} adjoint {ea:.3e}; "
+        f"element-wise {wf:.3e} {wa:.3e}")
     assert rel(Vg, Vd) <= TOL and rel(gg, gd) <= TOL
     assert ef <= TOL and ea <= TOL
+    assert wf <= 1.0 and wa <= 1.0
 
 
 def test_grid_config4_full_size_against_direct():
@@ -264,12 +276,17 @@ def test_grid_config4_full_size_against_direct():
     p = O.Problem.from_workload(wl)
     ks = np.arange(0, wl.n_vis, 4099)
     js = np.concatenate([np.arange(0, 1024 * 1024, 10007), np.arange(1024 * 1024, wl.n_pix, 2003)])
-    ef = rel(Vg[ks], O.forward_rows(p, x, ks))
-    ea = rel(gg[js], O.adjoint_cols(p, r, js))
+    Vo, go = O.forward_rows(p, x, ks), O.adjoint_cols(p, r, js)
+    ef = rel(Vg[ks], Vo)
+    ea = rel(gg[js], go)
+    wf = E.worst_ratio(Vg[ks], Vo, E.abs_forward_rows(p, x, ks), wl.n_pix)
+    wa = E.worst_ratio(gg[js], go, E.abs_adjoint_cols(p, r, js), wl.n_vis)
     say(f"    grid vs direct forward {rel(Vg, Vd):.3e} adjoint {rel(gg, gd):.3e}; "
-        f"grid vs oracle sampled forward {ef:.3e} adjoint {ea:.3e}")
+        f"grid vs oracle sampled forward {ef:.3e} adjoint {ea:.3e}; "
+        f"element-wise {wf:.3e} {wa:.3e}")
     assert rel(Vg, Vd) <= TOL and rel(gg, gd) <= TOL
     assert ef <= TOL and ea <= TOL
+    assert wf <= 1.0 and wa <= 1.0
 
 
 # case -> whether multi-RHS calls of 2 and 4 sides take the grid evaluation
@@ -300,6 +317,8 @@ def test_grid_multi_rhs(name):
     rng = np.random.default_rng(SEEDS[name] + 50)
     X = rng.standard_normal((8, wl.l.size))
     Rr = rng.standard_normal((8, wl.u.size)) + 1j * rng.standard_normal((8, wl.u.size))
+    mags = ([E.abs_forward_rows(p, X[r]) for r in range(8)],
+            [E.abs_adjoint_cols(p, Rr[r]) for r in range(8)])
     for nr in (2, 4, 8):
         Vg = plan.forward_multi(X[:nr]).cpu().numpy()
         gg = plan.adjoint_multi(Rr[:nr]).cpu().numpy()
@@ -307,8 +326,12 @@ def test_grid_multi_rhs(name):
         go = O.adjoint(p, Rr[:nr])
         for r in range(nr):
             ef, ea = rel(Vg[r], Vo[r]), rel(gg[r], go[r])
-            say(f"    nr={nr} side {r}: forward {ef:.3e} adjoint {ea:.3e}")
+            wf = E.worst_ratio(Vg[r], Vo[r], mags[0][r], wl.l.size)
+            wa = E.worst_ratio(gg[r], go[r], mags[1][r], wl.u.size)
+            say(f"    nr={nr} side {r}: forward {ef:.3e} adjoint {ea:.3e} "
+                f"element-wise {wf:.3e} {wa:.3e}")
             assert ef <= TOL and ea <= TOL
+            assert wf <= 1.0 and wa <= 1.0
             V1 = plan.forward(X[r]).cpu().numpy()
             g1 = plan.adjoint(Rr[r]).cpu().numpy()
             say(f"    nr={nr} side {r}: multi vs single forward {rel(Vg[r], V1):.3e} "
