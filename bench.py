@@ -1,17 +1,33 @@
 """Benchmark of the SL1M hot path on one MI355X.
 
-Workload: config 2 of the measurement plan -- a 256x256 wide-field delta grid
-over l, m in +-0.3 (65,536 pixels) against 97,536 visibilities of a
-128-antenna array (12 snapshots over 6 h, 150 MHz), FP32 operator with FP64
-phase.  A step is one FISTA iteration: forward operator, residual, adjoint,
-threshold and momentum update, i.e. 2 x 65,536 x 97,536 pixel-visibility
-evaluations.  The timed region is exactly `--steps` iterations of one L1 solve
-(100 by default, the workload's solve length) with L fixed beforehand.
+Headline workload: config 4 of the measurement plan, the NGC2403-size
+problem -- a 1024x1024 wide-field delta grid over l, m in +-0.35 plus
+wide-field Gaussian-pixel layers with sigma = 2, 4, 8 grid spacings on 512^2,
+256^2 and 128^2 grids (1,392,640 pixels), 409,600 visibilities of a
+256-antenna array (13 snapshots, 150 MHz) with per-antenna complex gains and
+Gaussian primary beams, FP32 operator with FP64 phase, lambda = 3 sigma
+sqrt(N_v).  A step is one FISTA iteration of the L1 solve: forward operator,
+residual, adjoint, threshold and momentum update (2 x N_p x N_v
+pixel-visibility evaluations).  The timed region is one sl1m_solve call of
+exactly `--steps` iterations with L fixed beforehand; it ends with the
+objective's forward (counted: evals = (2 steps + 1) N_p N_v).
 
-Prints one JSON line with the throughput, the dominant kernel's roofline
-fraction (kernel durations from HIP events recorded by the library around
-each launch on the launch stream) and the FP64 CPU oracle's rate on a bounded
-sample of the same workload.
+Reported beside it, in the same JSON line:
+* the full L1 solve of the workload (30 power-iteration steps for L, 100
+  FISTA iterations, objective), timed once: `l1_solve_time_s`;
+* per-kernel durations of the grid evaluation (HIP events recorded by the
+  library around each launch, on the launch stream) and the dominant
+  kernel's roofline: its executed FLOPs against the FP32 vector peak, and
+  its issue-slot model priced at the issue rates measured on this GPU;
+* the served-latency part of the metric: config 5's stream of 256 requests
+  (Poisson arrivals at 4/s, 200 FISTA iterations each), batched by the
+  library's continuous-batching server and one at a time, p50/p99/mean
+  latency and evals/s; plus a saturated stream (the first 64 requests at
+  4x the arrival rate);
+* config 2's FISTA iteration (256^2 delta grid, 97,536 visibilities) as a
+  secondary operator figure;
+* the FP64 CPU oracle's rate on a bounded sample of config 4
+  (`cpu_baseline`).
 """
 from __future__ import annotations
 
@@ -31,6 +47,22 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector peak (published)
 FLOP_PER_EVAL_DELTA = 14            # phase 3 FMA, reduction 2, sin+cos 2, accumulate 2 FMA
+FLOP_PER_EVAL_GAUSS_WIDE = 26       # + taper 9, amplitude 1, kappa FMA 2
+# The same counting rules (FMA = 2, sin, cos, exp2 = 1) applied to what the
+# grid kernels execute: a mirrored pair of delta cells (8 entries) costs one
+# FP64 phase FMA, one sin/cos pair and about 20 FP32 operations, 36 FLOP; a
+# single delta cell (4 entries) 24; a Gaussian cell (4 entries) one sin/cos
+# pair, two exp2 and about 26 FP32 operations, at most 32.
+EXEC_FLOP_PER_EVAL = {
+    "k_grid_fwd_delta_pairs": 4.5,
+    "k_grid_adj_delta_square": 4.5,
+    "k_grid_fwd_delta": 6.0,
+    "k_grid_adj_delta": 6.0,
+    "k_grid_fwd_gauss_pairs": 8.0,
+    "k_grid_adj_gauss_multi": 8.0,
+    "k_fwd_delta<float,4>": 14.0,
+    "k_adj_delta<float,4>": 14.0,
+}
 
 
 def _function_text(src: str, name: str) -> str:
@@ -172,37 +204,6 @@ def ingest_counters(fetch_csv, write_csv, bench_log=None):
     print(json.dumps(out, indent=1))
 
 
-def cpu_baseline(wl, threads: int):
-    """The FP64 oracle, untuned, on a bounded sample of the workload: the
-    forward for the first 512*threads visibilities (all pixels) and the adjoint
-    for the first 2048*threads pixels against the first quarter of the
-    visibilities."""
-    import oracle as O
-    p = O.Problem.from_workload(wl, threads=threads)
-    rng = np.random.default_rng(0)
-    x = rng.standard_normal(wl.n_pix)
-    nf = min(wl.n_vis, 512 * threads)
-    t0 = time.perf_counter()
-    O.forward_rows(p, x, np.arange(nf))
-    tf = time.perf_counter() - t0
-    nvq = wl.n_vis // 4
-    pq = O.Problem(l=wl.l, m=wl.m, u=wl.u[:nvq], v=wl.v[:nvq], w=wl.w[:nvq], threads=threads)
-    na = min(wl.n_pix, 2048 * threads)
-    r = rng.standard_normal(nvq) + 1j * rng.standard_normal(nvq)
-    t0 = time.perf_counter()
-    O.adjoint_cols(pq, r, np.arange(na))
-    ta = time.perf_counter() - t0
-    evals = nf * wl.n_pix + na * nvq
-    return {
-        "value": evals / (tf + ta),
-        "unit": "evals/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": f"forward rows 0..{nf - 1} x {wl.n_pix} pixels + adjoint pixels 0..{na - 1} "
-                  f"x {nvq} visibilities ({evals:.3e} evals, {tf + ta:.1f} s)",
-    }
-
-
 def _time_ops(plan, fn, reps):
     import torch
     fn()
@@ -214,8 +215,11 @@ def _time_ops(plan, fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def extras(plan2, wl2, dev):
-    """Secondary workloads, reported beside the headline line (not in `value`)."""
+def extras(plan2, wl2, dev, c4):
+    """More workloads (`--extras`), reported beside the headline line (not in
+    `value`): direct evaluation, warm starts, MFISTA, several right-hand
+    sides, one GPU's share of config 4, the quad-tree refinement and the FP64
+    config 1 solve."""
     import torch
     from paper_1310_2078_amd import sl1m
     from paper_1310_2078_amd import workloads as W
@@ -309,72 +313,24 @@ def extras(plan2, wl2, dev):
         pm.close()
         del pm, Vm, G
     del X
-    # config 4: multiscale Gaussian pixels with direction-dependent gains
-    wl4 = W.config4()
-    t0 = time.perf_counter()
-    p4 = sl1m.Plan.from_workload(wl4, device=dev)
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t0
+    # config 4 (the headline workload): one GPU's share of it split over 8
+    # GPUs by visibilities (every 8th record, all pixels: the grid evaluation
+    # keeps its square pixel grid)
+    wl4, V4d, Ve32, rate4 = c4["wl"], c4["data"], c4["extended_data"], c4["evals_per_s"]
     x4 = torch.as_tensor(rng.standard_normal(wl4.n_pix), dtype=torch.float32, device=dev)
-    V4 = p4.forward(x4)
-    g4 = torch.empty(wl4.n_pix, dtype=torch.float32, device=dev)
-    p4.timing_begin(16)
-    tf = _time_ops(p4, lambda: p4.forward(x4, out=V4), 2)
-    ta = _time_ops(p4, lambda: p4.adjoint(V4, out=g4), 2)
-    t4 = p4.timing_end()
-    n_delta = 1024 * 1024
-    n_gauss = wl4.n_pix - n_delta
-    flops = (14 * n_delta + 26 * n_gauss) * wl4.n_vis
-    ex["config4"] = {
-        "n_pix": wl4.n_pix, "n_vis": wl4.n_vis, "plan_s": t_plan,
-        "evaluation": "grid" if p4.info()["grid"] else "direct",
-        "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
-        "forward_kernel_ms": t4["forward"][1] / max(t4["forward"][0], 1),
-        "adjoint_kernel_ms": t4["adjoint"][1] / max(t4["adjoint"][0], 1),
-        "evals_per_s": 2 * wl4.n_pix * wl4.n_vis / (tf + ta),
-        "fista_iteration_s_est": tf + ta,
-        "canonical_tflops": 2 * flops / (tf + ta) / 1e12}
-    # one GPU's share of config 4 split over 8 GPUs by visibilities (every 8th
-    # record, all pixels: the grid evaluation keeps its square pixel grid)
     ws = dataclasses.replace(wl4, u=wl4.u[::8], v=wl4.v[::8], w=wl4.w[::8],
                              ant_p=wl4.ant_p[::8], ant_q=wl4.ant_q[::8], noise=None)
     ps = sl1m.Plan.from_workload(ws, device=dev)
     Vs = ps.forward(x4)
     gsh = torch.empty(wl4.n_pix, dtype=torch.float32, device=dev)
-    ps.timing_begin(16)
     tfs = _time_ops(ps, lambda: ps.forward(x4, out=Vs), 3)
     tas = _time_ops(ps, lambda: ps.adjoint(Vs, out=gsh), 3)
-    tsh = ps.timing_end()
     rate_s = 2 * ws.n_pix * ws.n_vis / (tfs + tas)
     ex["config4_shard_1_of_8_by_visibilities"] = {
         "n_pix": ws.n_pix, "n_vis": ws.n_vis, "forward_ms": tfs * 1e3, "adjoint_ms": tas * 1e3,
-        "forward_kernel_ms": tsh["forward"][1] / max(tsh["forward"][0], 1),
-        "adjoint_kernel_ms": tsh["adjoint"][1] / max(tsh["adjoint"][0], 1),
-        "evals_per_s": rate_s, "rate_vs_full_config4": rate_s / ex["config4"]["evals_per_s"]}
+        "evals_per_s": rate_s, "rate_vs_full_config4": rate_s / rate4}
     ps.close()
-    del ps, Vs, gsh
-    # the config 4 L1 solve: data = the point sources through the operator plus
-    # the 50 extended sources as a fine FP64 sum of delta points (not the
-    # Gaussian-pixel model) plus noise; L from 30 power steps; 100 iterations
-    pe = sl1m.Plan(wl4.extra_l, wl4.extra_m, wl4.u, wl4.v, wl4.w, ant_p=wl4.ant_p,
-                   ant_q=wl4.ant_q, ant_gain=wl4.ant_gain, ant_fwhm=wl4.ant_fwhm,
-                   precision="fp64", device=dev)
-    Ve = pe.forward(wl4.extra_flux)
-    pe.close()
-    Ve32 = Ve.to(torch.complex64)
-    V4d = p4.forward(wl4.x_true) + Ve32 + \
-        torch.as_tensor(wl4.noise, dtype=torch.complex64, device=dev)
-    del Ve
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    img4, info4 = p4.solve(V4d, wl4.lam, wl4.n_iter, L=0.0, power_iters=wl4.power_iters)
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
-    ex["config4"]["solve"] = {
-        "time_s": ts, "iterations": wl4.n_iter, "power_iterations": wl4.power_iters,
-        "L": info4["L"], "F": info4["F"], "nnz": info4["nnz"],
-        "evals_per_s": 2 * wl4.n_pix * wl4.n_vis * (wl4.n_iter + wl4.power_iters) / ts}
-    del p4, x4, V4, g4, img4
+    del ps, Vs, gsh, x4
     # adaptive quad-tree refinement (Section "Acceleration strategies"): 32 x 32
     # cells over the field, six levels down to the 1024^2 grid's spacing, 100
     # iterations per level, against the full 1024^2 delta grid solved with the
@@ -408,7 +364,6 @@ def extras(plan2, wl2, dev):
             "full_grid_1024sq_delta": {"time_s": tf_, "F": infof["F"], "nnz": infof["nnz"]},
             "time_ratio_full_over_quadtree": tf_ / tq,
             "F_ratio_quadtree_over_full": lv[-1].info["F"] / infof["F"]}
-    del V4d, Ve32
     # config 1: plain SL1M in FP64 (100 iterations + 30 power steps)
     wl1 = W.config1()
     p1 = sl1m.Plan.from_workload(wl1, device=dev, precision="fp64")
@@ -424,14 +379,321 @@ def extras(plan2, wl2, dev):
     return ex
 
 
+
+
+def cpu_baseline(wl, threads: int):
+    """The FP64 oracle, untuned, on a bounded sample of config 4: the forward
+    of every 32nd pixel of each pixel kind and layer (its mix of delta and
+    Gaussian pixels, gains included) for the first 512 x threads
+    visibilities, and the adjoint of 2048 x threads pixels spread evenly over
+    the image against every 32nd visibility.  Returns evals/s over both."""
+    import oracle as O
+    sub = np.arange(0, wl.n_pix, 32)
+    nf = min(wl.n_vis, 512 * threads)
+    pf = O.Problem(l=wl.l[sub], m=wl.m[sub], u=wl.u[:nf], v=wl.v[:nf], w=wl.w[:nf],
+                   sigma=wl.sigma[sub], kind=wl.kind[sub], ant_p=wl.ant_p[:nf],
+                   ant_q=wl.ant_q[:nf], ant_gain=wl.ant_gain, ant_fwhm=wl.ant_fwhm,
+                   threads=threads)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(sub.size)
+    t0 = time.perf_counter()
+    O.forward(pf, x)
+    tf = time.perf_counter() - t0
+    ks = np.arange(0, wl.n_vis, 32)
+    na = min(wl.n_pix, 2048 * threads)
+    js = np.linspace(0, wl.n_pix - 1, na).astype(np.int64)
+    pa = O.Problem(l=wl.l, m=wl.m, u=wl.u[ks], v=wl.v[ks], w=wl.w[ks], sigma=wl.sigma,
+                   kind=wl.kind, ant_p=wl.ant_p[ks], ant_q=wl.ant_q[ks], ant_gain=wl.ant_gain,
+                   ant_fwhm=wl.ant_fwhm, threads=threads)
+    r = rng.standard_normal(ks.size) + 1j * rng.standard_normal(ks.size)
+    t0 = time.perf_counter()
+    O.adjoint_cols(pa, r, js)
+    ta = time.perf_counter() - t0
+    evals = sub.size * nf + na * ks.size
+    return {
+        "value": evals / (tf + ta),
+        "unit": "evals/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"config 4: forward of every 32nd pixel ({sub.size}, all kinds and layers) x "
+                  f"the first {nf} visibilities + adjoint of {na} pixels spread over the image x "
+                  f"every 32nd visibility ({ks.size}); gains and beams included "
+                  f"({evals:.3e} evals, {tf + ta:.1f} s)",
+    }
+
+
+def config4_data(wl4, plan, dev):
+    """Config 4's data (not timed): the point sources through the operator,
+    the 50 extended sources as a fine FP64 sum of delta points (not the
+    Gaussian-pixel model), and noise."""
+    import torch
+    from paper_1310_2078_amd import sl1m
+    pe = sl1m.Plan(wl4.extra_l, wl4.extra_m, wl4.u, wl4.v, wl4.w, ant_p=wl4.ant_p,
+                   ant_q=wl4.ant_q, ant_gain=wl4.ant_gain, ant_fwhm=wl4.ant_fwhm,
+                   precision="fp64", device=dev)
+    Ve32 = pe.forward(wl4.extra_flux).to(torch.complex64)
+    pe.close()
+    noise = torch.as_tensor(wl4.noise, dtype=torch.complex64, device=dev)
+    return plan.forward(wl4.x_true) + Ve32 + noise, Ve32 + noise
+
+
+def dominant_kernel(pinfo, tim, n_delta, n_gauss, n_vis, n_layers):
+    """The grid kernel with the longest average launch in the timed region:
+    (name, average ms, evals per launch)."""
+    pairs = bool(pinfo["grid_pairs"])
+    cands = [
+        ("k_grid_fwd_delta_pairs" if pairs else "k_grid_fwd_delta", "grid_fwd_delta",
+         n_delta * n_vis),
+        ("k_grid_adj_delta_square" if pairs else "k_grid_adj_delta", "grid_adj_delta",
+         n_delta * n_vis),
+        ("k_grid_adj_gauss_multi", "grid_adj_gauss", n_gauss * n_vis),
+        # one launch per layer: evals per launch on average
+        ("k_grid_fwd_gauss_pairs", "grid_fwd_gauss", n_gauss * n_vis / max(n_layers, 1)),
+    ]
+    best = None
+    for name, key, ev in cands:
+        n, ms = tim.get(key, (0, 0.0))
+        if n == 0:
+            continue
+        avg = ms / n
+        if best is None or avg > best[1]:
+            best = (name, avg, ev)
+    return best
+
+
+def headline(args, dev):
+    import torch
+    from paper_1310_2078_amd import sl1m
+    from paper_1310_2078_amd import workloads as W
+
+    wl4 = W.config4()
+    n_pix, n_vis = wl4.n_pix, wl4.n_vis
+    n_delta = int(np.sum(wl4.kind == W.PIX_DELTA))
+    n_gauss = n_pix - n_delta
+    n_layers = len(np.unique(wl4.sigma[wl4.kind != W.PIX_DELTA]))
+    print(f"[bench] config4 n_pix={n_pix} n_vis={n_vis} steps={args.steps} "
+          f"warmup={args.warmup}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plan = sl1m.Plan.from_workload(wl4, device=dev)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    tuning = None
+    if args.tune:
+        tuning = plan.tune(reps=3)
+        plan.close()
+        plan = sl1m.Plan.from_workload(wl4, device=dev, tuning=tuning)
+        print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
+    V, V_ext = config4_data(wl4, plan, dev)
+    torch.cuda.synchronize()
+
+    # the full L1 solve: 30 power steps, 100 iterations, objective
+    t0 = time.perf_counter()
+    img, info = plan.solve(V, wl4.lam, wl4.n_iter, L=0.0, power_iters=wl4.power_iters)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    L = info["L"]
+    solve_evals = float(n_pix) * n_vis * (2 * (wl4.power_iters + wl4.n_iter) + 1)
+    print(f"[bench] full solve {t_solve:.3f} s; info {info}", file=sys.stderr, flush=True)
+
+    if args.warmup > 0:
+        plan.solve(V, wl4.lam, args.warmup, L=L)
+    torch.cuda.synchronize()
+    plan.timing_begin(max(16, 4 * args.steps + 16))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    img, info_k = plan.solve(V, wl4.lam, args.steps, L=L)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tim = plan.timing_end()
+    evals = float(n_pix) * n_vis * (2 * args.steps + 1)
+    print(f"[bench] {args.steps} iterations in {elapsed:.4f} s; timing {tim}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.profile_ops):
+        plan.adjoint(plan.forward(img))
+    torch.cuda.synchronize()
+
+    pinfo = plan.info()
+    plan_shape = {k: pinfo[k] for k in PLAN_KEYS}
+    avg = {k: (ms / n if n else 0.0) for k, (n, ms) in tim.items()}
+    dom_name, dom_ms, dom_evals = dominant_kernel(pinfo, tim, n_delta, n_gauss, n_vis, n_layers)
+    exec_flop = EXEC_FLOP_PER_EVAL[dom_name]
+    achieved = exec_flop * dom_evals / (dom_ms * 1e-3) / 1e12
+    canonical = (FLOP_PER_EVAL_DELTA if "delta" in dom_name else FLOP_PER_EVAL_GAUSS_WIDE)
+    # executed FLOPs of one iteration (both operators) over the time of a step
+    exec_step = 2 * n_vis * (n_delta * EXEC_FLOP_PER_EVAL["k_grid_adj_delta_square"]
+                             + n_gauss * EXEC_FLOP_PER_EVAL["k_grid_adj_gauss_multi"])
+    canon_step = 2 * n_vis * (n_delta * FLOP_PER_EVAL_DELTA + n_gauss * FLOP_PER_EVAL_GAUSS_WIDE)
+    step_s = elapsed / args.steps
+    roof = {
+        "bound": "alu",
+        "kernel": dom_name,
+        "achieved": achieved,
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP32_TFLOPS,
+        "traffic": load_traffic(dom_name, plan_shape),
+        "kernel_avg_ms": dom_ms,
+        "evals_per_launch": dom_evals,
+        "executed_flop_per_eval": exec_flop,
+        "accounting": "achieved/frac: the FLOPs the kernel executes (FMA = 2; sin, cos, exp2 = "
+                      "1; the grid factorisation shares one sincos among 4 or 8 entries) over "
+                      "its average launch duration (HIP events on the launch stream); "
+                      "effective_*: the direct evaluation's count per entry at the same rate",
+        "effective_flop_per_eval": canonical,
+        "effective_tflops": canonical * dom_evals / (dom_ms * 1e-3) / 1e12,
+    }
+    if dom_name in SLOT_MIX:
+        rates = sl1m.issue_rates(dev)
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        per_unit, n32, n64, ntr = SLOT_MIX[dom_name]
+        t_model = (dom_evals / per_unit) / cus * (
+            n32 / rates["fp32_fma"] + n64 / rates["fp64_fma"] + ntr / rates["sin_cos"])
+        roof["slots"] = {
+            "unit": "wave64 instructions per s per CU", "rates": rates, "cus": cus,
+            "mix_per_unit": {"entries": per_unit, "fp32_rate": n32, "fp64": n64, "sin_cos": ntr},
+            "model_ms": t_model * 1e3, "frac": t_model * 1e3 / dom_ms}
+    out = {
+        "metric": "pixel x visibility evals/s (forward + adjoint) of the L1 solve on config 4; "
+                  "L1 solve time; p50/p99 served latency (config 5)",
+        "value": evals / elapsed,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * step_s,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 phase)",
+        "data": "synthetic",
+        "config": {
+            "workload": "config4: 1024^2 wide-field delta grid over +-0.35 plus wide-field "
+                        "Gaussian layers sigma = 2, 4, 8 spacings (512^2, 256^2, 128^2), "
+                        "1,392,640 pixels; 409,600 visibilities (256 antennas, 13 snapshots, "
+                        "150 MHz); per-antenna gains and 0.4 rad primary beams; FISTA "
+                        "lambda = 3 sigma sqrt(N_v)",
+            "n_pix": n_pix,
+            "n_vis": n_vis,
+            "evals_per_step": 2 * n_pix * n_vis,
+            "evaluation": "grid" if pinfo["grid"] else "direct",
+            "tuning": tuning,
+            "plan": plan_shape,
+        },
+        "l1_solve_time_s": t_solve,
+        "solve": {
+            "power_iterations": wl4.power_iters, "iterations": wl4.n_iter,
+            "time_s": t_solve, "evals": solve_evals, "evals_per_s": solve_evals / t_solve,
+            "L": L, "F": info["F"], "l2_term": info["l2_term"], "l1_term": info["l1_term"],
+            "nnz": info["nnz"], "plan_s": t_plan},
+        "kernels": {
+            "forward_avg_ms": avg["forward"],
+            "adjoint_avg_ms": avg["adjoint"],
+            "fista_update_avg_ms": avg["fista"],
+            "grid_fwd_delta_avg_ms": avg["grid_fwd_delta"],
+            "grid_adj_delta_avg_ms": avg["grid_adj_delta"],
+            "grid_fwd_gauss_avg_ms_per_layer": avg["grid_fwd_gauss"],
+            "grid_adj_gauss_avg_ms": avg["grid_adj_gauss"],
+            # the update's algorithmic bytes: read the gradient (adjoint
+            # output), scale, y and I, write y and I -- 20 B per pixel
+            "fista_update_hbm_gbs": 20.0 * n_pix / (avg["fista"] * 1e-3) / 1e9
+                                    if avg["fista"] else None,
+            "fista_update_hbm_frac": 20.0 * n_pix / (avg["fista"] * 1e-3) / HBM_PEAK_BPS
+                                     if avg["fista"] else None,
+            "fista_update_rows_read": pinfo["n_achunks"],
+            "executed_tflops_per_step": exec_step / step_s / 1e12,
+            "effective_tflops_per_step": canon_step / step_s / 1e12,
+        },
+        "roofline": roof,
+    }
+    ctx = {"wl": wl4, "plan": plan, "data": V, "extended_data": V_ext,
+           "evals_per_s": evals / elapsed}
+    return out, ctx
+
+
+def config2_secondary(dev, steps=20):
+    """Config 2's FISTA iteration (a 256^2 delta grid over +-0.3, 97,536
+    visibilities): evals/s and kernel durations."""
+    import torch
+    from paper_1310_2078_amd import sl1m
+    from paper_1310_2078_amd import workloads as W
+    wl = W.config2()
+    plan = sl1m.Plan.from_workload(wl, device=dev)
+    V = plan.forward(wl.x_true) + torch.as_tensor(wl.noise, dtype=torch.complex64, device=dev)
+    L = 1.01 * plan.estimate_L(wl.power_iters, seed=0)
+    plan.solve(V, wl.lam, 3, L=L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.solve(V, wl.lam, steps, L=L)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.timing_begin(4 * steps + 16)
+    plan.solve(V, wl.lam, steps, L=L)
+    tim = plan.timing_end()
+    avg = {k: (ms / n if n else 0.0) for k, (n, ms) in tim.items()}
+    pinfo = plan.info()
+    out = {"n_pix": wl.n_pix, "n_vis": wl.n_vis, "iterations": steps,
+           "ms_per_iteration": 1e3 * el / steps,
+           "evals_per_s": float(wl.n_pix) * wl.n_vis * (2 * steps + 1) / el,
+           "forward_avg_ms": avg["forward"], "adjoint_avg_ms": avg["adjoint"],
+           "fista_update_avg_ms": avg["fista"],
+           "grid_adj_delta_avg_ms": avg["grid_adj_delta"],
+           "grid_fwd_delta_avg_ms": avg["grid_fwd_delta"],
+           "plan": {k: pinfo[k] for k in PLAN_KEYS}}
+    name = "k_grid_adj_delta_square"
+    if avg["grid_adj_delta"] and name in SLOT_MIX:
+        rates = sl1m.issue_rates(dev)
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        per_unit, n32, n64, ntr = SLOT_MIX[name]
+        t_model = (wl.n_pix * wl.n_vis / per_unit) / cus * (
+            n32 / rates["fp32_fma"] + n64 / rates["fp64_fma"] + ntr / rates["sin_cos"])
+        out["adjoint_slot_frac"] = t_model * 1e3 / avg["grid_adj_delta"]
+        out["adjoint_executed_frac"] = (EXEC_FLOP_PER_EVAL[name] * wl.n_pix * wl.n_vis
+                                        / (avg["grid_adj_delta"] * 1e-3) / 1e12
+                                        / PEAK_FP32_TFLOPS)
+        out["adjoint_traffic"] = load_traffic(name, out["plan"])
+    return plan, wl, out
+
+
+def serving(dev, n_req: int, n_sat: int):
+    """Config 5: the 256-request stream batched and one at a time, and a
+    saturated stream of its first `n_sat` requests at 4x the arrival rate."""
+    from paper_1310_2078_amd import serve as S
+    res = {}
+    runs = [("stream", n_req, 1.0)]
+    if n_sat > 0:
+        runs.append(("saturated", n_sat, 0.25))
+    for key, n, scale in runs:
+        arrivals, reqs = S.make_stream(n, scale)
+        print(f"[bench] serving {key}: preparing {n} requests", file=sys.stderr, flush=True)
+        data = S.prepare(reqs, dev)
+        rec = {"requests": n, "arrival_rate_per_s": n / float(arrivals[-1]),
+               "offered_evals": sum(S.request_evals(r) for r in reqs)}
+        rec["batched"], _ = S.run_batched(arrivals, reqs, data, dev, log=sys.stderr)
+        print(f"[bench] serving {key} batched {rec['batched']}", file=sys.stderr, flush=True)
+        rec["unbatched"], _ = S.run_unbatched(arrivals, reqs, data, dev, log=sys.stderr)
+        print(f"[bench] serving {key} unbatched {rec['unbatched']}", file=sys.stderr, flush=True)
+        res[key] = rec
+        del data
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the secondary workloads (config 4, multi-RHS, FP64 config 1)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the config 5 request streams")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-saturated", type=int, default=64,
+                    help="requests in the saturated stream (4x arrival rate); 0 skips it")
+    ap.add_argument("--no-config2", action="store_true")
+    ap.add_argument("--extras", action="store_true",
+                    help="also run the secondary workloads (direct evaluation, warm starts, "
+                         "MFISTA, several right-hand sides, quad-tree, FP64 config 1)")
+    ap.add_argument("--tune", action="store_true",
+                    help="tune the headline plan's launch shapes (sl1m_tune) first")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM counters)")
     ap.add_argument("--ingest-counters", nargs="+", metavar="PATH",
@@ -439,14 +701,6 @@ def main():
                          "(FETCH_SIZE, WRITE_SIZE) of a --calib-copy run into "
                          "profiles/traffic.json (with the run's plan split, read from its "
                          "output line) and exit")
-    ap.add_argument("--grid", choices=["auto", "off", "require"], default="auto",
-                    help="evaluation of the delta pixels: grid factorisation when the pixels "
-                         "qualify (auto), always direct (off)")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="use the plan's default launch shapes instead of tuning them first")
-    ap.add_argument("--tuning", default=None,
-                    help="JSON of a tuning choice (the config.tuning of an earlier line): use it "
-                         "instead of tuning")
     ap.add_argument("--profile-ops", type=int, default=0,
                     help="after the timed region, run this many extra forward+adjoint pairs "
                          "(for profiler runs)")
@@ -458,181 +712,40 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(sharding over several GPUs, by visibilities for grid plans and by pixels otherwise, is not built)", file=sys.stderr)
+              "(sharding over several GPUs, by visibilities for grid plans and by pixels "
+              "otherwise, is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_1310_2078_amd import sl1m
-    from paper_1310_2078_amd import workloads as W
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    wl = W.config2()
-    n_pix, n_vis = wl.n_pix, wl.n_vis
-    print(f"[bench] config2 n_pix={n_pix} n_vis={n_vis} steps={args.steps} warmup={args.warmup}",
-          file=sys.stderr, flush=True)
-    plan = sl1m.Plan.from_workload(wl, device=dev, grid=args.grid)
-    tuning = None
-    if args.tuning:
-        # a fixed choice (e.g. the one a timed run printed), for profiler runs
-        tuning = json.loads(args.tuning)
-        plan.close()
-        plan = sl1m.Plan.from_workload(wl, device=dev, tuning=tuning)
-    elif not args.no_tune:
-        # launch shapes from the autotuner (sl1m_tune), restricted to the
-        # requested evaluation
-        tuning = plan.tune(reps=7)
-        if args.grid != "auto" and tuning["grid"] != args.grid:
-            tuning = None
-        else:
-            plan.close()
-            plan = sl1m.Plan.from_workload(wl, device=dev, tuning=tuning)
-        print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
-    noise = torch.as_tensor(wl.noise, dtype=torch.complex64, device=dev)
-    V = plan.forward(wl.x_true) + noise            # synthetic data, not timed
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rq = plan.estimate_L(wl.power_iters, seed=0)
-    torch.cuda.synchronize()
-    t_power = time.perf_counter() - t0
-    L = 1.01 * rq
-
-    if args.warmup > 0:
-        plan.solve(V, wl.lam, args.warmup, L=L)
-    torch.cuda.synchronize()
-    plan.timing_begin(max(16, 2 * args.steps + 8))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    img, info = plan.solve(V, wl.lam, args.steps, L=L)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tim = plan.timing_end()
-    elapsed = t1 - t0
-    evals = 2.0 * n_pix * n_vis * args.steps
-    print(f"[bench] solve {args.steps} it in {elapsed:.4f} s; timing {tim}; info {info}",
-          file=sys.stderr, flush=True)
-
-    for _ in range(args.profile_ops):
-        plan.adjoint(plan.forward(img))
+    out, c4 = headline(args, dev)
+    c4.pop("plan").close()
     if args.calib_copy:
         src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             torch.mul(src, 1.0, out=dst)   # an elementwise kernel: reads and writes CALIB_BYTES
-    torch.cuda.synchronize()
-
-    fwd_n, fwd_ms = tim["forward"]
-    adj_n, adj_ms = tim["adjoint"]
-    fis_n, fis_ms = tim["fista"]
-    fwd_avg = fwd_ms / max(fwd_n, 1)
-    adj_avg = adj_ms / max(adj_n, 1)
-    pinfo = plan.info()
-    plan_shape = {k: pinfo[k] for k in PLAN_KEYS}
-    grid = bool(pinfo["grid"])
-    if grid and pinfo["grid_pairs"]:
-        names = ("k_grid_adj_delta_square", "k_grid_fwd_delta_pairs")
-    elif grid:
-        names = ("k_grid_adj_delta", "k_grid_fwd_delta")
-    else:
-        names = ("k_adj_delta<float,4>", "k_fwd_delta<float,4>")
-    if adj_avg >= fwd_avg:
-        dom, dom_ms, dom_name = "adjoint", adj_avg, names[0]
-    else:
-        dom, dom_ms, dom_name = "forward", fwd_avg, names[1]
-    exec_flop = 4.5 if (grid and pinfo["grid_pairs"]) else 6.0 if grid else float(FLOP_PER_EVAL_DELTA)
-    flops = FLOP_PER_EVAL_DELTA * n_pix * n_vis
-    achieved = flops / (dom_ms * 1e-3) / 1e12
-    out = {
-        "metric": "pixel x visibility evals/s (forward + adjoint), FISTA iteration on config 2",
-        "value": evals / elapsed,
-        "unit": "evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 (f64 phase)",
-        "data": "synthetic",
-        "config": {
-            "workload": "config2: 256x256 wide-field delta pixels over +-0.3, 97,536 visibilities "
-                        "(128 antennas, 12 snapshots, 150 MHz), FISTA lambda=3*sigma*sqrt(N_v)",
-            "n_pix": n_pix,
-            "n_vis": n_vis,
-            "evals_per_step": 2 * n_pix * n_vis,
-            "evaluation": "grid" if grid else "direct",
-            "tuning": tuning,
-            "plan": plan_shape,
-        },
-        "l1_solve_time_s": elapsed,
-        "solve": {
-            "iterations": args.steps,
-            "time_s": elapsed,
-            "power_iteration_s": t_power,
-            "power_iterations": wl.power_iters,
-            "L": L,
-            "F": info["F"],
-            "nnz": info["nnz"],
-        },
-        "kernels": {
-            "forward_avg_ms": fwd_avg,
-            "adjoint_avg_ms": adj_avg,
-            "fista_update_avg_ms": fis_ms / max(fis_n, 1),
-            # the update reads the adjoint's split-K rows (n_achunks x 4 B per
-            # pixel) plus scale, y and I, and writes y and I: algorithmic HBM
-            # bytes per launch over its measured time, against 8 TB/s
-            "fista_update_hbm_gbs": n_pix * (4 * pinfo["n_achunks"] + 20)
-                                    / (fis_ms / max(fis_n, 1) * 1e-3) / 1e9,
-            "fista_update_hbm_frac": n_pix * (4 * pinfo["n_achunks"] + 20)
-                                     / (fis_ms / max(fis_n, 1) * 1e-3) / HBM_PEAK_BPS,
-            "forward_evals_per_s": n_pix * n_vis / (fwd_avg * 1e-3),
-            "adjoint_evals_per_s": n_pix * n_vis / (adj_avg * 1e-3),
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": dom_name,
-            "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": load_traffic(dom_name, plan_shape),
-            "flop_per_eval": FLOP_PER_EVAL_DELTA,
-            "evals_per_launch": n_pix * n_vis,
-            # the same counting rules applied to the work the kernel executes:
-            # a mirrored pair of cells (8 entries) takes 36 FLOP, a single cell
-            # (4 entries) 24, a direct entry 14
-            "executed_flop_per_eval": exec_flop,
-            "executed_achieved": exec_flop * n_pix * n_vis / (dom_ms * 1e-3) / 1e12,
-            "executed_frac": exec_flop * n_pix * n_vis / (dom_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
-            "accounting": "achieved/frac: canonical delta-eval FLOPs (14 per entry, the "
-                          "direct evaluation); executed_*: the grid evaluation's own count "
-                          "(one sincos per 4 entries, per 8 for mirrored pairs)" if grid else
-                          "canonical delta-eval FLOPs (14 per entry)",
-        },
-    }
-    # issue-slot roofline of the dominant kernel: its inner loop's instruction
-    # mix (from its gfx950 assembly) priced at the issue rates measured now
-    if dom_name in SLOT_MIX:
-        rates = sl1m.issue_rates(dev)
-        cus = torch.cuda.get_device_properties(dev).multi_processor_count
-        per_unit, n32, n64, ntr = SLOT_MIX[dom_name]
-        t_model = (n_pix * n_vis / per_unit) / cus * (
-            n32 / rates["fp32_fma"] + n64 / rates["fp64_fma"] + ntr / rates["sin_cos"])
-        out["roofline"]["slots"] = {
-            "unit": "wave64 instructions per s per CU", "rates": rates, "cus": cus,
-            "mix_per_unit": {"entries": per_unit, "fp32_rate": n32, "fp64": n64,
-                             "sin_cos": ntr},
-            "model_ms": t_model * 1e3, "frac": t_model * 1e3 / dom_ms}
-    if not args.no_extras:
-        out["extras"] = extras(plan, wl, dev)
+        torch.cuda.synchronize()
+        del src, dst
+    if not args.no_serving:
+        out["serving"] = serving(dev, args.serve_requests, args.serve_saturated)
+        st = out["serving"]["stream"]
+        out["p50_s"] = st["batched"]["p50_s"]
+        out["p99_s"] = st["batched"]["p99_s"]
+    plan2 = wl2 = None
+    if not args.no_config2 or args.extras:
+        plan2, wl2, out["config2"] = config2_secondary(dev)
+        print(f"[bench] config2 {out['config2']}", file=sys.stderr, flush=True)
+    if args.extras:
+        out["extras"] = extras(plan2, wl2, dev, c4)
     if not args.no_cpu_baseline:
         try:
             threads = max(1, min(16, len(os.sched_getaffinity(0))))
         except AttributeError:
             threads = 1
-        out["cpu_baseline"] = cpu_baseline(wl, threads)
+        print(f"[bench] cpu baseline on {threads} threads", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(c4["wl"], threads)
     print(json.dumps(out), flush=True)
 
 
