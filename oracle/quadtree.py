@@ -54,6 +54,13 @@ def refine(l, m, h, image, frac: float, h_min: float):
     image = np.asarray(image, np.float64)
     thr = frac * float(np.max(image)) if image.size else 0.0
     split = (image > thr) & (h > h_min * (1.0 + 1e-9)) & (image > 0.0)
+    return refine_mask(l, m, h, image, split)
+
+
+def refine_mask(l, m, h, image, split):
+    """Replaces the cells marked in `split` by their four children (reading
+    R17's order and start values)."""
+    image = np.asarray(image, np.float64)
     nl, nm, nh, x0 = [], [], [], []
     for j in range(l.shape[0]):
         if not split[j]:
@@ -64,6 +71,31 @@ def refine(l, m, h, image, frac: float, h_min: float):
             nl.append(l[j] + dl); nm.append(m[j] + dm); nh.append(h[j] / 2.0)
             x0.append(image[j] / 4.0)
     return np.array(nl), np.array(nm), np.array(nh), np.array(x0), split
+
+
+def certificate_split(problem_of, V, lam, l, m, h, image, op, h_min: float,
+                      sigma_factor: float = 0.5, tol: float = 1e-3):
+    """Cells whose refinement would lower the objective by the optimality
+    conditions (Section "Implementation of SL1M"): a cell with side > h_min is
+    marked when one of its four children, as a pixel of the next level, has
+    Re(M^H (V - M I))_child > lam (1 + tol), i.e. would leave zero in the
+    next solve.  Used by the refinement study beside the paper's
+    emission-detected rule."""
+    coarse = np.where(h > h_min * (1.0 + 1e-9))[0]
+    mark = np.zeros(l.shape[0], bool)
+    if coarse.size == 0:
+        return mark
+    res = np.asarray(V, np.complex128) - op.forward(image)
+    q = h[coarse] / 4.0
+    cl = np.concatenate([l[coarse] - q, l[coarse] + q, l[coarse] - q, l[coarse] + q])
+    cm = np.concatenate([m[coarse] - q, m[coarse] - q, m[coarse] + q, m[coarse] + q])
+    ch = np.concatenate([h[coarse] / 2.0] * 4)
+    fine = ch <= h_min * (1.0 + 1e-9)
+    cs = np.where(fine, 0.0, sigma_factor * ch)
+    ck = np.where(fine, O.PIX_DELTA, O.PIX_GAUSS_WIDE).astype(np.uint8)
+    G = O.adjoint(problem_of(cl, cm, cs, ck), res)
+    mark[coarse] = (G.reshape(4, -1) > lam * (1.0 + tol)).any(axis=0)
+    return mark
 
 
 def quadtree_solve(problem_of, V, lam: float, n0: int, half: float, levels: int, iters: int,
