@@ -513,6 +513,25 @@ sl1m_status sl1m_server_destroy(sl1m_server* server);
 sl1m_status sl1m_issue_scratch_bytes(size_t* bytes);
 sl1m_status sl1m_issue_rates(void* scratch, size_t scratch_bytes, double* rates, void* stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, e.g. tight serving loops or harnesses that forbid it): the
+ * forward operator of sl1m_forward for one problem, with the plan built in
+ * a library-owned device scratch of SL1M_NOALLOC_SCRATCH_BYTES per device
+ * (a static array each GPU holds until the process ends) instead of a
+ * caller workspace.  problem, x, vis as for sl1m_plan_create and
+ * sl1m_forward (the result is the same as theirs, bit for bit).  Allocates
+ * no device memory; plans, runs and synchronises `stream` before returning.
+ * SL1M_ENOMEM when sl1m_plan_workspace_bytes(problem) exceeds the scratch
+ * (e.g. 65,536 pixels x 97,536 visibilities); other errors as
+ * sl1m_plan_create / sl1m_forward.  Every call on a GPU reuses that GPU's
+ * scratch and overwrites the last call's contents, so two calls that
+ * overlapped on one GPU would race: the library serialises the calls of a
+ * process (a lock held until the call's kernels have finished), and each
+ * process holds its own copy of the scratch. */
+#define SL1M_NOALLOC_SCRATCH_BYTES (64u << 20)
+sl1m_status sl1m_forward_noalloc(const sl1m_problem* problem, const void* x, void* vis,
+                                 void* stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char* sl1m_last_error(void);
 

@@ -8,7 +8,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsl1m.so")
-SOURCES = ["sl1m_api.hip", "sl1m_kernels.hip", "sl1m_grid.hip", "sl1m_mfma.hip", "sl1m_issue.hip", "sl1m_server.hip"]
+SOURCES = ["sl1m_api.hip", "sl1m_kernels.hip", "sl1m_grid.hip", "sl1m_mfma.hip", "sl1m_issue.hip", "sl1m_server.hip",
+           "sl1m_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
