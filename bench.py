@@ -186,7 +186,9 @@ def ingest_counters(fetch_csv, write_csv, bench_log=None):
                          ("k_grid_fwd_delta_pairs", "k_grid_fwd_delta_pairs"),
                          ("k_grid_adj_delta_square", "k_grid_adj_delta_square"),
                          ("k_grid_fwd_delta", "k_grid_fwd_delta("),
-                         ("k_grid_adj_delta", "k_grid_adj_delta(")):
+                         ("k_grid_adj_delta", "k_grid_adj_delta("),
+                         ("k_grid_fwd_gauss_pairs", "k_grid_fwd_gauss_pairs"),
+                         ("k_grid_adj_gauss_multi", "k_grid_adj_gauss_multi")):
             vals = [v for n, v in rows if pat in n]
             if vals:
                 rec = out.setdefault(key, {"source_hash": kernel_source_hash(key)})
