@@ -453,9 +453,10 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
 
 typedef enum {
   SL1M_SERVE_FAIR = 0,         /* equal shares of each round                    */
-  SL1M_SERVE_OLDEST_FIRST = 1  /* the earliest admitted request first, small
-                                  requests expedited, a floor for the others
-                                  (default)                                     */
+  SL1M_SERVE_OLDEST_FIRST = 1  /* the earliest admitted request first (it
+                                  keeps at least 4/5 of each round), small
+                                  requests expedited in the rest, a floor for
+                                  the others (default)                          */
 } sl1m_serve_policy;
 
 /* Selects how rounds are shared from the next round on.  SL1M_EINVAL for an

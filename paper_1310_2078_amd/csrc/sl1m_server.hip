@@ -869,16 +869,23 @@ sl1m_status launch_round(sl1m_server* s) {
   // each request's share of the round.  FAIR: equal shares with a floor so
   // that a crowded round still moves every request by a useful amount.
   // OLDEST_FIRST: the earliest admitted request takes the whole budget (act
-  // is in admission order), small requests (at most 128 budgets of work in
-  // total) a quarter of it, the others a floor of budget/1024 (close to
+  // is in admission order); the small requests (at most 128 budgets of work
+  // in total) share a quarter of it between them, so that however many of
+  // them run alongside, the oldest keeps at least four fifths of each round;
+  // the other large ones get a floor of budget/1024 (close to
   // first-come-first-served among the large ones).
   const double fair = std::max(s->budget / static_cast<double>(act.size()), s->budget / 32.0);
+  auto is_small = [&](const sched::Request* r) {
+    const sched::Shape& sh = r->shape;
+    return sh.evals_per_op * (2.0 * (sh.power_iters + sh.max_iter) + 1.0) <= 128.0 * s->budget;
+  };
+  int n_small = 0;
+  for (size_t i = 1; i < act.size(); ++i) n_small += is_small(act[i]) ? 1 : 0;
+  const double small_share =
+      std::max(s->budget / 1024.0, s->budget / 4.0 / static_cast<double>(std::max(n_small, 1)));
   for (size_t i = 0; i < act.size(); ++i) {
-    const sched::Shape& sh = act[i]->shape;
-    const double total = sh.evals_per_op * (2.0 * (sh.power_iters + sh.max_iter) + 1.0);
     if (s->policy == SL1M_SERVE_OLDEST_FIRST)
-      act[i]->share = i == 0 ? s->budget : total <= 128.0 * s->budget ? s->budget / 4.0
-                                                                       : s->budget / 1024.0;
+      act[i]->share = i == 0 ? s->budget : is_small(act[i]) ? small_share : s->budget / 1024.0;
     else
       act[i]->share = fair;
   }
