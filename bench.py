@@ -104,19 +104,32 @@ def kernel_source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-# Inner-loop instruction mix of the kernels that can dominate the iteration
-# (counted in their gfx950 assembly): entries per wavefront unit of work, then
-# FP32-rate (FP32 arithmetic, bit operations, integer), FP64 and sin/cos
-# wave64 instructions per unit.  The pair adjoint's unit is a wavefront and a
-# visibility (64 lanes x 32 entries), the pair forward's a wavefront and a
-# (pair record, visibility) (64 lanes x 8 entries, with the per-|l| phasors
-# spread over the 8 records), the direct kernels' a wavefront and an entry.
+# Inner-loop instruction mix of the grid kernels (counted in their gfx950
+# assembly): entries per wavefront unit of work, then FP32-rate (FP32
+# arithmetic, bit operations, integer), FP64, sin/cos and exp2 wave64
+# instructions per unit.  Units: the pair adjoints' a wavefront and a
+# visibility (64 lanes x 32 entries); the delta pair forward's a wavefront
+# and a (pair record, visibility) (64 lanes x 8 entries, with the per-|l|
+# phasors spread over the 8 records); the Gaussian pair forward's a wavefront
+# and an |l| value (64 lanes x 8 pair records x 8 entries); the direct
+# kernels' a wavefront and an entry.
 SLOT_MIX = {
-    "k_grid_adj_delta_square": (2048, 76, 6, 12),
-    "k_grid_fwd_delta_pairs": (512, 21.25, 1.25, 2.5),
-    "k_adj_delta<float,4>": (64, 3, 3, 2),
-    "k_fwd_delta<float,4>": (64, 3, 3, 2),
+    "k_grid_adj_delta_square": (2048, 76, 6, 12, 0),
+    "k_grid_fwd_delta_pairs": (512, 21.25, 1.25, 2.5, 0),
+    "k_grid_adj_gauss_multi": (2048, 174, 10, 12, 4),
+    "k_grid_fwd_gauss_pairs": (4096, 319, 18, 20, 4),
+    "k_adj_delta<float,4>": (64, 3, 3, 2, 0),
+    "k_fwd_delta<float,4>": (64, 3, 3, 2, 0),
 }
+
+
+def slot_model_s(name, evals, rates, cus):
+    """Issue-slot time of `evals` entries of kernel `name` at the measured
+    per-CU issue rates."""
+    per_unit, n32, n64, ntr, nexp = SLOT_MIX[name]
+    return (evals / per_unit) / cus * (n32 / rates["fp32_fma"] + n64 / rates["fp64_fma"]
+                                       + ntr / rates["sin_cos"] + nexp / rates["exp"])
+
 
 HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E, published
 
@@ -333,6 +346,45 @@ def extras(plan2, wl2, dev, c4):
         "evals_per_s": rate_s, "rate_vs_full_config4": rate_s / rate4}
     ps.close()
     del ps, Vs, gsh, x4
+    # warm starts on config 4 (Section "Acceleration strategies"): relative
+    # objective gap after k iterations from a zero image, from the dirty
+    # image, and coarse-to-fine (the 512^2 delta grid with the same Gaussian
+    # layers solved for 50 iterations, upscaled to the 1024^2 grid), with F*
+    # from a 200-iteration cold solve; seconds include every level
+    from paper_1310_2078_amd import coarse as CF
+    p4 = sl1m.Plan.from_workload(wl4, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, ref4 = p4.solve(V4d, wl4.lam, 200, L=0.0, power_iters=wl4.power_iters)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    L4 = ref4["L"]
+    D4 = p4.dirty_image(V4d)
+    gk = wl4.kind != 0
+    extra = (wl4.l[gk], wl4.m[gk], wl4.sigma[gk], wl4.kind[gk])
+    ws = {}
+    for k in (10, 30, 100):
+        rec = {}
+        for label, x0 in (("cold", None), ("dirty_start", D4)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, inf = p4.solve(V4d, wl4.lam, k, L=L4, x0=x0)
+            torch.cuda.synchronize()
+            rec[label] = {"gap": (inf["F"] - ref4["F"]) / ref4["F"],
+                          "seconds": time.perf_counter() - t0}
+        t0 = time.perf_counter()
+        lv = CF.coarse_to_fine(1024, 0.35, 2, wl4.u, wl4.v, wl4.w, V4d, wl4.lam, [50, k],
+                               power_iters=wl4.power_iters, extra=extra, device=dev,
+                               ant_p=wl4.ant_p, ant_q=wl4.ant_q, ant_gain=wl4.ant_gain,
+                               ant_fwhm=wl4.ant_fwhm, L_per_level=[0.0, L4])
+        rec["coarse_to_fine"] = {"gap": (lv[-1].info["F"] - ref4["F"]) / ref4["F"],
+                                 "seconds": time.perf_counter() - t0,
+                                 "coarse_level_seconds": lv[0].seconds}
+        ws[str(k)] = rec
+    ex["config4_warm_starts"] = {"F_star_200_iterations": ref4["F"], "F_star_seconds": t_ref,
+                                 "after_k_iterations": ws}
+    p4.close()
+    del p4, D4
     # adaptive quad-tree refinement (Section "Acceleration strategies"): 32 x 32
     # cells over the field, six levels down to the 1024^2 grid's spacing, 100
     # iterations per level, against the full 1024^2 delta grid solved with the
@@ -544,15 +596,15 @@ def headline(args, dev):
         "effective_flop_per_eval": canonical,
         "effective_tflops": canonical * dom_evals / (dom_ms * 1e-3) / 1e12,
     }
+    rates = sl1m.issue_rates(dev)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
     if dom_name in SLOT_MIX:
-        rates = sl1m.issue_rates(dev)
-        cus = torch.cuda.get_device_properties(dev).multi_processor_count
-        per_unit, n32, n64, ntr = SLOT_MIX[dom_name]
-        t_model = (dom_evals / per_unit) / cus * (
-            n32 / rates["fp32_fma"] + n64 / rates["fp64_fma"] + ntr / rates["sin_cos"])
+        per_unit, n32, n64, ntr, nexp = SLOT_MIX[dom_name]
+        t_model = slot_model_s(dom_name, dom_evals, rates, cus)
         roof["slots"] = {
             "unit": "wave64 instructions per s per CU", "rates": rates, "cus": cus,
-            "mix_per_unit": {"entries": per_unit, "fp32_rate": n32, "fp64": n64, "sin_cos": ntr},
+            "mix_per_unit": {"entries": per_unit, "fp32_rate": n32, "fp64": n64, "sin_cos": ntr,
+                             "exp": nexp},
             "model_ms": t_model * 1e3, "frac": t_model * 1e3 / dom_ms}
     out = {
         "metric": "pixel x visibility evals/s (forward + adjoint) of the L1 solve on config 4; "
@@ -607,6 +659,16 @@ def headline(args, dev):
         },
         "roofline": roof,
     }
+    # every grid kernel against its issue-slot model (per launch)
+    pairs = bool(pinfo["grid_pairs"])
+    slot = {}
+    for name, key, ev in (("k_grid_fwd_delta_pairs", "grid_fwd_delta", n_delta * n_vis),
+                          ("k_grid_adj_delta_square", "grid_adj_delta", n_delta * n_vis),
+                          ("k_grid_adj_gauss_multi", "grid_adj_gauss", n_gauss * n_vis),
+                          ("k_grid_fwd_gauss_pairs", "grid_fwd_gauss", n_gauss * n_vis / n_layers)):
+        if pairs and avg.get(key) and name in SLOT_MIX:
+            slot[name] = slot_model_s(name, ev, rates, cus) * 1e3 / avg[key]
+    out["kernels"]["slot_frac"] = slot
     ctx = {"wl": wl4, "plan": plan, "data": V, "extended_data": V_ext,
            "evals_per_s": evals / elapsed}
     return out, ctx
@@ -645,9 +707,7 @@ def config2_secondary(dev, steps=20):
     if avg["grid_adj_delta"] and name in SLOT_MIX:
         rates = sl1m.issue_rates(dev)
         cus = torch.cuda.get_device_properties(dev).multi_processor_count
-        per_unit, n32, n64, ntr = SLOT_MIX[name]
-        t_model = (wl.n_pix * wl.n_vis / per_unit) / cus * (
-            n32 / rates["fp32_fma"] + n64 / rates["fp64_fma"] + ntr / rates["sin_cos"])
+        t_model = slot_model_s(name, wl.n_pix * wl.n_vis, rates, cus)
         out["adjoint_slot_frac"] = t_model * 1e3 / avg["grid_adj_delta"]
         out["adjoint_executed_frac"] = (EXEC_FLOP_PER_EVAL[name] * wl.n_pix * wl.n_vis
                                         / (avg["grid_adj_delta"] * 1e-3) / 1e12

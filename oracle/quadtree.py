@@ -24,6 +24,9 @@ every level.  Reading R17 fixes what the paper leaves open:
 * the next level starts from the previous image with a refined cell's value
   split equally among its children (flux conservation of the coarse-to-fine
   upscaling).
+
+`certificate_split` (an extra refinement rule used only by the study in
+`quadtree_study.py`, never compared with the GPU library) is parity unpinned.
 """
 from __future__ import annotations
 

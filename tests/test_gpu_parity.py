@@ -512,3 +512,44 @@ def test_solve_stops_on_nonzero_count():
         assert info["iters"] == ref.iters and err <= 1e-10
     _, off = plan.solve(V, wl.lam, 40, L=L, check_every=5)
     assert off["iters"] == 40 and off["converged"] == 0
+
+
+def test_config4_solve_against_oracle_checked_fp64_plan():
+    """Config 4 at full size (1,392,640 pixels x 409,600 visibilities, gains
+    and beams) in the benchmark's launch configuration: 5 FISTA iterations
+    of the FP32 grid-evaluated plan against the same iterations on an FP64
+    plan (direct evaluation), within 1e-4 of the peak, with the FP64 plan's
+    forward and adjoint first checked against the oracle on sampled outputs
+    (1e-11 norm-relative and the FP64 element-wise bound)."""
+    wl = W.config4()
+    say(f"[case] config4 solve FP32 grid vs FP64 plan n_pix={wl.n_pix} n_vis={wl.n_vis}")
+    p64 = sl1m.Plan.from_workload(wl, precision="fp64")
+    p = O.Problem.from_workload(wl)
+    x, r = _rand(23, wl.n_pix, wl.n_vis)
+    ks = np.arange(0, wl.n_vis, 8191)
+    js = np.concatenate([np.arange(0, 1024 * 1024, 20011), np.arange(1024 * 1024, wl.n_pix, 4001)])
+    Vs = p64.forward(x).cpu().numpy()[ks]
+    gs = p64.adjoint(r).cpu().numpy()[js]
+    Vo, go = O.forward_rows(p, x, ks), O.adjoint_cols(p, r, js)
+    ef, ea = rel(Vs, Vo), rel(gs, go)
+    wf = E.worst_ratio(Vs, Vo, E.abs_forward_rows(p, x, ks), wl.n_pix, "fp64")
+    wa = E.worst_ratio(gs, go, E.abs_adjoint_cols(p, r, js), wl.n_vis, "fp64")
+    say(f"    FP64 plan vs oracle sampled forward {ef:.3e} adjoint {ea:.3e} "
+        f"element-wise {wf:.3e} {wa:.3e}")
+    assert ef <= 1e-11 and ea <= 1e-11 and wf <= 1.0 and wa <= 1.0
+    V = p64.forward(wl.x_true) + torch.as_tensor(wl.noise, dtype=torch.complex128,
+                                                 device=p64.device)
+    L = 1.01 * p64.estimate_L(5, seed=0)
+    img64, info64 = p64.solve(V, wl.lam, 5, L=L)
+    img64 = img64.cpu().numpy()
+    p64.close()
+    p32 = sl1m.Plan.from_workload(wl)
+    assert p32.info()["grid"] == 4
+    img32, info32 = p32.solve(V.to(torch.complex64), wl.lam, 5, L=L)
+    img32 = img32.cpu().numpy()
+    peak = float(np.max(img64))
+    err = float(np.max(np.abs(img32 - img64))) / peak
+    say(f"    image err/peak {err:.3e}  F fp32 {info32['F']:.9g} fp64 {info64['F']:.9g}  "
+        f"nnz {info32['nnz']} {info64['nnz']}")
+    assert err <= 1e-4
+    assert abs(info32["F"] - info64["F"]) <= 1e-4 * info64["F"]
