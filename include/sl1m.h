@@ -464,7 +464,9 @@ typedef enum {
 sl1m_status sl1m_server_set_policy(sl1m_server* server, int32_t policy);
 
 /* Queue one solve.  problem: as for sl1m_plan_create (FP32, max_rhs <= 1); its
- * arrays must stay valid until the request is admitted.  vis: complex64
+ * arrays must stay valid until the request is admitted; its tile_blocks sets
+ * the request's work-item split (0: 2048, the best of a sweep on a saturated
+ * stream of mixed requests).  vis: complex64
  * [n_vis] data and img_out: float32 [n_pix] result, both device pointers valid
  * until the request is done.  Non-blocking apart from reading the problem's
  * grouping arrays (see sl1m_plan_workspace_bytes).  *ticket identifies the

@@ -34,7 +34,7 @@ constexpr int kSrvRing = 4;              // rounds in flight (table buffers)
 // one, the others in the second.  Lanes share no request, so their launches
 // may overlap: the tail of one lane's kernel is filled by the other's blocks.
 constexpr int kSrvLanes = 2;
-constexpr int kSrvTileBlocks = 8192;     // per-request operator split target (work-item count)
+constexpr int kSrvTileBlocks = 2048;     // per-request operator split target (work-item count)
 // item tables per round: 4 operator kinds x 6 variants (4 direct tile shapes,
 // the grid evaluation, the square-grid evaluation), then reduce, update, final
 // and the grid prep (delta, Gaussian).  Square grid requests use the

@@ -119,7 +119,7 @@ def test_admission_by_footprint():
     rng = np.random.default_rng(0)
     V1 = 10 * (rng.standard_normal(wl.n_vis) + 1j * rng.standard_normal(wl.n_vis))
     V2 = 10 * (rng.standard_normal(wl.n_vis) + 1j * rng.standard_normal(wl.n_vis))
-    probe = sl1m.Plan.from_workload(wl, tile_blocks=8192)
+    probe = sl1m.Plan.from_workload(wl, tile_blocks=2048)
     fp = probe.workspace_bytes + 4 * wl.n_pix + 8 * (wl.n_vis // 256 + 2 * wl.n_pix // 256 + 8) + 4096
     probe.close()
     a1, _ = _alone(wl, V1, L=0.0)
