@@ -230,6 +230,41 @@ def _time_ops(plan, fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
+def multi_rhs_table(wl2, dev, reps: int = 5):
+    """1, 2, 4 and 8 right-hand sides (the paper's polarisations, or stacked
+    iterates) through one plan at config 2's shape: the FP32 grid plan
+    against the float16 and bfloat16 matrix-core plans, forward and adjoint
+    times and side-products per second (2 R N_p N_v per operator pair)."""
+    import torch
+    from paper_1310_2078_amd import sl1m
+    ev = wl2.n_pix * wl2.n_vis
+    out = {}
+    for R in (1, 2, 4, 8):
+        X = torch.as_tensor(np.random.default_rng(5).standard_normal((R, wl2.n_pix)),
+                            dtype=torch.float32, device=dev)
+        for label, kw in (("fp32_grid", {}), ("mfma_f16", {"precision": "mfma_f16"}),
+                          ("mfma_bf16", {"precision": "mfma_bf16"})):
+            pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=R, **kw)
+            if R == 1:
+                Vm = pm.forward(X[0])
+                G = torch.empty(wl2.n_pix, dtype=torch.float32, device=dev)
+                tf = _time_ops(pm, lambda: pm.forward(X[0], out=Vm), reps)
+                ta = _time_ops(pm, lambda: pm.adjoint(Vm, out=G), reps)
+            else:
+                Vm = pm.forward_multi(X)
+                G = torch.empty((R, wl2.n_pix), dtype=torch.float32, device=dev)
+                tf = _time_ops(pm, lambda: pm.forward_multi(X, out=Vm), reps)
+                ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), reps)
+            out[f"R{R}_{label}"] = {"forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+                                    "side_products_per_s": 2 * R * ev / (tf + ta),
+                                    "grid_mfma": pm.info()["grid_mfma"]}
+            print(f"[bench] multi-RHS R={R} {label}: {out[f'R{R}_{label}']}", file=sys.stderr,
+                  flush=True)
+            pm.close()
+            del pm, Vm, G
+    return out
+
+
 def extras(plan2, wl2, dev, c4):
     """More workloads (`--extras`), reported beside the headline line (not in
     `value`): direct evaluation, warm starts, MFISTA, several right-hand
@@ -281,53 +316,9 @@ def extras(plan2, wl2, dev, c4):
     t_m = (time.perf_counter() - t0) / 50
     ex["config2_mfista"] = {"relative_gap": mf, "ms_per_iteration": t_m * 1e3}
     del V2, D
-    # multi-RHS: 4 right-hand sides (Stokes I, Q, U, V) at config 2's shape
-    rng = np.random.default_rng(5)
-    X = torch.as_tensor(rng.standard_normal((4, wl2.n_pix)), dtype=torch.float32, device=dev)
-    ev = wl2.n_pix * wl2.n_vis
-    for grid in ("auto", "off"):
-        pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=4, grid=grid)
-        Vm = pm.forward_multi(X)
-        tf = _time_ops(pm, lambda: pm.forward_multi(X, out=Vm), 5)
-        G = torch.empty((4, wl2.n_pix), dtype=torch.float32, device=dev)
-        ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), 5)
-        rec = {"evaluation": "grid" if pm.info()["grid_multi"] >= 4 else "direct",
-               "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
-               "phasor_evals_per_s": 2 * ev / (tf + ta),
-               "rhs_products_per_s": 8 * ev / (tf + ta)}
-        ex["config2_shape_multi_rhs4" if grid == "auto" else
-           "config2_shape_multi_rhs4_direct"] = rec
-        pm.close()
-        del pm, Vm, G
-    # eight sides: grid evaluation (FP32) against the matrix cores (FP16)
-    X8 = torch.as_tensor(np.random.default_rng(8).standard_normal((8, wl2.n_pix)),
-                         dtype=torch.float32, device=dev)
-    rec8 = {}
-    for label, kw in (("grid", {}), ("mfma_f16", {"precision": "mfma_f16"})):
-        pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=8, **kw)
-        Vm = pm.forward_multi(X8)
-        tf = _time_ops(pm, lambda: pm.forward_multi(X8, out=Vm), 5)
-        G = torch.empty((8, wl2.n_pix), dtype=torch.float32, device=dev)
-        ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), 5)
-        rec8[label] = {"forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
-                       "rhs_products_per_s": 16 * ev / (tf + ta)}
-        pm.close()
-        del pm, Vm, G
-    ex["config2_shape_multi_rhs8"] = rec8
-    del X8
-    # the same four sides on the matrix cores (float16 / bfloat16 operands)
-    for prec in ("mfma_f16", "mfma_bf16"):
-        pm = sl1m.Plan.from_workload(wl2, device=dev, max_rhs=4, precision=prec)
-        Vm = pm.forward_multi(X)
-        tf = _time_ops(pm, lambda: pm.forward_multi(X, out=Vm), 5)
-        G = torch.empty((4, wl2.n_pix), dtype=torch.float32, device=dev)
-        ta = _time_ops(pm, lambda: pm.adjoint_multi(Vm, out=G), 5)
-        ex[f"config2_shape_multi_rhs4_{prec}"] = {
-            "evaluation": "direct, MFMA 4x4x4", "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
-            "phasor_evals_per_s": 2 * ev / (tf + ta), "rhs_products_per_s": 8 * ev / (tf + ta)}
-        pm.close()
-        del pm, Vm, G
-    del X
+    # several right-hand sides at config 2's shape: FP32 grid evaluation
+    # against the matrix-core plans (float16, bfloat16)
+    ex["config2_shape_multi_rhs"] = multi_rhs_table(wl2, dev)
     # config 4 (the headline workload): one GPU's share of it split over 8
     # GPUs by visibilities (every 8th record, all pixels: the grid evaluation
     # keeps its square pixel grid)
@@ -754,6 +745,9 @@ def main():
     ap.add_argument("--extras", action="store_true",
                     help="also run the secondary workloads (direct evaluation, warm starts, "
                          "MFISTA, several right-hand sides, quad-tree, FP64 config 1)")
+    ap.add_argument("--multi-rhs-only", action="store_true",
+                    help="only the several-right-hand-sides table at config 2's shape "
+                         "(FP32 grid against the matrix-core plans), as one JSON line")
     ap.add_argument("--tune", action="store_true",
                     help="tune the headline plan's launch shapes (sl1m_tune) first")
     ap.add_argument("--calib-copy", action="store_true",
@@ -781,6 +775,11 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.multi_rhs_only:
+        from paper_1310_2078_amd import workloads as W
+        print(json.dumps({"config2_shape_multi_rhs": multi_rhs_table(W.config2(), dev)}),
+              flush=True)
+        return
     out, c4 = headline(args, dev)
     c4.pop("plan").close()
     if args.calib_copy:

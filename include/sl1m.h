@@ -251,7 +251,9 @@ typedef struct {
   int32_t grid_multi;       /* multi-RHS calls of 2, 4 (and 8) sides up to
                                this count evaluate on the grid (every grid
                                segment a square delta grid); 0: direct        */
-  int32_t reserved[3];
+  int32_t grid_mfma;        /* matrix-core plan whose forward runs on the grid
+                               evaluation (all pixels one square delta grid) */
+  int32_t reserved[2];
 } sl1m_plan_info;
 
 sl1m_status sl1m_plan_query(const sl1m_plan* plan, sl1m_plan_info* info);

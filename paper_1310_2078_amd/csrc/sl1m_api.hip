@@ -35,6 +35,7 @@ struct Analysis {
   std::vector<Chunk> fd, fg, pd, pg;
   int64_t kchunk = 0;
   int n_achunks = 0;
+  bool grid_mfma = false;     // matrix-core plan on one square delta grid (forward)
   int n_mfchunks = 0;         // matrix-core plans: forward chunks of mf_chunk pixels
   int64_t mf_chunk = 0, mf_np4 = 0, mf_nv4 = 0;
   // grid evaluation: segments on the grid path, their concatenated tables,
@@ -77,7 +78,7 @@ size_t visrecG_bytes(size_t rb) {
 bool analyze_grid(Analysis& a, int si, const std::vector<double>& L, const std::vector<double>& M,
                   std::string& why) {
   const Segment& sg = a.segs[si];
-  if (a.precision != SL1M_PREC_FP32) return why = "the plan is float64", false;
+  if (a.precision == SL1M_PREC_FP64) return why = "the plan is float64", false;
   if (a.beam_pair) return why = "the plan has per-pair beams", false;
   if (sg.count < 1024) return why = "fewer than 1024 pixels in the segment", false;
   const int64_t nd = sg.count;
@@ -314,11 +315,11 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   a.grid = false;
   if (pr->grid_mode != SL1M_GRID_OFF && nv > 0 && np > 0) {
     std::string why = "no segment has 1024 pixels";
-    if (a.precision != SL1M_PREC_FP32) why = "the plan's precision is not SL1M_PREC_FP32";
+    if (a.precision == SL1M_PREC_FP64) why = "the plan's precision is SL1M_PREC_FP64";
     else if (a.beam_pair) why = "the plan has per-pair beams";
     bool any_big = false;
     for (const Segment& sg : a.segs) any_big = any_big || sg.count >= 1024;
-    if (any_big && a.precision == SL1M_PREC_FP32 && !a.beam_pair) {
+    if (any_big && a.precision != SL1M_PREC_FP64 && !a.beam_pair) {
       std::vector<double> L(np), M(np);
       if (sl1m_status e = d2h(L.data(), pr->l, np * sizeof(double), "read l")) return e;
       if (sl1m_status e = d2h(M.data(), pr->m, np * sizeof(double), "read m")) return e;
@@ -417,6 +418,12 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     }
   }
 
+  // matrix-core plans evaluate the forward on the grid when all their pixels
+  // form one square delta grid (the adjoint stays on the direct evaluation)
+  a.grid_mfma = mfma && a.grid && a.gsegs.size() == 1 && a.gsegs[0].square &&
+                a.gsegs[0].kind == SL1M_PIX_DELTA && a.fd1.empty() && a.fg1.empty() &&
+                a.pd1.empty() && a.pg1.empty();
+
   // ---- visibility chunks of the adjoint (shared by all of its kernels)
   // The launches of one adjoint run one after another, so besides the plan's
   // block target every launch should have enough blocks of its own: the
@@ -458,6 +465,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   // of 4 x 4 x 4 blocks, fwd_vpl visibilities / adj_ppl pixels per lane;
   // chunks that give each launch kMinLaunchBlocks blocks
   if (mfma) {
+    const int64_t grid_kchunk = a.kchunk;
     // lanes per thread: two entries per scalar record load measured best at
     // config 2's shape for 1 to 4 sides, four pixels per lane for 8 sides'
     // adjoint (float16, 65,536 x 97,536)
@@ -476,10 +484,16 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
       const int64_t nf = std::max<int64_t>(1, std::min<int64_t>(np32 / 32, (kMinLaunchBlocks + vt - 1) / vt));
       a.mf_chunk = up32((np32 + nf - 1) / nf);
       a.n_mfchunks = static_cast<int>((np32 + a.mf_chunk - 1) / a.mf_chunk);
-      const int64_t pt = (np + kBlock * a.adj_ppl - 1) / (kBlock * a.adj_ppl);
-      const int64_t na = std::max<int64_t>(
-          1, std::min<int64_t>({256, nv32 / 32, (kMinLaunchBlocks + pt - 1) / pt}));
-      a.kchunk = up32((nv32 + na - 1) / na);
+      if (a.grid_mfma && grid_kchunk > 0) {
+        // the grid evaluation's visibility chunks (its FP32 adjoint serves up
+        // to 4 sides), rounded to the matrix-core adjoint's 32-visibility steps
+        a.kchunk = up32(grid_kchunk);
+      } else {
+        const int64_t pt = (np + kBlock * a.adj_ppl - 1) / (kBlock * a.adj_ppl);
+        const int64_t na = std::max<int64_t>(
+            1, std::min<int64_t>({256, nv32 / 32, (kMinLaunchBlocks + pt - 1) / pt}));
+        a.kchunk = up32((nv32 + na - 1) / na);
+      }
       a.n_achunks = static_cast<int>((nv32 + a.kchunk - 1) / a.kchunk);
     }
   }
@@ -491,7 +505,7 @@ struct Layout {
       rres, rpol, layerDs, chunks, fpart, apart, xperm, img, zbuf, res, red, red_out, flag, scal,
       grid_la,
       grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb,
-      grid_prec, grid_precm, mx, mr, mred, total;
+      grid_prec, grid_precm, mx, mr, mred, grid_mfma_b, grid_mfma_nu, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -562,6 +576,9 @@ Layout layout(const Analysis& a) {
   L.mx = take(2 * 16 * ngm * static_cast<size_t>(a.mf_np4));
   L.mr = take(2 * 32 * ngm * static_cast<size_t>(a.mf_nv4));
   L.mred = take(ngm ? sizeof(float) * (2 * 256 + 4) : 0);
+  const size_t pairs = static_cast<size_t>(a.grid_pairs);
+  L.grid_mfma_b = take(a.grid_mfma ? 64 * ngm * pairs : 0);
+  L.grid_mfma_nu = take(a.grid_mfma ? 8 * pairs : 0);
   L.total = off;
   return L;
 }
@@ -821,6 +838,11 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       p->mx = reinterpret_cast<uint16_t*>(w + L.mx);
       p->mr = reinterpret_cast<uint16_t*>(w + L.mr);
       p->mred = reinterpret_cast<float*>(w + L.mred);
+    }
+    p->grid_mfma = a.grid_mfma;
+    if (a.grid_mfma) {
+      p->grid_mfma_b = w + L.grid_mfma_b;
+      p->grid_mfma_nu = reinterpret_cast<double*>(w + L.grid_mfma_nu);
     }
     if (a.grid) {
       p->grid_la = reinterpret_cast<double*>(w + L.grid_la);
@@ -1156,6 +1178,7 @@ sl1m_status sl1m_plan_query(const sl1m_plan* p, sl1m_plan_info* info) {
   r.n_achunks = p->n_achunks;
   for (const GridSeg& g : p->grid_segs) r.grid_pairs += g.square ? 1 : 0;
   r.grid_multi = p->grid_multi;
+  r.grid_mfma = p->grid_mfma ? 1 : 0;
   *info = r;
   return SL1M_OK;
 }

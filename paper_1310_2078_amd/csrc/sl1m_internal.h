@@ -212,6 +212,12 @@ struct sl1m_plan {
   uint16_t* mx = nullptr;     // packed images [NG][np4][4 sides][4 pixels]
   uint16_t* mr = nullptr;     // packed residuals [NG][nv4][4 sides][re, -im][4 visibilities]
   float* mred = nullptr;      // block maxima [2][256], then inverse scales [2]
+  // matrix-core plans whose pixels are one square delta grid: the forward on
+  // the grid evaluation (per-call packed amplitude combinations of every pair
+  // [NG][n_pairs][4 sides][8 words], each pair's nu)
+  bool grid_mfma = false;
+  void* grid_mfma_b = nullptr;
+  double* grid_mfma_nu = nullptr;
 
   // grid evaluation (single right-hand side, FP32): segments on the grid path
   // and the direct chunks of the other segments

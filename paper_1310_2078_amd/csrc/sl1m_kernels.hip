@@ -671,9 +671,29 @@ hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, int nr, hipStrea
   return SL1M_DISPATCH_R(p, gather_t, p, x, xp, nr, st);
 }
 
+// A matrix-core plan whose pixels form one square delta grid has both
+// evaluations at hand and takes, per side count, the faster of the two as
+// measured at config 2's shape (65,536 pixels x 97,536 visibilities, ms;
+// FP32 grid / float16 / bfloat16 matrix cores):
+//   forward  4 sides 1.31 / 1.18 / 1.47,  8 sides 2.57 / 1.49 / 1.84
+//   adjoint  8 sides 2.79 / 2.42 / 4.88
+// so float16 plans use the matrix-core grid forward from 4 sides and the
+// matrix-core adjoint at 8, bfloat16 plans the matrix-core forward at 8 only;
+// everything else runs the FP32 grid evaluation (the more accurate one).
+static bool mfma_forward_call(const sl1m_plan* p, int nr) {
+  if (!p->mfma) return false;
+  if (!p->grid_mfma) return true;
+  return nr >= (p->mfma == SL1M_PREC_MFMA_F16 ? 4 : 8);
+}
+static bool mfma_adjoint_call(const sl1m_plan* p, int nr) {
+  if (!p->mfma) return false;
+  if (!p->grid_mfma) return true;
+  return p->mfma == SL1M_PREC_MFMA_F16 && nr >= 8;
+}
+
 template <typename R>
 static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
-  if (p->mfma) return launch_mfma_forward(p, xp, nr, st);
+  if (mfma_forward_call(p, nr)) return launch_mfma_forward(p, xp, nr, st);
   if (p->n_vis == 0 || p->n_fchunks == 0) return hipSuccess;
   const bool bm = p->beam_pair;
   if (nr == 1 && p->grid) {
@@ -720,7 +740,7 @@ hipError_t launch_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st) 
 }
 
 int forward_rows(const sl1m_plan* p, int nr) {
-  if (p->mfma) return p->n_mfchunks;
+  if (p->mfma) return p->grid_mfma ? p->grid_frows : p->n_mfchunks;
   if ((nr == 1 && p->grid) || grid_multi_ok(p, nr))
     return static_cast<int>(p->grid_frows + p->fd1.size() + p->fg1.size());
   return p->n_fchunks;
@@ -758,7 +778,7 @@ hipError_t launch_adjoint_prep(sl1m_plan* p, const void* r, int nr, hipStream_t 
 
 template <typename R>
 static hipError_t adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
-  if (p->mfma) return launch_mfma_adjoint(p, nr, st);
+  if (mfma_adjoint_call(p, nr)) return launch_mfma_adjoint(p, nr, st);
   if (p->n_pix == 0 || p->n_achunks == 0) return hipSuccess;
   const bool bm = p->beam_pair;
   if (nr == 1 && p->grid) {

@@ -26,7 +26,7 @@
 // those of the direct kernels: forward [side][chunk][n_vis] complex (pixel
 // amplitudes inside), adjoint [side][chunk][n_pix] (amplitudes applied by
 // the reduction).
-#include "sl1m_device.h"
+#include "sl1m_grid.h"
 
 namespace sl1m {
 
@@ -360,6 +360,144 @@ __global__ __launch_bounds__(kBlock) void k_adj_mfma(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Square delta grids on the matrix cores (forward).  The grid evaluation of
+// the FP32 kernels (sl1m_grid.h) writes the pair sum of a visibility as
+//   Re = cc (m1 e1 + m2 e2 + m5 f1 + m6 f2) - cs (m3 e3 + m4 e4 + m7 f3 + m8 f4)
+//   Im = -cs (m1 e1 + m2 e2 + m5 f1 + m6 f2) - cc (m3 e3 + m4 e4 + m7 f3 + m8 f4)
+// with C = (cc, cs) the pair's radius phasor, m1..m8 the eight products of
+// the A and B phasors of the cell and its mirror, and e1..e4, f1..f4 the
+// sign combinations of the pair's amplitudes (one set per side).  So with
+// the sixteen basis values b = (cc m1, cc m2, cc m5, cc m6 | -cs m3, -cs m4,
+// -cs m7, -cs m8) for Re and (-cs m1, -cs m2, -cs m5, -cs m6 | -cc m3, -cc m4,
+// -cc m7, -cc m8) for Im as A operands (the lane's visibility is its row) and
+// the per-side vectors Be = (e1, e2, f1, f2), Bo = (e3, e4, f3, f4) as B
+// operands (one per side, lane j + 4b holding side j), four 4 x 4 x 4 MFMAs
+// per pair accumulate up to four sides: the VALU forms 16 basis values per
+// pair whatever the side count, instead of 12 FP32 operations per pair and
+// side.
+// ---------------------------------------------------------------------------
+
+// Per call: the pairs' amplitude combinations, scaled by the power of two c
+// that brings 4 max|x scale| into [2^13, 2^14) (a combination adds at most
+// four amplitudes), rounded to the operand type:
+//   out[(g n_pairs + p) 4 + j] = (e1, e2, f1, f2 | e3, e4, f3, f4) of side 4g + j
+// (zero past nr), and nu of each pair into pnu.  One thread per (g, p, j).
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_grid_mfma_pack_pairs(
+    const float* __restrict__ xp, int64_t n_pix, int nr, const float* __restrict__ pscale,
+    const int32_t* __restrict__ slot, const double* __restrict__ nu, int na, int64_t n_pairs,
+    int ng, const float* __restrict__ bm, float* __restrict__ inv_out, double* __restrict__ pnu,
+    uint4* __restrict__ out) {
+  const float c = op_scale(4.0f * max_of_blocks(bm));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *inv_out = 1.0f / c;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= static_cast<int64_t>(ng) * n_pairs * 4) return;
+  const int j = static_cast<int>(t & 3);
+  const int64_t p = (t >> 2) % n_pairs;
+  const int g = static_cast<int>((t >> 2) / n_pairs);
+  const int r = 4 * g + j;
+  float e[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (r < nr) {
+    const PairSlots ps = grid_pair_slots(p, na, slot, xp + r * n_pix, pscale, c);
+    const float* x = ps.x;
+    const float* y = ps.y;
+    e[0] = (x[0] + x[1]) + (x[2] + x[3]);  // e1
+    e[1] = (x[1] + x[2]) - (x[0] + x[3]);  // e2
+    e[2] = (y[0] + y[1]) + (y[2] + y[3]);  // f1
+    e[3] = (y[1] + y[2]) - (y[0] + y[3]);  // f2
+    e[4] = (x[0] + x[1]) - (x[2] + x[3]);  // e3
+    e[5] = (x[0] - x[1]) + (x[2] - x[3]);  // e4
+    e[6] = (y[0] + y[1]) - (y[2] + y[3]);  // f3
+    e[7] = (y[0] - y[1]) + (y[2] - y[3]);  // f4
+    if (r == 0) pnu[p] = nu[ps.q];
+  }
+  uint16_t w[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) w[i] = MOp<PREC>::bits(e[i]);
+  uint4 o;
+  o.x = static_cast<uint32_t>(w[0]) | (static_cast<uint32_t>(w[1]) << 16);
+  o.y = static_cast<uint32_t>(w[2]) | (static_cast<uint32_t>(w[3]) << 16);
+  o.z = static_cast<uint32_t>(w[4]) | (static_cast<uint32_t>(w[5]) << 16);
+  o.w = static_cast<uint32_t>(w[6]) | (static_cast<uint32_t>(w[7]) << 16);
+  out[t] = o;
+}
+
+// Forward: block (visibility tile of kBlock, pair chunk blockIdx.y), one
+// visibility per lane as the lane's A row; partial row blockIdx.y of side r
+// at part + (r n_rows + y) n_vis.  Lanes past n_vis evaluate the last
+// visibility and write nothing.
+template <int PREC, int NG>
+__global__ __launch_bounds__(kBlock) void k_grid_fwd_pairs_mfma(
+    const uint4* __restrict__ bh, const double* __restrict__ pnu, int64_t n_pairs,
+    const double* __restrict__ la, const double* __restrict__ mb,
+    const GridChunk* __restrict__ chunks, int na, const double* __restrict__ vu,
+    const double* __restrict__ vv, const double* __restrict__ vw, int64_t n_vis,
+    const float* __restrict__ inv, float2* __restrict__ part, int n_rows, int nr) {
+  typedef typename MOp<PREC>::vec V;
+  const int lane = threadIdx.x & 63;
+  const int jcol = lane & 3;
+  const ConstPtr<GridChunk> cch = as_const(chunks) + blockIdx.y;
+  const int g0 = cch->g, ia0 = cch->ia0, ia1 = cch->ia1;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t kk = k < n_vis ? k : n_vis - 1;
+  const double u = vu[kk], v = vv[kk], w = vw[kk];
+  const ConstPtr<double> cla = as_const(la);
+  const ConstPtr<double> cmb = as_const(mb);
+  const ConstPtr<double> cnu = as_const(pnu);
+  const double origin = kMagic;
+  float bc[kGridNB], bs[kGridNB];  // B at |m|_b
+  float pc[kGridNB], ps[kGridNB];  // A at |l|_b (the mirror's)
+#pragma unroll
+  for (int b = 0; b < kGridNB; ++b) {
+    const double m = cmb[g0 * kGridNB + b];
+    phasor(fma(v, m, origin), bc[b], bs[b]);
+    phasor(fma(u, m, origin), pc[b], ps[b]);
+  }
+  f4_t are[NG], aim[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) are[g] = aim[g] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int ia = ia0; ia < ia1; ++ia) {
+    const double l = cla[ia];
+    float ac, as, qc, qs;  // A at |l|_ia, B at |m|_ia
+    phasor(fma(u, l, origin), ac, as);
+    phasor(fma(v, l, origin), qc, qs);
+    const int64_t p0 = pair_rec_base(g0, na) + static_cast<int64_t>(ia - kGridNB * g0) * kGridNB;
+#pragma unroll
+    for (int b = 0; b < kGridNB; ++b) {
+      float cc, cs;
+      phasor(fma(w, cnu[p0 + b], origin), cc, cs);
+      const float m1 = ac * bc[b], m2 = as * bs[b], m5 = pc[b] * qc, m6 = ps[b] * qs;
+      const float m3 = ac * bs[b], m4 = as * bc[b], m7 = pc[b] * qs, m8 = ps[b] * qc;
+      const float ncs = -cs, ncc = -cc;
+      const V a1 = pack4<PREC>(f4_t{cc * m1, cc * m2, cc * m5, cc * m6});
+      const V a2 = pack4<PREC>(f4_t{ncs * m3, ncs * m4, ncs * m7, ncs * m8});
+      const V a3 = pack4<PREC>(f4_t{ncs * m1, ncs * m2, ncs * m5, ncs * m6});
+      const V a4 = pack4<PREC>(f4_t{ncc * m3, ncc * m4, ncc * m7, ncc * m8});
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const uint4 bw = bh[(static_cast<int64_t>(g) * n_pairs + p0 + b) * 4 + jcol];
+        const V be = as_vec<V>(make_uint2(bw.x, bw.y)), bo = as_vec<V>(make_uint2(bw.z, bw.w));
+        are[g] = MOp<PREC>::mma(a1, be, are[g]);
+        are[g] = MOp<PREC>::mma(a2, bo, are[g]);
+        aim[g] = MOp<PREC>::mma(a3, be, aim[g]);
+        aim[g] = MOp<PREC>::mma(a4, bo, aim[g]);
+      }
+    }
+  }
+  const float sc = *inv;
+  const int64_t kb = static_cast<int64_t>(blockIdx.x) * kBlock + (threadIdx.x & ~3);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int r = 4 * g + jcol;
+    if (r >= nr) continue;
+    float2* out = part + (static_cast<int64_t>(r) * n_rows + blockIdx.y) * n_vis;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (kb + i < n_vis) out[kb + i] = make_float2(are[g][i] * sc, aim[g][i] * sc);
+  }
+}
+
 inline unsigned nblocks(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
 template <int PREC, int NG, int VPL>
@@ -399,7 +537,33 @@ hipError_t mfma_adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
 }
 
 template <int PREC, int NG>
+hipError_t grid_mfma_forward_t(sl1m_plan* p, const float* xp, int nr, hipStream_t st) {
+  const GridSeg& g = p->grid_segs[0];
+  const int64_t np = p->n_pix, n = static_cast<int64_t>(nr) * np;
+  hipLaunchKernelGGL(k_mfma_absmax, dim3(kMfmaRedBlocks), dim3(kBlock), 0, st, xp, n,
+                     static_cast<const float*>(p->pscale), np, p->mred);
+  hipLaunchKernelGGL((k_grid_mfma_pack_pairs<PREC>), dim3(nblocks(NG * g.n_pairs * 4)),
+                     dim3(kBlock), 0, st, xp, np, nr, static_cast<const float*>(p->pscale),
+                     p->grid_slot + 4 * g.cell_off, p->grid_c3 + g.cell_off, g.na, g.n_pairs,
+                     NG, p->mred, p->mred + 2 * kMfmaRedBlocks, p->grid_mfma_nu,
+                     reinterpret_cast<uint4*>(p->grid_mfma_b));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned vt = static_cast<unsigned>((p->n_vis + kBlock - 1) / kBlock);
+  return timed(p, T_GRID_FWD_DELTA, st, [&] {
+    hipLaunchKernelGGL((k_grid_fwd_pairs_mfma<PREC, NG>), dim3(vt, static_cast<unsigned>(g.nfc)),
+                       dim3(kBlock), 0, st, reinterpret_cast<const uint4*>(p->grid_mfma_b),
+                       p->grid_mfma_nu, g.n_pairs, p->grid_la + g.la_off, p->grid_mb + g.mb_off,
+                       p->d_grid_fchunks + g.fc0, g.na, p->vu, p->vv, p->vw, p->n_vis,
+                       p->mred + 2 * kMfmaRedBlocks, static_cast<float2*>(p->fpart),
+                       p->grid_frows, nr);
+    return hipGetLastError();
+  });
+}
+
+template <int PREC, int NG>
 hipError_t mfma_forward_v(sl1m_plan* p, const float* xp, int nr, hipStream_t st) {
+  if (p->grid_mfma) return grid_mfma_forward_t<PREC, NG>(p, xp, nr, st);
   if (p->fwd_vpl == 1) return mfma_forward_t<PREC, NG, 1>(p, xp, nr, st);
   if (p->fwd_vpl == 2) return mfma_forward_t<PREC, NG, 2>(p, xp, nr, st);
   return mfma_forward_t<PREC, NG, 4>(p, xp, nr, st);
@@ -415,7 +579,8 @@ hipError_t mfma_adjoint_v(sl1m_plan* p, int nr, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_mfma_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
-  if (p->n_vis == 0 || p->n_mfchunks == 0) return hipSuccess;
+  if (p->n_vis == 0 || (p->grid_mfma ? p->grid_frows == 0 : p->n_mfchunks == 0))
+    return hipSuccess;
   if (nr < 1 || nr > 8 || nr > p->max_rhs) return hipErrorInvalidValue;
   const float* x = static_cast<const float*>(xp);
   if (p->mfma == SL1M_PREC_MFMA_F16)

@@ -238,7 +238,8 @@ class PlanInfo(ctypes.Structure):
         ("fwd_vpl", ctypes.c_int32), ("adj_ppl", ctypes.c_int32),
         ("n_fchunks", ctypes.c_int32), ("n_fchunks_grid", ctypes.c_int32),
         ("n_achunks", ctypes.c_int32), ("grid_pairs", ctypes.c_int32),
-        ("grid_multi", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+        ("grid_multi", ctypes.c_int32), ("grid_mfma", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
     def as_dict(self):

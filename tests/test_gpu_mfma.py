@@ -21,6 +21,15 @@ units, accumulating in float32.  Two checks against the FP64 oracle:
   full cancellation and is loose; a handful of elements can cancel by
   chance, so short results get the bound alone).
 The norm-relative errors are printed for the precision table.
+
+Plans whose pixels form one square delta grid run the forward on the grid
+evaluation (`grid_mfma`): a mirrored pair of cells is sixteen FP32 basis
+values (products of the A, B and C phasors) against eight sign combinations
+of the pair's amplitudes, each rounded once.  Since the two basis values
+that share a combination have magnitudes summing to at most |C| <= 1 per
+component, a pair's error is at most 2 (2u + u^2) sum_j |M_kj| |x_j| (the
+factor 2 from the real and imaginary parts together), and a basis value
+left subnormal adds at most 2^-25 per product: n 2^-23 max|x| max|M|.
 """
 import sys
 
@@ -50,17 +59,23 @@ def _coef(prec, n):
     return 2 * u + u * u + n * 2.0 ** -24 + 2.0 ** -17
 
 
-def _check_forward(prec, p, Vg, X, ks=None):
-    """Vg[r][i] against the oracle at visibilities ks (all when None)."""
+def _check_forward(prec, p, Vg, X, ks=None, grid=False):
+    """Vg[r][i] against the oracle at visibilities ks (all when None); grid:
+    the plan's forward runs on the grid evaluation."""
     ks = np.arange(p.u.shape[0]) if ks is None else np.asarray(ks)
     M = O.matrix_block(p, ks, np.arange(p.l.shape[0]))
     absM = np.abs(M)
     n = X.shape[1]
     worst = 0.0
+    u = UNIT[prec]
     for r in range(X.shape[0]):
         Vo = M @ X[r]
         ax = np.abs(X[r])
-        b = _coef(prec, n) * (absM @ ax) + n * 2.0 ** -37 * ax.max() * absM.max()
+        if grid:
+            c = 2 * (2 * u + u * u) + n * 2.0 ** -24 + 2.0 ** -17
+            b = c * (absM @ ax) + n * 2.0 ** -23 * ax.max() * absM.max()
+        else:
+            b = _coef(prec, n) * (absM @ ax) + n * 2.0 ** -37 * ax.max() * absM.max()
         err = np.abs(Vg[r] - Vo)
         worst = max(worst, float((err / b).max()))
         assert np.all(err <= b), f"side {r}: error above the bound at {np.argmax(err / b)}"
@@ -104,13 +119,15 @@ def test_config3_stokes_mfma(prec):
     Vo, go = O.forward(p, X), O.adjoint(p, Rr)
     for r, name in enumerate("IQUV"):
         say(f"    Stokes {name}: forward {rel(Vg[r], Vo[r]):.3e} adjoint {rel(gg[r], go[r]):.3e}")
-    wf = _check_forward(prec, p, Vg, X)
+    grid = plan.info()["grid_mfma"] == 1
+    assert grid  # config 3's 32 x 32 image is a square delta grid
+    wf = _check_forward(prec, p, Vg, X, grid=grid)
     wa = _check_adjoint(prec, p, gg, Rr)
     say(f"    largest error / bound: forward {wf:.3f} adjoint {wa:.3f}")
     # a side alone equals that side of the multi-RHS call (same operand scale
     # only when it holds the largest magnitude: compare within the bound)
     V1 = plan.forward(X[0]).cpu().numpy()
-    _check_forward(prec, p, V1[None], X[:1])
+    _check_forward(prec, p, V1[None], X[:1], grid=grid)
 
 
 @pytest.mark.parametrize("prec", ["mfma_f16", "mfma_bf16"])
@@ -155,6 +172,41 @@ def test_mfma_lanes_per_thread(prec, lanes):
     say(f"    largest error / bound: forward {wf:.3f} adjoint {wa:.3f}")
 
 
+@pytest.mark.parametrize("prec", ["mfma_f16", "mfma_bf16"])
+def test_grid_mfma_side_counts(prec):
+    """A square delta grid (48 x 48 pixels: 1,152 mirrored pairs over several
+    pair chunks) with 3,001 visibilities (a ragged last tile) and antenna
+    gains, one plan called with 1, 2, 4 and 8 sides: the grid forward on the
+    matrix cores (float16 from 4 sides, bfloat16 at 8), the FP32 grid
+    evaluation below that, and each adjoint path, all within their bounds."""
+    say(f"[case] grid mfma {prec} 48x48 x 3001, sides 1/2/4/8")
+    rng = np.random.default_rng(41)
+    l, m, _ = W.grid_pixels(48, 0.1)
+    u, v, w = W.disk_uvw(rng, 3001, 400.0, 60.0)
+    n = l.shape[0]
+    wl = W.Workload("grid48", l, m, np.zeros(n), np.zeros(n, np.uint8), u, v, w)
+    wl.ant_p = rng.integers(0, 12, 3001).astype(np.int32)
+    wl.ant_q = ((wl.ant_p + rng.integers(1, 12, 3001)) % 12).astype(np.int32)
+    wl.ant_gain = (1.0 + 0.05 * rng.standard_normal(12)) * np.exp(1j * 0.05 * rng.standard_normal(12))
+    wl.ant_fwhm = np.full(12, 0.5)
+    plan = sl1m.Plan.from_workload(wl, precision=prec, max_rhs=8)
+    assert plan.info()["grid_mfma"] == 1
+    p = O.Problem.from_workload(wl)
+    for nr in (1, 2, 4, 8):
+        X = rng.standard_normal((nr, n))
+        Rr = rng.standard_normal((nr, 3001)) + 1j * rng.standard_normal((nr, 3001))
+        if nr == 1:
+            Vg = plan.forward(X[0]).cpu().numpy()[None]
+            gg = plan.adjoint(Rr[0]).cpu().numpy()[None]
+        else:
+            Vg = plan.forward_multi(X).cpu().numpy()
+            gg = plan.adjoint_multi(Rr).cpu().numpy()
+        wf = _check_forward(prec, p, Vg, X, grid=True)
+        wa = _check_adjoint(prec, p, gg, Rr)
+        say(f"    sides {nr}: largest error / bound forward {wf:.3f} adjoint {wa:.3f}")
+    plan.close()
+
+
 @pytest.mark.parametrize("shape", [(5, 3), (33, 31), (1, 64)])
 def test_mfma_tiny_shapes(shape):
     """Fewer pixels / visibilities than one 32-step, one lane, one block."""
@@ -189,7 +241,8 @@ def test_mfma_full_size_sampled():
     ks = np.append(ks, wl.n_vis - 1)
     js = np.sort(rng.choice(wl.n_pix - 1, 63, replace=False))
     js = np.append(js, wl.n_pix - 1)
-    wf = _check_forward("mfma_f16", p, Vg[:, ks], X, ks)
+    assert plan.info()["grid_mfma"] == 1
+    wf = _check_forward("mfma_f16", p, Vg[:, ks], X, ks, grid=True)
     wa = _check_adjoint("mfma_f16", p, gg[:, js], Rr, js)
     Vo = O.matrix_block(p, ks, np.arange(wl.n_pix)) @ X.T
     go = np.real(O.matrix_block(p, np.arange(wl.n_vis), js).conj().T @ Rr.T)
