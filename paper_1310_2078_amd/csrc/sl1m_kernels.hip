@@ -675,8 +675,9 @@ hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, int nr, hipStrea
 // evaluations at hand and takes, per side count, the faster of the two as
 // measured at config 2's shape (65,536 pixels x 97,536 visibilities, ms;
 // FP32 grid / float16 / bfloat16 matrix cores):
-//   forward  4 sides 1.31 / 1.18 / 1.47,  8 sides 2.57 / 1.49 / 1.84
-//   adjoint  8 sides 2.79 / 2.42 / 4.88
+//   forward  2 sides 0.83 / 0.84 / -,  4 sides 1.31 / 0.84 / 1.47,
+//            8 sides 2.59 / 1.18 / 1.86
+//   adjoint  8 sides 2.81 / 2.45 / 4.88
 // so float16 plans use the matrix-core grid forward from 4 sides and the
 // matrix-core adjoint at 8, bfloat16 plans the matrix-core forward at 8 only;
 // everything else runs the FP32 grid evaluation (the more accurate one).

@@ -498,6 +498,103 @@ __global__ __launch_bounds__(kBlock) void k_grid_fwd_pairs_mfma(
   }
 }
 
+// The same forward for float16 operands with the basis formed in packed
+// float16 arithmetic: the lane's A and B phasors at |l|_ia, the block's at
+// |m|_b and each pair's C are rounded to float16 once, and the sixteen basis
+// values of a pair are then four products of (cos, sin) halves (m1 m2 | m3 m4
+// from A at ia against B at b and its swap, m5 m6 | m7 m8 from the mirror's)
+// and eight products with C's components -- 12 v_pk_mul_f16 and one
+// conversion per pair instead of 24 float32 products and 8 conversions.  Each
+// basis value carries up to five float16 roundings (two inputs, two products,
+// C) against one when formed in float32.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ h2_t to_h2(float a, float b) {
+  return __builtin_convertvector((f2_t{a, b}), h2_t);
+}
+
+__device__ __forceinline__ h4_t cat_h2(h2_t a, h2_t b) {
+  return __builtin_shufflevector(a, b, 0, 1, 2, 3);
+}
+
+template <int NG>
+__global__ __launch_bounds__(kBlock) void k_grid_fwd_pairs_mfma_h(
+    const uint4* __restrict__ bh, const double* __restrict__ pnu, int64_t n_pairs,
+    const double* __restrict__ la, const double* __restrict__ mb,
+    const GridChunk* __restrict__ chunks, int na, const double* __restrict__ vu,
+    const double* __restrict__ vv, const double* __restrict__ vw, int64_t n_vis,
+    const float* __restrict__ inv, float2* __restrict__ part, int n_rows, int nr) {
+  const int lane = threadIdx.x & 63;
+  const int jcol = lane & 3;
+  const ConstPtr<GridChunk> cch = as_const(chunks) + blockIdx.y;
+  const int g0 = cch->g, ia0 = cch->ia0, ia1 = cch->ia1;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t kk = k < n_vis ? k : n_vis - 1;
+  const double u = vu[kk], v = vv[kk], w = vw[kk];
+  const ConstPtr<double> cla = as_const(la);
+  const ConstPtr<double> cmb = as_const(mb);
+  const ConstPtr<double> cnu = as_const(pnu);
+  const double origin = kMagic;
+  h2_t bb[kGridNB], pp[kGridNB];  // (cos, sin) of B at |m|_b and of A at |l|_b
+#pragma unroll
+  for (int b = 0; b < kGridNB; ++b) {
+    const double m = cmb[g0 * kGridNB + b];
+    float c, s;
+    phasor(fma(v, m, origin), c, s);
+    bb[b] = to_h2(c, s);
+    phasor(fma(u, m, origin), c, s);
+    pp[b] = to_h2(c, s);
+  }
+  f4_t are[NG], aim[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) are[g] = aim[g] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int ia = ia0; ia < ia1; ++ia) {
+    const double l = cla[ia];
+    float c, s;
+    phasor(fma(u, l, origin), c, s);
+    const h2_t aa = to_h2(c, s);  // A at |l|_ia
+    phasor(fma(v, l, origin), c, s);
+    const h2_t qq = to_h2(c, s);  // B at |m|_ia
+    const int64_t p0 = pair_rec_base(g0, na) + static_cast<int64_t>(ia - kGridNB * g0) * kGridNB;
+#pragma unroll
+    for (int b = 0; b < kGridNB; ++b) {
+      float cc, cs;
+      phasor(fma(w, cnu[p0 + b], origin), cc, cs);
+      const h2_t ch = to_h2(cc, cs);
+      const h2_t cx = ch.xx, cy = ch.yy;
+      const h2_t m12 = aa * bb[b];           // (m1, m2)
+      const h2_t m34 = aa * bb[b].yx;        // (m3, m4)
+      const h2_t m56 = pp[b] * qq;           // (m5, m6)
+      const h2_t m78 = pp[b] * qq.yx;        // (m7, m8)
+      const h4_t a1 = cat_h2(cx * m12, cx * m56);
+      const h4_t a2 = cat_h2(-(cy * m34), -(cy * m78));
+      const h4_t a3 = cat_h2(-(cy * m12), -(cy * m56));
+      const h4_t a4 = cat_h2(-(cx * m34), -(cx * m78));
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const uint4 bw = bh[(static_cast<int64_t>(g) * n_pairs + p0 + b) * 4 + jcol];
+        const h4_t be = as_vec<h4_t>(make_uint2(bw.x, bw.y)), bo = as_vec<h4_t>(make_uint2(bw.z, bw.w));
+        are[g] = __builtin_amdgcn_mfma_f32_4x4x4f16(a1, be, are[g], 0, 0, 0);
+        are[g] = __builtin_amdgcn_mfma_f32_4x4x4f16(a2, bo, are[g], 0, 0, 0);
+        aim[g] = __builtin_amdgcn_mfma_f32_4x4x4f16(a3, be, aim[g], 0, 0, 0);
+        aim[g] = __builtin_amdgcn_mfma_f32_4x4x4f16(a4, bo, aim[g], 0, 0, 0);
+      }
+    }
+  }
+  const float sc = *inv;
+  const int64_t kb = static_cast<int64_t>(blockIdx.x) * kBlock + (threadIdx.x & ~3);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int r = 4 * g + jcol;
+    if (r >= nr) continue;
+    float2* out = part + (static_cast<int64_t>(r) * n_rows + blockIdx.y) * n_vis;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (kb + i < n_vis) out[kb + i] = make_float2(are[g][i] * sc, aim[g][i] * sc);
+  }
+}
+
 inline unsigned nblocks(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
 template <int PREC, int NG, int VPL>
@@ -551,12 +648,21 @@ hipError_t grid_mfma_forward_t(sl1m_plan* p, const float* xp, int nr, hipStream_
   if (e != hipSuccess) return e;
   const unsigned vt = static_cast<unsigned>((p->n_vis + kBlock - 1) / kBlock);
   return timed(p, T_GRID_FWD_DELTA, st, [&] {
-    hipLaunchKernelGGL((k_grid_fwd_pairs_mfma<PREC, NG>), dim3(vt, static_cast<unsigned>(g.nfc)),
-                       dim3(kBlock), 0, st, reinterpret_cast<const uint4*>(p->grid_mfma_b),
-                       p->grid_mfma_nu, g.n_pairs, p->grid_la + g.la_off, p->grid_mb + g.mb_off,
-                       p->d_grid_fchunks + g.fc0, g.na, p->vu, p->vv, p->vw, p->n_vis,
-                       p->mred + 2 * kMfmaRedBlocks, static_cast<float2*>(p->fpart),
-                       p->grid_frows, nr);
+    const dim3 grid(vt, static_cast<unsigned>(g.nfc));
+    if constexpr (PREC == SL1M_PREC_MFMA_F16)
+      hipLaunchKernelGGL((k_grid_fwd_pairs_mfma_h<NG>), grid, dim3(kBlock), 0, st,
+                         reinterpret_cast<const uint4*>(p->grid_mfma_b), p->grid_mfma_nu,
+                         g.n_pairs, p->grid_la + g.la_off, p->grid_mb + g.mb_off,
+                         p->d_grid_fchunks + g.fc0, g.na, p->vu, p->vv, p->vw, p->n_vis,
+                         p->mred + 2 * kMfmaRedBlocks, static_cast<float2*>(p->fpart),
+                         p->grid_frows, nr);
+    else
+      hipLaunchKernelGGL((k_grid_fwd_pairs_mfma<PREC, NG>), grid, dim3(kBlock), 0, st,
+                         reinterpret_cast<const uint4*>(p->grid_mfma_b), p->grid_mfma_nu,
+                         g.n_pairs, p->grid_la + g.la_off, p->grid_mb + g.mb_off,
+                         p->d_grid_fchunks + g.fc0, g.na, p->vu, p->vv, p->vw, p->n_vis,
+                         p->mred + 2 * kMfmaRedBlocks, static_cast<float2*>(p->fpart),
+                         p->grid_frows, nr);
     return hipGetLastError();
   });
 }

@@ -23,13 +23,22 @@ units, accumulating in float32.  Two checks against the FP64 oracle:
 The norm-relative errors are printed for the precision table.
 
 Plans whose pixels form one square delta grid run the forward on the grid
-evaluation (`grid_mfma`): a mirrored pair of cells is sixteen FP32 basis
-values (products of the A, B and C phasors) against eight sign combinations
-of the pair's amplitudes, each rounded once.  Since the two basis values
-that share a combination have magnitudes summing to at most |C| <= 1 per
-component, a pair's error is at most 2 (2u + u^2) sum_j |M_kj| |x_j| (the
-factor 2 from the real and imaginary parts together), and a basis value
-left subnormal adds at most 2^-25 per product: n 2^-23 max|x| max|M|.
+evaluation (`grid_mfma`): a mirrored pair of cells is sixteen basis values
+(products of the A, B and C phasors) against eight sign combinations of the
+pair's amplitudes.  Since the two basis values that share a combination have
+magnitudes summing to at most |C| <= 1 per component, a pair's error is at
+most 2 e sum_j |M_kj| |x_j| (the factor 2 from the real and imaginary parts
+together), e the relative error of one basis value times one combination:
+* bfloat16: the basis is formed in float32 and rounded once, and the
+  combination once: e = 2u + u^2; a basis value left subnormal adds at most
+  2^-25 per product: n 2^-23 max|x| max|M|;
+* float16: the basis is formed in packed float16 arithmetic (the two phasor
+  components, their product, C and the product with C each rounded), so
+  e = (1 + u)^6 - 1; each of the five roundings of a value below float16's
+  normal range adds at most 2^-25 absolute, so a basis value is off by at
+  most 5 2^-25 beyond e, i.e. 320 2^-25 max|x| per pair over its 16 values
+  and combinations of four amplitudes; with at most n/8 + n/16 pairs this is
+  below n 2^-19 max|x| max|M|.
 """
 import sys
 
@@ -71,7 +80,10 @@ def _check_forward(prec, p, Vg, X, ks=None, grid=False):
     for r in range(X.shape[0]):
         Vo = M @ X[r]
         ax = np.abs(X[r])
-        if grid:
+        if grid and prec == "mfma_f16":
+            c = 2 * ((1 + u) ** 6 - 1) + n * 2.0 ** -24 + 2.0 ** -17
+            b = c * (absM @ ax) + n * 2.0 ** -19 * ax.max() * absM.max()
+        elif grid:
             c = 2 * (2 * u + u * u) + n * 2.0 ** -24 + 2.0 ** -17
             b = c * (absM @ ax) + n * 2.0 ** -23 * ax.max() * absM.max()
         else:
