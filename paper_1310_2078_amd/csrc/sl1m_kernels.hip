@@ -677,10 +677,10 @@ hipError_t launch_gather(sl1m_plan* p, const void* x, void* xp, int nr, hipStrea
 // FP32 grid / float16 / bfloat16 matrix cores):
 //   forward  2 sides 0.83 / 0.84 / -,  4 sides 1.31 / 0.84 / 1.47,
 //            8 sides 2.59 / 1.18 / 1.86
-//   adjoint  8 sides 2.81 / 2.45 / 4.88
-// so float16 plans use the matrix-core grid forward from 4 sides and the
-// matrix-core adjoint at 8, bfloat16 plans the matrix-core forward at 8 only;
-// everything else runs the FP32 grid evaluation (the more accurate one).
+//   adjoint  4 sides 1.45 / 1.22 / -,  8 sides 2.78 / 2.40 / 4.88
+// so float16 plans use the matrix-core grid forward and adjoint from 4
+// sides, bfloat16 plans the matrix-core forward at 8 only; everything else
+// runs the FP32 grid evaluation (the more accurate one).
 static bool mfma_forward_call(const sl1m_plan* p, int nr) {
   if (!p->mfma) return false;
   if (!p->grid_mfma) return true;
@@ -689,7 +689,7 @@ static bool mfma_forward_call(const sl1m_plan* p, int nr) {
 static bool mfma_adjoint_call(const sl1m_plan* p, int nr) {
   if (!p->mfma) return false;
   if (!p->grid_mfma) return true;
-  return p->mfma == SL1M_PREC_MFMA_F16 && nr >= 8;
+  return p->mfma == SL1M_PREC_MFMA_F16 && nr >= 4;
 }
 
 template <typename R>

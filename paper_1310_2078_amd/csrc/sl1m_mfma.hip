@@ -595,6 +595,187 @@ __global__ __launch_bounds__(kBlock) void k_grid_fwd_pairs_mfma_h(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Square delta grids on the matrix cores (adjoint, float16).  The pair
+// adjoint of the FP32 grid kernels accumulates, per cell pair and side, the
+// eight sums G_a = sum_k p_a(k) z_a(k) with p_1..p_8 the products of the A
+// and B phasors of the cell and its mirror (m1, m2, m3, m4, m5, m6, m7, m8
+// of the forward above) and, with C = (cc, cs) the pair's radius phasor and
+// r_k the residual record,
+//   z_a = cc Re r - cs Im r  (a = 1, 2, 5, 6),  z_a = cs Re r + cc Im r  (else).
+// So G_a contracts over (visibility, Re / Im) the basis (p_a cc, -p_a cs) or
+// (p_a cs, p_a cc) with the residual's (Re r, Im r): one 4 x 4 x 4 MFMA per
+// sum and two visibilities, its K the two visibilities' (Re, Im).  Lane
+// L = i + 4b gives A row i of block b (the basis of its own cell pair), B
+// column j of every block is side j's residual (lane j + 4b), and D column j
+// in lane j + 4b ends as G_a of the four pairs of lanes 4b .. 4b + 3 for
+// side j, which that lane writes.  The basis is formed in packed float16 as
+// in the forward; the residual records are scaled by a power of two per call
+// and rounded once.
+// ---------------------------------------------------------------------------
+
+// Residual records for the contraction: out[(kp ng + g) 4 + j] = (Re r, Im r)
+// of visibilities 2 kp and 2 kp + 1 of side 4 g + j, times c, as float16
+// (zero past n_vis or nr).  One thread per (kp, g, j).
+__global__ __launch_bounds__(kBlock) void k_grid_mfma_pack_res(
+    const float2* __restrict__ rres, int64_t n_vis, int nr, int64_t n_kp, int ng,
+    const float* __restrict__ bm, float* __restrict__ inv_out, uint2* __restrict__ out) {
+  const float c = op_scale(max_of_blocks(bm));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *inv_out = 1.0f / c;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= n_kp * ng * 4) return;
+  const int j = static_cast<int>(t & 3);
+  const int g = static_cast<int>((t >> 2) % ng);
+  const int64_t kp = (t >> 2) / ng;
+  const int r = 4 * g + j;
+  float2 v0 = make_float2(0.0f, 0.0f), v1 = make_float2(0.0f, 0.0f);
+  if (r < nr) {
+    if (2 * kp < n_vis) v0 = rres[2 * kp * nr + r];
+    if (2 * kp + 1 < n_vis) v1 = rres[(2 * kp + 1) * nr + r];
+  }
+  const h4_t h = __builtin_convertvector((f4_t{v0.x * c, v0.y * c, v1.x * c, v1.y * c}), h4_t);
+  out[t] = __builtin_bit_cast(uint2, h);
+}
+
+// Block (pair block x, visibility chunk y, cell slice z): the NBI cells
+// b = kGridNBA g4 + bo + bi (bo = z NBI) of each lane-set, as the FP32 pair
+// adjoint; side r of chunk y goes to part + r rstride + y n_pix.  Every
+// thread runs the whole loop (the MFMAs are wavefront-wide): lanes past the
+// block's lane-sets evaluate a dummy pair and write nothing.
+template <int NG, int NBI>
+__global__ __launch_bounds__(kBlock) void k_grid_adj_pairs_mfma_h(
+    const VisRecD<float>* __restrict__ vrec, const uint2* __restrict__ rh,
+    const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ la,
+    const double* __restrict__ mb, const double* __restrict__ nu,
+    const int32_t* __restrict__ slot, int na, const GridPairBlock* __restrict__ blocks,
+    int64_t kchunk, int64_t n_vis, const float* __restrict__ inv, float* __restrict__ part,
+    int64_t n_pix, int64_t rstride, int nr) {
+  static_assert(kGridNBA % NBI == 0, "NBI divides the cells of a lane-set");
+  constexpr int KB = kGridKBM;  // visibilities per LDS batch (even)
+  __shared__ uint2 bsh[KB][kGridMaxGL][NBI];  // (B, A) at |m|_b as float16 pairs
+  const ConstPtr<GridPairBlock> cb = as_const(blocks) + blockIdx.x;
+  GridPairBlock pb;
+  pb.g4 = cb->g4;
+  pb.ia = cb->ia;
+  pb.count = cb->count;
+  pb.n_gl = cb->n_gl;
+  const int bo = static_cast<int>(blockIdx.z) * NBI;
+  const PairLane pl = pair_lane(pb, na);
+  const int lane = threadIdx.x & 63;
+  const int jcol = lane & 3;
+  const double l = la[pl.ia];
+  double nuv[NBI];
+#pragma unroll
+  for (int bi = 0; bi < NBI; ++bi) nuv[bi] = pl.active ? nu[pl.qbase + bo + bi] : 0.0;
+  const ConstPtr<VisRecD<float>> cvrec = as_const(vrec);
+  const double origin = kMagic;
+  const int64_t kc = blockIdx.y;
+  const int k0 = static_cast<int>(kc * kchunk);
+  const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
+  f4_t acc[NBI][8][NG];
+#pragma unroll
+  for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) acc[bi][a][g] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  const FillSlot fs = fill_slot(pb.n_gl * NBI);
+  const int fgg = fs.slot / NBI, fbi = fs.slot % NBI;
+  const double fm = fs.on ? mb[(pb.g4 + fgg) * kGridNBA + bo + fbi] : 0.0;
+  for (int kb = k0; kb < k1; kb += KB) {
+    __syncthreads();  // the previous batch's reads are done
+    if (fs.on) {
+      for (int kk = fs.row0; kk < KB; kk += fs.step) {
+        const int k = kb + kk;
+        float bc = 0.0f, bs = 0.0f, ac = 0.0f, as = 0.0f;
+        if (k < k1) {
+          phasor(fma(vv[k], fm, origin), bc, bs);
+          phasor(fma(vu[k], fm, origin), ac, as);
+        }
+        const h4_t h = __builtin_convertvector((f4_t{bc, bs, ac, as}), h4_t);
+        bsh[kk][fgg][fbi] = __builtin_bit_cast(uint2, h);
+      }
+    }
+    __syncthreads();
+    const int ke = kb + KB < k1 ? kb + KB : k1;
+    for (int k = kb; k < ke; k += 2) {
+      // the basis of both visibilities (k + 1 may be past k1: its LDS entries
+      // are zero and so is its residual record; the records past n_vis are
+      // padding of the plan)
+      h2_t e[2][NBI][8];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int kv = k + h;
+        const double u = cvrec[kv].u, v = cvrec[kv].v, w = cvrec[kv].w;
+        float c, sn;
+        phasor(fma(u, l, origin), c, sn);
+        const h2_t aa = to_h2(c, sn);  // A at |l|_ia
+        phasor(fma(v, l, origin), c, sn);
+        const h2_t qq = to_h2(c, sn);  // B at |m|_ia
+#pragma unroll
+        for (int bi = 0; bi < NBI; ++bi) {
+          const h4_t t4 = __builtin_bit_cast(h4_t, bsh[kv - kb][pl.gl][bi]);
+          const h2_t bbm = __builtin_shufflevector(t4, t4, 0, 1);  // B at |m|_b
+          const h2_t pam = __builtin_shufflevector(t4, t4, 2, 3);  // A at |l|_b
+          float cc, cs;
+          phasor(fma(w, nuv[bi], origin), cc, cs);
+          const h2_t ch = to_h2(cc, cs);
+          const h2_t v1 = h2_t{ch.x, -ch.y};  // (cc, -cs)
+          const h2_t v2 = ch.yx;              // (cs, cc)
+          const h2_t m12 = aa * bbm, m34 = aa * bbm.yx, m56 = pam * qq, m78 = pam * qq.yx;
+          e[h][bi][0] = m12.xx * v1;
+          e[h][bi][1] = m12.yy * v1;
+          e[h][bi][2] = m34.xx * v2;
+          e[h][bi][3] = m34.yy * v2;
+          e[h][bi][4] = m56.xx * v1;
+          e[h][bi][5] = m56.yy * v1;
+          e[h][bi][6] = m78.xx * v2;
+          e[h][bi][7] = m78.yy * v2;
+        }
+      }
+      h4_t rb[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+        rb[g] = __builtin_bit_cast(h4_t, rh[(static_cast<int64_t>(k >> 1) * NG + g) * 4 + jcol]);
+#pragma unroll
+      for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const h4_t av = cat_h2(e[0][bi][a], e[1][bi][a]);
+#pragma unroll
+          for (int g = 0; g < NG; ++g)
+            acc[bi][a][g] = __builtin_amdgcn_mfma_f32_4x4x4f16(av, rb[g], acc[bi][a][g], 0, 0, 0);
+        }
+    }
+  }
+  // lane 4b + j writes side j (of each group) of the pairs of lanes 4b .. 4b + 3
+  const float sc = *inv;
+  float* out = part + kc * n_pix;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int src = (lane & ~3) + i;
+    PairLane pi;
+    pi.active = __shfl(pl.active ? 1 : 0, src, 64) != 0;
+    pi.g4 = __shfl(pl.g4, src, 64);
+    pi.ia = __shfl(pl.ia, src, 64);
+    pi.gl = __shfl(pl.gl, src, 64);
+    pi.qbase = __shfl(pl.qbase, src, 64);
+    if (!pi.active) continue;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int r = 4 * g + jcol;
+      if (r >= nr) continue;
+#pragma unroll
+      for (int bi = 0; bi < NBI; ++bi) {
+        float G8[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) G8[a] = acc[bi][a][g][i] * sc;
+        pair_write(pi, na, bo + bi, G8, slot, out + r * rstride);
+      }
+    }
+  }
+}
+
 inline unsigned nblocks(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
 template <int PREC, int NG, int VPL>
@@ -631,6 +812,35 @@ hipError_t mfma_adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
                      p->mred + 2 * kMfmaRedBlocks + 1, static_cast<float*>(p->apart),
                      p->n_achunks, nr);
   return hipGetLastError();
+}
+
+template <int NG, int NBI>
+hipError_t grid_mfma_adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
+  const GridSeg& g = p->grid_segs[0];
+  const int64_t nv = p->n_vis, n_kp = (nv + 1) / 2;
+  const float* rres = static_cast<const float*>(p->rres);  // delta slot: [n_vis][nr] complex
+  hipLaunchKernelGGL(k_mfma_absmax, dim3(kMfmaRedBlocks), dim3(kBlock), 0, st, rres,
+                     2 * nr * nv, static_cast<const float*>(nullptr), int64_t{1},
+                     p->mred + kMfmaRedBlocks);
+  hipLaunchKernelGGL(k_grid_mfma_pack_res, dim3(nblocks(n_kp * NG * 4)), dim3(kBlock), 0, st,
+                     reinterpret_cast<const float2*>(rres), nv, nr, n_kp, NG,
+                     p->mred + kMfmaRedBlocks, p->mred + 2 * kMfmaRedBlocks + 1,
+                     reinterpret_cast<uint2*>(p->mr));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g.pblocks == 0) return e;
+  const int64_t co = g.cell_off;
+  return timed(p, T_GRID_ADJ_DELTA, st, [&] {
+    hipLaunchKernelGGL((k_grid_adj_pairs_mfma_h<NG, NBI>),
+                       dim3(static_cast<unsigned>(g.pblocks), static_cast<unsigned>(p->n_achunks),
+                            static_cast<unsigned>(kGridNBA / NBI)),
+                       dim3(kBlock), 0, st, static_cast<const VisRecD<float>*>(p->visrecD),
+                       reinterpret_cast<const uint2*>(p->mr), p->vu, p->vv,
+                       p->grid_la + g.la_off, p->grid_mb + g.mb_off, p->grid_c3 + co,
+                       p->grid_slot + 4 * co, g.na, p->d_grid_pblocks + g.pb0, p->adj_kchunk,
+                       nv, p->mred + 2 * kMfmaRedBlocks + 1, static_cast<float*>(p->apart),
+                       p->n_pix, static_cast<int64_t>(p->n_achunks) * p->n_pix, nr);
+    return hipGetLastError();
+  });
 }
 
 template <int PREC, int NG>
@@ -699,6 +909,8 @@ hipError_t launch_mfma_forward(sl1m_plan* p, const void* xp, int nr, hipStream_t
 hipError_t launch_mfma_adjoint(sl1m_plan* p, int nr, hipStream_t st) {
   if (p->n_pix == 0 || p->n_achunks == 0) return hipSuccess;
   if (nr < 1 || nr > 8 || nr > p->max_rhs) return hipErrorInvalidValue;
+  if (p->grid_mfma && p->mfma == SL1M_PREC_MFMA_F16)
+    return nr <= 4 ? grid_mfma_adjoint_t<1, 2>(p, nr, st) : grid_mfma_adjoint_t<2, 1>(p, nr, st);
   if (p->mfma == SL1M_PREC_MFMA_F16)
     return nr <= 4 ? mfma_adjoint_v<SL1M_PREC_MFMA_F16, 1>(p, nr, st)
                    : mfma_adjoint_v<SL1M_PREC_MFMA_F16, 2>(p, nr, st);

@@ -39,6 +39,15 @@ together), e the relative error of one basis value times one combination:
   most 5 2^-25 beyond e, i.e. 320 2^-25 max|x| per pair over its 16 values
   and combinations of four amplitudes; with at most n/8 + n/16 pairs this is
   below n 2^-19 max|x| max|M|.
+The adjoint of float16 plans on such a grid (4 and 8 sides) contracts the
+same basis, as (p_a cc, -p_a cs) or (p_a cs, p_a cc) per visibility, with
+the scaled residual records (conj(G) r): a pixel's value adds four sums
+whose products p_a have magnitudes summing to at most 2, and |Re r'| +
+|Im r'| <= sqrt 2 |G| (|Re r| + |Im r|), so its error is at most
+2 sqrt 2 ((1 + u)^6 - 1) sum_k |M_kj| (|Re r_k| + |Im r_k|) plus the
+float32 terms above, and the subnormal basis values add at most
+4 x 5 2^-25 sqrt 2 per visibility: below n 2^-21 max(|Re r| + |Im r|) max|M|
+with n = 2 N_v.
 """
 import sys
 
@@ -96,17 +105,23 @@ def _check_forward(prec, p, Vg, X, ks=None, grid=False):
     return worst
 
 
-def _check_adjoint(prec, p, gg, Rr, js=None):
-    """gg[r][i] against the oracle at pixels js (all when None)."""
+def _check_adjoint(prec, p, gg, Rr, js=None, grid=False):
+    """gg[r][i] against the oracle at pixels js (all when None); grid: the
+    plan's pixels form one square delta grid."""
     js = np.arange(p.l.shape[0]) if js is None else np.asarray(js)
     M = O.matrix_block(p, np.arange(p.u.shape[0]), js)
     absMT = np.abs(M).T
     n = 2 * Rr.shape[1]  # the real and the imaginary product of each visibility
+    u = UNIT[prec]
     worst = 0.0
     for r in range(Rr.shape[0]):
         go = np.real(M.conj().T @ Rr[r])
         ar = np.abs(Rr[r].real) + np.abs(Rr[r].imag)
-        b = _coef(prec, n) * (absMT @ ar) + n * 2.0 ** -37 * ar.max() * absMT.max()
+        if grid and prec == "mfma_f16":
+            c = 2 * np.sqrt(2.0) * ((1 + u) ** 6 - 1) + n * 2.0 ** -24 + 2.0 ** -17
+            b = c * (absMT @ ar) + n * 2.0 ** -21 * ar.max() * absMT.max()
+        else:
+            b = _coef(prec, n) * (absMT @ ar) + n * 2.0 ** -37 * ar.max() * absMT.max()
         err = np.abs(gg[r] - go)
         worst = max(worst, float((err / b).max()))
         assert np.all(err <= b), f"side {r}: error above the bound at {np.argmax(err / b)}"
@@ -134,7 +149,7 @@ def test_config3_stokes_mfma(prec):
     grid = plan.info()["grid_mfma"] == 1
     assert grid  # config 3's 32 x 32 image is a square delta grid
     wf = _check_forward(prec, p, Vg, X, grid=grid)
-    wa = _check_adjoint(prec, p, gg, Rr)
+    wa = _check_adjoint(prec, p, gg, Rr, grid=grid)
     say(f"    largest error / bound: forward {wf:.3f} adjoint {wa:.3f}")
     # a side alone equals that side of the multi-RHS call (same operand scale
     # only when it holds the largest magnitude: compare within the bound)
@@ -214,7 +229,7 @@ def test_grid_mfma_side_counts(prec):
             Vg = plan.forward_multi(X).cpu().numpy()
             gg = plan.adjoint_multi(Rr).cpu().numpy()
         wf = _check_forward(prec, p, Vg, X, grid=True)
-        wa = _check_adjoint(prec, p, gg, Rr)
+        wa = _check_adjoint(prec, p, gg, Rr, grid=True)
         say(f"    sides {nr}: largest error / bound forward {wf:.3f} adjoint {wa:.3f}")
     plan.close()
 
@@ -255,7 +270,7 @@ def test_mfma_full_size_sampled():
     js = np.append(js, wl.n_pix - 1)
     assert plan.info()["grid_mfma"] == 1
     wf = _check_forward("mfma_f16", p, Vg[:, ks], X, ks, grid=True)
-    wa = _check_adjoint("mfma_f16", p, gg[:, js], Rr, js)
+    wa = _check_adjoint("mfma_f16", p, gg[:, js], Rr, js, grid=True)
     Vo = O.matrix_block(p, ks, np.arange(wl.n_pix)) @ X.T
     go = np.real(O.matrix_block(p, np.arange(wl.n_vis), js).conj().T @ Rr.T)
     ef, ea = rel(Vg[:, ks].T, Vo), rel(gg[:, js].T, go)
