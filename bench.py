@@ -276,20 +276,23 @@ def extras(plan2, wl2, dev, c4):
     ex = {}
     # the same FISTA iteration with every entry evaluated directly (no grid
     # factorisation), for comparison with the headline evaluation
-    pdir = sl1m.Plan.from_workload(wl2, device=dev, grid="off")
-    Vd = pdir.forward(wl2.x_true)
-    Ld = 1.01 * pdir.estimate_L(10, seed=0)
-    pdir.solve(Vd, wl2.lam, 3, L=Ld)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pdir.solve(Vd, wl2.lam, 20, L=Ld)
-    torch.cuda.synchronize()
-    td = time.perf_counter() - t0
-    ex["config2_direct_evaluation"] = {
-        "iterations": 20, "time_s": td,
-        "evals_per_s": 2.0 * wl2.n_pix * wl2.n_vis * 20 / td}
-    pdir.close()
-    del pdir, Vd
+    # (FP64 phase), and with the phase formed in float32 hi/lo arithmetic
+    for key, kw in (("config2_direct_evaluation", dict(grid="off")),
+                    ("config2_direct_hilo_phase", dict(precision="fp32_hilo"))):
+        pdir = sl1m.Plan.from_workload(wl2, device=dev, **kw)
+        Vd = pdir.forward(wl2.x_true)
+        Ld = 1.01 * pdir.estimate_L(10, seed=0)
+        pdir.solve(Vd, wl2.lam, 3, L=Ld)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pdir.solve(Vd, wl2.lam, 20, L=Ld)
+        torch.cuda.synchronize()
+        td = time.perf_counter() - t0
+        ex[key] = {"iterations": 20, "time_s": td,
+                   "evals_per_s": 2.0 * wl2.n_pix * wl2.n_vis * 20 / td}
+        print(f"[bench] {key}: {ex[key]}", file=sys.stderr, flush=True)
+        pdir.close()
+        del pdir, Vd
     # warm start from the dirty image (Section "Acceleration strategies"):
     # relative objective gap after k iterations, cold against warm, with F*
     # from a 400-iteration cold solve

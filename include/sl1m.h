@@ -27,8 +27,8 @@
  *  - Calls that share a plan must not run concurrently (the plan's workspace
  *    holds per-call scratch such as split-K partial sums).
  *  - Real/complex element types follow the plan's precision: float32 and
- *    complex64 (interleaved re, im) for SL1M_PREC_FP32 and the MFMA
- *    precisions, float64 and complex128 for SL1M_PREC_FP64.
+ *    complex64 (interleaved re, im) for SL1M_PREC_FP32, SL1M_PREC_FP32_HILO
+ *    and the MFMA precisions, float64 and complex128 for SL1M_PREC_FP64.
  */
 #ifndef SL1M_H_
 #define SL1M_H_
@@ -65,7 +65,9 @@ typedef enum {
                               entries and the images / residuals they multiply
                               rounded to float16 and contracted on the matrix
                               cores, float32 accumulation (see below)           */
-  SL1M_PREC_MFMA_BF16 = 3  /* as SL1M_PREC_MFMA_F16 with bfloat16 operands      */
+  SL1M_PREC_MFMA_BF16 = 3, /* as SL1M_PREC_MFMA_F16 with bfloat16 operands      */
+  SL1M_PREC_FP32_HILO = 4  /* the FP32 plan with the phase formed in float32
+                              hi/lo arithmetic instead of float64 (see below)   */
 } sl1m_precision;
 
 /*
@@ -87,9 +89,33 @@ typedef enum {
  * float16 operands below 2^-14 of the scale add at most 2^-38 of the largest
  * operand per term (subnormal spacing).  Only delta pixels (every pixel
  * SL1M_PIX_DELTA) and gains without per-pair beam widths are accepted
- * (SL1M_EINVAL otherwise); there is no grid evaluation, tuning or serving
- * with these precisions.  Real and complex arrays at the ABI are float32 and
- * complex64 as for SL1M_PREC_FP32.
+ * (SL1M_EINVAL otherwise); there is no tuning or serving with these
+ * precisions.  When all pixels form one square delta grid (see "Evaluation
+ * order" below) the plan also evaluates on the grid: sl1m_plan_info.grid_mfma
+ * is 1, and calls with fewer sides than the matrix cores pay off for (float16:
+ * 1 and 2 sides, bfloat16: 1, 2 and 4 sides, and bfloat16's adjoint at 8)
+ * run the FP32 grid evaluation.  The others contract the grid's products
+ * of the per-|l|, per-|m| and per-radius phasors (sixteen basis values per
+ * mirrored pair of cells) on the matrix cores; float16 forms them with
+ * packed float16 products, so each basis value carries up to five float16
+ * roundings and the per-entry bound above becomes
+ * (2 ((1 + u)^6 - 1) + N 2^-24 + 2^-17) sum_j |M_kj x_j| for the forward and
+ * 2 sqrt(2) times that relative term for the adjoint, plus N 2^-19 (forward)
+ * or N 2^-21 (adjoint) of the largest operand times the largest |M_kj| for
+ * float16's subnormal range.  Real and complex arrays at the ABI are float32
+ * and complex64 as for SL1M_PREC_FP32.
+ *
+ * FP32 hi/lo phase (SL1M_PREC_FP32_HILO).  theta = u l + v m + w (n - 1) is
+ * formed without float64: every coordinate is split once into a float32 pair
+ * a = a_hi + a_lo, each product's leading part a_hi b_hi is split exactly into
+ * its rounding p and error e (an FMA), p is reduced exactly to p - rint(p) in
+ * [-1/2, 1/2], and the three reduced parts, the errors and the cross terms
+ * a_hi b_lo + a_lo b_hi are added in float32: about three roundings of 2^-24
+ * turn, as the float64 phase.  It costs about twenty float32 operations per
+ * entry against three float64 FMAs, so it is slower on the MI355X; it exists
+ * for precision studies.  Delta pixels only, no per-pair beam widths, no grid
+ * evaluation, no tuning or serving (SL1M_EINVAL otherwise); float32 and
+ * complex64 arrays at the ABI.
  */
 
 /*

@@ -79,6 +79,7 @@ bool analyze_grid(Analysis& a, int si, const std::vector<double>& L, const std::
                   std::string& why) {
   const Segment& sg = a.segs[si];
   if (a.precision == SL1M_PREC_FP64) return why = "the plan is float64", false;
+  if (a.precision == SL1M_PREC_FP32_HILO) return why = "the plan's phase is float32 hi/lo", false;
   if (a.beam_pair) return why = "the plan has per-pair beams", false;
   if (sg.count < 1024) return why = "fewer than 1024 pixels in the segment", false;
   const int64_t nd = sg.count;
@@ -160,7 +161,7 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   if (pr->n_pix < 0 || pr->n_vis < 0) return set_error(SL1M_EINVAL, "negative size");
   if (pr->n_pix > INT32_MAX || pr->n_vis > INT32_MAX)
     return set_error(SL1M_EINVAL, "n_pix and n_vis must be below 2^31");
-  if (pr->precision < SL1M_PREC_FP64 || pr->precision > SL1M_PREC_MFMA_BF16)
+  if (pr->precision < SL1M_PREC_FP64 || pr->precision > SL1M_PREC_FP32_HILO)
     return set_error(SL1M_EINVAL, "unknown precision");
   const bool mfma = pr->precision == SL1M_PREC_MFMA_F16 || pr->precision == SL1M_PREC_MFMA_BF16;
   if (pr->n_pix > 0 && (!pr->l || !pr->m)) return set_error(SL1M_EINVAL, "l or m is NULL");
@@ -232,8 +233,11 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
     for (int64_t j = 0; j < np && identity; ++j) identity = a.perm[j] == j;
     if (identity) a.perm.clear();
   }
+  const bool hilo = pr->precision == SL1M_PREC_FP32_HILO;
   if (mfma && a.segs.size() != 1)
     return set_error(SL1M_EINVAL, "the MFMA precisions evaluate delta pixels only");
+  if (hilo && a.segs.size() != 1)
+    return set_error(SL1M_EINVAL, "the FP32 hi/lo phase evaluates delta pixels only");
 
   // ---- gains
   a.has_gain = pr->ant_p != nullptr && pr->n_vis > 0;
@@ -268,6 +272,8 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   }
   if (mfma && a.beam_pair)
     return set_error(SL1M_EINVAL, "the MFMA precisions need one beam width for all antennas");
+  if (hilo && a.beam_pair)
+    return set_error(SL1M_EINVAL, "the FP32 hi/lo phase needs one beam width for all antennas");
 
   // ---- tiling
   const int64_t nv = pr->n_vis;
@@ -316,10 +322,12 @@ sl1m_status analyze(const sl1m_problem* pr, Analysis& a) {
   if (pr->grid_mode != SL1M_GRID_OFF && nv > 0 && np > 0) {
     std::string why = "no segment has 1024 pixels";
     if (a.precision == SL1M_PREC_FP64) why = "the plan's precision is SL1M_PREC_FP64";
+    else if (a.precision == SL1M_PREC_FP32_HILO) why = "the plan's phase is float32 hi/lo";
     else if (a.beam_pair) why = "the plan has per-pair beams";
     bool any_big = false;
     for (const Segment& sg : a.segs) any_big = any_big || sg.count >= 1024;
-    if (any_big && a.precision != SL1M_PREC_FP64 && !a.beam_pair) {
+    if (any_big && a.precision != SL1M_PREC_FP64 && a.precision != SL1M_PREC_FP32_HILO &&
+        !a.beam_pair) {
       std::vector<double> L(np), M(np);
       if (sl1m_status e = d2h(L.data(), pr->l, np * sizeof(double), "read l")) return e;
       if (sl1m_status e = d2h(M.data(), pr->m, np * sizeof(double), "read m")) return e;
@@ -505,7 +513,7 @@ struct Layout {
       rres, rpol, layerDs, chunks, fpart, apart, xperm, img, zbuf, res, red, red_out, flag, scal,
       grid_la,
       grid_mb, grid_c3, grid_c4, grid_slot, grid_rec, grid_fc, grid_pb, grid_segs, grid_gb,
-      grid_prec, grid_precm, mx, mr, mred, grid_mfma_b, grid_mfma_nu, total;
+      grid_prec, grid_precm, mx, mr, mred, grid_mfma_b, grid_mfma_nu, phl, vhl, total;
 };
 
 Layout layout(const Analysis& a) {
@@ -523,7 +531,8 @@ Layout layout(const Analysis& a) {
   const size_t npt = a.pd.size() + a.pg.size();
   L.perm = take(4 * np);
   // matrix-core plans read records in steps of 32: padded with zero records
-  const bool mf = a.precision >= SL1M_PREC_MFMA_F16;
+  const bool mf = a.precision == SL1M_PREC_MFMA_F16 || a.precision == SL1M_PREC_MFMA_BF16;
+  const bool hl = a.precision == SL1M_PREC_FP32_HILO;
   L.pixrec = take(pixrec_bytes(rb) * (mf ? 4 * static_cast<size_t>(a.mf_np4) : np));
   L.pl = take(8 * np);
   L.pm = take(8 * np);
@@ -579,6 +588,8 @@ Layout layout(const Analysis& a) {
   const size_t pairs = static_cast<size_t>(a.grid_pairs);
   L.grid_mfma_b = take(a.grid_mfma ? 64 * ngm * pairs : 0);
   L.grid_mfma_nu = take(a.grid_mfma ? 8 * pairs : 0);
+  L.phl = take(hl ? sizeof(HLRec) * static_cast<size_t>(a.n_pix) : 0);
+  L.vhl = take(hl ? sizeof(HLRec) * static_cast<size_t>(a.n_vis) : 0);
   L.total = off;
   return L;
 }
@@ -780,7 +791,9 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     p->ptiles_gauss = a.pg;
     p->adj_kchunk = a.kchunk;
     p->n_achunks = a.n_achunks;
-    p->mfma = a.precision >= SL1M_PREC_MFMA_F16 ? a.precision : 0;
+    p->mfma = a.precision == SL1M_PREC_MFMA_F16 || a.precision == SL1M_PREC_MFMA_BF16
+                  ? a.precision : 0;
+    p->hilo = a.precision == SL1M_PREC_FP32_HILO;
     p->n_mfchunks = a.n_mfchunks;
     p->mf_chunk = a.mf_chunk;
     p->mf_np4 = a.mf_np4;
@@ -838,6 +851,10 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
       p->mx = reinterpret_cast<uint16_t*>(w + L.mx);
       p->mr = reinterpret_cast<uint16_t*>(w + L.mr);
       p->mred = reinterpret_cast<float*>(w + L.mred);
+    }
+    if (p->hilo) {
+      p->phl = reinterpret_cast<HLRec*>(w + L.phl);
+      p->vhl = reinterpret_cast<HLRec*>(w + L.vhl);
     }
     p->grid_mfma = a.grid_mfma;
     if (a.grid_mfma) {
@@ -910,6 +927,7 @@ sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t wor
     if (e == hipSuccess)
       e = launch_prep_vis(p, pr->u, pr->v, pr->w, pr->ant_p, pr->ant_q, pr->ant_gain,
                           a.beam_pair ? pr->ant_fwhm : nullptr, pr->n_ant, st);
+    if (e == hipSuccess) e = launch_prep_hilo(p, st);
     if (e == hipSuccess)
       e = launch_fill(p->apart, static_cast<size_t>(p->n_achunks) * p->n_pix * p->max_rhs, a.rb,
                       st);
@@ -1041,6 +1059,8 @@ sl1m_status sl1m_tune_workspace_bytes(const sl1m_problem* problem, size_t* bytes
     if (!problem || !bytes) return set_error(SL1M_EINVAL, "NULL argument");
     if (problem->precision == SL1M_PREC_MFMA_F16 || problem->precision == SL1M_PREC_MFMA_BF16)
       return set_error(SL1M_EINVAL, "the MFMA precisions have no tuned launch shapes");
+    if (problem->precision == SL1M_PREC_FP32_HILO)
+      return set_error(SL1M_EINVAL, "the FP32 hi/lo phase has no tuned launch shapes");
     // every plan sl1m_tune may build: the default, (grid mode, split) with the
     // plan's lane counts, and direct plans with every lane count and split
     size_t mx = 0;

@@ -53,6 +53,42 @@ __device__ __forceinline__ void phasor(double t, double& c, double& s) {
   sincospi(2.0 * r, &s, &c);
 }
 
+// FP32 hi/lo phase (SL1M_PREC_FP32_HILO).  For one product a b of split
+// coordinates: p = fl(a_hi b_hi) and e = a_hi b_hi - p (exact, one FMA);
+// p - rint(p) is exact (rint by adding and subtracting 1.5 2^23, valid for
+// |p| < 2^22 turns), and e with the cross terms a_hi b_lo + a_lo b_hi (a_lo b_lo
+// is below 2^-48 |a b|) goes into `lo`.  Returns p - rint(p).  Contraction is
+// off so every rounding is the one written.
+__device__ __forceinline__ float hl_term(float ah, float al, float bh, float bl, float& lo) {
+#pragma clang fp contract(off)
+  const float p = ah * bh;
+  const float e = __builtin_fmaf(ah, bh, -p);
+  const float n = (p + 12582912.0f) - 12582912.0f;
+  lo = __builtin_fmaf(al, bh, __builtin_fmaf(ah, bl, lo + e));
+  return p - n;
+}
+
+// (cos 2 pi theta, sin 2 pi theta) with theta = u l + v m + w nu from split
+// coordinates: the three reduced parts, then the small terms, added in
+// float32 (|result| < 2 turns, inside the range v_sin_f32 / v_cos_f32 take).
+__device__ __forceinline__ void hl_phasor(const HLRec& x, float uh, float ul, float vh, float vl,
+                                          float wh, float wl, float& c, float& s) {
+#pragma clang fp contract(off)
+  float lo = 0.0f;
+  const float fu = hl_term(uh, ul, x.ah, x.al, lo);
+  const float fv = hl_term(vh, vl, x.bh, x.bl, lo);
+  const float fw = hl_term(wh, wl, x.ch, x.cl, lo);
+  const float t = ((fu + fv) + fw) + lo;
+  s = __builtin_amdgcn_sinf(t);
+  c = __builtin_amdgcn_cosf(t);
+}
+
+// float32 split of a float64 value: hi + lo with hi its float32 rounding
+__device__ __forceinline__ void hl_split(double a, float& hi, float& lo) {
+  hi = static_cast<float>(a);
+  lo = static_cast<float>(a - static_cast<double>(hi));
+}
+
 // 2^x
 __device__ __forceinline__ float pow2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ double pow2(double x) { return exp2(x); }
@@ -124,16 +160,22 @@ __device__ __forceinline__ void strided_sum(const T* __restrict__ p, int n, int6
 // One forward tile: visibilities [vtile*kBlock*VPL, +kBlock*VPL) against the
 // pixel chunk `ch`; right-hand side r goes to out_row + r*row_stride.
 // `xscale` multiplies every amplitude (1 except in batched power steps).
-template <typename R, int VPL, bool BEAM, int NR>
+// HL: the FP32 hi/lo phase (R = float, no BEAM) from the pixels' splits
+// `phl` and the lane's visibilities split once.
+template <typename R, int VPL, bool BEAM, int NR, bool HL = false>
 __device__ __forceinline__ void fwd_delta_tile(
     const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, int64_t n_pix,
     const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ vw,
     const R* __restrict__ vbeta, const Chunk& ch, int64_t vtile, int64_t n_vis,
-    C2<R>* __restrict__ out_row, int64_t row_stride, R xscale) {
+    C2<R>* __restrict__ out_row, int64_t row_stride, R xscale,
+    const HLRec* __restrict__ phl = nullptr) {
+  static_assert(!HL || (std::is_same<R, float>::value && !BEAM), "hi/lo phase: float32, no pair beams");
   const int64_t kbase = vtile * (kBlock * VPL) + threadIdx.x;
   const ConstPtr<PixRec<R>> cpix = as_const(pix);
+  const ConstPtr<HLRec> chl = as_const(phl);
   const ConstPtr<R> cxp = as_const(xp);
   double u[VPL], v[VPL], w[VPL];
+  float uh[VPL], ul[VPL], vh[VPL], vl[VPL], wh[VPL], wl[VPL];
   R beta[VPL], ore[NR][VPL], oim[NR][VPL];
 #pragma unroll
   for (int i = 0; i < VPL; ++i) {
@@ -142,6 +184,11 @@ __device__ __forceinline__ void fwd_delta_tile(
     u[i] = ok ? vu[k] : 0.0;
     v[i] = ok ? vv[k] : 0.0;
     w[i] = ok ? vw[k] : 0.0;
+    if (HL) {
+      hl_split(u[i], uh[i], ul[i]);
+      hl_split(v[i], vh[i], vl[i]);
+      hl_split(w[i], wh[i], wl[i]);
+    }
     beta[i] = (BEAM && ok) ? vbeta[k] : R(0);
 #pragma unroll
     for (int r = 0; r < NR; ++r) ore[r][i] = oim[r][i] = R(0);
@@ -156,16 +203,30 @@ __device__ __forceinline__ void fwd_delta_tile(
 #pragma unroll
       for (int i = 0; i < VPL; ++i) re[r][i] = im[r][i] = R(0);
     for (int j = j0; j < j1; ++j) {
-      const double pl = cpix[j].l, pm = cpix[j].m, pn = cpix[j].c3;
+      double pl = 0.0, pm = 0.0, pn = 0.0;
+      HLRec hx;
+      if (HL) {
+        hx.ah = chl[j].ah; hx.al = chl[j].al;
+        hx.bh = chl[j].bh; hx.bl = chl[j].bl;
+        hx.ch = chl[j].ch; hx.cl = chl[j].cl;
+      } else {
+        pl = cpix[j].l;
+        pm = cpix[j].m;
+        pn = cpix[j].c3;
+      }
       R a[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) a[r] = cpix[j].scale * xscale * cxp[r * n_pix + j];
       const R r2 = BEAM ? cpix[j].r2r : R(0);
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
-        const double t = fma(w[i], pn, fma(v[i], pm, fma(u[i], pl, origin)));
         R c, s;
-        phasor(t, c, s);
+        if constexpr (HL) {
+          hl_phasor(hx, uh[i], ul[i], vh[i], vl[i], wh[i], wl[i], c, s);
+        } else {
+          const double t = fma(w[i], pn, fma(v[i], pm, fma(u[i], pl, origin)));
+          phasor(t, c, s);
+        }
         const R b = BEAM ? pow2(beta[i] * r2) : R(1);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -300,19 +361,25 @@ __device__ __forceinline__ void fwd_gauss_tile(
 // One adjoint tile: pixels [tl.j0 + sub_i*kBlock*PPL, +kBlock*PPL) of tile `tl`
 // against visibility chunk `kc`; right-hand side r goes to
 // out_row + r*row_stride (indexed by permuted pixel).
-template <typename R, int PPL, bool BEAM, int NR>
+// HL: the FP32 hi/lo phase (R = float, no BEAM) from the visibilities'
+// splits `vhl` and the lane's pixels split once.
+template <typename R, int PPL, bool BEAM, int NR, bool HL = false>
 __device__ __forceinline__ void adj_delta_tile(
     const VisRecD<R>* __restrict__ vrec, const C2<R>* __restrict__ rres,
     const R* __restrict__ vbeta, const double* __restrict__ pl, const double* __restrict__ pm,
     const double* __restrict__ pc3, const R* __restrict__ pr2, const Chunk& tl, int sub_i,
-    int64_t kc, int64_t kchunk, int64_t n_vis, R* __restrict__ out_row, int64_t row_stride) {
+    int64_t kc, int64_t kchunk, int64_t n_vis, R* __restrict__ out_row, int64_t row_stride,
+    const HLRec* __restrict__ vhl = nullptr) {
+  static_assert(!HL || (std::is_same<R, float>::value && !BEAM), "hi/lo phase: float32, no pair beams");
   const int64_t jbase = tl.j0 + static_cast<int64_t>(sub_i) * (kBlock * PPL) + threadIdx.x;
   const ConstPtr<VisRecD<R>> cvrec = as_const(vrec);
+  const ConstPtr<HLRec> chl = as_const(vhl);
   const ConstPtr<R> cres = as_const(reinterpret_cast<const R*>(rres));
   const ConstPtr<R> cbeta = as_const(vbeta);
   const int k0 = static_cast<int>(kc * kchunk);
   const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
   double l[PPL], m[PPL], c3[PPL];
+  HLRec px[PPL];
   R r2[PPL], og[NR][PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) {
@@ -321,6 +388,11 @@ __device__ __forceinline__ void adj_delta_tile(
     l[i] = ok ? pl[j] : 0.0;
     m[i] = ok ? pm[j] : 0.0;
     c3[i] = ok ? pc3[j] : 0.0;
+    if (HL) {
+      hl_split(l[i], px[i].ah, px[i].al);
+      hl_split(m[i], px[i].bh, px[i].bl);
+      hl_split(c3[i], px[i].ch, px[i].cl);
+    }
     r2[i] = (BEAM && ok) ? pr2[j] : R(0);
 #pragma unroll
     for (int r = 0; r < NR; ++r) og[r][i] = R(0);
@@ -334,7 +406,17 @@ __device__ __forceinline__ void adj_delta_tile(
 #pragma unroll
       for (int i = 0; i < PPL; ++i) g[r][i] = R(0);
     for (int k = kk; k < ke; ++k) {
-      const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
+      double u = 0.0, v = 0.0, w = 0.0;
+      float uh = 0.0f, ul = 0.0f, vh = 0.0f, vl = 0.0f, wh = 0.0f, wl = 0.0f;
+      if (HL) {
+        uh = chl[k].ah; ul = chl[k].al;
+        vh = chl[k].bh; vl = chl[k].bl;
+        wh = chl[k].ch; wl = chl[k].cl;
+      } else {
+        u = cvrec[k].u;
+        v = cvrec[k].v;
+        w = cvrec[k].w;
+      }
       R rre[NR], rim[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -344,9 +426,13 @@ __device__ __forceinline__ void adj_delta_tile(
       const R bt = BEAM ? cbeta[k] : R(0);
 #pragma unroll
       for (int i = 0; i < PPL; ++i) {
-        const double t = fma(c3[i], w, fma(m[i], v, fma(l[i], u, origin)));
         R c, s;
-        phasor(t, c, s);
+        if constexpr (HL) {
+          hl_phasor(px[i], uh, ul, vh, vl, wh, wl, c, s);
+        } else {
+          const double t = fma(c3[i], w, fma(m[i], v, fma(l[i], u, origin)));
+          phasor(t, c, s);
+        }
         if (BEAM) {
           const R b = pow2(bt * r2[i]);
           c *= b;

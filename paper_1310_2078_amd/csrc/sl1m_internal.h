@@ -41,6 +41,13 @@ struct VisRecD {
   double u, v, w, pad;
 };
 
+// Float32 hi/lo splits of three coordinates, a = a_hi + a_lo with a_hi the
+// float32 rounding of a (SL1M_PREC_FP32_HILO): (l, m, n - 1) per pixel and
+// (u, v, w) per visibility, read via scalar loads.
+struct HLRec {
+  float ah, al, bh, bl, ch, cl, pad0, pad1;
+};
+
 // Delta residual record of the square-grid adjoint in polar form: the
 // residual's phase folded into the phase origin of the per-cell phasor,
 // org = kMagic + arg(r) / (2 pi) (turns), and mag = |r|.
@@ -218,6 +225,11 @@ struct sl1m_plan {
   bool grid_mfma = false;
   void* grid_mfma_b = nullptr;
   double* grid_mfma_nu = nullptr;
+  // FP32 hi/lo phase plans (SL1M_PREC_FP32_HILO): the coordinates' float32
+  // splits, per pixel (permuted order) and per visibility
+  bool hilo = false;
+  sl1m::HLRec* phl = nullptr;
+  sl1m::HLRec* vhl = nullptr;
 
   // grid evaluation (single right-hand side, FP32): segments on the grid path
   // and the direct chunks of the other segments
@@ -315,6 +327,8 @@ sl1m_status hip_error(hipError_t e, const char* what);
 hipError_t launch_prep_pixels(sl1m_plan* p, const double* l, const double* m,
                               const double* ant_fwhm_dev_unused, double beam_coef,
                               hipStream_t st);
+// float32 hi/lo splits of the pixel and visibility coordinates (hi/lo plans)
+hipError_t launch_prep_hilo(sl1m_plan* p, hipStream_t st);
 hipError_t launch_prep_vis(sl1m_plan* p, const double* u, const double* v, const double* w,
                            const int32_t* ap, const int32_t* aq, const double* gain,
                            const double* fwhm, int32_t n_ant, hipStream_t st);

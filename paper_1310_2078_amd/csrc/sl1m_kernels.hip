@@ -42,16 +42,16 @@ using namespace dev;
 // NR right-hand sides share every phasor: x is [NR][n_pix] (permuted order),
 // partial rows are [NR][n_rows][n_vis].
 
-template <typename R, int VPL, bool BEAM, int NR>
+template <typename R, int VPL, bool BEAM, int NR, bool HL>
 __global__ __launch_bounds__(kBlock) void k_fwd_delta(
     const PixRec<R>* __restrict__ pix, const R* __restrict__ xp, int64_t n_pix,
     const double* __restrict__ vu, const double* __restrict__ vv, const double* __restrict__ vw,
     const R* __restrict__ vbeta, const Chunk* __restrict__ chunks, int64_t n_vis,
-    C2<R>* __restrict__ part, int row0, int n_rows) {
+    C2<R>* __restrict__ part, int row0, int n_rows, const HLRec* __restrict__ phl) {
   const Chunk ch = chunks[blockIdx.y];
-  fwd_delta_tile<R, VPL, BEAM, NR>(pix, xp, n_pix, vu, vv, vw, vbeta, ch, blockIdx.x, n_vis,
-                                   part + static_cast<int64_t>(row0 + blockIdx.y) * n_vis,
-                                   static_cast<int64_t>(n_rows) * n_vis, R(1));
+  fwd_delta_tile<R, VPL, BEAM, NR, HL>(pix, xp, n_pix, vu, vv, vw, vbeta, ch, blockIdx.x, n_vis,
+                                       part + static_cast<int64_t>(row0 + blockIdx.y) * n_vis,
+                                       static_cast<int64_t>(n_rows) * n_vis, R(1), phl);
 }
 
 template <typename R, int VPL, bool BEAM, int NR>
@@ -75,17 +75,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd_gauss(
 // Residual records: rres[(layer_slot * n_vis + k) * NR + r] (slot 0 = delta,
 // slot 1 + L = Gaussian layer L).  Partial rows are [NR][gridDim.y][n_pix].
 
-template <typename R, int PPL, bool BEAM, int NR>
+template <typename R, int PPL, bool BEAM, int NR, bool HL>
 __global__ __launch_bounds__(kBlock) void k_adj_delta(
     const VisRecD<R>* __restrict__ vrec, const C2<R>* __restrict__ rres,
     const R* __restrict__ vbeta, const double* __restrict__ pl, const double* __restrict__ pm,
     const double* __restrict__ pc3, const R* __restrict__ pr2, const Chunk* __restrict__ tiles,
-    int sub, int64_t kchunk, int64_t n_vis, int64_t n_pix, R* __restrict__ part) {
+    int sub, int64_t kchunk, int64_t n_vis, int64_t n_pix, R* __restrict__ part,
+    const HLRec* __restrict__ vhl) {
   const Chunk tl = tiles[blockIdx.x / sub];
-  adj_delta_tile<R, PPL, BEAM, NR>(vrec, rres, vbeta, pl, pm, pc3, pr2, tl, blockIdx.x % sub,
-                                   blockIdx.y, kchunk, n_vis,
-                                   part + static_cast<int64_t>(blockIdx.y) * n_pix,
-                                   static_cast<int64_t>(gridDim.y) * n_pix);
+  adj_delta_tile<R, PPL, BEAM, NR, HL>(vrec, rres, vbeta, pl, pm, pc3, pr2, tl, blockIdx.x % sub,
+                                       blockIdx.y, kchunk, n_vis,
+                                       part + static_cast<int64_t>(blockIdx.y) * n_pix,
+                                       static_cast<int64_t>(gridDim.y) * n_pix, vhl);
 }
 
 template <typename R, int PPL, bool BEAM, int NR>
@@ -566,7 +567,7 @@ inline unsigned grid1(int64_t n, int b = kBlock) { return static_cast<unsigned>(
 // Direct-evaluation forward launches.  With `grid` only the segments that are
 // not on the grid path are evaluated here (chunk lists fd1, fg1), into the
 // partial rows after the grid segments' rows.
-template <typename R, int VPL, bool BEAM, int NR>
+template <typename R, int VPL, bool BEAM, int NR, bool HL = false>
 hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st, bool grid = false) {
   const int64_t vt = (p->n_vis + kBlock * VPL - 1) / (kBlock * VPL);
   C2<R>* part = static_cast<C2<R>*>(p->fpart);
@@ -576,10 +577,11 @@ hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st, bool grid 
   const int row0 = grid ? p->grid_frows : 0;
   const int rows = row0 + nd + ng;
   if (nd > 0) {
-    hipLaunchKernelGGL((k_fwd_delta<R, VPL, BEAM, NR>), dim3(static_cast<unsigned>(vt), nd),
+    hipLaunchKernelGGL((k_fwd_delta<R, VPL, BEAM, NR, HL>), dim3(static_cast<unsigned>(vt), nd),
                        dim3(kBlock), 0, st, static_cast<const PixRec<R>*>(p->pixrec),
                        static_cast<const R*>(xp), p->n_pix, p->vu, p->vv, p->vw,
-                       static_cast<const R*>(p->vbeta), dch, p->n_vis, part, row0, rows);
+                       static_cast<const R*>(p->vbeta), dch, p->n_vis, part, row0, rows,
+                       static_cast<const HLRec*>(p->phl));
   }
   if (ng > 0) {
     hipLaunchKernelGGL((k_fwd_gauss<R, VPL, BEAM, NR>), dim3(static_cast<unsigned>(vt), ng),
@@ -593,7 +595,7 @@ hipError_t fwd_launch_t(sl1m_plan* p, const void* xp, hipStream_t st, bool grid 
 
 // Direct-evaluation adjoint launches; with `grid` only the tiles of segments
 // that are not on the grid path (pd1, pg1).
-template <typename R, int PPL, bool BEAM, int NR>
+template <typename R, int PPL, bool BEAM, int NR, bool HL = false>
 hipError_t adj_launch_t(sl1m_plan* p, hipStream_t st, bool grid = false) {
   R* part = static_cast<R*>(p->apart);
   const Chunk* dt = grid ? p->d_chunks1 + p->fd1.size() + p->fg1.size() : p->d_ptiles;
@@ -602,11 +604,11 @@ hipError_t adj_launch_t(sl1m_plan* p, hipStream_t st, bool grid = false) {
   const int sub = p->adj_ppl / PPL;  // blocks per plan tile
   const C2<R>* rres = static_cast<const C2<R>*>(p->rres);
   if (nd > 0) {
-    hipLaunchKernelGGL((k_adj_delta<R, PPL, BEAM, NR>), dim3(nd * sub, p->n_achunks), dim3(kBlock),
-                       0, st, static_cast<const VisRecD<R>*>(p->visrecD), rres,
+    hipLaunchKernelGGL((k_adj_delta<R, PPL, BEAM, NR, HL>), dim3(nd * sub, p->n_achunks),
+                       dim3(kBlock), 0, st, static_cast<const VisRecD<R>*>(p->visrecD), rres,
                        static_cast<const R*>(p->vbeta), p->pl, p->pm, p->pc3,
                        static_cast<const R*>(p->pr2), dt, sub, p->adj_kchunk, p->n_vis,
-                       p->n_pix, part);
+                       p->n_pix, part, static_cast<const HLRec*>(p->vhl));
   }
   if (ng > 0) {
     hipLaunchKernelGGL((k_adj_gauss<R, PPL, BEAM, NR>), dim3(ng * sub, p->n_achunks), dim3(kBlock),
@@ -660,6 +662,31 @@ hipError_t launch_prep_vis(sl1m_plan* p, const double* u, const double* v, const
   return SL1M_DISPATCH_R(p, prep_vis_t, p, u, v, w, ap, aq, gain, fwhm, p->red, st);
 }
 
+// Float32 hi/lo splits of (l, m, n - 1) per pixel and (u, v, w) per
+// visibility (SL1M_PREC_FP32_HILO), from the plan's float64 arrays.
+__global__ void k_prep_hilo(const double* __restrict__ a, const double* __restrict__ b,
+                            const double* __restrict__ c, int64_t n, HLRec* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  HLRec r;
+  hl_split(a[i], r.ah, r.al);
+  hl_split(b[i], r.bh, r.bl);
+  hl_split(c[i], r.ch, r.cl);
+  r.pad0 = r.pad1 = 0.0f;
+  out[i] = r;
+}
+
+hipError_t launch_prep_hilo(sl1m_plan* p, hipStream_t st) {
+  if (!p->hilo) return hipSuccess;
+  if (p->n_pix > 0)
+    hipLaunchKernelGGL(k_prep_hilo, dim3(grid1(p->n_pix)), dim3(kBlock), 0, st, p->pl, p->pm,
+                       p->pc3, p->n_pix, p->phl);
+  if (p->n_vis > 0)
+    hipLaunchKernelGGL(k_prep_hilo, dim3(grid1(p->n_vis)), dim3(kBlock), 0, st, p->vu, p->vv,
+                       p->vw, p->n_vis, p->vhl);
+  return hipGetLastError();
+}
+
 template <typename R>
 static hipError_t gather_t(sl1m_plan* p, const void* x, void* xp, int nr, hipStream_t st) {
   if (p->n_pix == 0) return hipSuccess;
@@ -692,9 +719,54 @@ static bool mfma_adjoint_call(const sl1m_plan* p, int nr) {
   return p->mfma == SL1M_PREC_MFMA_F16 && nr >= 4;
 }
 
+// FP32 hi/lo phase plans: delta pixels, no pair beams, no grid; lanes per
+// thread chosen as for the FP32 direct kernels.
+static hipError_t forward_hilo(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
+  switch (nr) {
+    case 1:
+      if (p->fwd_vpl == 1) return fwd_launch_t<float, 1, false, 1, true>(p, xp, st);
+      if (p->fwd_vpl == 2) return fwd_launch_t<float, 2, false, 1, true>(p, xp, st);
+      return fwd_launch_t<float, 4, false, 1, true>(p, xp, st);
+    case 2:
+      if (p->fwd_vpl >= 4) return fwd_launch_t<float, 4, false, 2, true>(p, xp, st);
+      return fwd_launch_t<float, 2, false, 2, true>(p, xp, st);
+    case 4:
+      if (p->fwd_vpl >= 2) return fwd_launch_t<float, 2, false, 4, true>(p, xp, st);
+      return fwd_launch_t<float, 1, false, 4, true>(p, xp, st);
+    case 8:
+      if (p->fwd_vpl >= 2) return fwd_launch_t<float, 2, false, 8, true>(p, xp, st);
+      return fwd_launch_t<float, 1, false, 8, true>(p, xp, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+static hipError_t adjoint_hilo(sl1m_plan* p, int nr, hipStream_t st) {
+  switch (nr) {
+    case 1:
+      if (p->adj_ppl == 1) return adj_launch_t<float, 1, false, 1, true>(p, st);
+      if (p->adj_ppl == 2) return adj_launch_t<float, 2, false, 1, true>(p, st);
+      return adj_launch_t<float, 4, false, 1, true>(p, st);
+    case 2:
+      if (p->adj_ppl == 1) return adj_launch_t<float, 1, false, 2, true>(p, st);
+      return adj_launch_t<float, 2, false, 2, true>(p, st);
+    case 4:
+      return adj_launch_t<float, 1, false, 4, true>(p, st);
+    case 8:
+      return adj_launch_t<float, 1, false, 8, true>(p, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 template <typename R>
 static hipError_t forward_t(sl1m_plan* p, const void* xp, int nr, hipStream_t st) {
   if (mfma_forward_call(p, nr)) return launch_mfma_forward(p, xp, nr, st);
+  if constexpr (std::is_same<R, float>::value) {
+    if (p->hilo) {
+      if (p->n_vis == 0 || p->n_fchunks == 0) return hipSuccess;
+      return forward_hilo(p, xp, nr, st);
+    }
+  }
   if (p->n_vis == 0 || p->n_fchunks == 0) return hipSuccess;
   const bool bm = p->beam_pair;
   if (nr == 1 && p->grid) {
@@ -781,6 +853,9 @@ template <typename R>
 static hipError_t adjoint_t(sl1m_plan* p, int nr, hipStream_t st) {
   if (mfma_adjoint_call(p, nr)) return launch_mfma_adjoint(p, nr, st);
   if (p->n_pix == 0 || p->n_achunks == 0) return hipSuccess;
+  if constexpr (std::is_same<R, float>::value) {
+    if (p->hilo) return adjoint_hilo(p, nr, st);
+  }
   const bool bm = p->beam_pair;
   if (nr == 1 && p->grid) {
     hipError_t e = launch_grid_adjoint(p, st);

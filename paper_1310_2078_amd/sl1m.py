@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libsl1m.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, EDIVERGED, ECANCELLED = 0, -1, -2, -3, -4, -5, -6
 PIX_DELTA, PIX_GAUSS_PARAXIAL, PIX_GAUSS_WIDE = 0, 1, 2
-PREC_FP64, PREC_FP32, PREC_MFMA_F16, PREC_MFMA_BF16 = 0, 1, 2, 3
+PREC_FP64, PREC_FP32, PREC_MFMA_F16, PREC_MFMA_BF16, PREC_FP32_HILO = 0, 1, 2, 3, 4
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "mfma_f16": PREC_MFMA_F16,
-              "mfma_bf16": PREC_MFMA_BF16}
+              "mfma_bf16": PREC_MFMA_BF16, "fp32_hilo": PREC_FP32_HILO}
 
 _lib = None
 
@@ -251,9 +251,10 @@ class Plan:
 
     Inputs are NumPy arrays or torch tensors; they are copied to the device
     and kept alive with the plan.  ``precision`` is "fp32" (FP64 phase,
-    FP32 sincos/accumulation), "fp64", or "mfma_f16" / "mfma_bf16" (the FP32
+    FP32 sincos/accumulation), "fp64", "mfma_f16" / "mfma_bf16" (the FP32
     entries and the images or residuals rounded to float16 / bfloat16 and
-    contracted on the matrix cores; delta pixels only).
+    contracted on the matrix cores; delta pixels only), or "fp32_hilo" (the
+    phase in float32 hi/lo arithmetic instead of FP64; delta pixels only).
     """
 
     def __init__(self, l, m, u, v, w, sigma=None, kind=None, ant_p=None, ant_q=None,

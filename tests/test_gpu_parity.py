@@ -21,7 +21,11 @@ from paper_1310_2078_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "fp64": 1e-11}
+TOL = {"fp32": 1e-5, "fp64": 1e-11, "fp32_hilo": 1e-5}
+# element-wise bound of each precision (the hi/lo phase plan accumulates in
+# float32 and its phase is off by about three roundings of 2^-24 turn, as the
+# FP32 plan's)
+EPREC = {"fp32": "fp32", "fp64": "fp64", "fp32_hilo": "fp32"}
 
 
 def say(*a):
@@ -54,8 +58,8 @@ def _check_ops(wl, prec, tag, x=None, r=None):
     gg = plan.adjoint(r).cpu().numpy()
     go = O.adjoint(p, r)
     ef, ea = rel(Vg, Vo), rel(gg, go)
-    wf = E.worst_ratio(Vg, Vo, E.abs_forward_rows(p, x), wl.n_pix, prec)
-    wa = E.worst_ratio(gg, go, E.abs_adjoint_cols(p, r), wl.n_vis, prec)
+    wf = E.worst_ratio(Vg, Vo, E.abs_forward_rows(p, x), wl.n_pix, EPREC[prec])
+    wa = E.worst_ratio(gg, go, E.abs_adjoint_cols(p, r), wl.n_vis, EPREC[prec])
     say(f"    forward rel err {ef:.3e}  adjoint rel err {ea:.3e}  "
         f"element-wise (fraction of bound) forward {wf:.3e} adjoint {wa:.3e}")
     assert ef <= TOL[prec] and ea <= TOL[prec]
@@ -63,7 +67,7 @@ def _check_ops(wl, prec, tag, x=None, r=None):
     return plan
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp32_hilo"])
 def test_config1_operators(prec):
     _check_ops(W.config1(), prec, "config1")
 
@@ -139,6 +143,36 @@ def test_config2_long_baseline_precision_stress():
                      wl.u[sub], wl.v[sub], wl.w[sub])
     assert np.max(np.abs(wl2.u)) > 2500
     _check_ops(wl2, "fp32", "config2 6km stress")
+
+
+@pytest.mark.parametrize("gains", [False, True])
+def test_hilo_phase_irregular_ragged(gains):
+    """The FP32 hi/lo phase plan on off-grid delta pixels with a ragged tail
+    (and separable gains with one beam width): within the FP32 bounds."""
+    wl = W.small_random(5, 2537, 3001, with_gains=gains, uv_radius=1200.0, w_sigma=300.0)
+    plan = _check_ops(wl, "fp32_hilo", f"hilo irregular gains={gains}")
+    assert plan.info()["grid"] == 0
+
+
+def test_hilo_phase_long_baseline_stress():
+    """The radius-3 km array of the FP64-phase stress test (phases ~1e4 rad)
+    with the phase formed in float32 hi/lo: the same tolerance holds."""
+    wl = W.config2(diameter_m=6000.0)
+    sub = np.arange(0, wl.n_vis, 8)
+    pix = np.arange(0, wl.n_pix, 16)
+    wl2 = W.Workload("stress", wl.l[pix], wl.m[pix], wl.sigma[pix], wl.kind[pix],
+                     wl.u[sub], wl.v[sub], wl.w[sub])
+    _check_ops(wl2, "fp32_hilo", "config2 6km stress, hi/lo phase")
+
+
+def test_hilo_phase_rejects_gaussian_and_pair_beams():
+    say("[case] hilo rejects")
+    wl = W.small_random(9, 300, 200, kind=W.PIX_GAUSS_WIDE, sigma=2e-3)
+    with pytest.raises(sl1m.SL1MError):
+        sl1m.Plan.from_workload(wl, precision="fp32_hilo")
+    wl = W.small_random(9, 300, 200, with_gains=True, distinct_fwhm=True)
+    with pytest.raises(sl1m.SL1MError):
+        sl1m.Plan.from_workload(wl, precision="fp32_hilo")
 
 
 def test_empty_inputs():
@@ -281,7 +315,7 @@ def test_kernel_timing_counts_launches():
     assert t["forward"][1] > 0
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp32_hilo"])
 def test_config3_multi_rhs_stokes(prec):
     """Config 3: Stokes I, Q, U, V of config 1's sky through one operator pass;
     error reported per product (forward and adjoint, per right-hand side)."""
