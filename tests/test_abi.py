@@ -114,9 +114,13 @@ def test_matrix_core_workspace_and_issue_rate_checks(L):
     assert L.sl1m_issue_scratch_bytes(None) == sl1m.EINVAL
     assert L.sl1m_issue_rates(None, 0, None, None) == sl1m.EINVAL
     pr = sl1m.Problem(n_pix=10, l=fake, m=fake, n_vis=10, u=fake, v=fake, w=fake,
-                      precision=4)
+                      precision=sl1m.PREC_FP32_HILO + 1)
     assert L.sl1m_plan_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
     assert b"precision" in L.sl1m_last_error()
+    pr = sl1m.Problem(n_pix=10, l=fake, m=fake, n_vis=10, u=fake, v=fake, w=fake,
+                      precision=sl1m.PREC_FP32_HILO)
+    assert L.sl1m_tune_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
+    assert b"hi/lo" in L.sl1m_last_error()
     pr = sl1m.Problem(n_pix=10, l=fake, m=fake, n_vis=10, u=fake, v=fake, w=fake,
                       precision=sl1m.PREC_MFMA_F16)
     assert L.sl1m_tune_workspace_bytes(ctypes.byref(pr), ctypes.byref(nbytes)) == sl1m.EINVAL
