@@ -466,16 +466,18 @@ typedef struct {
   int64_t completed_rounds;  /* rounds known to have finished on the GPU     */
   double evals_scheduled;    /* operator evaluations launched so far          */
   uint64_t arena_bytes;      /* usable arena bytes                            */
-  uint64_t arena_used;       /* bytes held by admitted requests               */
+  uint64_t arena_used;       /* bytes held by admitted and reserved requests  */
   int32_t active;            /* requests on the GPU                           */
-  int32_t pending;           /* requests waiting for admission                */
+  int32_t pending;           /* requests waiting for admission or being admitted */
 } sl1m_server_stats_t;
 
 /* arena: device memory owned by the caller (256-byte aligned), kept alive
  * until sl1m_server_destroy(); max_slots: at most this many requests on the
  * GPU at once (1..64); round_budget_evals: work per round (<= 0 selects 3e10,
  * about 10 ms of operator work).  The server creates its own non-blocking
- * streams. */
+ * streams (rounds, second lane, admission, result read-back) and one host
+ * thread that builds admitted requests' plans on the current device;
+ * sl1m_server_destroy() ends it after the build in progress. */
 sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
                                double round_budget_evals, sl1m_server** out);
 
@@ -492,7 +494,8 @@ typedef enum {
 sl1m_status sl1m_server_set_policy(sl1m_server* server, int32_t policy);
 
 /* Queue one solve.  problem: as for sl1m_plan_create (FP32, max_rhs <= 1); its
- * arrays must stay valid until the request is admitted; its tile_blocks sets
+ * arrays must stay valid until the request is admitted (sl1m_server_poll's
+ * times[1] > 0) or done; its tile_blocks sets
  * the request's work-item split (0: 2048, the best of a sweep on a saturated
  * stream of mixed requests).  vis: complex64
  * [n_vis] data and img_out: float32 [n_pix] result, both device pointers valid
@@ -503,10 +506,15 @@ sl1m_status sl1m_server_submit(sl1m_server* server, const sl1m_problem* problem,
                                const void* vis, const sl1m_solve_params* params,
                                void* img_out, uint64_t* ticket);
 
-/* One scheduling step: release finished requests, admit waiting ones that fit,
- * launch the next round (asynchronous; at most 4 rounds are in flight, after
- * which the step waits for the oldest).  Reports the numbers of active and
- * waiting requests (either pointer may be NULL). */
+/* One scheduling step: release finished requests; move requests whose plans
+ * the server's admission thread has built into the rounds (in submission
+ * order); reserve arena memory and a slot for waiting requests that fit and
+ * hand them to that thread; launch the next round (asynchronous; at most 4
+ * rounds are in flight, after which the step waits for the oldest).  Plans
+ * are built on the thread's own stream while rounds run, so a request becomes
+ * active a step or more after its reservation.  Reports the numbers of active
+ * requests and of waiting ones, those being admitted included (either pointer
+ * may be NULL). */
 sl1m_status sl1m_server_step(sl1m_server* server, int32_t* n_active, int32_t* n_pending);
 
 /* *done = 1 once the request's image is in img_out and info (host) is final;

@@ -8,15 +8,20 @@
 // over a table listing every active request's work items for that round.  The
 // item decomposition and every reduction order depend only on the request's
 // own plan, so a request's result is bitwise the same alone and in any mix.
-// Requests submitted while others run join at the next round.
+// Requests submitted while others run join a round once a host thread of
+// the server has built their plans (on a stream of its own, off the step
+// loop).
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sl1m_grid.h"
@@ -532,13 +537,16 @@ __global__ __launch_bounds__(kBlock) void k_srv_ggadj_pairs(const TabDev* __rest
 // host side
 // ---------------------------------------------------------------------------
 
+// A request moves PENDING -> ADMITTING (arena and slot reserved by the step
+// loop, plan built by the admission thread) -> ACTIVE (in the rounds) -> DONE,
+// or to CANCELLED from any state before DONE.
 struct Ticket {
   sched::Request req;
   sl1m_problem problem;
   const void* vis = nullptr;
   void* img_out = nullptr;
   sl1m_solve_params params{};
-  enum State { PENDING, ACTIVE, DONE, CANCELLED } state = PENDING;
+  enum State { PENDING, ADMITTING, ACTIVE, DONE, CANCELLED } state = PENDING;
   sl1m_plan* plan = nullptr;
   size_t arena_off = 0;
   size_t footprint = 0;
@@ -546,6 +554,10 @@ struct Ticket {
   double submit_s = 0, admit_s = 0, finish_s = 0;
   bool freed = true;
   bool grid_allowed = false;
+  // written by the admission thread, read by the step loop once `built` is set
+  std::atomic<int> built{0};
+  sl1m_status build_status = SL1M_OK;
+  int8_t fwd_variant = 0, adj_variant = 0, grid_kind = 0, lane = 0;
 };
 
 }  // namespace
@@ -562,8 +574,16 @@ struct sl1m_server {
   hipStream_t stream = nullptr;        // rounds (non-blocking, default priority)
   hipStream_t lane_stream = nullptr;   // the second lane of each round
   hipEvent_t lane_event[sl1m::kSrvRing] = {};  // end of the second lane's round
-  hipStream_t admit_stream = nullptr;  // plan creation of admitted requests
-  hipEvent_t admit_event = nullptr;
+  hipStream_t admit_stream = nullptr;  // plan creation of admitted requests (admission thread)
+  hipStream_t read_stream = nullptr;   // results of finished requests (step loop)
+  int device = 0;
+  // admission thread: builds the plans of reserved requests in submission order
+  std::thread admitter;
+  std::mutex wq_mu;
+  std::condition_variable wq_cv;
+  std::deque<sl1m::Ticket*> wq;
+  bool wq_stop = false;
+  std::deque<uint64_t> admitting;       // reserved requests, in submission order
   sl1m::ReqDev* d_reqs = nullptr;
   sl1m::TabDev* d_tabs = nullptr;      // [kSrvRing][kSrvLanes][kTabs]
   sl1m::TabDev* h_tabs = nullptr;      // pinned mirror
@@ -632,17 +652,17 @@ void harvest(sl1m_server* s) {
     for (uint64_t id : s->finishing.front().second) {
       Ticket& t = *s->tickets[id];
       if (t.state != Ticket::ACTIVE) continue;
-      // the round has completed; read through the (non-blocking) admission
-      // stream so that rounds still in flight are not waited for
+      // the round has completed; read through a stream of its own so that
+      // neither rounds in flight nor admissions are waited for
       ReqDev q;
       int nonfinite = 0;
       hipError_t e = hipMemcpyAsync(&q, s->d_reqs + t.req.slot, sizeof(ReqDev),
-                                    hipMemcpyDeviceToHost, s->admit_stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(s->admit_stream);
+                                    hipMemcpyDeviceToHost, s->read_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->read_stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(&nonfinite, q.flag, sizeof(int), hipMemcpyDeviceToHost,
-                           s->admit_stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(s->admit_stream);
+                           s->read_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->read_stream);
       if (e != hipSuccess) {
         t.info.status = SL1M_EHIP;
       } else {
@@ -803,11 +823,10 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   q.xscale = xscale;
   auto variant = [&](int per_lane) { return plan->beam_pair ? 3 : (per_lane == 4 ? 2 : per_lane == 2 ? 1 : 0); };
   const int gvar = gkind >= 3 ? kSquareVariant : kGridVariant;
-  s->fwd_variant[t.req.slot] = static_cast<int8_t>(gkind ? gvar : variant(q.vpl));
-  s->adj_variant[t.req.slot] = static_cast<int8_t>(gkind ? gvar : variant(q.ppl));
-  s->grid_kind[t.req.slot] = static_cast<int8_t>(gkind == 3 ? 1 : gkind == 4 ? 2 : gkind);
-  s->lane[t.req.slot] = static_cast<int8_t>(
-      s->grid_kind[t.req.slot] == 2 || (gkind == 0 && !plan->ptiles_gauss.empty()) ? 1 : 0);
+  t.fwd_variant = static_cast<int8_t>(gkind ? gvar : variant(q.vpl));
+  t.adj_variant = static_cast<int8_t>(gkind ? gvar : variant(q.ppl));
+  t.grid_kind = static_cast<int8_t>(gkind == 3 ? 1 : gkind == 4 ? 2 : gkind);
+  t.lane = static_cast<int8_t>(t.grid_kind == 2 || (gkind == 0 && !plan->ptiles_gauss.empty()) ? 1 : 0);
   SRV_HIP(hipMemcpyAsync(s->d_reqs + t.req.slot, &q, sizeof(ReqDev), hipMemcpyHostToDevice, st),
           "upload request descriptor");
   SRV_HIP(hipStreamSynchronize(st), "admission sync");
@@ -850,6 +869,69 @@ sl1m_status admit(sl1m_server* s, Ticket& t) {
   sh.max_iter = t.params.max_iter;
   sched::start_request(t.req);
   return SL1M_OK;
+}
+
+// The admission thread: builds the plan, start vector and device descriptor
+// of each reserved request (admit()) on the admission stream, in submission
+// order, without the server lock, so the step loop keeps launching rounds
+// meanwhile.  It touches only the ticket's own fields, the request's arena
+// range and its reserved slot of the descriptor table, none of which a round
+// in flight reads.
+void admission_thread(sl1m_server* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    Ticket* t = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->wq_mu);
+      s->wq_cv.wait(lk, [&] { return s->wq_stop || !s->wq.empty(); });
+      if (s->wq_stop) return;
+      t = s->wq.front();
+      s->wq.pop_front();
+    }
+    sl1m_status st;
+    try {
+      st = admit(s, *t);
+    } catch (...) {
+      st = set_error(SL1M_ENOMEM, "host allocation failed");
+    }
+    t->build_status = st;
+    t->built.store(1, std::memory_order_release);
+  }
+}
+
+// Returns a reserved request's plan, arena range and slot.
+void release_reserved(sl1m_server* s, Ticket& t) {
+  if (t.plan) sl1m_plan_destroy(t.plan);
+  t.plan = nullptr;
+  s->alloc.release(t.arena_off);
+  s->free_slots.push_back(t.req.slot);
+  t.freed = true;
+}
+
+// Moves built requests into the rounds, in submission order (the admission
+// thread builds in that order, so the first unbuilt one ends the pass).
+void integrate_admitted(sl1m_server* s) {
+  while (!s->admitting.empty()) {
+    Ticket& t = *s->tickets[s->admitting.front()];
+    if (!t.built.load(std::memory_order_acquire)) break;
+    s->admitting.pop_front();
+    if (t.state == Ticket::CANCELLED) {
+      release_reserved(s, t);
+    } else if (t.build_status != SL1M_OK) {
+      release_reserved(s, t);
+      t.state = Ticket::DONE;
+      t.info.status = t.build_status;
+    } else {
+      const int slot = t.req.slot;
+      s->fwd_variant[slot] = t.fwd_variant;
+      s->adj_variant[slot] = t.adj_variant;
+      s->grid_kind[slot] = t.grid_kind;
+      s->lane[slot] = t.lane;
+      t.admit_s = now_s(s);
+      t.state = Ticket::ACTIVE;
+      s->active.push_back(t.req.ticket);
+    }
+  }
 }
 
 sl1m_status launch_round(sl1m_server* s) {
@@ -1017,8 +1099,12 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
     SRV_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "round stream");
     SRV_HIP(hipStreamCreateWithFlags(&s->lane_stream, hipStreamNonBlocking), "lane stream");
     SRV_HIP(hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking), "admission stream");
+    SRV_HIP(hipStreamCreateWithFlags(&s->read_stream, hipStreamNonBlocking), "result stream");
+    SRV_HIP(hipGetDevice(&s->device), "current device");
     for (auto& e : s->ring_event) SRV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
     for (auto& e : s->lane_event) SRV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    sl1m_server* srv = s.get();
+    s->admitter = std::thread(admission_thread, srv);
     *out = s.release();
     return SL1M_OK;
   } catch (...) {
@@ -1086,7 +1172,9 @@ sl1m_status sl1m_server_step(sl1m_server* s, int32_t* n_active, int32_t* n_pendi
     if (!s) return set_error(SL1M_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     harvest(s);
-    // admit pending requests (in submission order) while slots and memory allow
+    integrate_admitted(s);
+    // reserve memory and a slot for pending requests (in submission order)
+    // while both allow, and hand them to the admission thread
     for (auto it = s->pending.begin(); it != s->pending.end() && !s->free_slots.empty();) {
       Ticket& t = *s->tickets[*it];
       size_t off = 0;
@@ -1098,21 +1186,13 @@ sl1m_status sl1m_server_step(sl1m_server* s, int32_t* n_active, int32_t* n_pendi
       t.req.slot = s->free_slots.back();
       s->free_slots.pop_back();
       t.freed = false;
-      sl1m_status st = admit(s, t);
-      if (st != SL1M_OK) {
-        if (t.plan) sl1m_plan_destroy(t.plan);
-        t.plan = nullptr;
-        s->alloc.release(off);
-        s->free_slots.push_back(t.req.slot);
-        t.freed = true;
-        t.state = Ticket::DONE;
-        t.info.status = st;
-        it = s->pending.erase(it);
-        continue;
+      t.state = Ticket::ADMITTING;
+      s->admitting.push_back(t.req.ticket);
+      {
+        std::lock_guard<std::mutex> wl(s->wq_mu);
+        s->wq.push_back(&t);
       }
-      t.admit_s = now_s(s);
-      t.state = Ticket::ACTIVE;
-      s->active.push_back(t.req.ticket);
+      s->wq_cv.notify_one();
       it = s->pending.erase(it);
     }
     sl1m_status st = launch_round(s);
@@ -1122,7 +1202,7 @@ sl1m_status sl1m_server_step(sl1m_server* s, int32_t* n_active, int32_t* n_pendi
         if (s->tickets[id]->state == Ticket::ACTIVE) ++a;
       *n_active = a;
     }
-    if (n_pending) *n_pending = static_cast<int32_t>(s->pending.size());
+    if (n_pending) *n_pending = static_cast<int32_t>(s->pending.size() + s->admitting.size());
     return st;
   } catch (...) {
     return set_error(SL1M_EINVAL, "unexpected host error");
@@ -1136,10 +1216,11 @@ sl1m_status sl1m_server_poll(sl1m_server* s, uint64_t ticket, sl1m_solve_info* i
   auto it = s->tickets.find(ticket);
   if (it == s->tickets.end()) return set_error(SL1M_EINVAL, "unknown ticket");
   // rounds already launched may still read a cancelled request's data and
-  // write its image: it is done only once they have all completed and its
-  // memory has been released (harvest), so the caller may then free vis and
-  // img_out
+  // write its image, and the admission thread may still be building it: it is
+  // done only once all of them have ended and its memory has been released
+  // (harvest, integrate_admitted), so the caller may then free vis and img_out
   harvest(s);
+  integrate_admitted(s);
   Ticket& t = *it->second;
   *done = t.state == Ticket::DONE || (t.state == Ticket::CANCELLED && t.freed);
   if (info) *info = t.info;
@@ -1165,6 +1246,8 @@ sl1m_status sl1m_server_cancel(sl1m_server* s, uint64_t ticket) {
         break;
       }
     t.state = Ticket::CANCELLED;
+  } else if (t.state == Ticket::ADMITTING) {
+    t.state = Ticket::CANCELLED;  // released once its build has ended (integrate_admitted)
   } else if (t.state == Ticket::ACTIVE) {
     t.req.cancelled = true;
     t.state = Ticket::CANCELLED;
@@ -1184,15 +1267,24 @@ sl1m_status sl1m_server_stats(sl1m_server* s, sl1m_server_stats_t* out) {
   for (uint64_t id : s->active)
     if (s->tickets[id]->state == Ticket::ACTIVE) ++a;
   out->active = a;
-  out->pending = static_cast<int32_t>(s->pending.size());
+  out->pending = static_cast<int32_t>(s->pending.size() + s->admitting.size());
   return SL1M_OK;
 }
 
 sl1m_status sl1m_server_destroy(sl1m_server* s) {
   if (!s) return SL1M_OK;
+  if (s->admitter.joinable()) {  // ends after the build in progress, if any
+    {
+      std::lock_guard<std::mutex> wl(s->wq_mu);
+      s->wq_stop = true;
+    }
+    s->wq_cv.notify_all();
+    s->admitter.join();
+  }
   (void)hipStreamSynchronize(s->stream);
   if (s->lane_stream) (void)hipStreamSynchronize(s->lane_stream);
   (void)hipStreamSynchronize(s->admit_stream);
+  if (s->read_stream) (void)hipStreamSynchronize(s->read_stream);
   for (auto& kv : s->tickets)
     if (kv.second->plan) sl1m_plan_destroy(kv.second->plan);
   for (auto& e : s->ring_event)
@@ -1201,6 +1293,7 @@ sl1m_status sl1m_server_destroy(sl1m_server* s) {
     if (e) (void)hipEventDestroy(e);
   if (s->lane_stream) (void)hipStreamDestroy(s->lane_stream);
   if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
+  if (s->read_stream) (void)hipStreamDestroy(s->read_stream);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->h_tabs) (void)hipHostFree(s->h_tabs);
   delete s;

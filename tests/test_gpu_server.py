@@ -86,7 +86,13 @@ def test_alone_equals_in_mix_with_arrivals_and_cancel():
     srv.step()
     srv.step()
     tz = srv.submit(Z[0], Z[2], 0.05, 30)
-    srv.step()
+    # plans are built by the server's admission thread: step until Z runs
+    for _ in range(1_000_000):
+        srv.step()
+        if srv.poll(tz)[2][1] > 0:
+            break
+    else:
+        raise AssertionError("request never admitted")
     tx = srv.submit(X[0], X[2], 0.05, 30)
     for _ in range(5):
         srv.step()
@@ -127,12 +133,47 @@ def test_admission_by_footprint():
     srv = sl1m.Server((2 << 20) + int(1.5 * fp), max_slots=8, round_budget=4e7)
     t1 = srv.submit(wl, V1, 0.05, 30)
     t2 = srv.submit(wl, V2, 0.05, 30)
+    # the first is admitted once the admission thread has built its plan; the
+    # second stays pending (not reserved) while the first holds the arena
     a, p = srv.step()
-    say(f"    footprint {fp} B; after first step active={a} pending={p}")
-    assert a == 1 and p == 1
+    for _ in range(1_000_000):
+        if a >= 1:
+            break
+        a, p = srv.step()
+    say(f"    footprint {fp} B; once the first runs active={a} pending={p}")
+    assert a == 1 and p == 1 and not srv.poll(t2)[0] and srv.poll(t2)[2][1] == 0
     srv.drain([t1, t2])
     assert np.array_equal(srv.result(t1).cpu().numpy(), a1)
     assert np.array_equal(srv.result(t2).cpu().numpy(), a2)
+
+
+def test_cancel_while_admitting_then_serve():
+    """A request cancelled right after its first step, while the admission
+    thread may still be building its plan: it ends cancelled with its memory
+    and slot returned, and the server then serves the next request exactly
+    as alone."""
+    say("[case] cancel during admission")
+    wl, _, V = _req(12, 6000, 8000)
+    X = _req(13, 1200, 1500)
+    ax, ix = _alone(X[0], X[2], L=0.0)
+    srv = sl1m.Server(1 * GIB, max_slots=1)
+    t = srv.submit(wl, V, 0.05, 30)
+    srv.step()
+    srv.cancel(t)
+    for _ in range(1_000_000):
+        if srv.poll(t)[0]:
+            break
+        srv.step()
+    else:
+        raise AssertionError("cancelled request never reported done")
+    assert srv.poll(t)[1]["status"] == sl1m.ECANCELLED
+    st = srv.stats()
+    say(f"    after the cancel: {st}")
+    assert st["active"] == 0 and st["pending"] == 0 and st["arena_used"] == 0
+    tx = srv.submit(X[0], X[2], 0.05, 30)   # needs the only slot
+    srv.drain([tx])
+    assert np.array_equal(srv.result(tx).cpu().numpy(), ax)
+    assert srv.poll(tx)[1]["F"] == ix["F"]
 
 
 def test_server_close_to_standalone_solve():
