@@ -569,7 +569,7 @@ struct sl1m_server {
   size_t arena_bytes = 0;
   sl1m::sched::Arena alloc;
   int max_slots = 0;
-  double budget = 3e10;                // evals per round, shared by the active requests
+  double budget = 6e10;                // evals per round, shared by the active requests
   int policy = SL1M_SERVE_OLDEST_FIRST;  // how the round budget is shared
   hipStream_t stream = nullptr;        // rounds (non-blocking, default priority)
   hipStream_t lane_stream = nullptr;   // the second lane of each round
@@ -1091,7 +1091,7 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
     s->arena_bytes = arena_bytes - hdr;
     s->alloc.reset(s->arena_bytes);
     s->max_slots = max_slots;
-    s->budget = round_budget_evals > 0 ? round_budget_evals : 3e10;
+    s->budget = round_budget_evals > 0 ? round_budget_evals : 6e10;
     for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     SRV_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->h_tabs),
                           sizeof(TabDev) * kSrvRing * kSrvLanes * kTabs, hipHostMallocDefault),
