@@ -319,3 +319,79 @@ def test_served_request_at_config5_largest_size():
     assert err <= 1e-5
     assert abs(info["F"] - info_s["F"]) <= 1e-5 * info_s["F"]
     srv.close()
+
+
+def _burst_request(rng, i):
+    """Request i of the burst: direct delta, direct Gaussian, grid delta or
+    grid Gaussian pixels (i mod 4), sizes drawn from rng, random data."""
+    n_vis = int(rng.integers(800, 2500))
+    kind = W.PIX_DELTA if i % 2 == 0 else W.PIX_GAUSS_WIDE
+    sigma = 0.0 if kind == W.PIX_DELTA else 2e-3
+    if i % 4 < 2:
+        wl = W.small_random(200 + i, int(rng.integers(800, 2500)), n_vis, half_extent=0.1,
+                            uv_radius=600.0, w_sigma=80.0, kind=kind, sigma=sigma,
+                            with_gains=i % 3 == 0)
+    else:
+        wl = W.small_random(200 + i, 10, n_vis, half_extent=0.1, uv_radius=600.0,
+                            w_sigma=80.0, with_gains=i % 3 == 0)
+        l, m, _ = W.grid_pixels(int(rng.integers(16, 28)) * 2, 0.1)
+        wl.l, wl.m = l, m
+        wl.sigma = np.full(l.size, sigma)
+        wl.kind = np.full(l.size, kind, np.uint8)
+    V = 10 * (rng.standard_normal(n_vis) + 1j * rng.standard_normal(n_vis))
+    return wl, V
+
+
+def test_burst_with_cancels_equals_alone():
+    """24 requests of four kinds submitted in one burst to a server with 6
+    slots (the plans built by its admission thread while rounds run), four of
+    them cancelled in different states (waiting, just reserved, running, late
+    in the run): every other request's image and objective equal the same
+    request served alone, bitwise, and the server ends empty."""
+    say("[case] burst of 24 with cancels")
+    rng = np.random.default_rng(77)
+    reqs = [_burst_request(rng, i) for i in range(24)]
+    alone = [_alone(wl, V, L=0.0) for wl, V in reqs]
+    srv = sl1m.Server(2 * GIB, max_slots=6, round_budget=2e7)
+    tk = [srv.submit(wl, V, 0.05, 30) for wl, V in reqs]
+    srv.cancel(tk[3])          # waiting: never reserved
+    srv.step()
+    srv.cancel(tk[5])          # reserved by that step, its plan maybe still being built
+    cancelled = {3, 5}
+    settled = set()   # 15 and 21 once cancelled or found finished first
+    late = None
+    for _ in range(1_000_000):
+        srv.step()
+        if 15 not in settled:
+            done15, _, times15 = srv.poll(tk[15])
+            if times15[1] > 0:      # running (no step between this poll and the cancel)
+                if not done15:
+                    srv.cancel(tk[15])
+                    cancelled.add(15)
+                settled.add(15)
+        if 21 not in settled:
+            done21, _, times21 = srv.poll(tk[21])
+            if late is None and times21[1] > 0:
+                late = srv.stats()["rounds"] + 3
+            if done21:
+                settled.add(21)
+            elif late is not None and srv.stats()["rounds"] >= late:
+                srv.cancel(tk[21])  # late in its run
+                cancelled.add(21)
+                settled.add(21)
+        if all(srv.poll(t)[0] for t in tk):
+            break
+    else:
+        raise AssertionError("burst never drained")
+    say(f"    cancelled {sorted(cancelled)}")
+    for i, t in enumerate(tk):
+        done, info, _ = srv.poll(t)
+        assert done
+        if i in cancelled:
+            assert info["status"] == sl1m.ECANCELLED
+            continue
+        assert info["status"] == 0
+        assert np.array_equal(srv.result(t).cpu().numpy(), alone[i][0]), f"request {i}"
+        assert info["F"] == alone[i][1]["F"], f"request {i}"
+    st = srv.stats()
+    assert st["active"] == 0 and st["pending"] == 0 and st["arena_used"] == 0
