@@ -25,7 +25,9 @@ Reported beside it, in the same JSON line:
   latency and evals/s; plus a saturated stream (the first 64 requests at
   4x the arrival rate);
 * config 2's FISTA iteration (256^2 delta grid, 97,536 visibilities) as a
-  secondary operator figure;
+  secondary operator figure, and at its shape 1, 2, 4 and 8 right-hand
+  sides through the FP32 grid evaluation and the float16 / bfloat16
+  matrix-core plans (`config2_shape_multi_rhs`);
 * the FP64 CPU oracle's rate on a bounded sample of config 4
   (`cpu_baseline`).
 """
@@ -801,6 +803,10 @@ def main():
     if not args.no_config2 or args.extras:
         plan2, wl2, out["config2"] = config2_secondary(dev)
         print(f"[bench] config2 {out['config2']}", file=sys.stderr, flush=True)
+        if not args.extras:
+            # several right-hand sides (Stokes images) at config 2's shape:
+            # FP32 grid against the matrix-core plans (also in --extras)
+            out["config2_shape_multi_rhs"] = multi_rhs_table(wl2, dev)
     if args.extras:
         out["extras"] = extras(plan2, wl2, dev, c4)
     if not args.no_cpu_baseline:
