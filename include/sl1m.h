@@ -447,9 +447,10 @@ sl1m_status sl1m_timing_end(sl1m_plan* plan, sl1m_timing* out /* host */);
  * each of the n active requests advances by at most max(budget / n,
  * budget / 32) evaluations (at least one work item, never past the end of its
  * current phase), so small requests finish a whole FISTA iteration per round
- * while large ones advance part of one; under OLDEST_FIRST the earliest
- * admitted request may take the whole budget, requests of at most 128 budgets
- * of work in total budget / 4, and the others budget / 1024 (close to
+ * while large ones advance part of one; under OLDEST_FIRST a round holds
+ * max(budget, one FISTA iteration of the earliest admitted request), at most
+ * 4 budgets, of which that request may take the whole, requests of at most
+ * 128 budgets of work in total a quarter, and the others 1/1024 (close to
  * first-come-first-served for the large requests, small requests not queued
  * behind them).
  * A request whose pixels form one grid segment (see sl1m_grid_mode) runs the
@@ -473,9 +474,10 @@ typedef struct {
 
 /* arena: device memory owned by the caller (256-byte aligned), kept alive
  * until sl1m_server_destroy(); max_slots: at most this many requests on the
- * GPU at once (1..64); round_budget_evals: work per round (<= 0 selects 6e10,
- * about 9 ms of operator work; measured on a stream of mixed requests, it
- * beat 3e10 on p99 latency and throughput and 1.2e11 on p50).  The server creates its own non-blocking
+ * GPU at once (1..64); round_budget_evals: work per round (<= 0 selects 3e10,
+ * about 4 ms of operator work); under OLDEST_FIRST a round grows to one FISTA
+ * iteration of the oldest request, at most 4 budgets, so that large requests
+ * run in rounds that fill the GPU while small ones keep short rounds.  The server creates its own non-blocking
  * streams (rounds, second lane, admission, result read-back) and one host
  * thread that builds admitted requests' plans on the current device;
  * sl1m_server_destroy() ends it after the build in progress. */

@@ -40,6 +40,7 @@ constexpr int kSrvRing = 4;              // rounds in flight (table buffers)
 // may overlap: the tail of one lane's kernel is filled by the other's blocks.
 constexpr int kSrvLanes = 2;
 constexpr int kSrvTileBlocks = 2048;     // per-request operator split target (work-item count)
+constexpr double kSrvMaxRound = 4.0;     // OLDEST_FIRST rounds: at most this many budgets
 // item tables per round: 4 operator kinds x 6 variants (4 direct tile shapes,
 // the grid evaluation, the square-grid evaluation), then reduce, update, final
 // and the grid prep (delta, Gaussian).  Square grid requests use the
@@ -569,7 +570,7 @@ struct sl1m_server {
   size_t arena_bytes = 0;
   sl1m::sched::Arena alloc;
   int max_slots = 0;
-  double budget = 6e10;                // evals per round, shared by the active requests
+  double budget = 3e10;                // evals per round (OLDEST_FIRST: the least), shared by the active requests
   int policy = SL1M_SERVE_OLDEST_FIRST;  // how the round budget is shared
   hipStream_t stream = nullptr;        // rounds (non-blocking, default priority)
   hipStream_t lane_stream = nullptr;   // the second lane of each round
@@ -950,13 +951,21 @@ sl1m_status launch_round(sl1m_server* s) {
   }
   // each request's share of the round.  FAIR: equal shares with a floor so
   // that a crowded round still moves every request by a useful amount.
-  // OLDEST_FIRST: the earliest admitted request takes the whole budget (act
+  // OLDEST_FIRST: the earliest admitted request takes the whole round (act
   // is in admission order); the small requests (at most 128 budgets of work
   // in total) share a quarter of it between them, so that however many of
   // them run alongside, the oldest keeps at least four fifths of each round;
-  // the other large ones get a floor of budget/1024 (close to
+  // the other large ones get a floor of 1/1024 of the round (close to
   // first-come-first-served among the large ones).
-  const double fair = std::max(s->budget / static_cast<double>(act.size()), s->budget / 32.0);
+  // OLDEST_FIRST rounds hold at least one FISTA iteration (two operator
+  // applications) of the oldest request, between the budget and kSrvMaxRound
+  // times it: a large request then runs in rounds of enough blocks to fill
+  // the GPU past the launch tails, while a queue of small requests keeps
+  // short rounds (each round advances a small request by one step).
+  double B = s->budget;
+  if (s->policy == SL1M_SERVE_OLDEST_FIRST)
+    B = std::min(kSrvMaxRound * s->budget, std::max(s->budget, 2.0 * act[0]->shape.evals_per_op));
+  const double fair = std::max(B / static_cast<double>(act.size()), B / 32.0);
   auto is_small = [&](const sched::Request* r) {
     const sched::Shape& sh = r->shape;
     return sh.evals_per_op * (2.0 * (sh.power_iters + sh.max_iter) + 1.0) <= 128.0 * s->budget;
@@ -964,10 +973,10 @@ sl1m_status launch_round(sl1m_server* s) {
   int n_small = 0;
   for (size_t i = 1; i < act.size(); ++i) n_small += is_small(act[i]) ? 1 : 0;
   const double small_share =
-      std::max(s->budget / 1024.0, s->budget / 4.0 / static_cast<double>(std::max(n_small, 1)));
+      std::max(B / 1024.0, B / 4.0 / static_cast<double>(std::max(n_small, 1)));
   for (size_t i = 0; i < act.size(); ++i) {
     if (s->policy == SL1M_SERVE_OLDEST_FIRST)
-      act[i]->share = i == 0 ? s->budget : is_small(act[i]) ? small_share : s->budget / 1024.0;
+      act[i]->share = i == 0 ? B : is_small(act[i]) ? small_share : B / 1024.0;
     else
       act[i]->share = fair;
   }
@@ -1091,7 +1100,7 @@ sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slot
     s->arena_bytes = arena_bytes - hdr;
     s->alloc.reset(s->arena_bytes);
     s->max_slots = max_slots;
-    s->budget = round_budget_evals > 0 ? round_budget_evals : 6e10;
+    s->budget = round_budget_evals > 0 ? round_budget_evals : 3e10;
     for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     SRV_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->h_tabs),
                           sizeof(TabDev) * kSrvRing * kSrvLanes * kTabs, hipHostMallocDefault),

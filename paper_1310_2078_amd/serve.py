@@ -70,7 +70,7 @@ def _summary(lat, total_s, evals):
 
 
 def run_batched(arrivals, reqs, data, device, arena_bytes=48 << 30, max_slots=32,
-                round_budget=6e10, policy="oldest", tile_blocks=0, log=None):
+                round_budget=3e10, policy="oldest", tile_blocks=0, log=None):
     srv = sl1m.Server(arena_bytes, max_slots=max_slots, round_budget=round_budget, device=device,
                       policy=policy)
     n = len(reqs)
@@ -145,7 +145,7 @@ def main():
                     help="multiply the arrival times (1 = 4 requests/s on average)")
     ap.add_argument("--mode", choices=["both", "batched", "unbatched"], default="both")
     ap.add_argument("--slots", type=int, default=32)
-    ap.add_argument("--budget", type=float, default=6e10)
+    ap.add_argument("--budget", type=float, default=3e10)
     ap.add_argument("--tile-blocks", type=int, default=0,
                     help="per-request operator split target in the server (0: its default)")
     ap.add_argument("--policy", choices=["fair", "oldest"], default="oldest",

@@ -479,7 +479,7 @@ class Server:
 
     POLICIES = {"fair": 0, "oldest": 1}
 
-    def __init__(self, arena_bytes: int, max_slots: int = 32, round_budget: float = 6e10,
+    def __init__(self, arena_bytes: int, max_slots: int = 32, round_budget: float = 3e10,
                  device="cuda", policy: str = "oldest"):
         self.device = torch.device(device)
         self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
