@@ -118,7 +118,7 @@ def kernel_source_hash(kernel: str) -> str:
 SLOT_MIX = {
     "k_grid_adj_delta_square": (2048, 76, 6, 12, 0),
     "k_grid_fwd_delta_pairs": (512, 21.25, 1.25, 2.5, 0),
-    "k_grid_adj_gauss_multi": (2048, 174, 10, 12, 4),
+    "k_grid_adj_gauss_multi": (2048, 158, 10, 12, 4),
     "k_grid_fwd_gauss_pairs": (4096, 319, 18, 20, 4),
     "k_adj_delta<float,4>": (64, 3, 3, 2, 0),
     "k_fwd_delta<float,4>": (64, 3, 3, 2, 0),

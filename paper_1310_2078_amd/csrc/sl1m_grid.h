@@ -971,7 +971,8 @@ __device__ __forceinline__ void grid_adj_delta_pairs_multi_tile(
     for (int r = 0; r < NR; ++r) pair_write(pl, na, bo + bi, o[bi][r], slot, out + r * rstride);
 }
 
-// `vrec` and `rres` are the layer's records and residuals (D (1 - i s) conj(G) r).
+// `vrec` and `rres` are the layer's records and residuals (D (1 - i s) conj(G) r);
+// LDS holds conj(b+-) r per visibility of the batch and |m| value.
 __device__ __forceinline__ void grid_adj_gauss_tile(
     const VisRecG<float>* __restrict__ vrec, const float2* __restrict__ rres,
     const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ r2c,
@@ -988,7 +989,6 @@ __device__ __forceinline__ void grid_adj_gauss_tile(
     kap[bi] = ls.active ? kapc[ls.qbase + bi] : 0.0;
   }
   const ConstPtr<VisRecG<float>> crec = as_const(vrec);
-  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
   const double origin = kMagic;
   const int k0 = static_cast<int>(kc * kchunk);
   const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
@@ -1013,7 +1013,11 @@ __device__ __forceinline__ void grid_adj_gauss_tile(
           const float w = vrec[k].wr, v = vrec[k].vr, c = vrec[k].c1;
           const float dp = fmaf(-w, mr, v), dm = fmaf(w, mr, v);
           const float tp = pow2(c * (dp * dp)), tm = pow2(c * (dm * dm));
-          val = make_float4(tp * cb, tp * sb, tm * cb, -tm * sb);  // b+, b-
+          // conj(b+-) r: the residual rides on the block's factors
+          const float2 rk = rres[k];  // per-lane index: a vector load
+          const float rr = rk.x, ri = rk.y;
+          const float p = cb * rr, q = sb * ri, s = cb * ri, t = sb * rr;
+          val = make_float4(tp * (p + q), tp * (s - t), tm * (p - q), tm * (s + t));
         }
         bsh[kk][fgg][fbi] = val;
       }
@@ -1028,7 +1032,6 @@ __device__ __forceinline__ void grid_adj_gauss_tile(
     for (int k = kb; k < ke; ++k) {
       const double A = crec[k].A, C = crec[k].C, NW = crec[k].NW, E0 = crec[k].E0;
       const float ur = crec[k].ur, wr = crec[k].wr, c1 = crec[k].c1;
-      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
       float ca, sa;
       phasor(fma(A, l, origin), ca, sa);
       const float dp = fmaf(-wr, lr, ur), dm = fmaf(wr, lr, ur);
@@ -1037,12 +1040,12 @@ __device__ __forceinline__ void grid_adj_gauss_tile(
       const float4* bp = &bsh[k - kb][ls.gl][0];
 #pragma unroll
       for (int bi = 0; bi < kGridNBA; ++bi) {
-        const float4 bb = bp[bi];
+        const float4 bb = bp[bi];  // conj(b+-) r
         float cg, sg;
         phasor(fma(C, r2[bi], fma(NW, kap[bi], E0)), cg, sg);
-        const float zr = fmaf(cg, rr, sg * ri), zi = fmaf(cg, ri, -sg * rr);
-        const float ypr = fmaf(bb.x, zr, bb.y * zi), ypi = fmaf(bb.x, zi, -bb.y * zr);
-        const float ymr = fmaf(bb.z, zr, bb.w * zi), ymi = fmaf(bb.z, zi, -bb.w * zr);
+        // Y+- = conj(P) conj(b+-) r
+        const float ypr = fmaf(cg, bb.x, sg * bb.y), ypi = fmaf(cg, bb.y, -sg * bb.x);
+        const float ymr = fmaf(cg, bb.z, sg * bb.w), ymi = fmaf(cg, bb.w, -sg * bb.z);
         g[bi][0] = fmaf(apr, ypr, fmaf(api, ypi, g[bi][0]));
         g[bi][1] = fmaf(amr, ypr, fmaf(ami, ypi, g[bi][1]));
         g[bi][2] = fmaf(apr, ymr, fmaf(api, ymi, g[bi][2]));
@@ -1060,9 +1063,11 @@ __device__ __forceinline__ void grid_adj_gauss_tile(
 // Square Gaussian grid, pair blocks (GridPairBlock): lane-set (g4, ia) owns
 // the cells (ia, b) and mirrors (b, ia), b = kGridNBA g4 + bi.  LDS holds, per
 // visibility of the batch and |m| value of the block's groups, the cells'
-// b+- and the mirrors' a+- (both at that value); the lane forms a+- at |l|_ia
-// for its cells and b+- at |m|_ia for its mirrors.  Writes as for the delta
-// pair blocks.  `vrec`, `rres` are the layer's.
+// conj(b+-) r and the mirrors' conj(a+-) r (both at that value, the residual
+// multiplied in once by the block instead of once per cell by every lane);
+// the lane forms a+- at |l|_ia for its cells and b+- at |m|_ia for its
+// mirrors.  Writes as for the delta pair blocks.  `vrec`, `rres` are the
+// layer's.
 __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
     const VisRecG<float>* __restrict__ vrec, const float2* __restrict__ rres,
     const double* __restrict__ la, const double* __restrict__ mb, const double* __restrict__ r2c,
@@ -1090,7 +1095,6 @@ __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
     kap[bi] = active ? kapc[qbase + bi] : 0.0;
   }
   const ConstPtr<VisRecG<float>> crec = as_const(vrec);
-  const ConstPtr<float> cres = as_const(reinterpret_cast<const float*>(rres));
   const double origin = kMagic;
   const int k0 = static_cast<int>(kc * kchunk);
   const int k1 = static_cast<int>(k0 + kchunk < n_vis ? k0 + kchunk : n_vis);
@@ -1118,8 +1122,14 @@ __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
           const float dup = fmaf(-w, mr, vrec[k].ur), dum = fmaf(w, mr, vrec[k].ur);
           const float tvp = pow2(c * (dvp * dvp)), tvm = pow2(c * (dvm * dvm));
           const float tup = pow2(c * (dup * dup)), tum = pow2(c * (dum * dum));
-          bv = make_float4(tvp * cb, tvp * sb, tvm * cb, -tvm * sb);  // cell b+, b-
-          av = make_float4(tup * ca, tup * sa, tum * ca, -tum * sa);  // mirror a+, a-
+          // the residual rides on the block's factors: conj(b+-) r for the
+          // cell, conj(a+-) r for the mirror
+          const float2 rk = rres[k];  // per-lane index: a vector load
+          const float rr = rk.x, ri = rk.y;
+          const float bp = cb * rr, bq = sb * ri, bs_ = cb * ri, bt = sb * rr;
+          const float ap = ca * rr, aq = sa * ri, as_ = ca * ri, at = sa * rr;
+          bv = make_float4(tvp * (bp + bq), tvp * (bs_ - bt), tvm * (bp - bq), tvm * (bs_ + bt));
+          av = make_float4(tup * (ap + aq), tup * (as_ - at), tum * (ap - aq), tum * (as_ + at));
         }
         bsh[kk][fgg][fbi][0] = bv;
         bsh[kk][fgg][fbi][1] = av;
@@ -1131,7 +1141,6 @@ __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
     for (int k = kb; k < ke; ++k) {
       const double A = crec[k].A, B = crec[k].B, C = crec[k].C, NW = crec[k].NW, E0 = crec[k].E0;
       const float ur = crec[k].ur, vr = crec[k].vr, wr = crec[k].wr, c1 = crec[k].c1;
-      const float rr = cres[2 * static_cast<int64_t>(k)], ri = cres[2 * static_cast<int64_t>(k) + 1];
       float ca, sa, cb, sb;
       phasor(fma(A, l, origin), ca, sa);
       phasor(fma(B, l, origin), cb, sb);
@@ -1143,25 +1152,24 @@ __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
       const float qpr = tvp * cb, qpi = tvp * sb, qmr = tvm * cb, qmi = -tvm * sb;  // mirror b+-
 #pragma unroll
       for (int bi = 0; bi < kGridNBA; ++bi) {
-        const float4 bb = bsh[k - kb][gl][bi][0];  // cell b+- at |m|_b
-        const float4 ma = bsh[k - kb][gl][bi][1];  // mirror a+- at |l|_b
+        const float4 bb = bsh[k - kb][gl][bi][0];  // cell: conj(b+-) r at |m|_b
+        const float4 ma = bsh[k - kb][gl][bi][1];  // mirror: conj(a+-) r at |l|_b
         float cg, sg;
         phasor(fma(C, r2[bi], fma(NW, kap[bi], E0)), cg, sg);
-        const float zr = fmaf(cg, rr, sg * ri), zi = fmaf(cg, ri, -sg * rr);
-        // cell: Y+- = conj(b+-) Z, g = Re conj(a) Y
-        const float ypr = fmaf(bb.x, zr, bb.y * zi), ypi = fmaf(bb.x, zi, -bb.y * zr);
-        const float ymr = fmaf(bb.z, zr, bb.w * zi), ymi = fmaf(bb.z, zi, -bb.w * zr);
+        // cell: Y+- = conj(P) conj(b+-) r, g = Re conj(a) Y
+        const float ypr = fmaf(cg, bb.x, sg * bb.y), ypi = fmaf(cg, bb.y, -sg * bb.x);
+        const float ymr = fmaf(cg, bb.z, sg * bb.w), ymi = fmaf(cg, bb.w, -sg * bb.z);
         G[bi][0] = fmaf(apr, ypr, fmaf(api, ypi, G[bi][0]));
         G[bi][1] = fmaf(amr, ypr, fmaf(ami, ypi, G[bi][1]));
         G[bi][2] = fmaf(apr, ymr, fmaf(api, ymi, G[bi][2]));
         G[bi][3] = fmaf(amr, ymr, fmaf(ami, ymi, G[bi][3]));
-        // mirror: Y'+- = conj(qb+-) Z, g' = Re conj(ma) Y'
-        const float wpr = fmaf(qpr, zr, qpi * zi), wpi = fmaf(qpr, zi, -qpi * zr);
-        const float wmr = fmaf(qmr, zr, qmi * zi), wmi = fmaf(qmr, zi, -qmi * zr);
-        G[bi][4] = fmaf(ma.x, wpr, fmaf(ma.y, wpi, G[bi][4]));
-        G[bi][5] = fmaf(ma.z, wpr, fmaf(ma.w, wpi, G[bi][5]));
-        G[bi][6] = fmaf(ma.x, wmr, fmaf(ma.y, wmi, G[bi][6]));
-        G[bi][7] = fmaf(ma.z, wmr, fmaf(ma.w, wmi, G[bi][7]));
+        // mirror: T+- = conj(P) conj(a+-) r, g' = Re conj(qb) T
+        const float tpr = fmaf(cg, ma.x, sg * ma.y), tpi = fmaf(cg, ma.y, -sg * ma.x);
+        const float tmr = fmaf(cg, ma.z, sg * ma.w), tmi = fmaf(cg, ma.w, -sg * ma.z);
+        G[bi][4] = fmaf(qpr, tpr, fmaf(qpi, tpi, G[bi][4]));
+        G[bi][5] = fmaf(qpr, tmr, fmaf(qpi, tmi, G[bi][5]));
+        G[bi][6] = fmaf(qmr, tpr, fmaf(qmi, tpi, G[bi][6]));
+        G[bi][7] = fmaf(qmr, tmr, fmaf(qmi, tmi, G[bi][7]));
       }
     }
   }
