@@ -116,7 +116,7 @@ def kernel_source_hash(kernel: str) -> str:
 # and an |l| value (64 lanes x 8 pair records x 8 entries); the direct
 # kernels' a wavefront and an entry.
 SLOT_MIX = {
-    "k_grid_adj_delta_square": (2048, 76, 6, 12, 0),
+    "k_grid_adj_delta_square": (2048, 72, 6, 12, 0),
     "k_grid_fwd_delta_pairs": (512, 21.25, 1.25, 2.5, 0),
     "k_grid_adj_gauss_multi": (2048, 158, 10, 12, 4),
     "k_grid_fwd_gauss_pairs": (4096, 319, 18, 20, 4),

@@ -789,7 +789,8 @@ __device__ __forceinline__ void pair_write(const PairLane& pl, int na, int bi,
 }
 
 // One right-hand side: the block's per-|m| factors B and the partners' A
-// (both at |m|_b = |l|_b) come from LDS; A and B at index ia per lane.  Each
+// (both at |m|_b = |l|_b, times the visibility's |r|) come from LDS; A and B
+// at index ia per lane.  Each
 // of the 32 sums runs over the chunk's visibilities in one float32
 // accumulator (no per-batch partial sums: 32 fewer registers, a fifth
 // wavefront per SIMD); the chunks' sums are added by the reduction.
@@ -829,6 +830,11 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
         if (k < k1) {
           phasor(fma(vv[k], fm, origin), bc, bs);
           phasor(fma(vu[k], fm, origin), ac, as);
+          const float mag = rpol[k].mag;  // per-lane index: a vector load
+          bc *= mag;
+          bs *= mag;
+          ac *= mag;
+          as *= mag;
         }
         bsh[kk][fgg][fbi] = make_float4(bc, bs, ac, as);
       }
@@ -838,22 +844,18 @@ __device__ __forceinline__ void grid_adj_delta_pairs_tile(
     float (&G)[kGridNBA][8] = o;  // one running sum per chunk (see above)
     for (int k = kb; k < ke; ++k) {
       // z = C r = |r| e^{2 pi i (w nu + arg r / 2 pi)}: the residual's phase
-      // rides in the phasor's origin, its modulus on the lane's own factors
-      // (a real factor, unchanged by the sign flips that conjugate A or B)
+      // rides in the phasor's origin, its modulus on the block's LDS factors
+      // (a real factor, unchanged by the sign flips that conjugate A or B;
+      // each of the eight products below holds one LDS factor)
       const double u = cvrec[k].u, v = cvrec[k].v, w = cvrec[k].w;
       const double org = cpol[k].org;
-      const float mag = cpol[k].mag;
-      float ac, as, qc, qs;  // |r| A and |r| B at index ia
+      float ac, as, qc, qs;  // A and B at index ia
       phasor(fma(u, l, origin), ac, as);
       phasor(fma(v, l, origin), qc, qs);
-      ac *= mag;
-      as *= mag;
-      qc *= mag;
-      qs *= mag;
       const float4* bp = &bsh[k - kb][gl][0];
 #pragma unroll
       for (int bi = 0; bi < kGridNBA; ++bi) {
-        const float4 bb = bp[bi];  // B at b (x, y), A at b (z, w)
+        const float4 bb = bp[bi];  // |r| B at b (x, y), |r| A at b (z, w)
         float cc, cs;              // z / |r|
         phasor(fma(w, nuv[bi], org), cc, cs);
         // cell (ia, b): A at ia, B at b
