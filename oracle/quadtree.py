@@ -26,7 +26,9 @@ every level.  Reading R17 fixes what the paper leaves open:
   upscaling).
 
 `certificate_split` (an extra refinement rule used only by the study in
-`quadtree_study.py`, never compared with the GPU library) is parity unpinned.
+`quadtree_study.py`, never compared with the GPU library) is pinned against
+the closed form of a point source at the phase centre
+(`tests/test_quadtree_oracle.py`).
 """
 from __future__ import annotations
 

@@ -67,3 +67,38 @@ def test_refinement_follows_a_point_source():
     last = res[-1]
     k = _covering_cells(last["l"], last["m"], last["h"], ls, ms)[0]
     assert last["h"][k] == h_min and last["image"][k] >= 0.5 * last["image"].max()
+
+
+def test_certificate_split_threshold_on_a_source_at_the_phase_centre():
+    """`certificate_split` against a closed form: a unit-gain point source of
+    flux S at the phase centre has V_k = S for every visibility (n = 1, zero
+    phase), so with a zero image the delta child at the phase centre has
+    Re(M^H (V - M I)) = S N_v exactly and every other child less.  A cell of
+    side 2 h_min centred at (h_min/2, h_min/2) has that child; it is marked
+    just below the threshold lam (1 + tol) = S N_v and not just above, and
+    not at all once the image explains V (residual zero)."""
+    rng = np.random.default_rng(11)
+    n_v, S, h_min, tol = 300, 1.5, 0.01, 1e-3
+    r = 250.0 * np.sqrt(rng.random(n_v))
+    th = 2 * np.pi * rng.random(n_v)
+    u, v, w = r * np.cos(th), r * np.sin(th), rng.normal(0, 20, n_v)
+    V = np.full(n_v, S, np.complex128)  # closed form, not the oracle's forward
+
+    def problem_of(l, m, sigma, kind):
+        return O.Problem(l=l, m=m, sigma=sigma, kind=kind, u=u, v=v, w=w, threads=2)
+
+    # a coarse cell (split candidate) and a fine delta cell at the phase centre
+    l = np.array([h_min / 2, 0.0])
+    m = np.array([h_min / 2, 0.0])
+    h = np.array([2 * h_min, h_min])
+    sigma, kind = Q.cell_pixels(h, h_min)
+    op = O.Operator(problem_of(l, m, sigma, kind))
+    thr = S * n_v / (1 + tol)
+    zero = np.zeros(2)
+    below = Q.certificate_split(problem_of, V, thr * (1 - 1e-6), l, m, h, zero, op, h_min, tol=tol)
+    above = Q.certificate_split(problem_of, V, thr * (1 + 1e-6), l, m, h, zero, op, h_min, tol=tol)
+    assert below.tolist() == [True, False]
+    assert above.tolist() == [False, False]
+    explained = Q.certificate_split(problem_of, V, 1e-9, l, m, h, np.array([0.0, S]), op, h_min,
+                                    tol=tol)
+    assert explained.tolist() == [False, False]
