@@ -330,8 +330,8 @@ typedef struct {
   int32_t method;       /* sl1m_method (0: the printed FISTA)                        */
   uint64_t seed;        /* SplitMix64 state for the power-iteration start            */
   double nnz_eps;       /* stop when |nnz_k - nnz_prev| < nnz_eps max(nnz_prev, 1)
-                           between two checks (the paper's other stopping rule: a
-                           small change in the number of non-zero pixels); 0
+                           between two checks (the paper's other stopping rule:
+                           the count of non-zero pixels has nearly settled); 0
                            disables.  Checks run every check_every iterations when
                            eps > 0 or nnz_eps > 0.                                   */
 } sl1m_solve_params;

@@ -549,8 +549,8 @@ def test_termination_by_relative_change():
 
 
 def test_termination_by_nonzero_count():
-    """The second stopping rule of Section "Implementation of SL1M" (a small
-    change in the number of non-zero pixels), brute-forced from the iterate
+    """The second stopping rule of Section "Implementation of SL1M" (the
+    count of non-zero pixels has nearly settled), brute-forced from the iterate
     history: the run stops at the first check k (every 5 iterations) whose
     count differs from the previous check's by less than nnz_eps times it,
     and returns that iterate."""
