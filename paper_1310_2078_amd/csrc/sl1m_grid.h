@@ -1076,18 +1076,9 @@ __device__ __forceinline__ void grid_adj_gauss_pairs_tile(
     const double* __restrict__ kapc, const int32_t* __restrict__ slot, int na,
     const GridPairBlock& pb, int64_t kc, int64_t kchunk, int64_t n_vis,
     float* __restrict__ out_row, float4 (*bsh)[kGridMaxGL][kGridNBA][2]) {
-  int g4 = pb.g4, ia = pb.ia + static_cast<int>(threadIdx.x);
-  const bool active = static_cast<int>(threadIdx.x) < pb.count;
-  while (active && ia >= na) {
-    ++g4;
-    ia = ia - na + kGridNBA * g4;
-  }
-  if (!active) {
-    g4 = pb.g4;
-    ia = 0;
-  }
-  const int gl = g4 - pb.g4;
-  const int qbase = ((g4 / 2) * na + ia) * kGridNB + (g4 % 2) * kGridNBA;
+  const PairLane pl = pair_lane(pb, na);
+  const bool active = pl.active;
+  const int g4 = pl.g4, ia = pl.ia, gl = pl.gl, qbase = pl.qbase;
   const double l = la[ia];
   const float lr = static_cast<float>(l);
   double r2[kGridNBA], kap[kGridNBA];
