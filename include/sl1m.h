@@ -477,10 +477,13 @@ typedef struct {
  * GPU at once (1..64); round_budget_evals: work per round (<= 0 selects 3e10,
  * about 4 ms of operator work); under OLDEST_FIRST a round grows to one FISTA
  * iteration of the oldest request, at most 4 budgets, so that large requests
- * run in rounds that fill the GPU while small ones keep short rounds.  The server creates its own non-blocking
- * streams (rounds, second lane, admission, result read-back) and one host
- * thread that builds admitted requests' plans on the current device;
- * sl1m_server_destroy() ends it after the build in progress. */
+ * run in rounds that fill the GPU while small ones keep short rounds.  The
+ * server creates its own non-blocking streams (rounds, second lane,
+ * admission, result read-back) and one host thread that builds admitted
+ * requests' plans on the current device; sl1m_server_destroy() ends it after
+ * the build in progress.  Calls on one server from several host threads are
+ * serialised by the server's lock (sl1m_server_destroy excepted: no other
+ * call may be in progress or follow it). */
 sl1m_status sl1m_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
                                double round_budget_evals, sl1m_server** out);
 
