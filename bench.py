@@ -328,6 +328,7 @@ def extras(plan2, wl2, dev, c4):
     # GPUs by visibilities (every 8th record, all pixels: the grid evaluation
     # keeps its square pixel grid)
     wl4, V4d, Ve32, rate4 = c4["wl"], c4["data"], c4["extended_data"], c4["evals_per_s"]
+    rng = np.random.default_rng(5)
     x4 = torch.as_tensor(rng.standard_normal(wl4.n_pix), dtype=torch.float32, device=dev)
     ws = dataclasses.replace(wl4, u=wl4.u[::8], v=wl4.v[::8], w=wl4.w[::8],
                              ant_p=wl4.ant_p[::8], ant_q=wl4.ant_q[::8], noise=None)
