@@ -424,7 +424,12 @@ sl1m_status sl1m_dirty_image(sl1m_plan* plan, const void* vis, void* img_out, vo
  * (k_grid_fwd_delta_pairs or k_grid_fwd_delta), 4 = delta adjoint
  * (k_grid_adj_delta_square or k_grid_adj_delta), 5 = Gaussian forward (one
  * launch per layer), 6 = Gaussian adjoint (every layer in one launch);
- * 7 is unused. */
+ * 7 is unused.
+ *
+ * Host trace ranges: sl1m_plan_create, sl1m_tune, the power iteration, every
+ * solve ("sl1m solve"), sl1m_server_step and each plan build of the server's
+ * admission thread are roctx ranges, shown on the host timeline of
+ * `rocprofv3 --marker-trace` beside the kernels of `--kernel-trace`. */
 typedef struct {
   int64_t launches[8];
   double total_ms[8];

@@ -19,6 +19,8 @@ HIPCC_FLAGS = [
     "-shared",
     # no packed FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # host trace ranges (roctx) for rocprofv3 --marker-trace
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

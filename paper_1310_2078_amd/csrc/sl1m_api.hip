@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "sl1m_internal.h"
+#include "sl1m_trace.h"
 
 namespace sl1m {
 
@@ -688,6 +689,7 @@ sl1m_status ensure_graph(sl1m_plan* p, const void* vis, int method) {
 
 sl1m_status power_iteration(sl1m_plan* p, int32_t iters, uint64_t seed, const void* x0,
                             double* rq_out, hipStream_t st) {
+  const TraceRange range("sl1m power iteration");
   if (x0)
     SL1M_HIP(launch_gather(p, x0, p->xperm, 1, st), "gather start vector");
   else
@@ -755,6 +757,7 @@ sl1m_status sl1m_plan_workspace_bytes(const sl1m_problem* problem, size_t* bytes
 
 sl1m_status sl1m_plan_create(const sl1m_problem* pr, void* workspace, size_t workspace_bytes,
                              void* stream, sl1m_plan** out) {
+  const TraceRange range("sl1m_plan_create");
   try {
     if (!out) return set_error(SL1M_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1092,6 +1095,7 @@ sl1m_status sl1m_tune_workspace_bytes(const sl1m_problem* problem, size_t* bytes
 
 sl1m_status sl1m_tune(const sl1m_problem* problem, void* workspace, size_t workspace_bytes,
                       int32_t reps, void* stream, sl1m_tuning* out) {
+  const TraceRange range("sl1m_tune");
   try {
     if (!problem || !out) return set_error(SL1M_EINVAL, "NULL argument");
     if (reps < 1 || reps > 100) return set_error(SL1M_EINVAL, "reps must be in [1, 100]");
@@ -1314,6 +1318,7 @@ sl1m_status sl1m_estimate_L(sl1m_plan* p, int32_t iters, uint64_t seed, const vo
 static sl1m_status solve_impl(sl1m_plan* p, const void* vis, const void* x0,
                               const sl1m_solve_params* prm, void* img_out, sl1m_solve_info* info,
                               void* stream, sl1m_fista_state* state = nullptr) {
+  const TraceRange range("sl1m solve");
   try {
     if (sl1m_status s = check_plan(p)) return s;
     if (!prm || !info) return set_error(SL1M_EINVAL, "params or info is NULL");

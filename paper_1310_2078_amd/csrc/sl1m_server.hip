@@ -26,6 +26,7 @@
 
 #include "sl1m_grid.h"
 #include "sl1m_sched.h"
+#include "sl1m_trace.h"
 
 namespace sl1m {
 namespace {
@@ -891,6 +892,7 @@ void admission_thread(sl1m_server* s) {
     }
     sl1m_status st;
     try {
+      const TraceRange range("sl1m server admission build");
       st = admit(s, *t);
     } catch (...) {
       st = set_error(SL1M_ENOMEM, "host allocation failed");
@@ -1177,6 +1179,7 @@ sl1m_status sl1m_server_set_policy(sl1m_server* s, int32_t policy) {
 }
 
 sl1m_status sl1m_server_step(sl1m_server* s, int32_t* n_active, int32_t* n_pending) {
+  const TraceRange range("sl1m_server_step");
   try {
     if (!s) return set_error(SL1M_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
